@@ -1,0 +1,167 @@
+/*
+ * gwswig.h - C ABI of the batched gravitational-wave likelihood library
+ * (libgwswig.so, HIP for gfx950).
+ *
+ * The library evaluates the matched-filter log-likelihood of the paper's
+ * Sec. III.A, Eq. (loglike),
+ *     log L(theta) = -1/2 sum_i <d_i - h_i(theta) | d_i - h_i(theta)>_i,
+ *     <a|b>_i      = 4 Re int a*(f) b(f) / S_i(f) df,
+ * for a batch of parameter vectors at once, with the analytic phase and
+ * distance marginalisations of Sec. III.A, on the full uniform frequency grid
+ * or on the heterodyned (relative-binning) grid of Sec. III.D.  The template
+ * is a TaylorF2 aligned-spin tidal inspiral (a stand-in for the paper's
+ * waveform family) projected on each detector through its antenna pattern
+ * and time delay.
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ * - Parameter vectors are FP64, 13 columns, row-major [n, 13]:
+ *     Mc (Msun, detector frame), q = m2/m1 in (0, 1], chi1, chi2, Lambda1,
+ *     Lambda2, d_L (Mpc), iota, ra, dec, psi, phi_c, t_c (s).
+ *   Modes that marginalise phi_c (and d_L) ignore those columns.
+ * - Frequency grid: f_k = (k0 + k) * df, k = 0 .. n_freq - 1 (both band
+ *   edges included); the inner product is the Riemann sum over that grid.
+ * - Device buffers are caller-owned, contiguous, and must stay alive until
+ *   the work queued on the caller's stream has completed.  The context owns
+ *   everything it uploads.  A context is not thread-safe; all work goes on the
+ *   stream passed in (a hipStream_t, NULL for the default stream).
+ * - Errors are returned as status codes; nothing throws across the ABI and on
+ *   an error no output is written.  gw_last_error() returns a thread-local
+ *   message for the last non-OK status of the calling thread.
+ * - A parameter vector that is non-finite or unphysical (Mc <= 0, q outside
+ *   (0, 1], |chi| >= 1, d_L <= 0 where d_L is used) gets log L = -inf; it is
+ *   not an error, so one bad row never fails a batch.
+ * - Asynchronous device faults surface at the next synchronising call.
+ */
+#ifndef GWSWIG_H
+#define GWSWIG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gw_ctx gw_ctx;
+
+typedef enum {
+  GW_OK = 0,
+  GW_EINVAL = -1,   /* bad argument (null pointer, size, mode) */
+  GW_ENOMEM = -2,   /* device or host allocation failed */
+  GW_EDEVICE = -3,  /* HIP runtime error or no usable device */
+  GW_ESTATE = -4,   /* call not valid in the context's current state */
+  GW_ENOTSUP = -5   /* unsupported configuration */
+} gw_status;
+
+/* Likelihood kind. */
+enum { GW_FULL = 0, GW_HET = 1 };
+/* Marginalisation (Sec. III.A): none, phi_c, phi_c and d_L. */
+enum { GW_MARG_NONE = 0, GW_MARG_PHASE = 1, GW_MARG_PHASE_DIST = 2 };
+/* Arithmetic: plain FP64, or FP64 phase with FP32 phasors and sums. */
+enum { GW_PREC_FP64 = 0, GW_PREC_MIXED = 1 };
+
+#define GW_MAX_DET 4
+#define GW_NPARAM 13
+
+/*
+ * Problem description (host pointers, FP64; copied at gw_ctx_create, the
+ * caller keeps ownership).  Cited definitions: strain d_i(f) and one-sided
+ * PSD S_i(f) of Sec. III.A; distance prior proportional to d_L^2 on a 1-D
+ * grid (Sec. III.A).
+ *   n_det        number of detectors, 1 .. GW_MAX_DET
+ *   k0, n_freq   grid start index and number of bins (n_freq >= 1)
+ *   df           bin width (Hz), > 0
+ *   data_re/im   [n_det, n_freq] real and imaginary parts of d_i(f_k)
+ *   psd          [n_det, n_freq] S_i(f_k) > 0
+ *   det_tensor   [n_det, 3, 3] detector response tensors (Earth-fixed frame)
+ *   det_pos      [n_det, 3] detector positions (m, Earth-fixed frame)
+ *   gmst         Greenwich sidereal angle (rad); phi = ra - gmst
+ *   dist_grid    [n_dist] d_L grid (Mpc), > 0; may be NULL if n_dist == 0
+ *   dist_logw    [n_dist] log prior-times-quadrature weights of the grid
+ */
+typedef struct {
+  int32_t n_det;
+  int64_t k0;
+  int64_t n_freq;
+  double df;
+  const double* data_re;
+  const double* data_im;
+  const double* psd;
+  const double* det_tensor;
+  const double* det_pos;
+  double gmst;
+  const double* dist_grid;
+  const double* dist_logw;
+  int32_t n_dist;
+} gw_problem;
+
+/* Message of the calling thread's last non-OK status ("" if none). */
+const char* gw_last_error(void);
+
+/* Library version string. */
+const char* gw_version(void);
+
+/*
+ * Create a context on HIP device ``device``: uploads the weighted data
+ * u_ik = 4 df d_ik* f_k^(-7/6) / S_ik, the per-bin frequency tables, the
+ * closed-form template-norm weights W_i = 4 df sum_k f_k^(-7/3) / S_ik and
+ * <d|d>.  *out receives the context (NULL on error).
+ * Errors: GW_EINVAL (null pointers, bad sizes, non-positive PSD or df),
+ * GW_EDEVICE (no device), GW_ENOMEM.
+ */
+gw_status gw_ctx_create(const gw_problem* problem, int32_t device, gw_ctx** out);
+
+/* Release every device buffer of the context; NULL is accepted. */
+gw_status gw_ctx_destroy(gw_ctx* ctx);
+
+/* sum_i <d_i|d_i> held by the context (host FP64). */
+gw_status gw_data_inner(const gw_ctx* ctx, double* dd_out);
+
+/*
+ * Batched log-likelihood (Sec. III.A, Eq. loglike; marginalisations of
+ * Sec. III.A; heterodyned form of Sec. III.D when like == GW_HET).
+ *   theta   device [n, 13] FP64 parameter vectors
+ *   n       batch size (0 is a no-op)
+ *   like    GW_FULL or GW_HET (GW_HET needs heterodyne_setup first)
+ *   marg    GW_MARG_NONE, GW_MARG_PHASE or GW_MARG_PHASE_DIST
+ *   prec    GW_PREC_FP64 or GW_PREC_MIXED
+ *   logl    device [n] FP64 output
+ *   stream  hipStream_t or NULL
+ * Errors: GW_EINVAL, GW_ESTATE (heterodyne not set up, or PHASE_DIST with an
+ * empty distance grid), GW_EDEVICE, GW_ENOMEM.
+ */
+gw_status loglike_batch(gw_ctx* ctx, const double* theta, int64_t n, int32_t like,
+                        int32_t marg, int32_t prec, double* logl, void* stream);
+
+/*
+ * Projected templates h_i(f_k) on the full grid (Sec. III.A): one parameter
+ * vector per row of ``theta`` (device [n, 13]); ``h`` is device
+ * [n, n_det, n_freq, 2] FP64 (interleaved real, imaginary).  Rows that are
+ * unphysical are written as zeros.  Used to build injections.
+ */
+gw_status gw_template(gw_ctx* ctx, const double* theta, int64_t n, double* h, void* stream);
+
+/*
+ * Launch shape of the full-band kernel: ``tpb`` proposals per workgroup
+ * (64, 128 or 256) and ``n_chunks`` frequency chunks (a multiple of 8 keeps
+ * every chunk on one XCD).  0 restores the built-in heuristic.  Used by the
+ * autotuner; results do not depend on the shape beyond summation order.
+ */
+gw_status gw_set_full_shape(gw_ctx* ctx, int32_t tpb, int32_t n_chunks);
+
+/*
+ * Kernel timing of the dominant kernel (full-band overlap kernel, or the
+ * heterodyned evaluation kernel) for roofline reporting: while enabled, every
+ * launch of it is bracketed by HIP events recorded on the launch stream.
+ * gw_profile_read waits for the recorded events, returns the summed kernel
+ * time (ms) and the number of launches, and clears the record.  At most 4096
+ * launches are recorded between reads (later ones are not timed).
+ */
+gw_status gw_profile_enable(gw_ctx* ctx, int32_t enable);
+gw_status gw_profile_read(gw_ctx* ctx, double* kernel_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWSWIG_H */

@@ -1,0 +1,57 @@
+"""MI355X (gfx950) batched gravitational-wave likelihood for slice-within-Gibbs
+nested sampling.
+
+The compute lives in ``libgwswig.so`` (hand-written HIP); this package only
+marshals arguments to its C ABI (``_lib``) and wraps the context in a small
+class.  There is no CPU fallback: importing works without the library, but
+every call that needs it raises if it has not been built.
+"""
+from . import _lib  # noqa: F401
+from ._lib import (  # noqa: F401
+    GW_FULL, GW_HET, GW_MARG_NONE, GW_MARG_PHASE, GW_MARG_PHASE_DIST, GW_PREC_FP64, GW_PREC_MIXED,
+    GwError, gw_ctx_create, gw_ctx_destroy, gw_data_inner, gw_last_error, gw_set_full_shape, gw_template,
+    gw_version, loglike_batch,
+)
+
+
+class Context:
+    """Owns one library context (problem data resident on one GPU)."""
+
+    def __init__(self, prob, device: int = 0):
+        self.n_det = int(prob.data.shape[0])
+        self.n_freq = int(prob.n_freq)
+        self.device = device
+        self._ctx = gw_ctx_create(prob, device)
+
+    @property
+    def handle(self):
+        return self._ctx
+
+    def loglike(self, theta, like=GW_FULL, marg=GW_MARG_NONE, prec=GW_PREC_FP64, out=None, stream=None):
+        return loglike_batch(self._ctx, theta, like, marg, prec, out, stream)
+
+    def template(self, theta, stream=None):
+        return gw_template(self._ctx, theta, self.n_det, self.n_freq, stream)
+
+    def data_inner(self) -> float:
+        return gw_data_inner(self._ctx)
+
+    def set_full_shape(self, tpb: int = 0, n_chunks: int = 0):
+        gw_set_full_shape(self._ctx, tpb, n_chunks)
+
+    def close(self):
+        if self._ctx is not None and self._ctx.value:
+            gw_ctx_destroy(self._ctx)
+        self._ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,199 @@
+"""ctypes binding of libgwswig.so (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/gwswig.h with
+the same name; all arithmetic happens in the library's HIP kernels.  Device
+buffers are torch CUDA tensors (PyTorch provides device memory and streams).
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgwswig.so")
+
+GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_ESTATE, GW_ENOTSUP = 0, -1, -2, -3, -4, -5
+GW_FULL, GW_HET = 0, 1
+GW_MARG_NONE, GW_MARG_PHASE, GW_MARG_PHASE_DIST = 0, 1, 2
+GW_PREC_FP64, GW_PREC_MIXED = 0, 1
+GW_MAX_DET = 4
+GW_NPARAM = 13
+
+_STATUS_NAMES = {0: "GW_OK", -1: "GW_EINVAL", -2: "GW_ENOMEM", -3: "GW_EDEVICE", -4: "GW_ESTATE", -5: "GW_ENOTSUP"}
+
+
+class GwError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class gw_problem(ctypes.Structure):
+    _fields_ = [
+        ("n_det", ctypes.c_int32),
+        ("k0", ctypes.c_int64),
+        ("n_freq", ctypes.c_int64),
+        ("df", ctypes.c_double),
+        ("data_re", ctypes.POINTER(ctypes.c_double)),
+        ("data_im", ctypes.POINTER(ctypes.c_double)),
+        ("psd", ctypes.POINTER(ctypes.c_double)),
+        ("det_tensor", ctypes.POINTER(ctypes.c_double)),
+        ("det_pos", ctypes.POINTER(ctypes.c_double)),
+        ("gmst", ctypes.c_double),
+        ("dist_grid", ctypes.POINTER(ctypes.c_double)),
+        ("dist_logw", ctypes.POINTER(ctypes.c_double)),
+        ("n_dist", ctypes.c_int32),
+    ]
+
+
+_LIB = None
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "gw_last_error": (ctypes.c_char_p, []),
+    "gw_version": (ctypes.c_char_p, []),
+    "gw_ctx_create": (ctypes.c_int, [ctypes.POINTER(gw_problem), ctypes.c_int32, ctypes.POINTER(_P)]),
+    "gw_ctx_destroy": (ctypes.c_int, [_P]),
+    "gw_data_inner": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "loglike_batch": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "gw_template": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+    "gw_set_full_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "gw_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "gw_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load the library once; raise if it is missing (no fallback exists)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2607_28265_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def register(name: str, restype, argtypes):
+    """Declare an additional exported symbol's signature."""
+    _SIGS[name] = (restype, argtypes)
+    if _LIB is not None:
+        fn = getattr(_LIB, name)
+        fn.restype = restype
+        fn.argtypes = argtypes
+
+
+def gw_last_error() -> str:
+    return load().gw_last_error().decode()
+
+
+def gw_version() -> str:
+    return load().gw_version().decode()
+
+
+def check(status: int, where: str):
+    if status != GW_OK:
+        raise GwError(status, where, gw_last_error())
+
+
+def _dptr(arr):
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _tensor_ptr(t):
+    return ctypes.c_void_p(int(t.data_ptr()))
+
+
+def gw_ctx_create(prob, device: int = 0) -> ctypes.c_void_p:
+    """Create a context from a problem object (see gwsynth.Problem)."""
+    import numpy as np
+    lib = load()
+    data = np.ascontiguousarray(prob.data)
+    keep = dict(
+        re=np.ascontiguousarray(data.real, dtype=np.float64),
+        im=np.ascontiguousarray(data.imag, dtype=np.float64),
+        psd=np.ascontiguousarray(prob.psd, dtype=np.float64),
+        ten=np.ascontiguousarray(prob.det_tensor, dtype=np.float64),
+        pos=np.ascontiguousarray(prob.det_pos, dtype=np.float64),
+        dg=np.ascontiguousarray(prob.dist_grid, dtype=np.float64),
+        dw=np.ascontiguousarray(prob.dist_logw, dtype=np.float64),
+    )
+    p = gw_problem(n_det=data.shape[0], k0=int(prob.k0), n_freq=int(prob.n_freq), df=float(prob.df),
+                   data_re=_dptr(keep["re"]), data_im=_dptr(keep["im"]), psd=_dptr(keep["psd"]),
+                   det_tensor=_dptr(keep["ten"]), det_pos=_dptr(keep["pos"]), gmst=float(prob.gmst),
+                   dist_grid=_dptr(keep["dg"]), dist_logw=_dptr(keep["dw"]), n_dist=len(keep["dg"]))
+    out = ctypes.c_void_p()
+    check(lib.gw_ctx_create(ctypes.byref(p), device, ctypes.byref(out)), "gw_ctx_create")
+    return out
+
+
+def gw_ctx_destroy(ctx):
+    check(load().gw_ctx_destroy(ctx), "gw_ctx_destroy")
+
+
+def gw_data_inner(ctx) -> float:
+    v = ctypes.c_double()
+    check(load().gw_data_inner(ctx, ctypes.byref(v)), "gw_data_inner")
+    return v.value
+
+
+def _check_theta(theta):
+    import torch
+    if not (theta.is_cuda and theta.dtype == torch.float64 and theta.dim() == 2 and theta.shape[1] == GW_NPARAM
+            and theta.is_contiguous()):
+        raise ValueError("theta must be a contiguous CUDA float64 tensor of shape [n, 13]")
+
+
+def loglike_batch(ctx, theta, like: int = GW_FULL, marg: int = GW_MARG_NONE, prec: int = GW_PREC_FP64,
+                  out=None, stream=None):
+    """log L for every row of ``theta`` (CUDA float64 [n, 13]) -> CUDA float64 [n]."""
+    import torch
+    _check_theta(theta)
+    n = theta.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=theta.device)
+    elif not (out.is_cuda and out.dtype == torch.float64 and out.numel() >= n and out.is_contiguous()):
+        raise ValueError("out must be a contiguous CUDA float64 tensor with at least n elements")
+    check(load().loglike_batch(ctx, _tensor_ptr(theta), n, like, marg, prec, _tensor_ptr(out), _stream_ptr(stream)),
+          "loglike_batch")
+    return out
+
+
+def gw_template(ctx, theta, n_det: int, n_freq: int, stream=None):
+    """Projected templates -> CUDA complex128 [n, n_det, n_freq]."""
+    import torch
+    _check_theta(theta)
+    n = theta.shape[0]
+    h = torch.empty((n, n_det, n_freq, 2), dtype=torch.float64, device=theta.device)
+    check(load().gw_template(ctx, _tensor_ptr(theta), n, _tensor_ptr(h), _stream_ptr(stream)), "gw_template")
+    return torch.view_as_complex(h)
+
+
+def gw_set_full_shape(ctx, tpb: int, n_chunks: int):
+    check(load().gw_set_full_shape(ctx, tpb, n_chunks), "gw_set_full_shape")
+
+
+def gw_profile_enable(ctx, enable: bool = True):
+    check(load().gw_profile_enable(ctx, 1 if enable else 0), "gw_profile_enable")
+
+
+def gw_profile_read(ctx):
+    """(summed kernel ms, number of timed launches) since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    check(load().gw_profile_read(ctx, ctypes.byref(ms), ctypes.byref(n)), "gw_profile_read")
+    return ms.value, n.value

@@ -1,0 +1,79 @@
+// Host-side definition of the library context and the internal launch
+// helpers shared by the library's HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "gw_device.h"
+#include "gwswig.h"
+
+struct gw_het_state;
+struct gw_graph_cache;
+
+struct gw_ctx {
+  int device = 0;
+  gw::Geom geom{};
+  int n_det = 0;
+  double dd = 0.0;                 // sum_i <d_i|d_i>
+  // full-band per-bin records [n_freq][4 + 2 n_det] FP64:
+  //   x = f^(1/3), x^2, f^(-5/3), ln f, then Re/Im of u_ik per detector
+  double* bins = nullptr;
+  int rec_stride = 0;
+  // distance grid
+  double* dist_grid = nullptr;
+  double* dist_logw = nullptr;
+  int32_t n_dist = 0;
+  std::vector<double> h_dist_grid, h_dist_logw;
+  // host copies kept for heterodyne set-up
+  std::vector<double> h_data_re, h_data_im, h_psd;
+  // workspace (grown on demand)
+  double* coef = nullptr;          // [C_NCOEF][cap_n]
+  int64_t coef_cap = 0;
+  double* partial = nullptr;       // full-band partial sums
+  int64_t partial_cap = 0;         // doubles
+  double* zbuf = nullptr;          // [2][cap_n] (|Z1|, <h|h>_1) for the distance marginal
+  int64_t zbuf_cap = 0;
+  // launch configuration of the full-band kernel (0 = heuristic)
+  int full_tpb = 0;
+  int full_chunks = 0;
+  // kernel timing (gw_profile_enable / gw_profile_read)
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
+  int prof_used = 0;
+  gw_het_state* het = nullptr;
+  gw_graph_cache* graphs = nullptr;
+};
+
+namespace gw {
+
+gw_status set_error(gw_status st, const char* fmt, ...);
+gw_status check_hip(hipError_t e, const char* what);
+gw_status ensure_buffer(double** buf, int64_t* cap, int64_t need, const char* what);
+
+// Launch helpers (all asynchronous on ``st``).
+gw_status launch_prologue(gw_ctx* ctx, const double* theta, int64_t n, int marg, double* coef,
+                          int64_t ld, hipStream_t st);
+gw_status launch_full(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec,
+                      int tpb, int n_chunks, double* partial, hipStream_t st);
+gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, const double* coef,
+                          int64_t ld, int64_t n, int marg, double* logl, hipStream_t st);
+gw_status launch_template(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, double* h,
+                          hipStream_t st);
+void full_launch_shape(const gw_ctx* ctx, int64_t n, int* tpb, int* n_chunks);
+
+// Kernel timing: record a start / stop event pair around the dominant kernel.
+// prof_begin returns the pair index or -1 when timing is off or full.
+int prof_begin(gw_ctx* ctx, hipStream_t st);
+void prof_end(gw_ctx* ctx, int slot, hipStream_t st);
+
+// Heterodyne and graph state owned by the context.
+void het_free(gw_ctx* ctx);
+void graphs_free(gw_ctx* ctx);
+gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl,
+                      hipStream_t st);
+
+}  // namespace gw

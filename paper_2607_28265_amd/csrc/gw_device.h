@@ -1,0 +1,296 @@
+// Device-side building blocks shared by the library's HIP sources:
+// constants, the per-proposal prologue (TaylorF2 coefficients, antenna
+// patterns, delays, amplitudes), FP64 sin/cos in cycles, ln I0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gw {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kTwoPi = 6.283185307179586476925286766559005768;
+constexpr double kInvTwoPi = 0.159154943091895335768883763372514362;
+constexpr double kMsunSec = 4.925490947641267e-6;     // G Msun / c^3 (s)
+constexpr double kLightSpeed = 299792458.0;            // m / s
+constexpr double kMpcMetre = 3.085677581491367e22;     // m
+constexpr double kEulerGamma = 0.5772156649015328606;
+constexpr double kLog4 = 1.386294361119890618834464242916;
+
+constexpr int kMaxDet = 4;
+
+// Column indices of the per-proposal coefficient table (structure of arrays,
+// column c of a batch of n lives at coef[c * n + p]).
+enum CoefCol {
+  // phase in cycles: psi(f) = xm5 * P(x) + (b5 + b6 x) ln f, x = f^(1/3),
+  // P(x) = a0 + a2 x^2 + ... + a8 x^8 + a10 x^10 + a12 x^12, with the
+  // linear-in-f time shift of detector 0 in a8 and the constant phase in a5.
+  C_A0 = 0, C_A2, C_A3, C_A4, C_A5, C_A6, C_A7, C_A8, C_A10, C_A12, C_B5, C_B6,
+  C_DT1 = 12,        // t-shift of detector i (i >= 1) relative to detector 0, s
+  C_VALID = 15,      // 1 for a physical row, 0 otherwise
+  C_APRE = 16,       // Re(A P_i), i < kMaxDet
+  C_APIM = 20,       // Im(A P_i)
+  C_HH = 24,         // <h|h> summed over detectors (closed form)
+  C_TAU0 = 25,       // total time shift of detector 0 (t_c + dt_0), s
+  C_AMP = 26,        // amplitude A
+  C_NCOEF = 32
+};
+
+// Detector network and grid constants passed by value to kernels.
+struct Geom {
+  double tensor[kMaxDet][9];
+  double pos[kMaxDet][3];
+  double hhw[kMaxDet];   // W_i = 4 df sum_k f_k^(-7/3) / S_ik
+  double gmst;
+  double df;
+  int64_t k0;
+  int64_t n_freq;
+  int32_t n_det;
+};
+
+__device__ inline bool finite_d(double v) { return __builtin_isfinite(v); }
+
+// Per-proposal prologue.  Writes C_NCOEF values into out[] (stride ``ld``).
+// marg: 0 plain, 1 phase-marginalised (phi_c := 0), 2 phase+distance
+// (phi_c := 0, d_L := 1 Mpc).
+__device__ inline void prologue(const double* __restrict__ th, int marg, const Geom& g,
+                                double* out, int64_t ld) {
+  double v[13];
+#pragma unroll
+  for (int j = 0; j < 13; ++j) v[j] = th[j];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 13; ++j) ok = ok && finite_d(v[j]);
+  const double mc = v[0], q = v[1], c1 = v[2], c2 = v[3], l1 = v[4], l2 = v[5];
+  double dl = v[6];
+  const double iota = v[7], ra = v[8], dec = v[9], psi = v[10];
+  double phic = v[11];
+  const double tc = v[12];
+  ok = ok && mc > 0.0 && q > 0.0 && q <= 1.0 && fabs(c1) < 1.0 && fabs(c2) < 1.0;
+  if (marg != 2) ok = ok && dl > 0.0;
+  if (!ok) {
+    for (int c = 0; c < C_NCOEF; ++c) out[c * ld] = 0.0;
+    return;
+  }
+  if (marg != 0) phic = 0.0;
+  if (marg == 2) dl = 1.0;
+
+  // Masses: X1 = m1/M >= X2, eta = X1 X2, delta = X1 - X2.
+  const double x1 = 1.0 / (1.0 + q);
+  const double x2 = q * x1;
+  const double eta = x1 * x2;
+  const double dlt = x1 - x2;
+  const double mtot = mc * pow(eta, -0.6);
+  const double eta2 = eta * eta, eta3 = eta2 * eta;
+
+  // Aligned-spin combinations.
+  const double sl = x1 * x1 * c1 + x2 * x2 * c2;
+  const double dsl = dlt * (x2 * c2 - x1 * c1);
+
+  // Post-Newtonian coefficients of sum_j (p_j + l_j ln v) v^j.
+  const double p0 = 1.0;
+  const double p2 = 3715.0 / 756.0 + 55.0 / 9.0 * eta;
+  const double p3 = -16.0 * kPi + 188.0 / 3.0 * sl + 25.0 * dsl;
+  const double sig = 79.0 / 8.0 * eta * c1 * c2 + 81.0 / 16.0 * (x1 * x1 * c1 * c1 + x2 * x2 * c2 * c2);
+  const double p4 = 15293365.0 / 508032.0 + 27145.0 / 504.0 * eta + 3085.0 / 72.0 * eta2 - 10.0 * sig;
+  const double gam = (554345.0 / 1134.0 + 110.0 / 9.0 * eta) * sl + (13915.0 / 84.0 - 10.0 / 3.0 * eta) * dsl;
+  const double p5 = kPi * (38645.0 / 756.0 - 65.0 / 9.0 * eta) - gam;
+  const double l5 = 3.0 * p5;
+  const double p6 = 11583231236531.0 / 4694215680.0 - 640.0 / 3.0 * kPi * kPi
+                    - 6848.0 / 21.0 * (kEulerGamma + kLog4)
+                    + (-15737765635.0 / 3048192.0 + 2255.0 / 12.0 * kPi * kPi) * eta
+                    + 76055.0 / 1728.0 * eta2 - 127825.0 / 1296.0 * eta3
+                    + kPi * (3760.0 * sl + 1490.0 * dsl) / 3.0;
+  const double l6 = -6848.0 / 21.0;
+  const double p7 = kPi * (77096675.0 / 254016.0 + 378515.0 / 1512.0 * eta - 74045.0 / 756.0 * eta2)
+                    + (-8980424995.0 / 762048.0 + 6586595.0 / 756.0 * eta - 305.0 / 36.0 * eta2) * sl
+                    - (170978035.0 / 48384.0 - 2876425.0 / 672.0 * eta - 4735.0 / 144.0 * eta2) * dsl;
+  // Tidal (Lambda-tilde at 5PN, delta-Lambda-tilde at 6PN).
+  const double lp = l1 + l2, lm = l1 - l2;
+  const double ltil = 8.0 / 13.0 * ((1.0 + 7.0 * eta - 31.0 * eta2) * lp + dlt * (1.0 + 9.0 * eta - 11.0 * eta2) * lm);
+  const double dltil = 0.5 * (dlt * (1.0 - 13272.0 / 1319.0 * eta + 8944.0 / 1319.0 * eta2) * lp
+                              + (1.0 - 15910.0 / 1319.0 * eta + 32850.0 / 1319.0 * eta2 + 3380.0 / 1319.0 * eta3) * lm);
+  const double t10 = -19.5 * ltil;
+  const double t12 = -3115.0 / 64.0 * ltil + 6595.0 / 364.0 * dlt * dltil;
+
+  // v = kappa x with kappa = (pi M)^(1/3), x = f^(1/3); ln v = ln kappa + ln f / 3.
+  const double kap = cbrt(kPi * mtot * kMsunSec);
+  const double lk = log(kap);
+  const double ki = 1.0 / kap;
+  const double ki2 = ki * ki, ki3 = ki2 * ki, ki5 = ki3 * ki2;
+  const double pref = 3.0 / (128.0 * eta) * kInvTwoPi;  // cycles
+  double a[13];
+  a[0] = pref * ki5 * p0;
+  a[2] = pref * ki3 * p2;
+  a[3] = pref * ki2 * p3;
+  a[4] = pref * ki * p4;
+  a[5] = pref * (p5 + l5 * lk) + (-phic - 0.25 * kPi) * kInvTwoPi;
+  a[6] = pref * kap * (p6 + l6 * lk);
+  a[7] = pref * kap * kap * p7;
+  const double kap5 = kap * kap * kap * kap * kap;
+  a[10] = pref * kap5 * t10;
+  a[12] = pref * kap5 * kap * kap * t12;
+  const double b5 = pref * l5 / 3.0;
+  const double b6 = pref * l6 * kap / 3.0;
+
+  // Detector frame: phi = ra - gmst.
+  const double ph = ra - g.gmst;
+  double sp, cp, sd, cd, ss, cs;
+  sincos(ph, &sp, &cp);
+  sincos(dec, &sd, &cd);
+  sincos(psi, &ss, &cs);
+  const double s[3] = {cd * cp, cd * sp, sd};
+  const double m[3] = {-sp, cp, 0.0};
+  const double nn[3] = {-sd * cp, -sd * sp, cd};
+  double X[3], Y[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    X[j] = -cs * m[j] + ss * nn[j];
+    Y[j] = ss * m[j] + cs * nn[j];
+  }
+  const double amp = sqrt(5.0 / 24.0) * pow(kPi, -2.0 / 3.0) * kLightSpeed / (dl * kMpcMetre)
+                     * pow(mc * kMsunSec, 5.0 / 6.0);
+  const double ci = cos(iota);
+  const double pp = 0.5 * (1.0 + ci * ci);
+  double tau0 = 0.0, hh = 0.0;
+  for (int i = 0; i < kMaxDet; ++i) {
+    double fp = 0.0, fx = 0.0, dt = 0.0;
+    if (i < g.n_det) {
+      const double* D = g.tensor[i];
+      double DX[3], DY[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        DX[r] = D[3 * r] * X[0] + D[3 * r + 1] * X[1] + D[3 * r + 2] * X[2];
+        DY[r] = D[3 * r] * Y[0] + D[3 * r + 1] * Y[1] + D[3 * r + 2] * Y[2];
+      }
+      fp = (X[0] * DX[0] + X[1] * DX[1] + X[2] * DX[2]) - (Y[0] * DY[0] + Y[1] * DY[1] + Y[2] * DY[2]);
+      fx = (X[0] * DY[0] + X[1] * DY[1] + X[2] * DY[2]) + (Y[0] * DX[0] + Y[1] * DX[1] + Y[2] * DX[2]);
+      dt = -(s[0] * g.pos[i][0] + s[1] * g.pos[i][1] + s[2] * g.pos[i][2]) / kLightSpeed;
+    }
+    const double tau = tc + dt;
+    if (i == 0) tau0 = tau;
+    const double apr = amp * fp * pp;
+    const double api = -amp * fx * ci;
+    out[(C_APRE + i) * ld] = apr;
+    out[(C_APIM + i) * ld] = api;
+    if (i >= 1 && i < 4) out[(C_DT1 + i - 1) * ld] = (i < g.n_det) ? tau - tau0 : 0.0;
+    if (i < g.n_det) hh += (apr * apr + api * api) * g.hhw[i];
+  }
+  a[8] = tau0;
+  out[C_A0 * ld] = a[0];
+  out[C_A2 * ld] = a[2];
+  out[C_A3 * ld] = a[3];
+  out[C_A4 * ld] = a[4];
+  out[C_A5 * ld] = a[5];
+  out[C_A6 * ld] = a[6];
+  out[C_A7 * ld] = a[7];
+  out[C_A8 * ld] = a[8];
+  out[C_A10 * ld] = a[10];
+  out[C_A12 * ld] = a[12];
+  out[C_B5 * ld] = b5;
+  out[C_B6 * ld] = b6;
+  out[C_VALID * ld] = 1.0;
+  out[C_HH * ld] = hh;
+  out[C_TAU0 * ld] = tau0;
+  out[C_AMP * ld] = amp;
+  for (int c = C_AMP + 1; c < C_NCOEF; ++c) out[c * ld] = 0.0;
+}
+
+// Phase in cycles of the template at one frequency, from the coefficient
+// registers: xm5 * P(x) + (b5 + b6 x) ln f.
+struct PhaseCoef {
+  double a0, a2, a3, a4, a5, a6, a7, a8, a10, a12, b5, b6;
+};
+
+__device__ inline double phase_cycles(const PhaseCoef& c, double x, double x2, double xm5, double lnf) {
+  double t = fma(x2, c.a12, c.a10);
+  t = fma(x2, t, c.a8);
+  t = fma(x, t, c.a7);
+  t = fma(x, t, c.a6);
+  t = fma(x, t, c.a5);
+  t = fma(x, t, c.a4);
+  t = fma(x, t, c.a3);
+  t = fma(x, t, c.a2);
+  t = fma(x2, t, c.a0);
+  const double lg = fma(c.b6, x, c.b5);
+  return fma(lg, lnf, t * xm5);
+}
+
+// Coefficients of the FP64 sin/cos polynomials.  Kernels take them as a
+// kernel argument so that they sit in SGPRs (a VOP3 FMA can read one SGPR
+// pair directly, which avoids a register copy per coefficient).
+struct TrigConsts {
+  double s[10];  // sin: (-1)^j / (2j+3)!, j = 0..9  (a^3 .. a^21)
+  double c[11];  // cos: (-1)^(j+1) / (2j+2)!, j = 0..10 (a^2 .. a^22)
+};
+
+__host__ __device__ inline TrigConsts make_trig_consts() {
+  TrigConsts t;
+  double fact = 1.0;  // n!
+  int n = 1;
+  for (int j = 0; j < 10; ++j) {
+    while (n < 2 * j + 3) fact *= (double)(++n);
+    t.s[j] = ((j & 1) ? 1.0 : -1.0) / fact;
+  }
+  fact = 1.0;
+  n = 1;
+  for (int j = 0; j < 11; ++j) {
+    while (n < 2 * j + 2) fact *= (double)(++n);
+    t.c[j] = ((j & 1) ? 1.0 : -1.0) / fact;
+  }
+  return t;
+}
+
+// sin and cos of 2 pi r for a phase r in cycles, FP64.  The phase is reduced
+// to the nearest half turn (exact in FP64: r * 2 and r - q / 2 are exact), the
+// remainder |a| <= pi/2 rad goes through the Taylor series of sin to a^21 and
+// of cos to a^22 (truncation below 2e-18 on that interval), and the half-turn
+// count flips both signs.
+__device__ inline void sincos_cycles(double r, const TrigConsts& T, double* s_out, double* c_out) {
+  const double q = rint(r * 2.0);
+  const double t = fma(q, -0.5, r);
+  const double a = t * kTwoPi;
+  const double a2 = a * a;
+  double ps = T.s[9];
+#pragma unroll
+  for (int j = 8; j >= 0; --j) ps = fma(ps, a2, T.s[j]);
+  const double sn = fma(a * a2, ps, a);
+  double pc = T.c[10];
+#pragma unroll
+  for (int j = 9; j >= 0; --j) pc = fma(pc, a2, T.c[j]);
+  const double cn = fma(a2, pc, 1.0);
+  // (-1)^q on both: flip the sign bits when q is odd.
+  const unsigned flip = ((unsigned)(int)q) << 31;
+  *s_out = __hiloint2double(__double2hiint(sn) ^ flip, __double2loint(sn));
+  *c_out = __hiloint2double(__double2hiint(cn) ^ flip, __double2loint(cn));
+}
+
+// ln I0(x), x >= 0.  Power series sum_k (x^2/4)^k / (k!)^2 for x < 20, and
+// the large-argument expansion I0(x) ~ e^x / sqrt(2 pi x) sum_k c_k x^-k,
+// c_k = ((2k-1)!!)^2 / (k! 8^k) (Abramowitz & Stegun 9.7.1) otherwise; the
+// expansion is cut at its smallest term, whose size is about e^(-2x).
+__device__ inline double log_i0(double x) {
+  if (x < 20.0) {
+    const double y = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 200; ++k) {
+      term *= y / ((double)k * (double)k);
+      sum += term;
+      if (term < 1e-17 * sum) break;
+    }
+    return log(sum);
+  }
+  const double ix = 1.0 / x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 60; ++k) {
+    const double tk = 2.0 * k - 1.0;
+    const double next = term * tk * tk * 0.125 * ix / (double)k;
+    if (next > term) break;
+    term = next;
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return x - 0.5 * log(kTwoPi * x) + log(sum);
+}
+
+}  // namespace gw

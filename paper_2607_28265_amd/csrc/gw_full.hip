@@ -1,0 +1,363 @@
+// Full-band batched likelihood: per-proposal prologue, the fused
+// phase/phasor/projection/overlap kernel and the FP64 epilogue with the
+// phase and distance marginalisations (Sec. III.A).
+//
+// Layout.  One lane owns one proposal; a workgroup owns ``tpb`` proposals and
+// one contiguous chunk of frequency bins.  Every lane of a wave walks the same
+// bins in the same order, so the per-bin records (frequency powers and the
+// weighted data u_ik = 4 df d_ik* f^(-7/6) / S_ik) are wave-uniform and are
+// fetched with scalar loads into SGPRs; the proposal's phase coefficients live
+// in VGPRs.  Per bin a lane evaluates the TaylorF2 phase in FP64 (Horner in
+// x = f^(1/3)), one complex phasor exp(-i Phi_0) for detector 0, and folds the
+// other detectors' linear time-shift phases into a Horner recurrence over the
+// bins of the chunk: S_i <- S_i rho_i + u_ik g_k with rho_i = exp(-2 pi i df
+// (tau_i - tau_0)), which is multiplied by exp(-2 pi i f_start (tau_i - tau_0))
+// at the end.  The template norm <h|h> has a closed form (|h|^2 / S does not
+// depend on the phase), so only z_i = sum_k u_ik exp(-i Phi_ik) is summed.
+// Partial sums per (chunk, proposal) are combined in a fixed order by the
+// epilogue, so results are bitwise reproducible.
+#include <math.h>
+
+#include "gw_ctx.h"
+
+namespace gw {
+
+__global__ void __launch_bounds__(256) k_prologue(const double* __restrict__ theta, int64_t n, int marg,
+                                                  Geom geom, double* __restrict__ coef, int64_t ld) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  prologue(theta + p * 13, marg, geom, coef + p, ld);
+}
+
+// Decode a workgroup index into (chunk, proposal tile).  Workgroups are
+// dealt round-robin to the 8 XCDs; when n_chunks is a multiple of 8 all
+// workgroups of one chunk land on one XCD so its L2 holds that chunk's bins.
+__device__ inline void decode_block(int bid, int nptile, int n_chunks, int* chunk, int* ptile) {
+  if ((n_chunks & 7) == 0) {
+    const int slot = bid >> 3;
+    *chunk = (bid & 7) + 8 * (slot / nptile);
+    *ptile = slot % nptile;
+  } else {
+    *chunk = bid / nptile;
+    *ptile = bid % nptile;
+  }
+}
+
+template <int PREC>
+__device__ inline void phasor(double r, const TrigConsts& T, double* gr, double* gi) {
+  if (PREC == 0) {
+    double s, c;
+    sincos_cycles(r, T, &s, &c);
+    *gr = c;
+    *gi = -s;
+  } else {
+    // FP64 reduction to a fraction of a cycle, FP32 hardware sin/cos
+    // (argument in revolutions).
+    const float t = (float)(r - rint(r));
+    *gr = (double)__builtin_amdgcn_cosf(t);
+    *gi = -(double)__builtin_amdgcn_sinf(t);
+  }
+}
+
+template <int ND, int PREC>
+__global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, int64_t ld, int64_t n,
+                                              const double* __restrict__ bins, int64_t k0, double df,
+                                              int n_freq, int chunk_len, int n_chunks, TrigConsts T,
+                                              double* __restrict__ partial) {
+  constexpr int RS = 4 + 2 * ND;
+  const int tpb = blockDim.x;
+  const int nptile = (int)((n + tpb - 1) / tpb);
+  int chunk, ptile;
+  decode_block(blockIdx.x, nptile, n_chunks, &chunk, &ptile);
+  const int64_t p = (int64_t)ptile * tpb + threadIdx.x;
+  const int64_t pc = p < n ? p : n - 1;
+
+  PhaseCoef c;
+  c.a0 = coef[C_A0 * ld + pc];
+  c.a2 = coef[C_A2 * ld + pc];
+  c.a3 = coef[C_A3 * ld + pc];
+  c.a4 = coef[C_A4 * ld + pc];
+  c.a5 = coef[C_A5 * ld + pc];
+  c.a6 = coef[C_A6 * ld + pc];
+  c.a7 = coef[C_A7 * ld + pc];
+  c.a8 = coef[C_A8 * ld + pc];
+  c.a10 = coef[C_A10 * ld + pc];
+  c.a12 = coef[C_A12 * ld + pc];
+  c.b5 = coef[C_B5 * ld + pc];
+  c.b6 = coef[C_B6 * ld + pc];
+
+  const int kb = chunk * chunk_len;
+  const int ke = kb + chunk_len < n_freq ? kb + chunk_len : n_freq;
+
+  double zr[ND], zi[ND];
+  double rr[ND], ri[ND];  // rho_i
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    zr[i] = 0.0;
+    zi[i] = 0.0;
+    rr[i] = 1.0;
+    ri[i] = 0.0;
+  }
+#pragma unroll
+  for (int i = 1; i < ND; ++i) {
+    const double dt = coef[(C_DT1 + i - 1) * ld + pc];
+    double s, co;
+    sincos_cycles(df * dt, T, &s, &co);
+    rr[i] = co;
+    ri[i] = -s;
+  }
+
+  // Descending walk so that the Horner recurrence leaves rho^0 on the first bin.
+  for (int k = ke - 1; k >= kb; --k) {
+    const double* __restrict__ rec = bins + (int64_t)k * RS;
+    const double x = rec[0], x2 = rec[1], xm5 = rec[2], lnf = rec[3];
+    const double r = phase_cycles(c, x, x2, xm5, lnf);
+    double gr, gi;
+    phasor<PREC>(r, T, &gr, &gi);
+    {
+      const double ur = rec[4], ui = rec[5];
+      zr[0] = fma(ur, gr, zr[0]);
+      zr[0] = fma(-ui, gi, zr[0]);
+      zi[0] = fma(ur, gi, zi[0]);
+      zi[0] = fma(ui, gr, zi[0]);
+    }
+#pragma unroll
+    for (int i = 1; i < ND; ++i) {
+      const double ur = rec[4 + 2 * i], ui = rec[5 + 2 * i];
+      double tr = zr[i] * rr[i];
+      tr = fma(-zi[i], ri[i], tr);
+      tr = fma(ur, gr, tr);
+      tr = fma(-ui, gi, tr);
+      double ti = zr[i] * ri[i];
+      ti = fma(zi[i], rr[i], ti);
+      ti = fma(ur, gi, ti);
+      ti = fma(ui, gr, ti);
+      zr[i] = tr;
+      zi[i] = ti;
+    }
+  }
+  // Apply exp(-2 pi i f_kb (tau_i - tau_0)) to the recurrences.
+#pragma unroll
+  for (int i = 1; i < ND; ++i) {
+    const double dt = coef[(C_DT1 + i - 1) * ld + pc];
+    const double fb = (double)(k0 + kb) * df;
+    double s, co;
+    sincos_cycles(fb * dt, T, &s, &co);
+    const double er = co, ei = -s;
+    const double tr = zr[i] * er - zi[i] * ei;
+    const double ti = zr[i] * ei + zi[i] * er;
+    zr[i] = tr;
+    zi[i] = ti;
+  }
+  if (p < n) {
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      partial[((int64_t)chunk * 2 * ND + 2 * i) * n + p] = zr[i];
+      partial[((int64_t)chunk * 2 * ND + 2 * i + 1) * n + p] = zi[i];
+    }
+  }
+}
+
+// Combine the chunk partials in chunk order and apply the marginalisation.
+// For the distance marginal this writes (|Z_1|, <h|h>_1) for k_dist_marg.
+__global__ void __launch_bounds__(256) k_epilogue(const double* __restrict__ partial, int n_chunks, int nd,
+                                                  const double* __restrict__ coef, int64_t ld, int64_t n,
+                                                  double dd, int marg, double* __restrict__ logl,
+                                                  double* __restrict__ zbuf) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const bool valid = coef[C_VALID * ld + p] != 0.0;
+  double Zr = 0.0, Zi = 0.0, plain = 0.0;
+  for (int i = 0; i < nd; ++i) {
+    double zr = 0.0, zi = 0.0;
+    for (int c = 0; c < n_chunks; ++c) {
+      zr += partial[((int64_t)c * 2 * nd + 2 * i) * n + p];
+      zi += partial[((int64_t)c * 2 * nd + 2 * i + 1) * n + p];
+    }
+    const double ar = coef[(C_APRE + i) * ld + p];
+    const double ai = coef[(C_APIM + i) * ld + p];
+    const double hr = ar * zr - ai * zi;
+    const double hi = ar * zi + ai * zr;
+    plain += hr;
+    Zr += hr;
+    Zi += hi;
+  }
+  const double hh = coef[C_HH * ld + p];
+  if (marg == 2) {
+    zbuf[p] = valid ? sqrt(Zr * Zr + Zi * Zi) : -1.0;
+    zbuf[n + p] = hh;
+    return;
+  }
+  double out;
+  if (!valid) {
+    out = -INFINITY;
+  } else if (marg == 0) {
+    out = -0.5 * dd + plain - 0.5 * hh;
+  } else {
+    out = -0.5 * dd - 0.5 * hh + log_i0(sqrt(Zr * Zr + Zi * Zi));
+  }
+  logl[p] = out;
+}
+
+// Distance marginal: one wave per proposal, lanes stride the d_L grid,
+// log-sum-exp by a fixed shuffle tree.
+__global__ void __launch_bounds__(256) k_dist_marg(const double* __restrict__ zbuf, int64_t n,
+                                                   const double* __restrict__ grid,
+                                                   const double* __restrict__ logw, int n_dist, double dd,
+                                                   double* __restrict__ logl) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (p >= n) return;
+  const double z1 = zbuf[p];
+  const double hh1 = zbuf[n + p];
+  if (z1 < 0.0) {
+    if (lane == 0) logl[p] = -INFINITY;
+    return;
+  }
+  double m = -INFINITY;
+  for (int j = lane; j < n_dist; j += 64) {
+    const double d = grid[j];
+    const double t = logw[j] - 0.5 * hh1 / (d * d) + log_i0(z1 / d);
+    m = fmax(m, t);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  double s = 0.0;
+  for (int j = lane; j < n_dist; j += 64) {
+    const double d = grid[j];
+    const double t = logw[j] - 0.5 * hh1 / (d * d) + log_i0(z1 / d);
+    s += exp(t - m);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) logl[p] = -0.5 * dd + m + log(s);
+}
+
+// Materialise h_i(f_k) = A P_i f^(-7/6) exp(-2 pi i Phi_i(f)) for injections.
+__global__ void __launch_bounds__(256) k_template(const double* __restrict__ coef, int64_t ld, int64_t n,
+                                                  const double* __restrict__ bins, int rs, int nd, int64_t k0,
+                                                  double df, int64_t n_freq, TrigConsts T,
+                                                  double* __restrict__ h) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = blockIdx.y;
+  if (k >= n_freq || p >= n) return;
+  const bool valid = coef[C_VALID * ld + p] != 0.0;
+  PhaseCoef c;
+  c.a0 = coef[C_A0 * ld + p];
+  c.a2 = coef[C_A2 * ld + p];
+  c.a3 = coef[C_A3 * ld + p];
+  c.a4 = coef[C_A4 * ld + p];
+  c.a5 = coef[C_A5 * ld + p];
+  c.a6 = coef[C_A6 * ld + p];
+  c.a7 = coef[C_A7 * ld + p];
+  c.a8 = coef[C_A8 * ld + p];
+  c.a10 = coef[C_A10 * ld + p];
+  c.a12 = coef[C_A12 * ld + p];
+  c.b5 = coef[C_B5 * ld + p];
+  c.b6 = coef[C_B6 * ld + p];
+  const double* rec = bins + k * rs;
+  const double r0 = phase_cycles(c, rec[0], rec[1], rec[2], rec[3]);
+  const double f = (double)(k0 + k) * df;
+  const double fa = pow(f, -7.0 / 6.0);
+  for (int i = 0; i < nd; ++i) {
+    const double dt = i == 0 ? 0.0 : coef[(C_DT1 + i - 1) * ld + p];
+    double s, co;
+    sincos_cycles(r0 + f * dt, T, &s, &co);
+    const double ar = coef[(C_APRE + i) * ld + p] * fa;
+    const double ai = coef[(C_APIM + i) * ld + p] * fa;
+    // (ar + i ai) (co - i s)
+    double* out = h + ((p * nd + i) * n_freq + k) * 2;
+    out[0] = valid ? ar * co + ai * s : 0.0;
+    out[1] = valid ? ai * co - ar * s : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+
+gw_status launch_prologue(gw_ctx* ctx, const double* theta, int64_t n, int marg, double* coef, int64_t ld,
+                          hipStream_t st) {
+  if (n == 0) return GW_OK;
+  const int tpb = 256;
+  const int64_t blocks = (n + tpb - 1) / tpb;
+  hipLaunchKernelGGL(k_prologue, dim3((unsigned)blocks), dim3(tpb), 0, st, theta, n, marg, ctx->geom, coef, ld);
+  return check_hip(hipGetLastError(), "prologue launch");
+}
+
+void full_launch_shape(const gw_ctx* ctx, int64_t n, int* tpb_out, int* chunks_out) {
+  int tpb = ctx->full_tpb;
+  int ch = ctx->full_chunks;
+  if (tpb <= 0) tpb = n >= 2048 ? 256 : 64;
+  const int64_t nptile = (n + tpb - 1) / tpb;
+  if (ch <= 0) {
+    // Aim for ~2048 workgroups, keep at least 32 bins per chunk.
+    int64_t want = (2048 + nptile - 1) / nptile;
+    want = (want + 7) / 8 * 8;
+    const int64_t maxc = ctx->geom.n_freq / 32 > 8 ? ctx->geom.n_freq / 32 : 8;
+    if (want > maxc) want = maxc / 8 * 8 > 0 ? maxc / 8 * 8 : 8;
+    if (want < 8) want = 8;
+    ch = (int)want;
+  }
+  *tpb_out = tpb;
+  *chunks_out = ch;
+}
+
+template <int ND>
+static gw_status launch_full_nd(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, int tpb,
+                                int n_chunks, double* partial, hipStream_t st) {
+  const int nf = (int)ctx->geom.n_freq;
+  const int chunk_len = (int)((nf + n_chunks - 1) / n_chunks);
+  const TrigConsts T = make_trig_consts();
+  const int64_t nptile = (n + tpb - 1) / tpb;
+  const int64_t blocks = nptile * n_chunks;
+  if (blocks > 0x7fffffff) return set_error(GW_EINVAL, "batch too large for one launch");
+  if (prec == GW_PREC_FP64) {
+    hipLaunchKernelGGL((k_full<ND, 0>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
+                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, partial);
+  } else {
+    hipLaunchKernelGGL((k_full<ND, 1>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
+                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, partial);
+  }
+  return check_hip(hipGetLastError(), "full-band kernel launch");
+}
+
+gw_status launch_full(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, int tpb, int n_chunks,
+                      double* partial, hipStream_t st) {
+  if (n == 0) return GW_OK;
+  if (tpb != 64 && tpb != 128 && tpb != 256) return set_error(GW_EINVAL, "tpb must be 64, 128 or 256");
+  if (n_chunks < 1) return set_error(GW_EINVAL, "n_chunks must be >= 1");
+  switch (ctx->n_det) {
+    case 1: return launch_full_nd<1>(ctx, coef, ld, n, prec, tpb, n_chunks, partial, st);
+    case 2: return launch_full_nd<2>(ctx, coef, ld, n, prec, tpb, n_chunks, partial, st);
+    case 3: return launch_full_nd<3>(ctx, coef, ld, n, prec, tpb, n_chunks, partial, st);
+    case 4: return launch_full_nd<4>(ctx, coef, ld, n, prec, tpb, n_chunks, partial, st);
+    default: return set_error(GW_ENOTSUP, "n_det %d not supported", ctx->n_det);
+  }
+}
+
+gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, const double* coef, int64_t ld,
+                          int64_t n, int marg, double* logl, hipStream_t st) {
+  if (n == 0) return GW_OK;
+  const int tpb = 256;
+  const int64_t blocks = (n + tpb - 1) / tpb;
+  hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(tpb), 0, st, partial, n_chunks, ctx->n_det, coef, ld,
+                     n, ctx->dd, marg, logl, ctx->zbuf);
+  gw_status s = check_hip(hipGetLastError(), "epilogue launch");
+  if (s != GW_OK || marg != 2) return s;
+  const int64_t dblocks = (n + 3) / 4;
+  hipLaunchKernelGGL(k_dist_marg, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_grid,
+                     ctx->dist_logw, ctx->n_dist, ctx->dd, logl);
+  return check_hip(hipGetLastError(), "distance marginal launch");
+}
+
+gw_status launch_template(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, double* h, hipStream_t st) {
+  if (n == 0) return GW_OK;
+  if (n > 65535) return set_error(GW_EINVAL, "gw_template: at most 65535 rows per call");
+  const int tpb = 256;
+  const int64_t bx = (ctx->geom.n_freq + tpb - 1) / tpb;
+  hipLaunchKernelGGL(k_template, dim3((unsigned)bx, (unsigned)n), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
+                     ctx->rec_stride, ctx->n_det, ctx->geom.k0, ctx->geom.df, ctx->geom.n_freq, make_trig_consts(), h);
+  return check_hip(hipGetLastError(), "template launch");
+}
+
+}  // namespace gw
