@@ -142,6 +142,66 @@ gw_status loglike_batch(gw_ctx* ctx, const double* theta, int64_t n, int32_t lik
 gw_status gw_template(gw_ctx* ctx, const double* theta, int64_t n, double* h, void* stream);
 
 /*
+ * Heterodyne (relative-binning) set-up, Sec. III.D: builds the bin grid of
+ * "equal maximum phase change" shared across the network and the
+ * per-detector summary data of the reference template h0 = h(theta0).
+ *   theta0     host [13] reference parameters (must be physical)
+ *   n_bins     requested bins, 1 .. n_freq - 1; edges are snapped to the
+ *              fine grid and merged, so the context may hold fewer (see
+ *              gw_het_info)
+ *   bin_rule   0: equal steps of the phase bound
+ *                 sum_g sgn(g) (f / f*_g)^g, g in {-5/3, -2/3, 1, 5/3, 7/3},
+ *                 f*_g = f_max for g > 0 else f_min;
+ *              1: geometric (log-spaced) edges
+ *   edges_out  host [n_bins + 1] edge frequencies (Hz), or NULL; only the
+ *              first (held bins + 1) entries are written
+ * Replaces any previous summary data and drops captured graphs.  Blocks
+ * until the set-up has completed.  Errors: GW_EINVAL, GW_EDEVICE, GW_ENOMEM.
+ */
+gw_status heterodyne_setup(gw_ctx* ctx, const double* theta0, int32_t n_bins, int32_t bin_rule,
+                           double* edges_out);
+
+/* Number of bins held after heterodyne_setup.  GW_ESTATE before set-up. */
+gw_status gw_het_info(const gw_ctx* ctx, int32_t* n_bins);
+
+/*
+ * Batched log-likelihood over uneven sub-batches in one launch sequence
+ * (persistent work-list kernels; with use_graph != 0 the sequence is
+ * captured once per (marg, prec, launch shape) into a hipGraph and replayed).
+ *   theta     device [n_rows, 13]
+ *   subs      device int64 [2 * n_sub]: (row offset, row count) pairs; rows
+ *             outside [0, n_rows) are clipped, counts <= 0 are empty
+ *   n_sub     number of sub-batches, 0 .. 65536
+ *   like      GW_HET (the full-band form returns GW_ENOTSUP)
+ *   logl      device [n_rows]; only rows covered by a sub-batch are written
+ * The work list is read on the device, so one captured graph serves every
+ * sub-batch layout.  Errors as loglike_batch.
+ */
+gw_status loglike_batch_uneven(gw_ctx* ctx, const double* theta, int64_t n_rows, const int64_t* subs,
+                               int32_t n_sub, int32_t like, int32_t marg, int32_t prec, int32_t use_graph,
+                               double* logl, void* stream);
+
+/* Launch shape of the heterodyned kernels: waves per workgroup (1, 2, 4) and
+ * persistent grid size in workgroups (0 = heuristic). */
+gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid);
+
+/* Number of instantiated graphs and the last instantiation time (ms), which
+ * plays the role of a one-off compilation cost. */
+gw_status gw_graph_info(const gw_ctx* ctx, int32_t* n_graphs, double* last_instantiate_ms);
+
+/*
+ * Autotuner: times every candidate launch shape of the full-band (like =
+ * GW_FULL) or heterodyned (GW_HET) kernels on the caller's batch ``theta``
+ * (device [n, 13]), ``reps`` timed calls each after one warm-up, keeps the
+ * fastest in the context and returns it: best_shape[0..1] = (proposals per
+ * workgroup, frequency chunks) for the full band or (waves per workgroup,
+ * persistent workgroups) for the heterodyned form; *best_ms the mean time of
+ * one call.  Synchronises the stream.  Errors as loglike_batch.
+ */
+gw_status gw_autotune(gw_ctx* ctx, const double* theta, int64_t n, int32_t like, int32_t marg, int32_t prec,
+                      int32_t reps, int32_t* best_shape, double* best_ms, void* stream);
+
+/*
  * Launch shape of the full-band kernel: ``tpb`` proposals per workgroup
  * (64, 128 or 256) and ``n_chunks`` frequency chunks (a multiple of 8 keeps
  * every chunk on one XCD).  0 restores the built-in heuristic.  Used by the

@@ -10,7 +10,8 @@ from . import _lib  # noqa: F401
 from ._lib import (  # noqa: F401
     GW_FULL, GW_HET, GW_MARG_NONE, GW_MARG_PHASE, GW_MARG_PHASE_DIST, GW_PREC_FP64, GW_PREC_MIXED,
     GwError, gw_ctx_create, gw_ctx_destroy, gw_data_inner, gw_last_error, gw_set_full_shape, gw_template,
-    gw_version, loglike_batch,
+    gw_version, loglike_batch, heterodyne_setup, gw_het_info, loglike_batch_uneven, gw_set_het_shape,
+    gw_graph_info, gw_profile_enable, gw_profile_read,
 )
 
 
@@ -32,6 +33,16 @@ class Context:
 
     def template(self, theta, stream=None):
         return gw_template(self._ctx, theta, self.n_det, self.n_freq, stream)
+
+    def heterodyne_setup(self, theta0, n_bins: int, bin_rule: int = 0):
+        return heterodyne_setup(self._ctx, theta0, n_bins, bin_rule)
+
+    def loglike_uneven(self, theta, subs, marg=GW_MARG_NONE, prec=GW_PREC_FP64, use_graph=True, out=None,
+                       stream=None):
+        return loglike_batch_uneven(self._ctx, theta, subs, GW_HET, marg, prec, use_graph, out, stream)
+
+    def set_het_shape(self, waves_per_block: int = 4, grid: int = 0):
+        gw_set_het_shape(self._ctx, waves_per_block, grid)
 
     def data_inner(self) -> float:
         return gw_data_inner(self._ctx)

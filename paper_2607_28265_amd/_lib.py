@@ -60,6 +60,16 @@ _SIGS = {
     "gw_template": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     "gw_set_full_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "gw_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "heterodyne_setup": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "gw_het_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "loglike_batch_uneven": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "gw_set_het_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "gw_autotune": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                   _P]),
+    "gw_graph_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "gw_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
 
@@ -197,3 +207,59 @@ def gw_profile_read(ctx):
     n = ctypes.c_int64()
     check(load().gw_profile_read(ctx, ctypes.byref(ms), ctypes.byref(n)), "gw_profile_read")
     return ms.value, n.value
+
+
+def heterodyne_setup(ctx, theta0, n_bins: int, bin_rule: int = 0):
+    """Build the relative-binning summary data; returns the edge frequencies (numpy)."""
+    import numpy as np
+    th = np.ascontiguousarray(theta0, dtype=np.float64)
+    if th.shape != (GW_NPARAM,):
+        raise ValueError("theta0 must have 13 entries")
+    edges = np.zeros(n_bins + 1)
+    check(load().heterodyne_setup(ctx, _dptr(th), n_bins, bin_rule, _dptr(edges)), "heterodyne_setup")
+    nb = gw_het_info(ctx)
+    return edges[:nb + 1]
+
+
+def gw_het_info(ctx) -> int:
+    v = ctypes.c_int32()
+    check(load().gw_het_info(ctx, ctypes.byref(v)), "gw_het_info")
+    return v.value
+
+
+def loglike_batch_uneven(ctx, theta, subs, like: int = GW_HET, marg: int = GW_MARG_NONE,
+                         prec: int = GW_PREC_FP64, use_graph: bool = True, out=None, stream=None):
+    """Sub-batches ``subs`` (CUDA int64 [n_sub, 2] of (row offset, count)) in one launch sequence."""
+    import torch
+    _check_theta(theta)
+    if not (subs.is_cuda and subs.dtype == torch.int64 and subs.is_contiguous() and subs.dim() == 2
+            and subs.shape[1] == 2):
+        raise ValueError("subs must be a contiguous CUDA int64 tensor of shape [n_sub, 2]")
+    n = theta.shape[0]
+    if out is None:
+        out = torch.full((n,), float("nan"), dtype=torch.float64, device=theta.device)
+    check(load().loglike_batch_uneven(ctx, _tensor_ptr(theta), n, _tensor_ptr(subs), subs.shape[0], like, marg,
+                                      prec, 1 if use_graph else 0, _tensor_ptr(out), _stream_ptr(stream)),
+          "loglike_batch_uneven")
+    return out
+
+
+def gw_set_het_shape(ctx, waves_per_block: int, grid: int):
+    check(load().gw_set_het_shape(ctx, waves_per_block, grid), "gw_set_het_shape")
+
+
+def gw_graph_info(ctx):
+    n = ctypes.c_int32()
+    ms = ctypes.c_double()
+    check(load().gw_graph_info(ctx, ctypes.byref(n), ctypes.byref(ms)), "gw_graph_info")
+    return n.value, ms.value
+
+
+def gw_autotune(ctx, theta, like: int, marg: int, prec: int, reps: int = 3, stream=None):
+    """Pick the fastest launch shape on ``theta``; returns ((a, b), ms per call)."""
+    _check_theta(theta)
+    shape = (ctypes.c_int32 * 2)()
+    ms = ctypes.c_double()
+    check(load().gw_autotune(ctx, _tensor_ptr(theta), theta.shape[0], like, marg, prec, reps, shape,
+                             ctypes.byref(ms), _stream_ptr(stream)), "gw_autotune")
+    return (shape[0], shape[1]), ms.value

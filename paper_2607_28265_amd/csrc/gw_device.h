@@ -69,6 +69,7 @@ __device__ inline void prologue(const double* __restrict__ th, int marg, const G
   ok = ok && mc > 0.0 && q > 0.0 && q <= 1.0 && fabs(c1) < 1.0 && fabs(c2) < 1.0;
   if (marg != 2) ok = ok && dl > 0.0;
   if (!ok) {
+#pragma unroll
     for (int c = 0; c < C_NCOEF; ++c) out[c * ld] = 0.0;
     return;
   }
@@ -153,6 +154,7 @@ __device__ inline void prologue(const double* __restrict__ th, int marg, const G
   const double ci = cos(iota);
   const double pp = 0.5 * (1.0 + ci * ci);
   double tau0 = 0.0, hh = 0.0;
+#pragma unroll
   for (int i = 0; i < kMaxDet; ++i) {
     double fp = 0.0, fx = 0.0, dt = 0.0;
     if (i < g.n_det) {
@@ -193,6 +195,7 @@ __device__ inline void prologue(const double* __restrict__ th, int marg, const G
   out[C_HH * ld] = hh;
   out[C_TAU0 * ld] = tau0;
   out[C_AMP * ld] = amp;
+#pragma unroll
   for (int c = C_AMP + 1; c < C_NCOEF; ++c) out[c * ld] = 0.0;
 }
 

@@ -1,19 +1,807 @@
-// Heterodyned (relative-binning) likelihood: set-up and evaluation.
+// Heterodyned (relative-binning) likelihood, Sec. III.D.
+//
+// Set-up (once per reference parameters theta0): bin edges of equal maximum
+// phase change on the host, then on the device the reference phase at the
+// edges and the per-detector summary data A0, A1 (data x reference) and
+// B0, B1 (reference norm) per bin, by segmented sums over the fine grid with a
+// fixed-order workgroup reduction.
+//
+// Evaluation: one lane per proposal, edge records wave-uniform (scalar loads).
+// For TaylorF2 without a cut-off the ratio r_i = h_i / h0_i at an edge is
+// (A P_i / A0 P0_i) exp(-2 pi i (Phi_i - Phi0_i)); the complex prefactor is
+// pulled out of the bin sums, so per edge a lane evaluates the FP64 phase
+// difference per detector, one phasor each, and the linear-in-bin contraction
+// with the summary data.  Work arrives as a device-resident list of
+// (row offset, count) sub-batches; a persistent grid of waves walks 64-row
+// tiles of that list, so one launch (and one captured hipGraph) serves any
+// sub-batch layout.  The distance marginal is evaluated inside the same wave.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <vector>
+
 #include "gw_ctx.h"
 
-struct gw_het_state {};
-struct gw_graph_cache {};
+// Device-resident arguments of the work-list kernels; a one-thread kernel
+// writes them before each launch so that a captured graph can be replayed
+// with new buffers.
+struct HetArgs {
+  const double* theta;
+  const int64_t* subs;  // (row offset, count) pairs
+  double* logl;
+  double* coef;         // per-row coefficients [C_NCOEF][ld]
+  int64_t n_rows;
+  int64_t ld;
+  int32_t n_sub;
+  int32_t pad;
+};
+
+struct gw_het_state {
+  int n_bins = 0;
+  int n_edges = 0;
+  int rs = 0;                    // record stride (doubles)
+  double* rec = nullptr;         // [n_edges][rs]
+  std::vector<double> f_edges;   // host copy
+  std::vector<double> theta0;
+  double ap0_inv_re[gw::kMaxDet] = {0};
+  double ap0_inv_im[gw::kMaxDet] = {0};
+  // work-list machinery
+  HetArgs* args = nullptr;       // device
+  int64_t* tile_pre = nullptr;   // device [max_sub + 1]
+  int64_t* subs_single = nullptr;  // device [2]
+  int max_sub = 0;
+  // launch shape of the evaluation kernel
+  int wpb = 4;                   // waves per workgroup
+  int grid = 0;                  // workgroups (0 = heuristic)
+};
+
+struct GraphKey {
+  int marg, prec, wpb, grid;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(marg, prec, wpb, grid) < std::tie(o.marg, o.prec, o.wpb, o.grid);
+  }
+};
+
+struct gw_graph_cache {
+  std::map<GraphKey, hipGraphExec_t> exec;
+  std::map<GraphKey, hipGraph_t> graph;
+  hipStream_t cap_stream = nullptr;
+  double last_instantiate_ms = 0.0;
+};
 
 namespace gw {
 
-void het_free(gw_ctx* ctx) { ctx->het = nullptr; }
-void graphs_free(gw_ctx* ctx) { ctx->graphs = nullptr; }
+constexpr int kMaxSub = 1 << 16;
 
-gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl,
-                      hipStream_t st) {
-  (void)theta; (void)n; (void)marg; (void)prec; (void)logl; (void)st;
+// Record layout of one edge e (bin e-1 data rides along with edge e).
+__host__ __device__ constexpr int het_rs(int nd) { return 6 + 7 * nd; }
+enum HetRec { H_X = 0, H_X2 = 1, H_XM5 = 2, H_LNF = 3, H_F = 4, H_PHI0 = 5 };  // then f dtau0_i (i >= 1)
+__host__ __device__ constexpr int het_bin_off(int nd) { return 5 + nd; }      // inv width, then 6 per det
+
+// ---------------------------------------------------------------------------
+// Set-up kernels
+
+__global__ void k_het_edges(const double* __restrict__ bins, int bin_rs, const int64_t* __restrict__ edge_idx,
+                            int n_edges, int nd, const double* __restrict__ coef0, TrigConsts T, int64_t k0,
+                            double df, double* __restrict__ rec) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_edges) return;
+  const int rs = het_rs(nd);
+  const int64_t k = edge_idx[e];
+  const double* b = bins + k * bin_rs;
+  PhaseCoef c;
+  c.a0 = coef0[C_A0]; c.a2 = coef0[C_A2]; c.a3 = coef0[C_A3]; c.a4 = coef0[C_A4];
+  c.a5 = coef0[C_A5]; c.a6 = coef0[C_A6]; c.a7 = coef0[C_A7]; c.a8 = coef0[C_A8];
+  c.a10 = coef0[C_A10]; c.a12 = coef0[C_A12]; c.b5 = coef0[C_B5]; c.b6 = coef0[C_B6];
+  const double f = (double)(k0 + k) * df;
+  double* r = rec + (int64_t)e * rs;
+  r[H_X] = b[0];
+  r[H_X2] = b[1];
+  r[H_XM5] = b[2];
+  r[H_LNF] = b[3];
+  r[H_F] = f;
+  r[H_PHI0] = phase_cycles(c, b[0], b[1], b[2], b[3]);
+  for (int i = 1; i < nd; ++i) r[H_PHI0 + i] = f * coef0[C_DT1 + i - 1];
+  const int bo = het_bin_off(nd);
+  if (e > 0) {
+    const double fl = (double)(k0 + edge_idx[e - 1]) * df;
+    r[bo] = 1.0 / (f - fl);
+  } else {
+    for (int j = bo; j < rs; ++j) r[j] = 0.0;
+  }
+  (void)T;
+}
+
+// One workgroup per (bin, detector): segmented sums over the fine bins of the
+// bin with a fixed-order LDS tree.
+__global__ void __launch_bounds__(256) k_het_summary(const double* __restrict__ bins, int bin_rs,
+                                                     const double* __restrict__ hw, int64_t n_freq,
+                                                     const int64_t* __restrict__ edge_idx, int n_bins,
+                                                     const double* __restrict__ coef0, TrigConsts T, int64_t k0,
+                                                     double df, double* __restrict__ rec, int nd) {
+  const int b = blockIdx.x;
+  const int i = blockIdx.y;
+  const int64_t lo = edge_idx[b];
+  const int64_t hi = edge_idx[b + 1];
+  const int64_t stop = (b == n_bins - 1) ? hi + 1 : hi;
+  const double fc = 0.5 * ((double)(k0 + lo) + (double)(k0 + hi)) * df;
+  PhaseCoef c;
+  c.a0 = coef0[C_A0]; c.a2 = coef0[C_A2]; c.a3 = coef0[C_A3]; c.a4 = coef0[C_A4];
+  c.a5 = coef0[C_A5]; c.a6 = coef0[C_A6]; c.a7 = coef0[C_A7]; c.a8 = coef0[C_A8];
+  c.a10 = coef0[C_A10]; c.a12 = coef0[C_A12]; c.b5 = coef0[C_B5]; c.b6 = coef0[C_B6];
+  const double dt = i == 0 ? 0.0 : coef0[C_DT1 + i - 1];
+  const double apr = coef0[C_APRE + i], api = coef0[C_APIM + i];
+  const double ap2 = apr * apr + api * api;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t k = lo + threadIdx.x; k < stop; k += blockDim.x) {
+    const double* r = bins + k * bin_rs;
+    const double f = (double)(k0 + k) * df;
+    const double ph = phase_cycles(c, r[0], r[1], r[2], r[3]) + f * dt;
+    double s, co;
+    sincos_cycles(ph, T, &s, &co);
+    // 4 df d* h0 / S = u_ik (A P0_i) exp(-2 pi i phi)
+    const double ur = r[4 + 2 * i], ui = r[5 + 2 * i];
+    const double gr = apr * co + api * s, gi = api * co - apr * s;
+    const double tr = ur * gr - ui * gi, ti = ur * gi + ui * gr;
+    const double w = ap2 * hw[(int64_t)i * n_freq + k];
+    const double dfc = f - fc;
+    acc[0] += tr;
+    acc[1] += ti;
+    acc[2] += tr * dfc;
+    acc[3] += ti * dfc;
+    acc[4] += w;
+    acc[5] += w * dfc;
+  }
+  __shared__ double red[6][256];
+  for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = acc[j];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int j = 0; j < 6; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* r = rec + (int64_t)(b + 1) * het_rs(nd) + het_bin_off(nd) + 1 + 6 * i;
+    r[0] = red[0][0];
+    r[1] = red[1][0];
+    r[2] = red[2][0];
+    r[3] = red[3][0];
+    r[4] = red[4][0];
+    r[5] = 2.0 * red[5][0];  // 2 B1
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Work-list kernels
+
+__global__ void k_set_args(HetArgs* a, const double* theta, const int64_t* subs, double* logl, double* coef,
+                           int64_t n_rows, int32_t n_sub, int64_t* subs_single, int64_t single_n) {
+  a->theta = theta;
+  a->subs = subs;
+  a->logl = logl;
+  a->coef = coef;
+  a->n_rows = n_rows;
+  a->ld = n_rows;
+  a->n_sub = n_sub;
+  a->pad = 0;
+  if (subs_single) {
+    subs_single[0] = 0;
+    subs_single[1] = single_n;
+  }
+}
+
+// Prefix sums of 64-row tiles per sub-batch: tile_pre[s] = tiles before s.
+__global__ void __launch_bounds__(256) k_tile_scan(const HetArgs* __restrict__ a, int64_t* __restrict__ pre) {
+  const int n_sub = a->n_sub;
+  const int64_t n_rows = a->n_rows;
+  const int64_t* subs = a->subs;
+  __shared__ int64_t part[256];
+  const int per = (n_sub + 255) / 256;
+  const int s0 = threadIdx.x * per;
+  const int s1 = min(s0 + per, n_sub);
+  int64_t sum = 0;
+  for (int s = s0; s < s1; ++s) {
+    int64_t cnt = subs[2 * s + 1];
+    const int64_t off = subs[2 * s];
+    if (off < 0 || off >= n_rows || cnt <= 0) cnt = 0;
+    else if (cnt > n_rows - off) cnt = n_rows - off;
+    sum += (cnt + 63) / 64;
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int j = 0; j < 256; ++j) {
+      const int64_t v = part[j];
+      part[j] = run;
+      run += v;
+    }
+    pre[n_sub] = run;
+  }
+  __syncthreads();
+  int64_t run = part[threadIdx.x];
+  for (int s = s0; s < s1; ++s) {
+    pre[s] = run;
+    int64_t cnt = subs[2 * s + 1];
+    const int64_t off = subs[2 * s];
+    if (off < 0 || off >= n_rows || cnt <= 0) cnt = 0;
+    else if (cnt > n_rows - off) cnt = n_rows - off;
+    run += (cnt + 63) / 64;
+  }
+}
+
+// Tile t of the work list -> (first row, one-past-last row); returns false
+// for an empty tile.
+__device__ inline bool tile_rows(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre, int64_t t,
+                                 int64_t* row0, int64_t* row_end) {
+  int lo = 0, hi = ab->n_sub;  // invariant pre[lo] <= t < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  const int64_t off = ab->subs[2 * lo];
+  int64_t cnt = ab->subs[2 * lo + 1];
+  if (cnt > ab->n_rows - off) cnt = ab->n_rows - off;
+  *row0 = off + (t - pre[lo]) * 64;
+  *row_end = off + cnt;
+  return *row0 < *row_end;
+}
+
+// Per-row prologue over the work list (same tiles as the evaluation kernel).
+__global__ void __launch_bounds__(256) k_het_prologue(const HetArgs* __restrict__ ab,
+                                                      const int64_t* __restrict__ pre, int marg, Geom geom) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * wpb;
+  const int64_t total = pre[ab->n_sub];
+  const int64_t ld = ab->ld;
+  for (int64_t t = wid; t < total; t += nwaves) {
+    int64_t row0, row_end;
+    if (!tile_rows(ab, pre, t, &row0, &row_end)) continue;
+    const int64_t row = row0 + lane;
+    if (row < row_end) prologue(ab->theta + row * 13, marg, geom, ab->coef + row, ld);
+  }
+}
+
+struct HetConst {
+  double ap0_inv_re[kMaxDet];
+  double ap0_inv_im[kMaxDet];
+  double dd;
+};
+
+template <int PREC>
+__device__ inline void het_phasor(double r, const TrigConsts& T, double* gr, double* gi) {
+  if (PREC == 0) {
+    double s, c;
+    sincos_cycles(r, T, &s, &c);
+    *gr = c;
+    *gi = -s;
+  } else {
+    const float t = (float)(r - rint(r));
+    *gr = (double)__builtin_amdgcn_cosf(t);
+    *gi = -(double)__builtin_amdgcn_sinf(t);
+  }
+}
+
+template <int ND, int PREC>
+__global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
+                                             const double* __restrict__ rec, int n_edges, int marg, HetConst hc,
+                                             const double* __restrict__ dgrid, const double* __restrict__ dlogw,
+                                             int n_dist, TrigConsts T) {
+  constexpr int RS = het_rs(ND);
+  constexpr int BO = het_bin_off(ND);
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * wpb;
+  const int64_t total = pre[ab->n_sub];
+  const int64_t ld = ab->ld;
+  const double* __restrict__ coef = ab->coef;
+  double* logl = ab->logl;
+
+  for (int64_t t = wid; t < total; t += nwaves) {
+    int64_t row0, row_end;
+    if (!tile_rows(ab, pre, t, &row0, &row_end)) continue;
+    const int64_t row = row0 + lane;
+    const bool active = row < row_end;
+    const int64_t rr = active ? row : row0;
+    const double* cf = coef + rr;
+    PhaseCoef c;
+    c.a0 = cf[C_A0 * ld]; c.a2 = cf[C_A2 * ld]; c.a3 = cf[C_A3 * ld]; c.a4 = cf[C_A4 * ld];
+    c.a5 = cf[C_A5 * ld]; c.a6 = cf[C_A6 * ld]; c.a7 = cf[C_A7 * ld]; c.a8 = cf[C_A8 * ld];
+    c.a10 = cf[C_A10 * ld]; c.a12 = cf[C_A12 * ld]; c.b5 = cf[C_B5 * ld]; c.b6 = cf[C_B6 * ld];
+    double dt[ND];
+    dt[0] = 0.0;
+#pragma unroll
+    for (int i = 1; i < ND; ++i) dt[i] = cf[(C_DT1 + i - 1) * ld];
+
+    double zr[ND], zi[ND], hh[ND], pr[ND], pi[ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      zr[i] = zi[i] = hh[i] = 0.0;
+      pr[i] = pi[i] = 0.0;
+    }
+    for (int e = 0; e < n_edges; ++e) {
+      const double* __restrict__ r = rec + (int64_t)e * RS;
+      const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
+      const double f = r[H_F];
+      const double inv = r[BO];
+#pragma unroll
+      for (int i = 0; i < ND; ++i) {
+        const double di = i == 0 ? d0 : fma(f, dt[i], d0) - r[H_PHI0 + i];
+        double gr, gi;
+        het_phasor<PREC>(di, T, &gr, &gi);
+        if (e > 0) {
+          const double* __restrict__ bd = r + BO + 1 + 6 * i;
+          const double r0r = 0.5 * (gr + pr[i]), r0i = 0.5 * (gi + pi[i]);
+          const double r1r = (gr - pr[i]) * inv, r1i = (gi - pi[i]) * inv;
+          zr[i] = fma(bd[0], r0r, zr[i]);
+          zr[i] = fma(-bd[1], r0i, zr[i]);
+          zr[i] = fma(bd[2], r1r, zr[i]);
+          zr[i] = fma(-bd[3], r1i, zr[i]);
+          zi[i] = fma(bd[0], r0i, zi[i]);
+          zi[i] = fma(bd[1], r0r, zi[i]);
+          zi[i] = fma(bd[2], r1i, zi[i]);
+          zi[i] = fma(bd[3], r1r, zi[i]);
+          const double m = fma(r0r, r0r, r0i * r0i);
+          const double x = fma(r0r, r1r, r0i * r1i);
+          hh[i] = fma(bd[4], m, hh[i]);
+          hh[i] = fma(bd[5], x, hh[i]);
+        }
+        pr[i] = gr;
+        pi[i] = gi;
+      }
+    }
+    // Restore the prefactor (A P_i) / (A0 P0_i) and combine detectors.
+    double Zr = 0.0, Zi = 0.0, plain = 0.0, hht = 0.0;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const double ar = cf[(C_APRE + i) * ld], ai = cf[(C_APIM + i) * ld];
+      const double qr = ar * hc.ap0_inv_re[i] - ai * hc.ap0_inv_im[i];
+      const double qi = ar * hc.ap0_inv_im[i] + ai * hc.ap0_inv_re[i];
+      const double wr = qr * zr[i] - qi * zi[i];
+      const double wi = qr * zi[i] + qi * zr[i];
+      plain += wr;
+      Zr += wr;
+      Zi += wi;
+      hht += (qr * qr + qi * qi) * hh[i];
+    }
+    const bool valid = active && cf[C_VALID * ld] != 0.0;
+    const double zabs = sqrt(Zr * Zr + Zi * Zi);
+    if (marg != 2) {
+      if (active) {
+        double out;
+        if (!valid) out = -INFINITY;
+        else if (marg == 0) out = -0.5 * hc.dd + plain - 0.5 * hht;
+        else out = -0.5 * hc.dd - 0.5 * hht + log_i0(zabs);
+        logl[row] = out;
+      }
+    } else {
+      // Distance marginal: the wave takes its 64 proposals one at a time,
+      // lanes stride the distance grid, fixed shuffle-tree reductions.
+      double mine = -INFINITY;
+      for (int j = 0; j < 64; ++j) {
+        const int vj = __shfl(valid ? 1 : 0, j, 64);
+        if (!vj) continue;
+        const double z1 = __shfl(zabs, j, 64);
+        const double h1 = __shfl(hht, j, 64);
+        double m = -INFINITY;
+        for (int q = lane; q < n_dist; q += 64) {
+          const double d = dgrid[q];
+          m = fmax(m, dlogw[q] - 0.5 * h1 / (d * d) + log_i0(z1 / d));
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        double sum = 0.0;
+        for (int q = lane; q < n_dist; q += 64) {
+          const double d = dgrid[q];
+          sum += exp(dlogw[q] - 0.5 * h1 / (d * d) + log_i0(z1 / d) - m);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (lane == j) mine = -0.5 * hc.dd + m + log(sum);
+      }
+      if (active) logl[row] = valid ? mine : -INFINITY;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+
+static void free_state(gw_het_state* h) {
+  if (!h) return;
+  if (h->rec) (void)hipFree(h->rec);
+  if (h->args) (void)hipFree(h->args);
+  if (h->tile_pre) (void)hipFree(h->tile_pre);
+  if (h->subs_single) (void)hipFree(h->subs_single);
+  delete h;
+}
+
+void het_free(gw_ctx* ctx) {
+  free_state(ctx->het);
+  ctx->het = nullptr;
+}
+
+static void graphs_clear(gw_graph_cache* g) {
+  for (auto& kv : g->exec) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : g->graph) (void)hipGraphDestroy(kv.second);
+  g->exec.clear();
+  g->graph.clear();
+}
+
+void graphs_free(gw_ctx* ctx) {
+  if (!ctx->graphs) return;
+  graphs_clear(ctx->graphs);
+  if (ctx->graphs->cap_stream) (void)hipStreamDestroy(ctx->graphs->cap_stream);
+  delete ctx->graphs;
+  ctx->graphs = nullptr;
+}
+
+// Edge indices of the bin grid (host, FP64); see heterodyne_setup in gwswig.h.
+static std::vector<int64_t> make_edges(const Geom& g, int n_bins, int rule) {
+  const int64_t n = g.n_freq;
+  std::vector<double> f(n);
+  for (int64_t k = 0; k < n; ++k) f[k] = (double)(g.k0 + k) * g.df;
+  const double fmin = f[0], fmax = f[n - 1];
+  std::vector<double> fe(n_bins + 1);
+  if (rule == 0) {
+    const double gam[5] = {-5.0 / 3.0, -2.0 / 3.0, 1.0, 5.0 / 3.0, 7.0 / 3.0};
+    std::vector<double> phi(n);
+    for (int64_t k = 0; k < n; ++k) {
+      double s = 0.0;
+      for (double gg : gam) {
+        const double fs = gg > 0 ? fmax : fmin;
+        s += (gg > 0 ? 1.0 : -1.0) * pow(f[k] / fs, gg);
+      }
+      phi[k] = s;
+    }
+    int64_t k = 0;
+    for (int j = 0; j <= n_bins; ++j) {
+      const double y = phi[0] + j * (phi[n - 1] - phi[0]) / n_bins;
+      while (k + 1 < n - 1 && phi[k + 1] <= y) ++k;
+      if (y <= phi[0]) fe[j] = f[0];
+      else if (y >= phi[n - 1]) fe[j] = f[n - 1];
+      else fe[j] = f[k] + (y - phi[k]) * (f[k + 1] - f[k]) / (phi[k + 1] - phi[k]);
+    }
+  } else {
+    for (int j = 0; j <= n_bins; ++j) fe[j] = fmin * pow(fmax / fmin, (double)j / n_bins);
+  }
+  std::vector<int64_t> idx(n_bins + 1);
+  for (int j = 0; j <= n_bins; ++j) {
+    int64_t v = (int64_t)rint((fe[j] - fmin) / (f[1 < n ? 1 : 0] - f[0] + (n > 1 ? 0.0 : 1.0)));
+    idx[j] = std::min<int64_t>(std::max<int64_t>(v, 0), n - 1);
+  }
+  idx[0] = 0;
+  idx[n_bins] = n - 1;
+  std::sort(idx.begin(), idx.end());
+  idx.erase(std::unique(idx.begin(), idx.end()), idx.end());
+  return idx;
+}
+
+template <int ND>
+static gw_status launch_het_nd(gw_ctx* ctx, int marg, int prec, hipStream_t st) {
+  gw_het_state* h = ctx->het;
+  HetConst hc;
+  for (int i = 0; i < kMaxDet; ++i) {
+    hc.ap0_inv_re[i] = h->ap0_inv_re[i];
+    hc.ap0_inv_im[i] = h->ap0_inv_im[i];
+  }
+  hc.dd = ctx->dd;
+  const TrigConsts T = make_trig_consts();
+  const int tpb = 64 * h->wpb;
+  int grid = h->grid;
+  if (grid <= 0) grid = 256 * 8 / h->wpb;  // 8 waves per CU
+  if (prec == GW_PREC_FP64)
+    hipLaunchKernelGGL((k_het<ND, 0>), dim3(grid), dim3(tpb), 0, st, h->args, h->tile_pre, h->rec, h->n_edges, marg,
+                       hc, ctx->dist_grid, ctx->dist_logw, ctx->n_dist, T);
+  else
+    hipLaunchKernelGGL((k_het<ND, 1>), dim3(grid), dim3(tpb), 0, st, h->args, h->tile_pre, h->rec, h->n_edges, marg,
+                       hc, ctx->dist_grid, ctx->dist_logw, ctx->n_dist, T);
+  return check_hip(hipGetLastError(), "heterodyne kernel launch");
+}
+
+// Queue tile scan + evaluation (reads the device argument block).
+static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, hipStream_t st) {
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, st, ctx->het->args, ctx->het->tile_pre);
+  gw_status s = check_hip(hipGetLastError(), "tile scan launch");
+  if (s != GW_OK) return s;
+  hipLaunchKernelGGL(k_het_prologue, dim3(256 * 4), dim3(256), 0, st, ctx->het->args, ctx->het->tile_pre, marg,
+                     ctx->geom);
+  s = check_hip(hipGetLastError(), "heterodyne prologue launch");
+  if (s != GW_OK) return s;
+  const int slot = prof_begin(ctx, st);
+  switch (ctx->n_det) {
+    case 1: s = launch_het_nd<1>(ctx, marg, prec, st); break;
+    case 2: s = launch_het_nd<2>(ctx, marg, prec, st); break;
+    case 3: s = launch_het_nd<3>(ctx, marg, prec, st); break;
+    case 4: s = launch_het_nd<4>(ctx, marg, prec, st); break;
+    default: s = set_error(GW_ENOTSUP, "n_det not supported");
+  }
+  prof_end(ctx, slot, st);
+  return s;
+}
+
+gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl, hipStream_t st) {
   if (!ctx->het) return set_error(GW_ESTATE, "loglike_batch: heterodyne_setup has not been called");
-  return GW_OK;
+  gw_het_state* h = ctx->het;
+  gw_status s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
+  if (s != GW_OK) return s;
+  hipLaunchKernelGGL(k_set_args, dim3(1), dim3(1), 0, st, h->args, theta, (const int64_t*)h->subs_single, logl,
+                     ctx->coef, n, 1, h->subs_single, n);
+  s = check_hip(hipGetLastError(), "argument kernel launch");
+  if (s != GW_OK) return s;
+  return enqueue_het(ctx, marg, prec, st);
 }
 
 }  // namespace gw
+
+using namespace gw;
+
+extern "C" {
+
+gw_status heterodyne_setup(gw_ctx* ctx, const double* theta0, int32_t n_bins, int32_t bin_rule, double* edges_out) {
+  if (!ctx) return set_error(GW_EINVAL, "heterodyne_setup: ctx is NULL");
+  if (!theta0) return set_error(GW_EINVAL, "heterodyne_setup: theta0 is NULL");
+  if (bin_rule != 0 && bin_rule != 1) return set_error(GW_EINVAL, "heterodyne_setup: bin_rule must be 0 or 1");
+  if (n_bins < 1 || (int64_t)n_bins > ctx->geom.n_freq - 1)
+    return set_error(GW_EINVAL, "heterodyne_setup: n_bins must be in 1 .. n_freq - 1");
+  for (int j = 0; j < 13; ++j)
+    if (!isfinite(theta0[j])) return set_error(GW_EINVAL, "heterodyne_setup: theta0 must be finite");
+  if (!(theta0[0] > 0.0) || !(theta0[1] > 0.0) || theta0[1] > 1.0 || fabs(theta0[2]) >= 1.0 ||
+      fabs(theta0[3]) >= 1.0 || !(theta0[6] > 0.0))
+    return set_error(GW_EINVAL, "heterodyne_setup: theta0 is unphysical");
+  gw_status s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+  if (s != GW_OK) return s;
+  het_free(ctx);
+  if (ctx->graphs) graphs_clear(ctx->graphs);
+
+  const int nd = ctx->n_det;
+  const int64_t nf = ctx->geom.n_freq;
+  std::vector<int64_t> edges = make_edges(ctx->geom, n_bins, bin_rule);
+  const int ne = (int)edges.size();
+  gw_het_state* h = new (std::nothrow) gw_het_state();
+  if (!h) return set_error(GW_ENOMEM, "heterodyne_setup: host allocation");
+  h->n_edges = ne;
+  h->n_bins = ne - 1;
+  h->rs = het_rs(nd);
+  h->theta0.assign(theta0, theta0 + 13);
+  h->max_sub = kMaxSub;
+  h->f_edges.resize(ne);
+  for (int e = 0; e < ne; ++e) h->f_edges[e] = (double)(ctx->geom.k0 + edges[e]) * ctx->geom.df;
+
+  // hh weights 4 df f^(-7/3) / S for the set-up sums
+  std::vector<double> hw((size_t)nd * nf);
+  for (int i = 0; i < nd; ++i)
+    for (int64_t k = 0; k < nf; ++k) {
+      const double f = (double)(ctx->geom.k0 + k) * ctx->geom.df;
+      hw[(size_t)i * nf + k] = 4.0 * ctx->geom.df * pow(f, -7.0 / 3.0) / ctx->h_psd[(size_t)i * nf + k];
+    }
+  double *d_hw = nullptr, *d_th = nullptr, *d_coef0 = nullptr;
+  int64_t* d_edges = nullptr;
+  auto cleanup = [&]() {
+    if (d_hw) (void)hipFree(d_hw);
+    if (d_th) (void)hipFree(d_th);
+    if (d_coef0) (void)hipFree(d_coef0);
+    if (d_edges) (void)hipFree(d_edges);
+  };
+  s = check_hip(hipMalloc((void**)&d_hw, hw.size() * sizeof(double)), "het alloc");
+  if (s == GW_OK) s = check_hip(hipMalloc((void**)&d_th, 13 * sizeof(double)), "het alloc");
+  if (s == GW_OK) s = check_hip(hipMalloc((void**)&d_coef0, C_NCOEF * sizeof(double)), "het alloc");
+  if (s == GW_OK) s = check_hip(hipMalloc((void**)&d_edges, ne * sizeof(int64_t)), "het alloc");
+  if (s == GW_OK) s = check_hip(hipMalloc((void**)&h->rec, (size_t)ne * h->rs * sizeof(double)), "het alloc");
+  if (s == GW_OK) s = check_hip(hipMalloc((void**)&h->args, sizeof(HetArgs)), "het alloc");
+  if (s == GW_OK) s = check_hip(hipMalloc((void**)&h->tile_pre, (kMaxSub + 1) * sizeof(int64_t)), "het alloc");
+  if (s == GW_OK) s = check_hip(hipMalloc((void**)&h->subs_single, 2 * sizeof(int64_t)), "het alloc");
+  if (s == GW_OK) s = check_hip(hipMemcpy(d_hw, hw.data(), hw.size() * sizeof(double), hipMemcpyHostToDevice), "copy");
+  if (s == GW_OK) s = check_hip(hipMemcpy(d_th, theta0, 13 * sizeof(double), hipMemcpyHostToDevice), "copy");
+  if (s == GW_OK)
+    s = check_hip(hipMemcpy(d_edges, edges.data(), ne * sizeof(int64_t), hipMemcpyHostToDevice), "copy");
+  if (s == GW_OK) s = check_hip(hipMemset(h->rec, 0, (size_t)ne * h->rs * sizeof(double)), "memset");
+  if (s == GW_OK) s = launch_prologue(ctx, d_th, 1, 0, d_coef0, 1, nullptr);
+  const TrigConsts T = make_trig_consts();
+  if (s == GW_OK) {
+    hipLaunchKernelGGL(k_het_edges, dim3((ne + 255) / 256), dim3(256), 0, nullptr, ctx->bins, ctx->rec_stride,
+                       d_edges, ne, nd, d_coef0, T, ctx->geom.k0, ctx->geom.df, h->rec);
+    s = check_hip(hipGetLastError(), "het edge kernel");
+  }
+  if (s == GW_OK) {
+    hipLaunchKernelGGL(k_het_summary, dim3(ne - 1, nd), dim3(256), 0, nullptr, ctx->bins, ctx->rec_stride, d_hw, nf,
+                       d_edges, ne - 1, d_coef0, T, ctx->geom.k0, ctx->geom.df, h->rec, nd);
+    s = check_hip(hipGetLastError(), "het summary kernel");
+  }
+  double coef0[C_NCOEF];
+  if (s == GW_OK) s = check_hip(hipMemcpy(coef0, d_coef0, sizeof(coef0), hipMemcpyDeviceToHost), "copy");
+  if (s == GW_OK) s = check_hip(hipDeviceSynchronize(), "heterodyne set-up");
+  cleanup();
+  if (s != GW_OK) {
+    free_state(h);
+    return s;
+  }
+  for (int i = 0; i < nd; ++i) {
+    const double ar = coef0[C_APRE + i], ai = coef0[C_APIM + i];
+    const double m = ar * ar + ai * ai;
+    if (!(m > 0.0)) {
+      free_state(h);
+      return set_error(GW_EINVAL, "heterodyne_setup: reference template vanishes in detector %d", i);
+    }
+    h->ap0_inv_re[i] = ar / m;
+    h->ap0_inv_im[i] = -ai / m;
+  }
+  ctx->het = h;
+  if (edges_out)
+    for (int e = 0; e < ne; ++e) edges_out[e] = h->f_edges[e];
+  return GW_OK;
+}
+
+gw_status gw_het_info(const gw_ctx* ctx, int32_t* n_bins) {
+  if (!ctx || !n_bins) return set_error(GW_EINVAL, "gw_het_info: null argument");
+  if (!ctx->het) return set_error(GW_ESTATE, "gw_het_info: heterodyne_setup has not been called");
+  *n_bins = ctx->het->n_bins;
+  return GW_OK;
+}
+
+gw_status loglike_batch_uneven(gw_ctx* ctx, const double* theta, int64_t n_rows, const int64_t* subs, int32_t n_sub,
+                               int32_t like, int32_t marg, int32_t prec, int32_t use_graph, double* logl,
+                               void* stream) {
+  if (!ctx) return set_error(GW_EINVAL, "loglike_batch_uneven: ctx is NULL");
+  if (n_rows < 0 || n_sub < 0) return set_error(GW_EINVAL, "loglike_batch_uneven: negative size");
+  if (n_sub > kMaxSub) return set_error(GW_EINVAL, "loglike_batch_uneven: at most %d sub-batches", kMaxSub);
+  if (n_sub > 0 && (!theta || !subs || !logl)) return set_error(GW_EINVAL, "loglike_batch_uneven: null pointer");
+  if (like != GW_HET) return set_error(GW_ENOTSUP, "loglike_batch_uneven: only GW_HET is supported");
+  if (marg < GW_MARG_NONE || marg > GW_MARG_PHASE_DIST) return set_error(GW_EINVAL, "loglike_batch_uneven: bad marg");
+  if (prec != GW_PREC_FP64 && prec != GW_PREC_MIXED) return set_error(GW_EINVAL, "loglike_batch_uneven: bad prec");
+  if (marg == GW_MARG_PHASE_DIST && ctx->n_dist <= 0)
+    return set_error(GW_ESTATE, "loglike_batch_uneven: distance marginal needs a distance grid");
+  if (!ctx->het) return set_error(GW_ESTATE, "loglike_batch_uneven: heterodyne_setup has not been called");
+  if (n_sub == 0 || n_rows == 0) return GW_OK;
+  hipStream_t st = (hipStream_t)stream;
+  gw_status s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+  if (s != GW_OK) return s;
+  gw_het_state* h = ctx->het;
+  s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n_rows, "coefficient workspace");
+  if (s != GW_OK) return s;
+  hipLaunchKernelGGL(k_set_args, dim3(1), dim3(1), 0, st, h->args, theta, subs, logl, ctx->coef, n_rows, n_sub,
+                     (int64_t*)nullptr, (int64_t)0);
+  s = check_hip(hipGetLastError(), "argument kernel launch");
+  if (s != GW_OK) return s;
+  if (!use_graph || ctx->prof) return enqueue_het(ctx, marg, prec, st);
+
+  if (!ctx->graphs) {
+    ctx->graphs = new (std::nothrow) gw_graph_cache();
+    if (!ctx->graphs) return set_error(GW_ENOMEM, "graph cache");
+  }
+  gw_graph_cache* gc = ctx->graphs;
+  const GraphKey key{marg, prec, h->wpb, h->grid};
+  auto it = gc->exec.find(key);
+  if (it == gc->exec.end()) {
+    if (!gc->cap_stream) {
+      s = check_hip(hipStreamCreateWithFlags(&gc->cap_stream, hipStreamNonBlocking), "capture stream");
+      if (s != GW_OK) return s;
+    }
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    s = check_hip(hipStreamBeginCapture(gc->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (s != GW_OK) return s;
+    gw_status sq = enqueue_het(ctx, marg, prec, gc->cap_stream);
+    s = check_hip(hipStreamEndCapture(gc->cap_stream, &g), "end capture");
+    if (sq != GW_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return sq;
+    }
+    if (s != GW_OK) return s;
+    const auto t0 = std::chrono::steady_clock::now();
+    s = check_hip(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "graph instantiate");
+    const auto t1 = std::chrono::steady_clock::now();
+    gc->last_instantiate_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    if (s != GW_OK) {
+      (void)hipGraphDestroy(g);
+      return s;
+    }
+    gc->graph[key] = g;
+    gc->exec[key] = ge;
+    it = gc->exec.find(key);
+  }
+  return check_hip(hipGraphLaunch(it->second, st), "graph launch");
+}
+
+gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid) {
+  if (!ctx) return set_error(GW_EINVAL, "gw_set_het_shape: ctx is NULL");
+  if (!ctx->het) return set_error(GW_ESTATE, "gw_set_het_shape: heterodyne_setup has not been called");
+  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+    return set_error(GW_EINVAL, "gw_set_het_shape: waves_per_block must be 1, 2 or 4");
+  if (grid < 0 || grid > (1 << 20)) return set_error(GW_EINVAL, "gw_set_het_shape: grid out of range");
+  ctx->het->wpb = waves_per_block;
+  ctx->het->grid = grid;
+  return GW_OK;
+}
+
+gw_status gw_graph_info(const gw_ctx* ctx, int32_t* n_graphs, double* last_instantiate_ms) {
+  if (!ctx || !n_graphs || !last_instantiate_ms) return set_error(GW_EINVAL, "gw_graph_info: null argument");
+  *n_graphs = ctx->graphs ? (int32_t)ctx->graphs->exec.size() : 0;
+  *last_instantiate_ms = ctx->graphs ? ctx->graphs->last_instantiate_ms : 0.0;
+  return GW_OK;
+}
+
+// Autotuner: time every candidate launch shape on the caller's batch and keep
+// the fastest in the context.  Candidates: full band, proposals per workgroup
+// {64, 128, 256} x frequency chunks {8 .. 512} (multiples of 8, at least 16
+// bins per chunk); heterodyned, waves per workgroup {1, 2, 4} x persistent
+// grid {1, 2, 4, 8, 16} workgroups per CU.
+gw_status gw_autotune(gw_ctx* ctx, const double* theta, int64_t n, int32_t like, int32_t marg, int32_t prec,
+                      int32_t reps, int32_t* best_shape, double* best_ms, void* stream) {
+  if (!ctx || !theta || !best_shape || !best_ms) return set_error(GW_EINVAL, "gw_autotune: null argument");
+  if (n < 1 || reps < 1) return set_error(GW_EINVAL, "gw_autotune: n and reps must be >= 1");
+  if (like != GW_FULL && like != GW_HET) return set_error(GW_EINVAL, "gw_autotune: bad like");
+  if (like == GW_HET && !ctx->het) return set_error(GW_ESTATE, "gw_autotune: heterodyne_setup has not been called");
+  hipStream_t st = (hipStream_t)stream;
+  gw_status s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+  if (s != GW_OK) return s;
+  double* out = nullptr;
+  s = check_hip(hipMalloc((void**)&out, (size_t)n * sizeof(double)), "autotune output");
+  if (s != GW_OK) return s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  std::vector<std::pair<int, int>> cands;
+  if (like == GW_FULL) {
+    for (int tpb : {64, 128, 256})
+      for (int ch : {8, 16, 32, 64, 128, 256, 512})
+        if (ctx->geom.n_freq / ch >= 16) cands.push_back({tpb, ch});
+  } else {
+    for (int w : {1, 2, 4})
+      for (int per_cu : {1, 2, 4, 8, 16}) cands.push_back({w, 256 * per_cu});
+  }
+  double best = 1e300;
+  std::pair<int, int> arg{0, 0};
+  for (auto cand : cands) {
+    if (like == GW_FULL) {
+      ctx->full_tpb = cand.first;
+      ctx->full_chunks = cand.second;
+    } else {
+      ctx->het->wpb = cand.first;
+      ctx->het->grid = cand.second / cand.first;
+    }
+    s = loglike_batch(ctx, theta, n, like, marg, prec, out, st);  // warm-up
+    if (s != GW_OK) break;
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < reps && s == GW_OK; ++r) s = loglike_batch(ctx, theta, n, like, marg, prec, out, st);
+    (void)hipEventRecord(e1, st);
+    if (s != GW_OK) break;
+    s = check_hip(hipEventSynchronize(e1), "autotune sync");
+    if (s != GW_OK) break;
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double per = ms / reps;
+    if (per < best) {
+      best = per;
+      arg = cand;
+    }
+  }
+  if (like == GW_FULL) {
+    ctx->full_tpb = arg.first;
+    ctx->full_chunks = arg.second;
+  } else {
+    ctx->het->wpb = arg.first > 0 ? arg.first : 4;
+    ctx->het->grid = arg.first > 0 ? arg.second / arg.first : 0;
+    if (ctx->graphs) graphs_clear(ctx->graphs);
+  }
+  ctx->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  if (s != GW_OK) return s;
+  best_shape[0] = arg.first;
+  best_shape[1] = like == GW_FULL ? arg.second : ctx->het->grid;
+  *best_ms = best;
+  return GW_OK;
+}
+
+}  // extern "C"
