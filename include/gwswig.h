@@ -202,9 +202,10 @@ gw_status gw_autotune(gw_ctx* ctx, const double* theta, int64_t n, int32_t like,
                       int32_t reps, int32_t* best_shape, double* best_ms, void* stream);
 
 /*
- * Launch shape of the full-band kernel: ``tpb`` proposals per workgroup
- * (64, 128 or 256) and ``n_chunks`` frequency chunks (a multiple of 8 keeps
- * every chunk on one XCD).  0 restores the built-in heuristic.  Used by the
+ * Launch shape of the full-band kernel: ``tpb`` proposals per workgroup (64,
+ * 128 or 256, i.e. 1, 2 or 4 waves walking the same frequency chunk) and
+ * ``n_chunks`` frequency chunks (a multiple of 8 keeps every chunk on one
+ * XCD).  0 restores the built-in heuristic.  Used by the
  * autotuner; results do not depend on the shape beyond summation order.
  */
 gw_status gw_set_full_shape(gw_ctx* ctx, int32_t tpb, int32_t n_chunks);

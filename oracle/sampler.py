@@ -1,0 +1,213 @@
+"""Constrained slice sampling and nested sampling, plain FP64 reference.
+
+Sec. II.B (nested sampling, Eq. cprior): m live points; each iteration
+deletes the k lowest-likelihood points, raises log L* to the largest deleted
+log-likelihood (equivalent to k sequential deletions), accumulates their
+volume contributions into the evidence and replaces them by constrained draws.
+Sec. II.C / III.B (Eq. block_cprior): the constrained draw is a Gibbs sweep
+over parameter blocks, each updated by a hit-and-run slice step along a random
+direction drawn from the block covariance of the live points, with stepping
+out and shrinking.
+
+Readings used here (where the paper is silent):
+* sampling space: the 11-dimensional unit cube of the synthetic prior
+  [Mc, q, chi1, chi2, Lambda1, Lambda2, iota, ra, dec, psi, t_c], with d_L and
+  phi_c marginalised;
+* direction: u uniform on the unit sphere of the block (normalised Gaussian
+  draws, Box-Muller from uniforms), d = L u with L the Cholesky factor of the
+  block covariance; bracket width w along t, placed at a uniform offset;
+  stepping out at most ``max_out`` times per side; shrinking at most
+  ``max_shrink`` times, after which the chain keeps its point (status 1);
+* a point outside the unit cube fails the constraint without an evaluation;
+* random numbers: explicit uniforms per chain, laid out as
+  [4 direction, 1 offset, max_shrink shrink draws]; or Philox4x64-10
+  (Salmon et al. 2011), uniform j of chain c from counter
+  (counter_base, c, j // 4, 0) and key (seed, 0), output word j % 4,
+  u = ((word >> 11) + 0.5) * 2^-53;
+* evidence bookkeeping: the k deletions of an iteration are taken in order of
+  increasing log L with live counts m, m-1, ..., m-k+1, ln X dropping by
+  1/(live count) each; weight L_j (X_{j-1} - X_j); termination when
+  ln(Z_dead + Z_live) - ln Z_dead < dlogz with Z_live = X mean(L_live); the
+  final live points are added with equal shares of X.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import logsumexp
+
+N_DIM = 11
+PRIOR_LO = np.array([1.1, 0.5, -0.05, -0.05, 0.0, 0.0])
+PRIOR_HI = np.array([1.4, 1.0, 0.05, 0.05, 5000.0, 5000.0])
+BLOCKS = ((0, 1, 4, 5), (2,), (3,), (6,), (7, 8), (9,), (10,))
+N_UNIFORM_FIXED = 5  # 4 direction + 1 offset
+
+_M0 = 0xD2E7470EE14C6C93
+_M1 = 0xCA5A826395121157
+_W0 = 0x9E3779B97F4A7C15
+_W1 = 0xBB67AE8584CAA73B
+_MASK = (1 << 64) - 1
+
+
+def prior_transform(u: np.ndarray) -> np.ndarray:
+    """Unit-cube point [11] -> parameter vector [13] (d_L = 1, phi_c = 0)."""
+    u = np.asarray(u, dtype=np.float64)
+    th = np.zeros(13)
+    th[:6] = PRIOR_LO + (PRIOR_HI - PRIOR_LO) * u[:6]
+    th[6] = 1.0
+    th[7] = math.acos(1.0 - 2.0 * u[6])
+    th[8] = 2.0 * math.pi * u[7]
+    th[9] = math.asin(2.0 * u[8] - 1.0)
+    th[10] = math.pi * u[9]
+    th[11] = 0.0
+    th[12] = -0.1 + 0.2 * u[10]
+    return th
+
+
+def philox4x64(counter, key):
+    """Philox4x64 with 10 rounds (Salmon, Moraes, Dror & Shaw 2011)."""
+    c = [int(v) & _MASK for v in counter]
+    k0, k1 = int(key[0]) & _MASK, int(key[1]) & _MASK
+    for _ in range(10):
+        p0 = _M0 * c[0]
+        p1 = _M1 * c[2]
+        hi0, lo0 = p0 >> 64, p0 & _MASK
+        hi1, lo1 = p1 >> 64, p1 & _MASK
+        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+        k0 = (k0 + _W0) & _MASK
+        k1 = (k1 + _W1) & _MASK
+    return c
+
+
+def philox_uniforms(seed: int, counter_base: int, chain: int, n: int) -> np.ndarray:
+    out = np.empty(n)
+    block = None
+    for j in range(n):
+        if j % 4 == 0:
+            block = philox4x64((counter_base, chain, j // 4, 0), (seed, 0))
+        out[j] = ((block[j % 4] >> 11) + 0.5) * 2.0 ** -53
+    return out
+
+
+def direction(uni: np.ndarray, chol: np.ndarray) -> np.ndarray:
+    """d = L u, u a unit vector from Box-Muller normals of uni[0:4]."""
+    b = chol.shape[0]
+    r0 = math.sqrt(-2.0 * math.log(uni[0]))
+    r1 = math.sqrt(-2.0 * math.log(uni[2]))
+    z = np.array([r0 * math.cos(2 * math.pi * uni[1]), r0 * math.sin(2 * math.pi * uni[1]),
+                  r1 * math.cos(2 * math.pi * uni[3]), r1 * math.sin(2 * math.pi * uni[3])])[:b]
+    z = z / np.linalg.norm(z)
+    return chol @ z
+
+
+def slice_chain(x0, logl0, logl_star, block, chol, uni, loglike, w=1.0, max_out=10, max_shrink=100):
+    """One hit-and-run slice update of one chain on one block.
+
+    Returns (x, logl, n_evals, status, min_margin): status 1 when the shrink cap
+    was hit (old point kept); min_margin = smallest |logL - logL*| seen, which
+    tells a caller how close a comparison came to a tie.
+    """
+    x0 = np.asarray(x0, dtype=np.float64)
+    idx = np.asarray(block)
+    d = direction(uni, chol)
+    n_evals = 0
+    margin = math.inf
+
+    def point(t):
+        x = x0.copy()
+        x[idx] = x0[idx] + t * d
+        return x
+
+    def ok(t):
+        nonlocal n_evals, margin
+        x = point(t)
+        if np.any(x[idx] < 0.0) or np.any(x[idx] > 1.0):
+            return False, x, -math.inf
+        v = loglike(x)
+        n_evals += 1
+        margin = min(margin, abs(v - logl_star))
+        return v > logl_star, x, v
+
+    r = uni[4]
+    t_lo = -r * w
+    t_hi = (1.0 - r) * w
+    for _ in range(max_out):
+        good, _, _ = ok(t_lo)
+        if not good:
+            break
+        t_lo -= w
+    for _ in range(max_out):
+        good, _, _ = ok(t_hi)
+        if not good:
+            break
+        t_hi += w
+    for s in range(max_shrink):
+        t = t_lo + uni[N_UNIFORM_FIXED + s] * (t_hi - t_lo)
+        good, x, v = ok(t)
+        if good:
+            return x, v, n_evals, 0, margin
+        if t < 0.0:
+            t_lo = t
+        else:
+            t_hi = t
+    return x0.copy(), logl0, n_evals, 1, margin
+
+
+def block_cholesky(live: np.ndarray, block) -> np.ndarray:
+    """Cholesky factor of the covariance of the live points on ``block``."""
+    sub = np.asarray(live)[:, list(block)]
+    cov = np.atleast_2d(np.cov(sub, rowvar=False))
+    cov = cov + 1e-12 * np.eye(cov.shape[0])
+    return np.linalg.cholesky(cov)
+
+
+def nested_sampling(loglike, n_live: int, n_delete: int, seed: int, dlogz: float = 0.1, blocks=BLOCKS,
+                    n_dim: int = N_DIM, max_iter: int = 100000, sweeps: int = 1, w: float = 1.0,
+                    max_out: int = 10, max_shrink: int = 100):
+    """Slice-within-Gibbs nested sampling; returns a dict with logZ, H, counts."""
+    rng = np.random.default_rng(seed)
+    live = rng.uniform(size=(n_live, n_dim))
+    logl = np.array([loglike(x) for x in live])
+    n_evals = n_live
+    dead_logl, dead_logw = [], []
+    log_x = 0.0
+    it = 0
+    counter = 0
+    while it < max_iter:
+        order = np.argsort(logl)
+        worst = order[:n_delete]
+        logl_star = float(logl[worst[-1]])
+        for j, i in enumerate(worst):
+            new_log_x = log_x - 1.0 / (n_live - j)
+            dead_logl.append(float(logl[i]))
+            dead_logw.append(float(logl[i]) + log_x + math.log1p(-math.exp(new_log_x - log_x)))
+            log_x = new_log_x
+        survivors = order[n_delete:]
+        starts = rng.choice(survivors, size=n_delete, replace=True)
+        chols = [block_cholesky(live[survivors], b) for b in blocks]
+        new_x = live[starts].copy()
+        new_l = logl[starts].copy()
+        for _ in range(sweeps):
+            for bi, b in enumerate(blocks):
+                for c in range(n_delete):
+                    uni = philox_uniforms(seed, counter, c, N_UNIFORM_FIXED + max_shrink)
+                    x, v, ne, st, _ = slice_chain(new_x[c], new_l[c], logl_star, b, chols[bi], uni, loglike,
+                                                  w, max_out, max_shrink)
+                    new_x[c], new_l[c] = x, v
+                    n_evals += ne
+                counter += 1
+        live[worst] = new_x
+        logl[worst] = new_l
+        it += 1
+        log_z_dead = logsumexp(dead_logw)
+        log_z_live = log_x + logsumexp(logl) - math.log(n_live)
+        if np.logaddexp(log_z_dead, log_z_live) - log_z_dead < dlogz:
+            break
+    all_logw = np.concatenate([dead_logw, logl + log_x - math.log(n_live)])
+    all_logl = np.concatenate([dead_logl, logl])
+    log_z = float(logsumexp(all_logw))
+    p = np.exp(all_logw - log_z)
+    h = float(np.sum(p * all_logl) - log_z)
+    return dict(log_z=log_z, h=h, log_z_err=math.sqrt(max(h, 0.0) / n_live), iterations=it, n_evals=n_evals,
+                live=live, logl=logl, dead_logl=np.array(dead_logl), dead_logw=np.array(dead_logw))

@@ -186,13 +186,17 @@ gw_status gw_ctx_create(const gw_problem* pr, int32_t device, gw_ctx** out) {
     ctx->n_dist = pr->n_dist;
     ctx->h_dist_grid.assign(pr->dist_grid, pr->dist_grid + pr->n_dist);
     ctx->h_dist_logw.assign(pr->dist_logw, pr->dist_logw + pr->n_dist);
-    st = check_hip(hipMalloc((void**)&ctx->dist_grid, pr->n_dist * sizeof(double)), "dist alloc");
-    if (st == GW_OK) st = check_hip(hipMalloc((void**)&ctx->dist_logw, pr->n_dist * sizeof(double)), "dist alloc");
+    std::vector<double> tab(4 * (size_t)pr->n_dist);
+    for (int j = 0; j < pr->n_dist; ++j) {
+      const double d = pr->dist_grid[j];
+      tab[4 * j] = d;
+      tab[4 * j + 1] = 1.0 / d;
+      tab[4 * j + 2] = 0.5 / (d * d);
+      tab[4 * j + 3] = pr->dist_logw[j];
+    }
+    st = check_hip(hipMalloc((void**)&ctx->dist_tab, tab.size() * sizeof(double)), "dist alloc");
     if (st == GW_OK)
-      st = check_hip(hipMemcpy(ctx->dist_grid, pr->dist_grid, pr->n_dist * sizeof(double), hipMemcpyHostToDevice),
-                     "dist copy");
-    if (st == GW_OK)
-      st = check_hip(hipMemcpy(ctx->dist_logw, pr->dist_logw, pr->n_dist * sizeof(double), hipMemcpyHostToDevice),
+      st = check_hip(hipMemcpy(ctx->dist_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice),
                      "dist copy");
   }
   if (st != GW_OK) {
@@ -210,7 +214,7 @@ gw_status gw_ctx_destroy(gw_ctx* ctx) {
   graphs_free(ctx);
   for (hipEvent_t e : ctx->prof_ev)
     if (e) (void)hipEventDestroy(e);
-  double* bufs[] = {ctx->bins, ctx->dist_grid, ctx->dist_logw, ctx->coef, ctx->partial, ctx->zbuf};
+  double* bufs[] = {ctx->bins, ctx->dist_tab, ctx->coef, ctx->partial, ctx->zbuf};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   delete ctx;

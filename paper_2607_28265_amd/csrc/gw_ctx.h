@@ -24,8 +24,7 @@ struct gw_ctx {
   double* bins = nullptr;
   int rec_stride = 0;
   // distance grid
-  double* dist_grid = nullptr;
-  double* dist_logw = nullptr;
+  double* dist_tab = nullptr;      // [n_dist][4]: d, 1/d, 1/(2 d^2), ln w
   int32_t n_dist = 0;
   std::vector<double> h_dist_grid, h_dist_logw;
   // host copies kept for heterodyne set-up

@@ -268,32 +268,90 @@ __device__ inline void sincos_cycles(double r, const TrigConsts& T, double* s_ou
   *c_out = __hiloint2double(__double2hiint(cn) ^ flip, __double2loint(cn));
 }
 
-// ln I0(x), x >= 0.  Power series sum_k (x^2/4)^k / (k!)^2 for x < 20, and
-// the large-argument expansion I0(x) ~ e^x / sqrt(2 pi x) sum_k c_k x^-k,
-// c_k = ((2k-1)!!)^2 / (k! 8^k) (Abramowitz & Stegun 9.7.1) otherwise; the
-// expansion is cut at its smallest term, whose size is about e^(-2x).
-__device__ inline double log_i0(double x) {
+// ln I0(x), x >= 0, at a fixed cost.  For x < 20 the defining power series
+// I0(x) = sum_k (x^2/4)^k / (k!)^2, summed by Horner in y = x^2/4 with 40
+// terms (truncation below 1e-23 relative on that range); for x >= 20 the
+// large-argument expansion I0(x) ~ e^x / sqrt(2 pi x) sum_k c_k x^-k with
+// c_k = ((2k-1)!!)^2 / (k! 8^k) (Abramowitz & Stegun 9.7.1), Horner in
+// u = 1/x with 24 terms (the terms still decrease there; truncation below
+// 1e-16).  Kernels take the coefficients as an argument.
+struct LogI0Consts {
+  double ser[40];
+  double asy[24];
+};
+
+__host__ __device__ inline LogI0Consts make_log_i0_consts() {
+  LogI0Consts c;
+  double f = 1.0;
+  for (int k = 0; k < 40; ++k) {
+    if (k > 0) f *= (double)k;
+    c.ser[k] = 1.0 / (f * f);
+  }
+  double a = 1.0;
+  for (int k = 0; k < 24; ++k) {
+    if (k > 0) a *= (double)(2 * k - 1) * (double)(2 * k - 1) / (8.0 * k);
+    c.asy[k] = a;
+  }
+  return c;
+}
+
+// ln I0(x) given x and u = 1/x (u is only used when x >= 20).
+__device__ inline double log_i0_xu(double x, double u, const LogI0Consts& C) {
+  double arg, base, scale;
   if (x < 20.0) {
     const double y = 0.25 * x * x;
-    double term = 1.0, sum = 1.0;
-    for (int k = 1; k < 200; ++k) {
-      term *= y / ((double)k * (double)k);
-      sum += term;
-      if (term < 1e-17 * sum) break;
-    }
-    return log(sum);
+    double p = C.ser[39];
+#pragma unroll
+    for (int k = 38; k >= 0; --k) p = fma(p, y, C.ser[k]);
+    arg = p;
+    base = 0.0;
+    scale = 1.0;
+  } else {
+    double p = C.asy[23];
+#pragma unroll
+    for (int k = 22; k >= 0; --k) p = fma(p, u, C.asy[k]);
+    // x - ln(2 pi x)/2 + ln p = x + ln(p^2 u / (2 pi)) / 2
+    arg = p * p * u * kInvTwoPi;
+    base = x;
+    scale = 0.5;
   }
-  const double ix = 1.0 / x;
-  double term = 1.0, sum = 1.0;
-  for (int k = 1; k < 60; ++k) {
-    const double tk = 2.0 * k - 1.0;
-    const double next = term * tk * tk * 0.125 * ix / (double)k;
-    if (next > term) break;
-    term = next;
-    sum += term;
-    if (term < 1e-17 * sum) break;
+  return fma(scale, log(arg), base);
+}
+
+__device__ inline double log_i0(double x, const LogI0Consts& C) {
+  return log_i0_xu(x, x >= 20.0 ? 1.0 / x : 0.0, C);
+}
+
+// Distance marginal over a grid, evaluated by one wave for one proposal:
+//   LSE_j [ ln w_j - hh1 / (2 d_j^2) + ln I0(|Z1| / d_j) ],
+// with the grid as records (d_j, 1/d_j, 1/(2 d_j^2), ln w_j).  Lanes stride the
+// grid with an online log-sum-exp (one exp per point); the 64 partial
+// (max, sum) pairs are merged by a fixed shuffle tree, so every lane returns
+// the same, reproducible value.
+__device__ inline double wave_dist_lse(double z1, double hh1, const double* __restrict__ tab, int n_dist, int lane,
+                                       const LogI0Consts& C) {
+  double m = -INFINITY, s = 0.0;
+  const double iz = z1 > 0.0 ? 1.0 / z1 : 0.0;
+  for (int j = lane; j < n_dist; j += 64) {
+    const double* r = tab + 4 * j;
+    const double x = z1 * r[1];
+    const double t = r[3] - hh1 * r[2] + log_i0_xu(x, r[0] * iz, C);
+    const bool up = t > m;
+    const double e = exp(up ? m - t : t - m);
+    s = up ? fma(s, e, 1.0) : s + e;
+    m = up ? t : m;
   }
-  return x - 0.5 * log(kTwoPi * x) + log(sum);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double m2 = __shfl_xor(m, o, 64);
+    const double s2 = __shfl_xor(s, o, 64);
+    const double mm = fmax(m, m2);
+    const double a = (m == -INFINITY) ? 0.0 : s * exp(m - mm);
+    const double b = (m2 == -INFINITY) ? 0.0 : s2 * exp(m2 - mm);
+    m = mm;
+    s = a + b;
+  }
+  return m + log(s);
 }
 
 }  // namespace gw

@@ -2,8 +2,9 @@
 // phase/phasor/projection/overlap kernel and the FP64 epilogue with the
 // phase and distance marginalisations (Sec. III.A).
 //
-// Layout.  One lane owns one proposal; a workgroup owns ``tpb`` proposals and
-// one contiguous chunk of frequency bins.  Every lane of a wave walks the same
+// Layout.  One lane owns one proposal; a workgroup owns ``tpb`` proposals
+// (one to four waves) and one contiguous chunk of frequency bins, which all
+// of its waves walk in step so that they share each bin record.  Every lane of a wave walks the same
 // bins in the same order, so the per-bin records (frequency powers and the
 // weighted data u_ik = 4 df d_ik* f^(-7/6) / S_ik) are wave-uniform and are
 // fetched with scalar loads into SGPRs; the proposal's phase coefficients live
@@ -107,11 +108,11 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
     ri[i] = -s;
   }
 
-  // Descending walk so that the Horner recurrence leaves rho^0 on the first bin.
-  for (int k = ke - 1; k >= kb; --k) {
-    const double* __restrict__ rec = bins + (int64_t)k * RS;
-    const double x = rec[0], x2 = rec[1], xm5 = rec[2], lnf = rec[3];
-    const double r = phase_cycles(c, x, x2, xm5, lnf);
+  // Descending walk so that the Horner recurrence leaves rho^0 on the first
+  // bin.  Records alternate between two register sets: while one bin is
+  // processed the next one's record is already in flight.
+  auto step = [&](const double* __restrict__ rec) {
+    const double r = phase_cycles(c, rec[0], rec[1], rec[2], rec[3]);
     double gr, gi;
     phasor<PREC>(r, T, &gr, &gi);
     {
@@ -134,6 +135,24 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
       ti = fma(ui, gr, ti);
       zr[i] = tr;
       zi[i] = ti;
+    }
+  };
+  if (ke > kb) {
+    double ra[RS], rb[RS];
+#pragma unroll
+    for (int j = 0; j < RS; ++j) ra[j] = bins[(int64_t)(ke - 1) * RS + j];
+    int k = ke - 1;
+    while (true) {
+      const int k1 = k - 1 >= kb ? k - 1 : kb;
+#pragma unroll
+      for (int j = 0; j < RS; ++j) rb[j] = bins[(int64_t)k1 * RS + j];
+      step(ra);
+      if (--k < kb) break;
+      const int k2 = k - 1 >= kb ? k - 1 : kb;
+#pragma unroll
+      for (int j = 0; j < RS; ++j) ra[j] = bins[(int64_t)k2 * RS + j];
+      step(rb);
+      if (--k < kb) break;
     }
   }
   // Apply exp(-2 pi i f_kb (tau_i - tau_0)) to the recurrences.
@@ -158,22 +177,43 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
   }
 }
 
-// Combine the chunk partials in chunk order and apply the marginalisation.
-// For the distance marginal this writes (|Z_1|, <h|h>_1) for k_dist_marg.
+// Combine the chunk partials and apply the marginalisation.  A workgroup
+// takes 64 proposals; its 4 waves sum the chunks c = w (mod 4) in order and
+// wave 0 adds the four sums in order, so the result is reproducible.  For the
+// distance marginal this writes (|Z_1|, <h|h>_1) for k_dist_marg.
 __global__ void __launch_bounds__(256) k_epilogue(const double* __restrict__ partial, int n_chunks, int nd,
                                                   const double* __restrict__ coef, int64_t ld, int64_t n,
-                                                  double dd, int marg, double* __restrict__ logl,
+                                                  double dd, int marg, LogI0Consts C, double* __restrict__ logl,
                                                   double* __restrict__ zbuf) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t pc = p < n ? p : n - 1;
+  double z[2 * kMaxDet];
+#pragma unroll
+  for (int j = 0; j < 2 * kMaxDet; ++j) z[j] = 0.0;
+  for (int c = wave; c < n_chunks; c += 4) {
+#pragma unroll
+    for (int j = 0; j < 2 * kMaxDet; ++j)
+      if (j < 2 * nd) z[j] += partial[((int64_t)c * 2 * nd + j) * n + pc];
+  }
+  __shared__ double red[3][2 * kMaxDet][64];
+  if (wave > 0) {
+#pragma unroll
+    for (int j = 0; j < 2 * kMaxDet; ++j) red[wave - 1][j][lane] = z[j];
+  }
+  __syncthreads();
+  if (wave != 0 || p >= n) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int j = 0; j < 2 * kMaxDet; ++j) z[j] += red[w][j][lane];
   const bool valid = coef[C_VALID * ld + p] != 0.0;
   double Zr = 0.0, Zi = 0.0, plain = 0.0;
-  for (int i = 0; i < nd; ++i) {
-    double zr = 0.0, zi = 0.0;
-    for (int c = 0; c < n_chunks; ++c) {
-      zr += partial[((int64_t)c * 2 * nd + 2 * i) * n + p];
-      zi += partial[((int64_t)c * 2 * nd + 2 * i + 1) * n + p];
-    }
+#pragma unroll
+  for (int i = 0; i < kMaxDet; ++i) {
+    if (i >= nd) break;
+    const double zr = z[2 * i], zi = z[2 * i + 1];
     const double ar = coef[(C_APRE + i) * ld + p];
     const double ai = coef[(C_APIM + i) * ld + p];
     const double hr = ar * zr - ai * zi;
@@ -194,17 +234,15 @@ __global__ void __launch_bounds__(256) k_epilogue(const double* __restrict__ par
   } else if (marg == 0) {
     out = -0.5 * dd + plain - 0.5 * hh;
   } else {
-    out = -0.5 * dd - 0.5 * hh + log_i0(sqrt(Zr * Zr + Zi * Zi));
+    out = -0.5 * dd - 0.5 * hh + log_i0(sqrt(Zr * Zr + Zi * Zi), C);
   }
   logl[p] = out;
 }
 
-// Distance marginal: one wave per proposal, lanes stride the d_L grid,
-// log-sum-exp by a fixed shuffle tree.
+// Distance marginal: one wave per proposal (see wave_dist_lse).
 __global__ void __launch_bounds__(256) k_dist_marg(const double* __restrict__ zbuf, int64_t n,
-                                                   const double* __restrict__ grid,
-                                                   const double* __restrict__ logw, int n_dist, double dd,
-                                                   double* __restrict__ logl) {
+                                                   const double* __restrict__ tab, int n_dist, double dd,
+                                                   LogI0Consts C, double* __restrict__ logl) {
   const int lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (p >= n) return;
@@ -214,23 +252,8 @@ __global__ void __launch_bounds__(256) k_dist_marg(const double* __restrict__ zb
     if (lane == 0) logl[p] = -INFINITY;
     return;
   }
-  double m = -INFINITY;
-  for (int j = lane; j < n_dist; j += 64) {
-    const double d = grid[j];
-    const double t = logw[j] - 0.5 * hh1 / (d * d) + log_i0(z1 / d);
-    m = fmax(m, t);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  double s = 0.0;
-  for (int j = lane; j < n_dist; j += 64) {
-    const double d = grid[j];
-    const double t = logw[j] - 0.5 * hh1 / (d * d) + log_i0(z1 / d);
-    s += exp(t - m);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) logl[p] = -0.5 * dd + m + log(s);
+  const double v = wave_dist_lse(z1, hh1, tab, n_dist, lane, C);
+  if (lane == 0) logl[p] = -0.5 * dd + v;
 }
 
 // Materialise h_i(f_k) = A P_i f^(-7/6) exp(-2 pi i Phi_i(f)) for injections.
@@ -338,15 +361,15 @@ gw_status launch_full(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, in
 gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, const double* coef, int64_t ld,
                           int64_t n, int marg, double* logl, hipStream_t st) {
   if (n == 0) return GW_OK;
-  const int tpb = 256;
-  const int64_t blocks = (n + tpb - 1) / tpb;
-  hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(tpb), 0, st, partial, n_chunks, ctx->n_det, coef, ld,
-                     n, ctx->dd, marg, logl, ctx->zbuf);
+  const int64_t blocks = (n + 63) / 64;
+  const LogI0Consts C = make_log_i0_consts();
+  hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(256), 0, st, partial, n_chunks, ctx->n_det, coef, ld,
+                     n, ctx->dd, marg, C, logl, ctx->zbuf);
   gw_status s = check_hip(hipGetLastError(), "epilogue launch");
   if (s != GW_OK || marg != 2) return s;
   const int64_t dblocks = (n + 3) / 4;
-  hipLaunchKernelGGL(k_dist_marg, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_grid,
-                     ctx->dist_logw, ctx->n_dist, ctx->dd, logl);
+  hipLaunchKernelGGL(k_dist_marg, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_tab,
+                     ctx->n_dist, ctx->dd, C, logl);
   return check_hip(hipGetLastError(), "distance marginal launch");
 }
 

@@ -33,6 +33,8 @@ struct HetArgs {
   const int64_t* subs;  // (row offset, count) pairs
   double* logl;
   double* coef;         // per-row coefficients [C_NCOEF][ld]
+  double* zbuf;         // per-row (|Z_1|, <h|h>_1) [2][ld] for the distance marginal
+  double* part;         // per-row partial sums [edge chunk][3 n_det][ld]
   int64_t n_rows;
   int64_t ld;
   int32_t n_sub;
@@ -59,9 +61,9 @@ struct gw_het_state {
 };
 
 struct GraphKey {
-  int marg, prec, wpb, grid;
+  int marg, prec, wpb, grid, n_ech;
   bool operator<(const GraphKey& o) const {
-    return std::tie(marg, prec, wpb, grid) < std::tie(o.marg, o.prec, o.wpb, o.grid);
+    return std::tie(marg, prec, wpb, grid, n_ech) < std::tie(o.marg, o.prec, o.wpb, o.grid, o.n_ech);
   }
 };
 
@@ -178,11 +180,14 @@ __global__ void __launch_bounds__(256) k_het_summary(const double* __restrict__ 
 // Work-list kernels
 
 __global__ void k_set_args(HetArgs* a, const double* theta, const int64_t* subs, double* logl, double* coef,
-                           int64_t n_rows, int32_t n_sub, int64_t* subs_single, int64_t single_n) {
+                           double* zbuf, double* part, int64_t n_rows, int32_t n_sub, int64_t* subs_single,
+                           int64_t single_n) {
   a->theta = theta;
   a->subs = subs;
   a->logl = logl;
   a->coef = coef;
+  a->zbuf = zbuf;
+  a->part = part;
   a->n_rows = n_rows;
   a->ld = n_rows;
   a->n_sub = n_sub;
@@ -283,30 +288,39 @@ __device__ inline void het_phasor(double r, const TrigConsts& T, double* gr, dou
     *gi = -s;
   } else {
     const float t = (float)(r - rint(r));
-    *gr = (double)__builtin_amdgcn_cosf(t);
-    *gi = -(double)__builtin_amdgcn_sinf(t);
+    const double c = (double)__builtin_amdgcn_cosf(t);
+    const double s = (double)__builtin_amdgcn_sinf(t);
+    // One Newton step towards unit modulus: the hardware pair has |g|^2 about
+    // 6e-8 below 1 on average, and the binned norm sums are quadratic in g.
+    const double k = fma(-0.5, fma(c, c, s * s), 1.5);
+    *gr = c * k;
+    *gi = -s * k;
   }
 }
 
+// Binned sums of one (tile, edge chunk) work item.  The waves of a workgroup
+// take consecutive tiles of the same edge chunk, so they share the edge
+// records; per lane the partial (Z_i, <h_i|h_i>) of the chunk's bins go to
+// ab->part, without the (A P_i) / (A0 P0_i) prefactor.
 template <int ND, int PREC>
 __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
-                                             const double* __restrict__ rec, int n_edges, int marg, HetConst hc,
-                                             const double* __restrict__ dgrid, const double* __restrict__ dlogw,
-                                             int n_dist, TrigConsts T) {
+                                             const double* __restrict__ rec, int n_bins, int n_ech, TrigConsts T) {
   constexpr int RS = het_rs(ND);
   constexpr int BO = het_bin_off(ND);
   const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
-  const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * wpb;
   const int64_t total = pre[ab->n_sub];
+  const int64_t groups = (total + wpb - 1) / wpb;
   const int64_t ld = ab->ld;
   const double* __restrict__ coef = ab->coef;
-  double* logl = ab->logl;
+  const int per = (n_bins + n_ech - 1) / n_ech;
 
-  for (int64_t t = wid; t < total; t += nwaves) {
-    int64_t row0, row_end;
-    if (!tile_rows(ab, pre, t, &row0, &row_end)) continue;
+  for (int64_t q = blockIdx.x; q < groups * n_ech; q += gridDim.x) {
+    const int ech = (int)(q % n_ech);
+    const int64_t t = (q / n_ech) * wpb + wave;
+    int64_t row0 = 0, row_end = 0;
+    if (t >= total || !tile_rows(ab, pre, t, &row0, &row_end)) continue;
     const int64_t row = row0 + lane;
     const bool active = row < row_end;
     const int64_t rr = active ? row : row0;
@@ -320,13 +334,16 @@ __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, con
 #pragma unroll
     for (int i = 1; i < ND; ++i) dt[i] = cf[(C_DT1 + i - 1) * ld];
 
+    // bins [b0, b1) of this chunk use edges b0 .. b1
+    const int b0 = ech * per < n_bins ? ech * per : n_bins;
+    const int b1 = b0 + per < n_bins ? b0 + per : n_bins;
     double zr[ND], zi[ND], hh[ND], pr[ND], pi[ND];
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
       zr[i] = zi[i] = hh[i] = 0.0;
       pr[i] = pi[i] = 0.0;
     }
-    for (int e = 0; e < n_edges; ++e) {
+    for (int e = b0; e <= b1 && b1 > b0; ++e) {
       const double* __restrict__ r = rec + (int64_t)e * RS;
       const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
       const double f = r[H_F];
@@ -336,7 +353,7 @@ __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, con
         const double di = i == 0 ? d0 : fma(f, dt[i], d0) - r[H_PHI0 + i];
         double gr, gi;
         het_phasor<PREC>(di, T, &gr, &gi);
-        if (e > 0) {
+        if (e > b0) {
           const double* __restrict__ bd = r + BO + 1 + 6 * i;
           const double r0r = 0.5 * (gr + pr[i]), r0i = 0.5 * (gi + pi[i]);
           const double r1r = (gr - pr[i]) * inv, r1i = (gi - pi[i]) * inv;
@@ -357,57 +374,93 @@ __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, con
         pi[i] = gi;
       }
     }
-    // Restore the prefactor (A P_i) / (A0 P0_i) and combine detectors.
-    double Zr = 0.0, Zi = 0.0, plain = 0.0, hht = 0.0;
+    if (active) {
+      double* out = ab->part + (int64_t)ech * 3 * ND * ld + row;
 #pragma unroll
-    for (int i = 0; i < ND; ++i) {
+      for (int i = 0; i < ND; ++i) {
+        out[(3 * i) * ld] = zr[i];
+        out[(3 * i + 1) * ld] = zi[i];
+        out[(3 * i + 2) * ld] = hh[i];
+      }
+    }
+  }
+}
+
+// Combine the edge-chunk partials of each row in chunk order, restore the
+// prefactor (A P_i) / (A0 P0_i), sum the detectors and apply the plain or
+// phase-marginalised epilogue (or stage |Z_1| and <h|h>_1 for the distance
+// marginal).
+__global__ void __launch_bounds__(256) k_het_combine(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
+                                                     int nd, int n_ech, int marg, HetConst hc, LogI0Consts C) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * wpb;
+  const int64_t total = pre[ab->n_sub];
+  const int64_t ld = ab->ld;
+  for (int64_t t = wid; t < total; t += nwaves) {
+    int64_t row0, row_end;
+    if (!tile_rows(ab, pre, t, &row0, &row_end)) continue;
+    const int64_t row = row0 + lane;
+    if (row >= row_end) continue;
+    const double* cf = ab->coef + row;
+    double Zr = 0.0, Zi = 0.0, plain = 0.0, hht = 0.0;
+    for (int i = 0; i < nd; ++i) {
+      double zr = 0.0, zi = 0.0, hh = 0.0;
+      for (int e = 0; e < n_ech; ++e) {
+        const double* p = ab->part + ((int64_t)e * 3 * nd + 3 * i) * ld + row;
+        zr += p[0];
+        zi += p[ld];
+        hh += p[2 * ld];
+      }
       const double ar = cf[(C_APRE + i) * ld], ai = cf[(C_APIM + i) * ld];
       const double qr = ar * hc.ap0_inv_re[i] - ai * hc.ap0_inv_im[i];
       const double qi = ar * hc.ap0_inv_im[i] + ai * hc.ap0_inv_re[i];
-      const double wr = qr * zr[i] - qi * zi[i];
-      const double wi = qr * zi[i] + qi * zr[i];
+      const double wr = qr * zr - qi * zi;
+      const double wi = qr * zi + qi * zr;
       plain += wr;
       Zr += wr;
       Zi += wi;
-      hht += (qr * qr + qi * qi) * hh[i];
+      hht += (qr * qr + qi * qi) * hh;
     }
-    const bool valid = active && cf[C_VALID * ld] != 0.0;
+    const bool valid = cf[C_VALID * ld] != 0.0;
     const double zabs = sqrt(Zr * Zr + Zi * Zi);
-    if (marg != 2) {
-      if (active) {
-        double out;
-        if (!valid) out = -INFINITY;
-        else if (marg == 0) out = -0.5 * hc.dd + plain - 0.5 * hht;
-        else out = -0.5 * hc.dd - 0.5 * hht + log_i0(zabs);
-        logl[row] = out;
-      }
+    if (marg == 2) {
+      ab->zbuf[row] = valid ? zabs : -1.0;
+      ab->zbuf[ld + row] = hht;
     } else {
-      // Distance marginal: the wave takes its 64 proposals one at a time,
-      // lanes stride the distance grid, fixed shuffle-tree reductions.
-      double mine = -INFINITY;
-      for (int j = 0; j < 64; ++j) {
-        const int vj = __shfl(valid ? 1 : 0, j, 64);
-        if (!vj) continue;
-        const double z1 = __shfl(zabs, j, 64);
-        const double h1 = __shfl(hht, j, 64);
-        double m = -INFINITY;
-        for (int q = lane; q < n_dist; q += 64) {
-          const double d = dgrid[q];
-          m = fmax(m, dlogw[q] - 0.5 * h1 / (d * d) + log_i0(z1 / d));
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-        double sum = 0.0;
-        for (int q = lane; q < n_dist; q += 64) {
-          const double d = dgrid[q];
-          sum += exp(dlogw[q] - 0.5 * h1 / (d * d) + log_i0(z1 / d) - m);
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-        if (lane == j) mine = -0.5 * hc.dd + m + log(sum);
-      }
-      if (active) logl[row] = valid ? mine : -INFINITY;
+      double out;
+      if (!valid) out = -INFINITY;
+      else if (marg == 0) out = -0.5 * hc.dd + plain - 0.5 * hht;
+      else out = -0.5 * hc.dd - 0.5 * hht + log_i0(zabs, C);
+      ab->logl[row] = out;
     }
+  }
+}
+
+// Distance marginal over the work list: one wave per row (wave_dist_lse).
+__global__ void __launch_bounds__(256) k_het_dist(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
+                                                  const double* __restrict__ dtab, int n_dist, double dd,
+                                                  LogI0Consts C) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * wpb;
+  const int64_t total = pre[ab->n_sub] * 64;
+  const int64_t ld = ab->ld;
+  for (int64_t it = wid; it < total; it += nwaves) {
+    int64_t row0, row_end;
+    if (!tile_rows(ab, pre, it >> 6, &row0, &row_end)) continue;
+    const int64_t row = row0 + (it & 63);
+    if (row >= row_end) continue;
+    const double z1 = ab->zbuf[row];
+    const double h1 = ab->zbuf[ld + row];
+    if (z1 < 0.0) {
+      if (lane == 0) ab->logl[row] = -INFINITY;
+      continue;
+    }
+    const double v = wave_dist_lse(z1, h1, dtab, n_dist, lane, C);
+    if (lane == 0) ab->logl[row] = -0.5 * dd + v;
   }
 }
 
@@ -484,59 +537,91 @@ static std::vector<int64_t> make_edges(const Geom& g, int n_bins, int rule) {
   return idx;
 }
 
+// Edge chunks per tile: enough (tile, chunk) items to give every SIMD a few
+// waves at this batch size, at least 16 bins per chunk, at most 32 chunks.
+static int het_ech(const gw_ctx* ctx, int64_t n_rows) {
+  const int64_t tiles = (n_rows + 63) / 64;
+  int64_t e = (4096 + tiles - 1) / tiles;
+  const int64_t emax = std::max<int64_t>(1, std::min<int64_t>(32, ctx->het->n_bins / 16));
+  e = std::max<int64_t>(1, std::min(e, emax));
+  return (int)e;
+}
+
 template <int ND>
-static gw_status launch_het_nd(gw_ctx* ctx, int marg, int prec, hipStream_t st) {
+static gw_status launch_het_nd(gw_ctx* ctx, int marg, int prec, int n_ech, hipStream_t st) {
   gw_het_state* h = ctx->het;
+  const TrigConsts T = make_trig_consts();
+  const int tpb = 64 * h->wpb;
+  int grid = h->grid;
+  if (grid <= 0) grid = 256 * 8 / h->wpb;  // 8 waves per CU
+  const int slot = prof_begin(ctx, st);
+  if (prec == GW_PREC_FP64)
+    hipLaunchKernelGGL((k_het<ND, 0>), dim3(grid), dim3(tpb), 0, st, h->args, h->tile_pre, h->rec, h->n_bins, n_ech,
+                       T);
+  else
+    hipLaunchKernelGGL((k_het<ND, 1>), dim3(grid), dim3(tpb), 0, st, h->args, h->tile_pre, h->rec, h->n_bins, n_ech,
+                       T);
+  prof_end(ctx, slot, st);
+  (void)marg;
+  return check_hip(hipGetLastError(), "heterodyne kernel launch");
+}
+
+// Queue the work-list sequence: tile scan, prologue, binned sums, combine
+// (+ distance marginal).  Reads the device argument block only.
+static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStream_t st) {
+  gw_het_state* h = ctx->het;
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, st, h->args, h->tile_pre);
+  gw_status s = check_hip(hipGetLastError(), "tile scan launch");
+  if (s != GW_OK) return s;
+  hipLaunchKernelGGL(k_het_prologue, dim3(256 * 4), dim3(256), 0, st, h->args, h->tile_pre, marg, ctx->geom);
+  s = check_hip(hipGetLastError(), "heterodyne prologue launch");
+  if (s != GW_OK) return s;
+  switch (ctx->n_det) {
+    case 1: s = launch_het_nd<1>(ctx, marg, prec, n_ech, st); break;
+    case 2: s = launch_het_nd<2>(ctx, marg, prec, n_ech, st); break;
+    case 3: s = launch_het_nd<3>(ctx, marg, prec, n_ech, st); break;
+    case 4: s = launch_het_nd<4>(ctx, marg, prec, n_ech, st); break;
+    default: s = set_error(GW_ENOTSUP, "n_det not supported");
+  }
+  if (s != GW_OK) return s;
   HetConst hc;
   for (int i = 0; i < kMaxDet; ++i) {
     hc.ap0_inv_re[i] = h->ap0_inv_re[i];
     hc.ap0_inv_im[i] = h->ap0_inv_im[i];
   }
   hc.dd = ctx->dd;
-  const TrigConsts T = make_trig_consts();
-  const int tpb = 64 * h->wpb;
-  int grid = h->grid;
-  if (grid <= 0) grid = 256 * 8 / h->wpb;  // 8 waves per CU
-  if (prec == GW_PREC_FP64)
-    hipLaunchKernelGGL((k_het<ND, 0>), dim3(grid), dim3(tpb), 0, st, h->args, h->tile_pre, h->rec, h->n_edges, marg,
-                       hc, ctx->dist_grid, ctx->dist_logw, ctx->n_dist, T);
-  else
-    hipLaunchKernelGGL((k_het<ND, 1>), dim3(grid), dim3(tpb), 0, st, h->args, h->tile_pre, h->rec, h->n_edges, marg,
-                       hc, ctx->dist_grid, ctx->dist_logw, ctx->n_dist, T);
-  return check_hip(hipGetLastError(), "heterodyne kernel launch");
+  const LogI0Consts C = make_log_i0_consts();
+  hipLaunchKernelGGL(k_het_combine, dim3(256 * 4), dim3(256), 0, st, h->args, h->tile_pre, ctx->n_det, n_ech, marg, hc,
+                     C);
+  s = check_hip(hipGetLastError(), "heterodyne combine launch");
+  if (s != GW_OK || marg != 2) return s;
+  hipLaunchKernelGGL(k_het_dist, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab, ctx->n_dist,
+                     ctx->dd, C);
+  return check_hip(hipGetLastError(), "heterodyne distance marginal launch");
 }
 
-// Queue tile scan + evaluation (reads the device argument block).
-static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, hipStream_t st) {
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, st, ctx->het->args, ctx->het->tile_pre);
-  gw_status s = check_hip(hipGetLastError(), "tile scan launch");
+// Workspace for n_rows rows and the argument block; returns the edge-chunk count.
+static gw_status het_prepare(gw_ctx* ctx, const double* theta, const int64_t* subs, int32_t n_sub, int64_t n_rows,
+                             double* logl, bool single, int* n_ech, hipStream_t st) {
+  gw_het_state* h = ctx->het;
+  *n_ech = het_ech(ctx, n_rows);
+  gw_status s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n_rows, "coefficient workspace");
+  if (s == GW_OK) s = ensure_buffer(&ctx->zbuf, &ctx->zbuf_cap, 2 * n_rows, "marginal workspace");
+  if (s == GW_OK)
+    s = ensure_buffer(&ctx->partial, &ctx->partial_cap, (int64_t)(*n_ech) * 3 * ctx->n_det * n_rows, "partials");
   if (s != GW_OK) return s;
-  hipLaunchKernelGGL(k_het_prologue, dim3(256 * 4), dim3(256), 0, st, ctx->het->args, ctx->het->tile_pre, marg,
-                     ctx->geom);
-  s = check_hip(hipGetLastError(), "heterodyne prologue launch");
-  if (s != GW_OK) return s;
-  const int slot = prof_begin(ctx, st);
-  switch (ctx->n_det) {
-    case 1: s = launch_het_nd<1>(ctx, marg, prec, st); break;
-    case 2: s = launch_het_nd<2>(ctx, marg, prec, st); break;
-    case 3: s = launch_het_nd<3>(ctx, marg, prec, st); break;
-    case 4: s = launch_het_nd<4>(ctx, marg, prec, st); break;
-    default: s = set_error(GW_ENOTSUP, "n_det not supported");
-  }
-  prof_end(ctx, slot, st);
-  return s;
+  hipLaunchKernelGGL(k_set_args, dim3(1), dim3(1), 0, st, h->args, theta,
+                     single ? (const int64_t*)h->subs_single : subs, logl, ctx->coef, ctx->zbuf, ctx->partial, n_rows,
+                     single ? 1 : n_sub, single ? h->subs_single : (int64_t*)nullptr, single ? n_rows : (int64_t)0);
+  return check_hip(hipGetLastError(), "argument kernel launch");
 }
 
 gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl, hipStream_t st) {
   if (!ctx->het) return set_error(GW_ESTATE, "loglike_batch: heterodyne_setup has not been called");
-  gw_het_state* h = ctx->het;
-  gw_status s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
+  int n_ech = 1;
+  gw_status s = het_prepare(ctx, theta, nullptr, 1, n, logl, true, &n_ech, st);
   if (s != GW_OK) return s;
-  hipLaunchKernelGGL(k_set_args, dim3(1), dim3(1), 0, st, h->args, theta, (const int64_t*)h->subs_single, logl,
-                     ctx->coef, n, 1, h->subs_single, n);
-  s = check_hip(hipGetLastError(), "argument kernel launch");
-  if (s != GW_OK) return s;
-  return enqueue_het(ctx, marg, prec, st);
+  return enqueue_het(ctx, marg, prec, n_ech, st);
 }
 
 }  // namespace gw
@@ -664,20 +749,17 @@ gw_status loglike_batch_uneven(gw_ctx* ctx, const double* theta, int64_t n_rows,
   gw_status s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
   if (s != GW_OK) return s;
   gw_het_state* h = ctx->het;
-  s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n_rows, "coefficient workspace");
+  int n_ech = 1;
+  s = het_prepare(ctx, theta, subs, n_sub, n_rows, logl, false, &n_ech, st);
   if (s != GW_OK) return s;
-  hipLaunchKernelGGL(k_set_args, dim3(1), dim3(1), 0, st, h->args, theta, subs, logl, ctx->coef, n_rows, n_sub,
-                     (int64_t*)nullptr, (int64_t)0);
-  s = check_hip(hipGetLastError(), "argument kernel launch");
-  if (s != GW_OK) return s;
-  if (!use_graph || ctx->prof) return enqueue_het(ctx, marg, prec, st);
+  if (!use_graph || ctx->prof) return enqueue_het(ctx, marg, prec, n_ech, st);
 
   if (!ctx->graphs) {
     ctx->graphs = new (std::nothrow) gw_graph_cache();
     if (!ctx->graphs) return set_error(GW_ENOMEM, "graph cache");
   }
   gw_graph_cache* gc = ctx->graphs;
-  const GraphKey key{marg, prec, h->wpb, h->grid};
+  const GraphKey key{marg, prec, h->wpb, h->grid, n_ech};
   auto it = gc->exec.find(key);
   if (it == gc->exec.end()) {
     if (!gc->cap_stream) {
@@ -688,7 +770,7 @@ gw_status loglike_batch_uneven(gw_ctx* ctx, const double* theta, int64_t n_rows,
     hipGraphExec_t ge = nullptr;
     s = check_hip(hipStreamBeginCapture(gc->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
     if (s != GW_OK) return s;
-    gw_status sq = enqueue_het(ctx, marg, prec, gc->cap_stream);
+    gw_status sq = enqueue_het(ctx, marg, prec, n_ech, gc->cap_stream);
     s = check_hip(hipStreamEndCapture(gc->cap_stream, &g), "end capture");
     if (sq != GW_OK) {
       if (g) (void)hipGraphDestroy(g);

@@ -60,7 +60,9 @@ def test_cfg1_het_parity(cfg1_het, marg, prec):
     prob, het, ctx, th, ref = cfg1_het
     got = ctx.loglike(_t(th), like=1, marg=marg, prec=prec).cpu().numpy()
     err = np.abs(got - ref[marg])
-    print(f"het cfg1 marg={marg} prec={prec}: max|dlogL|={err.max():.3e}", flush=True)
+    w = int(np.argmax(err))
+    print(f"het cfg1 marg={marg} prec={prec}: max|dlogL|={err.max():.3e} p99={np.quantile(err, 0.99):.3e} "
+          f"worst row {w} ({'near' if w < 512 else 'prior'}) logL={ref[marg][w]:.3f}", flush=True)
     assert np.all(np.isfinite(got))
     assert err.max() < TOL[prec]
 

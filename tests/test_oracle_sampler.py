@@ -1,0 +1,100 @@
+"""Pins of the sampler oracle: Philox against NumPy's Philox, the prior
+transform, slice-step invariance and nested sampling on a Gaussian with a
+known evidence."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import sampler as S
+
+
+def test_philox_matches_numpy():
+    # NumPy's Philox bit generator is Philox4x64-10; it increments the counter
+    # before producing a block, so its first block is ours at counter + 1.
+    def inc(c):  # 256-bit counter increment with carry
+        v = sum(int(w) << (64 * i) for i, w in enumerate(c)) + 1
+        return [(v >> (64 * i)) & (2 ** 64 - 1) for i in range(4)]
+
+    for key, ctr in [(0, [0, 0, 0, 0]), (0x1234567890ABCDEF, [5, 7, 9, 11]), (2 ** 64 - 1, [2 ** 64 - 2, 3, 0, 1])]:
+        bg = np.random.Philox(key=np.array([key, 0], dtype=np.uint64), counter=np.array(ctr, dtype=np.uint64))
+        raw = [int(v) for v in bg.random_raw(8)]
+        c1 = inc(ctr)
+        assert S.philox4x64(c1, (key, 0)) == raw[:4]
+        assert S.philox4x64(inc(c1), (key, 0)) == raw[4:]
+
+
+def test_philox_uniforms_range_and_uniformity():
+    u = np.concatenate([S.philox_uniforms(7, 3, c, 64) for c in range(64)])
+    assert np.all((u > 0) & (u < 1))
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+
+
+def test_prior_transform():
+    th = S.prior_transform(np.zeros(11))
+    assert np.allclose(th[:6], [1.1, 0.5, -0.05, -0.05, 0, 0])
+    assert th[7] == 0.0 and th[8] == 0.0 and abs(th[9] + math.pi / 2) < 1e-15 and th[12] == -0.1
+    th = S.prior_transform(np.ones(11))
+    assert np.allclose(th[:6], [1.4, 1.0, 0.05, 0.05, 5000, 5000])
+    assert abs(th[7] - math.pi) < 1e-15 and abs(th[9] - math.pi / 2) < 1e-15
+    # isotropic inclination and declination: cos(iota), sin(dec) uniform
+    u = np.random.default_rng(0).uniform(size=(4000, 11))
+    t = np.array([S.prior_transform(x) for x in u])
+    assert stats.kstest(np.cos(t[:, 7]), "uniform", args=(-1, 2)).pvalue > 1e-3
+    assert stats.kstest(np.sin(t[:, 9]), "uniform", args=(-1, 2)).pvalue > 1e-3
+
+
+def test_slice_step_keeps_uniform_on_a_ball():
+    # P17: uniform on a ball (the constrained prior of logL = -|x - c|^2) is
+    # invariant under the slice step; radial CDF (r / R)^d and a marginal stay
+    # uniform after many updates.
+    d, n, rad = 3, 1500, 0.3
+    rng = np.random.default_rng(1)
+    c = np.full(d, 0.5)
+    g = rng.normal(size=(n, d))
+    x = c + rad * (g / np.linalg.norm(g, axis=1, keepdims=True)) * rng.uniform(size=(n, 1)) ** (1 / d)
+    loglike = lambda p: -float(np.sum((p - c) ** 2))
+    lstar = -rad * rad
+    chol = np.linalg.cholesky(np.cov(x, rowvar=False))
+    logl = np.array([loglike(p) for p in x])
+    for step in range(6):
+        for i in range(n):
+            uni = S.philox_uniforms(11, step, i, S.N_UNIFORM_FIXED + 100)
+            x[i], logl[i], _, st, _ = S.slice_chain(x[i], logl[i], lstar, (0, 1, 2), chol, uni, loglike, w=0.5)
+            assert st == 0
+    r = np.linalg.norm(x - c, axis=1) / rad
+    assert np.all(r < 1)
+    assert stats.kstest(r ** d, "uniform").pvalue > 1e-3
+    # marginal of a uniform ball along one axis: density ~ 1 - s^2 on [-1, 1]
+    s = (x[:, 0] - c[0]) / rad
+    cdf = lambda v: 0.5 + 0.75 * (v - v ** 3 / 3)
+    assert stats.kstest(s, cdf).pvalue > 1e-3
+
+
+def test_slice_step_block_moves_only_block():
+    x0 = np.full(11, 0.5)
+    uni = S.philox_uniforms(3, 0, 0, S.N_UNIFORM_FIXED + 100)
+    x, v, ne, st, _ = S.slice_chain(x0, 0.0, -1.0, (7, 8), 0.1 * np.eye(2), uni, lambda p: 0.0)
+    assert st == 0 and ne >= 1
+    mask = np.ones(11, bool)
+    mask[[7, 8]] = False
+    assert np.array_equal(x[mask], x0[mask]) and not np.array_equal(x[[7, 8]], x0[[7, 8]])
+
+
+@pytest.mark.slow
+def test_nested_sampling_gaussian_evidence():
+    # P16: a normalised Gaussian likelihood well inside the unit cube has
+    # Z = 1 (log Z = 0) under the uniform prior; the estimate must fall within
+    # 3 sigma, sigma = sqrt(H / m).
+    d, sig = 6, 0.06
+    mu = np.full(d, 0.5)
+
+    def loglike(x):
+        return float(-0.5 * np.sum(((x - mu) / sig) ** 2) - d * math.log(sig * math.sqrt(2 * math.pi)))
+
+    blocks = ((0, 1), (2,), (3, 4), (5,))
+    res = S.nested_sampling(loglike, n_live=150, n_delete=20, seed=5, dlogz=0.1, blocks=blocks, n_dim=d,
+                            max_shrink=60)
+    assert abs(res["log_z"]) < 3 * res["log_z_err"] + 0.05, res["log_z"]
+    assert res["h"] > 5
