@@ -190,6 +190,60 @@ gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid);
 gw_status gw_graph_info(const gw_ctx* ctx, int32_t* n_graphs, double* last_instantiate_ms);
 
 /*
+ * Constrained slice step (Sec. II.B Eq. cprior, Sec. II.C Eq. block_cprior,
+ * Sec. III.B): one hit-and-run slice update of one Gibbs block for each of k
+ * chains on the constrained prior pi(theta) 1[log L(theta) > log L*].
+ * The sampler space is the 11-dimensional unit cube
+ *   [Mc, q, chi1, chi2, Lambda1, Lambda2, iota, ra, dec, psi, t_c]
+ * of the uniform / isotropic prior Mc in [1.1, 1.4], q in [0.5, 1],
+ * chi in [-0.05, 0.05], Lambda in [0, 5000], cos(iota) and sin(dec)
+ * uniform, ra in [0, 2 pi), psi in [0, pi), t_c in [-0.1, 0.1] s, with phi_c
+ * and d_L marginalised (marg must be GW_MARG_PHASE_DIST).
+ * Per chain: u a uniform unit vector (Box-Muller from uniforms 0..3), the
+ * direction d = L u with L the block's lower Cholesky factor; a bracket
+ * [-r w, (1 - r) w] with r = uniform 4; each end stepped out by w while
+ * log L > log L* (at most max_out steps per side); then shrink draws
+ * t = t_lo + u_s (t_hi - t_lo), s = 0 .. max_shrink - 1 (uniform 5 + s),
+ * until log L > log L*, the bracket end on the side of t moving to t.  A point
+ * outside the cube fails without a likelihood call.  After max_shrink
+ * failures the chain keeps its point (status 1).
+ * Random numbers: ``uniforms`` (device [k, 5 + max_shrink]) when not NULL,
+ * else Philox4x64-10 (Salmon et al. 2011): uniform j of chain c is word j % 4
+ * of the block at counter (counter, c, j / 4, 0) under key (seed, 0), mapped
+ * to ((w >> 11) + 0.5) 2^-53.
+ * Blocks until done (the host checks progress every four rounds).
+ */
+typedef struct {
+  int64_t k;              /* number of chains */
+  double* x;              /* device [k, 11] unit-cube points, updated in place */
+  double* logl;           /* device [k] log L of x, updated in place */
+  double logl_star;       /* constraint log L* */
+  const int32_t* block;   /* host [block_dim] coordinate indices 0..10, distinct */
+  int32_t block_dim;      /* 1 .. 4 */
+  const double* chol;     /* host [block_dim, block_dim] lower-triangular, row-major */
+  uint64_t seed;          /* Philox key */
+  uint64_t counter;       /* Philox counter base */
+  const double* uniforms; /* device [k, 5 + max_shrink] or NULL */
+  double w;               /* bracket width along t (> 0) */
+  int32_t max_out;        /* >= 0 */
+  int32_t max_shrink;     /* 1 .. 10000 */
+  int32_t like;           /* GW_FULL or GW_HET */
+  int32_t marg;           /* GW_MARG_PHASE_DIST */
+  int32_t prec;           /* GW_PREC_FP64 or GW_PREC_MIXED */
+  int32_t* n_evals;       /* device [k] likelihood calls per chain, or NULL */
+  int32_t* status;        /* device [k] 0 moved, 1 kept, or NULL */
+} gw_slice_args;
+
+gw_status slice_step(gw_ctx* ctx, const gw_slice_args* args, void* stream);
+
+/*
+ * The sampler's prior transform: unit-cube points x (device [n, 11], layout
+ * as for slice_step) to parameter vectors theta (device [n, 13]; d_L = 1 and
+ * phi_c = 0, both marginalised).  Used to evaluate a fresh live set.
+ */
+gw_status gw_prior_transform(gw_ctx* ctx, const double* x, int64_t n, double* theta, void* stream);
+
+/*
  * Autotuner: times every candidate launch shape of the full-band (like =
  * GW_FULL) or heterodyned (GW_HET) kernels on the caller's batch ``theta``
  * (device [n, 13]), ``reps`` timed calls each after one warm-up, keeps the

@@ -175,7 +175,7 @@ def nested_sampling(loglike, n_live: int, n_delete: int, seed: int, dlogz: float
     it = 0
     counter = 0
     while it < max_iter:
-        order = np.argsort(logl)
+        order = np.argsort(logl, kind="stable")
         worst = order[:n_delete]
         logl_star = float(logl[worst[-1]])
         for j, i in enumerate(worst):

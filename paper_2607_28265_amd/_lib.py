@@ -47,6 +47,29 @@ class gw_problem(ctypes.Structure):
     ]
 
 
+class gw_slice_args(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int64),
+        ("x", ctypes.c_void_p),
+        ("logl", ctypes.c_void_p),
+        ("logl_star", ctypes.c_double),
+        ("block", ctypes.POINTER(ctypes.c_int32)),
+        ("block_dim", ctypes.c_int32),
+        ("chol", ctypes.POINTER(ctypes.c_double)),
+        ("seed", ctypes.c_uint64),
+        ("counter", ctypes.c_uint64),
+        ("uniforms", ctypes.c_void_p),
+        ("w", ctypes.c_double),
+        ("max_out", ctypes.c_int32),
+        ("max_shrink", ctypes.c_int32),
+        ("like", ctypes.c_int32),
+        ("marg", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("n_evals", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+    ]
+
+
 _LIB = None
 
 _P = ctypes.c_void_p
@@ -70,6 +93,8 @@ _SIGS = {
                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                    _P]),
     "gw_graph_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "slice_step": (ctypes.c_int, [_P, ctypes.POINTER(gw_slice_args), _P]),
+    "gw_prior_transform": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     "gw_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
 
@@ -263,3 +288,43 @@ def gw_autotune(ctx, theta, like: int, marg: int, prec: int, reps: int = 3, stre
     check(load().gw_autotune(ctx, _tensor_ptr(theta), theta.shape[0], like, marg, prec, reps, shape,
                              ctypes.byref(ms), _stream_ptr(stream)), "gw_autotune")
     return (shape[0], shape[1]), ms.value
+
+
+def slice_step(ctx, x, logl, logl_star: float, block, chol, seed: int = 0, counter: int = 0, uniforms=None,
+               w: float = 1.0, max_out: int = 10, max_shrink: int = 100, like: int = GW_HET,
+               marg: int = GW_MARG_PHASE_DIST, prec: int = GW_PREC_FP64, n_evals=None, status=None, stream=None):
+    """One slice update of one block for every chain; x [k, 11] and logl [k] (CUDA float64) change in place."""
+    import numpy as np
+    import torch
+    if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == 11):
+        raise ValueError("x must be a contiguous CUDA float64 tensor of shape [k, 11]")
+    k = x.shape[0]
+    if not (logl.is_cuda and logl.dtype == torch.float64 and logl.is_contiguous() and logl.numel() == k):
+        raise ValueError("logl must be a contiguous CUDA float64 tensor with k entries")
+    blk = np.ascontiguousarray(block, dtype=np.int32)
+    ch = np.ascontiguousarray(chol, dtype=np.float64).reshape(len(blk), len(blk))
+    if uniforms is not None and not (uniforms.is_cuda and uniforms.dtype == torch.float64
+                                     and uniforms.is_contiguous() and uniforms.shape == (k, 5 + max_shrink)):
+        raise ValueError("uniforms must be a contiguous CUDA float64 tensor of shape [k, 5 + max_shrink]")
+    for t in (n_evals, status):
+        if t is not None and not (t.is_cuda and t.dtype == torch.int32 and t.numel() == k and t.is_contiguous()):
+            raise ValueError("n_evals / status must be contiguous CUDA int32 tensors with k entries")
+    a = gw_slice_args(k=k, x=x.data_ptr(), logl=logl.data_ptr(), logl_star=float(logl_star),
+                      block=blk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), block_dim=len(blk),
+                      chol=ch.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), seed=int(seed), counter=int(counter),
+                      uniforms=uniforms.data_ptr() if uniforms is not None else None, w=float(w),
+                      max_out=int(max_out), max_shrink=int(max_shrink), like=int(like), marg=int(marg),
+                      prec=int(prec), n_evals=n_evals.data_ptr() if n_evals is not None else None,
+                      status=status.data_ptr() if status is not None else None)
+    check(load().slice_step(ctx, ctypes.byref(a), _stream_ptr(stream)), "slice_step")
+
+
+def gw_prior_transform(ctx, x, stream=None):
+    """Unit-cube points (CUDA float64 [n, 11]) -> parameter vectors [n, 13]."""
+    import torch
+    if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == 11):
+        raise ValueError("x must be a contiguous CUDA float64 tensor of shape [n, 11]")
+    th = torch.empty((x.shape[0], GW_NPARAM), dtype=torch.float64, device=x.device)
+    check(load().gw_prior_transform(ctx, _tensor_ptr(x), x.shape[0], _tensor_ptr(th), _stream_ptr(stream)),
+          "gw_prior_transform")
+    return th

@@ -212,6 +212,7 @@ gw_status gw_ctx_destroy(gw_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   het_free(ctx);
   graphs_free(ctx);
+  slice_free(ctx);
   for (hipEvent_t e : ctx->prof_ev)
     if (e) (void)hipEventDestroy(e);
   double* bufs[] = {ctx->bins, ctx->dist_tab, ctx->coef, ctx->partial, ctx->zbuf};

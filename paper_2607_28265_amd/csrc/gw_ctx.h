@@ -13,6 +13,7 @@
 
 struct gw_het_state;
 struct gw_graph_cache;
+struct gw_slice_ws;
 
 struct gw_ctx {
   int device = 0;
@@ -45,6 +46,7 @@ struct gw_ctx {
   int prof_used = 0;
   gw_het_state* het = nullptr;
   gw_graph_cache* graphs = nullptr;
+  gw_slice_ws* slice = nullptr;
 };
 
 namespace gw {
@@ -72,6 +74,7 @@ void prof_end(gw_ctx* ctx, int slot, hipStream_t st);
 // Heterodyne and graph state owned by the context.
 void het_free(gw_ctx* ctx);
 void graphs_free(gw_ctx* ctx);
+void slice_free(gw_ctx* ctx);
 gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl,
                       hipStream_t st);
 

@@ -324,18 +324,46 @@ __device__ inline double log_i0(double x, const LogI0Consts& C) {
 
 // Distance marginal over a grid, evaluated by one wave for one proposal:
 //   LSE_j [ ln w_j - hh1 / (2 d_j^2) + ln I0(|Z1| / d_j) ],
-// with the grid as records (d_j, 1/d_j, 1/(2 d_j^2), ln w_j).  Lanes stride the
-// grid with an online log-sum-exp (one exp per point); the 64 partial
-// (max, sum) pairs are merged by a fixed shuffle tree, so every lane returns
-// the same, reproducible value.
+// with the grid as records (d_j, 1/d_j, 1/(2 d_j^2), ln w_j).  Since
+// ln I0(x) <= x, b_j = ln w_j - hh1 / (2 d_j^2) + |Z1| / d_j bounds each term
+// from above; the exact term at the largest bound is a lower bound on the
+// maximum, so points whose bound is more than 42 below it (together below
+// 1000 e^-42 < 1e-15 of the sum) are skipped.  The rest go through an online
+// log-sum-exp (one exp per point); the 64 per-lane (max, sum) pairs are merged
+// by a fixed shuffle tree, so every lane returns the same, reproducible value.
 __device__ inline double wave_dist_lse(double z1, double hh1, const double* __restrict__ tab, int n_dist, int lane,
                                        const LogI0Consts& C) {
-  double m = -INFINITY, s = 0.0;
   const double iz = z1 > 0.0 ? 1.0 / z1 : 0.0;
+  // pass 1: largest upper bound and where it is
+  double bmax = -INFINITY;
+  int jmax = 0;
   for (int j = lane; j < n_dist; j += 64) {
     const double* r = tab + 4 * j;
-    const double x = z1 * r[1];
-    const double t = r[3] - hh1 * r[2] + log_i0_xu(x, r[0] * iz, C);
+    const double b = r[3] - hh1 * r[2] + z1 * r[1];
+    if (b > bmax) {
+      bmax = b;
+      jmax = j;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double b2 = __shfl_xor(bmax, o, 64);
+    const int j2 = __shfl_xor(jmax, o, 64);
+    if (b2 > bmax || (b2 == bmax && j2 < jmax)) {
+      bmax = b2;
+      jmax = j2;
+    }
+  }
+  const double* rm = tab + 4 * jmax;
+  const double tmax = rm[3] - hh1 * rm[2] + log_i0_xu(z1 * rm[1], rm[0] * iz, C);
+  const double cut = tmax - 42.0;
+  // pass 2: exact terms that can matter
+  double m = -INFINITY, s = 0.0;
+  for (int j = lane; j < n_dist; j += 64) {
+    const double* r = tab + 4 * j;
+    const double b = r[3] - hh1 * r[2] + z1 * r[1];
+    if (b < cut) continue;
+    const double t = r[3] - hh1 * r[2] + log_i0_xu(z1 * r[1], r[0] * iz, C);
     const bool up = t > m;
     const double e = exp(up ? m - t : t - m);
     s = up ? fma(s, e, 1.0) : s + e;

@@ -178,10 +178,10 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
 }
 
 // Combine the chunk partials and apply the marginalisation.  A workgroup
-// takes 64 proposals; its 4 waves sum the chunks c = w (mod 4) in order and
-// wave 0 adds the four sums in order, so the result is reproducible.  For the
+// takes 64 proposals; its 16 waves sum the chunks c = w (mod 16) in order and
+// wave 0 adds the sixteen sums in order, so the result is reproducible.  For the
 // distance marginal this writes (|Z_1|, <h|h>_1) for k_dist_marg.
-__global__ void __launch_bounds__(256) k_epilogue(const double* __restrict__ partial, int n_chunks, int nd,
+__global__ void __launch_bounds__(1024) k_epilogue(const double* __restrict__ partial, int n_chunks, int nd,
                                                   const double* __restrict__ coef, int64_t ld, int64_t n,
                                                   double dd, int marg, LogI0Consts C, double* __restrict__ logl,
                                                   double* __restrict__ zbuf) {
@@ -192,20 +192,19 @@ __global__ void __launch_bounds__(256) k_epilogue(const double* __restrict__ par
   double z[2 * kMaxDet];
 #pragma unroll
   for (int j = 0; j < 2 * kMaxDet; ++j) z[j] = 0.0;
-  for (int c = wave; c < n_chunks; c += 4) {
+  for (int c = wave; c < n_chunks; c += 16) {
 #pragma unroll
     for (int j = 0; j < 2 * kMaxDet; ++j)
       if (j < 2 * nd) z[j] += partial[((int64_t)c * 2 * nd + j) * n + pc];
   }
-  __shared__ double red[3][2 * kMaxDet][64];
+  __shared__ double red[15][2 * kMaxDet][64];
   if (wave > 0) {
 #pragma unroll
     for (int j = 0; j < 2 * kMaxDet; ++j) red[wave - 1][j][lane] = z[j];
   }
   __syncthreads();
   if (wave != 0 || p >= n) return;
-#pragma unroll
-  for (int w = 0; w < 3; ++w)
+  for (int w = 0; w < 15; ++w)
 #pragma unroll
     for (int j = 0; j < 2 * kMaxDet; ++j) z[j] += red[w][j][lane];
   const bool valid = coef[C_VALID * ld + p] != 0.0;
@@ -363,7 +362,7 @@ gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, cons
   if (n == 0) return GW_OK;
   const int64_t blocks = (n + 63) / 64;
   const LogI0Consts C = make_log_i0_consts();
-  hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(256), 0, st, partial, n_chunks, ctx->n_det, coef, ld,
+  hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(1024), 0, st, partial, n_chunks, ctx->n_det, coef, ld,
                      n, ctx->dd, marg, C, logl, ctx->zbuf);
   gw_status s = check_hip(hipGetLastError(), "epilogue launch");
   if (s != GW_OK || marg != 2) return s;

@@ -299,14 +299,19 @@ __device__ inline void het_phasor(double r, const TrigConsts& T, double* gr, dou
 }
 
 // Binned sums of one (tile, edge chunk) work item.  The waves of a workgroup
-// take consecutive tiles of the same edge chunk, so they share the edge
-// records; per lane the partial (Z_i, <h_i|h_i>) of the chunk's bins go to
-// ab->part, without the (A P_i) / (A0 P0_i) prefactor.
+// take consecutive tiles of the same edge chunk; the chunk's edge records are
+// staged through LDS in pieces of up to kLdsEdges edges (coalesced copy by the
+// whole workgroup, then wave-uniform broadcast reads).  Per lane the partial
+// (Z_i, <h_i|h_i>) of the chunk's bins go to ab->part, without the
+// (A P_i) / (A0 P0_i) prefactor.
+constexpr int kLdsEdges = 128;
+
 template <int ND, int PREC>
 __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
                                              const double* __restrict__ rec, int n_bins, int n_ech, TrigConsts T) {
   constexpr int RS = het_rs(ND);
   constexpr int BO = het_bin_off(ND);
+  __shared__ double srec[kLdsEdges * RS];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
@@ -320,19 +325,21 @@ __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, con
     const int ech = (int)(q % n_ech);
     const int64_t t = (q / n_ech) * wpb + wave;
     int64_t row0 = 0, row_end = 0;
-    if (t >= total || !tile_rows(ab, pre, t, &row0, &row_end)) continue;
+    const bool has = t < total && tile_rows(ab, pre, t, &row0, &row_end);
     const int64_t row = row0 + lane;
-    const bool active = row < row_end;
-    const int64_t rr = active ? row : row0;
+    const bool active = has && row < row_end;
+    const int64_t rr = active ? row : (has ? row0 : 0);
     const double* cf = coef + rr;
     PhaseCoef c;
-    c.a0 = cf[C_A0 * ld]; c.a2 = cf[C_A2 * ld]; c.a3 = cf[C_A3 * ld]; c.a4 = cf[C_A4 * ld];
-    c.a5 = cf[C_A5 * ld]; c.a6 = cf[C_A6 * ld]; c.a7 = cf[C_A7 * ld]; c.a8 = cf[C_A8 * ld];
-    c.a10 = cf[C_A10 * ld]; c.a12 = cf[C_A12 * ld]; c.b5 = cf[C_B5 * ld]; c.b6 = cf[C_B6 * ld];
     double dt[ND];
     dt[0] = 0.0;
+    if (has) {
+      c.a0 = cf[C_A0 * ld]; c.a2 = cf[C_A2 * ld]; c.a3 = cf[C_A3 * ld]; c.a4 = cf[C_A4 * ld];
+      c.a5 = cf[C_A5 * ld]; c.a6 = cf[C_A6 * ld]; c.a7 = cf[C_A7 * ld]; c.a8 = cf[C_A8 * ld];
+      c.a10 = cf[C_A10 * ld]; c.a12 = cf[C_A12 * ld]; c.b5 = cf[C_B5 * ld]; c.b6 = cf[C_B6 * ld];
 #pragma unroll
-    for (int i = 1; i < ND; ++i) dt[i] = cf[(C_DT1 + i - 1) * ld];
+      for (int i = 1; i < ND; ++i) dt[i] = cf[(C_DT1 + i - 1) * ld];
+    }
 
     // bins [b0, b1) of this chunk use edges b0 .. b1
     const int b0 = ech * per < n_bins ? ech * per : n_bins;
@@ -343,35 +350,44 @@ __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, con
       zr[i] = zi[i] = hh[i] = 0.0;
       pr[i] = pi[i] = 0.0;
     }
-    for (int e = b0; e <= b1 && b1 > b0; ++e) {
-      const double* __restrict__ r = rec + (int64_t)e * RS;
-      const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
-      const double f = r[H_F];
-      const double inv = r[BO];
+    const int e_last = b1 > b0 ? b1 : b0 - 1;  // empty chunk: no edges
+    for (int e0 = b0; e0 <= e_last; e0 += kLdsEdges) {
+      const int ne = e_last - e0 + 1 < kLdsEdges ? e_last - e0 + 1 : kLdsEdges;
+      __syncthreads();
+      for (int j = threadIdx.x; j < ne * RS; j += blockDim.x) srec[j] = rec[(int64_t)e0 * RS + j];
+      __syncthreads();
+      if (!has) continue;
+      for (int el = 0; el < ne; ++el) {
+        const int e = e0 + el;
+        const double* r = srec + el * RS;
+        const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
+        const double f = r[H_F];
+        const double inv = r[BO];
 #pragma unroll
-      for (int i = 0; i < ND; ++i) {
-        const double di = i == 0 ? d0 : fma(f, dt[i], d0) - r[H_PHI0 + i];
-        double gr, gi;
-        het_phasor<PREC>(di, T, &gr, &gi);
-        if (e > b0) {
-          const double* __restrict__ bd = r + BO + 1 + 6 * i;
-          const double r0r = 0.5 * (gr + pr[i]), r0i = 0.5 * (gi + pi[i]);
-          const double r1r = (gr - pr[i]) * inv, r1i = (gi - pi[i]) * inv;
-          zr[i] = fma(bd[0], r0r, zr[i]);
-          zr[i] = fma(-bd[1], r0i, zr[i]);
-          zr[i] = fma(bd[2], r1r, zr[i]);
-          zr[i] = fma(-bd[3], r1i, zr[i]);
-          zi[i] = fma(bd[0], r0i, zi[i]);
-          zi[i] = fma(bd[1], r0r, zi[i]);
-          zi[i] = fma(bd[2], r1i, zi[i]);
-          zi[i] = fma(bd[3], r1r, zi[i]);
-          const double m = fma(r0r, r0r, r0i * r0i);
-          const double x = fma(r0r, r1r, r0i * r1i);
-          hh[i] = fma(bd[4], m, hh[i]);
-          hh[i] = fma(bd[5], x, hh[i]);
+        for (int i = 0; i < ND; ++i) {
+          const double di = i == 0 ? d0 : fma(f, dt[i], d0) - r[H_PHI0 + i];
+          double gr, gi;
+          het_phasor<PREC>(di, T, &gr, &gi);
+          if (e > b0) {
+            const double* bd = r + BO + 1 + 6 * i;
+            const double r0r = 0.5 * (gr + pr[i]), r0i = 0.5 * (gi + pi[i]);
+            const double r1r = (gr - pr[i]) * inv, r1i = (gi - pi[i]) * inv;
+            zr[i] = fma(bd[0], r0r, zr[i]);
+            zr[i] = fma(-bd[1], r0i, zr[i]);
+            zr[i] = fma(bd[2], r1r, zr[i]);
+            zr[i] = fma(-bd[3], r1i, zr[i]);
+            zi[i] = fma(bd[0], r0i, zi[i]);
+            zi[i] = fma(bd[1], r0r, zi[i]);
+            zi[i] = fma(bd[2], r1i, zi[i]);
+            zi[i] = fma(bd[3], r1r, zi[i]);
+            const double m = fma(r0r, r0r, r0i * r0i);
+            const double x = fma(r0r, r1r, r0i * r1i);
+            hh[i] = fma(bd[4], m, hh[i]);
+            hh[i] = fma(bd[5], x, hh[i]);
+          }
+          pr[i] = gr;
+          pi[i] = gi;
         }
-        pr[i] = gr;
-        pi[i] = gi;
       }
     }
     if (active) {

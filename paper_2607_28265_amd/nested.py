@@ -1,0 +1,187 @@
+"""Slice-within-Gibbs nested sampling driven from the host.
+
+Sec. II.B: m live points; every iteration deletes the k lowest-likelihood
+points, raises log L* to the largest deleted value, accumulates their prior
+volume into the evidence and replaces them by constrained draws.  Sec. II.C /
+III.B: a replacement starts from a surviving live point and runs M Gibbs
+sweeps over the parameter blocks, each block moved by one hit-and-run slice
+step on the GPU (``slice_step``, all k chains at once) along directions from
+the block covariance of the live points.
+
+The host keeps the FP64 evidence bookkeeping (the k deletions taken in order
+with live counts m, m-1, ..., m-k+1), the start-point choice and the block
+Cholesky factors; the live points and every likelihood stay on the device.
+State can be written to an .npz checkpoint and resumed bit for bit.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import _lib
+
+N_DIM = 11
+# Slow blocks {Mc, q, Lambda1, Lambda2}, {chi1}, {chi2}, {iota};
+# fast blocks {ra, dec}, {psi}, {t_c} (indices into the unit cube).
+BLOCKS = ((0, 1, 4, 5), (2,), (3,), (6,), (7, 8), (9,), (10,))
+
+
+def _logsumexp(a):
+    a = np.asarray(a, dtype=np.float64)
+    if a.size == 0:
+        return -math.inf
+    m = np.max(a)
+    if not np.isfinite(m):
+        return float(m)
+    return float(m + math.log(np.sum(np.exp(a - m))))
+
+
+class NestedSampler:
+    def __init__(self, ctx, n_live: int = 1000, n_delete: int = 125, seed: int = 6, dlogz: float = 0.1,
+                 blocks=BLOCKS, like: int = _lib.GW_HET, prec: int = _lib.GW_PREC_MIXED, sweeps: int = 1,
+                 w: float = 1.0, max_out: int = 10, max_shrink: int = 100):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        self.m, self.k = int(n_live), int(n_delete)
+        self.seed = int(seed)
+        self.dlogz = float(dlogz)
+        self.blocks = tuple(tuple(b) for b in blocks)
+        self.like, self.prec = like, prec
+        self.sweeps, self.w, self.max_out, self.max_shrink = sweeps, w, max_out, max_shrink
+        self.rng = np.random.default_rng(self.seed)
+        self.dev = torch.device("cuda", ctx.device)
+        x0 = self.rng.uniform(size=(self.m, N_DIM))
+        self.x = torch.from_numpy(x0).to(self.dev)
+        self.logl = torch.empty(self.m, dtype=torch.float64, device=self.dev)
+        self._eval(self.x, self.logl)
+        self.dead_logl: list[float] = []
+        self.dead_logw: list[float] = []
+        self.dead_x: list[np.ndarray] = []
+        self.log_x = 0.0
+        self.iteration = 0
+        self.counter = 0
+        self.n_evals = self.m
+        self.wall = 0.0
+
+    # -- likelihood of unit-cube points (initial live set) ------------------
+    def _eval(self, x, out):
+        torch = self.torch
+        th = self._unit_to_theta(x)
+        if self.like == _lib.GW_HET:
+            _lib.loglike_batch(self.ctx.handle, th, _lib.GW_HET, _lib.GW_MARG_PHASE_DIST, self.prec, out=out)
+        else:
+            _lib.loglike_batch(self.ctx.handle, th, _lib.GW_FULL, _lib.GW_MARG_PHASE_DIST, self.prec, out=out)
+        torch.cuda.synchronize()
+
+    def _unit_to_theta(self, x):
+        return _lib.gw_prior_transform(self.ctx.handle, x.contiguous())
+
+    # -- evidence ----------------------------------------------------------
+    def log_z_dead(self):
+        return _logsumexp(self.dead_logw)
+
+    def log_z_live(self, logl_host):
+        return self.log_x + _logsumexp(logl_host) - math.log(self.m)
+
+    def converged(self, logl_host) -> bool:
+        zd = self.log_z_dead()
+        if not np.isfinite(zd):
+            return False
+        return np.logaddexp(zd, self.log_z_live(logl_host)) - zd < self.dlogz
+
+    # -- one iteration -----------------------------------------------------
+    def step(self):
+        torch = self.torch
+        logl = self.logl.cpu().numpy()
+        x_host = self.x.cpu().numpy()
+        order = np.argsort(logl, kind="stable")
+        worst = order[: self.k]
+        lstar = float(logl[worst[-1]])
+        for j, i in enumerate(worst):
+            new_log_x = self.log_x - 1.0 / (self.m - j)
+            self.dead_logl.append(float(logl[i]))
+            self.dead_logw.append(float(logl[i]) + self.log_x + math.log1p(-math.exp(new_log_x - self.log_x)))
+            self.dead_x.append(x_host[i].copy())
+            self.log_x = new_log_x
+        survivors = order[self.k:]
+        starts = self.rng.choice(survivors, size=self.k, replace=True)
+        chols = []
+        for b in self.blocks:
+            sub = x_host[survivors][:, list(b)]
+            cov = np.atleast_2d(np.cov(sub, rowvar=False)) + 1e-12 * np.eye(len(b))
+            chols.append(np.linalg.cholesky(cov))
+        idx = torch.from_numpy(starts).to(self.dev)
+        xn = self.x.index_select(0, idx).contiguous()
+        ln = self.logl.index_select(0, idx).contiguous()
+        ne = torch.zeros(self.k, dtype=torch.int32, device=self.dev)
+        for _ in range(self.sweeps):
+            for bi, b in enumerate(self.blocks):
+                _lib.slice_step(self.ctx.handle, xn, ln, lstar, b, chols[bi], seed=self.seed, counter=self.counter,
+                                w=self.w, max_out=self.max_out, max_shrink=self.max_shrink, like=self.like,
+                                marg=_lib.GW_MARG_PHASE_DIST, prec=self.prec, n_evals=ne)
+                self.n_evals += int(ne.sum().item())
+                self.counter += 1
+        wi = torch.from_numpy(worst).to(self.dev)
+        self.x.index_copy_(0, wi, xn)
+        self.logl.index_copy_(0, wi, ln)
+        self.iteration += 1
+
+    def run(self, max_iter: int = 100000, checkpoint: str | None = None, every: int = 50, verbose: bool = False):
+        t0 = time.perf_counter()
+        while self.iteration < max_iter:
+            self.step()
+            logl = self.logl.cpu().numpy()
+            if verbose and self.iteration % 20 == 0:
+                print(f"it {self.iteration} logL*={max(self.dead_logl[-self.k:]):.3f} "
+                      f"logZ_dead={self.log_z_dead():.3f} evals={self.n_evals}", flush=True)
+            if checkpoint and self.iteration % every == 0:
+                self.save(checkpoint)
+            if self.converged(logl):
+                break
+        self.torch.cuda.synchronize()
+        self.wall += time.perf_counter() - t0
+        return self.result()
+
+    def result(self) -> dict:
+        logl = self.logl.cpu().numpy()
+        all_logw = np.concatenate([self.dead_logw, logl + self.log_x - math.log(self.m)])
+        all_logl = np.concatenate([self.dead_logl, logl])
+        log_z = _logsumexp(all_logw)
+        p = np.exp(all_logw - log_z)
+        h = float(np.sum(p * all_logl) - log_z)
+        ess = float(1.0 / np.sum(p * p))
+        return dict(log_z=log_z, log_z_err=math.sqrt(max(h, 0.0) / self.m), h=h, iterations=self.iteration,
+                    n_evals=self.n_evals, wall_s=self.wall, ess=ess)
+
+    def samples(self):
+        """(unit-cube points, normalised posterior weights) of dead + live points."""
+        x = np.concatenate([np.array(self.dead_x).reshape(-1, N_DIM), self.x.cpu().numpy()])
+        logl = self.logl.cpu().numpy()
+        lw = np.concatenate([self.dead_logw, logl + self.log_x - math.log(self.m)])
+        w = np.exp(lw - _logsumexp(lw))
+        return x, w
+
+    # -- checkpoint / resume -----------------------------------------------
+    def save(self, path: str):
+        np.savez(path, x=self.x.cpu().numpy(), logl=self.logl.cpu().numpy(),
+                 dead_logl=np.array(self.dead_logl), dead_logw=np.array(self.dead_logw),
+                 dead_x=np.array(self.dead_x).reshape(-1, N_DIM), log_x=self.log_x, iteration=self.iteration,
+                 counter=self.counter, n_evals=self.n_evals,
+                 rng=np.frombuffer(repr(self.rng.bit_generator.state).encode(), dtype=np.uint8))
+
+    def load(self, path: str):
+        import ast
+        d = np.load(path, allow_pickle=False)
+        self.x = self.torch.from_numpy(d["x"]).to(self.dev)
+        self.logl = self.torch.from_numpy(d["logl"]).to(self.dev)
+        self.dead_logl = list(d["dead_logl"])
+        self.dead_logw = list(d["dead_logw"])
+        self.dead_x = list(d["dead_x"])
+        self.log_x = float(d["log_x"])
+        self.iteration = int(d["iteration"])
+        self.counter = int(d["counter"])
+        self.n_evals = int(d["n_evals"])
+        self.rng.bit_generator.state = ast.literal_eval(bytes(d["rng"]).decode())

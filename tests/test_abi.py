@@ -33,7 +33,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared_functions()
-    assert {"loglike_batch", "gw_template", "heterodyne_setup", "loglike_batch_uneven"} <= set(names)
+    assert {"loglike_batch", "gw_template", "heterodyne_setup", "loglike_batch_uneven", "slice_step"} <= set(names)
     for n in names:
         assert hasattr(lib, n), f"symbol {n} declared in gwswig.h but not exported"
 
