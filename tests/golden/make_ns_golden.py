@@ -1,0 +1,59 @@
+"""Write the oracle nested-sampling reference for a seeded heterodyned problem.
+
+Calls only the oracle and the seeded input generator:
+    python tests/golden/make_ns_golden.py cfg1   # 8 s segment, m=200, k=25, 200 bins
+    python tests/golden/make_ns_golden.py cfg2   # 128 s segment, m=1000, k=125, 500 bins
+The injection sits at network SNR 24 under the 1e-49 PSD scale; phi_c and d_L
+are marginalised; seeds as in gwsynth.SEEDS (sampler seed 6).
+"""
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import gwsynth  # noqa: E402
+from oracle import heterodyne as H  # noqa: E402
+from oracle import likelihood as L  # noqa: E402
+from oracle import sampler as S  # noqa: E402
+
+SETTINGS = {"cfg1": dict(n_live=200, n_delete=25, n_bins=200), "cfg2": dict(n_live=1000, n_delete=125, n_bins=500)}
+
+
+def loud_problem(name):
+    cfg = gwsynth.CONFIGS[name]
+    prob = gwsynth.make_problem(cfg["duration"], cfg["f_min"], cfg["f_max"], psd_scale=1e-49)
+    th = gwsynth.prior_draws(gwsynth.SEEDS["injection"], 1)[0]
+    _, hh = L.overlap(th, prob)
+    th[6] *= math.sqrt(hh) / 24.0
+    prob.data = prob.data + L.strain(th, prob)
+    return prob, th
+
+
+def main(name):
+    st = SETTINGS[name]
+    prob, th0 = loud_problem(name)
+    het = H.setup(prob, th0, st["n_bins"])
+    dd = L.data_inner(prob)
+    loglike = lambda u: H.loglike(S.prior_transform(u), prob, het, L.PHASE_DIST, dd)
+    t0 = time.time()
+    res = S.nested_sampling(loglike, st["n_live"], st["n_delete"], seed=gwsynth.SEEDS["sampler"], dlogz=0.1,
+                            max_shrink=100, max_out=10)
+    out = {"config": name, "n_live": st["n_live"], "n_delete": st["n_delete"], "n_bins": st["n_bins"],
+           "seed": gwsynth.SEEDS["sampler"], "snr": 24.0, "psd_scale": 1e-49, "dlogz": 0.1,
+           "log_z": res["log_z"], "log_z_err": res["log_z_err"], "h": res["h"], "iterations": res["iterations"],
+           "n_evals": res["n_evals"], "cpu_wall_s": time.time() - t0}
+    path = os.path.join(HERE, f"ns_{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "cfg1")
