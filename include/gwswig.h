@@ -244,6 +244,58 @@ gw_status slice_step(gw_ctx* ctx, const gw_slice_args* args, void* stream);
 gw_status gw_prior_transform(gw_ctx* ctx, const double* x, int64_t n, double* theta, void* stream);
 
 /*
+ * Learned prescreen (not part of the paper's method, which uses exact
+ * likelihoods only): a network 11 -> 256 -> 256 -> 256 -> 1 with exact GELU
+ * g(z) = z Phi(z), inputs the standardised unit-cube point of gw_slice_args,
+ * output the standardised log L.  Weights W_l are [fan_in, fan_out] row-major
+ * followed by the bias, layers in order (134,913 FP32 values, gw_mlp_n_params).
+ * Training is mean squared error with Adam (b1 0.9, b2 0.999, eps 1e-8) in
+ * FP32; inference runs the hidden layers with BF16 weights and activations on
+ * the matrix cores, accumulated in FP32.
+ */
+typedef struct gw_mlp gw_mlp;
+
+/* He-normal weights from ``seed``, zero biases; identity scaling. */
+gw_status gw_mlp_create(gw_ctx* ctx, uint64_t seed, gw_mlp** out);
+gw_status gw_mlp_destroy(gw_mlp* mlp);
+gw_status gw_mlp_n_params(int64_t* n);
+/* Input standardisation (x - x_mean) / x_std per coordinate (host [11]) and
+ * output scaling log L = y_mean + y_std * y. */
+gw_status gw_mlp_set_scaling(gw_mlp* mlp, const double* x_mean, const double* x_std, double y_mean, double y_std);
+/* Host FP32 parameter vector in the layout above; set resets Adam's state. */
+gw_status gw_mlp_set_params(gw_mlp* mlp, const float* params);
+gw_status gw_mlp_get_params(gw_mlp* mlp, float* params);
+/* Gradients of the mean squared error on (x device [n, 11], logl device [n])
+ * into host [n_params]; the loss (standardised units) into *loss when not
+ * NULL.  Synchronises the stream. */
+gw_status gw_mlp_grad(gw_mlp* mlp, const double* x, const double* logl, int64_t n, float* grads, float* loss,
+                      void* stream);
+/* One Adam step of learning rate ``lr`` on a batch; *loss (before the step)
+ * when not NULL (then synchronises). */
+gw_status gw_mlp_train_step(gw_mlp* mlp, const double* x, const double* logl, int64_t n, float lr, float* loss,
+                            void* stream);
+/* Predicted log L for x (device [n, 11]) into out (device [n]); use_bf16
+ * selects the matrix-core path, else the FP32 path. */
+gw_status gw_mlp_forward(gw_mlp* mlp, const double* x, int64_t n, double* out, int32_t use_bf16, void* stream);
+
+/*
+ * Prescreened exact evaluation of candidate points x (device [n, 11], unit
+ * cube as for gw_slice_args; phi_c and d_L marginalised).  With use_mlp the
+ * network predicts log L for every candidate (BF16 path); candidates with a
+ * prediction >= logl_star - margin, plus an audit fraction of the others
+ * (Philox4x64-10 word 0 of counter (i, 0, 0, 0), key (seed, 1), below
+ * audit_frac), get the exact likelihood (like, prec); without use_mlp every
+ * candidate does.  logl (device [n]) receives the exact value or -inf for a
+ * candidate not evaluated; flags (device int32 [n]) bit0 evaluated exactly,
+ * bit1 predicted to pass, bit2 audited; pred (device [n] or NULL) the
+ * predictions; *n_exact the number of exact evaluations.  An accept decision
+ * must use logl only.  Synchronises the stream once (to size the exact batch).
+ */
+gw_status gw_prescreen_batch(gw_ctx* ctx, gw_mlp* mlp, const double* x, int64_t n, double logl_star, double margin,
+                             double audit_frac, uint64_t seed, int32_t use_mlp, int32_t like, int32_t prec,
+                             double* logl, double* pred, int32_t* flags, int64_t* n_exact, void* stream);
+
+/*
  * Autotuner: times every candidate launch shape of the full-band (like =
  * GW_FULL) or heterodyned (GW_HET) kernels on the caller's batch ``theta``
  * (device [n, 13]), ``reps`` timed calls each after one warm-up, keeps the

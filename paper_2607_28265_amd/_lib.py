@@ -95,6 +95,21 @@ _SIGS = {
     "gw_graph_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "slice_step": (ctypes.c_int, [_P, ctypes.POINTER(gw_slice_args), _P]),
     "gw_prior_transform": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+    "gw_mlp_create": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "gw_mlp_destroy": (ctypes.c_int, [_P]),
+    "gw_mlp_n_params": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64)]),
+    "gw_mlp_set_scaling": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.c_double, ctypes.c_double]),
+    "gw_mlp_set_params": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float)]),
+    "gw_mlp_get_params": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float)]),
+    "gw_mlp_grad": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_float),
+                                   ctypes.POINTER(ctypes.c_float), _P]),
+    "gw_mlp_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_float, ctypes.POINTER(ctypes.c_float),
+                                         _P]),
+    "gw_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, _P]),
+    "gw_prescreen_batch": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int64), _P]),
     "gw_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
 
@@ -328,3 +343,99 @@ def gw_prior_transform(ctx, x, stream=None):
     check(load().gw_prior_transform(ctx, _tensor_ptr(x), x.shape[0], _tensor_ptr(th), _stream_ptr(stream)),
           "gw_prior_transform")
     return th
+
+
+def _fptr(arr):
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _check_unit(x):
+    import torch
+    if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == 11):
+        raise ValueError("x must be a contiguous CUDA float64 tensor of shape [n, 11]")
+
+
+class Mlp:
+    """Owns one prescreen network on the context's device."""
+
+    def __init__(self, ctx, seed: int = 7):
+        self.ctx = ctx
+        self._m = ctypes.c_void_p()
+        check(load().gw_mlp_create(ctx.handle, seed, ctypes.byref(self._m)), "gw_mlp_create")
+
+    @staticmethod
+    def n_params() -> int:
+        v = ctypes.c_int64()
+        check(load().gw_mlp_n_params(ctypes.byref(v)), "gw_mlp_n_params")
+        return v.value
+
+    def set_scaling(self, x_mean, x_std, y_mean: float, y_std: float):
+        import numpy as np
+        xm = np.ascontiguousarray(x_mean, dtype=np.float64)
+        xs = np.ascontiguousarray(x_std, dtype=np.float64)
+        check(load().gw_mlp_set_scaling(self._m, _dptr(xm), _dptr(xs), float(y_mean), float(y_std)),
+              "gw_mlp_set_scaling")
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        check(load().gw_mlp_set_params(self._m, _fptr(p)), "gw_mlp_set_params")
+
+    def get_params(self):
+        import numpy as np
+        p = np.empty(self.n_params(), dtype=np.float32)
+        check(load().gw_mlp_get_params(self._m, _fptr(p)), "gw_mlp_get_params")
+        return p
+
+    def grad(self, x, logl, stream=None):
+        import numpy as np
+        _check_unit(x)
+        g = np.empty(self.n_params(), dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        check(load().gw_mlp_grad(self._m, _tensor_ptr(x), _tensor_ptr(logl), x.shape[0], _fptr(g), _fptr(loss),
+                                 _stream_ptr(stream)), "gw_mlp_grad")
+        return g, float(loss[0])
+
+    def train_step(self, x, logl, lr: float, want_loss: bool = False, stream=None):
+        import numpy as np
+        _check_unit(x)
+        loss = np.zeros(1, dtype=np.float32)
+        check(load().gw_mlp_train_step(self._m, _tensor_ptr(x), _tensor_ptr(logl), x.shape[0], float(lr),
+                                       _fptr(loss) if want_loss else None, _stream_ptr(stream)), "gw_mlp_train_step")
+        return float(loss[0]) if want_loss else None
+
+    def forward(self, x, bf16: bool = True, out=None, stream=None):
+        import torch
+        _check_unit(x)
+        if out is None:
+            out = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+        check(load().gw_mlp_forward(self._m, _tensor_ptr(x), x.shape[0], _tensor_ptr(out), 1 if bf16 else 0,
+                                    _stream_ptr(stream)), "gw_mlp_forward")
+        return out
+
+    def prescreen(self, x, logl_star: float, margin: float, audit_frac: float = 0.01, seed: int = 7,
+                  use_mlp: bool = True, like: int = GW_FULL, prec: int = GW_PREC_MIXED, stream=None):
+        """(exact log L or -inf, flags, predictions, number of exact evaluations)."""
+        import torch
+        _check_unit(x)
+        n = x.shape[0]
+        logl = torch.empty(n, dtype=torch.float64, device=x.device)
+        pred = torch.empty(n, dtype=torch.float64, device=x.device)
+        flags = torch.empty(n, dtype=torch.int32, device=x.device)
+        ne = ctypes.c_int64()
+        check(load().gw_prescreen_batch(self.ctx.handle, self._m, _tensor_ptr(x), n, float(logl_star), float(margin),
+                                        float(audit_frac), int(seed), 1 if use_mlp else 0, like, prec,
+                                        _tensor_ptr(logl), _tensor_ptr(pred), _tensor_ptr(flags), ctypes.byref(ne),
+                                        _stream_ptr(stream)), "gw_prescreen_batch")
+        return logl, flags, pred, ne.value
+
+    def close(self):
+        if self._m is not None and self._m.value:
+            load().gw_mlp_destroy(self._m)
+        self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
