@@ -84,3 +84,50 @@ def init(seed: int, sizes=SIZES):
     """He-normal weights, zero biases (any initialisation serves the tests)."""
     rng = np.random.default_rng(seed)
     return [(rng.normal(0.0, math.sqrt(2.0 / a), size=(a, b)), np.zeros(b)) for a, b in zip(sizes[:-1], sizes[1:])]
+
+
+def bf16(a):
+    """Round to the nearest bfloat16 (ties to even), returned as float64.
+
+    bfloat16 keeps the sign, the 8 exponent bits and the top 7 fraction bits
+    of an IEEE binary32 value; the value is first rounded to binary32.
+    """
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(params, x):
+    """Forward pass with the quantisation points of the BF16 inference path.
+
+    Reading (not in the paper): the standardised input, the weights of the
+    three hidden layers and the activations entering hidden layers 2 and 3 are
+    rounded to bfloat16; every product and sum is exact (FP64 here); biases,
+    GELU and the 256 -> 1 output layer stay at full precision.
+    """
+    a = bf16(x)
+    n_layers = len(params)
+    for li, (w, b) in enumerate(params):
+        if li == n_layers - 1:
+            return (a @ w + b)[:, 0]
+        z = a @ bf16(w) + b
+        a = gelu(z)
+        if li < n_layers - 2:
+            a = bf16(a)
+    return a[:, 0]
+
+
+def flatten(params):
+    """Parameter list -> one vector: W1, b1, W2, b2, ... (W row-major [in, out])."""
+    return np.concatenate([np.concatenate([w.reshape(-1), b.reshape(-1)]) for w, b in params])
+
+
+def unflatten(vec, sizes=SIZES):
+    vec = np.asarray(vec, dtype=np.float64)
+    out, o = [], 0
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        w = vec[o:o + a * b].reshape(a, b)
+        o += a * b
+        out.append((w, vec[o:o + b].copy()))
+        o += b
+    return out

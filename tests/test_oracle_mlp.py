@@ -67,3 +67,49 @@ def test_learns_a_smooth_function():
         y, cache = M.forward(params, x)
         M.adam_step(params, M.backward(params, cache, y, t), st, lr=3e-3)
     assert M.loss(params, x, t) < 0.05 * l0
+
+
+def test_bf16_rounding_ties_to_even_and_fixed_points():
+    one = 1.0
+    # halfway between 1 and 1 + 2^-7 -> even (1.0); halfway between 1 + 2^-7
+    # and 1 + 2^-6 -> even (1 + 2^-6); just above halfway -> up
+    assert M.bf16(np.array([one + 2.0 ** -8]))[0] == 1.0
+    assert M.bf16(np.array([one + 3 * 2.0 ** -8]))[0] == one + 2.0 ** -6
+    assert M.bf16(np.array([one + 2.0 ** -8 + 2.0 ** -20]))[0] == one + 2.0 ** -7
+    assert M.bf16(np.array([-(one + 2.0 ** -8 + 2.0 ** -20)]))[0] == -(one + 2.0 ** -7)
+    rng = np.random.default_rng(0)
+    v = rng.normal(size=10000) * 10.0 ** rng.uniform(-5, 5, size=10000)
+    q = M.bf16(v)
+    assert np.all(np.abs(q - v) <= 2.0 ** -8 * np.abs(v) * 1.0000001)
+    assert np.array_equal(M.bf16(q), q)  # idempotent
+    # 8 significant bits: q * 2^-e has at most 8 bits
+    m, _ = np.frexp(q)
+    assert np.all((m * 256.0) == np.round(m * 256.0))
+
+
+def test_forward_bf16_equals_forward_on_representable_values():
+    sizes = (11, 16, 16, 16, 1)
+    rng = np.random.default_rng(3)
+    params = [(M.bf16(rng.normal(0, 0.3, (a, b))), rng.normal(0, 0.1, b)) for a, b in zip(sizes[:-1], sizes[1:])]
+    x = M.bf16(rng.normal(size=(7, 11)))
+    y_q = M.forward_bf16(params, x)
+    # with activations also representable the two agree; here only the inputs
+    # and weights are, so compare against a forward that rounds activations
+    a = x
+    for li, (w, b) in enumerate(params[:-1]):
+        a = M.gelu(a @ w + b)
+        if li < 2:
+            a = M.bf16(a)
+    y_ref = (a @ params[-1][0] + params[-1][1])[:, 0]
+    assert np.allclose(y_q, y_ref, rtol=0, atol=1e-13)
+    y = M.forward(params, x)[0]
+    assert np.max(np.abs(y - y_q)) < 0.05 * np.max(np.abs(y)) + 1e-3
+
+
+def test_flatten_roundtrip_layout():
+    p = M.init(0)
+    v = M.flatten(p)
+    assert v.size == 11 * 256 + 256 + 2 * (256 * 256 + 256) + 256 + 1 == 134913
+    q = M.unflatten(v)
+    assert all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(p, q))
+    assert v[0] == p[0][0][0, 0] and v[1] == p[0][0][0, 1] and v[11 * 256] == p[0][1][0]
