@@ -257,7 +257,7 @@ gw_status loglike_batch(gw_ctx* ctx, const double* theta, int64_t n, int32_t lik
     s = launch_full(ctx, ctx->coef, ld, n, prec, tpb, nch, ctx->partial, st);
     prof_end(ctx, slot, st);
   }
-  if (s == GW_OK) s = launch_epilogue(ctx, ctx->partial, nch, ctx->coef, ld, n, marg, logl, st);
+  if (s == GW_OK) s = launch_epilogue(ctx, ctx->partial, nch, ctx->coef, ld, n, marg, prec, logl, st);
   return s;
 }
 

@@ -61,7 +61,7 @@ gw_status launch_prologue(gw_ctx* ctx, const double* theta, int64_t n, int marg,
 gw_status launch_full(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec,
                       int tpb, int n_chunks, double* partial, hipStream_t st);
 gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, const double* coef,
-                          int64_t ld, int64_t n, int marg, double* logl, hipStream_t st);
+                          int64_t ld, int64_t n, int marg, int prec, double* logl, hipStream_t st);
 gw_status launch_template(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, double* h,
                           hipStream_t st);
 void full_launch_shape(const gw_ctx* ctx, int64_t n, int* tpb, int* n_chunks);

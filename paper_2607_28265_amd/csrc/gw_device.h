@@ -6,11 +6,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gw_i0_fit.h"
+
 namespace gw {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr double kTwoPi = 6.283185307179586476925286766559005768;
 constexpr double kInvTwoPi = 0.159154943091895335768883763372514362;
+constexpr double kLog2E = 1.44269504088896340735992468100189214;
 constexpr double kMsunSec = 4.925490947641267e-6;     // G Msun / c^3 (s)
 constexpr double kLightSpeed = 299792458.0;            // m / s
 constexpr double kMpcMetre = 3.085677581491367e22;     // m
@@ -325,61 +328,100 @@ __device__ inline double log_i0(double x, const LogI0Consts& C) {
 // Distance marginal over a grid, evaluated by one wave for one proposal:
 //   LSE_j [ ln w_j - hh1 / (2 d_j^2) + ln I0(|Z1| / d_j) ],
 // with the grid as records (d_j, 1/d_j, 1/(2 d_j^2), ln w_j).  Since
-// ln I0(x) <= x, b_j = ln w_j - hh1 / (2 d_j^2) + |Z1| / d_j bounds each term
-// from above; the exact term at the largest bound is a lower bound on the
-// maximum, so points whose bound is more than 42 below it (together below
-// 1000 e^-42 < 1e-15 of the sum) are skipped.  The rest go through an online
-// log-sum-exp (one exp per point); the 64 per-lane (max, sum) pairs are merged
-// by a fixed shuffle tree, so every lane returns the same, reproducible value.
+// ln I0(x) <= x, b_j = a_j + x_j with a_j = ln w_j - hh1 / (2 d_j^2) and
+// x_j = |Z1| / d_j bounds term j from above, so every term is summed as
+// exp(t_j - B) with B = max_j b_j and never overflows; the largest term is at
+// least B - (x - ln I0(x)) at the maximising point, a gap below 15 for any
+// finite x, so points with b_j < B - 60 (together below 1000 e^-45 of the sum)
+// are skipped.  The 64 per-lane sums are merged by a fixed shuffle tree, so
+// every lane returns the same, reproducible value.
+
+// Wave-wide maximum of the bounds b_j.
+__device__ inline double wave_dist_bound(double z1, double hh1, const double* __restrict__ tab, int n_dist, int lane) {
+  double bmax = -INFINITY;
+  for (int j = lane; j < n_dist; j += 64) {
+    const double* r = tab + 4 * j;
+    bmax = fmax(bmax, fma(-hh1, r[2], r[3]) + z1 * r[1]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) bmax = fmax(bmax, __shfl_xor(bmax, o, 64));
+  return bmax;
+}
+
+__device__ inline double wave_sum(double s) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  return s;
+}
+
+// FP64 form: I0 by its power series in y = x^2/4 below x = 20 (40 terms) and
+// by the asymptotic series e^x / sqrt(2 pi x) sum_k c_k x^-k above (24 terms).
 __device__ inline double wave_dist_lse(double z1, double hh1, const double* __restrict__ tab, int n_dist, int lane,
                                        const LogI0Consts& C) {
+  const double bmax = wave_dist_bound(z1, hh1, tab, n_dist, lane);
+  const double cut = bmax - 60.0;
   const double iz = z1 > 0.0 ? 1.0 / z1 : 0.0;
-  // pass 1: largest upper bound and where it is
-  double bmax = -INFINITY;
-  int jmax = 0;
+  double s = 0.0;
   for (int j = lane; j < n_dist; j += 64) {
     const double* r = tab + 4 * j;
-    const double b = r[3] - hh1 * r[2] + z1 * r[1];
-    if (b > bmax) {
-      bmax = b;
-      jmax = j;
-    }
-  }
+    const double a = fma(-hh1, r[2], r[3]);
+    const double x = z1 * r[1];
+    if (a + x < cut) continue;
+    double v, e;
+    if (x < 20.0) {
+      const double y = 0.25 * x * x;
+      double p = C.ser[39];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double b2 = __shfl_xor(bmax, o, 64);
-    const int j2 = __shfl_xor(jmax, o, 64);
-    if (b2 > bmax || (b2 == bmax && j2 < jmax)) {
-      bmax = b2;
-      jmax = j2;
+      for (int k = 38; k >= 0; --k) p = fma(p, y, C.ser[k]);
+      v = p;
+      e = a - bmax;
+    } else {
+      const double u = r[0] * iz;  // 1 / x
+      double p = C.asy[23];
+#pragma unroll
+      for (int k = 22; k >= 0; --k) p = fma(p, u, C.asy[k]);
+      v = p * sqrt(u * kInvTwoPi);
+      e = (a + x) - bmax;
     }
+    s = fma(exp(e), v, s);
   }
-  const double* rm = tab + 4 * jmax;
-  const double tmax = rm[3] - hh1 * rm[2] + log_i0_xu(z1 * rm[1], rm[0] * iz, C);
-  const double cut = tmax - 42.0;
-  // pass 2: exact terms that can matter
-  double m = -INFINITY, s = 0.0;
+  return bmax + log(wave_sum(s));
+}
+
+// Single-precision form (the mixed path): the exponent arguments a_j, x_j and
+// t_j - B stay FP64; I0 comes from the FP32 polynomial fits of gw_i0_fit.h
+// (relative error below 4e-7 after FP32 rounding) and exp from the hardware
+// 2^x, the per-lane sums are FP32 and the tree FP64.
+__device__ inline double wave_dist_lse_f32(double z1, double hh1, const double* __restrict__ tab, int n_dist,
+                                           int lane) {
+  const double bmax = wave_dist_bound(z1, hh1, tab, n_dist, lane);
+  const double cut = bmax - 60.0;
+  float s = 0.0f;
   for (int j = lane; j < n_dist; j += 64) {
     const double* r = tab + 4 * j;
-    const double b = r[3] - hh1 * r[2] + z1 * r[1];
-    if (b < cut) continue;
-    const double t = r[3] - hh1 * r[2] + log_i0_xu(z1 * r[1], r[0] * iz, C);
-    const bool up = t > m;
-    const double e = exp(up ? m - t : t - m);
-    s = up ? fma(s, e, 1.0) : s + e;
-    m = up ? t : m;
-  }
+    const double a = fma(-hh1, r[2], r[3]);
+    const double x = z1 * r[1];
+    if (a + x < cut) continue;
+    const float xf = (float)x;
+    float p;
+    double e;
+    if (xf <= 8.0f) {
+      const float sv = xf * xf * 0.015625f;
+      p = kI0Small[kI0SmallDeg];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double m2 = __shfl_xor(m, o, 64);
-    const double s2 = __shfl_xor(s, o, 64);
-    const double mm = fmax(m, m2);
-    const double a = (m == -INFINITY) ? 0.0 : s * exp(m - mm);
-    const double b = (m2 == -INFINITY) ? 0.0 : s2 * exp(m2 - mm);
-    m = mm;
-    s = a + b;
+      for (int k = kI0SmallDeg - 1; k >= 0; --k) p = fmaf(p, sv, kI0Small[k]);
+      e = a - bmax;
+    } else {
+      const float t = 8.0f * __builtin_amdgcn_rcpf(xf);
+      float q = kI0Large[kI0LargeDeg];
+#pragma unroll
+      for (int k = kI0LargeDeg - 1; k >= 0; --k) q = fmaf(q, t, kI0Large[k]);
+      p = q * __builtin_amdgcn_rsqf(xf);
+      e = (a + x) - bmax;
+    }
+    s = fmaf(__builtin_amdgcn_exp2f((float)(e * kLog2E)), p, s);
   }
-  return m + log(s);
+  return bmax + log(wave_sum((double)s));
 }
 
 }  // namespace gw

@@ -239,6 +239,7 @@ __global__ void __launch_bounds__(1024) k_epilogue(const double* __restrict__ pa
 }
 
 // Distance marginal: one wave per proposal (see wave_dist_lse).
+template <int PREC>
 __global__ void __launch_bounds__(256) k_dist_marg(const double* __restrict__ zbuf, int64_t n,
                                                    const double* __restrict__ tab, int n_dist, double dd,
                                                    LogI0Consts C, double* __restrict__ logl) {
@@ -251,7 +252,8 @@ __global__ void __launch_bounds__(256) k_dist_marg(const double* __restrict__ zb
     if (lane == 0) logl[p] = -INFINITY;
     return;
   }
-  const double v = wave_dist_lse(z1, hh1, tab, n_dist, lane, C);
+  const double v = PREC == 0 ? wave_dist_lse(z1, hh1, tab, n_dist, lane, C)
+                             : wave_dist_lse_f32(z1, hh1, tab, n_dist, lane);
   if (lane == 0) logl[p] = -0.5 * dd + v;
 }
 
@@ -358,7 +360,7 @@ gw_status launch_full(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, in
 }
 
 gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, const double* coef, int64_t ld,
-                          int64_t n, int marg, double* logl, hipStream_t st) {
+                          int64_t n, int marg, int prec, double* logl, hipStream_t st) {
   if (n == 0) return GW_OK;
   const int64_t blocks = (n + 63) / 64;
   const LogI0Consts C = make_log_i0_consts();
@@ -367,8 +369,12 @@ gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, cons
   gw_status s = check_hip(hipGetLastError(), "epilogue launch");
   if (s != GW_OK || marg != 2) return s;
   const int64_t dblocks = (n + 3) / 4;
-  hipLaunchKernelGGL(k_dist_marg, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_tab,
-                     ctx->n_dist, ctx->dd, C, logl);
+  if (prec == GW_PREC_MIXED)
+    hipLaunchKernelGGL(k_dist_marg<1>, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_tab,
+                       ctx->n_dist, ctx->dd, C, logl);
+  else
+    hipLaunchKernelGGL(k_dist_marg<0>, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_tab,
+                       ctx->n_dist, ctx->dd, C, logl);
   return check_hip(hipGetLastError(), "distance marginal launch");
 }
 

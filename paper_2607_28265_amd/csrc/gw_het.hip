@@ -455,6 +455,7 @@ __global__ void __launch_bounds__(256) k_het_combine(const HetArgs* __restrict__
 }
 
 // Distance marginal over the work list: one wave per row (wave_dist_lse).
+template <int PREC>
 __global__ void __launch_bounds__(256) k_het_dist(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
                                                   const double* __restrict__ dtab, int n_dist, double dd,
                                                   LogI0Consts C) {
@@ -475,7 +476,8 @@ __global__ void __launch_bounds__(256) k_het_dist(const HetArgs* __restrict__ ab
       if (lane == 0) ab->logl[row] = -INFINITY;
       continue;
     }
-    const double v = wave_dist_lse(z1, h1, dtab, n_dist, lane, C);
+    const double v = PREC == 0 ? wave_dist_lse(z1, h1, dtab, n_dist, lane, C)
+                               : wave_dist_lse_f32(z1, h1, dtab, n_dist, lane);
     if (lane == 0) ab->logl[row] = -0.5 * dd + v;
   }
 }
@@ -611,8 +613,12 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
                      C);
   s = check_hip(hipGetLastError(), "heterodyne combine launch");
   if (s != GW_OK || marg != 2) return s;
-  hipLaunchKernelGGL(k_het_dist, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab, ctx->n_dist,
-                     ctx->dd, C);
+  if (prec == GW_PREC_MIXED)
+    hipLaunchKernelGGL(k_het_dist<1>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
+                       ctx->n_dist, ctx->dd, C);
+  else
+    hipLaunchKernelGGL(k_het_dist<0>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
+                       ctx->n_dist, ctx->dd, C);
   return check_hip(hipGetLastError(), "heterodyne distance marginal launch");
 }
 
