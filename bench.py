@@ -34,6 +34,25 @@ METRIC = "logL evals/sec (full-band & heterodyned) vs FP64 plain at |dlogL|<1e-3
 FLOPS_PER_BIN = {"mixed": 60.0, "fp64": 107.0}
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector, dense
 
+# HBM bytes per launch of k_full<3, 1> at 4096 x 259,585, from two rocprofv3 PMC
+# runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
+# plain 256 MiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid
+# only for the kernel sources they were taken on (hash below).
+TRAFFIC = {"sources_sha256": "96ffb3f6a09d4ed95d0dc40218eb22a310c60c82854d722ecbca1ca1c32a0f4d",
+           "read_bytes": 22152.3 * 1.9998 * 1024, "write_bytes": 24576.0 * 1024}
+TRAFFIC_SOURCES = ("paper_2607_28265_amd/csrc/gw_full.hip", "paper_2607_28265_amd/csrc/gw_device.h")
+
+
+def traffic_bytes():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sources_sha256"]:
+        return None
+    return TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
@@ -310,7 +329,7 @@ def main():
                    "batch": n, "n_freq": int(prob.n_freq), "n_det": 3, "marg": "phase+distance",
                    "prec": "mixed"},
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": ach / PEAK_FP64_TFLOPS, "traffic": traffic_bytes(), "traffic_unit": "bytes/launch",
                      "kernel": "k_full<3,1> (mixed)", "kernel_ms": k_mix,
                      "flops_per_launch": FLOPS_PER_BIN["mixed"] * units},
         "fp64_plain": {"value": fp_value, "ms_per_step": dt_fp / fp_steps * 1e3, "kernel_ms": k_fp,
