@@ -317,6 +317,21 @@ gw_status gw_autotune(gw_ctx* ctx, const double* theta, int64_t n, int32_t like,
 gw_status gw_set_full_shape(gw_ctx* ctx, int32_t tpb, int32_t n_chunks);
 
 /*
+ * Reduction used by the mixed-precision full band: 0 automatic (currently the
+ * vector-ALU form, the faster one at a batch of 4096), 1 vector ALUs (one sin/cos per bin, per-detector delay
+ * rotation by recurrence), 2 matrix cores (block moments: the delay rotation
+ * of detectors 1.. is expanded within blocks of B bins in powers of the bin
+ * offset, truncated where the first dropped term is below 1e-9, and the block
+ * moments are an FP32 contraction on v_mfma_f32_16x16x4_f32, folded into FP64
+ * per block).  Kind 2 on a context where the form is unavailable makes
+ * loglike_batch return GW_ENOTSUP.  The FP64 form always uses kind 1.
+ */
+gw_status gw_set_full_kernel(gw_ctx* ctx, int32_t kind);
+/* Block length B of the matrix-core form (0 when the detectors are too far
+ * apart for a block of 8 bins at this frequency spacing). */
+gw_status gw_full_info(const gw_ctx* ctx, int32_t* mom_blk);
+
+/*
  * Kernel timing of the dominant kernel (full-band overlap kernel, or the
  * heterodyned evaluation kernel) for roofline reporting: while enabled, every
  * launch of it is bracketed by HIP events recorded on the launch stream.

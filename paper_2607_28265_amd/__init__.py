@@ -12,6 +12,7 @@ from ._lib import (  # noqa: F401
     GwError, gw_ctx_create, gw_ctx_destroy, gw_data_inner, gw_last_error, gw_set_full_shape, gw_template,
     gw_version, loglike_batch, heterodyne_setup, gw_het_info, loglike_batch_uneven, gw_set_het_shape,
     gw_graph_info, gw_profile_enable, gw_profile_read, slice_step, gw_prior_transform, Mlp,
+    gw_set_full_kernel, gw_full_info,
 )
 
 
@@ -46,6 +47,14 @@ class Context:
 
     def data_inner(self) -> float:
         return gw_data_inner(self._ctx)
+
+    def set_full_kernel(self, kind: int = 0):
+        """0 automatic, 1 vector-ALU reduction, 2 matrix-core reduction (mixed precision)."""
+        gw_set_full_kernel(self._ctx, kind)
+
+    @property
+    def mom_blk(self) -> int:
+        return gw_full_info(self._ctx)
 
     def set_full_shape(self, tpb: int = 0, n_chunks: int = 0):
         gw_set_full_shape(self._ctx, tpb, n_chunks)

@@ -95,6 +95,8 @@ _SIGS = {
     "gw_graph_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "slice_step": (ctypes.c_int, [_P, ctypes.POINTER(gw_slice_args), _P]),
     "gw_prior_transform": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+    "gw_set_full_kernel": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "gw_full_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "gw_mlp_create": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_P)]),
     "gw_mlp_destroy": (ctypes.c_int, [_P]),
     "gw_mlp_n_params": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64)]),
@@ -235,6 +237,16 @@ def gw_template(ctx, theta, n_det: int, n_freq: int, stream=None):
 
 def gw_set_full_shape(ctx, tpb: int, n_chunks: int):
     check(load().gw_set_full_shape(ctx, tpb, n_chunks), "gw_set_full_shape")
+
+
+def gw_set_full_kernel(ctx, kind: int):
+    check(load().gw_set_full_kernel(ctx, kind), "gw_set_full_kernel")
+
+
+def gw_full_info(ctx) -> int:
+    v = ctypes.c_int32()
+    check(load().gw_full_info(ctx, ctypes.byref(v)), "gw_full_info")
+    return v.value
 
 
 def gw_profile_enable(ctx, enable: bool = True):

@@ -199,6 +199,7 @@ gw_status gw_ctx_create(const gw_problem* pr, int32_t device, gw_ctx** out) {
       st = check_hip(hipMemcpy(ctx->dist_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice),
                      "dist copy");
   }
+  if (st == GW_OK) st = build_moment_table(ctx, rec, pr->det_pos);
   if (st != GW_OK) {
     gw_ctx_destroy(ctx);
     return st;
@@ -218,6 +219,7 @@ gw_status gw_ctx_destroy(gw_ctx* ctx) {
   double* bufs[] = {ctx->bins, ctx->dist_tab, ctx->coef, ctx->partial, ctx->zbuf};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
+  if (ctx->wtab) (void)hipFree(ctx->wtab);
   delete ctx;
   return GW_OK;
 }
@@ -305,6 +307,19 @@ gw_status gw_set_full_shape(gw_ctx* ctx, int32_t tpb, int32_t n_chunks) {
   if (n_chunks < 0) return set_error(GW_EINVAL, "gw_set_full_shape: n_chunks < 0");
   ctx->full_tpb = tpb;
   ctx->full_chunks = n_chunks;
+  return GW_OK;
+}
+
+gw_status gw_set_full_kernel(gw_ctx* ctx, int32_t kind) {
+  if (!ctx) return set_error(GW_EINVAL, "gw_set_full_kernel: ctx is NULL");
+  if (kind < 0 || kind > 2) return set_error(GW_EINVAL, "gw_set_full_kernel: kind must be 0, 1 or 2");
+  ctx->full_kernel = kind;
+  return GW_OK;
+}
+
+gw_status gw_full_info(const gw_ctx* ctx, int32_t* mom_blk) {
+  if (!ctx || !mom_blk) return set_error(GW_EINVAL, "gw_full_info: null argument");
+  *mom_blk = ctx->mom_blk;
   return GW_OK;
 }
 

@@ -40,6 +40,12 @@ struct gw_ctx {
   // launch configuration of the full-band kernel (0 = heuristic)
   int full_tpb = 0;
   int full_chunks = 0;
+  int full_kernel = 0;             // 0 auto, 1 vector-ALU reduction, 2 matrix-core reduction (mixed only)
+  // matrix-core form of the mixed reduction: block moments
+  //   W[k][q][plane], q = detector/moment column, planes (w_r, w_i - w_r, w_r + w_i)
+  float* wtab = nullptr;
+  int mom_blk = 0;                 // bins per block (power of two, >= 8); 0 = form unavailable
+  int64_t mom_pad = 0;             // n_freq rounded up to a multiple of mom_blk
   // kernel timing (gw_profile_enable / gw_profile_read)
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
@@ -65,6 +71,10 @@ gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, cons
 gw_status launch_template(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, double* h,
                           hipStream_t st);
 void full_launch_shape(const gw_ctx* ctx, int64_t n, int* tpb, int* n_chunks);
+// Block-moment table of the matrix-core reduction from the per-bin records
+// (host [n_freq][4 + 2 n_det]); leaves the form unavailable (mom_blk = 0) when
+// the detector delays are too long for a block of 8 bins.
+gw_status build_moment_table(gw_ctx* ctx, const std::vector<double>& rec, const double* det_pos);
 
 // Kernel timing: record a start / stop event pair around the dominant kernel.
 // prof_begin returns the pair index or -1 when timing is off or full.

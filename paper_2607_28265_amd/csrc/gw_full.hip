@@ -177,6 +177,196 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
   }
 }
 
+// Matrix-core form of the mixed reduction.
+//
+// Within a block of B bins (k = b0 + j) with centre c = (B - 1) / 2 the delay
+// rotation of detector i is expanded in t_j = (j - c) / (B / 2):
+//   e^{-2 pi i f_k tau_i} = E_ib sum_m (-i phi_i)^m t_j^m / m!,
+//   E_ib = e^{-2 pi i f_centre tau_i},  phi_i = pi df tau_i B,
+// and B is chosen so that |phi_i| keeps the first dropped term below 1e-9.
+// The block sums then become moments M_iq = sum_j W_q[k] g_k of the phasors
+// g_k = e^{-2 pi i Phi_0(f_k)} with proposal-independent weights
+// W_q[k] = t_j^m u_ik: a dense [proposals x bins] x [bins x 16] contraction per
+// block, done by v_mfma_f32_16x16x4_f32 in the three-multiplication complex
+// form (k1 = (g_r + g_i) w_r, k2 = g_r (w_i - w_r), k3 = g_i (w_r + w_i);
+// re = k1 - k3, im = k1 + k2).  Lane l of a wave computes the phasor of
+// proposal (l mod 16) of each of its MT 16-row tiles at bin (l / 16) of each
+// 4-bin step, which is exactly the MFMA A-operand layout.  After each block the
+// 16 x 16 FP32 accumulators go through LDS to one lane per proposal, which
+// folds them into FP64 sums with the FP64 block factor E_ib (advanced by the
+// exact rotation e^{-2 pi i B df tau_i}).  Partials have the layout of k_full.
+constexpr int kMomCols = 16;
+
+template <int ND>
+struct MomCount {
+  static constexpr int value = ND > 1 ? (kMomCols - 1) / (ND - 1) : 0;
+};
+
+template <int ND, int MT>
+__global__ void __launch_bounds__(256) k_full_mfma(const double* __restrict__ coef, int64_t ld, int64_t n,
+                                                   const double* __restrict__ bins, const float* __restrict__ wtab,
+                                                   int64_t k0, double df, int n_freq, int n_pad, int blk,
+                                                   int chunk_len, int n_chunks, TrigConsts T,
+                                                   double* __restrict__ partial) {
+  constexpr int RS = 4 + 2 * ND;
+  constexpr int TPW = 16 * MT;  // proposals per wave
+  constexpr int KM = MomCount<ND>::value;
+  constexpr int RW = 3 * kMomCols + 1;  // LDS row stride (floats), odd against bank conflicts
+  __shared__ float red[4][TPW][RW];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nptile = (int)((n + 4 * TPW - 1) / (4 * TPW));
+  int chunk, ptile;
+  decode_block(blockIdx.x, nptile, n_chunks, &chunk, &ptile);
+  const int64_t pw = (int64_t)ptile * 4 * TPW + (int64_t)wave * TPW;
+
+  PhaseCoef c[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    int64_t pc = pw + mt * 16 + (lane & 15);
+    pc = pc < n ? pc : n - 1;
+    c[mt].a0 = coef[C_A0 * ld + pc];
+    c[mt].a2 = coef[C_A2 * ld + pc];
+    c[mt].a3 = coef[C_A3 * ld + pc];
+    c[mt].a4 = coef[C_A4 * ld + pc];
+    c[mt].a5 = coef[C_A5 * ld + pc];
+    c[mt].a6 = coef[C_A6 * ld + pc];
+    c[mt].a7 = coef[C_A7 * ld + pc];
+    c[mt].a8 = coef[C_A8 * ld + pc];
+    c[mt].a10 = coef[C_A10 * ld + pc];
+    c[mt].a12 = coef[C_A12 * ld + pc];
+    c[mt].b5 = coef[C_B5 * ld + pc];
+    c[mt].b6 = coef[C_B6 * ld + pc];
+  }
+
+  // Folding lane: proposal pf (lanes >= TPW fold nothing).
+  const int64_t pf = pw + lane;
+  const int64_t pfc = pf < n ? (pf >= 0 ? pf : 0) : n - 1;
+  const int kb = chunk * chunk_len;
+  const int ke = kb + chunk_len < n_pad ? kb + chunk_len : n_pad;
+  double zr[ND], zi[ND], er[ND], ei[ND], qr[ND], qi[ND];
+  float phi[ND];
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    zr[i] = 0.0;
+    zi[i] = 0.0;
+    er[i] = 1.0;
+    ei[i] = 0.0;
+    qr[i] = 1.0;
+    qi[i] = 0.0;
+    phi[i] = 0.0f;
+  }
+#pragma unroll
+  for (int i = 1; i < ND; ++i) {
+    const double tau = coef[(C_DT1 + i - 1) * ld + pfc];
+    phi[i] = (float)(kPi * df * tau * (double)blk);
+    double s, co;
+    sincos_cycles(((double)(k0 + kb) + 0.5 * (double)(blk - 1)) * df * tau, T, &s, &co);
+    er[i] = co;
+    ei[i] = -s;
+    sincos_cycles((double)blk * df * tau, T, &s, &co);
+    qr[i] = co;
+    qi[i] = -s;
+  }
+
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  // Operands of one 4-bin step: the phase record of bin (lane / 16) and the
+  // three weight planes of column (lane mod 16).  Two sets alternate so that
+  // the next step's loads are in flight while this step computes.
+  struct Ops {
+    double x, x2, xm5, lnf;
+    float w0, w1, w2;
+  };
+  auto load_ops = [&](int k, Ops& o) {
+    k = k < n_pad ? k : n_pad - 1;
+    const int kr = k < n_freq ? k : n_freq - 1;
+    const double* rec = bins + (int64_t)kr * RS;
+    o.x = rec[0];
+    o.x2 = rec[1];
+    o.xm5 = rec[2];
+    o.lnf = rec[3];
+    const float* w = wtab + ((int64_t)k * kMomCols + (lane & 15)) * 3;
+    o.w0 = w[0];
+    o.w1 = w[1];
+    o.w2 = w[2];
+  };
+  f4v acc[MT][3];
+  auto step = [&](const Ops& o) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const double r = phase_cycles(c[mt], o.x, o.x2, o.xm5, o.lnf);
+      const float tf = (float)(r - rint(r));
+      const float gr = __builtin_amdgcn_cosf(tf);
+      const float gi = -__builtin_amdgcn_sinf(tf);
+      acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr + gi, o.w0, acc[mt][0], 0, 0, 0);
+      acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr, o.w1, acc[mt][1], 0, 0, 0);
+      acc[mt][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi, o.w2, acc[mt][2], 0, 0, 0);
+    }
+  };
+  Ops oa, ob;
+  load_ops(kb + (lane >> 4), oa);
+  for (int b0 = kb; b0 < ke; b0 += blk) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc[mt][t] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    // blk is a multiple of 8: steps pair up; the last prefetch is the next
+    // block's first step.
+    for (int s = 0; s < blk; s += 8) {
+      load_ops(b0 + s + 4 + (lane >> 4), ob);
+      step(oa);
+      load_ops(b0 + s + 8 + (lane >> 4), oa);
+      step(ob);
+    }
+    // D[row = 4 (lane / 16) + v][column = lane mod 16] of each tile
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          red[wave][mt * 16 + 4 * (lane >> 4) + v][t * kMomCols + (lane & 15)] = acc[mt][t][v];
+    __syncthreads();
+    if (lane < TPW) {
+      const float* rw = red[wave][lane];
+      // detector 0: column 0, no rotation
+      zr[0] += (double)(rw[0] - rw[2 * kMomCols]);
+      zi[0] += (double)(rw[0] + rw[kMomCols]);
+#pragma unroll
+      for (int i = 1; i < ND; ++i) {
+        // S_i = sum_m (-i phi)^m / m! * M_i,m by a Horner sweep from the top moment
+        float sr = 0.0f, si = 0.0f;
+#pragma unroll
+        for (int m = KM - 1; m >= 0; --m) {
+          const int q = 1 + (i - 1) * KM + m;
+          const float mr = rw[q] - rw[2 * kMomCols + q];
+          const float mi = rw[q] + rw[kMomCols + q];
+          // (s) * (-i phi / (m + 1)) + M_m
+          const float f = phi[i] / (float)(m + 1);
+          const float nr = si * f + mr;
+          const float ni = -sr * f + mi;
+          sr = nr;
+          si = ni;
+        }
+        const double dr = (double)sr, di = (double)si;
+        zr[i] = fma(er[i], dr, fma(-ei[i], di, zr[i]));
+        zi[i] = fma(er[i], di, fma(ei[i], dr, zi[i]));
+        const double tr = er[i] * qr[i] - ei[i] * qi[i];
+        ei[i] = er[i] * qi[i] + ei[i] * qr[i];
+        er[i] = tr;
+      }
+    }
+    __syncthreads();
+  }
+  if (lane < TPW && pf < n) {
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      partial[((int64_t)chunk * 2 * ND + 2 * i) * n + pf] = zr[i];
+      partial[((int64_t)chunk * 2 * ND + 2 * i + 1) * n + pf] = zi[i];
+    }
+  }
+}
+
 // Combine the chunk partials and apply the marginalisation.  A workgroup
 // takes 64 proposals; its 16 waves sum the chunks c = w (mod 16) in order and
 // wave 0 adds the sixteen sums in order, so the result is reproducible.  For the
@@ -345,11 +535,55 @@ static gw_status launch_full_nd(gw_ctx* ctx, const double* coef, int64_t ld, int
   return check_hip(hipGetLastError(), "full-band kernel launch");
 }
 
+template <int ND, int MT>
+static gw_status launch_mfma_mt(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int n_chunks,
+                                double* partial, hipStream_t st) {
+  const int nf = (int)ctx->geom.n_freq;
+  const int blk = ctx->mom_blk;
+  const int per = (int)((nf + n_chunks - 1) / n_chunks);
+  const int chunk_len = (per + blk - 1) / blk * blk;
+  const TrigConsts T = make_trig_consts();
+  const int64_t nptile = (n + 64 * MT - 1) / (64 * MT);
+  const int64_t blocks = nptile * n_chunks;
+  if (blocks > 0x7fffffff) return set_error(GW_EINVAL, "batch too large for one launch");
+  hipLaunchKernelGGL((k_full_mfma<ND, MT>), dim3((unsigned)blocks), dim3(256), 0, st, coef, ld, n, ctx->bins,
+                     ctx->wtab, ctx->geom.k0, ctx->geom.df, nf, (int)ctx->mom_pad, blk, chunk_len, n_chunks, T,
+                     partial);
+  return check_hip(hipGetLastError(), "full-band matrix-core kernel launch");
+}
+
+template <int ND>
+static gw_status launch_mfma_nd(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int tpb, int n_chunks,
+                                double* partial, hipStream_t st) {
+  switch (tpb) {
+    case 64: return launch_mfma_mt<ND, 1>(ctx, coef, ld, n, n_chunks, partial, st);
+    case 128: return launch_mfma_mt<ND, 2>(ctx, coef, ld, n, n_chunks, partial, st);
+    default: return launch_mfma_mt<ND, 4>(ctx, coef, ld, n, n_chunks, partial, st);
+  }
+}
+
+// Automatic choice: the vector-ALU reduction (measured faster at the
+// benchmark shape); the matrix-core form on request.
+bool use_mfma(const gw_ctx* ctx, int prec) {
+  return prec == GW_PREC_MIXED && ctx->mom_blk > 0 && ctx->full_kernel == 2;
+}
+
 gw_status launch_full(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, int tpb, int n_chunks,
                       double* partial, hipStream_t st) {
   if (n == 0) return GW_OK;
   if (tpb != 64 && tpb != 128 && tpb != 256) return set_error(GW_EINVAL, "tpb must be 64, 128 or 256");
   if (n_chunks < 1) return set_error(GW_EINVAL, "n_chunks must be >= 1");
+  if (ctx->full_kernel == 2 && prec == GW_PREC_MIXED && ctx->mom_blk == 0)
+    return set_error(GW_ENOTSUP, "matrix-core reduction unavailable: detector delays too long for 8-bin blocks");
+  if (use_mfma(ctx, prec)) {
+    switch (ctx->n_det) {
+      case 1: return launch_mfma_nd<1>(ctx, coef, ld, n, tpb, n_chunks, partial, st);
+      case 2: return launch_mfma_nd<2>(ctx, coef, ld, n, tpb, n_chunks, partial, st);
+      case 3: return launch_mfma_nd<3>(ctx, coef, ld, n, tpb, n_chunks, partial, st);
+      case 4: return launch_mfma_nd<4>(ctx, coef, ld, n, tpb, n_chunks, partial, st);
+      default: return set_error(GW_ENOTSUP, "n_det %d not supported", ctx->n_det);
+    }
+  }
   switch (ctx->n_det) {
     case 1: return launch_full_nd<1>(ctx, coef, ld, n, prec, tpb, n_chunks, partial, st);
     case 2: return launch_full_nd<2>(ctx, coef, ld, n, prec, tpb, n_chunks, partial, st);
@@ -357,6 +591,71 @@ gw_status launch_full(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, in
     case 4: return launch_full_nd<4>(ctx, coef, ld, n, prec, tpb, n_chunks, partial, st);
     default: return set_error(GW_ENOTSUP, "n_det %d not supported", ctx->n_det);
   }
+}
+
+// Block length: the largest power of two B in [8, 256] with
+// |phi| = pi df tau_max B small enough that the first dropped term of the
+// rotation series, |phi|^KM / KM!, stays below 1e-9 (tau_max: the largest
+// light travel time between detector 0 and another detector).
+gw_status build_moment_table(gw_ctx* ctx, const std::vector<double>& rec, const double* det_pos) {
+  const int nd = ctx->n_det;
+  const int64_t nf = ctx->geom.n_freq;
+  const double df = ctx->geom.df;
+  const int km = nd > 1 ? (kMomCols - 1) / (nd - 1) : 0;
+  double tau_max = 0.0;
+  for (int i = 1; i < nd; ++i) {
+    double d2 = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      const double d = det_pos[3 * i + j] - det_pos[j];
+      d2 += d * d;
+    }
+    tau_max = fmax(tau_max, sqrt(d2) / kLightSpeed);
+  }
+  double phi_max = 1e300;
+  if (km > 0) {
+    double fact = 1.0;
+    for (int m = 2; m <= km; ++m) fact *= (double)m;
+    phi_max = pow(1e-9 * fact, 1.0 / km);
+  }
+  int blk = 0;
+  for (int b = 256; b >= 8; b >>= 1) {
+    if (kPi * df * tau_max * b <= phi_max) {
+      blk = b;
+      break;
+    }
+  }
+  ctx->mom_blk = 0;
+  ctx->mom_pad = 0;
+  if (blk == 0) return GW_OK;
+  const int rs = 4 + 2 * nd;
+  const int64_t npad = (nf + blk - 1) / blk * blk;
+  std::vector<float> w((size_t)npad * 3 * kMomCols, 0.0f);
+  const double cen = 0.5 * (blk - 1), half = 0.5 * blk;
+  for (int64_t k = 0; k < nf; ++k) {
+    const double t = ((double)(k % blk) - cen) / half;
+    const double* r = &rec[(size_t)k * rs];
+    float* wk = &w[(size_t)k * 3 * kMomCols];
+    auto put = [&](int q, double ur, double ui) {
+      wk[3 * q] = (float)ur;
+      wk[3 * q + 1] = (float)(ui - ur);
+      wk[3 * q + 2] = (float)(ur + ui);
+    };
+    put(0, r[4], r[5]);
+    for (int i = 1; i < nd; ++i) {
+      double tm = 1.0;
+      for (int m = 0; m < km; ++m) {
+        put(1 + (i - 1) * km + m, tm * r[4 + 2 * i], tm * r[5 + 2 * i]);
+        tm *= t;
+      }
+    }
+  }
+  gw_status s = check_hip(hipMalloc((void**)&ctx->wtab, w.size() * sizeof(float)), "moment table alloc");
+  if (s == GW_OK)
+    s = check_hip(hipMemcpy(ctx->wtab, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice), "moment copy");
+  if (s != GW_OK) return s;
+  ctx->mom_blk = blk;
+  ctx->mom_pad = npad;
+  return GW_OK;
 }
 
 gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, const double* coef, int64_t ld,

@@ -45,15 +45,44 @@ def _gpu(ctx, th, marg, prec):
     return out.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+# (precision, full-band reduction kind): FP64; mixed on vector ALUs; mixed on
+# matrix cores (block moments)
+FORMS = [(0, 1), (1, 1), (1, 2)]
+
+
+@pytest.mark.parametrize("prec,kind", FORMS)
 @pytest.mark.parametrize("marg", MARGS)
-def test_cfg1_all_draws(cfg1, marg, prec):
+def test_cfg1_all_draws(cfg1, marg, prec, kind):
     prob, ctx, th, ref = cfg1
-    got = _gpu(ctx, th, marg, prec)
+    ctx.set_full_kernel(kind)
+    try:
+        got = _gpu(ctx, th, marg, prec)
+    finally:
+        ctx.set_full_kernel(0)
     err = np.abs(got - ref[marg])
-    print(f"cfg1 marg={marg} prec={prec}: max|dlogL|={err.max():.3e} p99={np.quantile(err, 0.99):.3e}", flush=True)
+    print(f"cfg1 marg={marg} prec={prec} kind={kind}: max|dlogL|={err.max():.3e} "
+          f"p99={np.quantile(err, 0.99):.3e}", flush=True)
     assert np.all(np.isfinite(got))
     assert err.max() < TOL[prec]
+
+
+def test_matrix_core_form_available(cfg1, cfg2):
+    # 8 s (df = 1/8 Hz) and 128 s (df = 1/128 Hz) segments both admit blocks
+    assert cfg1[1].mom_blk >= 8
+    assert cfg2[1].mom_blk >= cfg1[1].mom_blk
+
+
+@pytest.mark.parametrize("tpb,chunks", [(64, 8), (128, 24), (256, 64), (64, 5)])
+def test_matrix_core_shapes_agree(cfg1, tpb, chunks):
+    prob, ctx, th, ref = cfg1
+    ctx.set_full_kernel(2)
+    ctx.set_full_shape(tpb, chunks)
+    try:
+        got = _gpu(ctx, th[:333], L.PHASE_DIST, 1)
+    finally:
+        ctx.set_full_shape(0, 0)
+        ctx.set_full_kernel(0)
+    assert np.max(np.abs(got - ref[L.PHASE_DIST][:333])) < TOL[1]
 
 
 def test_cfg1_data_inner(cfg1):
@@ -149,11 +178,15 @@ def test_cfg2_full_batch_sampled(cfg2, marg):
     # launch configuration, checked on a sample of rows the oracle can afford.
     prob, ctx, th, idx = cfg2
     ref = oracle_many(th[idx], prob, marg)
-    for prec in (0, 1):
-        got = _gpu(ctx, th, marg, prec)
+    for prec, kind in FORMS:
+        ctx.set_full_kernel(kind)
+        try:
+            got = _gpu(ctx, th, marg, prec)
+        finally:
+            ctx.set_full_kernel(0)
         assert np.all(np.isfinite(got))
         err = np.abs(got[idx] - ref)
-        print(f"cfg2 marg={marg} prec={prec}: max|dlogL|={err.max():.3e}", flush=True)
+        print(f"cfg2 marg={marg} prec={prec} kind={kind}: max|dlogL|={err.max():.3e}", flush=True)
         assert err.max() < TOL[prec]
 
 
@@ -165,9 +198,10 @@ def test_cfg2_loud_precision(gw):
     with gw.Context(prob) as ctx:
         for marg in (L.PLAIN, L.PHASE_DIST):
             ref = oracle_many(th, prob, marg)
-            for prec in (0, 1):
+            for prec, kind in FORMS:
+                ctx.set_full_kernel(kind)
                 got = _gpu(ctx, th, marg, prec)
                 err = np.abs(got - ref)
-                print(f"cfg2 loud marg={marg} prec={prec}: max|dlogL|={err.max():.3e} "
+                print(f"cfg2 loud marg={marg} prec={prec} kind={kind}: max|dlogL|={err.max():.3e} "
                       f"logL range=[{ref.min():.1f}, {ref.max():.1f}]", flush=True)
                 assert err.max() < TOL[prec]
