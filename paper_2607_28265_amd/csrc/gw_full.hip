@@ -193,8 +193,9 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
 // proposal (l mod 16) of each of its MT 16-row tiles at bin (l / 16) of each
 // 4-bin step, which is exactly the MFMA A-operand layout.  After each block the
 // 16 x 16 FP32 accumulators go through LDS to one lane per proposal, which
-// folds them into FP64 sums with the FP64 block factor E_ib (advanced by the
-// exact rotation e^{-2 pi i B df tau_i}).  Partials have the layout of k_full.
+// folds them into FP64 sums with the block factor E_ib (phase reduced in FP64,
+// FP32 hardware sin/cos as for the phasors).  Partials have the layout of
+// k_full.
 constexpr int kMomCols = 16;
 
 template <int ND>
@@ -202,132 +203,160 @@ struct MomCount {
   static constexpr int value = ND > 1 ? (kMomCols - 1) / (ND - 1) : 0;
 };
 
-template <int ND, int MT>
+// 4 x 4 transpose between the 16-lane rows of a wave and four registers:
+// afterwards v[j] in row R holds what v[R] held in row j (same column).
+__device__ inline void transpose_rows4(float v[4]) {
+  auto sw32 = [](float& a, float& b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+  };
+  auto sw16 = [](float& a, float& b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+  };
+  sw32(v[0], v[2]);
+  sw32(v[1], v[3]);
+  sw16(v[0], v[1]);
+  sw16(v[2], v[3]);
+}
+
+// Lane l owns proposal l of its wave for the whole walk, as in k_full; the
+// bin records of a 4-bin step are wave-uniform (scalar loads).  Each lane
+// computes its proposal's phasor at the 4 bins (four independent FP64 phase
+// evaluations); a row/register transpose then gives, for each 16-proposal
+// tile mt, the A operand of v_mfma_f32_16x16x4_f32 (lane r + 16 R: proposal
+// 16 mt + r at bin R), and the B operand is the weight row of bin (lane / 16),
+// column (lane mod 16).
+template <int ND>
 __global__ void __launch_bounds__(256) k_full_mfma(const double* __restrict__ coef, int64_t ld, int64_t n,
                                                    const double* __restrict__ bins, const float* __restrict__ wtab,
                                                    int64_t k0, double df, int n_freq, int n_pad, int blk,
-                                                   int chunk_len, int n_chunks, TrigConsts T,
-                                                   double* __restrict__ partial) {
+                                                   int chunk_len, int n_chunks, double* __restrict__ partial) {
   constexpr int RS = 4 + 2 * ND;
-  constexpr int TPW = 16 * MT;  // proposals per wave
   constexpr int KM = MomCount<ND>::value;
   constexpr int RW = 3 * kMomCols + 1;  // LDS row stride (floats), odd against bank conflicts
-  __shared__ float red[4][TPW][RW];
+  __shared__ float red[4][64][RW];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int nptile = (int)((n + 4 * TPW - 1) / (4 * TPW));
+  const int tpb = blockDim.x;
+  const int nptile = (int)((n + tpb - 1) / tpb);
   int chunk, ptile;
   decode_block(blockIdx.x, nptile, n_chunks, &chunk, &ptile);
-  const int64_t pw = (int64_t)ptile * 4 * TPW + (int64_t)wave * TPW;
+  const int64_t p = (int64_t)ptile * tpb + threadIdx.x;
+  const int64_t pc = p < n ? p : n - 1;
 
-  PhaseCoef c[MT];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    int64_t pc = pw + mt * 16 + (lane & 15);
-    pc = pc < n ? pc : n - 1;
-    c[mt].a0 = coef[C_A0 * ld + pc];
-    c[mt].a2 = coef[C_A2 * ld + pc];
-    c[mt].a3 = coef[C_A3 * ld + pc];
-    c[mt].a4 = coef[C_A4 * ld + pc];
-    c[mt].a5 = coef[C_A5 * ld + pc];
-    c[mt].a6 = coef[C_A6 * ld + pc];
-    c[mt].a7 = coef[C_A7 * ld + pc];
-    c[mt].a8 = coef[C_A8 * ld + pc];
-    c[mt].a10 = coef[C_A10 * ld + pc];
-    c[mt].a12 = coef[C_A12 * ld + pc];
-    c[mt].b5 = coef[C_B5 * ld + pc];
-    c[mt].b6 = coef[C_B6 * ld + pc];
-  }
+  PhaseCoef c;
+  c.a0 = coef[C_A0 * ld + pc];
+  c.a2 = coef[C_A2 * ld + pc];
+  c.a3 = coef[C_A3 * ld + pc];
+  c.a4 = coef[C_A4 * ld + pc];
+  c.a5 = coef[C_A5 * ld + pc];
+  c.a6 = coef[C_A6 * ld + pc];
+  c.a7 = coef[C_A7 * ld + pc];
+  c.a8 = coef[C_A8 * ld + pc];
+  c.a10 = coef[C_A10 * ld + pc];
+  c.a12 = coef[C_A12 * ld + pc];
+  c.b5 = coef[C_B5 * ld + pc];
+  c.b6 = coef[C_B6 * ld + pc];
 
-  // Folding lane: proposal pf (lanes >= TPW fold nothing).
-  const int64_t pf = pw + lane;
-  const int64_t pfc = pf < n ? (pf >= 0 ? pf : 0) : n - 1;
   const int kb = chunk * chunk_len;
   const int ke = kb + chunk_len < n_pad ? kb + chunk_len : n_pad;
-  double zr[ND], zi[ND], er[ND], ei[ND], qr[ND], qi[ND];
+  double zr[ND], zi[ND], tau[ND];
   float phi[ND];
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
     zr[i] = 0.0;
     zi[i] = 0.0;
-    er[i] = 1.0;
-    ei[i] = 0.0;
-    qr[i] = 1.0;
-    qi[i] = 0.0;
+    tau[i] = 0.0;
     phi[i] = 0.0f;
   }
 #pragma unroll
   for (int i = 1; i < ND; ++i) {
-    const double tau = coef[(C_DT1 + i - 1) * ld + pfc];
-    phi[i] = (float)(kPi * df * tau * (double)blk);
-    double s, co;
-    sincos_cycles(((double)(k0 + kb) + 0.5 * (double)(blk - 1)) * df * tau, T, &s, &co);
-    er[i] = co;
-    ei[i] = -s;
-    sincos_cycles((double)blk * df * tau, T, &s, &co);
-    qr[i] = co;
-    qi[i] = -s;
+    tau[i] = coef[(C_DT1 + i - 1) * ld + pc];
+    phi[i] = (float)(kPi * df * tau[i] * (double)blk);
   }
-
   typedef float f4v __attribute__((ext_vector_type(4)));
-  // Operands of one 4-bin step: the phase record of bin (lane / 16) and the
-  // three weight planes of column (lane mod 16).  Two sets alternate so that
-  // the next step's loads are in flight while this step computes.
-  struct Ops {
-    double x, x2, xm5, lnf;
-    float w0, w1, w2;
-  };
-  auto load_ops = [&](int k, Ops& o) {
+  f4v acc[4][3];
+  auto load_w = [&](int k, float* w) {
     k = k < n_pad ? k : n_pad - 1;
-    const int kr = k < n_freq ? k : n_freq - 1;
-    const double* rec = bins + (int64_t)kr * RS;
-    o.x = rec[0];
-    o.x2 = rec[1];
-    o.xm5 = rec[2];
-    o.lnf = rec[3];
-    const float* w = wtab + ((int64_t)k * kMomCols + (lane & 15)) * 3;
-    o.w0 = w[0];
-    o.w1 = w[1];
-    o.w2 = w[2];
+    const float* src = wtab + ((int64_t)k * kMomCols + (lane & 15)) * 3;
+    w[0] = src[0];
+    w[1] = src[1];
+    w[2] = src[2];
   };
-  f4v acc[MT][3];
-  auto step = [&](const Ops& o) {
+  // Phase records of the 4 bins of a step (wave-uniform, scalar loads).
+  struct Recs {
+    double v[4][4];
+  };
+  auto load_recs = [&](int kq, Recs& r) {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const double r = phase_cycles(c[mt], o.x, o.x2, o.xm5, o.lnf);
-      const float tf = (float)(r - rint(r));
-      const float gr = __builtin_amdgcn_cosf(tf);
-      const float gi = -__builtin_amdgcn_sinf(tf);
-      acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr + gi, o.w0, acc[mt][0], 0, 0, 0);
-      acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr, o.w1, acc[mt][1], 0, 0, 0);
-      acc[mt][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi, o.w2, acc[mt][2], 0, 0, 0);
+    for (int b = 0; b < 4; ++b) {
+      const int k = kq + b < n_freq ? kq + b : n_freq - 1;
+      const double* rec = bins + (int64_t)k * RS;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) r.v[b][j] = rec[j];
     }
   };
-  Ops oa, ob;
-  load_ops(kb + (lane >> 4), oa);
+  float wa[3], wb[3];
+  Recs ra, rb;
+  load_w(kb + (lane >> 4), wa);
+  load_recs(kb, ra);
+  // One 4-bin step with records r and weights w (this lane's column).
+  auto step = [&](const Recs& rc, const float* w) {
+    float gr[4], gi[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double r = phase_cycles(c, rc.v[b][0], rc.v[b][1], rc.v[b][2], rc.v[b][3]);
+      const float tf = (float)(r - rint(r));
+      gr[b] = __builtin_amdgcn_cosf(tf);
+      gi[b] = -__builtin_amdgcn_sinf(tf);
+    }
+    transpose_rows4(gr);
+    transpose_rows4(gi);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[mt] + gi[mt], w[0], acc[mt][0], 0, 0, 0);
+      acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[mt], w[1], acc[mt][1], 0, 0, 0);
+      acc[mt][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[mt], w[2], acc[mt][2], 0, 0, 0);
+    }
+  };
   for (int b0 = kb; b0 < ke; b0 += blk) {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
       for (int t = 0; t < 3; ++t) acc[mt][t] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
-    // blk is a multiple of 8: steps pair up; the last prefetch is the next
-    // block's first step.
+    // blk is a multiple of 8: steps pair up, each one's operands loaded
+    // while the other computes.  Scalar loads complete out of order, so the
+    // only usable wait is lgkmcnt(0): it is placed before the other set's loads
+    // are issued, so that it never waits for a load issued just before it.
+    // The last loads run ahead into the next block.
     for (int s = 0; s < blk; s += 8) {
-      load_ops(b0 + s + 4 + (lane >> 4), ob);
-      step(oa);
-      load_ops(b0 + s + 8 + (lane >> 4), oa);
-      step(ob);
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): set a is in
+      load_w(b0 + s + 4 + (lane >> 4), wb);
+      load_recs(b0 + s + 4, rb);
+      __builtin_amdgcn_sched_barrier(0);
+      step(ra, wa);
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // set b is in
+      load_w(b0 + s + 8 + (lane >> 4), wa);
+      load_recs(b0 + s + 8, ra);
+      __builtin_amdgcn_sched_barrier(0);
+      step(rb, wb);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    // D[row = 4 (lane / 16) + v][column = lane mod 16] of each tile
+    // D[row = 4 (lane / 16) + v][column = lane mod 16] of tile mt is proposal
+    // 16 mt + row, moment column q.
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
       for (int t = 0; t < 3; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
           red[wave][mt * 16 + 4 * (lane >> 4) + v][t * kMomCols + (lane & 15)] = acc[mt][t][v];
     __syncthreads();
-    if (lane < TPW) {
+    {
       const float* rw = red[wave][lane];
       // detector 0: column 0, no rotation
       zr[0] += (double)(rw[0] - rw[2 * kMomCols]);
@@ -341,28 +370,29 @@ __global__ void __launch_bounds__(256) k_full_mfma(const double* __restrict__ co
           const int q = 1 + (i - 1) * KM + m;
           const float mr = rw[q] - rw[2 * kMomCols + q];
           const float mi = rw[q] + rw[kMomCols + q];
-          // (s) * (-i phi / (m + 1)) + M_m
-          const float f = phi[i] / (float)(m + 1);
+          const float f = phi[i] / (float)(m + 1);  // s <- s (-i phi / (m + 1)) + M_m
           const float nr = si * f + mr;
           const float ni = -sr * f + mi;
           sr = nr;
           si = ni;
         }
+        // block factor E = exp(-2 pi i f_centre tau_i): FP64 reduction to a
+        // fraction of a cycle, FP32 hardware sin/cos
+        const double cyc = ((double)(k0 + b0) + 0.5 * (double)(blk - 1)) * df * tau[i];
+        const float tf = (float)(cyc - rint(cyc));
+        const double er = (double)__builtin_amdgcn_cosf(tf), ei = -(double)__builtin_amdgcn_sinf(tf);
         const double dr = (double)sr, di = (double)si;
-        zr[i] = fma(er[i], dr, fma(-ei[i], di, zr[i]));
-        zi[i] = fma(er[i], di, fma(ei[i], dr, zi[i]));
-        const double tr = er[i] * qr[i] - ei[i] * qi[i];
-        ei[i] = er[i] * qi[i] + ei[i] * qr[i];
-        er[i] = tr;
+        zr[i] = fma(er, dr, fma(-ei, di, zr[i]));
+        zi[i] = fma(er, di, fma(ei, dr, zi[i]));
       }
     }
     __syncthreads();
   }
-  if (lane < TPW && pf < n) {
+  if (p < n) {
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
-      partial[((int64_t)chunk * 2 * ND + 2 * i) * n + pf] = zr[i];
-      partial[((int64_t)chunk * 2 * ND + 2 * i + 1) * n + pf] = zi[i];
+      partial[((int64_t)chunk * 2 * ND + 2 * i) * n + p] = zr[i];
+      partial[((int64_t)chunk * 2 * ND + 2 * i + 1) * n + p] = zi[i];
     }
   }
 }
@@ -535,31 +565,20 @@ static gw_status launch_full_nd(gw_ctx* ctx, const double* coef, int64_t ld, int
   return check_hip(hipGetLastError(), "full-band kernel launch");
 }
 
-template <int ND, int MT>
-static gw_status launch_mfma_mt(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int n_chunks,
+template <int ND>
+static gw_status launch_mfma_nd(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int tpb, int n_chunks,
                                 double* partial, hipStream_t st) {
   const int nf = (int)ctx->geom.n_freq;
   const int blk = ctx->mom_blk;
   const int per = (int)((nf + n_chunks - 1) / n_chunks);
   const int chunk_len = (per + blk - 1) / blk * blk;
-  const TrigConsts T = make_trig_consts();
-  const int64_t nptile = (n + 64 * MT - 1) / (64 * MT);
+  const int64_t nptile = (n + tpb - 1) / tpb;
   const int64_t blocks = nptile * n_chunks;
   if (blocks > 0x7fffffff) return set_error(GW_EINVAL, "batch too large for one launch");
-  hipLaunchKernelGGL((k_full_mfma<ND, MT>), dim3((unsigned)blocks), dim3(256), 0, st, coef, ld, n, ctx->bins,
-                     ctx->wtab, ctx->geom.k0, ctx->geom.df, nf, (int)ctx->mom_pad, blk, chunk_len, n_chunks, T,
+  hipLaunchKernelGGL((k_full_mfma<ND>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
+                     ctx->wtab, ctx->geom.k0, ctx->geom.df, nf, (int)ctx->mom_pad, blk, chunk_len, n_chunks,
                      partial);
   return check_hip(hipGetLastError(), "full-band matrix-core kernel launch");
-}
-
-template <int ND>
-static gw_status launch_mfma_nd(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int tpb, int n_chunks,
-                                double* partial, hipStream_t st) {
-  switch (tpb) {
-    case 64: return launch_mfma_mt<ND, 1>(ctx, coef, ld, n, n_chunks, partial, st);
-    case 128: return launch_mfma_mt<ND, 2>(ctx, coef, ld, n, n_chunks, partial, st);
-    default: return launch_mfma_mt<ND, 4>(ctx, coef, ld, n, n_chunks, partial, st);
-  }
 }
 
 // Automatic choice: the vector-ALU reduction (measured faster at the
