@@ -181,9 +181,10 @@ gw_status loglike_batch_uneven(gw_ctx* ctx, const double* theta, int64_t n_rows,
                                int32_t n_sub, int32_t like, int32_t marg, int32_t prec, int32_t use_graph,
                                double* logl, void* stream);
 
-/* Launch shape of the heterodyned kernels: waves per workgroup (1, 2, 4) and
- * persistent grid size in workgroups (0 = heuristic). */
-gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid);
+/* Launch shape of the heterodyned kernels: waves per workgroup (1, 2, 4),
+ * persistent grid size in workgroups and number of edge chunks a row's bins
+ * are split into (0 = heuristic for either). */
+gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid, int32_t n_ech);
 
 /* Number of instantiated graphs and the last instantiation time (ms), which
  * plays the role of a one-off compilation cost. */
@@ -299,10 +300,11 @@ gw_status gw_prescreen_batch(gw_ctx* ctx, gw_mlp* mlp, const double* x, int64_t 
  * Autotuner: times every candidate launch shape of the full-band (like =
  * GW_FULL) or heterodyned (GW_HET) kernels on the caller's batch ``theta``
  * (device [n, 13]), ``reps`` timed calls each after one warm-up, keeps the
- * fastest in the context and returns it: best_shape[0..1] = (proposals per
- * workgroup, frequency chunks) for the full band or (waves per workgroup,
- * persistent workgroups) for the heterodyned form; *best_ms the mean time of
- * one call.  Synchronises the stream.  Errors as loglike_batch.
+ * fastest in the context and returns it: best_shape[0..2] = (proposals per
+ * workgroup, frequency chunks, 0) for the full band or (waves per workgroup,
+ * persistent workgroups, edge chunks with 0 = heuristic) for the heterodyned
+ * form; *best_ms the mean time of one call.  Synchronises the stream.  Errors
+ * as loglike_batch.
  */
 gw_status gw_autotune(gw_ctx* ctx, const double* theta, int64_t n, int32_t like, int32_t marg, int32_t prec,
                       int32_t reps, int32_t* best_shape, double* best_ms, void* stream);

@@ -42,8 +42,8 @@ class Context:
                        stream=None):
         return loglike_batch_uneven(self._ctx, theta, subs, GW_HET, marg, prec, use_graph, out, stream)
 
-    def set_het_shape(self, waves_per_block: int = 4, grid: int = 0):
-        gw_set_het_shape(self._ctx, waves_per_block, grid)
+    def set_het_shape(self, waves_per_block: int = 4, grid: int = 0, n_ech: int = 0):
+        gw_set_het_shape(self._ctx, waves_per_block, grid, n_ech)
 
     def data_inner(self) -> float:
         return gw_data_inner(self._ctx)

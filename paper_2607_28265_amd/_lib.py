@@ -88,7 +88,7 @@ _SIGS = {
     "gw_het_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "loglike_batch_uneven": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
-    "gw_set_het_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "gw_set_het_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "gw_autotune": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                    _P]),
@@ -296,8 +296,8 @@ def loglike_batch_uneven(ctx, theta, subs, like: int = GW_HET, marg: int = GW_MA
     return out
 
 
-def gw_set_het_shape(ctx, waves_per_block: int, grid: int):
-    check(load().gw_set_het_shape(ctx, waves_per_block, grid), "gw_set_het_shape")
+def gw_set_het_shape(ctx, waves_per_block: int, grid: int, n_ech: int = 0):
+    check(load().gw_set_het_shape(ctx, waves_per_block, grid, n_ech), "gw_set_het_shape")
 
 
 def gw_graph_info(ctx):
@@ -308,13 +308,13 @@ def gw_graph_info(ctx):
 
 
 def gw_autotune(ctx, theta, like: int, marg: int, prec: int, reps: int = 3, stream=None):
-    """Pick the fastest launch shape on ``theta``; returns ((a, b), ms per call)."""
+    """Pick the fastest launch shape on ``theta``; returns ((a, b, c), ms per call)."""
     _check_theta(theta)
-    shape = (ctypes.c_int32 * 2)()
+    shape = (ctypes.c_int32 * 3)()
     ms = ctypes.c_double()
     check(load().gw_autotune(ctx, _tensor_ptr(theta), theta.shape[0], like, marg, prec, reps, shape,
                              ctypes.byref(ms), _stream_ptr(stream)), "gw_autotune")
-    return (shape[0], shape[1]), ms.value
+    return (shape[0], shape[1], shape[2]), ms.value
 
 
 def slice_step(ctx, x, logl, logl_star: float, block, chol, seed: int = 0, counter: int = 0, uniforms=None,

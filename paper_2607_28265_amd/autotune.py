@@ -50,13 +50,13 @@ def tune(ctx, theta, like: int, marg: int, prec: int, reps: int = 3, use_cache: 
     """
     key = _key(ctx, like, theta.shape[0], marg, prec, extra)
     cache = _load() if use_cache else {}
-    if key in cache:
-        a, b = cache[key]["shape"]
+    if key in cache and len(cache[key].get("shape", ())) == 3:
+        a, b, c = cache[key]["shape"]
         if like == _lib.GW_FULL:
             ctx.set_full_shape(a, b)
         else:
-            ctx.set_het_shape(a, b)
-        return (a, b), None
+            ctx.set_het_shape(a, b, c)
+        return (a, b, c), None
     shape, ms = _lib.gw_autotune(ctx.handle, theta, like, marg, prec, reps)
     if use_cache:
         cache[key] = {"shape": list(shape), "ms": ms}

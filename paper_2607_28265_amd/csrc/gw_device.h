@@ -424,4 +424,111 @@ __device__ inline double wave_dist_lse_f32(double z1, double hh1, const double* 
   return bmax + log(wave_sum((double)s));
 }
 
+// Sliced forms of the distance marginal: one proposal per lane, and the
+// waves of a workgroup share the same 64 proposals, each wave taking a slice
+// [j0, j1) of the grid.  All lanes of a wave walk their slice together, so
+// each grid record is a wave-uniform (scalar) load shared by 64 proposals
+// instead of a separate vector load per lane.  The caller combines the slice
+// maxima (order-independent) and then the slice sums in a fixed order; the
+// bound, cut and term arithmetic are those of the wave forms above.
+__device__ inline double slice_dist_bound(double z1, double hh1, const double* __restrict__ tab, int j0, int j1) {
+  double bmax = -INFINITY;
+  for (int j = j0; j < j1; ++j) {
+    const double* r = tab + 4 * j;
+    bmax = fmax(bmax, fma(-hh1, r[2], r[3]) + z1 * r[1]);
+  }
+  return bmax;
+}
+
+// sum_j exp(t_j - bmax) over the slice (FP64 form).
+__device__ inline double slice_dist_sum(double z1, double hh1, double bmax, const double* __restrict__ tab, int j0,
+                                        int j1, const LogI0Consts& C) {
+  const double cut = bmax - 60.0;
+  const double iz = z1 > 0.0 ? 1.0 / z1 : 0.0;
+  double s = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    const double* r = tab + 4 * j;
+    const double a = fma(-hh1, r[2], r[3]);
+    const double x = z1 * r[1];
+    if (a + x < cut) continue;
+    double v, e;
+    if (x < 20.0) {
+      const double y = 0.25 * x * x;
+      double p = C.ser[39];
+#pragma unroll
+      for (int k = 38; k >= 0; --k) p = fma(p, y, C.ser[k]);
+      v = p;
+      e = a - bmax;
+    } else {
+      const double u = r[0] * iz;  // 1 / x
+      double p = C.asy[23];
+#pragma unroll
+      for (int k = 22; k >= 0; --k) p = fma(p, u, C.asy[k]);
+      v = p * sqrt(u * kInvTwoPi);
+      e = (a + x) - bmax;
+    }
+    s = fma(exp(e), v, s);
+  }
+  return s;
+}
+
+// Same sum, single-precision form.
+__device__ inline double slice_dist_sum_f32(double z1, double hh1, double bmax, const double* __restrict__ tab,
+                                            int j0, int j1) {
+  const double cut = bmax - 60.0;
+  float s = 0.0f;
+  for (int j = j0; j < j1; ++j) {
+    const double* r = tab + 4 * j;
+    const double a = fma(-hh1, r[2], r[3]);
+    const double x = z1 * r[1];
+    if (a + x < cut) continue;
+    const float xf = (float)x;
+    float p;
+    double e;
+    if (xf <= 8.0f) {
+      const float sv = xf * xf * 0.015625f;
+      p = kI0Small[kI0SmallDeg];
+#pragma unroll
+      for (int k = kI0SmallDeg - 1; k >= 0; --k) p = fmaf(p, sv, kI0Small[k]);
+      e = a - bmax;
+    } else {
+      const float t = 8.0f * __builtin_amdgcn_rcpf(xf);
+      float q = kI0Large[kI0LargeDeg];
+#pragma unroll
+      for (int k = kI0LargeDeg - 1; k >= 0; --k) q = fmaf(q, t, kI0Large[k]);
+      p = q * __builtin_amdgcn_rsqf(xf);
+      e = (a + x) - bmax;
+    }
+    s = fmaf(__builtin_amdgcn_exp2f((float)(e * kLog2E)), p, s);
+  }
+  return (double)s;
+}
+
+// Workgroup-level driver: waves w = 0 .. nw-1 of the block share 64
+// proposals (lane = proposal); red is LDS scratch of nw x 64 doubles.
+// Returns the log-sum-exp in every lane of wave 0 (other waves return 0).
+template <int PREC>
+__device__ inline double block_dist_lse(double z1, double hh1, const double* __restrict__ tab, int n_dist, int nw,
+                                        double* red, const LogI0Consts& C) {
+  const int lane = threadIdx.x & 63;
+  // wave index, made visibly wave-uniform so that the grid loads are scalar
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int per = (n_dist + nw - 1) / nw;
+  const int j0 = w * per < n_dist ? w * per : n_dist;
+  const int j1 = j0 + per < n_dist ? j0 + per : n_dist;
+  red[w * 64 + lane] = slice_dist_bound(z1, hh1, tab, j0, j1);
+  __syncthreads();
+  double bmax = -INFINITY;
+  for (int v = 0; v < nw; ++v) bmax = fmax(bmax, red[v * 64 + lane]);
+  __syncthreads();
+  red[w * 64 + lane] = PREC == 0 ? slice_dist_sum(z1, hh1, bmax, tab, j0, j1, C)
+                                 : slice_dist_sum_f32(z1, hh1, bmax, tab, j0, j1);
+  __syncthreads();
+  double s = 0.0;
+  if (w == 0)
+    for (int v = 0; v < nw; ++v) s += red[v * 64 + lane];
+  __syncthreads();
+  return w == 0 ? bmax + log(s) : 0.0;
+}
+
 }  // namespace gw

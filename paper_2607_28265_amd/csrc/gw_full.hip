@@ -458,11 +458,13 @@ __global__ void __launch_bounds__(1024) k_epilogue(const double* __restrict__ pa
   logl[p] = out;
 }
 
-// Distance marginal: one wave per proposal (see wave_dist_lse).
+// Distance marginal: one lane per proposal, waves splitting the grid (see block_dist_lse).
+// Small batches: one wave per proposal (see wave_dist_lse), which keeps many
+// waves busy when there are few proposals.
 template <int PREC>
-__global__ void __launch_bounds__(256) k_dist_marg(const double* __restrict__ zbuf, int64_t n,
-                                                   const double* __restrict__ tab, int n_dist, double dd,
-                                                   LogI0Consts C, double* __restrict__ logl) {
+__global__ void __launch_bounds__(256) k_dist_marg_w(const double* __restrict__ zbuf, int64_t n,
+                                                     const double* __restrict__ tab, int n_dist, double dd,
+                                                     LogI0Consts C, double* __restrict__ logl) {
   const int lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (p >= n) return;
@@ -475,6 +477,26 @@ __global__ void __launch_bounds__(256) k_dist_marg(const double* __restrict__ zb
   const double v = PREC == 0 ? wave_dist_lse(z1, hh1, tab, n_dist, lane, C)
                              : wave_dist_lse_f32(z1, hh1, tab, n_dist, lane);
   if (lane == 0) logl[p] = -0.5 * dd + v;
+}
+
+// Large batches: a workgroup of kDistWaves waves per 64 proposals, the grid
+// split between the waves (see block_dist_lse).
+constexpr int kDistWaves = 16;
+constexpr int64_t kDistSliced = 8192;  // batches from this size use the sliced form
+
+template <int PREC>
+__global__ void __launch_bounds__(1024) k_dist_marg(const double* __restrict__ zbuf, int64_t n,
+                                                    const double* __restrict__ tab, int n_dist, double dd,
+                                                    LogI0Consts C, double* __restrict__ logl) {
+  __shared__ double red[kDistWaves * 64];
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t pc = p < n ? p : n - 1;
+  const double z1 = zbuf[pc];
+  const double hh1 = zbuf[n + pc];
+  // invalid rows (z1 < 0) still take part in the block's barriers
+  const double v = block_dist_lse<PREC>(z1 < 0.0 ? 0.0 : z1, hh1, tab, n_dist, kDistWaves, red, C);
+  if ((threadIdx.x >> 6) == 0 && p < n) logl[p] = z1 < 0.0 ? -INFINITY : -0.5 * dd + v;
 }
 
 // Materialise h_i(f_k) = A P_i f^(-7/6) exp(-2 pi i Phi_i(f)) for injections.
@@ -686,13 +708,23 @@ gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, cons
                      n, ctx->dd, marg, C, logl, ctx->zbuf);
   gw_status s = check_hip(hipGetLastError(), "epilogue launch");
   if (s != GW_OK || marg != 2) return s;
-  const int64_t dblocks = (n + 3) / 4;
-  if (prec == GW_PREC_MIXED)
-    hipLaunchKernelGGL(k_dist_marg<1>, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_tab,
-                       ctx->n_dist, ctx->dd, C, logl);
-  else
-    hipLaunchKernelGGL(k_dist_marg<0>, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_tab,
-                       ctx->n_dist, ctx->dd, C, logl);
+  if (n >= kDistSliced) {
+    const int64_t dblocks = (n + 63) / 64;
+    if (prec == GW_PREC_MIXED)
+      hipLaunchKernelGGL(k_dist_marg<1>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, ctx->zbuf, n,
+                         ctx->dist_tab, ctx->n_dist, ctx->dd, C, logl);
+    else
+      hipLaunchKernelGGL(k_dist_marg<0>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, ctx->zbuf, n,
+                         ctx->dist_tab, ctx->n_dist, ctx->dd, C, logl);
+  } else {
+    const int64_t dblocks = (n + 3) / 4;
+    if (prec == GW_PREC_MIXED)
+      hipLaunchKernelGGL(k_dist_marg_w<1>, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_tab,
+                         ctx->n_dist, ctx->dd, C, logl);
+    else
+      hipLaunchKernelGGL(k_dist_marg_w<0>, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_tab,
+                         ctx->n_dist, ctx->dd, C, logl);
+  }
   return check_hip(hipGetLastError(), "distance marginal launch");
 }
 

@@ -50,6 +50,7 @@ struct gw_het_state {
   std::vector<double> theta0;
   double ap0_inv_re[gw::kMaxDet] = {0};
   double ap0_inv_im[gw::kMaxDet] = {0};
+  double hh0[gw::kMaxDet] = {0};  // sum_b B0_b / 2 per detector (unit-phasor <h|h> constant)
   // work-list machinery
   HetArgs* args = nullptr;       // device
   int64_t* tile_pre = nullptr;   // device [max_sub + 1]
@@ -58,12 +59,14 @@ struct gw_het_state {
   // launch shape of the evaluation kernel
   int wpb = 4;                   // waves per workgroup
   int grid = 0;                  // workgroups (0 = heuristic)
+  int ech = 0;                   // edge chunks (0 = heuristic)
+  int64_t n_rows_last = 0;       // rows of the batch being enqueued (selects the distance form)
 };
 
 struct GraphKey {
-  int marg, prec, wpb, grid, n_ech;
+  int marg, prec, wpb, grid, n_ech, sliced;
   bool operator<(const GraphKey& o) const {
-    return std::tie(marg, prec, wpb, grid, n_ech) < std::tie(o.marg, o.prec, o.wpb, o.grid, o.n_ech);
+    return std::tie(marg, prec, wpb, grid, n_ech, sliced) < std::tie(o.marg, o.prec, o.wpb, o.grid, o.n_ech, o.sliced);
   }
 };
 
@@ -82,6 +85,12 @@ constexpr int kMaxSub = 1 << 16;
 __host__ __device__ constexpr int het_rs(int nd) { return 6 + 7 * nd; }
 enum HetRec { H_X = 0, H_X2 = 1, H_XM5 = 2, H_LNF = 3, H_F = 4, H_PHI0 = 5 };  // then f dtau0_i (i >= 1)
 __host__ __device__ constexpr int het_bin_off(int nd) { return 5 + nd; }      // inv width, then 6 per det
+// The 6 per-detector slots of edge e first receive the summary data of bin e
+// (between edges e-1 and e): A0 (re, im), A1 (re, im), B0, 2 B1.  The set-up
+// then rewrites them as per-edge weights of the summed-by-parts bin sums
+// (see k_het): C_e = R_e + L_{e+1} (re, im), R_e (re, im), B0_e / 2, 0, with
+// R_e = A0_e / 2 + A1_e / w_e and L_e = A0_e / 2 - A1_e / w_e (w_e the width
+// of bin e; R_0 = L_{n+1} = 0, B0_0 = 0).
 
 // ---------------------------------------------------------------------------
 // Set-up kernels
@@ -276,6 +285,7 @@ __global__ void __launch_bounds__(256) k_het_prologue(const HetArgs* __restrict_
 struct HetConst {
   double ap0_inv_re[kMaxDet];
   double ap0_inv_im[kMaxDet];
+  double hh0[kMaxDet];
   double dd;
 };
 
@@ -341,7 +351,7 @@ __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, con
       for (int i = 1; i < ND; ++i) dt[i] = cf[(C_DT1 + i - 1) * ld];
     }
 
-    // bins [b0, b1) of this chunk use edges b0 .. b1
+    // bins (b0, b1] of this chunk (bin e lies between edges e - 1 and e) use edges b0 .. b1
     const int b0 = ech * per < n_bins ? ech * per : n_bins;
     const int b1 = b0 + per < n_bins ? b0 + per : n_bins;
     double zr[ND], zi[ND], hh[ND], pr[ND], pi[ND];
@@ -362,29 +372,22 @@ __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, con
         const double* r = srec + el * RS;
         const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
         const double f = r[H_F];
-        const double inv = r[BO];
+        // weight of this edge in the chunk's bins (b0, b1]: C inside, the
+        // left-edge part C - R at b0, the right-edge part R at b1 (uniform)
+        const int side = e == b0 ? 1 : (e == b1 ? 2 : 0);
 #pragma unroll
         for (int i = 0; i < ND; ++i) {
           const double di = i == 0 ? d0 : fma(f, dt[i], d0) - r[H_PHI0 + i];
           double gr, gi;
           het_phasor<PREC>(di, T, &gr, &gi);
-          if (e > b0) {
-            const double* bd = r + BO + 1 + 6 * i;
-            const double r0r = 0.5 * (gr + pr[i]), r0i = 0.5 * (gi + pi[i]);
-            const double r1r = (gr - pr[i]) * inv, r1i = (gi - pi[i]) * inv;
-            zr[i] = fma(bd[0], r0r, zr[i]);
-            zr[i] = fma(-bd[1], r0i, zr[i]);
-            zr[i] = fma(bd[2], r1r, zr[i]);
-            zr[i] = fma(-bd[3], r1i, zr[i]);
-            zi[i] = fma(bd[0], r0i, zi[i]);
-            zi[i] = fma(bd[1], r0r, zi[i]);
-            zi[i] = fma(bd[2], r1i, zi[i]);
-            zi[i] = fma(bd[3], r1r, zi[i]);
-            const double m = fma(r0r, r0r, r0i * r0i);
-            const double x = fma(r0r, r1r, r0i * r1i);
-            hh[i] = fma(bd[4], m, hh[i]);
-            hh[i] = fma(bd[5], x, hh[i]);
-          }
+          const double* w = r + BO + 1 + 6 * i;
+          const double kr = side == 0 ? w[0] : (side == 1 ? w[0] - w[2] : w[2]);
+          const double ki = side == 0 ? w[1] : (side == 1 ? w[1] - w[3] : w[3]);
+          zr[i] = fma(kr, gr, fma(-ki, gi, zr[i]));
+          zi[i] = fma(kr, gi, fma(ki, gr, zi[i]));
+          // |r0|^2 = (1 + Re(g_e conj g_{e-1})) / 2 for unit phasors; the
+          // constant half is added once per row by the combine kernel
+          if (e > b0) hh[i] = fma(w[4], fma(gr, pr[i], gi * pi[i]), hh[i]);
           pr[i] = gr;
           pi[i] = gi;
         }
@@ -437,7 +440,7 @@ __global__ void __launch_bounds__(256) k_het_combine(const HetArgs* __restrict__
       plain += wr;
       Zr += wr;
       Zi += wi;
-      hht += (qr * qr + qi * qi) * hh;
+      hht += (qr * qr + qi * qi) * (hc.hh0[i] + hh);
     }
     const bool valid = cf[C_VALID * ld] != 0.0;
     const double zabs = sqrt(Zr * Zr + Zi * Zi);
@@ -454,11 +457,12 @@ __global__ void __launch_bounds__(256) k_het_combine(const HetArgs* __restrict__
   }
 }
 
-// Distance marginal over the work list: one wave per row (wave_dist_lse).
+// Distance marginal over the work list, small batches: one wave per row
+// (wave_dist_lse), which keeps many waves busy when there are few rows.
 template <int PREC>
-__global__ void __launch_bounds__(256) k_het_dist(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
-                                                  const double* __restrict__ dtab, int n_dist, double dd,
-                                                  LogI0Consts C) {
+__global__ void __launch_bounds__(256) k_het_dist_w(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
+                                                    const double* __restrict__ dtab, int n_dist, double dd,
+                                                    LogI0Consts C) {
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
@@ -479,6 +483,33 @@ __global__ void __launch_bounds__(256) k_het_dist(const HetArgs* __restrict__ ab
     const double v = PREC == 0 ? wave_dist_lse(z1, h1, dtab, n_dist, lane, C)
                                : wave_dist_lse_f32(z1, h1, dtab, n_dist, lane);
     if (lane == 0) ab->logl[row] = -0.5 * dd + v;
+  }
+}
+
+// Distance marginal over the work list, large batches: a workgroup per 64-row
+// tile, lane = row, waves splitting the grid (block_dist_lse), so that grid
+// records are scalar loads shared by 64 rows.
+constexpr int64_t kDistRowsPerLane = 8192;  // batches from this size use the sliced form
+template <int PREC>
+__global__ void __launch_bounds__(256) k_het_dist(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
+                                                  const double* __restrict__ dtab, int n_dist, double dd,
+                                                  LogI0Consts C) {
+  __shared__ double red[4 * 64];
+  const int lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  const int64_t tiles = pre[ab->n_sub];
+  const int64_t ld = ab->ld;
+  // one 64-row tile per workgroup iteration (uniform across the block)
+  for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    int64_t row0 = 0, row_end = 0;
+    const bool has = tile_rows(ab, pre, t, &row0, &row_end);
+    const int64_t row = row0 + lane;
+    const bool active = has && row < row_end;
+    const int64_t rr = active ? row : (has ? row0 : 0);
+    const double z1 = has ? ab->zbuf[rr] : 0.0;
+    const double h1 = has ? ab->zbuf[ld + rr] : 0.0;
+    const double v = block_dist_lse<PREC>(z1 < 0.0 ? 0.0 : z1, h1, dtab, n_dist, nw, red, C);
+    if ((threadIdx.x >> 6) == 0 && active) ab->logl[row] = z1 < 0.0 ? -INFINITY : -0.5 * dd + v;
   }
 }
 
@@ -557,10 +588,17 @@ static std::vector<int64_t> make_edges(const Geom& g, int n_bins, int rule) {
 
 // Edge chunks per tile: enough (tile, chunk) items to give every SIMD a few
 // waves at this batch size, at least 16 bins per chunk, at most 32 chunks.
+// Default persistent grid of the evaluation kernel, in waves (measured best
+// of 2048 .. 16384 at 65,536 rows and 500 bins).
+constexpr int64_t kHetWaves = 16384;
+
 static int het_ech(const gw_ctx* ctx, int64_t n_rows) {
+  const int64_t nb = ctx->het->n_bins;
+  if (ctx->het->ech > 0) return (int)std::min<int64_t>(ctx->het->ech, nb);
+  // about one (tile, edge chunk) item per wave of the default grid
   const int64_t tiles = (n_rows + 63) / 64;
-  int64_t e = (4096 + tiles - 1) / tiles;
-  const int64_t emax = std::max<int64_t>(1, std::min<int64_t>(32, ctx->het->n_bins / 16));
+  int64_t e = (kHetWaves + tiles - 1) / tiles;
+  const int64_t emax = std::max<int64_t>(1, std::min<int64_t>(32, nb / 16));
   e = std::max<int64_t>(1, std::min(e, emax));
   return (int)e;
 }
@@ -571,7 +609,7 @@ static gw_status launch_het_nd(gw_ctx* ctx, int marg, int prec, int n_ech, hipSt
   const TrigConsts T = make_trig_consts();
   const int tpb = 64 * h->wpb;
   int grid = h->grid;
-  if (grid <= 0) grid = 256 * 8 / h->wpb;  // 8 waves per CU
+  if (grid <= 0) grid = kHetWaves / h->wpb;  // 64 waves per CU, several rounds of the resident 20
   const int slot = prof_begin(ctx, st);
   if (prec == GW_PREC_FP64)
     hipLaunchKernelGGL((k_het<ND, 0>), dim3(grid), dim3(tpb), 0, st, h->args, h->tile_pre, h->rec, h->n_bins, n_ech,
@@ -606,6 +644,7 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
   for (int i = 0; i < kMaxDet; ++i) {
     hc.ap0_inv_re[i] = h->ap0_inv_re[i];
     hc.ap0_inv_im[i] = h->ap0_inv_im[i];
+    hc.hh0[i] = h->hh0[i];
   }
   hc.dd = ctx->dd;
   const LogI0Consts C = make_log_i0_consts();
@@ -613,11 +652,18 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
                      C);
   s = check_hip(hipGetLastError(), "heterodyne combine launch");
   if (s != GW_OK || marg != 2) return s;
-  if (prec == GW_PREC_MIXED)
-    hipLaunchKernelGGL(k_het_dist<1>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
+  const bool sliced = h->n_rows_last >= kDistRowsPerLane;
+  if (sliced && prec == GW_PREC_MIXED)
+    hipLaunchKernelGGL(k_het_dist<1>, dim3(256 * 16), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
+                       ctx->n_dist, ctx->dd, C);
+  else if (sliced)
+    hipLaunchKernelGGL(k_het_dist<0>, dim3(256 * 16), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
+                       ctx->n_dist, ctx->dd, C);
+  else if (prec == GW_PREC_MIXED)
+    hipLaunchKernelGGL(k_het_dist_w<1>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
                        ctx->n_dist, ctx->dd, C);
   else
-    hipLaunchKernelGGL(k_het_dist<0>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
+    hipLaunchKernelGGL(k_het_dist_w<0>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
                        ctx->n_dist, ctx->dd, C);
   return check_hip(hipGetLastError(), "heterodyne distance marginal launch");
 }
@@ -626,6 +672,7 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
 static gw_status het_prepare(gw_ctx* ctx, const double* theta, const int64_t* subs, int32_t n_sub, int64_t n_rows,
                              double* logl, bool single, int* n_ech, hipStream_t st) {
   gw_het_state* h = ctx->het;
+  h->n_rows_last = n_rows;
   *n_ech = het_ech(ctx, n_rows);
   gw_status s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n_rows, "coefficient workspace");
   if (s == GW_OK) s = ensure_buffer(&ctx->zbuf, &ctx->zbuf_cap, 2 * n_rows, "marginal workspace");
@@ -740,6 +787,50 @@ gw_status heterodyne_setup(gw_ctx* ctx, const double* theta0, int32_t n_bins, in
     h->ap0_inv_re[i] = ar / m;
     h->ap0_inv_im[i] = -ai / m;
   }
+  // Bin summaries -> per-edge weights of the summed-by-parts sums.
+  {
+    const int rs = h->rs, bo = het_bin_off(nd), nb = ne - 1;
+    std::vector<double> rh((size_t)ne * rs);
+    s = check_hip(hipMemcpy(rh.data(), h->rec, rh.size() * sizeof(double), hipMemcpyDeviceToHost), "copy");
+    if (s != GW_OK) {
+      free_state(h);
+      return s;
+    }
+    std::vector<double> out(rh);
+    for (int i = 0; i < nd; ++i) {
+      double hh0 = 0.0;
+      for (int e = 0; e < ne; ++e) {
+        double rr = 0.0, ri = 0.0, lr = 0.0, li = 0.0, b0h = 0.0;
+        if (e >= 1) {  // bin e: right edge e
+          const double* sb = &rh[(size_t)e * rs + bo + 1 + 6 * i];
+          const double inv = rh[(size_t)e * rs + bo];
+          rr = 0.5 * sb[0] + sb[2] * inv;
+          ri = 0.5 * sb[1] + sb[3] * inv;
+          b0h = 0.5 * sb[4];
+          hh0 += b0h;
+        }
+        if (e + 1 <= nb) {  // bin e + 1: left edge e
+          const double* sb = &rh[(size_t)(e + 1) * rs + bo + 1 + 6 * i];
+          const double inv = rh[(size_t)(e + 1) * rs + bo];
+          lr = 0.5 * sb[0] - sb[2] * inv;
+          li = 0.5 * sb[1] - sb[3] * inv;
+        }
+        double* o = &out[(size_t)e * rs + bo + 1 + 6 * i];
+        o[0] = rr + lr;
+        o[1] = ri + li;
+        o[2] = rr;
+        o[3] = ri;
+        o[4] = b0h;
+        o[5] = 0.0;
+      }
+      h->hh0[i] = hh0;
+    }
+    s = check_hip(hipMemcpy(h->rec, out.data(), out.size() * sizeof(double), hipMemcpyHostToDevice), "copy");
+    if (s != GW_OK) {
+      free_state(h);
+      return s;
+    }
+  }
   ctx->het = h;
   if (edges_out)
     for (int e = 0; e < ne; ++e) edges_out[e] = h->f_edges[e];
@@ -781,7 +872,7 @@ gw_status loglike_batch_uneven(gw_ctx* ctx, const double* theta, int64_t n_rows,
     if (!ctx->graphs) return set_error(GW_ENOMEM, "graph cache");
   }
   gw_graph_cache* gc = ctx->graphs;
-  const GraphKey key{marg, prec, h->wpb, h->grid, n_ech};
+  const GraphKey key{marg, prec, h->wpb, h->grid, n_ech, h->n_rows_last >= kDistRowsPerLane ? 1 : 0};
   auto it = gc->exec.find(key);
   if (it == gc->exec.end()) {
     if (!gc->cap_stream) {
@@ -814,14 +905,16 @@ gw_status loglike_batch_uneven(gw_ctx* ctx, const double* theta, int64_t n_rows,
   return check_hip(hipGraphLaunch(it->second, st), "graph launch");
 }
 
-gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid) {
+gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid, int32_t n_ech) {
   if (!ctx) return set_error(GW_EINVAL, "gw_set_het_shape: ctx is NULL");
   if (!ctx->het) return set_error(GW_ESTATE, "gw_set_het_shape: heterodyne_setup has not been called");
   if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
     return set_error(GW_EINVAL, "gw_set_het_shape: waves_per_block must be 1, 2 or 4");
   if (grid < 0 || grid > (1 << 20)) return set_error(GW_EINVAL, "gw_set_het_shape: grid out of range");
+  if (n_ech < 0 || n_ech > 256) return set_error(GW_EINVAL, "gw_set_het_shape: n_ech must be 0 .. 256");
   ctx->het->wpb = waves_per_block;
   ctx->het->grid = grid;
+  ctx->het->ech = n_ech;
   return GW_OK;
 }
 
@@ -836,7 +929,7 @@ gw_status gw_graph_info(const gw_ctx* ctx, int32_t* n_graphs, double* last_insta
 // the fastest in the context.  Candidates: full band, proposals per workgroup
 // {64, 128, 256} x frequency chunks {8 .. 512} (multiples of 8, at least 16
 // bins per chunk); heterodyned, waves per workgroup {1, 2, 4} x persistent
-// grid {1, 2, 4, 8, 16} workgroups per CU.
+// grid {8, 16, 32, 64} waves per CU x edge chunks {heuristic, 8, 16, 32}.
 gw_status gw_autotune(gw_ctx* ctx, const double* theta, int64_t n, int32_t like, int32_t marg, int32_t prec,
                       int32_t reps, int32_t* best_shape, double* best_ms, void* stream) {
   if (!ctx || !theta || !best_shape || !best_ms) return set_error(GW_EINVAL, "gw_autotune: null argument");
@@ -854,24 +947,29 @@ gw_status gw_autotune(gw_ctx* ctx, const double* theta, int64_t n, int32_t like,
   (void)hipEventCreate(&e1);
   const bool prof = ctx->prof;
   ctx->prof = false;
-  std::vector<std::pair<int, int>> cands;
+  struct Cand {
+    int a, b, c;
+  };
+  std::vector<Cand> cands;
   if (like == GW_FULL) {
     for (int tpb : {64, 128, 256})
       for (int ch : {8, 16, 32, 64, 128, 256, 512})
-        if (ctx->geom.n_freq / ch >= 16) cands.push_back({tpb, ch});
+        if (ctx->geom.n_freq / ch >= 16) cands.push_back({tpb, ch, 0});
   } else {
     for (int w : {1, 2, 4})
-      for (int per_cu : {1, 2, 4, 8, 16}) cands.push_back({w, 256 * per_cu});
+      for (int per_cu : {8, 16, 32, 64})
+        for (int ech : {0, 8, 16, 32}) cands.push_back({w, 256 * per_cu, ech});
   }
   double best = 1e300;
-  std::pair<int, int> arg{0, 0};
-  for (auto cand : cands) {
+  Cand arg{0, 0, 0};
+  for (const Cand& cand : cands) {
     if (like == GW_FULL) {
-      ctx->full_tpb = cand.first;
-      ctx->full_chunks = cand.second;
+      ctx->full_tpb = cand.a;
+      ctx->full_chunks = cand.b;
     } else {
-      ctx->het->wpb = cand.first;
-      ctx->het->grid = cand.second / cand.first;
+      ctx->het->wpb = cand.a;
+      ctx->het->grid = cand.b / cand.a;
+      ctx->het->ech = cand.c;
     }
     s = loglike_batch(ctx, theta, n, like, marg, prec, out, st);  // warm-up
     if (s != GW_OK) break;
@@ -890,11 +988,12 @@ gw_status gw_autotune(gw_ctx* ctx, const double* theta, int64_t n, int32_t like,
     }
   }
   if (like == GW_FULL) {
-    ctx->full_tpb = arg.first;
-    ctx->full_chunks = arg.second;
+    ctx->full_tpb = arg.a;
+    ctx->full_chunks = arg.b;
   } else {
-    ctx->het->wpb = arg.first > 0 ? arg.first : 4;
-    ctx->het->grid = arg.first > 0 ? arg.second / arg.first : 0;
+    ctx->het->wpb = arg.a > 0 ? arg.a : 4;
+    ctx->het->grid = arg.a > 0 ? arg.b / arg.a : 0;
+    ctx->het->ech = arg.c;
     if (ctx->graphs) graphs_clear(ctx->graphs);
   }
   ctx->prof = prof;
@@ -902,8 +1001,9 @@ gw_status gw_autotune(gw_ctx* ctx, const double* theta, int64_t n, int32_t like,
   (void)hipEventDestroy(e1);
   (void)hipFree(out);
   if (s != GW_OK) return s;
-  best_shape[0] = arg.first;
-  best_shape[1] = like == GW_FULL ? arg.second : ctx->het->grid;
+  best_shape[0] = arg.a;
+  best_shape[1] = like == GW_FULL ? arg.b : ctx->het->grid;
+  best_shape[2] = arg.c;
   *best_ms = best;
   return GW_OK;
 }

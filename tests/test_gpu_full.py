@@ -205,3 +205,19 @@ def test_cfg2_loud_precision(gw):
                 print(f"cfg2 loud marg={marg} prec={prec} kind={kind}: max|dlogL|={err.max():.3e} "
                       f"logL range=[{ref.min():.1f}, {ref.max():.1f}]", flush=True)
                 assert err.max() < TOL[prec]
+
+
+def test_large_batch_sliced_distance_marginal(cfg1):
+    # from 8192 proposals the distance marginal switches to the sliced
+    # lane-per-proposal form; check it on a sample against the oracle
+    prob, ctx, _, _ = cfg1
+    th = gwsynth.prior_draws(44, 9000)
+    th[:16] = gwsynth.near_posterior(45, prob.theta_inj, 16)
+    idx = np.concatenate([np.arange(16), np.random.default_rng(46).choice(np.arange(16, 9000), 100, replace=False)])
+    ref = oracle_many(th[idx], prob, L.PHASE_DIST)
+    for prec in (0, 1):
+        got = _gpu(ctx, th, L.PHASE_DIST, prec)
+        assert np.all(np.isfinite(got))
+        err = np.abs(got[idx] - ref)
+        print(f"cfg1 9000-row batch prec={prec}: max|dlogL|={err.max():.3e}", flush=True)
+        assert err.max() < TOL[prec]

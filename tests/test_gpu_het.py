@@ -101,15 +101,19 @@ def test_uneven_edge_cases(cfg1_het, gw):
     assert torch.all(torch.isnan(out))
 
 
-@pytest.mark.parametrize("wpb,grid", [(1, 0), (2, 37), (4, 1), (4, 1024)])
-def test_het_shapes_agree(cfg1_het, wpb, grid):
+@pytest.mark.parametrize("wpb,grid,ech", [(1, 0, 0), (2, 37, 3), (4, 1, 1), (4, 1024, 0), (4, 4096, 16),
+                                          (2, 0, 200)])
+def test_het_shapes_agree(cfg1_het, wpb, grid, ech):
+    # ech 200 exceeds the 200-bin grid's useful range only at the margin: it
+    # is clamped to the bin count (one bin per chunk)
     prob, het, ctx, th, ref = cfg1_het
-    ctx.set_het_shape(wpb, grid)
+    ctx.set_het_shape(wpb, grid, ech)
     try:
-        got = ctx.loglike(_t(th), like=1, marg=L.PHASE_DIST, prec=0).cpu().numpy()
+        for prec in (0, 1):
+            got = ctx.loglike(_t(th), like=1, marg=L.PHASE_DIST, prec=prec).cpu().numpy()
+            assert np.max(np.abs(got - ref[L.PHASE_DIST])) < TOL[prec]
     finally:
-        ctx.set_het_shape(4, 0)
-    assert np.max(np.abs(got - ref[L.PHASE_DIST])) < TOL[0]
+        ctx.set_het_shape(4, 0, 0)
 
 
 @pytest.fixture(scope="module")
@@ -184,5 +188,5 @@ def test_autotune_keeps_results(cfg1_het, gw, tmp_path, monkeypatch):
             want = ref[L.PHASE] if like == 1 else np.array([L.loglike(x, prob, L.PHASE) for x in th[:64]])
             assert np.max(np.abs(got[:len(want)] - want)) < TOL[1]
     finally:
-        ctx.set_het_shape(4, 0)
+        ctx.set_het_shape(4, 0, 0)
         ctx.set_full_shape(0, 0)
