@@ -38,8 +38,8 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector, dense
 # runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
 # plain 256 MiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid
 # only for the kernel sources they were taken on (hash below).
-TRAFFIC = {"sources_sha256": "96ffb3f6a09d4ed95d0dc40218eb22a310c60c82854d722ecbca1ca1c32a0f4d",
-           "read_bytes": 22152.3 * 1.9998 * 1024, "write_bytes": 24576.0 * 1024}
+TRAFFIC = {"sources_sha256": "829b2001f9fc24b8f693cdcc51a8a9c10c770c6b3f3b19af15415cd99730c1c6",
+           "read_bytes": 22152.7 * 1.9998 * 1024, "write_bytes": 24576.0 * 1024}
 TRAFFIC_SOURCES = ("paper_2607_28265_amd/csrc/gw_full.hip", "paper_2607_28265_amd/csrc/gw_device.h")
 
 
