@@ -61,8 +61,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="full,het,prescreen",
-                    help="comma list of legs to run: full (always timed), het, prescreen, copy")
+    ap.add_argument("--legs", default="full,het,nested,prescreen",
+                    help="comma list of legs to run: full (always timed), het, nested, prescreen, copy")
     return ap.parse_args()
 
 
@@ -241,6 +241,42 @@ def prescreen_leg(gw, torch, reps):
     return res
 
 
+def nested_leg(gw, torch):
+    """End-to-end nested sampling: 1000 live points, 125 deletions per
+    iteration, 11 dimensions in 7 Gibbs blocks, heterodyned (500 bins)
+    phase+distance-marginalised likelihood in the mixed form, dlogz 0.1, on the
+    SNR-24 injection at the 1e-49 PSD; wall time excludes problem set-up.  The
+    oracle's own run of the same settings (stored by the test suite's golden
+    script) is quoted beside it."""
+    import numpy as np
+    import gwsynth
+    from paper_2607_28265_amd import prescreen as P
+    from paper_2607_28265_amd.nested import NestedSampler
+    cfg = gwsynth.CONFIGS["cfg2"]
+    prob = gwsynth.make_problem(cfg["duration"], cfg["f_min"], cfg["f_max"], psd_scale=1e-49)
+    th = gwsynth.prior_draws(gwsynth.SEEDS["injection"], 1)[0]
+    th_inj = P.library_injection(gw.Context, prob, th, snr=24.0)
+    with gw.Context(prob) as ctx:
+        ctx.heterodyne_setup(th_inj, 500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ns = NestedSampler(ctx, n_live=1000, n_delete=125, seed=gwsynth.SEEDS["sampler"], like=gw.GW_HET,
+                           prec=gw.GW_PREC_MIXED)
+        r = ns.run()
+        wall = time.perf_counter() - t0
+    out = {"wall_s": wall, "log_z": r["log_z"], "log_z_err": r["log_z_err"], "iterations": r["iterations"],
+           "n_evals": r["n_evals"], "evals_per_s": r["n_evals"] / wall}
+    gold = os.path.join(ROOT, "tests", "golden", "ns_cfg2.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            g = json.load(f)
+        out["oracle_run"] = {"log_z": g["log_z"], "log_z_err": g["log_z_err"], "iterations": g["iterations"],
+                             "n_evals": g["n_evals"], "cpu_wall_s_single_process": g["cpu_wall_s"]}
+    out["workload"] = ("nested sampling: 1000 live points, 125 deletions per iteration, 7 Gibbs blocks over 11 "
+                       "dimensions, heterodyned 500-bin likelihood (mixed form), dlogz 0.1, SNR-24 injection")
+    return out
+
+
 def copy_leg(torch, reps=5, mib=256):
     """A plain device copy of known size, the reference for the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of the kernels above."""
@@ -340,6 +376,8 @@ def main():
     legs = set(args.legs.split(","))
     if "het" in legs:
         res["heterodyned"] = het_leg(gw, torch, prob, th_inj, max(5, args.steps // 2), 2)
+    if "nested" in legs:
+        res["nested_sampling"] = nested_leg(gw, torch)
     if "prescreen" in legs:
         res["prescreen"] = prescreen_leg(gw, torch, 10)
     if "copy" in legs:

@@ -490,11 +490,14 @@ __global__ void __launch_bounds__(256) k_het_dist_w(const HetArgs* __restrict__ 
 // tile, lane = row, waves splitting the grid (block_dist_lse), so that grid
 // records are scalar loads shared by 64 rows.
 constexpr int64_t kDistRowsPerLane = 8192;  // batches from this size use the sliced form
+constexpr int kHetDistWaves = 8;  // waves per 64-row tile in the sliced form
+
 template <int PREC>
-__global__ void __launch_bounds__(256) k_het_dist(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
-                                                  const double* __restrict__ dtab, int n_dist, double dd,
-                                                  LogI0Consts C) {
-  __shared__ double red[4 * 64];
+__global__ void __launch_bounds__(64 * kHetDistWaves) k_het_dist(const HetArgs* __restrict__ ab,
+                                                                 const int64_t* __restrict__ pre,
+                                                                 const double* __restrict__ dtab, int n_dist,
+                                                                 double dd, LogI0Consts C) {
+  __shared__ double red[kHetDistWaves * 64];
   const int lane = threadIdx.x & 63;
   const int nw = blockDim.x >> 6;
   const int64_t tiles = pre[ab->n_sub];
@@ -654,11 +657,11 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
   if (s != GW_OK || marg != 2) return s;
   const bool sliced = h->n_rows_last >= kDistRowsPerLane;
   if (sliced && prec == GW_PREC_MIXED)
-    hipLaunchKernelGGL(k_het_dist<1>, dim3(256 * 16), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
-                       ctx->n_dist, ctx->dd, C);
+    hipLaunchKernelGGL(k_het_dist<1>, dim3(256 * 8), dim3(64 * kHetDistWaves), 0, st, h->args, h->tile_pre,
+                       ctx->dist_tab, ctx->n_dist, ctx->dd, C);
   else if (sliced)
-    hipLaunchKernelGGL(k_het_dist<0>, dim3(256 * 16), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
-                       ctx->n_dist, ctx->dd, C);
+    hipLaunchKernelGGL(k_het_dist<0>, dim3(256 * 8), dim3(64 * kHetDistWaves), 0, st, h->args, h->tile_pre,
+                       ctx->dist_tab, ctx->n_dist, ctx->dd, C);
   else if (prec == GW_PREC_MIXED)
     hipLaunchKernelGGL(k_het_dist_w<1>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
                        ctx->n_dist, ctx->dd, C);
