@@ -188,59 +188,66 @@ __global__ void __launch_bounds__(256) k_het_summary(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // Work-list kernels
 
-__global__ void k_set_args(HetArgs* a, const double* theta, const int64_t* subs, double* logl, double* coef,
-                           double* zbuf, double* part, int64_t n_rows, int32_t n_sub, int64_t* subs_single,
-                           int64_t single_n) {
-  a->theta = theta;
-  a->subs = subs;
-  a->logl = logl;
-  a->coef = coef;
-  a->zbuf = zbuf;
-  a->part = part;
-  a->n_rows = n_rows;
-  a->ld = n_rows;
-  a->n_sub = n_sub;
-  a->pad = 0;
-  if (subs_single) {
-    subs_single[0] = 0;
-    subs_single[1] = single_n;
+// Writes the argument block and the prefix sums of 64-row tiles per
+// sub-batch (pre[s] = tiles before sub-batch s, pre[n_sub] = all tiles) in one
+// launch of 256 threads.  ``subs`` is read from the device; a single batch
+// (subs_single != NULL) is described by (0, single_n) without reading it back.
+__global__ void __launch_bounds__(256) k_set_args(HetArgs* a, const double* theta, const int64_t* subs, double* logl,
+                                                  double* coef, double* zbuf, double* part, int64_t n_rows,
+                                                  int32_t n_sub, int64_t* subs_single, int64_t single_n,
+                                                  int64_t* __restrict__ pre) {
+  if (threadIdx.x == 0) {
+    a->theta = theta;
+    a->subs = subs;
+    a->logl = logl;
+    a->coef = coef;
+    a->zbuf = zbuf;
+    a->part = part;
+    a->n_rows = n_rows;
+    a->ld = n_rows;
+    a->n_sub = n_sub;
+    a->pad = 0;
+    if (subs_single) {
+      subs_single[0] = 0;
+      subs_single[1] = single_n;
+    }
   }
-}
-
-// Prefix sums of 64-row tiles per sub-batch: tile_pre[s] = tiles before s.
-__global__ void __launch_bounds__(256) k_tile_scan(const HetArgs* __restrict__ a, int64_t* __restrict__ pre) {
-  const int n_sub = a->n_sub;
-  const int64_t n_rows = a->n_rows;
-  const int64_t* subs = a->subs;
-  __shared__ int64_t part[256];
+  if (subs_single) {
+    if (threadIdx.x == 0) {
+      pre[0] = 0;
+      pre[1] = n_rows > 0 ? (n_rows + 63) / 64 : 0;
+    }
+    return;
+  }
+  __shared__ int64_t acc[256];
   const int per = (n_sub + 255) / 256;
   const int s0 = threadIdx.x * per;
   const int s1 = min(s0 + per, n_sub);
   int64_t sum = 0;
-  for (int s = s0; s < s1; ++s) {
-    int64_t cnt = subs[2 * s + 1];
-    const int64_t off = subs[2 * s];
+  for (int q = s0; q < s1; ++q) {
+    int64_t cnt = subs[2 * q + 1];
+    const int64_t off = subs[2 * q];
     if (off < 0 || off >= n_rows || cnt <= 0) cnt = 0;
     else if (cnt > n_rows - off) cnt = n_rows - off;
     sum += (cnt + 63) / 64;
   }
-  part[threadIdx.x] = sum;
+  acc[threadIdx.x] = sum;
   __syncthreads();
   if (threadIdx.x == 0) {
     int64_t run = 0;
     for (int j = 0; j < 256; ++j) {
-      const int64_t v = part[j];
-      part[j] = run;
+      const int64_t v = acc[j];
+      acc[j] = run;
       run += v;
     }
     pre[n_sub] = run;
   }
   __syncthreads();
-  int64_t run = part[threadIdx.x];
-  for (int s = s0; s < s1; ++s) {
-    pre[s] = run;
-    int64_t cnt = subs[2 * s + 1];
-    const int64_t off = subs[2 * s];
+  int64_t run = acc[threadIdx.x];
+  for (int q = s0; q < s1; ++q) {
+    pre[q] = run;
+    int64_t cnt = subs[2 * q + 1];
+    const int64_t off = subs[2 * q];
     if (off < 0 || off >= n_rows || cnt <= 0) cnt = 0;
     else if (cnt > n_rows - off) cnt = n_rows - off;
     run += (cnt + 63) / 64;
@@ -409,6 +416,43 @@ __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, con
 // prefactor (A P_i) / (A0 P0_i), sum the detectors and apply the plain or
 // phase-marginalised epilogue (or stage |Z_1| and <h|h>_1 for the distance
 // marginal).
+// Finish one row from its per-detector sums (z_i, unit-phasor <h|h> part):
+// restore the prefactor (A P_i) / (A0 P0_i), sum the detectors and apply the
+// plain or phase-marginalised epilogue (or stage |Z_1| and <h|h>_1 for the
+// distance marginal).
+__device__ inline void het_finish_row(const HetArgs* __restrict__ ab, int64_t row, int nd, int marg,
+                                      const double* zr, const double* zi, const double* hh, const HetConst& hc,
+                                      const LogI0Consts& C) {
+  const int64_t ld = ab->ld;
+  const double* cf = ab->coef + row;
+  double Zr = 0.0, Zi = 0.0, plain = 0.0, hht = 0.0;
+  for (int i = 0; i < nd; ++i) {
+    const double ar = cf[(C_APRE + i) * ld], ai = cf[(C_APIM + i) * ld];
+    const double qr = ar * hc.ap0_inv_re[i] - ai * hc.ap0_inv_im[i];
+    const double qi = ar * hc.ap0_inv_im[i] + ai * hc.ap0_inv_re[i];
+    const double wr = qr * zr[i] - qi * zi[i];
+    const double wi = qr * zi[i] + qi * zr[i];
+    plain += wr;
+    Zr += wr;
+    Zi += wi;
+    hht += (qr * qr + qi * qi) * (hc.hh0[i] + hh[i]);
+  }
+  const bool valid = cf[C_VALID * ld] != 0.0;
+  const double zabs = sqrt(Zr * Zr + Zi * Zi);
+  if (marg == 2) {
+    ab->zbuf[row] = valid ? zabs : -1.0;
+    ab->zbuf[ld + row] = hht;
+  } else {
+    double out;
+    if (!valid) out = -INFINITY;
+    else if (marg == 0) out = -0.5 * hc.dd + plain - 0.5 * hht;
+    else out = -0.5 * hc.dd - 0.5 * hht + log_i0(zabs, C);
+    ab->logl[row] = out;
+  }
+}
+
+// Large batches: one lane per row (coalesced over rows), the edge-chunk
+// partials summed in chunk order.
 __global__ void __launch_bounds__(256) k_het_combine(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
                                                      int nd, int n_ech, int marg, HetConst hc, LogI0Consts C) {
   const int lane = threadIdx.x & 63;
@@ -422,38 +466,57 @@ __global__ void __launch_bounds__(256) k_het_combine(const HetArgs* __restrict__
     if (!tile_rows(ab, pre, t, &row0, &row_end)) continue;
     const int64_t row = row0 + lane;
     if (row >= row_end) continue;
-    const double* cf = ab->coef + row;
-    double Zr = 0.0, Zi = 0.0, plain = 0.0, hht = 0.0;
+    double zr[kMaxDet], zi[kMaxDet], hh[kMaxDet];
     for (int i = 0; i < nd; ++i) {
-      double zr = 0.0, zi = 0.0, hh = 0.0;
+      zr[i] = zi[i] = hh[i] = 0.0;
       for (int e = 0; e < n_ech; ++e) {
         const double* p = ab->part + ((int64_t)e * 3 * nd + 3 * i) * ld + row;
-        zr += p[0];
-        zi += p[ld];
-        hh += p[2 * ld];
+        zr[i] += p[0];
+        zi[i] += p[ld];
+        hh[i] += p[2 * ld];
       }
-      const double ar = cf[(C_APRE + i) * ld], ai = cf[(C_APIM + i) * ld];
-      const double qr = ar * hc.ap0_inv_re[i] - ai * hc.ap0_inv_im[i];
-      const double qi = ar * hc.ap0_inv_im[i] + ai * hc.ap0_inv_re[i];
-      const double wr = qr * zr - qi * zi;
-      const double wi = qr * zi + qi * zr;
-      plain += wr;
-      Zr += wr;
-      Zi += wi;
-      hht += (qr * qr + qi * qi) * (hc.hh0[i] + hh);
     }
-    const bool valid = cf[C_VALID * ld] != 0.0;
-    const double zabs = sqrt(Zr * Zr + Zi * Zi);
-    if (marg == 2) {
-      ab->zbuf[row] = valid ? zabs : -1.0;
-      ab->zbuf[ld + row] = hht;
-    } else {
-      double out;
-      if (!valid) out = -INFINITY;
-      else if (marg == 0) out = -0.5 * hc.dd + plain - 0.5 * hht;
-      else out = -0.5 * hc.dd - 0.5 * hht + log_i0(zabs, C);
-      ab->logl[row] = out;
+    het_finish_row(ab, row, nd, marg, zr, zi, hh, hc, C);
+  }
+}
+
+// Small batches (and at most 64 edge chunks): one wave per row, lane e
+// holding chunk e's partials, summed by a fixed shuffle tree, so that the
+// loads of a row are issued together instead of one chain per thread.
+__global__ void __launch_bounds__(256) k_het_combine_w(const HetArgs* __restrict__ ab,
+                                                       const int64_t* __restrict__ pre, int nd, int n_ech, int marg,
+                                                       HetConst hc, LogI0Consts C) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * wpb;
+  const int64_t total = pre[ab->n_sub] * 64;
+  const int64_t ld = ab->ld;
+  for (int64_t it = wid; it < total; it += nwaves) {
+    int64_t row0, row_end;
+    if (!tile_rows(ab, pre, it >> 6, &row0, &row_end)) continue;
+    const int64_t row = row0 + (it & 63);
+    if (row >= row_end) continue;
+    double zr[kMaxDet], zi[kMaxDet], hh[kMaxDet];
+    for (int i = 0; i < nd; ++i) {
+      double a = 0.0, b = 0.0, c = 0.0;
+      if (lane < n_ech) {
+        const double* p = ab->part + ((int64_t)lane * 3 * nd + 3 * i) * ld + row;
+        a = p[0];
+        b = p[ld];
+        c = p[2 * ld];
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+        c += __shfl_xor(c, o, 64);
+      }
+      zr[i] = a;
+      zi[i] = b;
+      hh[i] = c;
     }
+    if (lane == 0) het_finish_row(ab, row, nd, marg, zr, zi, hh, hc, C);
   }
 }
 
@@ -612,7 +675,9 @@ static gw_status launch_het_nd(gw_ctx* ctx, int marg, int prec, int n_ech, hipSt
   const TrigConsts T = make_trig_consts();
   const int tpb = 64 * h->wpb;
   int grid = h->grid;
-  if (grid <= 0) grid = kHetWaves / h->wpb;  // 64 waves per CU, several rounds of the resident 20
+  // 64 waves per CU (several rounds of the resident 20); small batches have
+  // few items, and an idle grid still costs dispatch time
+  if (grid <= 0) grid = (h->n_rows_last < kDistRowsPerLane ? 1024 : kHetWaves) / h->wpb;
   const int slot = prof_begin(ctx, st);
   if (prec == GW_PREC_FP64)
     hipLaunchKernelGGL((k_het<ND, 0>), dim3(grid), dim3(tpb), 0, st, h->args, h->tile_pre, h->rec, h->n_bins, n_ech,
@@ -629,11 +694,10 @@ static gw_status launch_het_nd(gw_ctx* ctx, int marg, int prec, int n_ech, hipSt
 // (+ distance marginal).  Reads the device argument block only.
 static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStream_t st) {
   gw_het_state* h = ctx->het;
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(256), 0, st, h->args, h->tile_pre);
-  gw_status s = check_hip(hipGetLastError(), "tile scan launch");
-  if (s != GW_OK) return s;
-  hipLaunchKernelGGL(k_het_prologue, dim3(256 * 4), dim3(256), 0, st, h->args, h->tile_pre, marg, ctx->geom);
-  s = check_hip(hipGetLastError(), "heterodyne prologue launch");
+  const bool small = h->n_rows_last < kDistRowsPerLane;
+  hipLaunchKernelGGL(k_het_prologue, dim3(small ? 32 : 256 * 4), dim3(256), 0, st, h->args, h->tile_pre, marg,
+                     ctx->geom);
+  gw_status s = check_hip(hipGetLastError(), "heterodyne prologue launch");
   if (s != GW_OK) return s;
   switch (ctx->n_det) {
     case 1: s = launch_het_nd<1>(ctx, marg, prec, n_ech, st); break;
@@ -651,8 +715,12 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
   }
   hc.dd = ctx->dd;
   const LogI0Consts C = make_log_i0_consts();
-  hipLaunchKernelGGL(k_het_combine, dim3(256 * 4), dim3(256), 0, st, h->args, h->tile_pre, ctx->n_det, n_ech, marg, hc,
-                     C);
+  if (h->n_rows_last < kDistRowsPerLane && n_ech <= 64)
+    hipLaunchKernelGGL(k_het_combine_w, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->n_det, n_ech,
+                       marg, hc, C);
+  else
+    hipLaunchKernelGGL(k_het_combine, dim3(256 * 4), dim3(256), 0, st, h->args, h->tile_pre, ctx->n_det, n_ech,
+                       marg, hc, C);
   s = check_hip(hipGetLastError(), "heterodyne combine launch");
   if (s != GW_OK || marg != 2) return s;
   const bool sliced = h->n_rows_last >= kDistRowsPerLane;
@@ -682,9 +750,10 @@ static gw_status het_prepare(gw_ctx* ctx, const double* theta, const int64_t* su
   if (s == GW_OK)
     s = ensure_buffer(&ctx->partial, &ctx->partial_cap, (int64_t)(*n_ech) * 3 * ctx->n_det * n_rows, "partials");
   if (s != GW_OK) return s;
-  hipLaunchKernelGGL(k_set_args, dim3(1), dim3(1), 0, st, h->args, theta,
+  hipLaunchKernelGGL(k_set_args, dim3(1), dim3(256), 0, st, h->args, theta,
                      single ? (const int64_t*)h->subs_single : subs, logl, ctx->coef, ctx->zbuf, ctx->partial, n_rows,
-                     single ? 1 : n_sub, single ? h->subs_single : (int64_t*)nullptr, single ? n_rows : (int64_t)0);
+                     single ? 1 : n_sub, single ? h->subs_single : (int64_t*)nullptr, single ? n_rows : (int64_t)0,
+                     h->tile_pre);
   return check_hip(hipGetLastError(), "argument kernel launch");
 }
 
