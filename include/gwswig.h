@@ -212,7 +212,8 @@ gw_status gw_graph_info(const gw_ctx* ctx, int32_t* n_graphs, double* last_insta
  * else Philox4x64-10 (Salmon et al. 2011): uniform j of chain c is word j % 4
  * of the block at counter (counter, c, j / 4, 0) under key (seed, 0), mapped
  * to ((w >> 11) + 0.5) 2^-53.
- * Blocks until done (the host checks progress every four rounds).
+ * Blocks until done (the host checks progress every four rounds; rounds
+ * after every chain has finished change nothing).
  */
 typedef struct {
   int64_t k;              /* number of chains */
@@ -233,6 +234,10 @@ typedef struct {
   int32_t prec;           /* GW_PREC_FP64 or GW_PREC_MIXED */
   int32_t* n_evals;       /* device [k] likelihood calls per chain, or NULL */
   int32_t* status;        /* device [k] 0 moved, 1 kept, or NULL */
+  int32_t use_graph;      /* 1: replay a captured graph of 4 rounds (captured on
+                             first use and again when k, like, marg, prec, the
+                             launch shapes or a workspace change); 0: launch
+                             each kernel.  Results are identical. */
 } gw_slice_args;
 
 gw_status slice_step(gw_ctx* ctx, const gw_slice_args* args, void* stream);

@@ -67,6 +67,7 @@ class gw_slice_args(ctypes.Structure):
         ("prec", ctypes.c_int32),
         ("n_evals", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
+        ("use_graph", ctypes.c_int32),
     ]
 
 
@@ -319,7 +320,8 @@ def gw_autotune(ctx, theta, like: int, marg: int, prec: int, reps: int = 3, stre
 
 def slice_step(ctx, x, logl, logl_star: float, block, chol, seed: int = 0, counter: int = 0, uniforms=None,
                w: float = 1.0, max_out: int = 10, max_shrink: int = 100, like: int = GW_HET,
-               marg: int = GW_MARG_PHASE_DIST, prec: int = GW_PREC_FP64, n_evals=None, status=None, stream=None):
+               marg: int = GW_MARG_PHASE_DIST, prec: int = GW_PREC_FP64, n_evals=None, status=None, stream=None,
+               use_graph: bool = True):
     """One slice update of one block for every chain; x [k, 11] and logl [k] (CUDA float64) change in place."""
     import numpy as np
     import torch
@@ -342,7 +344,7 @@ def slice_step(ctx, x, logl, logl_star: float, block, chol, seed: int = 0, count
                       uniforms=uniforms.data_ptr() if uniforms is not None else None, w=float(w),
                       max_out=int(max_out), max_shrink=int(max_shrink), like=int(like), marg=int(marg),
                       prec=int(prec), n_evals=n_evals.data_ptr() if n_evals is not None else None,
-                      status=status.data_ptr() if status is not None else None)
+                      status=status.data_ptr() if status is not None else None, use_graph=1 if use_graph else 0)
     check(load().slice_step(ctx, ctypes.byref(a), _stream_ptr(stream)), "slice_step")
 
 

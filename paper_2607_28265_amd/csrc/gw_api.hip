@@ -89,6 +89,17 @@ void prof_end(gw_ctx* ctx, int slot, hipStream_t st) {
 
 using namespace gw;
 
+namespace gw {
+gw_status full_reserve(gw_ctx* ctx, int64_t n) {
+  int tpb, nch;
+  full_launch_shape(ctx, n, &tpb, &nch);
+  gw_status s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
+  if (s == GW_OK) s = ensure_buffer(&ctx->partial, &ctx->partial_cap, (int64_t)nch * 2 * ctx->n_det * n, "partials");
+  if (s == GW_OK) s = ensure_buffer(&ctx->zbuf, &ctx->zbuf_cap, 2 * n, "marginal workspace");
+  return s;
+}
+}  // namespace gw
+
 extern "C" {
 
 const char* gw_last_error(void) { return g_err; }

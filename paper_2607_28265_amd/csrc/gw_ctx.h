@@ -81,6 +81,13 @@ gw_status build_moment_table(gw_ctx* ctx, const std::vector<double>& rec, const 
 int prof_begin(gw_ctx* ctx, hipStream_t st);
 void prof_end(gw_ctx* ctx, int slot, hipStream_t st);
 
+// Grow the workspace a likelihood call of n rows needs, without launching
+// (graph capture must not allocate); het_shape_key reports the heterodyned
+// launch shape (zeros without heterodyne set-up).
+gw_status full_reserve(gw_ctx* ctx, int64_t n);
+gw_status het_reserve(gw_ctx* ctx, int64_t n);
+void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech);
+
 // Heterodyne and graph state owned by the context.
 void het_free(gw_ctx* ctx);
 void graphs_free(gw_ctx* ctx);

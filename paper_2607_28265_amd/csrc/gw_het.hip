@@ -757,6 +757,21 @@ static gw_status het_prepare(gw_ctx* ctx, const double* theta, const int64_t* su
   return check_hip(hipGetLastError(), "argument kernel launch");
 }
 
+gw_status het_reserve(gw_ctx* ctx, int64_t n) {
+  if (!ctx->het) return set_error(GW_ESTATE, "heterodyne_setup has not been called");
+  const int n_ech = het_ech(ctx, n);
+  gw_status s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
+  if (s == GW_OK) s = ensure_buffer(&ctx->zbuf, &ctx->zbuf_cap, 2 * n, "marginal workspace");
+  if (s == GW_OK) s = ensure_buffer(&ctx->partial, &ctx->partial_cap, (int64_t)n_ech * 3 * ctx->n_det * n, "partials");
+  return s;
+}
+
+void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech) {
+  *wpb = ctx->het ? ctx->het->wpb : 0;
+  *grid = ctx->het ? ctx->het->grid : 0;
+  *ech = ctx->het ? ctx->het->ech : 0;
+}
+
 gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl, hipStream_t st) {
   if (!ctx->het) return set_error(GW_ESTATE, "loglike_batch: heterodyne_setup has not been called");
   int n_ech = 1;

@@ -8,6 +8,7 @@
 // batched likelihood evaluates them all, and an update kernel moves each
 // chain's state machine; the host checks for completion every few rounds.
 #include <math.h>
+#include <string.h>
 
 #include <vector>
 
@@ -29,6 +30,14 @@ struct SliceParams {
   uint64_t seed, counter;
   const double* uniforms;  // [k][kUniFixed + max_shrink] or null
   int64_t k;
+};
+
+// Parameters of one call as a device block, so that a captured graph of the
+// round loop reads them at replay time instead of baking them in.
+struct SliceDev {
+  SliceParams P;
+  double* x;
+  double* logl;
 };
 
 // Per-chain state (structure of arrays inside one device allocation).
@@ -134,8 +143,15 @@ __device__ inline bool make_point(const SliceParams& P, const SliceState& S, con
 // Write the candidates of every chain that is still moving: the two bracket
 // ends while stepping out, else one shrink draw (points outside the cube
 // count as rejections immediately, without a likelihood call).
-__global__ void k_slice_propose(SliceParams P, SliceState S, const double* __restrict__ x0,
-                                double* __restrict__ cand) {
+__global__ void k_slice_set(SliceDev* D, SliceParams P, double* x, double* logl) {
+  D->P = P;
+  D->x = x;
+  D->logl = logl;
+}
+
+__global__ void k_slice_propose(const SliceDev* __restrict__ D, SliceState S, double* __restrict__ cand) {
+  const SliceParams& P = D->P;
+  const double* __restrict__ x0 = D->x;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c == 0) *S.n_active = 0;
   if (c >= P.k) return;
@@ -187,8 +203,10 @@ __global__ void k_slice_propose(SliceParams P, SliceState S, const double* __res
   S.flags[c] = fl;
 }
 
-__global__ void k_slice_update(SliceParams P, SliceState S, double* __restrict__ x, double* __restrict__ logl,
-                               const double* __restrict__ cand_logl) {
+__global__ void k_slice_update(const SliceDev* __restrict__ D, SliceState S, const double* __restrict__ cand_logl) {
+  const SliceParams& P = D->P;
+  double* __restrict__ x = D->x;
+  double* __restrict__ logl = D->logl;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P.k) return;
   int fl = S.flags[c];
@@ -248,6 +266,15 @@ __global__ void k_slice_finish(SliceParams P, SliceState S, int32_t* n_evals, in
 
 using namespace gw;
 
+// What a captured round group bakes in: any change means a new capture.
+struct SliceGraphKey {
+  int64_t k;
+  int32_t like, marg, prec;
+  const void *ws_mem, *coef, *partial, *zbuf, *het;
+  int32_t het_wpb, het_grid, het_ech, full_tpb, full_chunks, full_kernel;
+  bool operator==(const SliceGraphKey& o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
 struct gw_slice_ws {
   int64_t cap = 0;
   void* mem = nullptr;
@@ -255,9 +282,69 @@ struct gw_slice_ws {
   double* cand_logl = nullptr;  // [2k]
   int32_t* h_active = nullptr;  // pinned host
   SliceState S{};
+  SliceDev* dev = nullptr;      // device parameter block
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  SliceGraphKey key{};
+  bool have_graph = false;
 };
 
 static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out);
+
+// Capture one round group into a graph (re-captured when anything it bakes in
+// changes) on the workspace's own capture stream.  Buffers the likelihood
+// would grow are reserved first: no allocation may happen during capture.
+template <class Group>
+static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, const gw_slice_args* a, Group group) {
+  const int64_t n = 2 * a->k;
+  gw_status s = a->like == GW_HET ? het_reserve(ctx, n) : full_reserve(ctx, n);
+  if (s != GW_OK) return s;
+  SliceGraphKey key;
+  memset(&key, 0, sizeof(key));
+  key.k = a->k;
+  key.like = a->like;
+  key.marg = a->marg;
+  key.prec = a->prec;
+  key.ws_mem = ws->mem;
+  key.coef = ctx->coef;
+  key.partial = ctx->partial;
+  key.zbuf = ctx->zbuf;
+  key.het = ctx->het;
+  het_shape_key(ctx, &key.het_wpb, &key.het_grid, &key.het_ech);
+  key.full_tpb = ctx->full_tpb;
+  key.full_chunks = ctx->full_chunks;
+  key.full_kernel = ctx->full_kernel;
+  if (ws->have_graph && ws->key == key) return GW_OK;
+  if (ws->exec) (void)hipGraphExecDestroy(ws->exec);
+  if (ws->graph) (void)hipGraphDestroy(ws->graph);
+  ws->exec = nullptr;
+  ws->graph = nullptr;
+  ws->have_graph = false;
+  if (!ws->cap_stream) {
+    s = check_hip(hipStreamCreateWithFlags(&ws->cap_stream, hipStreamNonBlocking), "capture stream");
+    if (s != GW_OK) return s;
+  }
+  const bool prof = ctx->prof;
+  ctx->prof = false;  // no timing events inside the graph
+  s = check_hip(hipStreamBeginCapture(ws->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  gw_status g = GW_OK;
+  if (s == GW_OK) g = group(ws->cap_stream);
+  hipGraph_t graph = nullptr;
+  if (s == GW_OK) s = check_hip(hipStreamEndCapture(ws->cap_stream, &graph), "end capture");
+  ctx->prof = prof;
+  if (s == GW_OK && g != GW_OK) s = g;
+  if (s == GW_OK) s = check_hip(hipGraphInstantiate(&ws->exec, graph, nullptr, nullptr, 0), "graph instantiate");
+  if (s != GW_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    ws->exec = nullptr;
+    return s;
+  }
+  ws->graph = graph;
+  ws->key = key;
+  ws->have_graph = true;
+  return GW_OK;
+}
 
 extern "C" {
 
@@ -302,23 +389,33 @@ gw_status slice_step(gw_ctx* ctx, const gw_slice_args* a, void* stream) {
   P.k = a->k;
   const int tpb = 256;
   const unsigned blocks = (unsigned)((a->k + tpb - 1) / tpb);
+  hipLaunchKernelGGL(k_slice_set, dim3(1), dim3(1), 0, st, ws->dev, P, a->x, a->logl);
   hipLaunchKernelGGL(k_slice_init, dim3(blocks), dim3(tpb), 0, st, P, ws->S);
   s = check_hip(hipGetLastError(), "slice init launch");
-  // Rounds: stepping out takes at most max_out + 1 rounds per side (both sides
-  // in parallel), shrinking at most max_shrink; check completion every 4.
+  // One group = 4 rounds of (propose, batched likelihood, update); after a
+  // group the host reads the number of chains still moving.  Stepping out
+  // takes at most max_out + 1 rounds per side (both sides in parallel) and
+  // shrinking at most max_shrink, so after max_rounds every chain is done and
+  // further rounds change nothing.
   const int max_rounds = a->max_out + 1 + a->max_shrink + 1;
-  int rounds = 0;
-  while (s == GW_OK && rounds < max_rounds) {
-    for (int r = 0; r < 4 && s == GW_OK && rounds < max_rounds; ++r, ++rounds) {
-      hipLaunchKernelGGL(k_slice_propose, dim3(blocks), dim3(tpb), 0, st, P, ws->S, (const double*)a->x, ws->cand);
-      s = check_hip(hipGetLastError(), "slice propose launch");
-      if (s == GW_OK) s = loglike_batch(ctx, ws->cand, 2 * a->k, a->like, a->marg, a->prec, ws->cand_logl, st);
-      if (s == GW_OK) {
-        hipLaunchKernelGGL(k_slice_update, dim3(blocks), dim3(tpb), 0, st, P, ws->S, a->x, a->logl,
+  auto group = [&](hipStream_t gs) -> gw_status {
+    gw_status g = GW_OK;
+    for (int r = 0; r < 4 && g == GW_OK; ++r) {
+      hipLaunchKernelGGL(k_slice_propose, dim3(blocks), dim3(tpb), 0, gs, (const SliceDev*)ws->dev, ws->S, ws->cand);
+      g = check_hip(hipGetLastError(), "slice propose launch");
+      if (g == GW_OK) g = loglike_batch(ctx, ws->cand, 2 * a->k, a->like, a->marg, a->prec, ws->cand_logl, gs);
+      if (g == GW_OK) {
+        hipLaunchKernelGGL(k_slice_update, dim3(blocks), dim3(tpb), 0, gs, (const SliceDev*)ws->dev, ws->S,
                            (const double*)ws->cand_logl);
-        s = check_hip(hipGetLastError(), "slice update launch");
+        g = check_hip(hipGetLastError(), "slice update launch");
       }
     }
+    return g;
+  };
+  if (s == GW_OK && a->use_graph) s = slice_graph(ctx, ws, a, group);
+  for (int rounds = 0; s == GW_OK && rounds < max_rounds; rounds += 4) {
+    if (a->use_graph) s = check_hip(hipGraphLaunch(ws->exec, st), "slice graph launch");
+    else s = group(st);
     if (s != GW_OK) break;
     s = check_hip(hipMemcpyAsync(ws->h_active, ws->S.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
     if (s == GW_OK) s = check_hip(hipStreamSynchronize(st), "slice round sync");
@@ -350,6 +447,7 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
     if (!ws) return set_error(GW_ENOMEM, "slice workspace");
     if (hipHostMalloc((void**)&ws->h_active, sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
       return set_error(GW_ENOMEM, "slice pinned flag");
+    if (hipMalloc((void**)&ws->dev, sizeof(SliceDev)) != hipSuccess) return set_error(GW_ENOMEM, "slice parameters");
   }
   if (ws->cap >= k) {
     *out = ws;
@@ -389,7 +487,11 @@ namespace gw {
 void slice_free(gw_ctx* ctx) {
   gw_slice_ws* ws = ctx->slice;
   if (!ws) return;
+  if (ws->exec) (void)hipGraphExecDestroy(ws->exec);
+  if (ws->graph) (void)hipGraphDestroy(ws->graph);
+  if (ws->cap_stream) (void)hipStreamDestroy(ws->cap_stream);
   if (ws->mem) (void)hipFree(ws->mem);
+  if (ws->dev) (void)hipFree(ws->dev);
   if (ws->h_active) (void)hipHostFree(ws->h_active);
   delete ws;
   ctx->slice = nullptr;

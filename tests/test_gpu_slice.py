@@ -58,15 +58,16 @@ def setup():
     ctx.close()
 
 
-def _run_gpu(gw, ctx, x, logl, lstar, block, chol, uni=None, seed=0, counter=0, max_shrink=60, max_out=4):
+def _run_gpu(gw, ctx, x, logl, lstar, block, chol, uni=None, seed=0, counter=0, max_shrink=60, max_out=4,
+             use_graph=True, prec=0, like=None):
     xt = torch.from_numpy(x.copy()).cuda()
     lt = torch.from_numpy(logl.copy()).cuda()
     ne = torch.zeros(len(x), dtype=torch.int32, device="cuda")
     stt = torch.zeros(len(x), dtype=torch.int32, device="cuda")
     ut = torch.from_numpy(uni).cuda() if uni is not None else None
     gw.slice_step(ctx.handle, xt, lt, lstar, block, chol, seed=seed, counter=counter, uniforms=ut, w=1.0,
-                  max_out=max_out, max_shrink=max_shrink, like=gw.GW_HET, marg=gw.GW_MARG_PHASE_DIST, prec=0,
-                  n_evals=ne, status=stt)
+                  max_out=max_out, max_shrink=max_shrink, like=gw.GW_HET if like is None else like,
+                  marg=gw.GW_MARG_PHASE_DIST, prec=prec, n_evals=ne, status=stt, use_graph=use_graph)
     torch.cuda.synchronize()
     return xt.cpu().numpy(), lt.cpu().numpy(), ne.cpu().numpy(), stt.cpu().numpy()
 
@@ -115,3 +116,23 @@ def test_slice_step_argument_errors(setup):
         gw.slice_step(ctx.handle, xt, lt, 0.0, [11], np.eye(1))  # out of range
     with pytest.raises(gw.GwError):
         gw.slice_step(ctx.handle, xt, lt, 0.0, [0], np.eye(1), marg=gw.GW_MARG_NONE)
+
+
+@pytest.mark.parametrize("like", [0, 1])
+def test_graph_replay_equals_eager(setup, like):
+    # the captured round group and the eager launches run the same kernels in
+    # the same order: bit-identical moves; consecutive calls with different
+    # blocks, constraints and chain counts reuse or re-capture the graph
+    gw, ctx, prob, het, loglike_u, x, logl = setup
+    for call, bi in enumerate([0, 4, 0, 6, 1]):
+        block = S.BLOCKS[bi]
+        chol = S.block_cholesky(x, block)
+        lstar = float(np.quantile(logl, 0.2 + 0.05 * call))
+        keep = logl > lstar
+        if call == 3:
+            keep[: len(keep) // 2] = False  # a smaller k forces a new capture
+        xs, ls = x[keep], logl[keep]
+        outs = [_run_gpu(gw, ctx, xs, ls, lstar, block, chol, None, 99, 1000 + call, 60, 4, use_graph=g, prec=1,
+                         like=like) for g in (False, True)]
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b), (call, bi)
