@@ -339,6 +339,16 @@ gw_status gw_set_full_kernel(gw_ctx* ctx, int32_t kind);
 gw_status gw_full_info(const gw_ctx* ctx, int32_t* mom_blk);
 
 /*
+ * Correction factor 1 / (1 + b) applied to the mixed full-band sums, where b
+ * is the mean complex deviation g~ conj(g) - 1 of the FP32 hardware phasor
+ * g~ = cos(2 pi t) - i sin(2 pi t) from the exact one over 2^20 uniform
+ * arguments t, measured once at gw_ctx_create.  Every full-band sum is linear
+ * in the phasor, so removing the mean bias leaves only the unbiased rounding,
+ * whose effect on log L averages down over the bins.
+ */
+gw_status gw_phasor_gain(const gw_ctx* ctx, double* re, double* im);
+
+/*
  * Kernel timing of the dominant kernel (full-band overlap kernel, or the
  * heterodyned evaluation kernel) for roofline reporting: while enabled, every
  * launch of it is bracketed by HIP events recorded on the launch stream.

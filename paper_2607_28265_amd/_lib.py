@@ -98,6 +98,7 @@ _SIGS = {
     "gw_prior_transform": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     "gw_set_full_kernel": (ctypes.c_int, [_P, ctypes.c_int32]),
     "gw_full_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "gw_phasor_gain": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "gw_mlp_create": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_P)]),
     "gw_mlp_destroy": (ctypes.c_int, [_P]),
     "gw_mlp_n_params": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64)]),
@@ -248,6 +249,12 @@ def gw_full_info(ctx) -> int:
     v = ctypes.c_int32()
     check(load().gw_full_info(ctx, ctypes.byref(v)), "gw_full_info")
     return v.value
+
+
+def gw_phasor_gain(ctx):
+    re, im = ctypes.c_double(), ctypes.c_double()
+    check(load().gw_phasor_gain(ctx, ctypes.byref(re), ctypes.byref(im)), "gw_phasor_gain")
+    return complex(re.value, im.value)
 
 
 def gw_profile_enable(ctx, enable: bool = True):

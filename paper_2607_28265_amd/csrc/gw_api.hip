@@ -211,6 +211,7 @@ gw_status gw_ctx_create(const gw_problem* pr, int32_t device, gw_ctx** out) {
                      "dist copy");
   }
   if (st == GW_OK) st = build_moment_table(ctx, rec, pr->det_pos);
+  if (st == GW_OK) st = calibrate_phasor(ctx);
   if (st != GW_OK) {
     gw_ctx_destroy(ctx);
     return st;
@@ -325,6 +326,13 @@ gw_status gw_set_full_kernel(gw_ctx* ctx, int32_t kind) {
   if (!ctx) return set_error(GW_EINVAL, "gw_set_full_kernel: ctx is NULL");
   if (kind < 0 || kind > 2) return set_error(GW_EINVAL, "gw_set_full_kernel: kind must be 0, 1 or 2");
   ctx->full_kernel = kind;
+  return GW_OK;
+}
+
+gw_status gw_phasor_gain(const gw_ctx* ctx, double* re, double* im) {
+  if (!ctx || !re || !im) return set_error(GW_EINVAL, "gw_phasor_gain: null argument");
+  *re = ctx->pgain_re;
+  *im = ctx->pgain_im;
   return GW_OK;
 }
 

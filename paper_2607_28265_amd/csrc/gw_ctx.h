@@ -41,6 +41,10 @@ struct gw_ctx {
   int full_tpb = 0;
   int full_chunks = 0;
   int full_kernel = 0;             // 0 auto, 1 vector-ALU reduction, 2 matrix-core reduction (mixed only)
+  // 1 / (1 + b), b the mean complex deviation of the FP32 hardware phasor
+  // cos(2 pi t) - i sin(2 pi t) from the exact one over uniform t (measured at
+  // context creation); applied to the mixed reductions' sums
+  double pgain_re = 1.0, pgain_im = 0.0;
   // matrix-core form of the mixed reduction: block moments
   //   W[k][q][plane], q = detector/moment column, planes (w_r, w_i - w_r, w_r + w_i)
   float* wtab = nullptr;
@@ -75,6 +79,8 @@ void full_launch_shape(const gw_ctx* ctx, int64_t n, int* tpb, int* n_chunks);
 // (host [n_freq][4 + 2 n_det]); leaves the form unavailable (mom_blk = 0) when
 // the detector delays are too long for a block of 8 bins.
 gw_status build_moment_table(gw_ctx* ctx, const std::vector<double>& rec, const double* det_pos);
+// Measure the hardware phasor bias and set ctx->pgain_re / pgain_im.
+gw_status calibrate_phasor(gw_ctx* ctx);
 
 // Kernel timing: record a start / stop event pair around the dominant kernel.
 // prof_begin returns the pair index or -1 when timing is off or full.

@@ -63,8 +63,8 @@ __device__ inline void phasor(double r, const TrigConsts& T, double* gr, double*
 template <int ND, int PREC>
 __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, int64_t ld, int64_t n,
                                               const double* __restrict__ bins, int64_t k0, double df,
-                                              int n_freq, int chunk_len, int n_chunks, TrigConsts T,
-                                              double* __restrict__ partial) {
+                                              int n_freq, int chunk_len, int n_chunks, TrigConsts T, double pg_re,
+                                              double pg_im, double* __restrict__ partial) {
   constexpr int RS = 4 + 2 * ND;
   const int tpb = blockDim.x;
   const int nptile = (int)((n + tpb - 1) / tpb);
@@ -168,6 +168,15 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
     zr[i] = tr;
     zi[i] = ti;
   }
+  if (PREC == 1) {
+    // remove the mean bias of the hardware phasor (every sum is linear in it)
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const double tr = zr[i] * pg_re - zi[i] * pg_im;
+      zi[i] = zr[i] * pg_im + zi[i] * pg_re;
+      zr[i] = tr;
+    }
+  }
   if (p < n) {
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
@@ -233,7 +242,8 @@ template <int ND>
 __global__ void __launch_bounds__(256) k_full_mfma(const double* __restrict__ coef, int64_t ld, int64_t n,
                                                    const double* __restrict__ bins, const float* __restrict__ wtab,
                                                    int64_t k0, double df, int n_freq, int n_pad, int blk,
-                                                   int chunk_len, int n_chunks, double* __restrict__ partial) {
+                                                   int chunk_len, int n_chunks, double pg_re, double pg_im,
+                                                   double* __restrict__ partial) {
   constexpr int RS = 4 + 2 * ND;
   constexpr int KM = MomCount<ND>::value;
   constexpr int RW = 3 * kMomCols + 1;  // LDS row stride (floats), odd against bank conflicts
@@ -387,6 +397,18 @@ __global__ void __launch_bounds__(256) k_full_mfma(const double* __restrict__ co
       }
     }
     __syncthreads();
+  }
+  // remove the mean bias of the hardware phasor: once in the phasors, once
+  // more in the block factors of detectors 1..
+  {
+    const double g2r = pg_re * pg_re - pg_im * pg_im, g2i = 2.0 * pg_re * pg_im;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const double gr = i == 0 ? pg_re : g2r, gi = i == 0 ? pg_im : g2i;
+      const double tr = zr[i] * gr - zi[i] * gi;
+      zi[i] = zr[i] * gi + zi[i] * gr;
+      zr[i] = tr;
+    }
   }
   if (p < n) {
 #pragma unroll
@@ -579,10 +601,11 @@ static gw_status launch_full_nd(gw_ctx* ctx, const double* coef, int64_t ld, int
   if (blocks > 0x7fffffff) return set_error(GW_EINVAL, "batch too large for one launch");
   if (prec == GW_PREC_FP64) {
     hipLaunchKernelGGL((k_full<ND, 0>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
-                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, partial);
+                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, 1.0, 0.0, partial);
   } else {
     hipLaunchKernelGGL((k_full<ND, 1>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
-                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, partial);
+                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, ctx->pgain_re, ctx->pgain_im,
+                       partial);
   }
   return check_hip(hipGetLastError(), "full-band kernel launch");
 }
@@ -599,7 +622,7 @@ static gw_status launch_mfma_nd(gw_ctx* ctx, const double* coef, int64_t ld, int
   if (blocks > 0x7fffffff) return set_error(GW_EINVAL, "batch too large for one launch");
   hipLaunchKernelGGL((k_full_mfma<ND>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
                      ctx->wtab, ctx->geom.k0, ctx->geom.df, nf, (int)ctx->mom_pad, blk, chunk_len, n_chunks,
-                     partial);
+                     ctx->pgain_re, ctx->pgain_im, partial);
   return check_hip(hipGetLastError(), "full-band matrix-core kernel launch");
 }
 
@@ -632,6 +655,62 @@ gw_status launch_full(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, in
     case 4: return launch_full_nd<4>(ctx, coef, ld, n, prec, tpb, n_chunks, partial, st);
     default: return set_error(GW_ENOTSUP, "n_det %d not supported", ctx->n_det);
   }
+}
+
+// Mean deviation of the FP32 hardware phasor g~ = cos(2 pi t) - i sin(2 pi t)
+// from the exact one g over n uniform midpoints t in [-1/2, 1/2): per block,
+// sum_i (g~_i conj(g_i) - 1), reduced in a fixed order.
+__global__ void __launch_bounds__(256) k_phasor_bias(int n, TrigConsts T, double* __restrict__ out) {
+  __shared__ double red[2][256];
+  double ar = 0.0, ai = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const float t = (float)(((double)i + 0.5) / (double)n - 0.5);
+    const double c = (double)__builtin_amdgcn_cosf(t), sn = (double)__builtin_amdgcn_sinf(t);
+    double se, ce;
+    sincos_cycles((double)t, T, &se, &ce);
+    // (c - i sn) (ce + i se)
+    ar += c * ce + sn * se - 1.0;
+    ai += c * se - sn * ce;
+  }
+  red[0][threadIdx.x] = ar;
+  red[1][threadIdx.x] = ai;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = red[0][0];
+    out[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+gw_status calibrate_phasor(gw_ctx* ctx) {
+  const int n = 1 << 20, blocks = 256;
+  double* d = nullptr;
+  gw_status s = check_hip(hipMalloc((void**)&d, 2 * blocks * sizeof(double)), "calibration buffer");
+  if (s != GW_OK) return s;
+  hipLaunchKernelGGL(k_phasor_bias, dim3(blocks), dim3(256), 0, nullptr, n, make_trig_consts(), d);
+  std::vector<double> h(2 * blocks);
+  s = check_hip(hipGetLastError(), "calibration launch");
+  if (s == GW_OK) s = check_hip(hipMemcpy(h.data(), d, h.size() * sizeof(double), hipMemcpyDeviceToHost), "copy");
+  (void)hipFree(d);
+  if (s != GW_OK) return s;
+  double br = 0.0, bi = 0.0;
+  for (int b = 0; b < blocks; ++b) {
+    br += h[2 * b];
+    bi += h[2 * b + 1];
+  }
+  br /= n;
+  bi /= n;
+  // 1 / (1 + b)
+  const double mr = 1.0 + br, m2 = mr * mr + bi * bi;
+  ctx->pgain_re = mr / m2;
+  ctx->pgain_im = -bi / m2;
+  return GW_OK;
 }
 
 // Block length: the largest power of two B in [8, 256] with

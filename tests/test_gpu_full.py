@@ -221,3 +221,13 @@ def test_large_batch_sliced_distance_marginal(cfg1):
         err = np.abs(got[idx] - ref)
         print(f"cfg1 9000-row batch prec={prec}: max|dlogL|={err.max():.3e}", flush=True)
         assert err.max() < TOL[prec]
+
+
+def test_phasor_calibration_is_small_and_stable(cfg1, gw):
+    # the measured hardware phasor bias is tiny (a few 1e-8) and reproducible
+    prob, ctx, _, _ = cfg1
+    g1 = gw.gw_phasor_gain(ctx.handle)
+    with gw.Context(prob) as c2:
+        g2 = gw.gw_phasor_gain(c2.handle)
+    print(f"phasor gain {g1}", flush=True)
+    assert abs(g1 - 1) < 1e-6 and g1 == g2
