@@ -204,6 +204,7 @@ gw_status gw_ctx_create(const gw_problem* pr, int32_t device, gw_ctx** out) {
       tab[4 * j + 1] = 1.0 / d;
       tab[4 * j + 2] = 0.5 / (d * d);
       tab[4 * j + 3] = pr->dist_logw[j];
+      ctx->dist_r1max = fmax(ctx->dist_r1max, 1.0 / d);
     }
     st = check_hip(hipMalloc((void**)&ctx->dist_tab, tab.size() * sizeof(double)), "dist alloc");
     if (st == GW_OK)

@@ -27,6 +27,7 @@ struct gw_ctx {
   // distance grid
   double* dist_tab = nullptr;      // [n_dist][4]: d, 1/d, 1/(2 d^2), ln w
   int32_t n_dist = 0;
+  double dist_r1max = 0.0;         // max_j 1/d_j
   std::vector<double> h_dist_grid, h_dist_logw;
   // host copies kept for heterodyne set-up
   std::vector<double> h_data_re, h_data_im, h_psd;

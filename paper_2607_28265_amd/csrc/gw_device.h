@@ -281,6 +281,7 @@ __device__ inline void sincos_cycles(double r, const TrigConsts& T, double* s_ou
 struct LogI0Consts {
   double ser[40];
   double asy[24];
+  double r1max;  // largest 1/d of the distance grid (bounds x = |Z1| / d); 0 if unknown
 };
 
 __host__ __device__ inline LogI0Consts make_log_i0_consts() {
@@ -295,7 +296,45 @@ __host__ __device__ inline LogI0Consts make_log_i0_consts() {
     if (k > 0) a *= (double)(2 * k - 1) * (double)(2 * k - 1) / (8.0 * k);
     c.asy[k] = a;
   }
+  c.r1max = 0.0;
   return c;
+}
+
+// Power series of I0 in y = x^2 / 4 truncated after K terms (Horner).
+template <int K>
+__device__ inline double i0_series(double y, const LogI0Consts& C) {
+  double p = C.ser[K - 1];
+#pragma unroll
+  for (int k = K - 2; k >= 0; --k) p = fma(p, y, C.ser[k]);
+  return p;
+}
+
+// Series length for every y <= ymax: the first dropped term y^K / (K!)^2 is
+// below 1e-17 (and I0 >= 1) for K = 8, 12, 16, 24 up to y = 0.106, 1.07, 4.00,
+// 18.8; otherwise the full 40 terms (enough for y <= 100, i.e. x < 20).
+__device__ inline int i0_tier(double ymax) {
+  return ymax <= 0.106 ? 0 : (ymax <= 1.07 ? 1 : (ymax <= 4.0 ? 2 : (ymax <= 18.8 ? 3 : 4)));
+}
+
+__device__ inline double i0_series_tier(int tier, double y, const LogI0Consts& C) {
+  switch (tier) {
+    case 0: return i0_series<8>(y, C);
+    case 1: return i0_series<12>(y, C);
+    case 2: return i0_series<16>(y, C);
+    case 3: return i0_series<24>(y, C);
+    default: return i0_series<40>(y, C);
+  }
+}
+
+// Wave-uniform series tier for arguments up to x = z1 * r1max (z1 may differ
+// between lanes): the largest need over the wave.
+__device__ inline int wave_i0_tier(double z1, const LogI0Consts& C) {
+  if (!(C.r1max > 0.0)) return 4;
+  const double x = z1 * C.r1max;
+  double y = 0.25 * x * x;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) y = fmax(y, __shfl_xor(y, o, 64));
+  return __builtin_amdgcn_readfirstlane(i0_tier(y));
 }
 
 // ln I0(x) given x and u = 1/x (u is only used when x >= 20).
@@ -361,6 +400,7 @@ __device__ inline double wave_dist_lse(double z1, double hh1, const double* __re
   const double bmax = wave_dist_bound(z1, hh1, tab, n_dist, lane);
   const double cut = bmax - 60.0;
   const double iz = z1 > 0.0 ? 1.0 / z1 : 0.0;
+  const int tier = wave_i0_tier(z1, C);
   double s = 0.0;
   for (int j = lane; j < n_dist; j += 64) {
     const double* r = tab + 4 * j;
@@ -369,11 +409,7 @@ __device__ inline double wave_dist_lse(double z1, double hh1, const double* __re
     if (a + x < cut) continue;
     double v, e;
     if (x < 20.0) {
-      const double y = 0.25 * x * x;
-      double p = C.ser[39];
-#pragma unroll
-      for (int k = 38; k >= 0; --k) p = fma(p, y, C.ser[k]);
-      v = p;
+      v = i0_series_tier(tier, 0.25 * x * x, C);
       e = a - bmax;
     } else {
       const double u = r[0] * iz;  // 1 / x
@@ -445,6 +481,7 @@ __device__ inline double slice_dist_sum(double z1, double hh1, double bmax, cons
                                         int j1, const LogI0Consts& C) {
   const double cut = bmax - 60.0;
   const double iz = z1 > 0.0 ? 1.0 / z1 : 0.0;
+  const int tier = wave_i0_tier(z1, C);
   double s = 0.0;
   for (int j = j0; j < j1; ++j) {
     const double* r = tab + 4 * j;
@@ -453,11 +490,7 @@ __device__ inline double slice_dist_sum(double z1, double hh1, double bmax, cons
     if (a + x < cut) continue;
     double v, e;
     if (x < 20.0) {
-      const double y = 0.25 * x * x;
-      double p = C.ser[39];
-#pragma unroll
-      for (int k = 38; k >= 0; --k) p = fma(p, y, C.ser[k]);
-      v = p;
+      v = i0_series_tier(tier, 0.25 * x * x, C);
       e = a - bmax;
     } else {
       const double u = r[0] * iz;  // 1 / x

@@ -782,7 +782,8 @@ gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, cons
                           int64_t n, int marg, int prec, double* logl, hipStream_t st) {
   if (n == 0) return GW_OK;
   const int64_t blocks = (n + 63) / 64;
-  const LogI0Consts C = make_log_i0_consts();
+  LogI0Consts C = make_log_i0_consts();
+  C.r1max = ctx->dist_r1max;
   hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(1024), 0, st, partial, n_chunks, ctx->n_det, coef, ld,
                      n, ctx->dd, marg, C, logl, ctx->zbuf);
   gw_status s = check_hip(hipGetLastError(), "epilogue launch");

@@ -714,7 +714,8 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
     hc.hh0[i] = h->hh0[i];
   }
   hc.dd = ctx->dd;
-  const LogI0Consts C = make_log_i0_consts();
+  LogI0Consts C = make_log_i0_consts();
+  C.r1max = ctx->dist_r1max;
   if (h->n_rows_last < kDistRowsPerLane && n_ech <= 64)
     hipLaunchKernelGGL(k_het_combine_w, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->n_det, n_ech,
                        marg, hc, C);
