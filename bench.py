@@ -366,6 +366,8 @@ def main():
                    "prec": "mixed"},
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": ach / PEAK_FP64_TFLOPS, "traffic": traffic_bytes(), "traffic_unit": "bytes/launch",
+                     "hbm_gbs": (traffic_bytes() / (k_mix * 1e-3) / 1e9) if traffic_bytes() else None,
+                     "hbm_peak_gbs": 8000.0,
                      "kernel": "k_full<3,1> (mixed)", "kernel_ms": k_mix,
                      "flops_per_launch": FLOPS_PER_BIN["mixed"] * units},
         "fp64_plain": {"value": fp_value, "ms_per_step": dt_fp / fp_steps * 1e3, "kernel_ms": k_fp,
