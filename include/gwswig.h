@@ -243,6 +243,45 @@ typedef struct {
 gw_status slice_step(gw_ctx* ctx, const gw_slice_args* args, void* stream);
 
 /*
+ * One Gibbs sweep (Sec. II.C Eq. block_cprior, Sec. III.B): every chain
+ * applies the slice update above to blocks 0 .. n_blocks - 1 in order, block b
+ * drawing its uniforms from Philox counter (counter + b, c, j / 4, 0).  Each
+ * chain's result is bit-for-bit that of n_blocks successive slice_step calls
+ * with counters counter, counter + 1, ... (same k, like, marg, prec and launch
+ * shapes), but a chain starts its next block as soon as it has finished one,
+ * so a sweep takes about the largest per-chain total of rounds instead of the
+ * sum over blocks of the largest per-block count.  The explicit uniforms
+ * table is not available here.  n_evals sums the likelihood calls over the
+ * sweep; status counts the blocks whose shrink cap was hit.
+ */
+typedef struct {
+  int64_t k;               /* number of chains */
+  double* x;               /* device [k, 11], updated in place */
+  double* logl;            /* device [k], updated in place */
+  double logl_star;        /* constraint log L* */
+  int32_t n_blocks;        /* 1 .. 16 */
+  const int32_t* block_dim;/* host [n_blocks], each 1 .. 4 */
+  const int32_t* block;    /* host [n_blocks, 4] coordinate indices, the first
+                              block_dim[b] of row b used, distinct, 0 .. 10 */
+  const double* chol;      /* host [n_blocks, 4, 4] lower Cholesky factor of
+                              each block, row-major, leading block_dim[b]
+                              rows and columns used */
+  uint64_t seed;           /* Philox key */
+  uint64_t counter;        /* counter base of block 0 */
+  double w;                /* bracket width along t (> 0) */
+  int32_t max_out;         /* >= 0 */
+  int32_t max_shrink;      /* 1 .. 10000 */
+  int32_t like;            /* GW_FULL or GW_HET */
+  int32_t marg;            /* GW_MARG_PHASE_DIST */
+  int32_t prec;            /* GW_PREC_FP64 or GW_PREC_MIXED */
+  int32_t* n_evals;        /* device [k] likelihood calls per chain, or NULL */
+  int32_t* status;         /* device [k] blocks kept at the shrink cap, or NULL */
+  int32_t use_graph;       /* as for slice_step */
+} gw_sweep_args;
+
+gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* args, void* stream);
+
+/*
  * The sampler's prior transform: unit-cube points x (device [n, 11], layout
  * as for slice_step) to parameter vectors theta (device [n, 13]; d_L = 1 and
  * phi_c = 0, both marginalised).  Used to evaluate a fresh live set.

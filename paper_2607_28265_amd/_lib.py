@@ -71,6 +71,30 @@ class gw_slice_args(ctypes.Structure):
     ]
 
 
+class gw_sweep_args(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int64),
+        ("x", ctypes.c_void_p),
+        ("logl", ctypes.c_void_p),
+        ("logl_star", ctypes.c_double),
+        ("n_blocks", ctypes.c_int32),
+        ("block_dim", ctypes.POINTER(ctypes.c_int32)),
+        ("block", ctypes.POINTER(ctypes.c_int32)),
+        ("chol", ctypes.POINTER(ctypes.c_double)),
+        ("seed", ctypes.c_uint64),
+        ("counter", ctypes.c_uint64),
+        ("w", ctypes.c_double),
+        ("max_out", ctypes.c_int32),
+        ("max_shrink", ctypes.c_int32),
+        ("like", ctypes.c_int32),
+        ("marg", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("n_evals", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+        ("use_graph", ctypes.c_int32),
+    ]
+
+
 _LIB = None
 
 _P = ctypes.c_void_p
@@ -95,6 +119,7 @@ _SIGS = {
                                    _P]),
     "gw_graph_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "slice_step": (ctypes.c_int, [_P, ctypes.POINTER(gw_slice_args), _P]),
+    "slice_sweep": (ctypes.c_int, [_P, ctypes.POINTER(gw_sweep_args), _P]),
     "gw_prior_transform": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     "gw_set_full_kernel": (ctypes.c_int, [_P, ctypes.c_int32]),
     "gw_full_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
@@ -353,6 +378,50 @@ def slice_step(ctx, x, logl, logl_star: float, block, chol, seed: int = 0, count
                       prec=int(prec), n_evals=n_evals.data_ptr() if n_evals is not None else None,
                       status=status.data_ptr() if status is not None else None, use_graph=1 if use_graph else 0)
     check(load().slice_step(ctx, ctypes.byref(a), _stream_ptr(stream)), "slice_step")
+
+
+def _check_chains(x, logl, n_evals, status):
+    import torch
+    if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == 11):
+        raise ValueError("x must be a contiguous CUDA float64 tensor of shape [k, 11]")
+    k = x.shape[0]
+    if not (logl.is_cuda and logl.dtype == torch.float64 and logl.is_contiguous() and logl.numel() == k):
+        raise ValueError("logl must be a contiguous CUDA float64 tensor with k entries")
+    for t in (n_evals, status):
+        if t is not None and not (t.is_cuda and t.dtype == torch.int32 and t.numel() == k and t.is_contiguous()):
+            raise ValueError("n_evals / status must be contiguous CUDA int32 tensors with k entries")
+    return k
+
+
+def slice_sweep(ctx, x, logl, logl_star: float, blocks, chols, seed: int = 0, counter: int = 0, w: float = 1.0,
+                max_out: int = 10, max_shrink: int = 100, like: int = GW_HET, marg: int = GW_MARG_PHASE_DIST,
+                prec: int = GW_PREC_FP64, n_evals=None, status=None, stream=None, use_graph: bool = True):
+    """One sweep over ``blocks`` (list of index lists, with their Cholesky
+    factors ``chols``) for every chain, block b with Philox counter
+    counter + b; x [k, 11] and logl [k] change in place."""
+    import numpy as np
+    k = _check_chains(x, logl, n_evals, status)
+    nb = len(blocks)
+    if not 1 <= nb <= 16 or len(chols) != nb:
+        raise ValueError("1..16 blocks, one Cholesky factor each")
+    bd = np.zeros(nb, np.int32)
+    blk = np.zeros((nb, 4), np.int32)
+    ch = np.zeros((nb, 4, 4), np.float64)
+    for b, (idx, L) in enumerate(zip(blocks, chols)):
+        idx = np.asarray(idx, dtype=np.int32).ravel()
+        if not 1 <= idx.size <= 4:
+            raise ValueError("each block has 1..4 coordinates")
+        bd[b] = idx.size
+        blk[b, :idx.size] = idx
+        ch[b, :idx.size, :idx.size] = np.asarray(L, dtype=np.float64).reshape(idx.size, idx.size)
+    a = gw_sweep_args(k=k, x=x.data_ptr(), logl=logl.data_ptr(), logl_star=float(logl_star), n_blocks=nb,
+                      block_dim=bd.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                      block=blk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                      chol=ch.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), seed=int(seed), counter=int(counter),
+                      w=float(w), max_out=int(max_out), max_shrink=int(max_shrink), like=int(like), marg=int(marg),
+                      prec=int(prec), n_evals=n_evals.data_ptr() if n_evals is not None else None,
+                      status=status.data_ptr() if status is not None else None, use_graph=1 if use_graph else 0)
+    check(load().slice_sweep(ctx, ctypes.byref(a), _stream_ptr(stream)), "slice_sweep")
 
 
 def gw_prior_transform(ctx, x, stream=None):

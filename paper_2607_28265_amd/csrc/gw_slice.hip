@@ -1,13 +1,15 @@
-// Constrained hit-and-run slice step over k chains for one Gibbs block
-// (Sec. II.C and III.B, Eq. block_cprior).  Each chain moves its block of
-// unit-cube coordinates along t -> x + t d with d = L u (u a random unit
-// vector, L the Cholesky factor of the block covariance), stepping the
-// bracket out while its ends satisfy log L > log L*, then shrinking it until a
-// point inside the constraint is found.  Chains advance in rounds: a propose
-// kernel writes every chain's candidate points as parameter vectors, the
-// batched likelihood evaluates them all, and an update kernel moves each
-// chain's state machine; the host checks for completion every few rounds.
+// Constrained hit-and-run slice moves over k chains (Sec. II.C and III.B,
+// Eq. block_cprior).  Each chain moves one Gibbs block of unit-cube
+// coordinates along t -> x + t d with d = L u (u a random unit vector, L the
+// Cholesky factor of the block covariance), stepping the bracket out while its
+// ends satisfy log L > log L*, then shrinking it until a point inside the
+// constraint is found; a sweep takes the blocks in order.  Chains advance in
+// rounds: a propose kernel writes every chain's candidate points as parameter
+// vectors, the batched likelihood evaluates them all, and an update kernel
+// moves each chain's state machine (to its next block once one is done); the
+// host checks for completion every few rounds.
 #include <math.h>
+#include <stdint.h>
 #include <string.h>
 
 #include <vector>
@@ -17,25 +19,25 @@
 namespace gw {
 
 constexpr int kSliceDim = 11;
-constexpr int kMaxBlock = 4;
-constexpr int kUniFixed = 5;  // 4 direction + 1 bracket offset
+constexpr int kMaxBlock = 4;    // coordinates per block
+constexpr int kMaxBlocks = 16;  // blocks per sweep
+constexpr int kUniFixed = 5;    // 4 direction + 1 bracket offset
 
-struct SliceParams {
-  int32_t block[kMaxBlock];
-  double chol[kMaxBlock * kMaxBlock];
-  int32_t bd;
+// One sweep: every chain visits blocks b = 0 .. nb - 1 in order, block b with
+// Philox counter (counter + b).  Chains are independent, so a chain starts its
+// next block as soon as it finishes one; each chain's moves are exactly those
+// of nb successive one-block steps.  A single slice_step is the nb = 1 case.
+struct SweepParams {
+  int32_t nb;
+  int32_t bd[kMaxBlocks];
+  int32_t block[kMaxBlocks][kMaxBlock];
+  double chol[kMaxBlocks][kMaxBlock * kMaxBlock];
   double w;
   double logl_star;
   int32_t max_out, max_shrink;
   uint64_t seed, counter;
-  const double* uniforms;  // [k][kUniFixed + max_shrink] or null
+  const double* uniforms;  // one-block calls: [k][kUniFixed + max_shrink], or null
   int64_t k;
-};
-
-// Parameters of one call as a device block, so that a captured graph of the
-// round loop reads them at replay time instead of baking them in.
-struct SliceDev {
-  SliceParams P;
   double* x;
   double* logl;
 };
@@ -46,11 +48,14 @@ struct SliceState {
   double* t_hi;
   double* d;        // [k][kMaxBlock]
   double* cand_t;   // [k][2]
-  int32_t* flags;   // [k]: bit0 lo stepping, bit1 hi stepping, bit2 done, bit3 kept (cap hit)
+  int32_t* flags;   // [k]: bit0 lo stepping, bit1 hi stepping, bit2 sweep done
   int32_t* n_out;   // [k][2]
   int32_t* n_shrink;
-  int32_t* n_evals;
+  int32_t* n_evals;  // likelihood calls in the current block
   int32_t* slot_ok;  // [k][2]: candidate inside the cube and needs a likelihood
+  int32_t* cur;      // current block
+  int32_t* tot_evals;
+  int32_t* n_caps;   // blocks whose shrink cap was hit
   int32_t* n_active;
 };
 
@@ -72,11 +77,11 @@ __device__ inline void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
   }
 }
 
-// Uniform j of chain c: explicit table, or Philox word j % 4 of counter
-// (counter_base, c, j / 4, 0) under key (seed, 0), mapped to (0, 1).
-__device__ inline double slice_uniform(const SliceParams& P, int64_t c, int j) {
+// Uniform j of chain c in block b: explicit table, or Philox word j % 4 of
+// counter (counter_base + b, c, j / 4, 0) under key (seed, 0), mapped to (0, 1).
+__device__ inline double slice_uniform(const SweepParams& P, int b, int64_t c, int j) {
   if (P.uniforms) return P.uniforms[c * (kUniFixed + P.max_shrink) + j];
-  uint64_t ctr[4] = {P.counter, (uint64_t)c, (uint64_t)(j >> 2), 0ull};
+  uint64_t ctr[4] = {P.counter + (uint64_t)b, (uint64_t)c, (uint64_t)(j >> 2), 0ull};
   philox4x64(ctr, P.seed, 0ull);
   return ((double)(ctr[j & 3] >> 11) + 0.5) * 1.1102230246251565404e-16;  // 2^-53
 }
@@ -97,42 +102,54 @@ __device__ inline void prior_transform(const double* u, double* th) {
   th[12] = -0.1 + 0.2 * u[10];
 }
 
-__global__ void k_slice_init(SliceParams P, SliceState S) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= P.k) return;
+// Start block b for chain c: direction d = L u (u from Box-Muller normals of
+// uniforms 0..3, normalised), bracket [-r w, (1 - r) w] with r = uniform 4.
+// Returns the chain's new flags.
+__device__ inline int start_block(const SweepParams& P, const SliceState& S, int64_t c, int b) {
   double u[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) u[j] = slice_uniform(P, c, j);
+  for (int j = 0; j < 4; ++j) u[j] = slice_uniform(P, b, c, j);
   const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
   double s0, c0, s1, c1;
   sincos(kTwoPi * u[1], &s0, &c0);
   sincos(kTwoPi * u[3], &s1, &c1);
-  double z[4] = {r0 * c0, r0 * s0, r1 * c1, r1 * s1};
+  const double z[4] = {r0 * c0, r0 * s0, r1 * c1, r1 * s1};
+  const int bd = P.bd[b];
   double nrm = 0.0;
-  for (int j = 0; j < P.bd; ++j) nrm += z[j] * z[j];
+  for (int j = 0; j < bd; ++j) nrm += z[j] * z[j];
   nrm = sqrt(nrm);
   for (int a = 0; a < kMaxBlock; ++a) {
     double v = 0.0;
-    for (int b = 0; b < P.bd; ++b)
-      if (a < P.bd) v += P.chol[a * kMaxBlock + b] * (z[b] / nrm);
-    S.d[c * kMaxBlock + a] = a < P.bd ? v : 0.0;
+    for (int q = 0; q < bd; ++q)
+      if (a < bd) v += P.chol[b][a * kMaxBlock + q] * (z[q] / nrm);
+    S.d[c * kMaxBlock + a] = a < bd ? v : 0.0;
   }
-  const double off = slice_uniform(P, c, 4);
+  const double off = slice_uniform(P, b, c, 4);
   S.t_lo[c] = -off * P.w;
   S.t_hi[c] = (1.0 - off) * P.w;
-  S.flags[c] = P.max_out > 0 ? 3 : 0;
   S.n_out[2 * c] = 0;
   S.n_out[2 * c + 1] = 0;
   S.n_shrink[c] = 0;
   S.n_evals[c] = 0;
+  S.cur[c] = b;
+  return P.max_out > 0 ? 3 : 0;
 }
 
-__device__ inline bool make_point(const SliceParams& P, const SliceState& S, const double* x0, int64_t c, double t,
-                                  double* u) {
+// The current block of chain c ends (moved, or kept when capped): count it
+// and start the next block, or mark the sweep done.  Returns the new flags.
+__device__ inline int finish_block(const SweepParams& P, const SliceState& S, int64_t c, bool capped) {
+  S.tot_evals[c] += S.n_evals[c];
+  if (capped) S.n_caps[c] += 1;
+  const int b = S.cur[c] + 1;
+  return b < P.nb ? start_block(P, S, c, b) : 4;
+}
+
+__device__ inline bool make_point(const SweepParams& P, int b, const SliceState& S, const double* x0, int64_t c,
+                                  double t, double* u) {
   for (int j = 0; j < kSliceDim; ++j) u[j] = x0[c * kSliceDim + j];
   bool inside = true;
-  for (int a = 0; a < P.bd; ++a) {
-    const int j = P.block[a];
+  for (int a = 0; a < P.bd[b]; ++a) {
+    const int j = P.block[b][a];
     const double v = x0[c * kSliceDim + j] + t * S.d[c * kMaxBlock + a];
     inside = inside && v >= 0.0 && v <= 1.0;
     u[j] = v;
@@ -140,30 +157,38 @@ __device__ inline bool make_point(const SliceParams& P, const SliceState& S, con
   return inside;
 }
 
+__global__ void k_sweep_set(SweepParams* D, SweepParams P) { *D = P; }
+
+__global__ void k_sweep_init(const SweepParams* __restrict__ D, SliceState S) {
+  const SweepParams& P = *D;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.k) return;
+  S.tot_evals[c] = 0;
+  S.n_caps[c] = 0;
+  S.flags[c] = start_block(P, S, c, 0);
+}
+
 // Write the candidates of every chain that is still moving: the two bracket
 // ends while stepping out, else one shrink draw (points outside the cube
 // count as rejections immediately, without a likelihood call).
-__global__ void k_slice_set(SliceDev* D, SliceParams P, double* x, double* logl) {
-  D->P = P;
-  D->x = x;
-  D->logl = logl;
-}
-
-__global__ void k_slice_propose(const SliceDev* __restrict__ D, SliceState S, double* __restrict__ cand) {
-  const SliceParams& P = D->P;
-  const double* __restrict__ x0 = D->x;
+__global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S, double* __restrict__ cand) {
+  const SweepParams& P = *D;
+  const double* __restrict__ x0 = P.x;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c == 0) *S.n_active = 0;
   if (c >= P.k) return;
   int fl = S.flags[c];
   double u[kSliceDim];
   int ok[2] = {0, 0};
-  if (!(fl & 4)) {
+  // a block whose shrink draws all leave the cube ends here without a call;
+  // the next block (if any) then proposes in the same round
+  for (int guard = 0; guard <= kMaxBlocks && !(fl & 4) && !ok[0] && !ok[1]; ++guard) {
+    const int b = S.cur[c];
     if (fl & 3) {
       for (int side = 0; side < 2; ++side) {
         if (!(fl & (1 << side))) continue;
         const double t = side == 0 ? S.t_lo[c] : S.t_hi[c];
-        if (make_point(P, S, x0, c, t, u)) {
+        if (make_point(P, b, S, x0, c, t, u)) {
           prior_transform(u, cand + (2 * c + side) * 13);
           S.cand_t[2 * c + side] = t;
           ok[side] = 1;
@@ -176,9 +201,9 @@ __global__ void k_slice_propose(const SliceDev* __restrict__ D, SliceState S, do
       // shrinking: draw until a point lies in the cube (no likelihood needed
       // for the others) or the cap is reached
       while (S.n_shrink[c] < P.max_shrink) {
-        const double v = slice_uniform(P, c, kUniFixed + S.n_shrink[c]);
+        const double v = slice_uniform(P, b, c, kUniFixed + S.n_shrink[c]);
         const double t = S.t_lo[c] + v * (S.t_hi[c] - S.t_lo[c]);
-        if (make_point(P, S, x0, c, t, u)) {
+        if (make_point(P, b, S, x0, c, t, u)) {
           prior_transform(u, cand + 2 * c * 13);
           S.cand_t[2 * c] = t;
           ok[0] = 1;
@@ -188,7 +213,7 @@ __global__ void k_slice_propose(const SliceDev* __restrict__ D, SliceState S, do
         else S.t_hi[c] = t;
         S.n_shrink[c] += 1;
       }
-      if (!ok[0]) fl |= 12;  // cap reached: keep the old point
+      if (!ok[0]) fl = finish_block(P, S, c, true);  // cap reached: keep the point
     }
   }
   // rows that need no likelihood get an unphysical vector (cheap -inf)
@@ -203,14 +228,15 @@ __global__ void k_slice_propose(const SliceDev* __restrict__ D, SliceState S, do
   S.flags[c] = fl;
 }
 
-__global__ void k_slice_update(const SliceDev* __restrict__ D, SliceState S, const double* __restrict__ cand_logl) {
-  const SliceParams& P = D->P;
-  double* __restrict__ x = D->x;
-  double* __restrict__ logl = D->logl;
+__global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, const double* __restrict__ cand_logl) {
+  const SweepParams& P = *D;
+  double* __restrict__ x = P.x;
+  double* __restrict__ logl = P.logl;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P.k) return;
   int fl = S.flags[c];
   if (fl & 4) return;
+  const int b = S.cur[c];
   const bool stepping = (fl & 3) != 0;
   if (stepping) {
     for (int side = 0; side < 2; ++side) {
@@ -233,17 +259,17 @@ __global__ void k_slice_update(const SliceDev* __restrict__ D, SliceState S, con
     const double v = cand_logl[2 * c];
     const double t = S.cand_t[2 * c];
     if (v > P.logl_star) {
-      for (int a = 0; a < P.bd; ++a) {
-        const int j = P.block[a];
+      for (int a = 0; a < P.bd[b]; ++a) {
+        const int j = P.block[b][a];
         x[c * kSliceDim + j] += t * S.d[c * kMaxBlock + a];
       }
       logl[c] = v;
-      fl |= 4;
+      fl = finish_block(P, S, c, false);
     } else {
       if (t < 0.0) S.t_lo[c] = t;
       else S.t_hi[c] = t;
       S.n_shrink[c] += 1;
-      if (S.n_shrink[c] >= P.max_shrink) fl |= 12;
+      if (S.n_shrink[c] >= P.max_shrink) fl = finish_block(P, S, c, true);
     }
   }
   S.flags[c] = fl;
@@ -255,11 +281,11 @@ __global__ void k_prior_transform(const double* __restrict__ x, int64_t n, doubl
   if (i < n) prior_transform(x + i * kSliceDim, theta + i * 13);
 }
 
-__global__ void k_slice_finish(SliceParams P, SliceState S, int32_t* n_evals, int32_t* status) {
+__global__ void k_sweep_finish(const SweepParams* __restrict__ D, SliceState S, int32_t* n_evals, int32_t* status) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= P.k) return;
-  if (n_evals) n_evals[c] = S.n_evals[c];
-  if (status) status[c] = (S.flags[c] & 8) ? 1 : 0;
+  if (c >= D->k) return;
+  if (n_evals) n_evals[c] = S.tot_evals[c];
+  if (status) status[c] = S.n_caps[c];
 }
 
 }  // namespace gw
@@ -282,7 +308,7 @@ struct gw_slice_ws {
   double* cand_logl = nullptr;  // [2k]
   int32_t* h_active = nullptr;  // pinned host
   SliceState S{};
-  SliceDev* dev = nullptr;      // device parameter block
+  SweepParams* dev = nullptr;   // device parameter block
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -292,20 +318,26 @@ struct gw_slice_ws {
 
 static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out);
 
+struct SweepCall {
+  int32_t like, marg, prec, use_graph;
+  int32_t* n_evals;
+  int32_t* status;
+};
+
 // Capture one round group into a graph (re-captured when anything it bakes in
 // changes) on the workspace's own capture stream.  Buffers the likelihood
 // would grow are reserved first: no allocation may happen during capture.
 template <class Group>
-static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, const gw_slice_args* a, Group group) {
-  const int64_t n = 2 * a->k;
-  gw_status s = a->like == GW_HET ? het_reserve(ctx, n) : full_reserve(ctx, n);
+static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const SweepCall& a, Group group) {
+  const int64_t n = 2 * k;
+  gw_status s = a.like == GW_HET ? het_reserve(ctx, n) : full_reserve(ctx, n);
   if (s != GW_OK) return s;
   SliceGraphKey key;
   memset(&key, 0, sizeof(key));
-  key.k = a->k;
-  key.like = a->like;
-  key.marg = a->marg;
-  key.prec = a->prec;
+  key.k = k;
+  key.like = a.like;
+  key.marg = a.marg;
+  key.prec = a.prec;
   key.ws_mem = ws->mem;
   key.coef = ctx->coef;
   key.partial = ctx->partial;
@@ -346,39 +378,107 @@ static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, const gw_slice_args* 
   return GW_OK;
 }
 
+// Validation shared by both entry points.
+static gw_status check_sweep(const char* who, int64_t k, const double* x, const double* logl, double w,
+                             int32_t max_out, int32_t max_shrink, int32_t like, int32_t marg, const gw_ctx* ctx) {
+  if (k < 0) return set_error(GW_EINVAL, "%s: k < 0", who);
+  if (k > 0 && (!x || !logl)) return set_error(GW_EINVAL, "%s: null pointer", who);
+  if (!(w > 0.0) || !isfinite(w)) return set_error(GW_EINVAL, "%s: w must be > 0", who);
+  if (max_out < 0 || max_shrink < 1 || max_shrink > 10000)
+    return set_error(GW_EINVAL, "%s: max_out >= 0, max_shrink 1..10000", who);
+  if (marg == GW_MARG_NONE)
+    return set_error(GW_ENOTSUP, "%s: the 11-D sampler needs phi_c and d_L marginalised (marg=2)", who);
+  if (marg != GW_MARG_PHASE_DIST)
+    return set_error(GW_ENOTSUP, "%s: marg must be GW_MARG_PHASE_DIST", who);
+  if (like != GW_FULL && like != GW_HET)
+    return set_error(GW_EINVAL, "%s: like must be GW_FULL or GW_HET", who);
+  if (like == GW_HET && !ctx->het)
+    return set_error(GW_ESTATE, "%s: heterodyne_setup has not been called", who);
+  return GW_OK;
+}
+
+// Check one block (indices distinct in 0..10, 1..4 of them) and copy its
+// lower Cholesky factor (row-major, stride ``ld``) into P's padded slot.
+static gw_status set_block(const char* who, SweepParams& P, int b, const int32_t* idx, int32_t bd, const double* L,
+                           int ld) {
+  if (bd < 1 || bd > kMaxBlock)
+    return set_error(GW_EINVAL, "%s: block %d: block_dim 1..4", who, b);
+  for (int i = 0; i < bd; ++i) {
+    if (idx[i] < 0 || idx[i] >= kSliceDim)
+      return set_error(GW_EINVAL, "%s: block %d: index 0..10", who, b);
+    for (int j = 0; j < i; ++j)
+      if (idx[j] == idx[i])
+        return set_error(GW_EINVAL, "%s: block %d: repeated index", who, b);
+  }
+  P.bd[b] = bd;
+  for (int i = 0; i < kMaxBlock; ++i) P.block[b][i] = i < bd ? idx[i] : 0;
+  for (int i = 0; i < kMaxBlock * kMaxBlock; ++i) P.chol[b][i] = 0.0;
+  for (int i = 0; i < bd; ++i)
+    for (int j = 0; j <= i; ++j) P.chol[b][i * kMaxBlock + j] = L[i * ld + j];
+  return GW_OK;
+}
+
+// Run one sweep of P.nb blocks for all chains to completion.
+static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a, hipStream_t st) {
+  gw_status s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+  if (s != GW_OK) return s;
+  gw_slice_ws* ws = nullptr;
+  s = slice_ws(ctx, P.k, &ws);
+  if (s != GW_OK) return s;
+  const int64_t k = P.k;
+  const int tpb = 256;
+  const unsigned blocks = (unsigned)((k + tpb - 1) / tpb);
+  hipLaunchKernelGGL(k_sweep_set, dim3(1), dim3(1), 0, st, ws->dev, P);
+  hipLaunchKernelGGL(k_sweep_init, dim3(blocks), dim3(tpb), 0, st, (const SweepParams*)ws->dev, ws->S);
+  s = check_hip(hipGetLastError(), "slice init launch");
+  // One group = 4 rounds of (propose, batched likelihood, update); after a
+  // group the host reads the number of chains still moving.  A block takes at
+  // most max_out + 1 stepping rounds (both sides in parallel) and max_shrink
+  // shrink rounds, so after max_rounds every chain is done and further rounds
+  // change nothing.
+  const int max_rounds = P.nb * (P.max_out + 1 + P.max_shrink + 1);
+  auto group = [&](hipStream_t gs) -> gw_status {
+    gw_status g = GW_OK;
+    for (int r = 0; r < 4 && g == GW_OK; ++r) {
+      hipLaunchKernelGGL(k_sweep_propose, dim3(blocks), dim3(tpb), 0, gs, (const SweepParams*)ws->dev, ws->S,
+                         ws->cand);
+      g = check_hip(hipGetLastError(), "slice propose launch");
+      if (g == GW_OK) g = loglike_batch(ctx, ws->cand, 2 * k, a.like, a.marg, a.prec, ws->cand_logl, gs);
+      if (g == GW_OK) {
+        hipLaunchKernelGGL(k_sweep_update, dim3(blocks), dim3(tpb), 0, gs, (const SweepParams*)ws->dev, ws->S,
+                           (const double*)ws->cand_logl);
+        g = check_hip(hipGetLastError(), "slice update launch");
+      }
+    }
+    return g;
+  };
+  if (s == GW_OK && a.use_graph) s = slice_graph(ctx, ws, k, a, group);
+  for (int rounds = 0; s == GW_OK && rounds < max_rounds; rounds += 4) {
+    if (a.use_graph) s = check_hip(hipGraphLaunch(ws->exec, st), "slice graph launch");
+    else s = group(st);
+    if (s != GW_OK) break;
+    s = check_hip(hipMemcpyAsync(ws->h_active, ws->S.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
+    if (s == GW_OK) s = check_hip(hipStreamSynchronize(st), "slice round sync");
+    if (s == GW_OK && *ws->h_active == 0) break;
+  }
+  if (s != GW_OK) return s;
+  hipLaunchKernelGGL(k_sweep_finish, dim3(blocks), dim3(tpb), 0, st, (const SweepParams*)ws->dev, ws->S, a.n_evals,
+                     a.status);
+  return check_hip(hipGetLastError(), "slice finish launch");
+}
+
 extern "C" {
 
 gw_status slice_step(gw_ctx* ctx, const gw_slice_args* a, void* stream) {
   if (!ctx || !a) return set_error(GW_EINVAL, "slice_step: null argument");
-  if (a->k < 0) return set_error(GW_EINVAL, "slice_step: k < 0");
   if (a->k == 0) return GW_OK;
-  if (!a->x || !a->logl || !a->block || !a->chol) return set_error(GW_EINVAL, "slice_step: null pointer");
-  if (a->block_dim < 1 || a->block_dim > kMaxBlock) return set_error(GW_EINVAL, "slice_step: block_dim 1..4");
-  for (int i = 0; i < a->block_dim; ++i) {
-    if (a->block[i] < 0 || a->block[i] >= kSliceDim) return set_error(GW_EINVAL, "slice_step: block index 0..10");
-    for (int j = 0; j < i; ++j)
-      if (a->block[j] == a->block[i]) return set_error(GW_EINVAL, "slice_step: repeated block index");
-  }
-  if (!(a->w > 0.0) || !isfinite(a->w)) return set_error(GW_EINVAL, "slice_step: w must be > 0");
-  if (a->max_out < 0 || a->max_shrink < 1 || a->max_shrink > 10000)
-    return set_error(GW_EINVAL, "slice_step: max_out >= 0, max_shrink 1..10000");
-  if (a->marg == GW_MARG_NONE)
-    return set_error(GW_ENOTSUP, "slice_step: the 11-D sampler needs phi_c and d_L marginalised (marg=2)");
-  if (a->marg != GW_MARG_PHASE_DIST) return set_error(GW_ENOTSUP, "slice_step: marg must be GW_MARG_PHASE_DIST");
-  if (a->like == GW_HET && !ctx->het) return set_error(GW_ESTATE, "slice_step: heterodyne_setup has not been called");
-  hipStream_t st = (hipStream_t)stream;
-  gw_status s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+  gw_status s = check_sweep("slice_step", a->k, a->x, a->logl, a->w, a->max_out, a->max_shrink, a->like, a->marg, ctx);
+  if (s != GW_OK || a->k == 0) return s;
+  if (!a->block || !a->chol) return set_error(GW_EINVAL, "slice_step: null pointer");
+  SweepParams P{};
+  s = set_block("slice_step", P, 0, a->block, a->block_dim, a->chol, a->block_dim);
   if (s != GW_OK) return s;
-  gw_slice_ws* ws = nullptr;
-  s = slice_ws(ctx, a->k, &ws);
-  if (s != GW_OK) return s;
-
-  SliceParams P{};
-  for (int i = 0; i < kMaxBlock; ++i) P.block[i] = i < a->block_dim ? a->block[i] : 0;
-  for (int i = 0; i < kMaxBlock * kMaxBlock; ++i) P.chol[i] = 0.0;
-  for (int i = 0; i < a->block_dim; ++i)
-    for (int j = 0; j <= i; ++j) P.chol[i * kMaxBlock + j] = a->chol[i * a->block_dim + j];
-  P.bd = a->block_dim;
+  P.nb = 1;
   P.w = a->w;
   P.logl_star = a->logl_star;
   P.max_out = a->max_out;
@@ -387,43 +487,41 @@ gw_status slice_step(gw_ctx* ctx, const gw_slice_args* a, void* stream) {
   P.counter = a->counter;
   P.uniforms = a->uniforms;
   P.k = a->k;
-  const int tpb = 256;
-  const unsigned blocks = (unsigned)((a->k + tpb - 1) / tpb);
-  hipLaunchKernelGGL(k_slice_set, dim3(1), dim3(1), 0, st, ws->dev, P, a->x, a->logl);
-  hipLaunchKernelGGL(k_slice_init, dim3(blocks), dim3(tpb), 0, st, P, ws->S);
-  s = check_hip(hipGetLastError(), "slice init launch");
-  // One group = 4 rounds of (propose, batched likelihood, update); after a
-  // group the host reads the number of chains still moving.  Stepping out
-  // takes at most max_out + 1 rounds per side (both sides in parallel) and
-  // shrinking at most max_shrink, so after max_rounds every chain is done and
-  // further rounds change nothing.
-  const int max_rounds = a->max_out + 1 + a->max_shrink + 1;
-  auto group = [&](hipStream_t gs) -> gw_status {
-    gw_status g = GW_OK;
-    for (int r = 0; r < 4 && g == GW_OK; ++r) {
-      hipLaunchKernelGGL(k_slice_propose, dim3(blocks), dim3(tpb), 0, gs, (const SliceDev*)ws->dev, ws->S, ws->cand);
-      g = check_hip(hipGetLastError(), "slice propose launch");
-      if (g == GW_OK) g = loglike_batch(ctx, ws->cand, 2 * a->k, a->like, a->marg, a->prec, ws->cand_logl, gs);
-      if (g == GW_OK) {
-        hipLaunchKernelGGL(k_slice_update, dim3(blocks), dim3(tpb), 0, gs, (const SliceDev*)ws->dev, ws->S,
-                           (const double*)ws->cand_logl);
-        g = check_hip(hipGetLastError(), "slice update launch");
-      }
-    }
-    return g;
-  };
-  if (s == GW_OK && a->use_graph) s = slice_graph(ctx, ws, a, group);
-  for (int rounds = 0; s == GW_OK && rounds < max_rounds; rounds += 4) {
-    if (a->use_graph) s = check_hip(hipGraphLaunch(ws->exec, st), "slice graph launch");
-    else s = group(st);
-    if (s != GW_OK) break;
-    s = check_hip(hipMemcpyAsync(ws->h_active, ws->S.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-    if (s == GW_OK) s = check_hip(hipStreamSynchronize(st), "slice round sync");
-    if (s == GW_OK && *ws->h_active == 0) break;
+  P.x = a->x;
+  P.logl = a->logl;
+  const SweepCall c{a->like, a->marg, a->prec, a->use_graph, a->n_evals, a->status};
+  return run_sweep(ctx, P, c, (hipStream_t)stream);
+}
+
+gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* a, void* stream) {
+  if (!ctx || !a) return set_error(GW_EINVAL, "slice_sweep: null argument");
+  if (a->k == 0) return GW_OK;
+  gw_status s = check_sweep("slice_sweep", a->k, a->x, a->logl, a->w, a->max_out, a->max_shrink, a->like, a->marg,
+                            ctx);
+  if (s != GW_OK || a->k == 0) return s;
+  if (a->n_blocks < 1 || a->n_blocks > kMaxBlocks) return set_error(GW_EINVAL, "slice_sweep: n_blocks 1..16");
+  if (!a->block_dim || !a->block || !a->chol) return set_error(GW_EINVAL, "slice_sweep: null pointer");
+  if (a->counter > UINT64_MAX - (uint64_t)a->n_blocks)
+    return set_error(GW_EINVAL, "slice_sweep: counter + n_blocks overflows");
+  SweepParams P{};
+  for (int b = 0; b < a->n_blocks; ++b) {
+    s = set_block("slice_sweep", P, b, a->block + b * kMaxBlock, a->block_dim[b], a->chol + b * kMaxBlock * kMaxBlock,
+                  kMaxBlock);
+    if (s != GW_OK) return s;
   }
-  if (s != GW_OK) return s;
-  hipLaunchKernelGGL(k_slice_finish, dim3(blocks), dim3(tpb), 0, st, P, ws->S, a->n_evals, a->status);
-  return check_hip(hipGetLastError(), "slice finish launch");
+  P.nb = a->n_blocks;
+  P.w = a->w;
+  P.logl_star = a->logl_star;
+  P.max_out = a->max_out;
+  P.max_shrink = a->max_shrink;
+  P.seed = a->seed;
+  P.counter = a->counter;
+  P.uniforms = nullptr;
+  P.k = a->k;
+  P.x = a->x;
+  P.logl = a->logl;
+  const SweepCall c{a->like, a->marg, a->prec, a->use_graph, a->n_evals, a->status};
+  return run_sweep(ctx, P, c, (hipStream_t)stream);
 }
 
 gw_status gw_prior_transform(gw_ctx* ctx, const double* x, int64_t n, double* theta, void* stream) {
@@ -447,7 +545,7 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
     if (!ws) return set_error(GW_ENOMEM, "slice workspace");
     if (hipHostMalloc((void**)&ws->h_active, sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
       return set_error(GW_ENOMEM, "slice pinned flag");
-    if (hipMalloc((void**)&ws->dev, sizeof(SliceDev)) != hipSuccess) return set_error(GW_ENOMEM, "slice parameters");
+    if (hipMalloc((void**)&ws->dev, sizeof(SweepParams)) != hipSuccess) return set_error(GW_ENOMEM, "slice parameters");
   }
   if (ws->cap >= k) {
     *out = ws;
@@ -457,9 +555,9 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
   ws->mem = nullptr;
   ws->cap = 0;
   // doubles: t_lo, t_hi, d[4], cand_t[2], cand[26], cand_logl[2]; ints: flags, n_out[2], n_shrink, n_evals,
-  // slot_ok[2], then the active counter
+  // slot_ok[2], cur, tot_evals, n_caps, then the active counter
   const size_t nd = (size_t)k * (1 + 1 + kMaxBlock + 2 + 26 + 2);
-  const size_t ni = (size_t)k * (1 + 2 + 1 + 1 + 2) + 1;
+  const size_t ni = (size_t)k * (1 + 2 + 1 + 1 + 2 + 3) + 1;
   char* m = nullptr;
   gw_status s = check_hip(hipMalloc((void**)&m, nd * sizeof(double) + ni * sizeof(int32_t)), "slice workspace");
   if (s != GW_OK) return s;
@@ -476,6 +574,9 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
   ws->S.n_shrink = ip; ip += k;
   ws->S.n_evals = ip; ip += k;
   ws->S.slot_ok = ip; ip += 2 * k;
+  ws->S.cur = ip; ip += k;
+  ws->S.tot_evals = ip; ip += k;
+  ws->S.n_caps = ip; ip += k;
   ws->S.n_active = ip;
   ws->mem = m;
   ws->cap = k;

@@ -5,8 +5,12 @@ points, raises log L* to the largest deleted value, accumulates their prior
 volume into the evidence and replaces them by constrained draws.  Sec. II.C /
 III.B: a replacement starts from a surviving live point and runs M Gibbs
 sweeps over the parameter blocks, each block moved by one hit-and-run slice
-step on the GPU (``slice_step``, all k chains at once) along directions from
-the block covariance of the live points.
+step on the GPU along directions from the block covariance of the live
+points.  By default a whole sweep is one ``slice_sweep`` call, in which each
+chain moves on to its next block as soon as it has finished one; with
+``async_sweep=False`` every block is a ``slice_step`` call of its own (all
+chains finish the block before any starts the next).  Both give the same
+chains bit for bit.
 
 The host keeps the FP64 evidence bookkeeping (the k deletions taken in order
 with live counts m, m-1, ..., m-k+1), the start-point choice and the block
@@ -41,7 +45,7 @@ def _logsumexp(a):
 class NestedSampler:
     def __init__(self, ctx, n_live: int = 1000, n_delete: int = 125, seed: int = 6, dlogz: float = 0.1,
                  blocks=BLOCKS, like: int = _lib.GW_HET, prec: int = _lib.GW_PREC_MIXED, sweeps: int = 1,
-                 w: float = 1.0, max_out: int = 10, max_shrink: int = 100):
+                 w: float = 1.0, max_out: int = 10, max_shrink: int = 100, async_sweep: bool = True):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -51,6 +55,7 @@ class NestedSampler:
         self.blocks = tuple(tuple(b) for b in blocks)
         self.like, self.prec = like, prec
         self.sweeps, self.w, self.max_out, self.max_shrink = sweeps, w, max_out, max_shrink
+        self.async_sweep = bool(async_sweep)
         self.rng = np.random.default_rng(self.seed)
         self.dev = torch.device("cuda", ctx.device)
         x0 = self.rng.uniform(size=(self.m, N_DIM))
@@ -118,6 +123,13 @@ class NestedSampler:
         ln = self.logl.index_select(0, idx).contiguous()
         ne = torch.zeros(self.k, dtype=torch.int32, device=self.dev)
         for _ in range(self.sweeps):
+            if self.async_sweep:
+                _lib.slice_sweep(self.ctx.handle, xn, ln, lstar, self.blocks, chols, seed=self.seed,
+                                 counter=self.counter, w=self.w, max_out=self.max_out, max_shrink=self.max_shrink,
+                                 like=self.like, marg=_lib.GW_MARG_PHASE_DIST, prec=self.prec, n_evals=ne)
+                self.n_evals += int(ne.sum().item())
+                self.counter += len(self.blocks)
+                continue
             for bi, b in enumerate(self.blocks):
                 _lib.slice_step(self.ctx.handle, xn, ln, lstar, b, chols[bi], seed=self.seed, counter=self.counter,
                                 w=self.w, max_out=self.max_out, max_shrink=self.max_shrink, like=self.like,

@@ -25,7 +25,7 @@ def golden(name):
         return json.load(f)
 
 
-def run(name, prec, max_iter=100000, checkpoint_at=None, path=None):
+def run(name, prec, max_iter=100000, checkpoint_at=None, path=None, async_sweep=True):
     import paper_2607_28265_amd as gw
     from paper_2607_28265_amd.nested import NestedSampler
     g = golden(name)
@@ -33,7 +33,7 @@ def run(name, prec, max_iter=100000, checkpoint_at=None, path=None):
     with gw.Context(prob) as ctx:
         ctx.heterodyne_setup(prob.theta_inj, g["n_bins"])
         ns = NestedSampler(ctx, n_live=g["n_live"], n_delete=g["n_delete"], seed=g["seed"], dlogz=g["dlogz"],
-                           like=gw.GW_HET, prec=prec)
+                           like=gw.GW_HET, prec=prec, async_sweep=async_sweep)
         if checkpoint_at is not None:
             ns.run(max_iter=checkpoint_at)
             ns.save(path)
@@ -66,3 +66,14 @@ def test_checkpoint_resume_is_exact(tmp_path):
     b = run("cfg1", gw.GW_PREC_MIXED, max_iter=90, checkpoint_at=40, path=path)
     assert a["iterations"] == b["iterations"] == 90
     assert a["log_z"] == b["log_z"] and a["n_evals"] == b["n_evals"]
+
+
+def test_async_sweep_equals_block_by_block():
+    # one slice_sweep call per sweep or one slice_step call per block: the
+    # same chains, so the same run
+    import paper_2607_28265_amd as gw
+    a = run("cfg1", gw.GW_PREC_MIXED, max_iter=60, async_sweep=True)
+    b = run("cfg1", gw.GW_PREC_MIXED, max_iter=60, async_sweep=False)
+    print(f"async {a['wall_s']:.2f} s, block by block {b['wall_s']:.2f} s")
+    assert a["iterations"] == b["iterations"] == 60
+    assert a["log_z"] == b["log_z"] and a["n_evals"] == b["n_evals"] and a["h"] == b["h"]

@@ -136,3 +136,69 @@ def test_graph_replay_equals_eager(setup, like):
                          like=like) for g in (False, True)]
         for a, b in zip(*outs):
             assert np.array_equal(a, b), (call, bi)
+
+
+@pytest.mark.parametrize("like,prec", [(1, 0), (1, 1), (0, 1)])
+def test_sweep_equals_sequential_steps(setup, like, prec):
+    # a chain's moves in one sweep are those of successive one-block steps
+    # with counters counter, counter + 1, ...: bit-identical, although chains
+    # start their next block at different rounds
+    gw, ctx, prob, het, loglike_u, x, logl = setup
+    lstar = float(np.quantile(logl, 0.25))
+    keep = logl > lstar
+    xs, ls = x[keep], logl[keep]
+    blocks = list(S.BLOCKS)
+    chols = [S.block_cholesky(x, b) for b in blocks]
+    seed, counter = 17, 500
+    k = len(xs)
+    xa = torch.from_numpy(xs.copy()).cuda()
+    la = torch.from_numpy(ls.copy()).cuda()
+    nea = torch.zeros(k, dtype=torch.int32, device="cuda")
+    sta = torch.zeros(k, dtype=torch.int32, device="cuda")
+    gw.slice_sweep(ctx.handle, xa, la, lstar, blocks, chols, seed=seed, counter=counter, w=1.0, max_out=4,
+                   max_shrink=60, like=like, marg=gw.GW_MARG_PHASE_DIST, prec=prec, n_evals=nea, status=sta)
+    xb = torch.from_numpy(xs.copy()).cuda()
+    lb = torch.from_numpy(ls.copy()).cuda()
+    ne_sum = np.zeros(k, np.int64)
+    st_sum = np.zeros(k, np.int64)
+    for b, (blk, ch) in enumerate(zip(blocks, chols)):
+        ne = torch.zeros(k, dtype=torch.int32, device="cuda")
+        st = torch.zeros(k, dtype=torch.int32, device="cuda")
+        gw.slice_step(ctx.handle, xb, lb, lstar, blk, ch, seed=seed, counter=counter + b, w=1.0, max_out=4,
+                      max_shrink=60, like=like, marg=gw.GW_MARG_PHASE_DIST, prec=prec, n_evals=ne, status=st)
+        ne_sum += ne.cpu().numpy()
+        st_sum += st.cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(xa.cpu().numpy(), xb.cpu().numpy())
+    assert np.array_equal(la.cpu().numpy(), lb.cpu().numpy())
+    assert np.array_equal(nea.cpu().numpy(), ne_sum)
+    assert np.array_equal(sta.cpu().numpy(), st_sum)
+    assert np.all(la.cpu().numpy() > lstar)
+    print(f"like {like} prec {prec}: {k} chains, {int(ne_sum.sum())} evals, {int(st_sum.sum())} capped blocks")
+
+
+def test_sweep_one_block_equals_step_and_errors(setup):
+    gw, ctx, prob, het, loglike_u, x, logl = setup
+    lstar = float(np.quantile(logl, 0.3))
+    keep = logl > lstar
+    xs, ls = x[keep], logl[keep]
+    blk = S.BLOCKS[0]
+    ch = S.block_cholesky(x, blk)
+    a = _run_gpu(gw, ctx, xs, ls, lstar, blk, ch, None, 3, 77, 60, 4, prec=1)
+    xt = torch.from_numpy(xs.copy()).cuda()
+    lt = torch.from_numpy(ls.copy()).cuda()
+    ne = torch.zeros(len(xs), dtype=torch.int32, device="cuda")
+    st = torch.zeros(len(xs), dtype=torch.int32, device="cuda")
+    gw.slice_sweep(ctx.handle, xt, lt, lstar, [blk], [ch], seed=3, counter=77, w=1.0, max_out=4, max_shrink=60,
+                   like=gw.GW_HET, marg=gw.GW_MARG_PHASE_DIST, prec=1, n_evals=ne, status=st)
+    torch.cuda.synchronize()
+    for u, v in zip(a, (xt.cpu().numpy(), lt.cpu().numpy(), ne.cpu().numpy(), st.cpu().numpy())):
+        assert np.array_equal(u, v)
+    with pytest.raises(gw.GwError):
+        gw.slice_sweep(ctx.handle, xt, lt, lstar, [[0, 0]], [np.eye(2)])  # repeated index
+    with pytest.raises(gw.GwError):
+        gw.slice_sweep(ctx.handle, xt, lt, lstar, [[0], [11]], [np.eye(1), np.eye(1)])  # out of range
+    with pytest.raises(gw.GwError):
+        gw.slice_sweep(ctx.handle, xt, lt, lstar, [[0]], [np.eye(1)], marg=gw.GW_MARG_PHASE)
+    with pytest.raises(ValueError):
+        gw.slice_sweep(ctx.handle, xt, lt, lstar, [[0]] * 17, [np.eye(1)] * 17)
