@@ -61,8 +61,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="full,het,nested,prescreen",
-                    help="comma list of legs to run: full (always timed), het, nested, prescreen, copy")
+    ap.add_argument("--legs", default="full,het,cache,nested,nested_full,prescreen",
+                    help="comma list of legs to run: full (always timed), het, cache, nested, nested_full, "
+                         "prescreen, copy")
     return ap.parse_args()
 
 
@@ -277,6 +278,114 @@ def nested_leg(gw, torch):
     return out
 
 
+def cache_leg(gw, torch, prob, steps, warmup, mixed_value):
+    """Waveform cache (the sampler's fast/slow split): 4096 rows on 2048
+    cached waveforms of the 128 s grid (two rows per slot, as the sampler's
+    two bracket ends), moved in sky position, t_c, psi, iota and d_L (kind 1:
+    the cached waveform re-summed with new delays) or in psi, iota and d_L
+    only (kind 2: cached overlaps reprojected), against the slow update that
+    generates and stores the 2048 waveforms."""
+    import numpy as np
+    import gwsynth
+    n_slots, n = 2048, 4096
+    base = gwsynth.prior_draws(gwsynth.SEEDS["prior"], n_slots)
+    rows = np.repeat(np.arange(n_slots), 2)
+    rng = np.random.default_rng(51)
+    res = {}
+    with gw.Context(prob) as ctx:
+        cache = gw.WaveformCache(ctx.handle, n_slots)
+        slots_b = torch.arange(n_slots, dtype=torch.int32, device="cuda")
+        tb = torch.from_numpy(base).cuda()
+        lb = torch.empty(n_slots, dtype=torch.float64, device="cuda")
+        for _ in range(max(1, warmup // 2)):
+            cache.update(tb, slots_b, prec=gw.GW_PREC_MIXED, out=lb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(3, steps // 5)
+        for _ in range(reps):
+            cache.update(tb, slots_b, prec=gw.GW_PREC_MIXED, out=lb)
+        torch.cuda.synchronize()
+        dt_up = (time.perf_counter() - t0) / reps
+        res["update"] = {"value": n_slots / dt_up, "ms_per_call": dt_up * 1e3, "rows": n_slots}
+        slots = torch.from_numpy(rows.astype(np.int32)).cuda()
+        for kind in (1, 2):
+            th = base[rows].copy()
+            th[:, 7] = np.clip(th[:, 7] + 0.05 * rng.standard_normal(n), 0.01, np.pi - 0.01)
+            th[:, 10] = np.mod(th[:, 10] + 0.1 * rng.standard_normal(n), np.pi)
+            if kind == 1:
+                th[:, 8] = np.mod(th[:, 8] + 0.02 * rng.standard_normal(n), 2 * np.pi)
+                th[:, 9] = np.clip(th[:, 9] + 0.02 * rng.standard_normal(n), -1.5, 1.5)
+                th[:, 12] += 1e-3 * rng.standard_normal(n)
+            tt = torch.from_numpy(th).cuda()
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+            for _ in range(warmup):
+                cache.loglike(tt, slots, kind, prec=gw.GW_PREC_MIXED, out=out)
+            torch.cuda.synchronize()
+            if kind == 1:
+                gw._lib.gw_profile_read(ctx.handle)
+                gw._lib.gw_profile_enable(ctx.handle, True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                cache.loglike(tt, slots, kind, prec=gw.GW_PREC_MIXED, out=out)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            r = {"value": n / dt, "ms_per_call": dt * 1e3, "speedup_vs_full_mixed": n / dt / mixed_value}
+            if kind == 1:
+                ms, nl = gw._lib.gw_profile_read(ctx.handle)
+                gw._lib.gw_profile_enable(ctx.handle, False)
+                k_ms = ms / max(nl, 1)
+                f2 = (prob.n_freq + 15) // 16 * 16
+                # algorithmic HBM bytes: each used waveform once (8 B per bin) plus the
+                # weighted data of the 3 detectors (48 B per bin)
+                nbytes = n_slots * f2 * 8 + prob.n_freq * 48
+                flops = n * prob.n_freq * 3 * 14
+                r["kernel"] = "k_stream<3>"
+                r["kernel_ms"] = k_ms
+                r["roofline"] = {"bound": "hbm", "achieved": nbytes / (k_ms * 1e-3) / 1e9, "peak": 8000.0,
+                                 "unit": "GB/s", "frac": nbytes / (k_ms * 1e-3) / 1e9 / 8000.0,
+                                 "bytes_per_launch": nbytes,
+                                 "fp64_tflops": flops / (k_ms * 1e-3) / 1e12,
+                                 "fp64_frac": flops / (k_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+            res[f"kind{kind}"] = r
+        cache.close()
+    res["unit"] = "logL evals/s"
+    res["workload"] = ("waveform cache on the 128 s grid: 2048 cached waveforms, 4096 rows (two per slot); "
+                       "kind 1 = sky/t_c/psi/iota/d_L moves on the cached waveform, kind 2 = psi/iota/d_L moves "
+                       "on the cached overlaps; phase+distance marginalised")
+    return res
+
+
+def nested_full_leg(gw, torch):
+    """Nested sampling on the full band (128 s, 259,585 bins per detector,
+    mixed form), settings as the heterodyned run, with and without the
+    waveform cache of the fast blocks."""
+    import gwsynth
+    from paper_2607_28265_amd import prescreen as P
+    from paper_2607_28265_amd.nested import NestedSampler
+    cfg = gwsynth.CONFIGS["cfg2"]
+    prob = gwsynth.make_problem(cfg["duration"], cfg["f_min"], cfg["f_max"], psd_scale=1e-49)
+    th = gwsynth.prior_draws(gwsynth.SEEDS["injection"], 1)[0]
+    th_inj = P.library_injection(gw.Context, prob, th, snr=24.0)
+    out = {}
+    with gw.Context(prob) as ctx:
+        for cache in (False, True):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ns = NestedSampler(ctx, n_live=1000, n_delete=125, seed=gwsynth.SEEDS["sampler"], like=gw.GW_FULL,
+                               prec=gw.GW_PREC_MIXED, cache=cache)
+            r = ns.run()
+            wall = time.perf_counter() - t0
+            d = {"wall_s": wall, "log_z": r["log_z"], "log_z_err": r["log_z_err"], "iterations": r["iterations"],
+                 "n_evals": r["n_evals"]}
+            if cache:
+                d["evals_full_cachedwaveform_cachedsums"] = r["eval_kinds"]
+            out["cache" if cache else "no_cache"] = d
+    out["workload"] = ("nested sampling on the full band: 1000 live points, 125 deletions, 7 Gibbs blocks, "
+                       "128 s at 259,585 bins per detector, mixed form, phase+distance marginalised, dlogz 0.1, "
+                       "SNR-24 injection")
+    return out
+
+
 def copy_leg(torch, reps=5, mib=256):
     """A plain device copy of known size, the reference for the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of the kernels above."""
@@ -378,8 +487,12 @@ def main():
     legs = set(args.legs.split(","))
     if "het" in legs:
         res["heterodyned"] = het_leg(gw, torch, prob, th_inj, max(5, args.steps // 2), 2)
+    if "cache" in legs:
+        res["waveform_cache"] = cache_leg(gw, torch, prob, args.steps, args.warmup, value)
     if "nested" in legs:
         res["nested_sampling"] = nested_leg(gw, torch)
+    if "nested_full" in legs:
+        res["nested_sampling_full_band"] = nested_full_leg(gw, torch)
     if "prescreen" in legs:
         res["prescreen"] = prescreen_leg(gw, torch, 10)
     if "copy" in legs:

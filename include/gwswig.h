@@ -277,9 +277,34 @@ typedef struct {
   int32_t* n_evals;        /* device [k] likelihood calls per chain, or NULL */
   int32_t* status;         /* device [k] blocks kept at the shrink cap, or NULL */
   int32_t use_graph;       /* as for slice_step */
+  int32_t use_cache;       /* 1 (like = GW_FULL only): fast/slow waveform
+                              cache, below */
+  int64_t* eval_kinds;     /* host [3] or NULL: with the cache, likelihood
+                              evaluations of the sweep in full (waveform
+                              generated, seeding included), from the cached
+                              waveform, and from the cached sums; -1 each
+                              without the cache.  Synchronises the stream. */
 } gw_sweep_args;
 
 gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* args, void* stream);
+/*
+ * Waveform cache (Sec. III.B: slow blocks regenerate the waveform, fast
+ * blocks reuse a cached one and only redo the projection).  With use_cache a
+ * block whose coordinates are all among {iota, psi} is projection-only: its
+ * candidates reuse the overlaps z_i of the chain's current point and cost
+ * O(1); a block among {iota, ra, dec, psi, t_c} is extrinsic: its candidates
+ * reuse the chain's cached waveform, held as block moments (see
+ * gw_wcache_loglike, kind 1), and only the detector delays change; any other
+ * block evaluates in full (prec as given).  Each sweep first evaluates every
+ * chain's current point in full to seed the overlaps (k extra evaluations,
+ * not counted in n_evals).  A chain's waveform is rebuilt lazily: when it is
+ * in an extrinsic block after a slow move (or at the start of the sweep), that
+ * round's candidates evaluate in full and the rebuild follows the round.
+ * Device memory: k x (n_freq / B) x n_det x 16 x 8 bytes (B the moment block,
+ * 256 bins at df = 1/128 Hz), at most 64 GiB, kept with the context.  Results
+ * agree with use_cache = 0 to rounding, so a near tie with log L* can resolve
+ * differently.
+ */
 
 /*
  * The sampler's prior transform: unit-cube points x (device [n, 11], layout
@@ -287,6 +312,48 @@ gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* args, void* stream);
  * phi_c = 0, both marginalised).  Used to evaluate a fresh live set.
  */
 gw_status gw_prior_transform(gw_ctx* ctx, const double* x, int64_t n, double* theta, void* stream);
+
+/*
+ * Waveform cache (Sec. III.B, Sec. III.A): the slow / fast likelihood pair.
+ * A slot holds one point's overlaps z_i = sum_k u_ik exp(-2 pi i Phi_ik)
+ * and its intrinsic waveform g_k = exp(-2 pi i Psi(f_k)) (Psi the TaylorF2
+ * phase without the linear time term) as block moments: for blocks of B bins
+ * with centre f_c and t_j = (j - (B - 1)/2) / (B/2),
+ *     M_m = sum_j t_j^m u_ij g_j,   m < 16   (FP64 sums stored as FP32),
+ * so that a delay tau_i contributes
+ *     exp(-2 pi i f_c tau_i) sum_m (-i pi df B tau_i)^m / m! M_m
+ * per block.  B is the largest power of two up to 512 with
+ * pi df B 0.25 s <= 1.61 (256 at df = 1/128 Hz), which keeps the first
+ * dropped term below 1e-10 of the block's sum of |u g| for |tau_i| <= 0.25 s.
+ *
+ * gw_wcache_update (slow): full-band log L of theta (device [n, 13]; marg,
+ *   prec as for loglike_batch) into logl (device [n]), and row r's overlaps
+ *   and moments into slot slots[r] (device int32 [n]).  When a slot appears
+ *   more than once the largest row index wins; a slot outside 0 .. n_slots-1
+ *   stores nothing and gives log L = NaN.
+ * gw_wcache_loglike (fast): log L of rows that differ from the point of
+ *   their slot slots[r] only in extrinsic parameters, without generating a
+ *   waveform:
+ *     kind 1: ra, dec, psi, iota, t_c (and d_L) may differ; the moments are
+ *             summed with each detector's delay t_c + dt_i (16 terms per
+ *             block, FP64 arithmetic); rows with |t_c + dt_i| > 0.25 s get
+ *             NaN;
+ *     kind 2: only psi, iota (and d_L) may differ; the cached overlaps are
+ *             reprojected, O(1) per row.
+ *   Intrinsic parameters (Mc, q, chi1, chi2, Lambda1, Lambda2) and, for
+ *   marg = GW_MARG_NONE, phi_c must equal the slot's; nothing checks this.
+ *   Slots outside 0 .. n_slots-1 give log L = NaN.
+ * Device memory: n_slots x (n_freq / B) x n_det x 128 bytes (at most
+ * 128 GiB) plus the overlaps.  Errors as loglike_batch; GW_EINVAL for kind
+ * not 1 or 2.
+ */
+typedef struct gw_wcache gw_wcache;
+gw_status gw_wcache_create(gw_ctx* ctx, int64_t n_slots, gw_wcache** out);
+gw_status gw_wcache_destroy(gw_wcache* cache);
+gw_status gw_wcache_update(gw_wcache* cache, const double* theta, const int32_t* slots, int64_t n, int32_t marg,
+                           int32_t prec, double* logl, void* stream);
+gw_status gw_wcache_loglike(gw_wcache* cache, const double* theta, const int32_t* slots, int64_t n, int32_t kind,
+                            int32_t marg, int32_t prec, double* logl, void* stream);
 
 /*
  * Learned prescreen (not part of the paper's method, which uses exact

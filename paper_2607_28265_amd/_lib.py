@@ -92,6 +92,8 @@ class gw_sweep_args(ctypes.Structure):
         ("n_evals", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
         ("use_graph", ctypes.c_int32),
+        ("use_cache", ctypes.c_int32),
+        ("eval_kinds", ctypes.POINTER(ctypes.c_int64)),
     ]
 
 
@@ -120,6 +122,11 @@ _SIGS = {
     "gw_graph_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "slice_step": (ctypes.c_int, [_P, ctypes.POINTER(gw_slice_args), _P]),
     "slice_sweep": (ctypes.c_int, [_P, ctypes.POINTER(gw_sweep_args), _P]),
+    "gw_wcache_create": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(_P)]),
+    "gw_wcache_destroy": (ctypes.c_int, [_P]),
+    "gw_wcache_update": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "gw_wcache_loglike": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         _P, _P]),
     "gw_prior_transform": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     "gw_set_full_kernel": (ctypes.c_int, [_P, ctypes.c_int32]),
     "gw_full_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
@@ -395,10 +402,13 @@ def _check_chains(x, logl, n_evals, status):
 
 def slice_sweep(ctx, x, logl, logl_star: float, blocks, chols, seed: int = 0, counter: int = 0, w: float = 1.0,
                 max_out: int = 10, max_shrink: int = 100, like: int = GW_HET, marg: int = GW_MARG_PHASE_DIST,
-                prec: int = GW_PREC_FP64, n_evals=None, status=None, stream=None, use_graph: bool = True):
+                prec: int = GW_PREC_FP64, n_evals=None, status=None, stream=None, use_graph: bool = True,
+                use_cache: bool = False):
     """One sweep over ``blocks`` (list of index lists, with their Cholesky
     factors ``chols``) for every chain, block b with Philox counter
-    counter + b; x [k, 11] and logl [k] change in place."""
+    counter + b; x [k, 11] and logl [k] change in place.  Returns the
+    evaluations by kind (full, cached waveform, cached sums) with the
+    waveform cache, else None."""
     import numpy as np
     k = _check_chains(x, logl, n_evals, status)
     nb = len(blocks)
@@ -420,8 +430,13 @@ def slice_sweep(ctx, x, logl, logl_star: float, blocks, chols, seed: int = 0, co
                       chol=ch.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), seed=int(seed), counter=int(counter),
                       w=float(w), max_out=int(max_out), max_shrink=int(max_shrink), like=int(like), marg=int(marg),
                       prec=int(prec), n_evals=n_evals.data_ptr() if n_evals is not None else None,
-                      status=status.data_ptr() if status is not None else None, use_graph=1 if use_graph else 0)
+                      status=status.data_ptr() if status is not None else None, use_graph=1 if use_graph else 0,
+                      use_cache=1 if use_cache else 0)
+    kinds = (ctypes.c_int64 * 3)()
+    if use_cache:
+        a.eval_kinds = kinds
     check(load().slice_sweep(ctx, ctypes.byref(a), _stream_ptr(stream)), "slice_sweep")
+    return (kinds[0], kinds[1], kinds[2]) if use_cache else None
 
 
 def gw_prior_transform(ctx, x, stream=None):
@@ -529,3 +544,52 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+class WaveformCache:
+    """Slow / fast likelihood pair over ``n_slots`` cached waveforms (see
+    gw_wcache_* in gwswig.h).  Slots are CUDA int32 tensors; parameter
+    vectors CUDA float64 [n, 13]."""
+
+    def __init__(self, ctx, n_slots: int):
+        h = _P()
+        check(load().gw_wcache_create(ctx, int(n_slots), ctypes.byref(h)), "gw_wcache_create")
+        self._h = h
+        self.n_slots = int(n_slots)
+
+    def close(self):
+        if self._h:
+            load().gw_wcache_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _args(theta, slots, out):
+        import torch
+        _check_theta(theta)
+        n = theta.shape[0]
+        if not (slots.is_cuda and slots.dtype == torch.int32 and slots.is_contiguous() and slots.numel() == n):
+            raise ValueError("slots must be a contiguous CUDA int32 tensor with one entry per row")
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=theta.device)
+        elif not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= n):
+            raise ValueError("out must be a contiguous CUDA float64 tensor with at least n elements")
+        return n, out
+
+    def update(self, theta, slots, marg: int = GW_MARG_PHASE_DIST, prec: int = GW_PREC_FP64, out=None, stream=None):
+        n, out = self._args(theta, slots, out)
+        check(load().gw_wcache_update(self._h, _tensor_ptr(theta), slots.data_ptr(), n, marg, prec, out.data_ptr(),
+                                      _stream_ptr(stream)), "gw_wcache_update")
+        return out
+
+    def loglike(self, theta, slots, kind: int, marg: int = GW_MARG_PHASE_DIST, prec: int = GW_PREC_FP64, out=None,
+                stream=None):
+        n, out = self._args(theta, slots, out)
+        check(load().gw_wcache_loglike(self._h, _tensor_ptr(theta), slots.data_ptr(), n, int(kind), marg, prec,
+                                       out.data_ptr(), _stream_ptr(stream)), "gw_wcache_loglike")
+        return out

@@ -71,10 +71,38 @@ gw_status launch_prologue(gw_ctx* ctx, const double* theta, int64_t n, int marg,
                           int64_t ld, hipStream_t st);
 gw_status launch_full(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec,
                       int tpb, int n_chunks, double* partial, hipStream_t st);
-gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, const double* coef,
+// The partials may be overwritten (small batches reduce them in place first).
+gw_status launch_epilogue(gw_ctx* ctx, double* partial, int n_chunks, const double* coef,
                           int64_t ld, int64_t n, int marg, int prec, double* logl, hipStream_t st);
 gw_status launch_template(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, double* h,
                           hipStream_t st);
+// Waveform-cache forms (fast/slow blocks of the sampler).  A cache slot holds
+// the block moments of one intrinsic waveform (float2 [n_blk][n_det][16],
+// wmom_slot_f2 entries; block length wmom_block bins).  launch_cached runs the
+// full reduction on rows slow_rows[0 .. counts[0]) (none when slow_rows is
+// NULL) into partials of n_chunks chunks and row stride n (coefficients with
+// ld = n), and, when mom is not NULL, the moment reduction on rows
+// fast_rows[0 .. counts[1]) (row p uses slot slot_of[p], or p / rows_per_slot
+// when slot_of is NULL), whose complete sums go to zfast[p][2 n_det] (rows
+// whose |t_c + dt_i| exceeds the cache's range get NaN).
+// launch_epilogue_cached combines partials (rows with zsrc[p] >= 0 take their
+// sums from zc[zsrc[p]]) and writes every row's sums to zrow when not NULL.
+// launch_wmom_build rebuilds the slots slots[i] >= 0, i < *count, from
+// coefficient row src[i] (slot * rows_per_slot when src is NULL).
+int wmom_block(const gw_ctx* ctx);
+int64_t wmom_slot_f2(const gw_ctx* ctx);
+gw_status launch_cached(gw_ctx* ctx, const double* coef, int64_t n, int prec, int tpb, int n_chunks,
+                        const int32_t* slow_rows, const int32_t* fast_rows, const int32_t* counts, int rows_per_slot,
+                        const int32_t* slot_of, const float2* mom, double* zfast, double* partial, hipStream_t st);
+gw_status launch_epilogue_cached(gw_ctx* ctx, double* partial, int n_chunks, const double* coef, int64_t ld,
+                                 int64_t n, int marg, int prec, double* logl, const int32_t* zsrc, const double* zc,
+                                 double* zrow, hipStream_t st);
+gw_status launch_wmom_build(gw_ctx* ctx, const double* coef, int64_t ld, const int32_t* slots, const int32_t* count,
+                            int rows_per_slot, const int32_t* src, float2* mom, hipStream_t st);
+// Cached-likelihood launch shape (64 rows per workgroup, chunks of ~512 bins)
+// and the workspace it needs for n rows.
+void cached_shape(const gw_ctx* ctx, int* tpb, int* nch);
+gw_status cached_reserve(gw_ctx* ctx, int64_t n);
 void full_launch_shape(const gw_ctx* ctx, int64_t n, int* tpb, int* n_chunks);
 // Block-moment table of the matrix-core reduction from the per-bin records
 // (host [n_freq][4 + 2 n_det]); leaves the form unavailable (mom_blk = 0) when

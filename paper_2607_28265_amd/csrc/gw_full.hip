@@ -44,6 +44,33 @@ __device__ inline void decode_block(int bid, int nptile, int n_chunks, int* chun
   }
 }
 
+// Add the sums of waves 1 .. W-1 (W <= 4) of the workgroup to wave 0's, in
+// wave order (lane l of every wave holds row l); true on wave 0, which then
+// owns them.
+template <int ND>
+__device__ inline bool wave_sums_combine(double* zr, double* zi) {
+  __shared__ double red[3][2 * ND][64];
+  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (nw == 1) return true;
+  if (wv > 0) {
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      red[wv - 1][2 * i][lane] = zr[i];
+      red[wv - 1][2 * i + 1][lane] = zi[i];
+    }
+  }
+  __syncthreads();
+  if (wv != 0) return false;
+  for (int w = 0; w < nw - 1; ++w) {
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      zr[i] += red[w][2 * i][lane];
+      zi[i] += red[w][2 * i + 1][lane];
+    }
+  }
+  return true;
+}
+
 template <int PREC>
 __device__ inline void phasor(double r, const TrigConsts& T, double* gr, double* gi) {
   if (PREC == 0) {
@@ -60,18 +87,36 @@ __device__ inline void phasor(double r, const TrigConsts& T, double* gr, double*
   }
 }
 
-template <int ND, int PREC>
+// LIST (small batches, e.g. the sampler's rounds): the rows are
+// rows[0 .. *count) (at most n, in any order) instead of 0 .. n - 1, 64 to a
+// workgroup, and the workgroup's waves split the chunk's bins between them
+// (each with its own start phase), their sums added in wave order; workgroups
+// past the count exit at once.
+template <int ND, int PREC, bool LIST>
 __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, int64_t ld, int64_t n,
                                               const double* __restrict__ bins, int64_t k0, double df,
                                               int n_freq, int chunk_len, int n_chunks, TrigConsts T, double pg_re,
-                                              double pg_im, double* __restrict__ partial) {
+                                              double pg_im, const int32_t* __restrict__ rows,
+                                              const int32_t* __restrict__ count, double* __restrict__ partial) {
   constexpr int RS = 4 + 2 * ND;
-  const int tpb = blockDim.x;
+  const int tpb = LIST ? 64 : blockDim.x;
   const int nptile = (int)((n + tpb - 1) / tpb);
   int chunk, ptile;
   decode_block(blockIdx.x, nptile, n_chunks, &chunk, &ptile);
-  const int64_t p = (int64_t)ptile * tpb + threadIdx.x;
-  const int64_t pc = p < n ? p : n - 1;
+  int64_t p, pc;
+  bool live;
+  if constexpr (LIST) {
+    const int cnt = *count;
+    if (ptile * tpb >= cnt) return;  // uniform over the workgroup
+    const int idx = ptile * tpb + (threadIdx.x & 63);
+    live = idx < cnt;
+    p = rows[live ? idx : cnt - 1];
+    pc = p;
+  } else {
+    p = (int64_t)ptile * tpb + threadIdx.x;
+    pc = p < n ? p : n - 1;
+    live = p < n;
+  }
 
   PhaseCoef c;
   c.a0 = coef[C_A0 * ld + pc];
@@ -87,8 +132,16 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
   c.b5 = coef[C_B5 * ld + pc];
   c.b6 = coef[C_B6 * ld + pc];
 
-  const int kb = chunk * chunk_len;
-  const int ke = kb + chunk_len < n_freq ? kb + chunk_len : n_freq;
+  int kb = chunk * chunk_len;
+  int ke = kb + chunk_len < n_freq ? kb + chunk_len : n_freq;
+  if constexpr (LIST) {
+    // wave index made visibly wave-uniform, so that the bin walk stays scalar
+    const int nw = blockDim.x >> 6, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sub = ((ke > kb ? ke - kb : 0) + nw - 1) / nw;
+    const int b2 = kb + wv * sub;
+    ke = b2 + sub < ke ? b2 + sub : ke;
+    kb = b2;
+  }
 
   double zr[ND], zi[ND];
   double rr[ND], ri[ND];  // rho_i
@@ -177,13 +230,238 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
       zr[i] = tr;
     }
   }
-  if (p < n) {
+  if constexpr (LIST) {
+    if (!wave_sums_combine<ND>(zr, zi)) return;
+  }
+  if (live) {
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
       partial[((int64_t)chunk * 2 * ND + 2 * i) * n + p] = zr[i];
       partial[((int64_t)chunk * 2 * ND + 2 * i + 1) * n + p] = zi[i];
     }
   }
+}
+
+constexpr int kWMom = 16;          // moments per block and detector
+constexpr double kTauCap = 0.25;    // largest |t_c + dt_i| (s) the moment cache is built for
+
+// Extrinsic moves with a cached waveform (Sec. III.B: the fast blocks reuse
+// the waveform of the chain's intrinsic parameters and only redo the
+// projection).  A fast row changes only the detector delays
+// tau_i = t_c + dt_i (and the per-detector factors A P_i applied later), so
+//   z_i = sum_k u_ik g_k exp(-2 pi i f_k tau_i),
+// g_k = exp(-2 pi i Psi(f_k)) the slot's intrinsic phasor (Psi without the
+// linear time term).  Over a block of B bins with centre f_c and
+// t_j = (j - (B - 1) / 2) / (B / 2) in [-1, 1],
+//   exp(-2 pi i f_k tau) = E exp(-i phi t_j),  E = exp(-2 pi i f_c tau),
+//   phi = pi df B tau,
+// so each block contributes E sum_m (-i phi)^m / m! M_m with the slot's
+// moments M_m = sum_j t_j^m u_ij g_j (m < kWMom).  The moments depend on the
+// slot only: they are built once per slot (k_wmom_build, FP64 sums rounded to
+// FP32) and a fast row costs kWMom terms per block and detector instead of B
+// bins.  B is chosen so that |phi| <= 1.61 for |tau| <= kTauCap, where the
+// first dropped term, |phi|^16 / 16!, is below 1e-10 of the block's sum of
+// |u g|; rows with a larger |tau_i| are flagged (NaN).
+//
+// Slot layout: float2 [n_blk][n_det][kWMom].
+constexpr double kInvInt[kWMom + 1] = {0.0,        1.0,        1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,
+                                       1.0 / 6,    1.0 / 7,    1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
+                                       1.0 / 12,   1.0 / 13,   1.0 / 14, 1.0 / 15, 1.0 / 16};
+
+// k_wmom_build: Q = blk / L lanes per (listed slot, block, detector),
+// L = min(blk, 16) bins each (blk <= 512, so Q <= 32 lanes of one wave).  A
+// lane walks its bins (FP64 phase and sin/cos, FP64 moment sums); the Q
+// partial sums are added by lane exchange in a fixed order and the group's
+// first lane stores them.
+constexpr int kWMomLane = 16;  // bins per lane
+
+__global__ void __launch_bounds__(256) k_wmom_build(const double* __restrict__ coef, int64_t ld,
+                                                    const int32_t* __restrict__ slots,
+                                                    const int32_t* __restrict__ count, int rows_per_slot,
+                                                    const int32_t* __restrict__ src, const double* __restrict__ bins,
+                                                    int rs, int n_freq, int nd, int blk, int n_blk, int64_t slot_f2,
+                                                    TrigConsts T, float2* __restrict__ mom) {
+  const int cnt = *count;
+  const int L = blk < kWMomLane ? blk : kWMomLane;
+  const int Q = blk / L;  // power of two, <= 32
+  const int per = n_blk * nd;
+  const int64_t items = (int64_t)cnt * per * Q;
+  const double cen = 0.5 * (blk - 1), hinv = 2.0 / blk;
+  // whole waves iterate together (the lane exchange needs every part)
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t it0 = (int64_t)blockIdx.x * blockDim.x; it0 < items; it0 += stride) {
+    const int64_t it = it0 + threadIdx.x;
+    const bool act = it < items;
+    const int64_t item = act ? it / Q : 0;
+    const int part = (int)(it - (it / Q) * Q);
+    const int li = (int)(item / per), rem = (int)(item - (int64_t)li * per);
+    const int64_t sl = act ? slots[li] : -1;
+    const int b = rem / nd, i = rem - b * nd;
+    double mr[kWMom], mi[kWMom];
+#pragma unroll
+    for (int m = 0; m < kWMom; ++m) mr[m] = mi[m] = 0.0;
+    if (sl >= 0) {
+      const int64_t r = src ? (int64_t)src[li] : sl * rows_per_slot;
+      PhaseCoef c;
+      c.a0 = coef[C_A0 * ld + r];
+      c.a2 = coef[C_A2 * ld + r];
+      c.a3 = coef[C_A3 * ld + r];
+      c.a4 = coef[C_A4 * ld + r];
+      c.a5 = coef[C_A5 * ld + r];
+      c.a6 = coef[C_A6 * ld + r];
+      c.a7 = coef[C_A7 * ld + r];
+      c.a8 = 0.0;  // the linear time term is applied per row
+      c.a10 = coef[C_A10 * ld + r];
+      c.a12 = coef[C_A12 * ld + r];
+      c.b5 = coef[C_B5 * ld + r];
+      c.b6 = coef[C_B6 * ld + r];
+      const int kb = b * blk, k1 = kb + part * L;
+      const int k2 = k1 + L < n_freq ? k1 + L : n_freq;
+      for (int k = k1; k < k2; ++k) {
+        const double* rec = bins + (int64_t)k * rs;
+        const double ph = phase_cycles(c, rec[0], rec[1], rec[2], rec[3]);
+        double sn, cs;
+        sincos_cycles(ph, T, &sn, &cs);
+        const double ur = rec[4 + 2 * i], ui = rec[5 + 2 * i];
+        // w = u g with g = cs - i sn
+        const double wr = ur * cs + ui * sn, wi = ui * cs - ur * sn;
+        const double t = ((double)(k - kb) - cen) * hinv;
+        double tp = 1.0;
+#pragma unroll
+        for (int m = 0; m < kWMom; ++m) {
+          mr[m] = fma(tp, wr, mr[m]);
+          mi[m] = fma(tp, wi, mi[m]);
+          tp *= t;
+        }
+      }
+    }
+    // parts sit in consecutive lanes: pairwise sums in a fixed order
+    for (int off = 1; off < Q; off <<= 1) {
+#pragma unroll
+      for (int m = 0; m < kWMom; ++m) {
+        mr[m] += __shfl_xor(mr[m], off);
+        mi[m] += __shfl_xor(mi[m], off);
+      }
+    }
+    if (sl >= 0 && part == 0) {
+      float2* __restrict__ out = mom + sl * slot_f2 + ((int64_t)b * nd + i) * kWMom;
+#pragma unroll
+      for (int m = 0; m < kWMom; ++m) out[m] = make_float2((float)mr[m], (float)mi[m]);
+    }
+  }
+}
+
+// k_wmom: the fast reduction.  Lane = row (rows[0 .. *count), 64 to a
+// workgroup, slot slot_of[p] or p / rows_per_slot); the workgroup owns a chunk
+// of blocks that its waves split, their sums added in wave order; chunk
+// partials as k_full's ([chunk][2 ND][n]).  Each lane streams its slot's
+// moments, one 128-byte line per detector and block.
+template <int ND>
+__global__ void __launch_bounds__(256) k_wmom(const double* __restrict__ coef, int64_t ld, int64_t n, int64_t k0,
+                                              double df, int blk, int n_blk, int n_chunks, TrigConsts T,
+                                              const int32_t* __restrict__ rows, const int32_t* __restrict__ count,
+                                              int rows_per_slot, const int32_t* __restrict__ slot_of,
+                                              const float2* __restrict__ mom, int64_t slot_f2,
+                                              double* __restrict__ partial) {
+  const int nptile = (int)((n + 63) / 64);
+  int chunk, ptile;
+  decode_block(blockIdx.x, nptile, n_chunks, &chunk, &ptile);
+  const int cnt = *count;
+  if (ptile * 64 >= cnt) return;  // uniform over the workgroup
+  const int idx = ptile * 64 + (threadIdx.x & 63);
+  const bool live = idx < cnt;
+  const int64_t p = rows[live ? idx : cnt - 1];
+  int64_t slot = slot_of ? (int64_t)slot_of[p] : p / rows_per_slot;
+  if (slot < 0) slot = 0;  // a row without a valid slot (the caller discards it)
+  const float4* __restrict__ ms = reinterpret_cast<const float4*>(mom + slot * slot_f2);
+
+  // this wave's blocks
+  const int per = (n_blk + n_chunks - 1) / n_chunks;
+  const int nw = blockDim.x >> 6, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cb = chunk * per, ce = cb + per < n_blk ? cb + per : n_blk;
+  const int sub = ((ce > cb ? ce - cb : 0) + nw - 1) / nw;
+  const int bb = cb + wv * sub, be = bb + sub < ce ? bb + sub : ce;
+
+  const double tau0 = coef[C_TAU0 * ld + p];
+  double zr[ND], zi[ND], er[ND], ei[ND], rr[ND], ri[ND], ph[ND];
+  bool in_range = true;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    const double tau = i == 0 ? tau0 : tau0 + coef[(C_DT1 + i - 1) * ld + p];
+    in_range = in_range && fabs(tau) <= kTauCap;
+    ph[i] = kPi * df * blk * tau;
+    double sn, cs;
+    // E at the centre of the first block, and the block-to-block rotation
+    sincos_cycles(((double)k0 + (double)bb * blk + 0.5 * (blk - 1)) * df * tau, T, &sn, &cs);
+    er[i] = cs;
+    ei[i] = -sn;
+    sincos_cycles((double)blk * df * tau, T, &sn, &cs);
+    rr[i] = cs;
+    ri[i] = -sn;
+    zr[i] = 0.0;
+    zi[i] = 0.0;
+  }
+  for (int b = bb; b < be; ++b) {
+    const float4* __restrict__ mb = ms + (int64_t)b * ND * (kWMom / 2);
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      float4 v[kWMom / 2];
+#pragma unroll
+      for (int q = 0; q < kWMom / 2; ++q) v[q] = mb[i * (kWMom / 2) + q];
+      // Horner in (-i phi): H = M_m + (-i phi / (m + 1)) H
+      double hr = (double)v[kWMom / 2 - 1].z, hi = (double)v[kWMom / 2 - 1].w;
+#pragma unroll
+      for (int m = kWMom - 2; m >= 0; --m) {
+        const double q = ph[i] * kInvInt[m + 1];
+        const double mr = (double)((m & 1) ? v[m >> 1].z : v[m >> 1].x);
+        const double mi = (double)((m & 1) ? v[m >> 1].w : v[m >> 1].y);
+        const double nr = fma(q, hi, mr);
+        const double ni = fma(-q, hr, mi);
+        hr = nr;
+        hi = ni;
+      }
+      zr[i] = fma(er[i], hr, zr[i]);
+      zr[i] = fma(-ei[i], hi, zr[i]);
+      zi[i] = fma(er[i], hi, zi[i]);
+      zi[i] = fma(ei[i], hr, zi[i]);
+      const double tr = er[i] * rr[i] - ei[i] * ri[i];
+      ei[i] = er[i] * ri[i] + ei[i] * rr[i];
+      er[i] = tr;
+    }
+  }
+  if (!in_range) {
+#pragma unroll
+    for (int i = 0; i < ND; ++i) zr[i] = zi[i] = __builtin_nan("");
+  }
+  if (!wave_sums_combine<ND>(zr, zi)) return;
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      partial[((int64_t)chunk * 2 * ND + 2 * i) * n + p] = zr[i];
+      partial[((int64_t)chunk * 2 * ND + 2 * i + 1) * n + p] = zi[i];
+    }
+  }
+}
+
+// Sum the fast rows' chunk partials (fixed order) into zout[p][2 nd]: one
+// lane per (listed row, component).
+__global__ void __launch_bounds__(256) k_wmom_sum(const double* __restrict__ partial, int n_chunks, int nd, int64_t n,
+                                                  const int32_t* __restrict__ rows,
+                                                  const int32_t* __restrict__ count, double* __restrict__ zout) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = t / (2 * nd), j = t - idx * (2 * nd);
+  if (idx >= *count) return;
+  const int64_t p = rows[idx];
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  int c = 0;
+  for (; c + 8 <= n_chunks; c += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] += partial[((int64_t)(c + q) * 2 * nd + j) * n + p];
+  }
+  for (int q = 0; c + q < n_chunks; ++q) acc[q] += partial[((int64_t)(c + q) * 2 * nd + j) * n + p];
+  zout[p * 2 * nd + j] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
 // Matrix-core form of the mixed reduction.
@@ -422,11 +700,17 @@ __global__ void __launch_bounds__(256) k_full_mfma(const double* __restrict__ co
 // Combine the chunk partials and apply the marginalisation.  A workgroup
 // takes 64 proposals; its 16 waves sum the chunks c = w (mod 16) in order and
 // wave 0 adds the sixteen sums in order, so the result is reproducible.  For the
-// distance marginal this writes (|Z_1|, <h|h>_1) for k_dist_marg.
-__global__ void __launch_bounds__(1024) k_epilogue(const double* __restrict__ partial, int n_chunks, int nd,
-                                                  const double* __restrict__ coef, int64_t ld, int64_t n,
+// distance marginal this writes (|Z_1|, <h|h>_1) for k_dist_marg.  With a
+// waveform cache, a row p with zsrc[p] >= 0 takes its sums z_i from slot
+// zsrc[p] of zc ([slot][2 nd]) instead of the partials (moves that change only
+// A P_i), and zrow (when not NULL) receives every row's z_i ([n][2 nd]).
+// The partials of chunk c are read at chunk index c * cstride (1, or the
+// group length after k_partial_reduce).
+__global__ void __launch_bounds__(1024) k_epilogue(const double* __restrict__ partial, int n_chunks, int cstride,
+                                                  int nd, const double* __restrict__ coef, int64_t ld, int64_t n,
                                                   double dd, int marg, LogI0Consts C, double* __restrict__ logl,
-                                                  double* __restrict__ zbuf) {
+                                                  double* __restrict__ zbuf, const int32_t* __restrict__ zsrc,
+                                                  const double* __restrict__ zc, double* __restrict__ zrow) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t p = (int64_t)blockIdx.x * 64 + lane;
@@ -437,7 +721,7 @@ __global__ void __launch_bounds__(1024) k_epilogue(const double* __restrict__ pa
   for (int c = wave; c < n_chunks; c += 16) {
 #pragma unroll
     for (int j = 0; j < 2 * kMaxDet; ++j)
-      if (j < 2 * nd) z[j] += partial[((int64_t)c * 2 * nd + j) * n + pc];
+      if (j < 2 * nd) z[j] += partial[((int64_t)c * cstride * 2 * nd + j) * n + pc];
   }
   __shared__ double red[15][2 * kMaxDet][64];
   if (wave > 0) {
@@ -449,6 +733,19 @@ __global__ void __launch_bounds__(1024) k_epilogue(const double* __restrict__ pa
   for (int w = 0; w < 15; ++w)
 #pragma unroll
     for (int j = 0; j < 2 * kMaxDet; ++j) z[j] += red[w][j][lane];
+  if (zsrc) {
+    const int32_t sl = zsrc[p];
+    if (sl >= 0) {
+#pragma unroll
+      for (int j = 0; j < 2 * kMaxDet; ++j)
+        if (j < 2 * nd) z[j] = zc[(int64_t)sl * 2 * nd + j];
+    }
+  }
+  if (zrow) {
+#pragma unroll
+    for (int j = 0; j < 2 * kMaxDet; ++j)
+      if (j < 2 * nd) zrow[p * 2 * nd + j] = z[j];
+  }
   const bool valid = coef[C_VALID * ld + p] != 0.0;
   double Zr = 0.0, Zi = 0.0, plain = 0.0;
 #pragma unroll
@@ -478,6 +775,40 @@ __global__ void __launch_bounds__(1024) k_epilogue(const double* __restrict__ pa
     out = -0.5 * dd - 0.5 * hh + log_i0(sqrt(Zr * Zr + Zi * Zi), C);
   }
   logl[p] = out;
+}
+
+// First level of the chunk reduction for small batches (few rows, many
+// chunks): workgroup (tile, g) adds chunks g cpg .. (g + 1) cpg - 1 of its 64
+// rows (its 4 waves interleaved, then in wave order) and stores the sum in
+// chunk g cpg of the same buffer, which no other workgroup reads.
+__global__ void __launch_bounds__(256) k_partial_reduce(double* __restrict__ partial, int n_chunks, int cpg, int nd,
+                                                        int64_t n) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t pc = p < n ? p : n - 1;
+  const int c0 = blockIdx.y * cpg;
+  const int c1 = c0 + cpg < n_chunks ? c0 + cpg : n_chunks;
+  double z[2 * kMaxDet];
+#pragma unroll
+  for (int j = 0; j < 2 * kMaxDet; ++j) z[j] = 0.0;
+  for (int c = c0 + wave; c < c1; c += 4) {
+#pragma unroll
+    for (int j = 0; j < 2 * kMaxDet; ++j)
+      if (j < 2 * nd) z[j] += partial[((int64_t)c * 2 * nd + j) * n + pc];
+  }
+  __shared__ double red[3][2 * kMaxDet][64];
+  if (wave > 0) {
+#pragma unroll
+    for (int j = 0; j < 2 * kMaxDet; ++j) red[wave - 1][j][lane] = z[j];
+  }
+  __syncthreads();
+  if (wave != 0 || p >= n) return;
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int j = 0; j < 2 * kMaxDet; ++j) z[j] += red[w][j][lane];
+#pragma unroll
+  for (int j = 0; j < 2 * kMaxDet; ++j)
+    if (j < 2 * nd) partial[((int64_t)c0 * 2 * nd + j) * n + p] = z[j];
 }
 
 // Distance marginal: one lane per proposal, waves splitting the grid (see block_dist_lse).
@@ -600,12 +931,12 @@ static gw_status launch_full_nd(gw_ctx* ctx, const double* coef, int64_t ld, int
   const int64_t blocks = nptile * n_chunks;
   if (blocks > 0x7fffffff) return set_error(GW_EINVAL, "batch too large for one launch");
   if (prec == GW_PREC_FP64) {
-    hipLaunchKernelGGL((k_full<ND, 0>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
-                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, 1.0, 0.0, partial);
+    hipLaunchKernelGGL((k_full<ND, 0, false>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
+                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, 1.0, 0.0, nullptr, nullptr, partial);
   } else {
-    hipLaunchKernelGGL((k_full<ND, 1>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
+    hipLaunchKernelGGL((k_full<ND, 1, false>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
                        ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, ctx->pgain_re, ctx->pgain_im,
-                       partial);
+                       nullptr, nullptr, partial);
   }
   return check_hip(hipGetLastError(), "full-band kernel launch");
 }
@@ -778,14 +1109,30 @@ gw_status build_moment_table(gw_ctx* ctx, const std::vector<double>& rec, const 
   return GW_OK;
 }
 
-gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, const double* coef, int64_t ld,
+gw_status launch_epilogue(gw_ctx* ctx, double* partial, int n_chunks, const double* coef, int64_t ld,
                           int64_t n, int marg, int prec, double* logl, hipStream_t st) {
+  return launch_epilogue_cached(ctx, partial, n_chunks, coef, ld, n, marg, prec, logl, nullptr, nullptr, nullptr, st);
+}
+
+gw_status launch_epilogue_cached(gw_ctx* ctx, double* partial, int n_chunks, const double* coef, int64_t ld,
+                                 int64_t n, int marg, int prec, double* logl, const int32_t* zsrc, const double* zc,
+                                 double* zrow, hipStream_t st) {
   if (n == 0) return GW_OK;
   const int64_t blocks = (n + 63) / 64;
   LogI0Consts C = make_log_i0_consts();
   C.r1max = ctx->dist_r1max;
-  hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(1024), 0, st, partial, n_chunks, ctx->n_det, coef, ld,
-                     n, ctx->dd, marg, C, logl, ctx->zbuf);
+  int groups = n_chunks, cstride = 1;
+  if (n <= 2048 && n_chunks >= 64) {
+    // few rows, many chunks: reduce groups of 8 chunks across the chip first
+    cstride = 8;
+    groups = (n_chunks + cstride - 1) / cstride;
+    hipLaunchKernelGGL(k_partial_reduce, dim3((unsigned)blocks, (unsigned)groups), dim3(256), 0, st, partial, n_chunks,
+                       cstride, ctx->n_det, n);
+    gw_status s = check_hip(hipGetLastError(), "partial reduction launch");
+    if (s != GW_OK) return s;
+  }
+  hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(1024), 0, st, partial, groups, cstride, ctx->n_det, coef,
+                     ld, n, ctx->dd, marg, C, logl, ctx->zbuf, zsrc, zc, zrow);
   gw_status s = check_hip(hipGetLastError(), "epilogue launch");
   if (s != GW_OK || marg != 2) return s;
   if (n >= kDistSliced) {
@@ -806,6 +1153,89 @@ gw_status launch_epilogue(gw_ctx* ctx, const double* partial, int n_chunks, cons
                          ctx->n_dist, ctx->dd, C, logl);
   }
   return check_hip(hipGetLastError(), "distance marginal launch");
+}
+
+// Block length of the moment cache: the largest power of two B in [4, 512]
+// with pi df B kTauCap <= 1.61.
+int wmom_block(const gw_ctx* ctx) {
+  int b = 4;
+  while (b < 512 && kPi * ctx->geom.df * (2 * b) * kTauCap <= 1.61) b *= 2;
+  return b;
+}
+
+int64_t wmom_slot_f2(const gw_ctx* ctx) {
+  const int blk = wmom_block(ctx);
+  const int64_t n_blk = (ctx->geom.n_freq + blk - 1) / blk;
+  return n_blk * ctx->n_det * kWMom;
+}
+
+template <int ND>
+static gw_status launch_cached_nd(gw_ctx* ctx, const double* coef, int64_t n, int prec, int tpb, int n_chunks,
+                                  const int32_t* slow_rows, const int32_t* fast_rows, const int32_t* counts,
+                                  int rows_per_slot, const int32_t* slot_of, const float2* mom, double* zfast,
+                                  double* partial, hipStream_t st) {
+  const int nf = (int)ctx->geom.n_freq;
+  const TrigConsts T = make_trig_consts();
+  const int64_t nptile = (n + 63) / 64;  // 64 rows per workgroup; tpb / 64 waves split each chunk
+  const int64_t blocks = nptile * n_chunks;
+  if (blocks > 0x7fffffff) return set_error(GW_EINVAL, "batch too large for one launch");
+  const int chunk_len = (int)((nf + n_chunks - 1) / n_chunks);
+  gw_status s = GW_OK;
+  if (slow_rows) {
+    if (prec == GW_PREC_FP64)
+      hipLaunchKernelGGL((k_full<ND, 0, true>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, n, n, ctx->bins,
+                         ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, 1.0, 0.0, slow_rows, counts, partial);
+    else
+      hipLaunchKernelGGL((k_full<ND, 1, true>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, n, n, ctx->bins,
+                         ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, ctx->pgain_re, ctx->pgain_im,
+                         slow_rows, counts, partial);
+    s = check_hip(hipGetLastError(), "full-band list kernel launch");
+  }
+  if (s != GW_OK || !mom) return s;  // no cache, no fast rows
+  const int blk = wmom_block(ctx);
+  const int n_blk = (nf + blk - 1) / blk;
+  // chunks of at least 8 blocks, at most the partials' chunk count
+  int cm = n_blk / 8 < n_chunks ? n_blk / 8 : n_chunks;
+  if (cm < 1) cm = 1;
+  if (cm > 8) cm = cm / 8 * 8;
+  const int slot = prof_begin(ctx, st);
+  hipLaunchKernelGGL((k_wmom<ND>), dim3((unsigned)(nptile * cm)), dim3(256), 0, st, coef, n, n, ctx->geom.k0,
+                     ctx->geom.df, blk, n_blk, cm, T, fast_rows, counts + 1, rows_per_slot, slot_of, mom,
+                     wmom_slot_f2(ctx), partial);
+  prof_end(ctx, slot, st);
+  s = check_hip(hipGetLastError(), "cached-waveform kernel launch");
+  if (s != GW_OK) return s;
+  hipLaunchKernelGGL(k_wmom_sum, dim3((unsigned)((n * 2 * ND + 255) / 256)), dim3(256), 0, st, partial, cm, ND, n,
+                     fast_rows, counts + 1, zfast);
+  return check_hip(hipGetLastError(), "cached-waveform sum launch");
+}
+
+gw_status launch_cached(gw_ctx* ctx, const double* coef, int64_t n, int prec, int tpb, int n_chunks,
+                        const int32_t* slow_rows, const int32_t* fast_rows, const int32_t* counts, int rows_per_slot,
+                        const int32_t* slot_of, const float2* mom, double* zfast, double* partial, hipStream_t st) {
+  if (n == 0) return GW_OK;
+  if (tpb != 64 && tpb != 128 && tpb != 256) return set_error(GW_EINVAL, "tpb must be 64, 128 or 256");
+  switch (ctx->n_det) {
+    case 1: return launch_cached_nd<1>(ctx, coef, n, prec, tpb, n_chunks, slow_rows, fast_rows, counts,
+                                       rows_per_slot, slot_of, mom, zfast, partial, st);
+    case 2: return launch_cached_nd<2>(ctx, coef, n, prec, tpb, n_chunks, slow_rows, fast_rows, counts,
+                                       rows_per_slot, slot_of, mom, zfast, partial, st);
+    case 3: return launch_cached_nd<3>(ctx, coef, n, prec, tpb, n_chunks, slow_rows, fast_rows, counts,
+                                       rows_per_slot, slot_of, mom, zfast, partial, st);
+    case 4: return launch_cached_nd<4>(ctx, coef, n, prec, tpb, n_chunks, slow_rows, fast_rows, counts,
+                                       rows_per_slot, slot_of, mom, zfast, partial, st);
+    default: return set_error(GW_ENOTSUP, "n_det %d not supported", ctx->n_det);
+  }
+}
+
+gw_status launch_wmom_build(gw_ctx* ctx, const double* coef, int64_t ld, const int32_t* slots, const int32_t* count,
+                            int rows_per_slot, const int32_t* src, float2* mom, hipStream_t st) {
+  const int blk = wmom_block(ctx);
+  const int n_blk = (int)((ctx->geom.n_freq + blk - 1) / blk);
+  hipLaunchKernelGGL(k_wmom_build, dim3(2048), dim3(256), 0, st, coef, ld, slots, count, rows_per_slot, src, ctx->bins,
+                     ctx->rec_stride, (int)ctx->geom.n_freq, ctx->n_det, blk, n_blk, wmom_slot_f2(ctx),
+                     make_trig_consts(), mom);
+  return check_hip(hipGetLastError(), "waveform cache build launch");
 }
 
 gw_status launch_template(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, double* h, hipStream_t st) {

@@ -40,6 +40,14 @@ struct SweepParams {
   int64_t k;
   double* x;
   double* logl;
+  // Full band: candidates go to the likelihood as row lists (lists = 1).
+  // Waveform cache (cache = 1): block kinds 0 slow (changes the intrinsic
+  // waveform), 1 extrinsic (sky and time: cached waveform, new delays),
+  // 2 projection only (psi, iota: cached sums z_i).
+  int32_t lists;
+  int32_t cache;
+  int32_t n_det;
+  int32_t kind[kMaxBlocks];
 };
 
 // Per-chain state (structure of arrays inside one device allocation).
@@ -57,6 +65,18 @@ struct SliceState {
   int32_t* tot_evals;
   int32_t* n_caps;   // blocks whose shrink cap was hit
   int32_t* n_active;
+  // row lists and waveform cache bookkeeping (list mode only)
+  int32_t* rkind;      // [2k]: 0 no likelihood, 1 full, 2 cached waveform, 3 cached sums
+  int32_t* zsrc;       // [2k]: slot whose cached sums the row uses, or -1
+  int32_t* build_list;  // [k]: chains whose waveform is rebuilt after this round
+  int32_t* dirty;      // [k]: the chain's cached waveform is older than its point
+  int32_t* slow_rows;  // [2k]
+  int32_t* stream_rows;  // [2k]
+  int32_t* counts;     // [3]: rows in the two lists, chains in build_list
+  unsigned long long* kind_tot;  // [3]: evaluations by kind over the sweep
+  double* zrow;        // [2k][2 n_det]: every row's sums z_i
+  double* zc;          // [k][2 n_det]: the sums at each chain's current point, then
+                       // [2k][2 n_det]: the cached-waveform rows' sums
 };
 
 // Philox4x64-10 (Salmon, Moraes, Dror & Shaw 2011).
@@ -157,7 +177,12 @@ __device__ inline bool make_point(const SweepParams& P, int b, const SliceState&
   return inside;
 }
 
-__global__ void k_sweep_set(SweepParams* D, SweepParams P) { *D = P; }
+__global__ void k_sweep_set(SweepParams* D, SweepParams P, unsigned long long* kind_tot) {
+  *D = P;
+  kind_tot[0] = 0;
+  kind_tot[1] = 0;
+  kind_tot[2] = 0;
+}
 
 __global__ void k_sweep_init(const SweepParams* __restrict__ D, SliceState S) {
   const SweepParams& P = *D;
@@ -226,6 +251,17 @@ __global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S,
   S.slot_ok[2 * c] = ok[0];
   S.slot_ok[2 * c + 1] = ok[1];
   S.flags[c] = fl;
+  if (P.lists) {
+    // an extrinsic block whose cached waveform is stale evaluates in full
+    // (for one round, until the rebuild queued below has run)
+    int kd = 0;
+    if (!(fl & 4)) {
+      const int kb = P.cache ? P.kind[S.cur[c]] : 0;
+      kd = kb == 1 && S.dirty[c] ? 1 : 1 + kb;
+    }
+    S.rkind[2 * c] = ok[0] ? kd : 0;
+    S.rkind[2 * c + 1] = ok[1] ? kd : 0;
+  }
 }
 
 __global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, const double* __restrict__ cand_logl) {
@@ -264,6 +300,13 @@ __global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, 
         x[c * kSliceDim + j] += t * S.d[c * kMaxBlock + a];
       }
       logl[c] = v;
+      if (P.cache) {
+        // the chain's cached sums follow its point; a slow move also needs
+        // the waveform rebuilt (from this row's coefficients)
+        for (int j = 0; j < 2 * kMaxDet; ++j)
+          if (j < 2 * P.n_det) S.zc[c * 2 * P.n_det + j] = S.zrow[2 * c * 2 * P.n_det + j];
+        if (P.kind[b] == 0) S.dirty[c] = 1;
+      }
       fl = finish_block(P, S, c, false);
     } else {
       if (t < 0.0) S.t_lo[c] = t;
@@ -273,7 +316,92 @@ __global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, 
     }
   }
   S.flags[c] = fl;
-  if (!(fl & 4)) atomicAdd(S.n_active, 1);
+  if (!(fl & 4)) {
+    atomicAdd(S.n_active, 1);
+    // the waveform is rebuilt lazily: when a chain is in an extrinsic block
+    // with a stale cache, after this round
+    if (P.cache && P.kind[S.cur[c]] == 1 && S.dirty[c]) {
+      S.dirty[c] = 0;
+      S.build_list[atomicAdd(&S.counts[2], 1)] = (int32_t)c;
+    }
+  }
+}
+
+// Row lists of the cached likelihood: rows of kind 1 and 2 in ascending
+// order (one workgroup of 1024 threads), and each row's cached-sums slot.
+__global__ void __launch_bounds__(1024) k_sweep_lists(const SweepParams* __restrict__ D, SliceState S) {
+  __shared__ int32_t tot[2][16];
+  const int64_t n = 2 * D->k;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+  int32_t base0 = 0, base1 = 0;
+  for (int64_t r0 = 0; r0 < n; r0 += 1024) {
+    const int64_t r = r0 + threadIdx.x;
+    const int kd = r < n ? S.rkind[r] : 0;
+    if (r < n) S.zsrc[r] = kd == 3 ? (int32_t)(r >> 1) : kd == 2 ? (int32_t)(D->k + r) : -1;
+    const uint64_t m1 = __ballot(kd == 1), m2 = __ballot(kd == 2);
+    if (lane == 0) {
+      tot[0][wave] = __popcll(m1);
+      tot[1][wave] = __popcll(m2);
+    }
+    __syncthreads();
+    int32_t o0 = base0, o1 = base1, t0 = 0, t1 = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < wave) {
+        o0 += tot[0][w];
+        o1 += tot[1][w];
+      }
+      t0 += tot[0][w];
+      t1 += tot[1][w];
+    }
+    if (kd == 1) S.slow_rows[o0 + __popcll(m1 & below)] = (int32_t)r;
+    if (kd == 2) S.stream_rows[o1 + __popcll(m2 & below)] = (int32_t)r;
+    base0 += t0;
+    base1 += t1;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    S.counts[0] = base0;
+    S.counts[1] = base1;
+    S.counts[2] = 0;  // the update kernel appends the chains to rebuild
+  }
+  // cached-sums rows, for the per-kind totals
+  int32_t n3 = 0;
+  for (int64_t r = threadIdx.x; r < n; r += 1024) n3 += S.rkind[r] == 3;
+  for (int off = 32; off > 0; off >>= 1) n3 += __shfl_xor(n3, off);
+  if (lane == 0) tot[0][wave] = n3;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t3 = 0;
+    for (int w = 0; w < 16; ++w) t3 += tot[0][w];
+    S.kind_tot[0] += (unsigned long long)base0;
+    S.kind_tot[1] += (unsigned long long)base1;
+    S.kind_tot[2] += (unsigned long long)t3;
+  }
+}
+
+// Cache set-up at the start of a sweep: row 2c evaluates chain c's current
+// point in full (row 2c + 1 needs nothing) ...
+__global__ void k_cache_init0(const SweepParams* __restrict__ D, SliceState S, double* __restrict__ cand) {
+  const SweepParams& P = *D;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.k) return;
+  prior_transform(P.x + c * kSliceDim, cand + 2 * c * 13);
+  double* th = cand + (2 * c + 1) * 13;
+  for (int j = 0; j < 13; ++j) th[j] = 0.0;
+  th[1] = -1.0;
+  S.rkind[2 * c] = 1;
+  S.rkind[2 * c + 1] = 0;
+}
+
+// ... and its sums seed the chain's cached sums; its waveform is built when
+// first needed.
+__global__ void k_cache_init1(const SweepParams* __restrict__ D, SliceState S) {
+  const SweepParams& P = *D;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.k) return;
+  for (int j = 0; j < 2 * P.n_det; ++j) S.zc[c * 2 * P.n_det + j] = S.zrow[2 * c * 2 * P.n_det + j];
+  S.dirty[c] = 1;
 }
 
 __global__ void k_prior_transform(const double* __restrict__ x, int64_t n, double* __restrict__ theta) {
@@ -295,8 +423,8 @@ using namespace gw;
 // What a captured round group bakes in: any change means a new capture.
 struct SliceGraphKey {
   int64_t k;
-  int32_t like, marg, prec;
-  const void *ws_mem, *coef, *partial, *zbuf, *het;
+  int32_t like, marg, prec, cache;
+  const void *ws_mem, *coef, *partial, *zbuf, *het, *wc;
   int32_t het_wpb, het_grid, het_ech, full_tpb, full_chunks, full_kernel;
   bool operator==(const SliceGraphKey& o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
 };
@@ -307,8 +435,12 @@ struct gw_slice_ws {
   double* cand = nullptr;       // [2k][13]
   double* cand_logl = nullptr;  // [2k]
   int32_t* h_active = nullptr;  // pinned host
+  unsigned long long* h_kinds = nullptr;  // pinned host [3]
   SliceState S{};
   SweepParams* dev = nullptr;   // device parameter block
+  float2* wc = nullptr;         // waveform cache (block moments) [cap_wc][slot_f2]
+  int64_t cap_wc = 0;
+  int64_t slot_f2 = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -317,12 +449,55 @@ struct gw_slice_ws {
 };
 
 static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out);
+static gw_status slice_wcache(gw_ctx* ctx, gw_slice_ws* ws, int64_t k);
 
 struct SweepCall {
   int32_t like, marg, prec, use_graph;
   int32_t* n_evals;
   int32_t* status;
+  int32_t cache;
+  int64_t* eval_kinds;  // host [3] or null
+  int32_t lists;        // full band: row-list likelihood (always with the cache)
 };
+
+// Launch shape of the row-list likelihood: 64 rows per workgroup, its four
+// waves splitting chunks of about 512 bins (the rows of a round are few, so
+// the bins supply the parallelism).
+void gw::cached_shape(const gw_ctx* ctx, int* tpb, int* nch) {
+  int64_t c = (ctx->geom.n_freq + 511) / 512;
+  c = (c + 7) / 8 * 8;
+  *tpb = 256;
+  *nch = (int)c;
+}
+
+gw_status gw::cached_reserve(gw_ctx* ctx, int64_t n) {
+  int tpb, nch;
+  cached_shape(ctx, &tpb, &nch);
+  gw_status s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
+  if (s == GW_OK) s = ensure_buffer(&ctx->partial, &ctx->partial_cap, (int64_t)nch * 2 * ctx->n_det * n, "partials");
+  if (s == GW_OK) s = ensure_buffer(&ctx->zbuf, &ctx->zbuf_cap, 2 * n, "marginal workspace");
+  return s;
+}
+
+// Likelihood of the round's 2k candidate rows into ws->cand_logl.
+static gw_status eval_rows(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const SweepCall& a, hipStream_t st) {
+  const int64_t n = 2 * k;
+  if (!a.lists) return loglike_batch(ctx, ws->cand, n, a.like, a.marg, a.prec, ws->cand_logl, st);
+  gw_status s = cached_reserve(ctx, n);
+  if (s != GW_OK) return s;
+  int tpb, nch;
+  cached_shape(ctx, &tpb, &nch);
+  hipLaunchKernelGGL(k_sweep_lists, dim3(1), dim3(1024), 0, st, (const SweepParams*)ws->dev, ws->S);
+  s = check_hip(hipGetLastError(), "row list launch");
+  if (s == GW_OK) s = launch_prologue(ctx, ws->cand, n, a.marg, ctx->coef, n, st);
+  if (s == GW_OK)
+    s = launch_cached(ctx, ctx->coef, n, a.prec, tpb, nch, ws->S.slow_rows, ws->S.stream_rows, ws->S.counts, 2,
+                      nullptr, a.cache ? ws->wc : nullptr, ws->S.zc + k * 2 * ctx->n_det, ctx->partial, st);
+  if (s == GW_OK)
+    s = launch_epilogue_cached(ctx, ctx->partial, nch, ctx->coef, n, n, a.marg, a.prec, ws->cand_logl, ws->S.zsrc,
+                               ws->S.zc, ws->S.zrow, st);
+  return s;
+}
 
 // Capture one round group into a graph (re-captured when anything it bakes in
 // changes) on the workspace's own capture stream.  Buffers the likelihood
@@ -330,7 +505,7 @@ struct SweepCall {
 template <class Group>
 static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const SweepCall& a, Group group) {
   const int64_t n = 2 * k;
-  gw_status s = a.like == GW_HET ? het_reserve(ctx, n) : full_reserve(ctx, n);
+  gw_status s = a.lists ? cached_reserve(ctx, n) : a.like == GW_HET ? het_reserve(ctx, n) : full_reserve(ctx, n);
   if (s != GW_OK) return s;
   SliceGraphKey key;
   memset(&key, 0, sizeof(key));
@@ -338,6 +513,8 @@ static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const Swee
   key.like = a.like;
   key.marg = a.marg;
   key.prec = a.prec;
+  key.cache = a.cache + 2 * a.lists;
+  key.wc = ws->wc;
   key.ws_mem = ws->mem;
   key.coef = ctx->coef;
   key.partial = ctx->partial;
@@ -424,13 +601,24 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
   if (s != GW_OK) return s;
   gw_slice_ws* ws = nullptr;
   s = slice_ws(ctx, P.k, &ws);
+  if (s == GW_OK && a.cache) s = slice_wcache(ctx, ws, P.k);
   if (s != GW_OK) return s;
   const int64_t k = P.k;
   const int tpb = 256;
   const unsigned blocks = (unsigned)((k + tpb - 1) / tpb);
-  hipLaunchKernelGGL(k_sweep_set, dim3(1), dim3(1), 0, st, ws->dev, P);
+  hipLaunchKernelGGL(k_sweep_set, dim3(1), dim3(1), 0, st, ws->dev, P, ws->S.kind_tot);
   hipLaunchKernelGGL(k_sweep_init, dim3(blocks), dim3(tpb), 0, st, (const SweepParams*)ws->dev, ws->S);
   s = check_hip(hipGetLastError(), "slice init launch");
+  if (s == GW_OK && a.cache) {
+    // seed every chain's cached sums from a full evaluation of its current point
+    hipLaunchKernelGGL(k_cache_init0, dim3(blocks), dim3(tpb), 0, st, (const SweepParams*)ws->dev, ws->S, ws->cand);
+    s = check_hip(hipGetLastError(), "cache init launch");
+    if (s == GW_OK) s = eval_rows(ctx, ws, k, a, st);
+    if (s == GW_OK) {
+      hipLaunchKernelGGL(k_cache_init1, dim3(blocks), dim3(tpb), 0, st, (const SweepParams*)ws->dev, ws->S);
+      s = check_hip(hipGetLastError(), "cache init launch");
+    }
+  }
   // One group = 4 rounds of (propose, batched likelihood, update); after a
   // group the host reads the number of chains still moving.  A block takes at
   // most max_out + 1 stepping rounds (both sides in parallel) and max_shrink
@@ -443,12 +631,14 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
       hipLaunchKernelGGL(k_sweep_propose, dim3(blocks), dim3(tpb), 0, gs, (const SweepParams*)ws->dev, ws->S,
                          ws->cand);
       g = check_hip(hipGetLastError(), "slice propose launch");
-      if (g == GW_OK) g = loglike_batch(ctx, ws->cand, 2 * k, a.like, a.marg, a.prec, ws->cand_logl, gs);
+      if (g == GW_OK) g = eval_rows(ctx, ws, k, a, gs);
       if (g == GW_OK) {
         hipLaunchKernelGGL(k_sweep_update, dim3(blocks), dim3(tpb), 0, gs, (const SweepParams*)ws->dev, ws->S,
                            (const double*)ws->cand_logl);
         g = check_hip(hipGetLastError(), "slice update launch");
       }
+      if (g == GW_OK && a.cache)
+        g = launch_wmom_build(ctx, ctx->coef, 2 * k, ws->S.build_list, ws->S.counts + 2, 2, nullptr, ws->wc, gs);
     }
     return g;
   };
@@ -464,7 +654,19 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
   if (s != GW_OK) return s;
   hipLaunchKernelGGL(k_sweep_finish, dim3(blocks), dim3(tpb), 0, st, (const SweepParams*)ws->dev, ws->S, a.n_evals,
                      a.status);
-  return check_hip(hipGetLastError(), "slice finish launch");
+  s = check_hip(hipGetLastError(), "slice finish launch");
+  if (s == GW_OK && a.eval_kinds) {
+    if (!a.cache) {
+      a.eval_kinds[0] = a.eval_kinds[1] = a.eval_kinds[2] = -1;  // not counted without the cache
+      return GW_OK;
+    }
+    s = check_hip(hipMemcpyAsync(ws->h_kinds, ws->S.kind_tot, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                 st), "copy");
+    if (s == GW_OK) s = check_hip(hipStreamSynchronize(st), "slice sync");
+    if (s == GW_OK)
+      for (int i = 0; i < 3; ++i) a.eval_kinds[i] = (int64_t)ws->h_kinds[i];
+  }
+  return s;
 }
 
 extern "C" {
@@ -489,7 +691,8 @@ gw_status slice_step(gw_ctx* ctx, const gw_slice_args* a, void* stream) {
   P.k = a->k;
   P.x = a->x;
   P.logl = a->logl;
-  const SweepCall c{a->like, a->marg, a->prec, a->use_graph, a->n_evals, a->status};
+  P.lists = a->like == GW_FULL;
+  const SweepCall c{a->like, a->marg, a->prec, a->use_graph, a->n_evals, a->status, 0, nullptr, P.lists};
   return run_sweep(ctx, P, c, (hipStream_t)stream);
 }
 
@@ -520,7 +723,25 @@ gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* a, void* stream) {
   P.k = a->k;
   P.x = a->x;
   P.logl = a->logl;
-  const SweepCall c{a->like, a->marg, a->prec, a->use_graph, a->n_evals, a->status};
+  if (a->use_cache) {
+    if (a->like != GW_FULL) return set_error(GW_ENOTSUP, "slice_sweep: the waveform cache is for like=GW_FULL");
+    // kind of each block from its coordinates: psi and iota only change the
+    // projection; sky position and t_c also change the delays; anything else
+    // changes the waveform
+    for (int b = 0; b < P.nb; ++b) {
+      bool proj = true, extr = true;
+      for (int i = 0; i < P.bd[b]; ++i) {
+        const int j = P.block[b][i];
+        proj = proj && (j == 6 || j == 9);
+        extr = extr && j >= 6;
+      }
+      P.kind[b] = proj ? 2 : extr ? 1 : 0;
+    }
+    P.cache = 1;
+    P.n_det = ctx->n_det;
+  }
+  P.lists = a->like == GW_FULL;
+  const SweepCall c{a->like, a->marg, a->prec, a->use_graph, a->n_evals, a->status, P.cache, a->eval_kinds, P.lists};
   return run_sweep(ctx, P, c, (hipStream_t)stream);
 }
 
@@ -545,6 +766,8 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
     if (!ws) return set_error(GW_ENOMEM, "slice workspace");
     if (hipHostMalloc((void**)&ws->h_active, sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
       return set_error(GW_ENOMEM, "slice pinned flag");
+    if (hipHostMalloc((void**)&ws->h_kinds, 3 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+      return set_error(GW_ENOMEM, "slice pinned counters");
     if (hipMalloc((void**)&ws->dev, sizeof(SweepParams)) != hipSuccess) return set_error(GW_ENOMEM, "slice parameters");
   }
   if (ws->cap >= k) {
@@ -554,20 +777,25 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
   if (ws->mem) (void)hipFree(ws->mem);
   ws->mem = nullptr;
   ws->cap = 0;
-  // doubles: t_lo, t_hi, d[4], cand_t[2], cand[26], cand_logl[2]; ints: flags, n_out[2], n_shrink, n_evals,
-  // slot_ok[2], cur, tot_evals, n_caps, then the active counter
-  const size_t nd = (size_t)k * (1 + 1 + kMaxBlock + 2 + 26 + 2);
-  const size_t ni = (size_t)k * (1 + 2 + 1 + 1 + 2 + 3) + 1;
+  // doubles: t_lo, t_hi, d[4], cand_t[2], cand[26], cand_logl[2], zrow[2][2 kMaxDet], zc[3][2 kMaxDet];
+  // ints: flags, n_out[2], n_shrink, n_evals, slot_ok[2], cur, tot_evals, n_caps, rkind[2], zsrc[2],
+  // build_list, dirty, slow_rows[2], stream_rows[2], then the active counter and the three list counts
+  const size_t nd = (size_t)k * (1 + 1 + kMaxBlock + 2 + 26 + 2 + 4 * kMaxDet + 6 * kMaxDet);
+  const size_t ni = (size_t)k * (1 + 2 + 1 + 1 + 2 + 3 + 2 + 2 + 1 + 1 + 2 + 2) + 4;
   char* m = nullptr;
-  gw_status s = check_hip(hipMalloc((void**)&m, nd * sizeof(double) + ni * sizeof(int32_t)), "slice workspace");
+  // three 64-bit counters first, then the doubles and the ints
+  gw_status s = check_hip(hipMalloc((void**)&m, 32 + nd * sizeof(double) + ni * sizeof(int32_t)), "slice workspace");
   if (s != GW_OK) return s;
-  double* dp = (double*)m;
+  ws->S.kind_tot = (unsigned long long*)m;
+  double* dp = (double*)(m + 32);
   ws->S.t_lo = dp; dp += k;
   ws->S.t_hi = dp; dp += k;
   ws->S.d = dp; dp += k * kMaxBlock;
   ws->S.cand_t = dp; dp += 2 * k;
   ws->cand = dp; dp += 26 * k;
   ws->cand_logl = dp; dp += 2 * k;
+  ws->S.zrow = dp; dp += 4 * kMaxDet * k;
+  ws->S.zc = dp; dp += 6 * kMaxDet * k;
   int32_t* ip = (int32_t*)dp;
   ws->S.flags = ip; ip += k;
   ws->S.n_out = ip; ip += 2 * k;
@@ -577,10 +805,34 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
   ws->S.cur = ip; ip += k;
   ws->S.tot_evals = ip; ip += k;
   ws->S.n_caps = ip; ip += k;
-  ws->S.n_active = ip;
+  ws->S.rkind = ip; ip += 2 * k;
+  ws->S.zsrc = ip; ip += 2 * k;
+  ws->S.build_list = ip; ip += k;
+  ws->S.dirty = ip; ip += k;
+  ws->S.slow_rows = ip; ip += 2 * k;
+  ws->S.stream_rows = ip; ip += 2 * k;
+  ws->S.n_active = ip; ip += 1;
+  ws->S.counts = ip;
   ws->mem = m;
   ws->cap = k;
   *out = ws;
+  return GW_OK;
+}
+
+// Waveform cache of k slots (grown on demand; at most 64 GiB).
+static gw_status slice_wcache(gw_ctx* ctx, gw_slice_ws* ws, int64_t k) {
+  const int64_t f2 = wmom_slot_f2(ctx);
+  if (ws->wc && ws->cap_wc >= k && ws->slot_f2 == f2) return GW_OK;
+  if ((double)k * (double)f2 * sizeof(float2) > 64.0 * (1ull << 30))
+    return set_error(GW_EINVAL, "slice_sweep: waveform cache of %lld chains x %lld bins exceeds 64 GiB",
+                     (long long)k, (long long)f2);
+  if (ws->wc) (void)hipFree(ws->wc);
+  ws->wc = nullptr;
+  ws->cap_wc = 0;
+  gw_status s = check_hip(hipMalloc((void**)&ws->wc, (size_t)k * f2 * sizeof(float2)), "waveform cache");
+  if (s != GW_OK) return s;
+  ws->cap_wc = k;
+  ws->slot_f2 = f2;
   return GW_OK;
 }
 
@@ -592,8 +844,10 @@ void slice_free(gw_ctx* ctx) {
   if (ws->graph) (void)hipGraphDestroy(ws->graph);
   if (ws->cap_stream) (void)hipStreamDestroy(ws->cap_stream);
   if (ws->mem) (void)hipFree(ws->mem);
+  if (ws->wc) (void)hipFree(ws->wc);
   if (ws->dev) (void)hipFree(ws->dev);
   if (ws->h_active) (void)hipHostFree(ws->h_active);
+  if (ws->h_kinds) (void)hipHostFree(ws->h_kinds);
   delete ws;
   ctx->slice = nullptr;
 }

@@ -10,7 +10,8 @@ points.  By default a whole sweep is one ``slice_sweep`` call, in which each
 chain moves on to its next block as soon as it has finished one; with
 ``async_sweep=False`` every block is a ``slice_step`` call of its own (all
 chains finish the block before any starts the next).  Both give the same
-chains bit for bit.
+chains bit for bit.  With ``cache=True`` (full band) the sweep keeps each
+chain's waveform and reuses it on the extrinsic blocks (Sec. III.B).
 
 The host keeps the FP64 evidence bookkeeping (the k deletions taken in order
 with live counts m, m-1, ..., m-k+1), the start-point choice and the block
@@ -45,7 +46,8 @@ def _logsumexp(a):
 class NestedSampler:
     def __init__(self, ctx, n_live: int = 1000, n_delete: int = 125, seed: int = 6, dlogz: float = 0.1,
                  blocks=BLOCKS, like: int = _lib.GW_HET, prec: int = _lib.GW_PREC_MIXED, sweeps: int = 1,
-                 w: float = 1.0, max_out: int = 10, max_shrink: int = 100, async_sweep: bool = True):
+                 w: float = 1.0, max_out: int = 10, max_shrink: int = 100, async_sweep: bool = True,
+                 cache: bool = False):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -56,6 +58,9 @@ class NestedSampler:
         self.like, self.prec = like, prec
         self.sweeps, self.w, self.max_out, self.max_shrink = sweeps, w, max_out, max_shrink
         self.async_sweep = bool(async_sweep)
+        self.cache = bool(cache)
+        if self.cache and (like != _lib.GW_FULL or not self.async_sweep):
+            raise ValueError("the waveform cache needs like=GW_FULL and async_sweep=True")
         self.rng = np.random.default_rng(self.seed)
         self.dev = torch.device("cuda", ctx.device)
         x0 = self.rng.uniform(size=(self.m, N_DIM))
@@ -69,6 +74,7 @@ class NestedSampler:
         self.iteration = 0
         self.counter = 0
         self.n_evals = self.m
+        self.eval_kinds = np.zeros(3, np.int64)  # with the cache: full, cached waveform, cached sums
         self.wall = 0.0
 
     # -- likelihood of unit-cube points (initial live set) ------------------
@@ -124,9 +130,12 @@ class NestedSampler:
         ne = torch.zeros(self.k, dtype=torch.int32, device=self.dev)
         for _ in range(self.sweeps):
             if self.async_sweep:
-                _lib.slice_sweep(self.ctx.handle, xn, ln, lstar, self.blocks, chols, seed=self.seed,
+                kinds = _lib.slice_sweep(self.ctx.handle, xn, ln, lstar, self.blocks, chols, seed=self.seed,
                                  counter=self.counter, w=self.w, max_out=self.max_out, max_shrink=self.max_shrink,
-                                 like=self.like, marg=_lib.GW_MARG_PHASE_DIST, prec=self.prec, n_evals=ne)
+                                 like=self.like, marg=_lib.GW_MARG_PHASE_DIST, prec=self.prec, n_evals=ne,
+                                 use_cache=self.cache)
+                if kinds is not None:
+                    self.eval_kinds += np.array(kinds, np.int64)
                 self.n_evals += int(ne.sum().item())
                 self.counter += len(self.blocks)
                 continue
@@ -165,8 +174,11 @@ class NestedSampler:
         p = np.exp(all_logw - log_z)
         h = float(np.sum(p * all_logl) - log_z)
         ess = float(1.0 / np.sum(p * p))
-        return dict(log_z=log_z, log_z_err=math.sqrt(max(h, 0.0) / self.m), h=h, iterations=self.iteration,
-                    n_evals=self.n_evals, wall_s=self.wall, ess=ess)
+        out = dict(log_z=log_z, log_z_err=math.sqrt(max(h, 0.0) / self.m), h=h, iterations=self.iteration,
+                   n_evals=self.n_evals, wall_s=self.wall, ess=ess)
+        if self.cache:
+            out["eval_kinds"] = [int(v) for v in self.eval_kinds]
+        return out
 
     def samples(self):
         """(unit-cube points, normalised posterior weights) of dead + live points."""
@@ -181,7 +193,7 @@ class NestedSampler:
         np.savez(path, x=self.x.cpu().numpy(), logl=self.logl.cpu().numpy(),
                  dead_logl=np.array(self.dead_logl), dead_logw=np.array(self.dead_logw),
                  dead_x=np.array(self.dead_x).reshape(-1, N_DIM), log_x=self.log_x, iteration=self.iteration,
-                 counter=self.counter, n_evals=self.n_evals,
+                 counter=self.counter, n_evals=self.n_evals, eval_kinds=self.eval_kinds,
                  rng=np.frombuffer(repr(self.rng.bit_generator.state).encode(), dtype=np.uint8))
 
     def load(self, path: str):
@@ -196,4 +208,5 @@ class NestedSampler:
         self.iteration = int(d["iteration"])
         self.counter = int(d["counter"])
         self.n_evals = int(d["n_evals"])
+        self.eval_kinds = np.array(d["eval_kinds"], np.int64)
         self.rng.bit_generator.state = ast.literal_eval(bytes(d["rng"]).decode())
