@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -334,13 +335,18 @@ def cache_leg(gw, torch, prob, steps, warmup, mixed_value):
                 ms, nl = gw._lib.gw_profile_read(ctx.handle)
                 gw._lib.gw_profile_enable(ctx.handle, False)
                 k_ms = ms / max(nl, 1)
-                f2 = (prob.n_freq + 15) // 16 * 16
-                # algorithmic HBM bytes: each used waveform once (8 B per bin) plus the
-                # weighted data of the 3 detectors (48 B per bin)
-                nbytes = n_slots * f2 * 8 + prob.n_freq * 48
-                flops = n * prob.n_freq * 3 * 14
-                r["kernel"] = "k_stream<3>"
+                # moment cache: blocks of B bins (256 at df = 1/128 Hz), 16 moments per block and detector,
+                # FP32 complex; algorithmic bytes = each used slot's moments once
+                blk = 4
+                while blk < 512 and math.pi * prob.df * (2 * blk) * 0.25 <= 1.61:
+                    blk *= 2
+                n_blk = -(-prob.n_freq // blk)
+                nbytes = n_slots * n_blk * 3 * 16 * 8
+                # per row, block and detector: 15 Horner steps (2 FMA) + block factor and rotation (8 flop-pairs)
+                flops = n * n_blk * 3 * (15 * 2 + 8) * 2
+                r["kernel"] = "k_wmom<3>"
                 r["kernel_ms"] = k_ms
+                r["moment_block_bins"] = blk
                 r["roofline"] = {"bound": "hbm", "achieved": nbytes / (k_ms * 1e-3) / 1e9, "peak": 8000.0,
                                  "unit": "GB/s", "frac": nbytes / (k_ms * 1e-3) / 1e9 / 8000.0,
                                  "bytes_per_launch": nbytes,
@@ -349,9 +355,9 @@ def cache_leg(gw, torch, prob, steps, warmup, mixed_value):
             res[f"kind{kind}"] = r
         cache.close()
     res["unit"] = "logL evals/s"
-    res["workload"] = ("waveform cache on the 128 s grid: 2048 cached waveforms, 4096 rows (two per slot); "
-                       "kind 1 = sky/t_c/psi/iota/d_L moves on the cached waveform, kind 2 = psi/iota/d_L moves "
-                       "on the cached overlaps; phase+distance marginalised")
+    res["workload"] = ("waveform cache on the 128 s grid: 2048 cached waveforms (block moments), 4096 rows (two "
+                       "per slot); kind 1 = sky/t_c/psi/iota/d_L moves on the cached moments, kind 2 = "
+                       "psi/iota/d_L moves on the cached overlaps; phase+distance marginalised")
     return res
 
 
