@@ -10,7 +10,15 @@ Marginalisations (Sec. III.A and the grid-marginalisation appendix):
   log L = -<d|d>/2 - <h|h>/2 + ln I0(|Z|);
 * distance on a grid d_j with normalised log-weights w_j of a d^2 prior:
   log L = -<d|d>/2 + logsumexp_j [ w_j - <h|h>_1 / (2 d_j^2) + ln I0(|Z_1| / d_j) ]
-  where the subscript 1 means the template at d_L = 1 Mpc.
+  where the subscript 1 means the template at d_L = 1 Mpc;
+* coalescence time together with the phase, uniform on [-W, W] (the
+  appendix's grid sum over time shifts, which the paper evaluates by FFT on
+  the uniform grid): on the grid t_j = j delta, |t_j| <= W, with delta = T / N,
+  T = 1 / df and N the smallest power of two >= 2 (k0 + n_freq - 1) (the
+  sampling interval of the segment),
+  log L = -<d|d>/2 - <h|h>/2 + ln[ (1 / N_t) sum_j I0(|Z(t_j)|) ],
+  Z(t) the phase-free overlap of the template shifted by t (h -> h exp(-2 pi i f t)),
+  the template evaluated at t_c = 0.
 
 Problems are any object with attributes k0, n_freq, df, data [n_det, n_freq]
 complex, psd [n_det, n_freq], det_tensor [n_det, 3, 3], det_pos [n_det, 3],
@@ -26,7 +34,8 @@ from scipy.special import i0e, logsumexp
 
 from . import detector, waveform
 
-PLAIN, PHASE, PHASE_DIST = 0, 1, 2
+PLAIN, PHASE, PHASE_DIST, PHASE_TIME = 0, 1, 2, 3
+TIME_WINDOW = 0.1  # half-width (s) of the uniform t_c prior that PHASE_TIME marginalises
 
 
 def freqs(prob) -> np.ndarray:
@@ -86,6 +95,41 @@ def overlap(theta: np.ndarray, prob):
     return complex(z), hh
 
 
+def time_grid(prob, window: float | None = None) -> np.ndarray:
+    """Time shifts t_j = j delta with |t_j| <= window (TIME_WINDOW by default;
+    see the module docstring)."""
+    if window is None:
+        window = TIME_WINDOW
+    top = 2 * (int(prob.k0) + int(prob.n_freq) - 1)
+    n = 1
+    while n < top:
+        n *= 2
+    delta = 1.0 / (n * prob.df)
+    jmax = int(math.floor(window / delta + 1e-9))
+    return np.arange(-jmax, jmax + 1, dtype=np.float64) * delta
+
+
+def overlap_weights(theta: np.ndarray, prob):
+    """a_k = sum_i 4 df d_ik* h_ik / S_ik (so that Z = sum_k a_k) and <h|h>."""
+    h = strain(np.asarray(theta, dtype=np.float64), prob)
+    a = np.zeros(prob.n_freq, dtype=np.complex128)
+    hh = 0.0
+    for i in range(h.shape[0]):
+        a += 4.0 * prob.df * np.conj(prob.data[i]) * h[i] / prob.psd[i]
+        hh += inner(h[i], h[i], prob.psd[i], prob.df)
+    return a, hh
+
+
+def time_shifted_overlaps(a: np.ndarray, prob, t: np.ndarray, rows: int = 16) -> np.ndarray:
+    """Z(t_j) = sum_k a_k exp(-2 pi i f_k t_j), by direct summation."""
+    f = freqs(prob)
+    out = np.empty(t.size, dtype=np.complex128)
+    for j0 in range(0, t.size, rows):
+        tt = t[j0:j0 + rows]
+        out[j0:j0 + rows] = np.exp(-2j * math.pi * np.outer(tt, f)) @ a
+    return out
+
+
 def loglike(theta: np.ndarray, prob, marg: int = PLAIN, dd: float | None = None) -> float:
     """Log-likelihood of one parameter vector in marginalisation mode ``marg``."""
     if not is_physical(theta, marg):
@@ -101,6 +145,12 @@ def loglike(theta: np.ndarray, prob, marg: int = PLAIN, dd: float | None = None)
             out -= 0.5 * inner(h[i], h[i], prob.psd[i], prob.df)
         return out
     th[11] = 0.0
+    if marg == PHASE_TIME:
+        th[12] = 0.0
+        a, hh = overlap_weights(th, prob)
+        t = time_grid(prob)
+        z = time_shifted_overlaps(a, prob, t)
+        return -0.5 * dd - 0.5 * hh + float(logsumexp(log_i0(np.abs(z)))) - math.log(t.size)
     if marg == PHASE_DIST:
         th[6] = 1.0
     z, hh = overlap(th, prob)

@@ -1,0 +1,92 @@
+"""Pins of the oracle's coalescence-time (and phase) marginal, PHASE_TIME.
+
+The marginal is a grid sum over time shifts t_j = j delta (the sampling
+interval of the segment) of I0(|Z(t_j)|), Z(t) the overlap of the template
+shifted by t.  It is pinned against:
+* a library routine: on the grid t_j = j delta the shifted overlaps are a
+  discrete Fourier transform of the per-bin overlap weights placed at their
+  frequency indices, which numpy's FFT computes independently;
+* the special case of a one-point grid, which is the phase marginal at t_c = 0;
+* the time-shift property: an injection at t_c = s delta moves the overlap
+  sequence by s grid points, with its peak at j = s (a wrong sign of the
+  shift exponent would put it at -s);
+* the zero-signal limit, where the grid average of I0(0) = 1 leaves -<d|d>/2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gwsynth
+from oracle import likelihood as L
+
+
+@pytest.fixture(scope="module")
+def prob():
+    cfg = gwsynth.CONFIGS["cfg1"]
+    p = gwsynth.make_problem(cfg["duration"], cfg["f_min"], cfg["f_max"], psd_scale=1e-49)
+    th = gwsynth.prior_draws(gwsynth.SEEDS["injection"], 1)[0]
+    p.theta_inj = th
+    return p
+
+
+def test_grid(prob):
+    t = L.time_grid(prob)
+    delta = t[1] - t[0]
+    # 8 s at 20-512 Hz: the segment's sampling interval is 1/1024 s
+    assert delta == pytest.approx(1.0 / 1024.0, rel=1e-15)
+    assert t[0] == -t[-1] and abs(t[-1]) <= L.TIME_WINDOW < abs(t[-1]) + delta
+    assert t.size == 2 * 102 + 1
+
+
+def test_shifted_overlaps_are_an_fft(prob):
+    th = prob.theta_inj.copy()
+    a, _ = L.overlap_weights(th, prob)
+    t = L.time_grid(prob)
+    z = L.time_shifted_overlaps(a, prob, t)
+    n = int(round(1.0 / ((t[1] - t[0]) * prob.df)))
+    x = np.zeros(n, dtype=np.complex128)
+    x[prob.k0:prob.k0 + prob.n_freq] = a
+    fx = np.fft.fft(x)
+    j = np.rint(t / (t[1] - t[0])).astype(int)
+    assert np.max(np.abs(z - fx[j % n])) < 1e-9 * np.max(np.abs(z))
+
+
+def test_one_point_grid_is_phase_marginal(prob, monkeypatch):
+    dd = 3.0
+    th = prob.theta_inj.copy()
+    th[12] = 0.0
+    monkeypatch.setattr(L, "TIME_WINDOW", 0.0)
+    assert L.time_grid(prob).size == 1
+    v = L.loglike(th, prob, L.PHASE_TIME, dd)
+    assert v == pytest.approx(L.loglike(th, prob, L.PHASE, dd), abs=1e-9)
+
+
+def test_time_shift_moves_the_overlap_peak(prob):
+    # noise-free data: the injection itself, at t_c = 0 and at t_c = 7 delta
+    t = L.time_grid(prob)
+    delta = t[1] - t[0]
+    th = prob.theta_inj.copy()
+    th[6] = 40.0
+    th[11] = 0.0
+    th[12] = 0.0
+    base = gwsynth.make_problem(8.0, 20.0, 512.0, psd_scale=1e-49)
+    seqs = []
+    for s in (0, 7):
+        p = base
+        inj = th.copy()
+        inj[12] = s * delta
+        p.data = L.strain(inj, p)
+        a, _ = L.overlap_weights(th, p)
+        seqs.append(np.abs(L.time_shifted_overlaps(a, p, t)))
+    mid = t.size // 2
+    assert int(np.argmax(seqs[0])) == mid
+    assert int(np.argmax(seqs[1])) == mid + 7
+    assert np.max(np.abs(seqs[1][7:] - seqs[0][:-7])) < 1e-9 * np.max(seqs[0])
+
+
+def test_zero_signal_limit(prob):
+    dd = L.data_inner(prob)
+    th = prob.theta_inj.copy()
+    th[6] = 1e30  # amplitude ~ 1e-30 of the injection's: Z and <h|h> vanish
+    assert L.loglike(th, prob, L.PHASE_TIME, dd) == pytest.approx(-0.5 * dd, abs=1e-9)
