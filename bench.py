@@ -62,9 +62,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="full,het,cache,nested,nested_full,prescreen",
-                    help="comma list of legs to run: full (always timed), het, cache, nested, nested_full, "
-                         "prescreen, copy")
+    ap.add_argument("--legs", default="full,het,tmarg,cache,nested,nested_full,prescreen",
+                    help="comma list of legs to run: full (always timed), het, tmarg, cache, nested, "
+                         "nested_full, prescreen, copy")
     return ap.parse_args()
 
 
@@ -361,6 +361,36 @@ def cache_leg(gw, torch, prob, steps, warmup, mixed_value):
     return res
 
 
+def tmarg_leg(gw, torch, ctx, theta, steps, warmup, mixed_value):
+    """Phase + coalescence-time marginal on the same 4096 proposals of the
+    128 s band: grid t_j = j / 4096 s over |t| <= 0.1 s (819 points), block
+    moments of 512 bins and 16 FFTs of length 1024 per proposal."""
+    n = theta.shape[0]
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    res = {}
+    for name, prec in (("mixed", gw.GW_PREC_MIXED), ("fp64", gw.GW_PREC_FP64)):
+        for _ in range(warmup):
+            ctx.loglike(theta, gw.GW_FULL, gw.GW_MARG_PHASE_TIME, prec, out=out)
+        torch.cuda.synchronize()
+        gw._lib.gw_profile_read(ctx.handle)
+        gw._lib.gw_profile_enable(ctx.handle, True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.loglike(theta, gw.GW_FULL, gw.GW_MARG_PHASE_TIME, prec, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ms, nl = gw._lib.gw_profile_read(ctx.handle)
+        gw._lib.gw_profile_enable(ctx.handle, False)
+        res[name] = {"value": n / dt, "ms_per_batch": dt * 1e3, "k_tmom_ms": ms / max(nl, 1)}
+    delta, n_t, p_len, blk = gw.gw_time_grid_info(ctx.handle)
+    res["cost_vs_distance_marginal_mixed"] = mixed_value / res["mixed"]["value"]
+    res.update({"unit": "logL evals/s", "batch": n, "grid_points": n_t, "delta_s": delta, "fft_len": p_len,
+                "block_bins": blk,
+                "workload": "phase+time marginal on the 128 s full band, 4096 prior draws, t_c grid of the "
+                            "segment's sampling interval over +-0.1 s"})
+    return res
+
+
 def nested_full_leg(gw, torch):
     """Nested sampling on the full band (128 s, 259,585 bins per detector,
     mixed form), settings as the heterodyned run, with and without the
@@ -455,6 +485,9 @@ def main():
         dt_fp, k_fp = time_steps(ctx, theta, out, fp_steps, 2, gw.GW_PREC_FP64, marg, torch, gw, profile=True)
         fp = out.clone()
         dlogl = float(torch.max(torch.abs(mix - fp)).item())
+        tm = None
+        if "tmarg" in set(args.legs.split(",")):
+            tm = tmarg_leg(gw, torch, ctx, theta, max(5, args.steps // 2), 2, n * args.steps / dt_mix)
     value = n * args.steps / dt_mix
     fp_value = n * fp_steps / dt_fp
     units = n * prob.n_freq
@@ -493,6 +526,8 @@ def main():
     legs = set(args.legs.split(","))
     if "het" in legs:
         res["heterodyned"] = het_leg(gw, torch, prob, th_inj, max(5, args.steps // 2), 2)
+    if tm is not None:
+        res["time_marginal"] = tm
     if "cache" in legs:
         res["waveform_cache"] = cache_leg(gw, torch, prob, args.steps, args.warmup, value)
     if "nested" in legs:

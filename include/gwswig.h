@@ -55,8 +55,10 @@ typedef enum {
 
 /* Likelihood kind. */
 enum { GW_FULL = 0, GW_HET = 1 };
-/* Marginalisation (Sec. III.A): none, phi_c, phi_c and d_L. */
-enum { GW_MARG_NONE = 0, GW_MARG_PHASE = 1, GW_MARG_PHASE_DIST = 2 };
+/* Marginalisation (Sec. III.A and the appendix on grid marginals): none,
+ * phi_c, phi_c and d_L, phi_c and t_c (full band only; see
+ * gw_set_time_window). */
+enum { GW_MARG_NONE = 0, GW_MARG_PHASE = 1, GW_MARG_PHASE_DIST = 2, GW_MARG_PHASE_TIME = 3 };
 /* Arithmetic: plain FP64, or FP64 phase with FP32 phasors and sums. */
 enum { GW_PREC_FP64 = 0, GW_PREC_MIXED = 1 };
 
@@ -123,7 +125,8 @@ gw_status gw_data_inner(const gw_ctx* ctx, double* dd_out);
  *   theta   device [n, 13] FP64 parameter vectors
  *   n       batch size (0 is a no-op)
  *   like    GW_FULL or GW_HET (GW_HET needs heterodyne_setup first)
- *   marg    GW_MARG_NONE, GW_MARG_PHASE or GW_MARG_PHASE_DIST
+ *   marg    GW_MARG_NONE, GW_MARG_PHASE, GW_MARG_PHASE_DIST or (like =
+ *           GW_FULL) GW_MARG_PHASE_TIME
  *   prec    GW_PREC_FP64 or GW_PREC_MIXED
  *   logl    device [n] FP64 output
  *   stream  hipStream_t or NULL
@@ -132,6 +135,26 @@ gw_status gw_data_inner(const gw_ctx* ctx, double* dd_out);
  */
 gw_status loglike_batch(gw_ctx* ctx, const double* theta, int64_t n, int32_t like,
                         int32_t marg, int32_t prec, double* logl, void* stream);
+
+/*
+ * Coalescence-time marginal (GW_MARG_PHASE_TIME, with the phase marginal;
+ * the appendix's grid sum over time shifts, evaluated by FFT on the uniform
+ * grid).  The t_c column of theta is ignored; d_L is used.  On the grid
+ * t_j = j delta, |t_j| <= W, delta = 1 / (N df) with N the smallest power of
+ * two >= 2 (k0 + n_freq - 1) (the segment's sampling interval):
+ *   log L = -<d|d>/2 - <h|h>/2 + ln[ (1/N_t) sum_j I0(|Z(t_j)|) ],
+ * Z(t) the overlap of the template shifted by t (template at t_c = 0).  The
+ * library evaluates Z on the whole grid with 16 FFTs of length P (the
+ * smallest power of two >= N_t) over blocks of N / P bins, within which the
+ * time shift is expanded to 16 terms (first dropped term below 1e-10 of the
+ * block's overlap sum).  W defaults to 0.1 s; gw_set_time_window changes it
+ * (GW_ENOTSUP if the grid would exceed 2048 points).  gw_time_grid_info
+ * reports delta, N_t, P and the block length.  Work space: n x (n_freq / B)
+ * x 256 bytes per call.
+ */
+gw_status gw_set_time_window(gw_ctx* ctx, double window);
+gw_status gw_time_grid_info(const gw_ctx* ctx, double* delta, int32_t* n_points, int32_t* fft_len,
+                            int32_t* block_bins);
 
 /*
  * Projected templates h_i(f_k) on the full grid (Sec. III.A): one parameter

@@ -8,11 +8,11 @@ every call that needs it raises if it has not been built.
 """
 from . import _lib  # noqa: F401
 from ._lib import (  # noqa: F401
-    GW_FULL, GW_HET, GW_MARG_NONE, GW_MARG_PHASE, GW_MARG_PHASE_DIST, GW_PREC_FP64, GW_PREC_MIXED,
+    GW_FULL, GW_HET, GW_MARG_NONE, GW_MARG_PHASE, GW_MARG_PHASE_DIST, GW_MARG_PHASE_TIME, GW_PREC_FP64, GW_PREC_MIXED,
     GwError, gw_ctx_create, gw_ctx_destroy, gw_data_inner, gw_last_error, gw_set_full_shape, gw_template,
     gw_version, loglike_batch, heterodyne_setup, gw_het_info, loglike_batch_uneven, gw_set_het_shape,
     gw_graph_info, gw_profile_enable, gw_profile_read, slice_step, slice_sweep, gw_prior_transform, Mlp,
-    gw_set_full_kernel, gw_full_info, gw_phasor_gain, WaveformCache,
+    gw_set_full_kernel, gw_full_info, gw_phasor_gain, WaveformCache, gw_set_time_window, gw_time_grid_info,
 )
 
 

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libgwswig.so")
 
 GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_ESTATE, GW_ENOTSUP = 0, -1, -2, -3, -4, -5
 GW_FULL, GW_HET = 0, 1
-GW_MARG_NONE, GW_MARG_PHASE, GW_MARG_PHASE_DIST = 0, 1, 2
+GW_MARG_NONE, GW_MARG_PHASE, GW_MARG_PHASE_DIST, GW_MARG_PHASE_TIME = 0, 1, 2, 3
 GW_PREC_FP64, GW_PREC_MIXED = 0, 1
 GW_MAX_DET = 4
 GW_NPARAM = 13
@@ -122,6 +122,9 @@ _SIGS = {
     "gw_graph_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "slice_step": (ctypes.c_int, [_P, ctypes.POINTER(gw_slice_args), _P]),
     "slice_sweep": (ctypes.c_int, [_P, ctypes.POINTER(gw_sweep_args), _P]),
+    "gw_set_time_window": (ctypes.c_int, [_P, ctypes.c_double]),
+    "gw_time_grid_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "gw_wcache_create": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(_P)]),
     "gw_wcache_destroy": (ctypes.c_int, [_P]),
     "gw_wcache_update": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P]),
@@ -593,3 +596,17 @@ class WaveformCache:
         check(load().gw_wcache_loglike(self._h, _tensor_ptr(theta), slots.data_ptr(), n, int(kind), marg, prec,
                                        out.data_ptr(), _stream_ptr(stream)), "gw_wcache_loglike")
         return out
+
+
+def gw_set_time_window(ctx, window: float):
+    """Half-width (s) of the uniform t_c prior of GW_MARG_PHASE_TIME."""
+    check(load().gw_set_time_window(ctx, float(window)), "gw_set_time_window")
+
+
+def gw_time_grid_info(ctx):
+    """(delta, grid points, FFT length, bins per block) of the time marginal."""
+    d = ctypes.c_double()
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(load().gw_time_grid_info(ctx, ctypes.byref(d), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+          "gw_time_grid_info")
+    return d.value, a.value, b.value, c.value

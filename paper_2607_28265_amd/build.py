@@ -18,7 +18,8 @@ BUILD_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libgwswig.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 
-SOURCES = ["gw_api.hip", "gw_full.hip", "gw_het.hip", "gw_slice.hip", "gw_mlp.hip", "gw_wcache.hip"]
+SOURCES = ["gw_api.hip", "gw_full.hip", "gw_het.hip", "gw_slice.hip", "gw_mlp.hip", "gw_wcache.hip",
+           "gw_tmarg.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 instructions are kept out of the generated code.

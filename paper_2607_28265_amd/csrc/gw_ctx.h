@@ -55,6 +55,12 @@ struct gw_ctx {
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
   int prof_used = 0;
+  // time marginal: window half-width (s), FFT twiddles and moment workspace
+  double tm_window = 0.1;
+  int tm_P = 0;
+  double* tm_tw = nullptr;
+  double* tm_mom = nullptr;
+  int64_t tm_mom_cap = 0;
   gw_het_state* het = nullptr;
   gw_graph_cache* graphs = nullptr;
   gw_slice_ws* slice = nullptr;
@@ -129,5 +135,7 @@ void graphs_free(gw_ctx* ctx);
 void slice_free(gw_ctx* ctx);
 gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl,
                       hipStream_t st);
+// Full-band phase+time marginal (GW_MARG_PHASE_TIME).
+gw_status loglike_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, hipStream_t st);
 
 }  // namespace gw

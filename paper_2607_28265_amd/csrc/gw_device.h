@@ -55,7 +55,7 @@ __device__ inline bool finite_d(double v) { return __builtin_isfinite(v); }
 
 // Per-proposal prologue.  Writes C_NCOEF values into out[] (stride ``ld``).
 // marg: 0 plain, 1 phase-marginalised (phi_c := 0), 2 phase+distance
-// (phi_c := 0, d_L := 1 Mpc).
+// (phi_c := 0, d_L := 1 Mpc), 3 phase+time (phi_c := 0, t_c := 0).
 __device__ inline void prologue(const double* __restrict__ th, int marg, const Geom& g,
                                 double* out, int64_t ld) {
   double v[13];
@@ -68,7 +68,7 @@ __device__ inline void prologue(const double* __restrict__ th, int marg, const G
   double dl = v[6];
   const double iota = v[7], ra = v[8], dec = v[9], psi = v[10];
   double phic = v[11];
-  const double tc = v[12];
+  double tc = v[12];
   ok = ok && mc > 0.0 && q > 0.0 && q <= 1.0 && fabs(c1) < 1.0 && fabs(c2) < 1.0;
   if (marg != 2) ok = ok && dl > 0.0;
   if (!ok) {
@@ -78,6 +78,7 @@ __device__ inline void prologue(const double* __restrict__ th, int marg, const G
   }
   if (marg != 0) phic = 0.0;
   if (marg == 2) dl = 1.0;
+  if (marg == 3) tc = 0.0;
 
   // Masses: X1 = m1/M >= X2, eta = X1 X2, delta = X1 - X2.
   const double x1 = 1.0 / (1.0 + q);
