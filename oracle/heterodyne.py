@@ -139,6 +139,16 @@ def loglike(theta: np.ndarray, prob, het: HetData, marg: int = likelihood.PLAIN,
         th[11] = 0.0
     if marg == likelihood.PHASE_DIST:
         th[6] = 1.0
+    if marg == likelihood.PHASE_TIME:
+        # the phase-marginal binned likelihood at every shift of the time grid
+        # (template at t_c = t_j), averaged over the grid
+        t = likelihood.time_grid(prob)
+        vals = np.empty(t.size)
+        for j, tj in enumerate(t):
+            th[12] = tj
+            z, hh = overlaps(th, prob, het)
+            vals[j] = -0.5 * float(np.sum(hh)) + float(likelihood.log_i0(abs(complex(np.sum(z)))))
+        return -0.5 * dd + float(logsumexp(vals)) - math.log(t.size)
     z, hh = overlaps(th, prob, het)
     hh_t = float(np.sum(hh))
     if marg == likelihood.PLAIN:
