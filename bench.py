@@ -132,6 +132,24 @@ def het_leg(gw, torch, prob, th_inj, steps, warmup):
             ms, nl = gw._lib.gw_profile_read(ctx.handle)
             gw._lib.gw_profile_enable(ctx.handle, False)
             res[name] = {"value": n * steps / dt, "ms_per_batch": dt / steps * 1e3, "kernel_ms": ms / max(nl, 1)}
+        # phase+time marginal on the same bins and proposals (one batched GEMM against the grid's phasors)
+        tm = {}
+        for name, prec in (("mixed", gw.GW_PREC_MIXED), ("fp64", gw.GW_PREC_FP64)):
+            for _ in range(2):
+                ctx.loglike(theta, gw.GW_HET, gw.GW_MARG_PHASE_TIME, prec, out=out)
+            torch.cuda.synchronize()
+            gw._lib.gw_profile_read(ctx.handle)
+            gw._lib.gw_profile_enable(ctx.handle, True)
+            reps = max(3, steps // 2)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.loglike(theta, gw.GW_HET, gw.GW_MARG_PHASE_TIME, prec, out=out)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            ms, nl = gw._lib.gw_profile_read(ctx.handle)
+            gw._lib.gw_profile_enable(ctx.handle, False)
+            tm[name] = {"value": n / dt, "ms_per_batch": dt * 1e3, "gemm_ms": ms / max(nl, 1)}
+        res["time_marginal"] = tm
         n_graphs, inst_ms = gw._lib.gw_graph_info(ctx.handle)
     res.update({"unit": "logL evals/s", "batch": n, "n_sub": int(subs.shape[0]), "n_bins": 500,
                 "graph_instantiate_ms": inst_ms,

@@ -56,7 +56,7 @@ typedef enum {
 /* Likelihood kind. */
 enum { GW_FULL = 0, GW_HET = 1 };
 /* Marginalisation (Sec. III.A and the appendix on grid marginals): none,
- * phi_c, phi_c and d_L, phi_c and t_c (full band only; see
+ * phi_c, phi_c and d_L, phi_c and t_c (loglike_batch only; see
  * gw_set_time_window). */
 enum { GW_MARG_NONE = 0, GW_MARG_PHASE = 1, GW_MARG_PHASE_DIST = 2, GW_MARG_PHASE_TIME = 3 };
 /* Arithmetic: plain FP64, or FP64 phase with FP32 phasors and sums. */
@@ -125,8 +125,8 @@ gw_status gw_data_inner(const gw_ctx* ctx, double* dd_out);
  *   theta   device [n, 13] FP64 parameter vectors
  *   n       batch size (0 is a no-op)
  *   like    GW_FULL or GW_HET (GW_HET needs heterodyne_setup first)
- *   marg    GW_MARG_NONE, GW_MARG_PHASE, GW_MARG_PHASE_DIST or (like =
- *           GW_FULL) GW_MARG_PHASE_TIME
+ *   marg    GW_MARG_NONE, GW_MARG_PHASE, GW_MARG_PHASE_DIST or
+ *           GW_MARG_PHASE_TIME
  *   prec    GW_PREC_FP64 or GW_PREC_MIXED
  *   logl    device [n] FP64 output
  *   stream  hipStream_t or NULL
@@ -151,6 +151,13 @@ gw_status loglike_batch(gw_ctx* ctx, const double* theta, int64_t n, int32_t lik
  * (GW_ENOTSUP if the grid would exceed 2048 points).  gw_time_grid_info
  * reports delta, N_t, P and the block length.  Work space: n x (n_freq / B)
  * x 256 bytes per call.
+ * With like = GW_HET the same grid sum runs on the binned likelihood, the
+ * appendix's direct summation on the heterodyned bins: at every t_j the
+ * phase-marginal binned log L of the template shifted by t_j (the binned
+ * <h|h> depends on t_j through the bin widths).  The library forms per-row
+ * edge weights and contracts them with the proposal-independent phasors
+ * exp(-2 pi i f_e t_j) and exp(-2 pi i (f_e - f_e-1) t_j) in one batched FP64
+ * complex GEMM (rocBLAS); work space n x (n_edges + N_t) x 64 bytes.
  */
 gw_status gw_set_time_window(gw_ctx* ctx, double window);
 gw_status gw_time_grid_info(const gw_ctx* ctx, double* delta, int32_t* n_points, int32_t* fft_len,

@@ -6,6 +6,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <rocblas/rocblas.h>
+
 #include "gw_ctx.h"
 
 namespace {
@@ -227,6 +229,7 @@ gw_status gw_ctx_destroy(gw_ctx* ctx) {
   het_free(ctx);
   graphs_free(ctx);
   slice_free(ctx);
+  if (ctx->blas) (void)rocblas_destroy_handle((rocblas_handle)ctx->blas);
   for (hipEvent_t e : ctx->prof_ev)
     if (e) (void)hipEventDestroy(e);
   double* bufs[] = {ctx->bins, ctx->dist_tab, ctx->coef, ctx->partial, ctx->zbuf, ctx->tm_tw, ctx->tm_mom};
@@ -250,8 +253,6 @@ gw_status loglike_batch(gw_ctx* ctx, const double* theta, int64_t n, int32_t lik
   if (n > 0 && (!theta || !logl)) return set_error(GW_EINVAL, "loglike_batch: null theta or logl");
   if (like != GW_FULL && like != GW_HET) return set_error(GW_EINVAL, "loglike_batch: bad like=%d", like);
   if (marg < GW_MARG_NONE || marg > GW_MARG_PHASE_TIME) return set_error(GW_EINVAL, "loglike_batch: bad marg=%d", marg);
-  if (marg == GW_MARG_PHASE_TIME && like != GW_FULL)
-    return set_error(GW_ENOTSUP, "loglike_batch: the time marginal is built for the full band only");
   if (prec != GW_PREC_FP64 && prec != GW_PREC_MIXED) return set_error(GW_EINVAL, "loglike_batch: bad prec=%d", prec);
   if (marg == GW_MARG_PHASE_DIST && ctx->n_dist <= 0)
     return set_error(GW_ESTATE, "loglike_batch: distance marginal needs a distance grid");

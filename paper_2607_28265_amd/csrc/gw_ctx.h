@@ -61,6 +61,7 @@ struct gw_ctx {
   double* tm_tw = nullptr;
   double* tm_mom = nullptr;
   int64_t tm_mom_cap = 0;
+  void* blas = nullptr;            // rocBLAS handle (created on first use)
   gw_het_state* het = nullptr;
   gw_graph_cache* graphs = nullptr;
   gw_slice_ws* slice = nullptr;

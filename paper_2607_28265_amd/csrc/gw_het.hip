@@ -23,6 +23,8 @@
 #include <map>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "gw_ctx.h"
 
 // Device-resident arguments of the work-list kernels; a one-thread kernel
@@ -61,6 +63,11 @@ struct gw_het_state {
   int grid = 0;                  // workgroups (0 = heuristic)
   int ech = 0;                   // edge chunks (0 = heuristic)
   int64_t n_rows_last = 0;       // rows of the batch being enqueued (selects the distance form)
+  // time marginal: phasors of the edges and bin widths on the time grid,
+  // [2][n_edges][n_t] complex (E then F), built on first use for a grid
+  double* tm_ef = nullptr;
+  int tm_nt = 0;
+  double tm_delta = 0.0;
 };
 
 struct GraphKey {
@@ -584,6 +591,7 @@ __global__ void __launch_bounds__(64 * kHetDistWaves) k_het_dist(const HetArgs* 
 
 static void free_state(gw_het_state* h) {
   if (!h) return;
+  if (h->tm_ef) (void)hipFree(h->tm_ef);
   if (h->rec) (void)hipFree(h->rec);
   if (h->args) (void)hipFree(h->args);
   if (h->tile_pre) (void)hipFree(h->tile_pre);
@@ -773,8 +781,236 @@ void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech)
   *ech = ctx->het ? ctx->het->ech : 0;
 }
 
+// ---------------------------------------------------------------------------
+// Time marginal on the binned likelihood (the appendix's direct sum on the
+// heterodyned bins).  A shift t multiplies every edge phasor by
+// exp(-2 pi i f_e t), so with per-row edge weights
+//   W_e = sum_i q_i K_ie g_ie          (K the summed-by-parts overlap weights),
+//   V_e = sum_i |q_i|^2 (B0_e / 2) g_ie conj(g_i,e-1)   (bin e's norm term),
+// q_i = (A P_i) / (A0 P0_i), the binned overlap and norm at t_j are
+//   Z(t_j)  = sum_e W_e E_ej,              E_ej = exp(-2 pi i f_e t_j),
+//   hh(t_j) = sum_i |q_i|^2 hh0_i + Re sum_e V_e F_ej,  F_ej = exp(-2 pi i (f_e - f_e-1) t_j),
+// two dense complex products [rows x edges] x [edges x grid] with
+// proposal-independent right factors (one batched GEMM), then the
+// phase-marginal log L per grid point and a fixed-order log-sum-exp.
+
+// E and F on the grid t_j = (j - J) delta (FP64 phase, FP64 sin/cos).
+__global__ void __launch_bounds__(256) k_het_tm_phasors(const double* __restrict__ rec, int rs, int n_edges, int nt,
+                                                        int J, double delta, TrigConsts T, double* __restrict__ ef) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)n_edges * nt;
+  if (idx >= 2 * per) return;
+  const int which = (int)(idx / per);
+  const int64_t r = idx - which * per;
+  const int e = (int)(r / nt), j = (int)(r - (int64_t)e * nt);
+  const double t = (double)(j - J) * delta;
+  double f = rec[(int64_t)e * rs + H_F];
+  if (which == 1) f = e > 0 ? f - rec[(int64_t)(e - 1) * rs + H_F] : 0.0;
+  double sn, cs;
+  sincos_cycles(f * t, T, &sn, &cs);
+  ef[2 * idx] = which == 1 && e == 0 ? 0.0 : cs;
+  ef[2 * idx + 1] = which == 1 && e == 0 ? 0.0 : -sn;
+}
+
+// Per row (lane), the edge weights W and V ([2][n][n_edges] complex) and the
+// constant norm part sum_i |q_i|^2 hh0_i (hhc[n]).  Edge records are
+// wave-uniform.
+template <int ND, int PREC>
+__global__ void __launch_bounds__(256) k_het_tw(const double* __restrict__ coef, int64_t ld, int64_t n,
+                                                const double* __restrict__ rec, int n_bins, HetConst hc, TrigConsts T,
+                                                double* __restrict__ wv, double* __restrict__ hhc) {
+  constexpr int RS = het_rs(ND);
+  constexpr int BO = het_bin_off(ND);
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t pc = p < n ? p : n - 1;
+  const double* cf = coef + pc;
+  PhaseCoef c;
+  c.a0 = cf[C_A0 * ld]; c.a2 = cf[C_A2 * ld]; c.a3 = cf[C_A3 * ld]; c.a4 = cf[C_A4 * ld];
+  c.a5 = cf[C_A5 * ld]; c.a6 = cf[C_A6 * ld]; c.a7 = cf[C_A7 * ld]; c.a8 = cf[C_A8 * ld];
+  c.a10 = cf[C_A10 * ld]; c.a12 = cf[C_A12 * ld]; c.b5 = cf[C_B5 * ld]; c.b6 = cf[C_B6 * ld];
+  double dt[ND], qr[ND], qi[ND], q2[ND], pr[ND], pim[ND];
+  double hconst = 0.0;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    dt[i] = i == 0 ? 0.0 : cf[(C_DT1 + i - 1) * ld];
+    const double ar = cf[(C_APRE + i) * ld], ai = cf[(C_APIM + i) * ld];
+    qr[i] = ar * hc.ap0_inv_re[i] - ai * hc.ap0_inv_im[i];
+    qi[i] = ar * hc.ap0_inv_im[i] + ai * hc.ap0_inv_re[i];
+    q2[i] = qr[i] * qr[i] + qi[i] * qi[i];
+    hconst = fma(q2[i], hc.hh0[i], hconst);
+    pr[i] = pim[i] = 0.0;
+  }
+  const int n_edges = n_bins + 1;
+  double* __restrict__ w_out = wv + pc * n_edges * 2;
+  double* __restrict__ v_out = wv + (n + pc) * n_edges * 2;
+  for (int e = 0; e < n_edges; ++e) {
+    const double* r = rec + (int64_t)e * RS;
+    const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
+    const double f = r[H_F];
+    const int side = e == 0 ? 1 : (e == n_bins ? 2 : 0);
+    double wr = 0.0, wi = 0.0, vr = 0.0, vi = 0.0;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const double di = i == 0 ? d0 : fma(f, dt[i], d0) - r[H_PHI0 + i];
+      double gr, gi;
+      het_phasor<PREC>(di, T, &gr, &gi);
+      const double* w = r + BO + 1 + 6 * i;
+      const double kr = side == 0 ? w[0] : (side == 1 ? w[0] - w[2] : w[2]);
+      const double ki = side == 0 ? w[1] : (side == 1 ? w[1] - w[3] : w[3]);
+      // q K g
+      const double kgr = kr * gr - ki * gi, kgi = kr * gi + ki * gr;
+      wr = fma(qr[i], kgr, fma(-qi[i], kgi, wr));
+      wi = fma(qr[i], kgi, fma(qi[i], kgr, wi));
+      if (e > 0) {
+        // |q|^2 (B0 / 2) g_e conj(g_e-1)
+        const double s = q2[i] * w[4];
+        vr = fma(s, fma(gr, pr[i], gi * pim[i]), vr);
+        vi = fma(s, fma(gi, pr[i], -gr * pim[i]), vi);
+      }
+      pr[i] = gr;
+      pim[i] = gi;
+    }
+    if (p < n) {
+      w_out[2 * e] = wr;
+      w_out[2 * e + 1] = wi;
+      v_out[2 * e] = vr;
+      v_out[2 * e + 1] = vi;
+    }
+  }
+  if (p < n) hhc[p] = hconst;
+}
+
+// One workgroup (256 threads) per row: log-mean-exp over the grid of the
+// phase-marginal binned log L.
+__global__ void __launch_bounds__(256) k_het_tfinal(const double* __restrict__ zh, const double* __restrict__ hhc,
+                                                    const double* __restrict__ coef, int64_t ld, int64_t n, int nt,
+                                                    double dd, LogI0Consts C, double* __restrict__ logl) {
+  __shared__ double red[256];
+  const int64_t p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double* z = zh + p * nt * 2;
+  const double* hv = zh + (n + p) * nt * 2;
+  const double h0 = hhc[p];
+  double mx = -INFINITY;
+  for (int j = tid; j < nt; j += 256) {
+    const double zr = z[2 * j], zi = z[2 * j + 1];
+    const double v = -0.5 * (h0 + hv[2 * j]) + log_i0(sqrt(zr * zr + zi * zi), C);
+    mx = fmax(mx, v);
+  }
+  red[tid] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  const double ref = red[0];
+  __syncthreads();
+  double acc = 0.0;
+  for (int j = tid; j < nt; j += 256) {
+    const double zr = z[2 * j], zi = z[2 * j + 1];
+    const double v = -0.5 * (h0 + hv[2 * j]) + log_i0(sqrt(zr * zr + zi * zi), C);
+    acc += exp(v - ref);
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const bool valid = coef[C_VALID * ld + p] != 0.0;
+    logl[p] = valid ? -0.5 * dd + ref + log(red[0]) - log((double)nt) : -INFINITY;
+  }
+}
+
+template <int ND>
+static void launch_het_tw_nd(gw_ctx* ctx, int64_t n, int prec, const HetConst& hc, double* wv, double* hhc,
+                             hipStream_t st) {
+  const gw_het_state* h = ctx->het;
+  const TrigConsts T = make_trig_consts();
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (prec == GW_PREC_FP64)
+    hipLaunchKernelGGL((k_het_tw<ND, 0>), dim3(blocks), dim3(256), 0, st, (const double*)ctx->coef, n, n,
+                       (const double*)h->rec, h->n_bins, hc, T, wv, hhc);
+  else
+    hipLaunchKernelGGL((k_het_tw<ND, 1>), dim3(blocks), dim3(256), 0, st, (const double*)ctx->coef, n, n,
+                       (const double*)h->rec, h->n_bins, hc, T, wv, hhc);
+}
+
+gw_status loglike_het_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, hipStream_t st) {
+  gw_het_state* h = ctx->het;
+  if (!h) return set_error(GW_ESTATE, "loglike_batch: heterodyne_setup has not been called");
+  double delta;
+  int32_t nt;
+  gw_status s = gw_time_grid_info(ctx, &delta, &nt, nullptr, nullptr);
+  if (s != GW_OK) return s;
+  const int J = (nt - 1) / 2;
+  const int ne = h->n_edges;
+  if (!h->tm_ef || h->tm_nt != nt || h->tm_delta != delta) {
+    if (h->tm_ef) (void)hipFree(h->tm_ef);
+    h->tm_ef = nullptr;
+    s = check_hip(hipMalloc((void**)&h->tm_ef, (size_t)2 * ne * nt * 2 * sizeof(double)), "time-grid phasors");
+    if (s != GW_OK) return s;
+    const int64_t tot = (int64_t)2 * ne * nt;
+    hipLaunchKernelGGL(k_het_tm_phasors, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                       (const double*)h->rec, h->rs, ne, nt, J, delta, make_trig_consts(), h->tm_ef);
+    s = check_hip(hipGetLastError(), "time-grid phasor launch");
+    if (s != GW_OK) return s;
+    h->tm_nt = nt;
+    h->tm_delta = delta;
+  }
+  // workspace: coefficients, W/V [2][n][ne], Z/H [2][n][nt], hhc [n]
+  s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
+  if (s == GW_OK)
+    s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap, (int64_t)2 * n * ne * 2 + (int64_t)2 * n * nt * 2 + n,
+                      "time-marginal workspace");
+  if (s != GW_OK) return s;
+  double* wv = ctx->tm_mom;
+  double* zh = wv + (int64_t)2 * n * ne * 2;
+  double* hhc = zh + (int64_t)2 * n * nt * 2;
+  s = launch_prologue(ctx, theta, n, GW_MARG_PHASE_TIME, ctx->coef, n, st);
+  if (s != GW_OK) return s;
+  HetConst hc;
+  for (int i = 0; i < kMaxDet; ++i) {
+    hc.ap0_inv_re[i] = h->ap0_inv_re[i];
+    hc.ap0_inv_im[i] = h->ap0_inv_im[i];
+    hc.hh0[i] = h->hh0[i];
+  }
+  hc.dd = ctx->dd;
+  switch (ctx->n_det) {
+    case 1: launch_het_tw_nd<1>(ctx, n, prec, hc, wv, hhc, st); break;
+    case 2: launch_het_tw_nd<2>(ctx, n, prec, hc, wv, hhc, st); break;
+    case 3: launch_het_tw_nd<3>(ctx, n, prec, hc, wv, hhc, st); break;
+    case 4: launch_het_tw_nd<4>(ctx, n, prec, hc, wv, hhc, st); break;
+    default: return set_error(GW_ENOTSUP, "n_det not supported");
+  }
+  s = check_hip(hipGetLastError(), "edge weight launch");
+  if (s != GW_OK) return s;
+  // Z^T = E^T W^T and H^T = F^T V^T in column-major terms: m = nt, n = rows, k = edges
+  if (!ctx->blas) {
+    if (rocblas_create_handle((rocblas_handle*)&ctx->blas) != rocblas_status_success)
+      return set_error(GW_EDEVICE, "rocblas_create_handle failed");
+  }
+  rocblas_handle bh = (rocblas_handle)ctx->blas;
+  if (rocblas_set_stream(bh, st) != rocblas_status_success) return set_error(GW_EDEVICE, "rocblas_set_stream failed");
+  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+  const int prof = prof_begin(ctx, st);
+  const rocblas_status bs = rocblas_zgemm_strided_batched(
+      bh, rocblas_operation_none, rocblas_operation_none, nt, (rocblas_int)n, ne, &one,
+      (const rocblas_double_complex*)h->tm_ef, nt, (rocblas_stride)ne * nt, (const rocblas_double_complex*)wv, ne,
+      (rocblas_stride)n * ne, &zero, (rocblas_double_complex*)zh, nt, (rocblas_stride)n * nt, 2);
+  prof_end(ctx, prof, st);
+  if (bs != rocblas_status_success) return set_error(GW_EDEVICE, "rocblas_zgemm_strided_batched: status %d", (int)bs);
+  LogI0Consts C = make_log_i0_consts();
+  C.r1max = ctx->dist_r1max;
+  hipLaunchKernelGGL(k_het_tfinal, dim3((unsigned)n), dim3(256), 0, st, (const double*)zh, (const double*)hhc,
+                     (const double*)ctx->coef, n, n, nt, ctx->dd, C, logl);
+  return check_hip(hipGetLastError(), "time-marginal epilogue launch");
+}
+
 gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl, hipStream_t st) {
   if (!ctx->het) return set_error(GW_ESTATE, "loglike_batch: heterodyne_setup has not been called");
+  if (marg == GW_MARG_PHASE_TIME) return loglike_het_tmarg(ctx, theta, n, prec, logl, st);
   int n_ech = 1;
   gw_status s = het_prepare(ctx, theta, nullptr, 1, n, logl, true, &n_ech, st);
   if (s != GW_OK) return s;
