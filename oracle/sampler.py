@@ -65,6 +65,19 @@ def prior_transform(u: np.ndarray) -> np.ndarray:
     return th
 
 
+def prior_transform_time(u: np.ndarray, d_lo: float, d_hi: float) -> np.ndarray:
+    """Unit-cube point [11] -> parameter vector [13] when t_c is marginalised
+    (the paper's GW170817 configuration samples d_L in its place): as
+    ``prior_transform`` but coordinate 10 is d_L with a prior proportional to
+    d_L^2 on [d_lo, d_hi] (inverse CDF d = (d_lo^3 + u (d_hi^3 - d_lo^3))^(1/3)),
+    and t_c = 0 (ignored)."""
+    th = prior_transform(u)
+    lo3 = d_lo ** 3
+    th[6] = (lo3 + float(u[10]) * (d_hi ** 3 - lo3)) ** (1.0 / 3.0)
+    th[12] = 0.0
+    return th
+
+
 def philox4x64(counter, key):
     """Philox4x64 with 10 rounds (Salmon, Moraes, Dror & Shaw 2011)."""
     c = [int(v) & _MASK for v in counter]

@@ -98,3 +98,20 @@ def test_nested_sampling_gaussian_evidence():
                             max_shrink=60)
     assert abs(res["log_z"]) < 3 * res["log_z_err"] + 0.05, res["log_z"]
     assert res["h"] > 5
+
+
+def test_time_marginal_transform_samples_a_d_squared_prior():
+    # coordinate 10 carries d_L with density proportional to d^2 on [10, 200]:
+    # KS test against the CDF (d^3 - 10^3) / (200^3 - 10^3); the other columns
+    # are those of the default transform, and t_c is zero
+    from scipy import stats
+    rng = np.random.default_rng(4)
+    u = rng.uniform(size=(4000, 11))
+    th = np.array([S.prior_transform_time(x, 10.0, 200.0) for x in u])
+    cdf = lambda d: (d ** 3 - 1e3) / (200.0 ** 3 - 1e3)
+    assert stats.kstest(th[:, 6], cdf).pvalue > 1e-3
+    assert np.all(th[:, 12] == 0.0)
+    ref = np.array([S.prior_transform(x) for x in u[:10]])
+    assert np.array_equal(np.delete(th[:10], [6, 12], axis=1), np.delete(ref, [6, 12], axis=1))
+    assert S.prior_transform_time(np.zeros(11), 10.0, 200.0)[6] == pytest.approx(10.0, rel=1e-15)
+    assert S.prior_transform_time(np.ones(11), 10.0, 200.0)[6] == pytest.approx(200.0, rel=1e-15)
