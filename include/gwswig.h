@@ -229,7 +229,10 @@ gw_status gw_graph_info(const gw_ctx* ctx, int32_t* n_graphs, double* last_insta
  * of the uniform / isotropic prior Mc in [1.1, 1.4], q in [0.5, 1],
  * chi in [-0.05, 0.05], Lambda in [0, 5000], cos(iota) and sin(dec)
  * uniform, ra in [0, 2 pi), psi in [0, pi), t_c in [-0.1, 0.1] s, with phi_c
- * and d_L marginalised (marg must be GW_MARG_PHASE_DIST).
+ * and d_L marginalised (marg = GW_MARG_PHASE_DIST), or, with marg =
+ * GW_MARG_PHASE_TIME (the paper's GW170817 configuration), phi_c and t_c
+ * marginalised and d_L sampled as coordinate 10 in place of t_c (see
+ * gw_prior_transform_marg); its rounds are launched without a graph.
  * Per chain: u a uniform unit vector (Box-Muller from uniforms 0..3), the
  * direction d = L u with L the block's lower Cholesky factor; a bracket
  * [-r w, (1 - r) w] with r = uniform 4; each end stepped out by w while
@@ -342,6 +345,12 @@ gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* args, void* stream);
  * phi_c = 0, both marginalised).  Used to evaluate a fresh live set.
  */
 gw_status gw_prior_transform(gw_ctx* ctx, const double* x, int64_t n, double* theta, void* stream);
+/* The same for a sampler run with marg = GW_MARG_PHASE_DIST (as above) or
+ * GW_MARG_PHASE_TIME: then coordinate 10 is d_L, with a prior proportional to
+ * d_L^2 between the first and last distance-grid nodes (inverse CDF
+ * d = (d_1^3 + u (d_n^3 - d_1^3))^(1/3)), and t_c = 0 (marginalised). */
+gw_status gw_prior_transform_marg(gw_ctx* ctx, const double* x, int64_t n, int32_t marg, double* theta,
+                                  void* stream);
 
 /*
  * Waveform cache (Sec. III.B, Sec. III.A): the slow / fast likelihood pair.

@@ -131,6 +131,7 @@ _SIGS = {
     "gw_wcache_loglike": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          _P, _P]),
     "gw_prior_transform": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+    "gw_prior_transform_marg": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P]),
     "gw_set_full_kernel": (ctypes.c_int, [_P, ctypes.c_int32]),
     "gw_full_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "gw_phasor_gain": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
@@ -442,14 +443,15 @@ def slice_sweep(ctx, x, logl, logl_star: float, blocks, chols, seed: int = 0, co
     return (kinds[0], kinds[1], kinds[2]) if use_cache else None
 
 
-def gw_prior_transform(ctx, x, stream=None):
-    """Unit-cube points (CUDA float64 [n, 11]) -> parameter vectors [n, 13]."""
+def gw_prior_transform(ctx, x, stream=None, marg: int = GW_MARG_PHASE_DIST):
+    """Unit-cube points (CUDA float64 [n, 11]) -> parameter vectors [n, 13]
+    (coordinate 10 is t_c, or d_L with marg = GW_MARG_PHASE_TIME)."""
     import torch
     if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == 11):
         raise ValueError("x must be a contiguous CUDA float64 tensor of shape [n, 11]")
     th = torch.empty((x.shape[0], GW_NPARAM), dtype=torch.float64, device=x.device)
-    check(load().gw_prior_transform(ctx, _tensor_ptr(x), x.shape[0], _tensor_ptr(th), _stream_ptr(stream)),
-          "gw_prior_transform")
+    check(load().gw_prior_transform_marg(ctx, _tensor_ptr(x), x.shape[0], int(marg), _tensor_ptr(th),
+                                         _stream_ptr(stream)), "gw_prior_transform")
     return th
 
 

@@ -23,6 +23,13 @@ constexpr int kMaxBlock = 4;    // coordinates per block
 constexpr int kMaxBlocks = 16;  // blocks per sweep
 constexpr int kUniFixed = 5;    // 4 direction + 1 bracket offset
 
+// How the sampler's last coordinate is read: t_c (phase and distance
+// marginalised) or d_L (phase and time marginalised).
+struct CubeMap {
+  int32_t time_marg;  // 0: coordinate 10 is t_c; 1: coordinate 10 is d_L
+  double d3_lo, d3_span;  // d_L^3 at the lower end of its prior, and the range of d_L^3
+};
+
 // One sweep: every chain visits blocks b = 0 .. nb - 1 in order, block b with
 // Philox counter (counter + b).  Chains are independent, so a chain starts its
 // next block as soon as it finishes one; each chain's moves are exactly those
@@ -46,6 +53,7 @@ struct SweepParams {
   // 2 projection only (psi, iota: cached sums z_i).
   int32_t lists;
   int32_t cache;
+  CubeMap cm;
   int32_t n_det;
   int32_t kind[kMaxBlocks];
 };
@@ -106,9 +114,11 @@ __device__ inline double slice_uniform(const SweepParams& P, int b, int64_t c, i
   return ((double)(ctr[j & 3] >> 11) + 0.5) * 1.1102230246251565404e-16;  // 2^-53
 }
 
-// Unit cube -> 13-column parameter vector (d_L = 1, phi_c = 0; both are
-// marginalised by the modes slice_step accepts).
-__device__ inline void prior_transform(const double* u, double* th) {
+// Unit cube -> 13-column parameter vector.  Coordinate 10 is t_c in [-0.1,
+// 0.1] s (d_L = 1, phi_c = 0, both marginalised) or, with time_marg, d_L with
+// a prior proportional to d_L^2 (inverse CDF (d3_lo + u d3_span)^(1/3); t_c =
+// 0 and phi_c = 0 marginalised).
+__device__ inline void prior_transform(const double* u, double* th, const CubeMap& cm) {
   const double lo[6] = {1.1, 0.5, -0.05, -0.05, 0.0, 0.0};
   const double hi[6] = {1.4, 1.0, 0.05, 0.05, 5000.0, 5000.0};
 #pragma unroll
@@ -120,6 +130,10 @@ __device__ inline void prior_transform(const double* u, double* th) {
   th[10] = kPi * u[9];
   th[11] = 0.0;
   th[12] = -0.1 + 0.2 * u[10];
+  if (cm.time_marg) {
+    th[6] = cbrt(fma(u[10], cm.d3_span, cm.d3_lo));
+    th[12] = 0.0;
+  }
 }
 
 // Start block b for chain c: direction d = L u (u from Box-Muller normals of
@@ -214,7 +228,7 @@ __global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S,
         if (!(fl & (1 << side))) continue;
         const double t = side == 0 ? S.t_lo[c] : S.t_hi[c];
         if (make_point(P, b, S, x0, c, t, u)) {
-          prior_transform(u, cand + (2 * c + side) * 13);
+          prior_transform(u, cand + (2 * c + side) * 13, P.cm);
           S.cand_t[2 * c + side] = t;
           ok[side] = 1;
         } else {
@@ -229,7 +243,7 @@ __global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S,
         const double v = slice_uniform(P, b, c, kUniFixed + S.n_shrink[c]);
         const double t = S.t_lo[c] + v * (S.t_hi[c] - S.t_lo[c]);
         if (make_point(P, b, S, x0, c, t, u)) {
-          prior_transform(u, cand + 2 * c * 13);
+          prior_transform(u, cand + 2 * c * 13, P.cm);
           S.cand_t[2 * c] = t;
           ok[0] = 1;
           break;
@@ -386,7 +400,7 @@ __global__ void k_cache_init0(const SweepParams* __restrict__ D, SliceState S, d
   const SweepParams& P = *D;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P.k) return;
-  prior_transform(P.x + c * kSliceDim, cand + 2 * c * 13);
+  prior_transform(P.x + c * kSliceDim, cand + 2 * c * 13, P.cm);
   double* th = cand + (2 * c + 1) * 13;
   for (int j = 0; j < 13; ++j) th[j] = 0.0;
   th[1] = -1.0;
@@ -404,9 +418,9 @@ __global__ void k_cache_init1(const SweepParams* __restrict__ D, SliceState S) {
   S.dirty[c] = 1;
 }
 
-__global__ void k_prior_transform(const double* __restrict__ x, int64_t n, double* __restrict__ theta) {
+__global__ void k_prior_transform(const double* __restrict__ x, int64_t n, CubeMap cm, double* __restrict__ theta) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) prior_transform(x + i * kSliceDim, theta + i * 13);
+  if (i < n) prior_transform(x + i * kSliceDim, theta + i * 13, cm);
 }
 
 __global__ void k_sweep_finish(const SweepParams* __restrict__ D, SliceState S, int32_t* n_evals, int32_t* status) {
@@ -555,6 +569,20 @@ static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const Swee
   return GW_OK;
 }
 
+// The cube map for a marginalisation mode: with the time marginal, d_L spans
+// the context's distance grid (prior proportional to d_L^2).
+static gw_status cube_map(const gw_ctx* ctx, int32_t marg, CubeMap* cm) {
+  cm->time_marg = 0;
+  cm->d3_lo = cm->d3_span = 0.0;
+  if (marg != GW_MARG_PHASE_TIME) return GW_OK;
+  if (ctx->h_dist_grid.size() < 2) return set_error(GW_ESTATE, "time-marginal sampler needs a distance grid");
+  const double lo = ctx->h_dist_grid.front(), hi = ctx->h_dist_grid.back();
+  cm->time_marg = 1;
+  cm->d3_lo = lo * lo * lo;
+  cm->d3_span = hi * hi * hi - cm->d3_lo;
+  return GW_OK;
+}
+
 // Validation shared by both entry points.
 static gw_status check_sweep(const char* who, int64_t k, const double* x, const double* logl, double w,
                              int32_t max_out, int32_t max_shrink, int32_t like, int32_t marg, const gw_ctx* ctx) {
@@ -564,9 +592,9 @@ static gw_status check_sweep(const char* who, int64_t k, const double* x, const 
   if (max_out < 0 || max_shrink < 1 || max_shrink > 10000)
     return set_error(GW_EINVAL, "%s: max_out >= 0, max_shrink 1..10000", who);
   if (marg == GW_MARG_NONE)
-    return set_error(GW_ENOTSUP, "%s: the 11-D sampler needs phi_c and d_L marginalised (marg=2)", who);
-  if (marg != GW_MARG_PHASE_DIST)
-    return set_error(GW_ENOTSUP, "%s: marg must be GW_MARG_PHASE_DIST", who);
+    return set_error(GW_ENOTSUP, "%s: the 11-D sampler needs phi_c and d_L, or phi_c and t_c, marginalised", who);
+  if (marg != GW_MARG_PHASE_DIST && marg != GW_MARG_PHASE_TIME)
+    return set_error(GW_ENOTSUP, "%s: marg must be GW_MARG_PHASE_DIST or GW_MARG_PHASE_TIME", who);
   if (like != GW_FULL && like != GW_HET)
     return set_error(GW_EINVAL, "%s: like must be GW_FULL or GW_HET", who);
   if (like == GW_HET && !ctx->het)
@@ -691,8 +719,13 @@ gw_status slice_step(gw_ctx* ctx, const gw_slice_args* a, void* stream) {
   P.k = a->k;
   P.x = a->x;
   P.logl = a->logl;
-  P.lists = a->like == GW_FULL;
-  const SweepCall c{a->like, a->marg, a->prec, a->use_graph, a->n_evals, a->status, 0, nullptr, P.lists};
+  P.lists = a->like == GW_FULL && a->marg == GW_MARG_PHASE_DIST;
+  s = cube_map(ctx, a->marg, &P.cm);
+  if (s != GW_OK) return s;
+  // the time marginal sets up tables on first use and calls the BLAS library:
+  // its rounds are launched eagerly
+  const int32_t graph = a->use_graph && a->marg != GW_MARG_PHASE_TIME;
+  const SweepCall c{a->like, a->marg, a->prec, graph, a->n_evals, a->status, 0, nullptr, P.lists};
   return run_sweep(ctx, P, c, (hipStream_t)stream);
 }
 
@@ -724,7 +757,8 @@ gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* a, void* stream) {
   P.x = a->x;
   P.logl = a->logl;
   if (a->use_cache) {
-    if (a->like != GW_FULL) return set_error(GW_ENOTSUP, "slice_sweep: the waveform cache is for like=GW_FULL");
+    if (a->like != GW_FULL || a->marg != GW_MARG_PHASE_DIST)
+      return set_error(GW_ENOTSUP, "slice_sweep: the waveform cache is for like=GW_FULL, marg=GW_MARG_PHASE_DIST");
     // kind of each block from its coordinates: psi and iota only change the
     // projection; sky position and t_c also change the delays; anything else
     // changes the waveform
@@ -740,21 +774,33 @@ gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* a, void* stream) {
     P.cache = 1;
     P.n_det = ctx->n_det;
   }
-  P.lists = a->like == GW_FULL;
-  const SweepCall c{a->like, a->marg, a->prec, a->use_graph, a->n_evals, a->status, P.cache, a->eval_kinds, P.lists};
+  P.lists = a->like == GW_FULL && a->marg == GW_MARG_PHASE_DIST;
+  s = cube_map(ctx, a->marg, &P.cm);
+  if (s != GW_OK) return s;
+  const int32_t graph = a->use_graph && a->marg != GW_MARG_PHASE_TIME;  // as in slice_step
+  const SweepCall c{a->like, a->marg, a->prec, graph, a->n_evals, a->status, P.cache, a->eval_kinds, P.lists};
   return run_sweep(ctx, P, c, (hipStream_t)stream);
 }
 
-gw_status gw_prior_transform(gw_ctx* ctx, const double* x, int64_t n, double* theta, void* stream) {
+gw_status gw_prior_transform_marg(gw_ctx* ctx, const double* x, int64_t n, int32_t marg, double* theta,
+                                  void* stream) {
   if (!ctx) return set_error(GW_EINVAL, "gw_prior_transform: ctx is NULL");
   if (n < 0) return set_error(GW_EINVAL, "gw_prior_transform: n < 0");
+  if (marg != GW_MARG_PHASE_DIST && marg != GW_MARG_PHASE_TIME)
+    return set_error(GW_EINVAL, "gw_prior_transform: marg must be GW_MARG_PHASE_DIST or GW_MARG_PHASE_TIME");
   if (n == 0) return GW_OK;
   if (!x || !theta) return set_error(GW_EINVAL, "gw_prior_transform: null pointer");
-  gw_status s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
+  CubeMap cm;
+  gw_status s = cube_map(ctx, marg, &cm);
+  if (s == GW_OK) s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
   if (s != GW_OK) return s;
   hipLaunchKernelGGL(k_prior_transform, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, x, n,
-                     theta);
+                     cm, theta);
   return check_hip(hipGetLastError(), "prior transform launch");
+}
+
+gw_status gw_prior_transform(gw_ctx* ctx, const double* x, int64_t n, double* theta, void* stream) {
+  return gw_prior_transform_marg(ctx, x, n, GW_MARG_PHASE_DIST, theta, stream);
 }
 
 }  // extern "C"

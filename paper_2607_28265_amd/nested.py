@@ -11,7 +11,9 @@ chain moves on to its next block as soon as it has finished one; with
 ``async_sweep=False`` every block is a ``slice_step`` call of its own (all
 chains finish the block before any starts the next).  Both give the same
 chains bit for bit.  With ``cache=True`` (full band) the sweep keeps each
-chain's waveform and reuses it on the extrinsic blocks (Sec. III.B).
+chain's waveform and reuses it on the extrinsic blocks (Sec. III.B).  With
+``marg=GW_MARG_PHASE_TIME`` the phase and coalescence time are marginalised
+and d_L is sampled in place of t_c (the paper's GW170817 configuration).
 
 The host keeps the FP64 evidence bookkeeping (the k deletions taken in order
 with live counts m, m-1, ..., m-k+1), the start-point choice and the block
@@ -47,7 +49,7 @@ class NestedSampler:
     def __init__(self, ctx, n_live: int = 1000, n_delete: int = 125, seed: int = 6, dlogz: float = 0.1,
                  blocks=BLOCKS, like: int = _lib.GW_HET, prec: int = _lib.GW_PREC_MIXED, sweeps: int = 1,
                  w: float = 1.0, max_out: int = 10, max_shrink: int = 100, async_sweep: bool = True,
-                 cache: bool = False):
+                 cache: bool = False, marg: int = _lib.GW_MARG_PHASE_DIST):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -59,6 +61,7 @@ class NestedSampler:
         self.sweeps, self.w, self.max_out, self.max_shrink = sweeps, w, max_out, max_shrink
         self.async_sweep = bool(async_sweep)
         self.cache = bool(cache)
+        self.marg = int(marg)
         if self.cache and (like != _lib.GW_FULL or not self.async_sweep):
             raise ValueError("the waveform cache needs like=GW_FULL and async_sweep=True")
         self.rng = np.random.default_rng(self.seed)
@@ -81,14 +84,11 @@ class NestedSampler:
     def _eval(self, x, out):
         torch = self.torch
         th = self._unit_to_theta(x)
-        if self.like == _lib.GW_HET:
-            _lib.loglike_batch(self.ctx.handle, th, _lib.GW_HET, _lib.GW_MARG_PHASE_DIST, self.prec, out=out)
-        else:
-            _lib.loglike_batch(self.ctx.handle, th, _lib.GW_FULL, _lib.GW_MARG_PHASE_DIST, self.prec, out=out)
+        _lib.loglike_batch(self.ctx.handle, th, self.like, self.marg, self.prec, out=out)
         torch.cuda.synchronize()
 
     def _unit_to_theta(self, x):
-        return _lib.gw_prior_transform(self.ctx.handle, x.contiguous())
+        return _lib.gw_prior_transform(self.ctx.handle, x.contiguous(), marg=self.marg)
 
     # -- evidence ----------------------------------------------------------
     def log_z_dead(self):
@@ -132,7 +132,7 @@ class NestedSampler:
             if self.async_sweep:
                 kinds = _lib.slice_sweep(self.ctx.handle, xn, ln, lstar, self.blocks, chols, seed=self.seed,
                                  counter=self.counter, w=self.w, max_out=self.max_out, max_shrink=self.max_shrink,
-                                 like=self.like, marg=_lib.GW_MARG_PHASE_DIST, prec=self.prec, n_evals=ne,
+                                 like=self.like, marg=self.marg, prec=self.prec, n_evals=ne,
                                  use_cache=self.cache)
                 if kinds is not None:
                     self.eval_kinds += np.array(kinds, np.int64)
@@ -142,7 +142,7 @@ class NestedSampler:
             for bi, b in enumerate(self.blocks):
                 _lib.slice_step(self.ctx.handle, xn, ln, lstar, b, chols[bi], seed=self.seed, counter=self.counter,
                                 w=self.w, max_out=self.max_out, max_shrink=self.max_shrink, like=self.like,
-                                marg=_lib.GW_MARG_PHASE_DIST, prec=self.prec, n_evals=ne)
+                                marg=self.marg, prec=self.prec, n_evals=ne)
                 self.n_evals += int(ne.sum().item())
                 self.counter += 1
         wi = torch.from_numpy(worst).to(self.dev)
