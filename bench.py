@@ -35,16 +35,18 @@ METRIC = "logL evals/sec (full-band & heterodyned) vs FP64 plain at |dlogL|<1e-3
 FLOPS_PER_BIN = {"mixed": 60.0, "fp64": 107.0}
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector, dense
 
-# HBM bytes per launch of k_full<3, 1> at 4096 x 259,585, from two rocprofv3 PMC
-# runs (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
-# plain 256 MiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).  Valid
-# only for the kernel sources they were taken on (hash below).
-TRAFFIC = {"sources_sha256": "829b2001f9fc24b8f693cdcc51a8a9c10c770c6b3f3b19af15415cd99730c1c6",
-           "read_bytes": 22152.7 * 1.9998 * 1024, "write_bytes": 24576.0 * 1024}
+# HBM bytes per launch from two rocprofv3 PMC runs (FETCH_SIZE, WRITE_SIZE)
+# scaled by what the same counters read for a plain 256 MiB device copy
+# (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.000): k_full<3, 1, false> at
+# 4096 x 259,585, and k_wmom<3> at 4096 rows on 2048 cached slots.  Valid only
+# for the kernel sources they were taken on (hash below).
+TRAFFIC = {"sources_sha256": "4908f7f52157efd3dacbe68c498ba2866c26f969e0cdf9d3267de25700568f25",
+           "k_full": {"read_bytes": 22141.1875 * 1.99981 * 1024, "write_bytes": 24576.0 * 1024},
+           "k_wmom": {"read_bytes": 397456.234 * 1.99981 * 1024, "write_bytes": 23040.0 * 1024}}
 TRAFFIC_SOURCES = ("paper_2607_28265_amd/csrc/gw_full.hip", "paper_2607_28265_amd/csrc/gw_device.h")
 
 
-def traffic_bytes():
+def traffic_bytes(kernel="k_full"):
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
@@ -52,7 +54,7 @@ def traffic_bytes():
             h.update(fh.read())
     if h.hexdigest() != TRAFFIC["sources_sha256"]:
         return None
-    return TRAFFIC["read_bytes"] + TRAFFIC["write_bytes"]
+    return TRAFFIC[kernel]["read_bytes"] + TRAFFIC[kernel]["write_bytes"]
 
 
 def parse():
@@ -367,7 +369,7 @@ def cache_leg(gw, torch, prob, steps, warmup, mixed_value):
                 r["moment_block_bins"] = blk
                 r["roofline"] = {"bound": "hbm", "achieved": nbytes / (k_ms * 1e-3) / 1e9, "peak": 8000.0,
                                  "unit": "GB/s", "frac": nbytes / (k_ms * 1e-3) / 1e9 / 8000.0,
-                                 "bytes_per_launch": nbytes,
+                                 "traffic": traffic_bytes("k_wmom"), "bytes_per_launch": nbytes,
                                  "fp64_tflops": flops / (k_ms * 1e-3) / 1e12,
                                  "fp64_frac": flops / (k_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
             res[f"kind{kind}"] = r
