@@ -17,6 +17,10 @@ heterodyne  relative-binning bin edges, summary data and evaluation
 sampler     prior transform, hit-and-run slice step, nested-sampling loop
             (Sec. II.B, II.C, III.B).
 mlp         FP64 forward / backward / Adam of the prescreen network.
+reconstruct post-hoc draws of the marginalised d_L and phi_c on their grids
+            (grid-marginalisation appendix).
+pp          credible levels, KS and Fisher p-values of an injection campaign
+            (P-P calibration section).
 
 Parity unpinned: the TaylorF2 post-Newtonian and spin coefficients beyond the
 Newtonian limit and the equal-mass tidal case (the paper prints no waveform

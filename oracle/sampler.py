@@ -15,12 +15,16 @@ Readings used here (where the paper is silent):
   phi_c marginalised;
 * direction: u uniform on the unit sphere of the block (normalised Gaussian
   draws, Box-Muller from uniforms), d = L u with L the Cholesky factor of the
-  block covariance; bracket width w along t, placed at a uniform offset;
+  block covariance; a block may hold every coordinate (the unblocked nested
+  slice sampler of the sampler-configuration section, run with M d joint
+  steps per iteration); bracket width w along t, placed at a uniform offset;
   stepping out at most ``max_out`` times per side; shrinking at most
   ``max_shrink`` times, after which the chain keeps its point (status 1);
 * a point outside the unit cube fails the constraint without an evaluation;
 * random numbers: explicit uniforms per chain, laid out as
-  [4 direction, 1 offset, max_shrink shrink draws]; or Philox4x64-10
+  [n_dir direction, 1 offset, max_shrink shrink draws] with
+  n_dir = max(4, 2 ceil(b / 2)) for a block of b coordinates (one Box-Muller
+  pair per two coordinates, at least two pairs); or Philox4x64-10
   (Salmon et al. 2011), uniform j of chain c from counter
   (counter_base, c, j // 4, 0) and key (seed, 0), output word j % 4,
   u = ((word >> 11) + 0.5) * 2^-53;
@@ -41,7 +45,7 @@ N_DIM = 11
 PRIOR_LO = np.array([1.1, 0.5, -0.05, -0.05, 0.0, 0.0])
 PRIOR_HI = np.array([1.4, 1.0, 0.05, 0.05, 5000.0, 5000.0])
 BLOCKS = ((0, 1, 4, 5), (2,), (3,), (6,), (7, 8), (9,), (10,))
-N_UNIFORM_FIXED = 5  # 4 direction + 1 offset
+N_UNIFORM_FIXED = 5  # 4 direction + 1 offset (blocks of up to 4 coordinates)
 
 _M0 = 0xD2E7470EE14C6C93
 _M1 = 0xCA5A826395121157
@@ -103,13 +107,26 @@ def philox_uniforms(seed: int, counter_base: int, chain: int, n: int) -> np.ndar
     return out
 
 
+def n_direction_uniforms(b: int) -> int:
+    """Uniforms spent on the direction of a block of b coordinates."""
+    return max(4, 2 * ((b + 1) // 2))
+
+
+def n_fixed_uniforms(b: int) -> int:
+    """Uniforms before the shrink draws: direction, then the bracket offset."""
+    return n_direction_uniforms(b) + 1
+
+
 def direction(uni: np.ndarray, chol: np.ndarray) -> np.ndarray:
-    """d = L u, u a unit vector from Box-Muller normals of uni[0:4]."""
+    """d = L u, u a unit vector from Box-Muller normals: pair p turns
+    (uni[2p], uni[2p + 1]) into r cos(2 pi uni[2p + 1]), r sin(2 pi uni[2p + 1])
+    with r = sqrt(-2 ln uni[2p]); the first b normals are used."""
     b = chol.shape[0]
-    r0 = math.sqrt(-2.0 * math.log(uni[0]))
-    r1 = math.sqrt(-2.0 * math.log(uni[2]))
-    z = np.array([r0 * math.cos(2 * math.pi * uni[1]), r0 * math.sin(2 * math.pi * uni[1]),
-                  r1 * math.cos(2 * math.pi * uni[3]), r1 * math.sin(2 * math.pi * uni[3])])[:b]
+    z = []
+    for p in range(n_direction_uniforms(b) // 2):
+        r = math.sqrt(-2.0 * math.log(uni[2 * p]))
+        z += [r * math.cos(2 * math.pi * uni[2 * p + 1]), r * math.sin(2 * math.pi * uni[2 * p + 1])]
+    z = np.array(z[:b])
     z = z / np.linalg.norm(z)
     return chol @ z
 
@@ -142,7 +159,8 @@ def slice_chain(x0, logl0, logl_star, block, chol, uni, loglike, w=1.0, max_out=
         margin = min(margin, abs(v - logl_star))
         return v > logl_star, x, v
 
-    r = uni[4]
+    nfix = n_fixed_uniforms(len(block))
+    r = uni[nfix - 1]
     t_lo = -r * w
     t_hi = (1.0 - r) * w
     for _ in range(max_out):
@@ -156,7 +174,7 @@ def slice_chain(x0, logl0, logl_star, block, chol, uni, loglike, w=1.0, max_out=
             break
         t_hi += w
     for s in range(max_shrink):
-        t = t_lo + uni[N_UNIFORM_FIXED + s] * (t_hi - t_lo)
+        t = t_lo + uni[nfix + s] * (t_hi - t_lo)
         good, x, v = ok(t)
         if good:
             return x, v, n_evals, 0, margin
@@ -204,7 +222,7 @@ def nested_sampling(loglike, n_live: int, n_delete: int, seed: int, dlogz: float
         for _ in range(sweeps):
             for bi, b in enumerate(blocks):
                 for c in range(n_delete):
-                    uni = philox_uniforms(seed, counter, c, N_UNIFORM_FIXED + max_shrink)
+                    uni = philox_uniforms(seed, counter, c, n_fixed_uniforms(len(b)) + max_shrink)
                     x, v, ne, st, _ = slice_chain(new_x[c], new_l[c], logl_star, b, chols[bi], uni, loglike,
                                                   w, max_out, max_shrink)
                     new_x[c], new_l[c] = x, v

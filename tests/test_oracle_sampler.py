@@ -72,6 +72,35 @@ def test_slice_step_keeps_uniform_on_a_ball():
     assert stats.kstest(s, cdf).pvalue > 1e-3
 
 
+def test_unblocked_slice_step_keeps_uniform_on_an_11_ball():
+    # P17 for one block holding every coordinate (the unblocked nested slice
+    # sampler): 6 Box-Muller pairs give the direction, the bracket offset is
+    # uniform 12 and the shrink draws follow.  Uniform on an 11-ball stays
+    # uniform: radial CDF r^11, one coordinate (s + 1) / 2 ~ Beta(6, 6).
+    d, n, rad = 11, 600, 0.3
+    assert S.n_direction_uniforms(d) == 12 and S.n_fixed_uniforms(d) == 13
+    assert S.n_fixed_uniforms(4) == S.N_UNIFORM_FIXED == S.n_fixed_uniforms(1)
+    rng = np.random.default_rng(2)
+    c = np.full(d, 0.5)
+    g = rng.normal(size=(n, d))
+    x = c + rad * (g / np.linalg.norm(g, axis=1, keepdims=True)) * rng.uniform(size=(n, 1)) ** (1 / d)
+    loglike = lambda p: -float(np.sum((p - c) ** 2))
+    lstar = -rad * rad
+    chol = np.linalg.cholesky(np.cov(x, rowvar=False))
+    logl = np.array([loglike(p) for p in x])
+    block = tuple(range(d))
+    for step in range(5):
+        for i in range(n):
+            uni = S.philox_uniforms(12, step, i, S.n_fixed_uniforms(d) + 100)
+            x[i], logl[i], _, st, _ = S.slice_chain(x[i], logl[i], lstar, block, chol, uni, loglike, w=0.5)
+            assert st == 0
+    r = np.linalg.norm(x - c, axis=1) / rad
+    assert np.all(r < 1)
+    assert stats.kstest(r ** d, "uniform").pvalue > 1e-3
+    s = (x[:, 3] - c[3]) / rad
+    assert stats.kstest((s + 1) / 2, stats.beta(6, 6).cdf).pvalue > 1e-3
+
+
 def test_slice_step_block_moves_only_block():
     x0 = np.full(11, 0.5)
     uni = S.philox_uniforms(3, 0, 0, S.N_UNIFORM_FIXED + 100)
