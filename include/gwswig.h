@@ -164,6 +164,37 @@ gw_status gw_time_grid_info(const gw_ctx* ctx, double* delta, int32_t* n_points,
                             int32_t* block_bins);
 
 /*
+ * Post-hoc reconstruction of the marginalised distance and phase (appendix on
+ * grid marginalisations: the marginalised parameters of each posterior sample
+ * are drawn after the run from their exact conditional on the grid, computed
+ * from the sample's inner products).  For each row of theta (device [n, 13],
+ * as for loglike_batch with the same like, marg and prec; phi_c ignored, d_L
+ * ignored for GW_MARG_PHASE_DIST), with Z, <h|h> the sample's overlap and norm
+ * at phi_c = 0 (at d_L = 1 Mpc for the distance marginal):
+ *   marg = GW_MARG_PHASE_DIST: d_L = d_j drawn from the grid weights
+ *       exp(ln w_j - <h|h>_1 / (2 d_j^2) + ln I0(|Z_1| / d_j)), then
+ *       phi_c given d_j;
+ *   marg = GW_MARG_PHASE: d_L = the sample's own, phi_c drawn;
+ *   phi_c = 2 pi m / n_phase drawn from the weights
+ *       exp(kappa cos(2 pi m / n_phase + arg Z')), Z' = Z / d_L, kappa = |Z'|
+ *       (the template carries exp(+i phi_c)).
+ * Each draw takes the first grid index whose cumulative weight exceeds
+ * u times the total weight, with u from ``uniforms`` (device [n, 2]:
+ * distance, phase; each in (0, 1)).
+ * out:    device [n, 2] (d_L in Mpc, phi_c in rad).
+ * idx:    device [n, 2] (distance-grid index or -1, phase index) or NULL.
+ * logl:   device [n] the row's marginal log L (as loglike_batch), or NULL.
+ * Unphysical rows give NaN and indices -1.  n_phase: 1 .. 2^20 (2048 is a
+ * good default: the conditional has width 1 / sqrt(kappa)).  Errors:
+ * GW_ENOTSUP for other marginals, GW_ESTATE without a distance grid (distance
+ * marginal) or heterodyne set-up (like = GW_HET).  Work space grows to
+ * n (4 + 2 n_det) doubles; the context's likelihood work space is reused.
+ */
+gw_status gw_reconstruct(gw_ctx* ctx, const double* theta, int64_t n, int32_t like, int32_t marg, int32_t prec,
+                         const double* uniforms, int32_t n_phase, double* out, int32_t* idx, double* logl,
+                         void* stream);
+
+/*
  * Projected templates h_i(f_k) on the full grid (Sec. III.A): one parameter
  * vector per row of ``theta`` (device [n, 13]); ``h`` is device
  * [n, n_det, n_freq, 2] FP64 (interleaved real, imaginary).  Rows that are
@@ -233,32 +264,39 @@ gw_status gw_graph_info(const gw_ctx* ctx, int32_t* n_graphs, double* last_insta
  * GW_MARG_PHASE_TIME (the paper's GW170817 configuration), phi_c and t_c
  * marginalised and d_L sampled as coordinate 10 in place of t_c (see
  * gw_prior_transform_marg); its rounds are launched without a graph.
- * Per chain: u a uniform unit vector (Box-Muller from uniforms 0..3), the
- * direction d = L u with L the block's lower Cholesky factor; a bracket
- * [-r w, (1 - r) w] with r = uniform 4; each end stepped out by w while
- * log L > log L* (at most max_out steps per side); then shrink draws
- * t = t_lo + u_s (t_hi - t_lo), s = 0 .. max_shrink - 1 (uniform 5 + s),
+ * A block holds 1 .. GW_MAX_BLOCK coordinates; one holding all 11 is the
+ * unblocked nested slice sampler of the sampler-configuration section.
+ * With F = GW_SLICE_UNI_FIXED(block_dim) = max(4, 2 ceil(block_dim / 2)) + 1:
+ * per chain, u a uniform unit vector (Box-Muller pair p from uniforms 2p and
+ * 2p + 1, the first block_dim normals, normalised), the direction d = L u
+ * with L the block's lower Cholesky factor; a bracket [-r w, (1 - r) w] with
+ * r = uniform F - 1; each end stepped out by w while log L > log L* (at most
+ * max_out steps per side); then shrink draws
+ * t = t_lo + u_s (t_hi - t_lo), s = 0 .. max_shrink - 1 (uniform F + s),
  * until log L > log L*, the bracket end on the side of t moving to t.  A point
  * outside the cube fails without a likelihood call.  After max_shrink
  * failures the chain keeps its point (status 1).
- * Random numbers: ``uniforms`` (device [k, 5 + max_shrink]) when not NULL,
+ * Random numbers: ``uniforms`` (device [k, F + max_shrink]) when not NULL,
  * else Philox4x64-10 (Salmon et al. 2011): uniform j of chain c is word j % 4
  * of the block at counter (counter, c, j / 4, 0) under key (seed, 0), mapped
  * to ((w >> 11) + 0.5) 2^-53.
  * Blocks until done (the host checks progress every four rounds; rounds
  * after every chain has finished change nothing).
  */
+#define GW_MAX_BLOCK 11
+#define GW_SLICE_UNI_FIXED(bd) (((bd) <= 4 ? 4 : 2 * (((bd) + 1) / 2)) + 1)
+
 typedef struct {
   int64_t k;              /* number of chains */
   double* x;              /* device [k, 11] unit-cube points, updated in place */
   double* logl;           /* device [k] log L of x, updated in place */
   double logl_star;       /* constraint log L* */
   const int32_t* block;   /* host [block_dim] coordinate indices 0..10, distinct */
-  int32_t block_dim;      /* 1 .. 4 */
+  int32_t block_dim;      /* 1 .. GW_MAX_BLOCK */
   const double* chol;     /* host [block_dim, block_dim] lower-triangular, row-major */
   uint64_t seed;          /* Philox key */
   uint64_t counter;       /* Philox counter base */
-  const double* uniforms; /* device [k, 5 + max_shrink] or NULL */
+  const double* uniforms; /* device [k, F + max_shrink] or NULL */
   double w;               /* bracket width along t (> 0) */
   int32_t max_out;        /* >= 0 */
   int32_t max_shrink;     /* 1 .. 10000 */
@@ -293,12 +331,17 @@ typedef struct {
   double* logl;            /* device [k], updated in place */
   double logl_star;        /* constraint log L* */
   int32_t n_blocks;        /* 1 .. 16 */
-  const int32_t* block_dim;/* host [n_blocks], each 1 .. 4 */
-  const int32_t* block;    /* host [n_blocks, 4] coordinate indices, the first
-                              block_dim[b] of row b used, distinct, 0 .. 10 */
-  const double* chol;      /* host [n_blocks, 4, 4] lower Cholesky factor of
-                              each block, row-major, leading block_dim[b]
-                              rows and columns used */
+  const int32_t* block_dim;/* host [n_blocks], each 1 .. GW_MAX_BLOCK */
+  const int32_t* block;    /* host [n_blocks, GW_MAX_BLOCK] coordinate indices,
+                              the first block_dim[b] of row b used, distinct,
+                              0 .. 10 */
+  const double* chol;      /* host [n_blocks, GW_MAX_BLOCK, GW_MAX_BLOCK] lower
+                              Cholesky factor of each block, row-major, leading
+                              block_dim[b] rows and columns used.  The
+                              distinct blocks (a block equal to an earlier one
+                              in coordinates and factor is not distinct) may
+                              hold at most 160 factor entries (block_dim^2
+                              each); beyond that GW_EINVAL. */
   uint64_t seed;           /* Philox key */
   uint64_t counter;        /* counter base of block 0 */
   double w;                /* bracket width along t (> 0) */

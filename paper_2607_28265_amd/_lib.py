@@ -19,6 +19,7 @@ GW_MARG_NONE, GW_MARG_PHASE, GW_MARG_PHASE_DIST, GW_MARG_PHASE_TIME = 0, 1, 2, 3
 GW_PREC_FP64, GW_PREC_MIXED = 0, 1
 GW_MAX_DET = 4
 GW_NPARAM = 13
+GW_MAX_BLOCK = 11  # coordinates per slice block (a block may hold all 11)
 
 _STATUS_NAMES = {0: "GW_OK", -1: "GW_EINVAL", -2: "GW_ENOMEM", -3: "GW_EDEVICE", -4: "GW_ESTATE", -5: "GW_ENOTSUP"}
 
@@ -151,6 +152,8 @@ _SIGS = {
                                           ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int64), _P]),
     "gw_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "gw_reconstruct": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                                      ctypes.c_int32, _P, _P, _P, _P]),
 }
 
 
@@ -361,6 +364,11 @@ def gw_autotune(ctx, theta, like: int, marg: int, prec: int, reps: int = 3, stre
     return (shape[0], shape[1], shape[2]), ms.value
 
 
+def slice_uniforms_fixed(block_dim: int) -> int:
+    """Uniforms of a slice update before its shrink draws (GW_SLICE_UNI_FIXED)."""
+    return (4 if block_dim <= 4 else 2 * ((block_dim + 1) // 2)) + 1
+
+
 def slice_step(ctx, x, logl, logl_star: float, block, chol, seed: int = 0, counter: int = 0, uniforms=None,
                w: float = 1.0, max_out: int = 10, max_shrink: int = 100, like: int = GW_HET,
                marg: int = GW_MARG_PHASE_DIST, prec: int = GW_PREC_FP64, n_evals=None, status=None, stream=None,
@@ -375,9 +383,10 @@ def slice_step(ctx, x, logl, logl_star: float, block, chol, seed: int = 0, count
         raise ValueError("logl must be a contiguous CUDA float64 tensor with k entries")
     blk = np.ascontiguousarray(block, dtype=np.int32)
     ch = np.ascontiguousarray(chol, dtype=np.float64).reshape(len(blk), len(blk))
+    nfix = slice_uniforms_fixed(len(blk))
     if uniforms is not None and not (uniforms.is_cuda and uniforms.dtype == torch.float64
-                                     and uniforms.is_contiguous() and uniforms.shape == (k, 5 + max_shrink)):
-        raise ValueError("uniforms must be a contiguous CUDA float64 tensor of shape [k, 5 + max_shrink]")
+                                     and uniforms.is_contiguous() and uniforms.shape == (k, nfix + max_shrink)):
+        raise ValueError(f"uniforms must be a contiguous CUDA float64 tensor of shape [k, {nfix} + max_shrink]")
     for t in (n_evals, status):
         if t is not None and not (t.is_cuda and t.dtype == torch.int32 and t.numel() == k and t.is_contiguous()):
             raise ValueError("n_evals / status must be contiguous CUDA int32 tensors with k entries")
@@ -419,12 +428,12 @@ def slice_sweep(ctx, x, logl, logl_star: float, blocks, chols, seed: int = 0, co
     if not 1 <= nb <= 16 or len(chols) != nb:
         raise ValueError("1..16 blocks, one Cholesky factor each")
     bd = np.zeros(nb, np.int32)
-    blk = np.zeros((nb, 4), np.int32)
-    ch = np.zeros((nb, 4, 4), np.float64)
+    blk = np.zeros((nb, GW_MAX_BLOCK), np.int32)
+    ch = np.zeros((nb, GW_MAX_BLOCK, GW_MAX_BLOCK), np.float64)
     for b, (idx, L) in enumerate(zip(blocks, chols)):
         idx = np.asarray(idx, dtype=np.int32).ravel()
-        if not 1 <= idx.size <= 4:
-            raise ValueError("each block has 1..4 coordinates")
+        if not 1 <= idx.size <= GW_MAX_BLOCK:
+            raise ValueError(f"each block has 1..{GW_MAX_BLOCK} coordinates")
         bd[b] = idx.size
         blk[b, :idx.size] = idx
         ch[b, :idx.size, :idx.size] = np.asarray(L, dtype=np.float64).reshape(idx.size, idx.size)
@@ -612,3 +621,25 @@ def gw_time_grid_info(ctx):
     check(load().gw_time_grid_info(ctx, ctypes.byref(d), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
           "gw_time_grid_info")
     return d.value, a.value, b.value, c.value
+
+
+def gw_reconstruct(ctx, theta, uniforms, like: int = GW_FULL, marg: int = GW_MARG_PHASE_DIST,
+                   prec: int = GW_PREC_MIXED, n_phase: int = 2048, stream=None):
+    """Post-hoc draws of (d_L, phi_c) for posterior samples ``theta``
+    (CUDA float64 [n, 13]) with ``uniforms`` (CUDA float64 [n, 2]).  Returns
+    (values [n, 2], grid indices int32 [n, 2], marginal log L [n])."""
+    import torch
+    if not (theta.is_cuda and theta.dtype == torch.float64 and theta.is_contiguous() and theta.dim() == 2
+            and theta.shape[1] == GW_NPARAM):
+        raise ValueError("theta must be a contiguous CUDA float64 tensor of shape [n, 13]")
+    n = theta.shape[0]
+    if not (uniforms.is_cuda and uniforms.dtype == torch.float64 and uniforms.is_contiguous()
+            and tuple(uniforms.shape) == (n, 2)):
+        raise ValueError("uniforms must be a contiguous CUDA float64 tensor of shape [n, 2]")
+    out = torch.empty((n, 2), dtype=torch.float64, device=theta.device)
+    idx = torch.empty((n, 2), dtype=torch.int32, device=theta.device)
+    logl = torch.empty(n, dtype=torch.float64, device=theta.device)
+    check(load().gw_reconstruct(ctx, _tensor_ptr(theta), n, int(like), int(marg), int(prec), _tensor_ptr(uniforms),
+                                int(n_phase), _tensor_ptr(out), _tensor_ptr(idx), _tensor_ptr(logl),
+                                _stream_ptr(stream)), "gw_reconstruct")
+    return out, idx, logl

@@ -62,6 +62,10 @@ struct gw_ctx {
   double* tm_mom = nullptr;
   int64_t tm_mom_cap = 0;
   void* blas = nullptr;            // rocBLAS handle (created on first use)
+  // post-hoc reconstruction workspace: (Re Z, Im Z, <h|h>) [3][n], per-detector
+  // sums [n][2 n_det], log L [n]
+  double* recon = nullptr;
+  int64_t recon_cap = 0;
   gw_het_state* het = nullptr;
   gw_graph_cache* graphs = nullptr;
   gw_slice_ws* slice = nullptr;
@@ -136,6 +140,10 @@ void graphs_free(gw_ctx* ctx);
 void slice_free(gw_ctx* ctx);
 gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl,
                       hipStream_t st);
+// Heterodyned likelihood that also stages each row's (Re Z, Im Z, <h|h>) in
+// zc3 [3][n] (Re Z NaN for rows that are not physical).
+gw_status loglike_het_staged(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl,
+                             double* zc3, hipStream_t st);
 // Full-band phase+time marginal (GW_MARG_PHASE_TIME).
 gw_status loglike_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, hipStream_t st);
 

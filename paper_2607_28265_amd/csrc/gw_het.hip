@@ -41,6 +41,7 @@ struct HetArgs {
   int64_t ld;
   int32_t n_sub;
   int32_t pad;
+  double* zcplx;        // or NULL: per-row (Re Z, Im Z, <h|h>) [3][ld] for post-hoc reconstruction
 };
 
 struct gw_het_state {
@@ -202,8 +203,9 @@ __global__ void __launch_bounds__(256) k_het_summary(const double* __restrict__ 
 __global__ void __launch_bounds__(256) k_set_args(HetArgs* a, const double* theta, const int64_t* subs, double* logl,
                                                   double* coef, double* zbuf, double* part, int64_t n_rows,
                                                   int32_t n_sub, int64_t* subs_single, int64_t single_n,
-                                                  int64_t* __restrict__ pre) {
+                                                  int64_t* __restrict__ pre, double* zcplx) {
   if (threadIdx.x == 0) {
+    a->zcplx = zcplx;
     a->theta = theta;
     a->subs = subs;
     a->logl = logl;
@@ -446,6 +448,11 @@ __device__ inline void het_finish_row(const HetArgs* __restrict__ ab, int64_t ro
   }
   const bool valid = cf[C_VALID * ld] != 0.0;
   const double zabs = sqrt(Zr * Zr + Zi * Zi);
+  if (ab->zcplx) {
+    ab->zcplx[row] = valid ? Zr : NAN;
+    ab->zcplx[ld + row] = Zi;
+    ab->zcplx[2 * ld + row] = hht;
+  }
   if (marg == 2) {
     ab->zbuf[row] = valid ? zabs : -1.0;
     ab->zbuf[ld + row] = hht;
@@ -750,7 +757,7 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
 
 // Workspace for n_rows rows and the argument block; returns the edge-chunk count.
 static gw_status het_prepare(gw_ctx* ctx, const double* theta, const int64_t* subs, int32_t n_sub, int64_t n_rows,
-                             double* logl, bool single, int* n_ech, hipStream_t st) {
+                             double* logl, bool single, int* n_ech, hipStream_t st, double* zcplx = nullptr) {
   gw_het_state* h = ctx->het;
   h->n_rows_last = n_rows;
   *n_ech = het_ech(ctx, n_rows);
@@ -762,7 +769,7 @@ static gw_status het_prepare(gw_ctx* ctx, const double* theta, const int64_t* su
   hipLaunchKernelGGL(k_set_args, dim3(1), dim3(256), 0, st, h->args, theta,
                      single ? (const int64_t*)h->subs_single : subs, logl, ctx->coef, ctx->zbuf, ctx->partial, n_rows,
                      single ? 1 : n_sub, single ? h->subs_single : (int64_t*)nullptr, single ? n_rows : (int64_t)0,
-                     h->tile_pre);
+                     h->tile_pre, zcplx);
   return check_hip(hipGetLastError(), "argument kernel launch");
 }
 
@@ -1011,8 +1018,14 @@ gw_status loglike_het_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int pre
 gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl, hipStream_t st) {
   if (!ctx->het) return set_error(GW_ESTATE, "loglike_batch: heterodyne_setup has not been called");
   if (marg == GW_MARG_PHASE_TIME) return loglike_het_tmarg(ctx, theta, n, prec, logl, st);
+  return loglike_het_staged(ctx, theta, n, marg, prec, logl, nullptr, st);
+}
+
+gw_status loglike_het_staged(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl,
+                             double* zc3, hipStream_t st) {
+  if (!ctx->het) return set_error(GW_ESTATE, "heterodyne_setup has not been called");
   int n_ech = 1;
-  gw_status s = het_prepare(ctx, theta, nullptr, 1, n, logl, true, &n_ech, st);
+  gw_status s = het_prepare(ctx, theta, nullptr, 1, n, logl, true, &n_ech, st, zc3);
   if (s != GW_OK) return s;
   return enqueue_het(ctx, marg, prec, n_ech, st);
 }

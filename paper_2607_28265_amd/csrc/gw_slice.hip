@@ -19,9 +19,14 @@
 namespace gw {
 
 constexpr int kSliceDim = 11;
-constexpr int kMaxBlock = 4;    // coordinates per block
+constexpr int kMaxBlock = 11;   // coordinates per block (a block may hold all of them)
 constexpr int kMaxBlocks = 16;  // blocks per sweep
-constexpr int kUniFixed = 5;    // 4 direction + 1 bracket offset
+constexpr int kCholPack = 160;  // doubles of packed Cholesky factors per sweep
+
+// Uniforms before the shrink draws of a block of bd coordinates: one
+// Box-Muller pair per two coordinates (at least two pairs), then the bracket
+// offset.
+__host__ __device__ inline int uni_fixed(int bd) { return (bd <= 4 ? 4 : 2 * ((bd + 1) / 2)) + 1; }
 
 // How the sampler's last coordinate is read: t_c (phase and distance
 // marginalised) or d_L (phase and time marginalised).
@@ -38,12 +43,13 @@ struct SweepParams {
   int32_t nb;
   int32_t bd[kMaxBlocks];
   int32_t block[kMaxBlocks][kMaxBlock];
-  double chol[kMaxBlocks][kMaxBlock * kMaxBlock];
+  int32_t choff[kMaxBlocks];  // block b's lower factor: chol[choff[b] + i * bd + j]
+  double chol[kCholPack];
   double w;
   double logl_star;
   int32_t max_out, max_shrink;
   uint64_t seed, counter;
-  const double* uniforms;  // one-block calls: [k][kUniFixed + max_shrink], or null
+  const double* uniforms;  // one-block calls: [k][uni_fixed(bd) + max_shrink], or null
   int64_t k;
   double* x;
   double* logl;
@@ -57,6 +63,10 @@ struct SweepParams {
   int32_t n_det;
   int32_t kind[kMaxBlocks];
 };
+
+// passed by value to the kernel that copies it to the device
+static_assert(sizeof(SweepParams) <= 4096, "sweep parameters must fit a kernel argument block");
+static_assert(GW_MAX_BLOCK == kMaxBlock, "block stride of the sweep arguments");
 
 // Per-chain state (structure of arrays inside one device allocation).
 struct SliceState {
@@ -108,7 +118,7 @@ __device__ inline void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
 // Uniform j of chain c in block b: explicit table, or Philox word j % 4 of
 // counter (counter_base + b, c, j / 4, 0) under key (seed, 0), mapped to (0, 1).
 __device__ inline double slice_uniform(const SweepParams& P, int b, int64_t c, int j) {
-  if (P.uniforms) return P.uniforms[c * (kUniFixed + P.max_shrink) + j];
+  if (P.uniforms) return P.uniforms[c * (uni_fixed(P.bd[b]) + P.max_shrink) + j];
   uint64_t ctr[4] = {P.counter + (uint64_t)b, (uint64_t)c, (uint64_t)(j >> 2), 0ull};
   philox4x64(ctr, P.seed, 0ull);
   return ((double)(ctr[j & 3] >> 11) + 0.5) * 1.1102230246251565404e-16;  // 2^-53
@@ -136,29 +146,31 @@ __device__ inline void prior_transform(const double* u, double* th, const CubeMa
   }
 }
 
-// Start block b for chain c: direction d = L u (u from Box-Muller normals of
-// uniforms 0..3, normalised), bracket [-r w, (1 - r) w] with r = uniform 4.
-// Returns the chain's new flags.
+// Start block b for chain c: direction d = L u (u from Box-Muller normals,
+// pair p from uniforms 2p and 2p + 1, normalised), bracket [-r w, (1 - r) w]
+// with r the uniform after the direction ones.  Returns the chain's new flags.
 __device__ inline int start_block(const SweepParams& P, const SliceState& S, int64_t c, int b) {
-  double u[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) u[j] = slice_uniform(P, b, c, j);
-  const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
-  double s0, c0, s1, c1;
-  sincos(kTwoPi * u[1], &s0, &c0);
-  sincos(kTwoPi * u[3], &s1, &c1);
-  const double z[4] = {r0 * c0, r0 * s0, r1 * c1, r1 * s1};
   const int bd = P.bd[b];
+  const int nfix = uni_fixed(bd);
+  double z[kMaxBlock + 1];
+  for (int p = 0; 2 * p < nfix - 1; ++p) {
+    const double r = sqrt(-2.0 * log(slice_uniform(P, b, c, 2 * p)));
+    double sn, cs;
+    sincos(kTwoPi * slice_uniform(P, b, c, 2 * p + 1), &sn, &cs);
+    if (2 * p < bd) z[2 * p] = r * cs;
+    if (2 * p + 1 < bd) z[2 * p + 1] = r * sn;
+  }
   double nrm = 0.0;
   for (int j = 0; j < bd; ++j) nrm += z[j] * z[j];
   nrm = sqrt(nrm);
+  const double* L = P.chol + P.choff[b];
   for (int a = 0; a < kMaxBlock; ++a) {
     double v = 0.0;
     for (int q = 0; q < bd; ++q)
-      if (a < bd) v += P.chol[b][a * kMaxBlock + q] * (z[q] / nrm);
+      if (a < bd) v += L[a * bd + q] * (z[q] / nrm);
     S.d[c * kMaxBlock + a] = a < bd ? v : 0.0;
   }
-  const double off = slice_uniform(P, b, c, 4);
+  const double off = slice_uniform(P, b, c, nfix - 1);
   S.t_lo[c] = -off * P.w;
   S.t_hi[c] = (1.0 - off) * P.w;
   S.n_out[2 * c] = 0;
@@ -240,7 +252,7 @@ __global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S,
       // shrinking: draw until a point lies in the cube (no likelihood needed
       // for the others) or the cap is reached
       while (S.n_shrink[c] < P.max_shrink) {
-        const double v = slice_uniform(P, b, c, kUniFixed + S.n_shrink[c]);
+        const double v = slice_uniform(P, b, c, uni_fixed(P.bd[b]) + S.n_shrink[c]);
         const double t = S.t_lo[c] + v * (S.t_hi[c] - S.t_lo[c]);
         if (make_point(P, b, S, x0, c, t, u)) {
           prior_transform(u, cand + 2 * c * 13, P.cm);
@@ -602,12 +614,14 @@ static gw_status check_sweep(const char* who, int64_t k, const double* x, const 
   return GW_OK;
 }
 
-// Check one block (indices distinct in 0..10, 1..4 of them) and copy its
-// lower Cholesky factor (row-major, stride ``ld``) into P's padded slot.
+// Check one block (indices distinct in 0..10, 1..11 of them) and pack its
+// lower Cholesky factor (row-major, stride ``ld``) into P.chol.  A block equal
+// to an earlier one of the sweep (same coordinates and factor) shares its
+// packed factor, so that one large block can be repeated.
 static gw_status set_block(const char* who, SweepParams& P, int b, const int32_t* idx, int32_t bd, const double* L,
-                           int ld) {
+                           int ld, int* used) {
   if (bd < 1 || bd > kMaxBlock)
-    return set_error(GW_EINVAL, "%s: block %d: block_dim 1..4", who, b);
+    return set_error(GW_EINVAL, "%s: block %d: block_dim 1..11", who, b);
   for (int i = 0; i < bd; ++i) {
     if (idx[i] < 0 || idx[i] >= kSliceDim)
       return set_error(GW_EINVAL, "%s: block %d: index 0..10", who, b);
@@ -617,9 +631,24 @@ static gw_status set_block(const char* who, SweepParams& P, int b, const int32_t
   }
   P.bd[b] = bd;
   for (int i = 0; i < kMaxBlock; ++i) P.block[b][i] = i < bd ? idx[i] : 0;
-  for (int i = 0; i < kMaxBlock * kMaxBlock; ++i) P.chol[b][i] = 0.0;
+  double f[kMaxBlock * kMaxBlock];
   for (int i = 0; i < bd; ++i)
-    for (int j = 0; j <= i; ++j) P.chol[b][i * kMaxBlock + j] = L[i * ld + j];
+    for (int j = 0; j < bd; ++j) f[i * bd + j] = j <= i ? L[i * ld + j] : 0.0;
+  for (int c = 0; c < b; ++c) {
+    if (P.bd[c] != bd) continue;
+    bool same = true;
+    for (int i = 0; i < bd && same; ++i) same = P.block[c][i] == idx[i];
+    for (int i = 0; i < bd * bd && same; ++i) same = P.chol[P.choff[c] + i] == f[i];
+    if (same) {
+      P.choff[b] = P.choff[c];
+      return GW_OK;
+    }
+  }
+  if (*used + bd * bd > kCholPack)
+    return set_error(GW_EINVAL, "%s: the distinct blocks' Cholesky factors exceed %d values", who, kCholPack);
+  P.choff[b] = *used;
+  for (int i = 0; i < bd * bd; ++i) P.chol[*used + i] = f[i];
+  *used += bd * bd;
   return GW_OK;
 }
 
@@ -706,7 +735,8 @@ gw_status slice_step(gw_ctx* ctx, const gw_slice_args* a, void* stream) {
   if (s != GW_OK || a->k == 0) return s;
   if (!a->block || !a->chol) return set_error(GW_EINVAL, "slice_step: null pointer");
   SweepParams P{};
-  s = set_block("slice_step", P, 0, a->block, a->block_dim, a->chol, a->block_dim);
+  int used = 0;
+  s = set_block("slice_step", P, 0, a->block, a->block_dim, a->chol, a->block_dim, &used);
   if (s != GW_OK) return s;
   P.nb = 1;
   P.w = a->w;
@@ -740,9 +770,10 @@ gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* a, void* stream) {
   if (a->counter > UINT64_MAX - (uint64_t)a->n_blocks)
     return set_error(GW_EINVAL, "slice_sweep: counter + n_blocks overflows");
   SweepParams P{};
+  int used = 0;
   for (int b = 0; b < a->n_blocks; ++b) {
-    s = set_block("slice_sweep", P, b, a->block + b * kMaxBlock, a->block_dim[b], a->chol + b * kMaxBlock * kMaxBlock,
-                  kMaxBlock);
+    s = set_block("slice_sweep", P, b, a->block + b * GW_MAX_BLOCK, a->block_dim[b],
+                  a->chol + b * GW_MAX_BLOCK * GW_MAX_BLOCK, GW_MAX_BLOCK, &used);
     if (s != GW_OK) return s;
   }
   P.nb = a->n_blocks;

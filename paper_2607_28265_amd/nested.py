@@ -10,7 +10,9 @@ points.  By default a whole sweep is one ``slice_sweep`` call, in which each
 chain moves on to its next block as soon as it has finished one; with
 ``async_sweep=False`` every block is a ``slice_step`` call of its own (all
 chains finish the block before any starts the next).  Both give the same
-chains bit for bit.  With ``cache=True`` (full band) the sweep keeps each
+chains bit for bit.  ``blocks=UNBLOCKED`` with ``sweeps=3 * 11`` is the
+unblocked nested slice sampler that the sampler-configuration section runs as
+a control (M d joint slice steps per iteration, M = 3).  With ``cache=True`` (full band) the sweep keeps each
 chain's waveform and reuses it on the extrinsic blocks (Sec. III.B).  With
 ``marg=GW_MARG_PHASE_TIME`` the phase and coalescence time are marginalised
 and d_L is sampled in place of t_c (the paper's GW170817 configuration).
@@ -33,6 +35,7 @@ N_DIM = 11
 # Slow blocks {Mc, q, Lambda1, Lambda2}, {chi1}, {chi2}, {iota};
 # fast blocks {ra, dec}, {psi}, {t_c} (indices into the unit cube).
 BLOCKS = ((0, 1, 4, 5), (2,), (3,), (6,), (7, 8), (9,), (10,))
+UNBLOCKED = (tuple(range(N_DIM)),)
 
 
 def _logsumexp(a):
@@ -128,17 +131,22 @@ class NestedSampler:
         xn = self.x.index_select(0, idx).contiguous()
         ln = self.logl.index_select(0, idx).contiguous()
         ne = torch.zeros(self.k, dtype=torch.int32, device=self.dev)
-        for _ in range(self.sweeps):
-            if self.async_sweep:
-                kinds = _lib.slice_sweep(self.ctx.handle, xn, ln, lstar, self.blocks, chols, seed=self.seed,
-                                 counter=self.counter, w=self.w, max_out=self.max_out, max_shrink=self.max_shrink,
-                                 like=self.like, marg=self.marg, prec=self.prec, n_evals=ne,
-                                 use_cache=self.cache)
+        if self.async_sweep:
+            # the M sweeps' blocks in order, at most 16 per call: the same
+            # moves as one call per sweep (block j of the sequence draws from
+            # counter + j either way)
+            seq = [bi for _ in range(self.sweeps) for bi in range(len(self.blocks))]
+            for j0 in range(0, len(seq), 16):
+                part = seq[j0:j0 + 16]
+                kinds = _lib.slice_sweep(self.ctx.handle, xn, ln, lstar, [self.blocks[b] for b in part],
+                                         [chols[b] for b in part], seed=self.seed, counter=self.counter, w=self.w,
+                                         max_out=self.max_out, max_shrink=self.max_shrink, like=self.like,
+                                         marg=self.marg, prec=self.prec, n_evals=ne, use_cache=self.cache)
                 if kinds is not None:
                     self.eval_kinds += np.array(kinds, np.int64)
                 self.n_evals += int(ne.sum().item())
-                self.counter += len(self.blocks)
-                continue
+                self.counter += len(part)
+        for _ in range(0 if self.async_sweep else self.sweeps):
             for bi, b in enumerate(self.blocks):
                 _lib.slice_step(self.ctx.handle, xn, ln, lstar, b, chols[bi], seed=self.seed, counter=self.counter,
                                 w=self.w, max_out=self.max_out, max_shrink=self.max_shrink, like=self.like,

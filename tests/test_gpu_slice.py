@@ -72,11 +72,18 @@ def _run_gpu(gw, ctx, x, logl, lstar, block, chol, uni=None, seed=0, counter=0, 
     return xt.cpu().numpy(), lt.cpu().numpy(), ne.cpu().numpy(), stt.cpu().numpy()
 
 
-@pytest.mark.parametrize("bi", range(len(S.BLOCKS)))
+# the Gibbs blocks, a 6-coordinate block and the unblocked sampler's single
+# block of all 11 coordinates (6 Box-Muller pairs)
+CASES = list(S.BLOCKS) + [(0, 1, 2, 3, 4, 5), tuple(range(11))]
+
+
+@pytest.mark.parametrize("bi", range(len(CASES)))
 @pytest.mark.parametrize("source", ["uniforms", "philox"])
 def test_slice_step_matches_oracle(setup, bi, source):
     gw, ctx, prob, het, loglike_u, x, logl = setup
-    block = S.BLOCKS[bi]
+    block = CASES[bi]
+    nfix = S.n_fixed_uniforms(len(block))
+    assert nfix == gw.slice_uniforms_fixed(len(block))
     chol = S.block_cholesky(x, block)
     lstar = float(np.quantile(logl, 0.25))
     ok0 = logl > lstar
@@ -85,11 +92,11 @@ def test_slice_step_matches_oracle(setup, bi, source):
     max_shrink, max_out = 60, 4
     seed, counter = 1234 + bi, 77
     if source == "uniforms":
-        uni = np.random.default_rng(100 + bi).uniform(size=(k, S.N_UNIFORM_FIXED + max_shrink))
+        uni = np.random.default_rng(100 + bi).uniform(size=(k, nfix + max_shrink))
         uni_c = lambda c: uni[c]
     else:
         uni = None
-        uni_c = lambda c: S.philox_uniforms(seed, counter, c, S.N_UNIFORM_FIXED + max_shrink)
+        uni_c = lambda c: S.philox_uniforms(seed, counter, c, nfix + max_shrink)
     gx, gl, gne, gst = _run_gpu(gw, ctx, x, logl, lstar, block, chol, uni, seed, counter, max_shrink, max_out)
     n_cmp = 0
     for c in range(k):
@@ -138,8 +145,8 @@ def test_graph_replay_equals_eager(setup, like):
             assert np.array_equal(a, b), (call, bi)
 
 
-@pytest.mark.parametrize("like,prec", [(1, 0), (1, 1), (0, 1)])
-def test_sweep_equals_sequential_steps(setup, like, prec):
+@pytest.mark.parametrize("like,prec,unblocked", [(1, 0, 0), (1, 1, 0), (0, 1, 0), (1, 1, 1)])
+def test_sweep_equals_sequential_steps(setup, like, prec, unblocked):
     # a chain's moves in one sweep are those of successive one-block steps
     # with counters counter, counter + 1, ...: bit-identical, although chains
     # start their next block at different rounds
@@ -147,7 +154,9 @@ def test_sweep_equals_sequential_steps(setup, like, prec):
     lstar = float(np.quantile(logl, 0.25))
     keep = logl > lstar
     xs, ls = x[keep], logl[keep]
-    blocks = list(S.BLOCKS)
+    # unblocked: the 11-coordinate block five times (one packed factor),
+    # then two Gibbs blocks
+    blocks = [tuple(range(11))] * 5 + list(S.BLOCKS[:2]) if unblocked else list(S.BLOCKS)
     chols = [S.block_cholesky(x, b) for b in blocks]
     seed, counter = 17, 500
     k = len(xs)
@@ -202,3 +211,5 @@ def test_sweep_one_block_equals_step_and_errors(setup):
         gw.slice_sweep(ctx.handle, xt, lt, lstar, [[0]], [np.eye(1)], marg=gw.GW_MARG_PHASE)
     with pytest.raises(ValueError):
         gw.slice_sweep(ctx.handle, xt, lt, lstar, [[0]] * 17, [np.eye(1)] * 17)
+    with pytest.raises(gw.GwError):  # two distinct 11-coordinate factors exceed the packed store
+        gw.slice_sweep(ctx.handle, xt, lt, lstar, [list(range(11))] * 2, [np.eye(11), 0.5 * np.eye(11)])
