@@ -165,6 +165,15 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2607_28265_amd.build` "
                            "(there is no CPU fallback)")
+    # Device memory and streams come from torch, which brings its own HIP
+    # runtime: start it before the library is loaded, so that the library
+    # binds to the runtime already in the process instead of starting a
+    # second one (a second runtime started first leaves torch without GPUs).
+    try:
+        import torch
+        torch.cuda.is_available()
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
