@@ -21,6 +21,8 @@ reconstruct post-hoc draws of the marginalised d_L and phi_c on their grids
             (grid-marginalisation appendix).
 pp          credible levels, KS and Fisher p-values of an injection campaign
             (P-P calibration section).
+fiducial    differential-evolution search for the heterodyne fiducial and the
+            conditional peak of (d_L, phi_c) (GW170817 section).
 
 Parity unpinned: the TaylorF2 post-Newtonian and spin coefficients beyond the
 Newtonian limit and the equal-mass tidal case (the paper prints no waveform

@@ -82,6 +82,55 @@ def prior_transform_time(u: np.ndarray, d_lo: float, d_hi: float) -> np.ndarray:
     return th
 
 
+C_SI = 299792458.0  # m / s
+
+
+def sky_frame_basis(det_pos: np.ndarray, a: int = 0, b: int = 1):
+    """Unit baseline n = (r_b - r_a) / |r_b - r_a| of detectors a and b and an
+    orthonormal pair across it: e1 is the Earth's axis z made orthogonal to n
+    (x when n lies along z), e2 = n x e1."""
+    base = np.asarray(det_pos[b], dtype=np.float64) - np.asarray(det_pos[a], dtype=np.float64)
+    n = base / np.linalg.norm(base)
+    ref = np.array([0.0, 0.0, 1.0])
+    if abs(n @ ref) > 0.99:
+        ref = np.array([1.0, 0.0, 0.0])
+    e1 = ref - (ref @ n) * n
+    e1 = e1 / np.linalg.norm(e1)
+    e2 = np.cross(n, e1)
+    return n, e1, e2
+
+
+def detector_frame_sky(u_az: float, u_zen: float, det_pos: np.ndarray, gmst: float = 0.0, a: int = 0,
+                       b: int = 1):
+    """(ra, dec) of the direction with azimuth 2 pi u_az and zenith
+    acos(1 - 2 u_zen) about the baseline of detectors a and b (the detector
+    sky frame of the blocked-kernel section); isotropic when u is uniform.
+    Returns (ra, dec, s) with s the unit source direction (Earth-fixed)."""
+    n, e1, e2 = sky_frame_basis(det_pos, a, b)
+    kap = 2.0 * math.pi * u_az
+    zen = math.acos(1.0 - 2.0 * u_zen)
+    s = math.cos(zen) * n + math.sin(zen) * (math.cos(kap) * e1 + math.sin(kap) * e2)
+    dec = math.asin(max(-1.0, min(1.0, float(s[2]))))
+    ra = (math.atan2(float(s[1]), float(s[0])) + gmst) % (2.0 * math.pi)
+    return ra, dec, s
+
+
+def prior_transform_frame(u: np.ndarray, det_pos: np.ndarray, gmst: float = 0.0, a: int = 0, b: int = 1,
+                          det_time: bool = False, d_range=None) -> np.ndarray:
+    """``prior_transform`` (or ``prior_transform_time`` when d_range = (d_lo,
+    d_hi)) with coordinates 7 and 8 read in the detector sky frame.  With
+    det_time, coordinate 10 is the arrival time t_a at detector a, uniform on
+    [-0.1, 0.1] s, and t_c = t_a + s . r_a / c (the detector-frame time that
+    the same section suggests); the implied prior on the geocentre t_c is
+    uniform only away from the ends of its range."""
+    th = prior_transform(u) if d_range is None else prior_transform_time(u, *d_range)
+    ra, dec, s = detector_frame_sky(float(u[7]), float(u[8]), det_pos, gmst, a, b)
+    th[8], th[9] = ra, dec
+    if det_time and d_range is None:
+        th[12] = (-0.1 + 0.2 * float(u[10])) + float(s @ np.asarray(det_pos[a], dtype=np.float64)) / C_SI
+    return th
+
+
 def philox4x64(counter, key):
     """Philox4x64 with 10 rounds (Salmon, Moraes, Dror & Shaw 2011)."""
     c = [int(v) & _MASK for v in counter]

@@ -144,3 +144,51 @@ def test_time_marginal_transform_samples_a_d_squared_prior():
     assert np.array_equal(np.delete(th[:10], [6, 12], axis=1), np.delete(ref, [6, 12], axis=1))
     assert S.prior_transform_time(np.zeros(11), 10.0, 200.0)[6] == pytest.approx(10.0, rel=1e-15)
     assert S.prior_transform_time(np.ones(11), 10.0, 200.0)[6] == pytest.approx(200.0, rel=1e-15)
+
+
+def test_detector_frame_sky_is_isotropic_and_keeps_the_baseline_delay():
+    # The detector sky frame (zenith and azimuth about the baseline of
+    # detectors 0 and 1): uniform u gives an isotropic sky (sin dec and ra
+    # uniform); the delay between the two detectors depends on the zenith
+    # only, -|r_1 - r_0| cos(zenith) / c, whatever the azimuth; u_zen = 0
+    # points along the baseline.  Delays come from the detector module's own
+    # (ra, dec) path, with a non-zero GMST.
+    from oracle import detector as D
+    import gwsynth
+    pos, _ = gwsynth.detectors()
+    gmst = 1.234
+    rng = np.random.default_rng(3)
+    u = rng.uniform(size=(4000, 2))
+    rd = np.array([S.detector_frame_sky(a, b, pos, gmst)[:2] for a, b in u])
+    assert stats.kstest(np.sin(rd[:, 1]), "uniform", args=(-1, 2)).pvalue > 1e-3
+    assert stats.kstest(rd[:, 0], "uniform", args=(0, 2 * math.pi)).pvalue > 1e-3
+    base = np.linalg.norm(pos[1] - pos[0])
+    for uz in (0.1, 0.37, 0.5, 0.93):
+        want = -base * (1 - 2 * uz) / S.C_SI
+        for ua in rng.uniform(size=5):
+            ra, dec, _ = S.detector_frame_sky(ua, uz, pos, gmst)
+            got = D.time_delay(pos[1], ra, dec, gmst) - D.time_delay(pos[0], ra, dec, gmst)
+            assert abs(got - want) < 1e-15
+    n, _, _ = S.sky_frame_basis(pos)
+    for ua in (0.0, 0.3, 0.8):
+        _, _, s = S.detector_frame_sky(ua, 0.0, pos, gmst)
+        assert np.allclose(s, n, rtol=0, atol=1e-15)
+
+
+def test_detector_frame_time():
+    # with det_time, coordinate 10 is the arrival time at detector 0:
+    # t_c + dt_0(ra, dec) equals -0.1 + 0.2 u_10; the other columns are those
+    # of the plain transform, apart from the sky
+    from oracle import detector as D
+    import gwsynth
+    pos, _ = gwsynth.detectors()
+    rng = np.random.default_rng(4)
+    for u in rng.uniform(size=(20, 11)):
+        th = S.prior_transform_frame(u, pos, 0.7, det_time=True)
+        ta = th[12] + D.time_delay(pos[0], th[8], th[9], 0.7)
+        assert abs(ta - (-0.1 + 0.2 * u[10])) < 1e-15
+        plain = S.prior_transform(u)
+        keep = [0, 1, 2, 3, 4, 5, 6, 7, 10, 11]
+        assert np.array_equal(th[keep], plain[keep])
+        tt = S.prior_transform_frame(u, pos, 0.7, d_range=(10.0, 200.0))
+        assert np.array_equal(tt[[6, 12]], S.prior_transform_time(u, 10.0, 200.0)[[6, 12]])
