@@ -64,9 +64,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="full,het,tmarg,cache,nested,nested_full,prescreen",
-                    help="comma list of legs to run: full (always timed), het, tmarg, cache, nested, "
-                         "nested_full, prescreen, copy")
+    ap.add_argument("--legs", default="full,het,tmarg,recon,cache,fiducial,nested,nested_full,prescreen",
+                    help="comma list of legs to run: full (always timed), het, tmarg, recon, cache, fiducial, "
+                         "nested, nested_full, prescreen, copy")
     return ap.parse_args()
 
 
@@ -286,8 +286,20 @@ def nested_leg(gw, torch):
                            prec=gw.GW_PREC_MIXED)
         r = ns.run()
         wall = time.perf_counter() - t0
+        # the same run with the sky sampled about the baseline of detectors 0
+        # and 1, then also with the arrival time at detector 0 as coordinate 10
+        frames = {}
+        for name, det_time in (("detector_frame", False), ("detector_frame_and_time", True)):
+            gw.gw_set_sky_frame(ctx.handle, 1, 0, 1, det_time)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rf = NestedSampler(ctx, n_live=1000, n_delete=125, seed=gwsynth.SEEDS["sampler"], like=gw.GW_HET,
+                               prec=gw.GW_PREC_MIXED).run()
+            frames[name] = {"wall_s": time.perf_counter() - t1, "log_z": rf["log_z"], "log_z_err": rf["log_z_err"],
+                            "iterations": rf["iterations"], "n_evals": rf["n_evals"], "ess": rf["ess"]}
+        gw.gw_set_sky_frame(ctx.handle, 0)
     out = {"wall_s": wall, "log_z": r["log_z"], "log_z_err": r["log_z_err"], "iterations": r["iterations"],
-           "n_evals": r["n_evals"], "evals_per_s": r["n_evals"] / wall}
+           "n_evals": r["n_evals"], "evals_per_s": r["n_evals"] / wall, "ess": r["ess"], "sky_frames": frames}
     gold = os.path.join(ROOT, "tests", "golden", "ns_cfg2.json")
     if os.path.exists(gold):
         with open(gold) as f:
@@ -442,6 +454,74 @@ def nested_full_leg(gw, torch):
     return out
 
 
+def recon_leg(gw, torch, ctx, theta, steps, warmup, dt_like):
+    """Post-hoc reconstruction of (d_L, phi_c) for the 4096 proposals of the
+    128 s band (mixed form): the likelihood pass that stages each overlap,
+    then one wave per sample draws on the 1000-point distance grid and the
+    2048-point phase grid."""
+    import numpy as np
+    n = theta.shape[0]
+    uni = torch.from_numpy(np.random.default_rng(8).uniform(size=(n, 2))).cuda()
+    for _ in range(warmup):
+        gw.gw_reconstruct(ctx.handle, theta, uni, like=gw.GW_FULL, marg=gw.GW_MARG_PHASE_DIST, prec=gw.GW_PREC_MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gw.gw_reconstruct(ctx.handle, theta, uni, like=gw.GW_FULL, marg=gw.GW_MARG_PHASE_DIST, prec=gw.GW_PREC_MIXED)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"value": n / dt, "unit": "samples/s", "ms_per_batch": dt * 1e3, "batch": n,
+            "draw_ms_over_likelihood": dt * 1e3 - dt_like * 1e3,
+            "workload": "post-hoc d_L and phi_c for 4096 samples of the 128 s band (likelihood pass included), "
+                        "1000 distance nodes, 2048 phase nodes"}
+
+
+def fiducial_leg(gw, torch, pop=8192, gens=300):
+    """Maximum-likelihood fiducial search on the loud 128 s injection: a box
+    narrowed in chirp mass (+-0.002 Msun) and t_c (+-5 ms) around the event,
+    all other coordinates over their whole prior range; then the heterodyne
+    (500 bins) from the found point against the one from the true point, on
+    2048 draws near the posterior."""
+    import numpy as np
+    import gwsynth
+    from paper_2607_28265_amd import prescreen as P
+    from paper_2607_28265_amd.pp import to_cube
+    cfg = gwsynth.CONFIGS["cfg2"]
+    prob = gwsynth.make_problem(cfg["duration"], cfg["f_min"], cfg["f_max"], psd_scale=1e-49)
+    th = gwsynth.prior_draws(gwsynth.SEEDS["injection"], 1)[0]
+    th_inj = P.library_injection(gw.Context, prob, th, snr=24.0)
+    u_inj = to_cube(th_inj, 10.0, 200.0, False)
+    lo, hi = np.zeros(11), np.ones(11)
+    lo[0], hi[0] = max(0.0, u_inj[0] - 0.002 / 0.3), min(1.0, u_inj[0] + 0.002 / 0.3)
+    lo[10], hi[10] = max(0.0, u_inj[10] - 0.005 / 0.2), min(1.0, u_inj[10] + 0.005 / 0.2)
+    out = {}
+    with gw.Context(prob) as ctx:
+        x = torch.from_numpy(lo + (hi - lo) * np.random.default_rng(12).uniform(size=(pop, 11))).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fx, best = gw.gw_fiducial_search(ctx.handle, x, gens, seed=13, lo=lo, hi=hi, prec=gw.GW_PREC_MIXED)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ti = torch.from_numpy(th_inj[None, :].copy()).cuda()
+        f_inj = float(ctx.loglike(ti, gw.GW_FULL, gw.GW_MARG_PHASE_DIST, gw.GW_PREC_FP64).item())
+        near = torch.from_numpy(gwsynth.near_posterior(14, th_inj, 2048, scale=0.5)).cuda()
+        full = ctx.loglike(near, gw.GW_FULL, gw.GW_MARG_PHASE_DIST, gw.GW_PREC_FP64)
+        errs = {}
+        for name, fid in (("found", best), ("true", th_inj)):
+            ctx.heterodyne_setup(fid, 500)
+            het = ctx.loglike(near, gw.GW_HET, gw.GW_MARG_PHASE_DIST, gw.GW_PREC_FP64)
+            errs[name] = float(torch.max(torch.abs(het - full)).item())
+        out = {"wall_s": wall, "pop": pop, "generations": gens, "evals": pop * (gens + 1),
+               "evals_per_s": pop * (gens + 1) / wall, "best_logl": float(fx.max().item()), "injection_logl": f_inj,
+               "best_minus_injection": float(fx.max().item()) - f_inj,
+               "het500_max_abs_err_near_posterior": errs,
+               "found_minus_true": {"mc": float(best[0] - th_inj[0]), "tc_ms": float(1e3 * (best[12] - th_inj[12]))},
+               "workload": "differential evolution (DE/rand/1/bin, F 0.6, CR 0.9) on the full-band phase+distance "
+                           "marginal of the 128 s SNR-24 injection; box: chirp mass +-0.002 Msun, t_c +-5 ms, "
+                           "the rest of the unit cube free"}
+    return out
+
+
 def copy_leg(torch, reps=5, mib=256):
     """A plain device copy of known size, the reference for the HBM byte
     counters (FETCH_SIZE, WRITE_SIZE) of the kernels above."""
@@ -508,6 +588,9 @@ def main():
         tm = None
         if "tmarg" in set(args.legs.split(",")):
             tm = tmarg_leg(gw, torch, ctx, theta, max(5, args.steps // 2), 2, n * args.steps / dt_mix)
+        rc = None
+        if "recon" in set(args.legs.split(",")):
+            rc = recon_leg(gw, torch, ctx, theta, max(5, args.steps // 2), 2, dt_mix / args.steps)
     value = n * args.steps / dt_mix
     fp_value = n * fp_steps / dt_fp
     units = n * prob.n_freq
@@ -548,8 +631,12 @@ def main():
         res["heterodyned"] = het_leg(gw, torch, prob, th_inj, max(5, args.steps // 2), 2)
     if tm is not None:
         res["time_marginal"] = tm
+    if rc is not None:
+        res["reconstruction"] = rc
     if "cache" in legs:
         res["waveform_cache"] = cache_leg(gw, torch, prob, args.steps, args.warmup, value)
+    if "fiducial" in legs:
+        res["fiducial_search"] = fiducial_leg(gw, torch)
     if "nested" in legs:
         res["nested_sampling"] = nested_leg(gw, torch)
     if "nested_full" in legs:

@@ -396,6 +396,72 @@ gw_status gw_prior_transform_marg(gw_ctx* ctx, const double* x, int64_t n, int32
                                   void* stream);
 
 /*
+ * Sky frame of the sampler's unit cube (blocked-kernel section: the source
+ * direction is sampled as zenith and azimuth about a detector baseline rather
+ * than as (ra, dec); the same section suggests detector-frame time too).
+ * frame = 0: coordinates 7 and 8 are ra and dec (the default).  frame = 1:
+ * with n = (r_b - r_a) / |r_b - r_a| the baseline of detectors det_a and
+ * det_b (Earth-fixed positions), e1 the Earth's axis z made orthogonal to n
+ * (x when |n_z| > 0.99) and e2 = n x e1, coordinate 7 is the azimuth
+ * kappa = 2 pi u_7 and coordinate 8 the zenith acos(1 - 2 u_8), so that
+ * s = cos(zen) n + sin(zen) (cos(kappa) e1 + sin(kappa) e2), dec = asin(s_z),
+ * ra = atan2(s_y, s_x) + gmst (mod 2 pi).  Uniform points give an isotropic
+ * sky, as before; the delay between the two detectors depends on the zenith
+ * alone.  det_time = 1 (frame 1 only, not with GW_MARG_PHASE_TIME): coordinate
+ * 10 is the arrival time t_a at detector det_a, uniform on [-0.1, 0.1] s, and
+ * t_c = t_a + s . r_a / c (the geocentre t_c is then uniform only away from
+ * the ends of its range).  Applies to slice_step, slice_sweep and the prior
+ * transforms from the next call on.  GW_EINVAL for bad detectors or flags.
+ */
+gw_status gw_set_sky_frame(gw_ctx* ctx, int32_t frame, int32_t det_a, int32_t det_b, int32_t det_time);
+
+/*
+ * Maximum-likelihood search for the heterodyne fiducial (GW170817 section:
+ * the reference parameters of the relative binning come from a
+ * maximum-likelihood optimisation over priors narrowed to the event; the
+ * limitations section notes that a deployment has to find them).  Maximises
+ * the full-band phase+distance marginal log L (like = GW_FULL,
+ * marg = GW_MARG_PHASE_DIST, the given prec) over the box [lo, hi] of the
+ * sampler's unit cube (in the context's sky frame) by differential evolution,
+ * DE/rand/1/bin (Storn & Price 1997): in generation g, member i draws
+ * uniforms u_j = Philox4x64-10 word j % 4 of counter (g, i, j / 4, 0) under
+ * key (seed, 2), mapped to ((w >> 11) + 0.5) 2^-53; u_0, u_1, u_2 choose three
+ * distinct partners r1, r2, r3 other than i (r1 the floor(u_0 (P - 1))-th
+ * index of 0..P-1 without i, r2 the floor(u_1 (P - 2))-th without {i, r1},
+ * r3 the floor(u_2 (P - 3))-th without {i, r1, r2}); coordinate j takes the
+ * mutant x_r1 + F (x_r2 - x_r3) (computed without fused multiply-add) when
+ * j = floor(11 u_3) or u_(4+j) < CR, else x_ij; a mutant coordinate outside
+ * [lo_j, hi_j] is mirrored at the wall it crossed and clipped.  All trials of
+ * a generation are made first; a trial then replaces its member when its
+ * log L is not NaN and at least the member's (or the member's is NaN).
+ * x:          device [pop, 11] initial population inside the box, replaced by
+ *             the final population.
+ * fx:         device [pop] log L of the final population.
+ * theta_best: host [13] parameter vector of the best member, with d_L and
+ *             phi_c at the peak of the unmarginalised likelihood:
+ *             phi_c = -arg Z_1 (mod 2 pi) and d_L = <h|h>_1 / |Z_1|, from the
+ *             member's FP64 overlap Z_1 and norm <h|h>_1 at d_L = 1 Mpc.
+ * Synchronises the stream.  Work space pop x 25 doubles for the call.
+ * Errors: GW_EINVAL for pop outside 4 .. 2^22, generations < 0, F outside
+ * (0, 2], CR outside [0, 1], a box outside [0, 1]; GW_ESTATE without a
+ * distance grid; GW_EDEVICE when no member has a finite log L or the best
+ * one has no overlap with the data.
+ */
+typedef struct {
+  int64_t pop;            /* population size P */
+  int32_t generations;    /* >= 0 */
+  double f_scale;         /* F */
+  double cr;              /* CR */
+  uint64_t seed;          /* Philox key word 0 */
+  const double* lo;       /* host [11] or NULL (zeros) */
+  const double* hi;       /* host [11] or NULL (ones) */
+  int32_t prec;           /* GW_PREC_FP64 or GW_PREC_MIXED */
+} gw_fiducial_args;
+
+gw_status gw_fiducial_search(gw_ctx* ctx, const gw_fiducial_args* args, double* x, double* fx, double* theta_best,
+                             void* stream);
+
+/*
  * Waveform cache (Sec. III.B, Sec. III.A): the slow / fast likelihood pair.
  * A slot holds one point's overlaps z_i = sum_k u_ik exp(-2 pi i Phi_ik)
  * and its intrinsic waveform g_k = exp(-2 pi i Psi(f_k)) (Psi the TaylorF2

@@ -98,6 +98,19 @@ class gw_sweep_args(ctypes.Structure):
     ]
 
 
+class gw_fiducial_args(ctypes.Structure):
+    _fields_ = [
+        ("pop", ctypes.c_int64),
+        ("generations", ctypes.c_int32),
+        ("f_scale", ctypes.c_double),
+        ("cr", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("lo", ctypes.POINTER(ctypes.c_double)),
+        ("hi", ctypes.POINTER(ctypes.c_double)),
+        ("prec", ctypes.c_int32),
+    ]
+
+
 _LIB = None
 
 _P = ctypes.c_void_p
@@ -152,6 +165,9 @@ _SIGS = {
                                           ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int64), _P]),
     "gw_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "gw_fiducial_search": (ctypes.c_int, [_P, ctypes.POINTER(gw_fiducial_args), _P, _P,
+                                          ctypes.POINTER(ctypes.c_double), _P]),
+    "gw_set_sky_frame": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "gw_reconstruct": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                                       ctypes.c_int32, _P, _P, _P, _P]),
 }
@@ -652,3 +668,32 @@ def gw_reconstruct(ctx, theta, uniforms, like: int = GW_FULL, marg: int = GW_MAR
                                 int(n_phase), _tensor_ptr(out), _tensor_ptr(idx), _tensor_ptr(logl),
                                 _stream_ptr(stream)), "gw_reconstruct")
     return out, idx, logl
+
+
+def gw_set_sky_frame(ctx, frame: int = 1, det_a: int = 0, det_b: int = 1, det_time: bool = False):
+    """Sample the sky as zenith / azimuth about the baseline of detectors
+    det_a -> det_b (frame 1) or as ra / dec (frame 0); det_time makes
+    coordinate 10 the arrival time at det_a."""
+    check(load().gw_set_sky_frame(ctx, int(frame), int(det_a), int(det_b), 1 if det_time else 0), "gw_set_sky_frame")
+
+
+def gw_fiducial_search(ctx, x, generations: int, seed: int = 0, f_scale: float = 0.6, cr: float = 0.9, lo=None,
+                       hi=None, prec: int = GW_PREC_MIXED, stream=None):
+    """Differential-evolution search for the maximum of the full-band
+    phase+distance marginal log L from population ``x`` (CUDA float64
+    [pop, 11], updated in place).  Returns (log L of the final population
+    [pop], best parameter vector [13] with d_L and phi_c at the peak)."""
+    import numpy as np
+    import torch
+    if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == 11):
+        raise ValueError("x must be a contiguous CUDA float64 tensor of shape [pop, 11]")
+    fx = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+    lo_a = None if lo is None else np.ascontiguousarray(lo, dtype=np.float64).reshape(11)
+    hi_a = None if hi is None else np.ascontiguousarray(hi, dtype=np.float64).reshape(11)
+    a = gw_fiducial_args(pop=x.shape[0], generations=int(generations), f_scale=float(f_scale), cr=float(cr),
+                         seed=int(seed), lo=_dptr(lo_a) if lo_a is not None else None,
+                         hi=_dptr(hi_a) if hi_a is not None else None, prec=int(prec))
+    best = np.zeros(13)
+    check(load().gw_fiducial_search(ctx, ctypes.byref(a), _tensor_ptr(x), _tensor_ptr(fx), _dptr(best),
+                                    _stream_ptr(stream)), "gw_fiducial_search")
+    return fx, best

@@ -62,6 +62,10 @@ struct gw_ctx {
   double* tm_mom = nullptr;
   int64_t tm_mom_cap = 0;
   void* blas = nullptr;            // rocBLAS handle (created on first use)
+  // sampler sky frame: 0 equatorial (ra, dec), 1 zenith and azimuth about the
+  // baseline of detectors sky_a -> sky_b; sky_det_time: coordinate 10 is the
+  // arrival time at detector sky_a
+  int sky_frame = 0, sky_a = 0, sky_b = 1, sky_det_time = 0;
   // post-hoc reconstruction workspace: (Re Z, Im Z, <h|h>) [3][n], per-detector
   // sums [n][2 n_det], log L [n]
   double* recon = nullptr;
@@ -144,6 +148,11 @@ gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int
 // zc3 [3][n] (Re Z NaN for rows that are not physical).
 gw_status loglike_het_staged(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl,
                              double* zc3, hipStream_t st);
+// Any likelihood (like, marg = GW_MARG_PHASE or GW_MARG_PHASE_DIST, prec):
+// stage each row's (Re Z, Im Z, <h|h>) in ctx->recon [3][n] and its log L in
+// logl (NULL: in the work space).
+gw_status stage_overlaps(gw_ctx* ctx, const double* theta, int64_t n, int like, int marg, int prec, double* logl,
+                         hipStream_t st);
 // Full-band phase+time marginal (GW_MARG_PHASE_TIME).
 gw_status loglike_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, hipStream_t st);
 

@@ -147,6 +147,32 @@ __global__ void __launch_bounds__(256) k_recon(const double* __restrict__ zc3, i
   }
 }
 
+// Stage (Re Z, Im Z, <h|h>) of n rows in ctx->recon [3][n] (Re Z NaN for
+// unphysical rows) and their marginal log L in logl (or in the work space).
+gw_status stage_overlaps(gw_ctx* ctx, const double* theta, int64_t n, int like, int marg, int prec, double* logl,
+                         hipStream_t st) {
+  const int nd = ctx->n_det;
+  gw_status s = ensure_buffer(&ctx->recon, &ctx->recon_cap, (int64_t)(3 + 2 * nd + 1) * n, "reconstruction workspace");
+  if (s != GW_OK) return s;
+  double* zc3 = ctx->recon;
+  double* zrow = zc3 + 3 * n;
+  double* ll = logl ? logl : zrow + 2 * nd * n;
+  if (like == GW_HET) return loglike_het_staged(ctx, theta, n, marg, prec, ll, zc3, st);
+  int tpb, nch;
+  full_launch_shape(ctx, n, &tpb, &nch);
+  s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
+  if (s == GW_OK) s = ensure_buffer(&ctx->partial, &ctx->partial_cap, (int64_t)nch * 2 * nd * n, "partials");
+  if (s == GW_OK) s = ensure_buffer(&ctx->zbuf, &ctx->zbuf_cap, 2 * n, "marginal workspace");
+  if (s == GW_OK) s = launch_prologue(ctx, theta, n, marg, ctx->coef, n, st);
+  if (s == GW_OK) s = launch_full(ctx, ctx->coef, n, n, prec, tpb, nch, ctx->partial, st);
+  if (s == GW_OK)
+    s = launch_epilogue_cached(ctx, ctx->partial, nch, ctx->coef, n, n, marg, prec, ll, nullptr, nullptr, zrow, st);
+  if (s != GW_OK) return s;
+  hipLaunchKernelGGL(k_recon_stage, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, zrow, nd, ctx->coef, n, n,
+                     zc3);
+  return check_hip(hipGetLastError(), "reconstruction staging launch");
+}
+
 }  // namespace gw
 
 using namespace gw;
@@ -171,32 +197,9 @@ gw_status gw_reconstruct(gw_ctx* ctx, const double* theta, int64_t n, int32_t li
   hipStream_t st = (hipStream_t)stream;
   gw_status s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
   if (s != GW_OK) return s;
-  const int nd = ctx->n_det;
-  s = ensure_buffer(&ctx->recon, &ctx->recon_cap, (int64_t)(3 + 2 * nd + 1) * n, "reconstruction workspace");
+  s = stage_overlaps(ctx, theta, n, like, marg, prec, logl, st);
   if (s != GW_OK) return s;
   double* zc3 = ctx->recon;
-  double* zrow = zc3 + 3 * n;
-  double* ll = logl ? logl : zrow + 2 * nd * n;
-  if (like == GW_HET) {
-    s = loglike_het_staged(ctx, theta, n, marg, prec, ll, zc3, st);
-  } else {
-    int tpb, nch;
-    full_launch_shape(ctx, n, &tpb, &nch);
-    s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
-    if (s == GW_OK) s = ensure_buffer(&ctx->partial, &ctx->partial_cap, (int64_t)nch * 2 * nd * n, "partials");
-    if (s == GW_OK) s = ensure_buffer(&ctx->zbuf, &ctx->zbuf_cap, 2 * n, "marginal workspace");
-    if (s == GW_OK) s = launch_prologue(ctx, theta, n, marg, ctx->coef, n, st);
-    if (s == GW_OK) s = launch_full(ctx, ctx->coef, n, n, prec, tpb, nch, ctx->partial, st);
-    if (s == GW_OK)
-      s = launch_epilogue_cached(ctx, ctx->partial, nch, ctx->coef, n, n, marg, prec, ll, nullptr, nullptr, zrow,
-                                 st);
-    if (s == GW_OK) {
-      hipLaunchKernelGGL(k_recon_stage, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, zrow, nd, ctx->coef, n, n,
-                         zc3);
-      s = check_hip(hipGetLastError(), "reconstruction staging launch");
-    }
-  }
-  if (s != GW_OK) return s;
   LogI0Consts C = make_log_i0_consts();
   C.r1max = ctx->dist_r1max;
   hipLaunchKernelGGL(k_recon, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, zc3, n, theta, ctx->dist_tab,

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "gw_ctx.h"
+#include "gw_rng.h"
 
 namespace gw {
 
@@ -33,6 +34,13 @@ __host__ __device__ inline int uni_fixed(int bd) { return (bd <= 4 ? 4 : 2 * ((b
 struct CubeMap {
   int32_t time_marg;  // 0: coordinate 10 is t_c; 1: coordinate 10 is d_L
   double d3_lo, d3_span;  // d_L^3 at the lower end of its prior, and the range of d_L^3
+  // Detector sky frame: coordinates 7 and 8 are the azimuth 2 pi u and the
+  // zenith acos(1 - 2 u) about the baseline nb of two detectors (e1, e2
+  // across it, Earth-fixed); with det_time, coordinate 10 is the arrival
+  // time at the first detector (position ra_m, in m).
+  int32_t sky, det_time;
+  double nb[3], e1[3], e2[3], ra_m[3];
+  double gmst;
 };
 
 // One sweep: every chain visits blocks b = 0 .. nb - 1 in order, block b with
@@ -97,31 +105,13 @@ struct SliceState {
                        // [2k][2 n_det]: the cached-waveform rows' sums
 };
 
-// Philox4x64-10 (Salmon, Moraes, Dror & Shaw 2011).
-__device__ inline void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += W0;
-    k1 += W1;
-  }
-}
-
 // Uniform j of chain c in block b: explicit table, or Philox word j % 4 of
 // counter (counter_base + b, c, j / 4, 0) under key (seed, 0), mapped to (0, 1).
 __device__ inline double slice_uniform(const SweepParams& P, int b, int64_t c, int j) {
   if (P.uniforms) return P.uniforms[c * (uni_fixed(P.bd[b]) + P.max_shrink) + j];
   uint64_t ctr[4] = {P.counter + (uint64_t)b, (uint64_t)c, (uint64_t)(j >> 2), 0ull};
   philox4x64(ctr, P.seed, 0ull);
-  return ((double)(ctr[j & 3] >> 11) + 0.5) * 1.1102230246251565404e-16;  // 2^-53
+  return philox_unit(ctr[j & 3]);
 }
 
 // Unit cube -> 13-column parameter vector.  Coordinate 10 is t_c in [-0.1,
@@ -143,6 +133,21 @@ __device__ inline void prior_transform(const double* u, double* th, const CubeMa
   if (cm.time_marg) {
     th[6] = cbrt(fma(u[10], cm.d3_span, cm.d3_lo));
     th[12] = 0.0;
+  }
+  if (cm.sky) {
+    double sk, ck, sz, cz;
+    sincos(kTwoPi * u[7], &sk, &ck);
+    sincos(acos(1.0 - 2.0 * u[8]), &sz, &cz);
+    double s[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s[i] = cz * cm.nb[i] + sz * (ck * cm.e1[i] + sk * cm.e2[i]);
+    th[9] = asin(fmin(1.0, fmax(-1.0, s[2])));
+    double ra = atan2(s[1], s[0]) + cm.gmst;
+    if (ra < 0.0) ra += kTwoPi;
+    else if (ra >= kTwoPi) ra -= kTwoPi;
+    th[8] = ra;
+    if (cm.det_time && !cm.time_marg)
+      th[12] = (-0.1 + 0.2 * u[10]) + (s[0] * cm.ra_m[0] + s[1] * cm.ra_m[1] + s[2] * cm.ra_m[2]) / kLightSpeed;
   }
 }
 
@@ -584,8 +589,35 @@ static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const Swee
 // The cube map for a marginalisation mode: with the time marginal, d_L spans
 // the context's distance grid (prior proportional to d_L^2).
 static gw_status cube_map(const gw_ctx* ctx, int32_t marg, CubeMap* cm) {
-  cm->time_marg = 0;
-  cm->d3_lo = cm->d3_span = 0.0;
+  *cm = CubeMap{};
+  if (ctx->sky_frame) {
+    // baseline n = (r_b - r_a) / |r_b - r_a|; e1 = z made orthogonal to n (x
+    // when n is nearly along z); e2 = n x e1
+    const double* ra = ctx->geom.pos[ctx->sky_a];
+    const double* rb = ctx->geom.pos[ctx->sky_b];
+    double n[3] = {rb[0] - ra[0], rb[1] - ra[1], rb[2] - ra[2]};
+    const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (double& v : n) v /= nn;
+    double ref[3] = {0.0, 0.0, 1.0};
+    if (fabs(n[2]) > 0.99) {
+      ref[0] = 1.0;
+      ref[2] = 0.0;
+    }
+    const double rn = ref[0] * n[0] + ref[1] * n[1] + ref[2] * n[2];
+    double e1[3] = {ref[0] - rn * n[0], ref[1] - rn * n[1], ref[2] - rn * n[2]};
+    const double ne = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (double& v : e1) v /= ne;
+    const double e2[3] = {n[1] * e1[2] - n[2] * e1[1], n[2] * e1[0] - n[0] * e1[2], n[0] * e1[1] - n[1] * e1[0]};
+    cm->sky = 1;
+    cm->det_time = ctx->sky_det_time;
+    for (int i = 0; i < 3; ++i) {
+      cm->nb[i] = n[i];
+      cm->e1[i] = e1[i];
+      cm->e2[i] = e2[i];
+      cm->ra_m[i] = ra[i];
+    }
+    cm->gmst = ctx->geom.gmst;
+  }
   if (marg != GW_MARG_PHASE_TIME) return GW_OK;
   if (ctx->h_dist_grid.size() < 2) return set_error(GW_ESTATE, "time-marginal sampler needs a distance grid");
   const double lo = ctx->h_dist_grid.front(), hi = ctx->h_dist_grid.back();
@@ -811,6 +843,30 @@ gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* a, void* stream) {
   const int32_t graph = a->use_graph && a->marg != GW_MARG_PHASE_TIME;  // as in slice_step
   const SweepCall c{a->like, a->marg, a->prec, graph, a->n_evals, a->status, P.cache, a->eval_kinds, P.lists};
   return run_sweep(ctx, P, c, (hipStream_t)stream);
+}
+
+gw_status gw_set_sky_frame(gw_ctx* ctx, int32_t frame, int32_t det_a, int32_t det_b, int32_t det_time) {
+  if (!ctx) return set_error(GW_EINVAL, "gw_set_sky_frame: ctx is NULL");
+  if (frame != 0 && frame != 1) return set_error(GW_EINVAL, "gw_set_sky_frame: frame must be 0 or 1");
+  if (frame == 0) {
+    if (det_time) return set_error(GW_EINVAL, "gw_set_sky_frame: det_time needs the detector frame");
+    ctx->sky_frame = 0;
+    ctx->sky_det_time = 0;
+    return GW_OK;
+  }
+  if (det_a < 0 || det_b < 0 || det_a >= ctx->n_det || det_b >= ctx->n_det || det_a == det_b)
+    return set_error(GW_EINVAL, "gw_set_sky_frame: two distinct detectors 0 .. %d", ctx->n_det - 1);
+  const double* ra = ctx->geom.pos[det_a];
+  const double* rb = ctx->geom.pos[det_b];
+  const double d2 = (rb[0] - ra[0]) * (rb[0] - ra[0]) + (rb[1] - ra[1]) * (rb[1] - ra[1]) +
+                    (rb[2] - ra[2]) * (rb[2] - ra[2]);
+  if (!(d2 > 1.0)) return set_error(GW_EINVAL, "gw_set_sky_frame: the two detectors are at the same place");
+  if (det_time != 0 && det_time != 1) return set_error(GW_EINVAL, "gw_set_sky_frame: det_time must be 0 or 1");
+  ctx->sky_frame = 1;
+  ctx->sky_a = det_a;
+  ctx->sky_b = det_b;
+  ctx->sky_det_time = det_time;
+  return GW_OK;
 }
 
 gw_status gw_prior_transform_marg(gw_ctx* ctx, const double* x, int64_t n, int32_t marg, double* theta,

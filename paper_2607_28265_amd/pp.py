@@ -40,40 +40,89 @@ from . import Context, _lib
 from .nested import BLOCKS, N_DIM, UNBLOCKED, NestedSampler
 
 CONFIGS = {"baseline": (BLOCKS, 1), "highres": (BLOCKS, 3), "nss": (UNBLOCKED, 3 * N_DIM)}
+C_SI = 299792458.0  # m / s
 PARAMS = ("mc", "q", "chi1", "chi2", "lambda1", "lambda2", "iota", "ra", "dec", "psi", "tc")
 LO = np.array([1.1, 0.5, -0.05, -0.05, 0.0, 0.0])
 HI = np.array([1.4, 1.0, 0.05, 0.05, 5000.0, 5000.0])
 
 
-def to_cube(theta, d_lo: float, d_hi: float, time_marg: bool) -> np.ndarray:
+@dataclasses.dataclass
+class SkyFrame:
+    """The detector sky frame of ``gw_set_sky_frame`` in numpy: baseline n of
+    detectors a -> b, e1 the Earth's axis made orthogonal to n (x when
+    |n_z| > 0.99), e2 = n x e1; with det_time, coordinate 10 is the arrival
+    time at detector a."""
+    det_pos: np.ndarray
+    gmst: float = 0.0
+    a: int = 0
+    b: int = 1
+    det_time: bool = False
+
+    def __post_init__(self):
+        n = np.asarray(self.det_pos[self.b], float) - np.asarray(self.det_pos[self.a], float)
+        n = n / np.linalg.norm(n)
+        ref = np.array([1.0, 0.0, 0.0]) if abs(n[2]) > 0.99 else np.array([0.0, 0.0, 1.0])
+        e1 = ref - (ref @ n) * n
+        e1 = e1 / np.linalg.norm(e1)
+        self.n, self.e1, self.e2 = n, e1, np.cross(n, e1)
+        self.ra_m = np.asarray(self.det_pos[self.a], float)
+
+    def direction(self, u7: float, u8: float) -> np.ndarray:
+        zen = math.acos(1.0 - 2.0 * u8)
+        kap = 2.0 * math.pi * u7
+        return math.cos(zen) * self.n + math.sin(zen) * (math.cos(kap) * self.e1 + math.sin(kap) * self.e2)
+
+    def cube(self, ra: float, dec: float):
+        """(u7, u8, s) of a sky position."""
+        phi = ra - self.gmst
+        s = np.array([math.cos(dec) * math.cos(phi), math.cos(dec) * math.sin(phi), math.sin(dec)])
+        return (math.atan2(s @ self.e2, s @ self.e1) % (2.0 * math.pi)) / (2.0 * math.pi), 0.5 * (1.0 - s @ self.n), s
+
+
+def to_cube(theta, d_lo: float, d_hi: float, time_marg: bool, frame: SkyFrame | None = None) -> np.ndarray:
     """Unit-cube coordinates of a parameter vector (inverse of the prior
-    transform); coordinate 10 is t_c, or d_L when t_c is marginalised."""
+    transform); coordinate 10 is t_c (or the arrival time at the frame's first
+    detector), or d_L when t_c is marginalised."""
     th = np.asarray(theta, dtype=np.float64)
     u = np.empty(N_DIM)
     u[:6] = (th[:6] - LO) / (HI - LO)
     u[6] = 0.5 * (1.0 - math.cos(th[7]))
-    u[7] = th[8] / (2.0 * math.pi)
-    u[8] = 0.5 * (math.sin(th[9]) + 1.0)
+    if frame is None:
+        u[7] = th[8] / (2.0 * math.pi)
+        u[8] = 0.5 * (math.sin(th[9]) + 1.0)
+    else:
+        u[7], u[8], s = frame.cube(th[8], th[9])
     u[9] = th[10] / math.pi
     if time_marg:
         u[10] = (th[6] ** 3 - d_lo ** 3) / (d_hi ** 3 - d_lo ** 3)
+    elif frame is not None and frame.det_time:
+        u[10] = (th[12] - float(s @ frame.ra_m) / C_SI + 0.1) / 0.2
     else:
         u[10] = (th[12] + 0.1) / 0.2
     return u
 
 
-def draw_truth(rng, d_lo: float, d_hi: float, time_marg: bool) -> np.ndarray:
-    """One parameter vector from the recovery prior."""
+def draw_truth(rng, d_lo: float, d_hi: float, time_marg: bool, frame: SkyFrame | None = None) -> np.ndarray:
+    """One parameter vector from the recovery prior: a uniform cube point
+    through the prior transform (in the given sky frame), d_L ~ d^2 and phi_c
+    uniform."""
     u = rng.uniform(size=N_DIM)
     th = np.zeros(13)
     th[:6] = LO + (HI - LO) * u[:6]
     th[7] = math.acos(1.0 - 2.0 * u[6])
-    th[8] = 2.0 * math.pi * u[7]
-    th[9] = math.asin(2.0 * u[8] - 1.0)
+    if frame is None:
+        th[8] = 2.0 * math.pi * u[7]
+        th[9] = math.asin(2.0 * u[8] - 1.0)
+    else:
+        s = frame.direction(u[7], u[8])
+        th[9] = math.asin(max(-1.0, min(1.0, float(s[2]))))
+        th[8] = (math.atan2(float(s[1]), float(s[0])) + frame.gmst) % (2.0 * math.pi)
     th[10] = math.pi * u[9]
     th[6] = (d_lo ** 3 + rng.uniform() * (d_hi ** 3 - d_lo ** 3)) ** (1.0 / 3.0)
     th[11] = 2.0 * math.pi * rng.uniform()
     th[12] = 0.0 if time_marg else -0.1 + 0.2 * u[10]
+    if frame is not None and frame.det_time and not time_marg:
+        th[12] += float(s @ frame.ra_m) / C_SI
     return th
 
 
@@ -109,6 +158,8 @@ class Campaign:
     seed: int = 2026
     n_phase: int = 2048
     recon_floor: float = 1e-12  # points below this fraction of the largest weight are not reconstructed
+    sky_frame: bool = False     # sample the sky about the baseline of detectors 0 -> 1
+    det_time: bool = False      # ... and the arrival time at detector 0
 
     def __post_init__(self):
         if self.config not in CONFIGS:
@@ -116,6 +167,7 @@ class Campaign:
         self.time_marg = self.marg == _lib.GW_MARG_PHASE_TIME
         self.d_lo = float(self.base.dist_grid[0])
         self.d_hi = float(self.base.dist_grid[-1])
+        self.frame = SkyFrame(self.base.det_pos, self.base.gmst, det_time=self.det_time) if self.sky_frame else None
         self._tctx = Context(dataclasses.replace(self.base, data=np.zeros_like(self.base.data)))
 
     def close(self):
@@ -126,7 +178,7 @@ class Campaign:
         import torch
         from gwsynth import gaussian_noise
         rng = np.random.default_rng([self.seed, i])
-        th = draw_truth(rng, self.d_lo, self.d_hi, self.time_marg)
+        th = draw_truth(rng, self.d_lo, self.d_hi, self.time_marg, self.frame)
         h = self._tctx.template(torch.from_numpy(th[None, :].copy()).cuda()).cpu().numpy()[0]  # complex
         noise_seed = int(rng.integers(1 << 62))
         noise = gaussian_noise(noise_seed, self.base.psd, self.base.df)
@@ -141,11 +193,13 @@ class Campaign:
         with Context(prob) as ctx:
             if self.like == _lib.GW_HET:
                 ctx.heterodyne_setup(th, self.n_bins)  # fiducial at the true parameters
+            if self.frame is not None:
+                _lib.gw_set_sky_frame(ctx.handle, 1, 0, 1, self.det_time)
             ns = NestedSampler(ctx, n_live=self.n_live, n_delete=self.n_delete, seed=self.seed * 1000 + i,
                                blocks=blocks, sweeps=sweeps, like=self.like, prec=self.prec, marg=self.marg)
             res = ns.run()
             x, w = ns.samples()
-            truth = to_cube(th, self.d_lo, self.d_hi, self.time_marg)
+            truth = to_cube(th, self.d_lo, self.d_hi, self.time_marg, self.frame)
             levels = [weighted_level(x[:, j], w, truth[j]) for j in range(N_DIM)]
             # post-hoc draws of the marginalised d_L and phi_c for the weighted points
             sel = np.nonzero(w > self.recon_floor * w.max())[0]
@@ -174,17 +228,22 @@ class Campaign:
 
     def summarise(self, runs) -> dict:
         names = list(PARAMS)
+        if self.frame is not None:
+            names[7], names[8] = "sky_azimuth", "sky_zenith"
+            if self.det_time:
+                names[10] = "t_det0"
         if self.time_marg:
             names[10] = "dl"
         lv = np.array([r["levels"] for r in runs])
         ks = {n: ks_pvalue(lv[:, j]) for j, n in enumerate(names)}
         out = dict(config=self.config, like="het" if self.like == _lib.GW_HET else "full",
+                   sky_frame="detector" if self.frame is not None else "equatorial", det_time=self.det_time,
                    marg="phase+time" if self.time_marg else "phase+distance", n_injections=len(runs),
                    ks_pvalues=ks, fisher_p=fisher_pvalue(list(ks.values())),
                    median_sampling_s=float(np.median([r["sampling_s"] for r in runs])),
                    median_evals=float(np.median([r["n_evals"] for r in runs])))
         if not self.time_marg:
-            sampled = [v for n, v in ks.items() if n != "tc"]
+            sampled = [v for n, v in ks.items() if n not in ("tc", "t_det0")]
             out["fisher_p_without_tc"] = fisher_pvalue(sampled)
             out["ks_reconstructed"] = {"dl": ks_pvalue([r["level_dl"] for r in runs]),
                                        "phic": ks_pvalue([r["level_phic"] for r in runs])}
@@ -204,13 +263,16 @@ def main(argv=None):
     ap.add_argument("--n-delete", type=int, default=64)
     ap.add_argument("--n-bins", type=int, default=500)
     ap.add_argument("--seed", type=int, default=2026)
+    ap.add_argument("--sky-frame", action="store_true", help="sample the sky about the baseline of detectors 0, 1")
+    ap.add_argument("--det-time", action="store_true", help="with --sky-frame: sample the arrival time at detector 0")
     ap.add_argument("--out", default=None, help="JSON file for the per-injection records and the summary")
     a = ap.parse_args(argv)
     import gwsynth
     base = gwsynth.make_problem(a.duration, 20.0, a.fmax, psd_scale=a.psd_scale, noise_seed=None)
     camp = Campaign(base, config=a.config, like=_lib.GW_HET if a.like == "het" else _lib.GW_FULL,
                     marg=_lib.GW_MARG_PHASE_TIME if a.marg == "time" else _lib.GW_MARG_PHASE_DIST,
-                    n_live=a.n_live, n_delete=a.n_delete, n_bins=a.n_bins, seed=a.seed)
+                    n_live=a.n_live, n_delete=a.n_delete, n_bins=a.n_bins, seed=a.seed, sky_frame=a.sky_frame,
+                    det_time=a.det_time)
     runs = []
     try:
         for i in range(a.n):
