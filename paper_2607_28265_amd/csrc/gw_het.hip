@@ -802,14 +802,20 @@ void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech)
 // phase-marginal log L per grid point and a fixed-order log-sum-exp.
 
 // E and F on the grid t_j = (j - J) delta (FP64 phase, FP64 sin/cos).
-__global__ void __launch_bounds__(256) k_het_tm_phasors(const double* __restrict__ rec, int rs, int n_edges, int nt,
-                                                        int J, double delta, TrigConsts T, double* __restrict__ ef) {
+__global__ void __launch_bounds__(256) k_het_tm_phasors(const double* __restrict__ rec, int rs, int n_edges,
+                                                        int ne_pad, int nt, int J, double delta, TrigConsts T,
+                                                        double* __restrict__ ef) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t per = (int64_t)n_edges * nt;
+  const int64_t per = (int64_t)ne_pad * nt;
   if (idx >= 2 * per) return;
   const int which = (int)(idx / per);
   const int64_t r = idx - which * per;
   const int e = (int)(r / nt), j = (int)(r - (int64_t)e * nt);
+  if (e >= n_edges) {  // padding edges take no part in the products
+    ef[2 * idx] = 0.0;
+    ef[2 * idx + 1] = 0.0;
+    return;
+  }
   const double t = (double)(j - J) * delta;
   double f = rec[(int64_t)e * rs + H_F];
   if (which == 1) f = e > 0 ? f - rec[(int64_t)(e - 1) * rs + H_F] : 0.0;
@@ -819,17 +825,20 @@ __global__ void __launch_bounds__(256) k_het_tm_phasors(const double* __restrict
   ef[2 * idx + 1] = which == 1 && e == 0 ? 0.0 : -sn;
 }
 
-// Per row (lane), the edge weights W and V ([2][n][n_edges] complex) and the
-// constant norm part sum_i |q_i|^2 hh0_i (hhc[n]).  Edge records are
-// wave-uniform.
+// The edge weights W and V ([2][n][ne_pad] complex, zero beyond the last
+// edge) and the constant norm part sum_i |q_i|^2 hh0_i (hhc[n]).  One wave
+// per (64-row tile, chunk of ``chunk`` edges): lane = row, edge records
+// wave-uniform; a chunk starts its phasor recurrence from the edge before it.
 template <int ND, int PREC>
-__global__ void __launch_bounds__(256) k_het_tw(const double* __restrict__ coef, int64_t ld, int64_t n,
-                                                const double* __restrict__ rec, int n_bins, HetConst hc, TrigConsts T,
-                                                double* __restrict__ wv, double* __restrict__ hhc) {
+__global__ void __launch_bounds__(64) k_het_tw(const double* __restrict__ coef, int64_t ld, int64_t n,
+                                               const double* __restrict__ rec, int n_bins, int ne_pad, int chunk,
+                                               HetConst hc, TrigConsts T, double* __restrict__ wv,
+                                               double* __restrict__ hhc) {
   constexpr int RS = het_rs(ND);
   constexpr int BO = het_bin_off(ND);
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
   const int64_t pc = p < n ? p : n - 1;
+  const int e0 = blockIdx.y * chunk;
   const double* cf = coef + pc;
   PhaseCoef c;
   c.a0 = cf[C_A0 * ld]; c.a2 = cf[C_A2 * ld]; c.a3 = cf[C_A3 * ld]; c.a4 = cf[C_A4 * ld];
@@ -848,9 +857,19 @@ __global__ void __launch_bounds__(256) k_het_tw(const double* __restrict__ coef,
     pr[i] = pim[i] = 0.0;
   }
   const int n_edges = n_bins + 1;
-  double* __restrict__ w_out = wv + pc * n_edges * 2;
-  double* __restrict__ v_out = wv + (n + pc) * n_edges * 2;
-  for (int e = 0; e < n_edges; ++e) {
+  double* __restrict__ w_out = wv + pc * ne_pad * 2;
+  double* __restrict__ v_out = wv + (n + pc) * ne_pad * 2;
+  if (e0 > 0 && e0 - 1 < n_edges) {  // the previous edge's phasors
+    const double* r = rec + (int64_t)(e0 - 1) * RS;
+    const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const double di = i == 0 ? d0 : fma(r[H_F], dt[i], d0) - r[H_PHI0 + i];
+      het_phasor<PREC>(di, T, &pr[i], &pim[i]);
+    }
+  }
+  const int e_end = e0 + chunk < n_edges ? e0 + chunk : n_edges;
+  for (int e = e0; e < e_end; ++e) {
     const double* r = rec + (int64_t)e * RS;
     const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
     const double f = r[H_F];
@@ -884,26 +903,41 @@ __global__ void __launch_bounds__(256) k_het_tw(const double* __restrict__ coef,
       v_out[2 * e + 1] = vi;
     }
   }
-  if (p < n) hhc[p] = hconst;
+  if (p < n && e0 + chunk >= n_edges) {  // the last chunk clears the padding
+    for (int e = n_edges > e0 ? n_edges : e0; e < ne_pad; ++e) {
+      w_out[2 * e] = w_out[2 * e + 1] = 0.0;
+      v_out[2 * e] = v_out[2 * e + 1] = 0.0;
+    }
+  }
+  if (p < n && e0 == 0) hhc[p] = hconst;
 }
 
 // One workgroup (256 threads) per row: log-mean-exp over the grid of the
 // phase-marginal binned log L.
+// The products come in nsk partial sums over chunks of edges
+// (zh [2][nsk][n][nt] complex), added here in chunk order.
+__device__ inline double het_tgrid_value(const double* __restrict__ zh, int64_t n, int nt, int nsk, int64_t p, int j,
+                                         double h0, const LogI0Consts& C) {
+  double zr = 0.0, zi = 0.0, hr = 0.0;
+  for (int c = 0; c < nsk; ++c) {
+    const double* z = zh + ((int64_t)c * n + p) * nt * 2;
+    const double* hv = zh + ((int64_t)(nsk + c) * n + p) * nt * 2;
+    zr += z[2 * j];
+    zi += z[2 * j + 1];
+    hr += hv[2 * j];
+  }
+  return -0.5 * (h0 + hr) + log_i0(sqrt(zr * zr + zi * zi), C);
+}
+
 __global__ void __launch_bounds__(256) k_het_tfinal(const double* __restrict__ zh, const double* __restrict__ hhc,
                                                     const double* __restrict__ coef, int64_t ld, int64_t n, int nt,
-                                                    double dd, LogI0Consts C, double* __restrict__ logl) {
+                                                    int nsk, double dd, LogI0Consts C, double* __restrict__ logl) {
   __shared__ double red[256];
   const int64_t p = blockIdx.x;
   const int tid = threadIdx.x;
-  const double* z = zh + p * nt * 2;
-  const double* hv = zh + (n + p) * nt * 2;
   const double h0 = hhc[p];
   double mx = -INFINITY;
-  for (int j = tid; j < nt; j += 256) {
-    const double zr = z[2 * j], zi = z[2 * j + 1];
-    const double v = -0.5 * (h0 + hv[2 * j]) + log_i0(sqrt(zr * zr + zi * zi), C);
-    mx = fmax(mx, v);
-  }
+  for (int j = tid; j < nt; j += 256) mx = fmax(mx, het_tgrid_value(zh, n, nt, nsk, p, j, h0, C));
   red[tid] = mx;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -913,11 +947,7 @@ __global__ void __launch_bounds__(256) k_het_tfinal(const double* __restrict__ z
   const double ref = red[0];
   __syncthreads();
   double acc = 0.0;
-  for (int j = tid; j < nt; j += 256) {
-    const double zr = z[2 * j], zi = z[2 * j + 1];
-    const double v = -0.5 * (h0 + hv[2 * j]) + log_i0(sqrt(zr * zr + zi * zi), C);
-    acc += exp(v - ref);
-  }
+  for (int j = tid; j < nt; j += 256) acc += exp(het_tgrid_value(zh, n, nt, nsk, p, j, h0, C) - ref);
   red[tid] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -930,18 +960,30 @@ __global__ void __launch_bounds__(256) k_het_tfinal(const double* __restrict__ z
   }
 }
 
+// Edge chunks of the weight kernel: enough (64-row tile, chunk) waves to fill
+// the chip, chunks of at least 32 edges.
+static int het_tw_chunk(int64_t n, int n_edges) {
+  const int64_t tiles = (n + 63) / 64;
+  int64_t want = (4096 + tiles - 1) / tiles;
+  const int64_t most = (n_edges + 31) / 32;
+  if (want > most) want = most;
+  if (want < 1) want = 1;
+  return (int)((n_edges + want - 1) / want);
+}
+
 template <int ND>
-static void launch_het_tw_nd(gw_ctx* ctx, int64_t n, int prec, const HetConst& hc, double* wv, double* hhc,
-                             hipStream_t st) {
+static void launch_het_tw_nd(gw_ctx* ctx, int64_t n, int prec, int ne_pad, const HetConst& hc, double* wv,
+                             double* hhc, hipStream_t st) {
   const gw_het_state* h = ctx->het;
   const TrigConsts T = make_trig_consts();
-  const unsigned blocks = (unsigned)((n + 255) / 256);
+  const int chunk = het_tw_chunk(n, h->n_edges);
+  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((h->n_edges + chunk - 1) / chunk));
   if (prec == GW_PREC_FP64)
-    hipLaunchKernelGGL((k_het_tw<ND, 0>), dim3(blocks), dim3(256), 0, st, (const double*)ctx->coef, n, n,
-                       (const double*)h->rec, h->n_bins, hc, T, wv, hhc);
+    hipLaunchKernelGGL((k_het_tw<ND, 0>), grid, dim3(64), 0, st, (const double*)ctx->coef, n, n,
+                       (const double*)h->rec, h->n_bins, ne_pad, chunk, hc, T, wv, hhc);
   else
-    hipLaunchKernelGGL((k_het_tw<ND, 1>), dim3(blocks), dim3(256), 0, st, (const double*)ctx->coef, n, n,
-                       (const double*)h->rec, h->n_bins, hc, T, wv, hhc);
+    hipLaunchKernelGGL((k_het_tw<ND, 1>), grid, dim3(64), 0, st, (const double*)ctx->coef, n, n,
+                       (const double*)h->rec, h->n_bins, ne_pad, chunk, hc, T, wv, hhc);
 }
 
 gw_status loglike_het_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, hipStream_t st) {
@@ -953,28 +995,38 @@ gw_status loglike_het_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int pre
   if (s != GW_OK) return s;
   const int J = (nt - 1) / 2;
   const int ne = h->n_edges;
+  // edges padded to a multiple of 32 (zero weights and phasors), so that the
+  // products can be split into up to 32 equal chunks of edges
+  const int ne_pad = (ne + 31) / 32 * 32;
   if (!h->tm_ef || h->tm_nt != nt || h->tm_delta != delta) {
     if (h->tm_ef) (void)hipFree(h->tm_ef);
     h->tm_ef = nullptr;
-    s = check_hip(hipMalloc((void**)&h->tm_ef, (size_t)2 * ne * nt * 2 * sizeof(double)), "time-grid phasors");
+    s = check_hip(hipMalloc((void**)&h->tm_ef, (size_t)2 * ne_pad * nt * 2 * sizeof(double)), "time-grid phasors");
     if (s != GW_OK) return s;
-    const int64_t tot = (int64_t)2 * ne * nt;
+    const int64_t tot = (int64_t)2 * ne_pad * nt;
     hipLaunchKernelGGL(k_het_tm_phasors, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
-                       (const double*)h->rec, h->rs, ne, nt, J, delta, make_trig_consts(), h->tm_ef);
+                       (const double*)h->rec, h->rs, ne, ne_pad, nt, J, delta, make_trig_consts(), h->tm_ef);
     s = check_hip(hipGetLastError(), "time-grid phasor launch");
     if (s != GW_OK) return s;
     h->tm_nt = nt;
     h->tm_delta = delta;
   }
-  // workspace: coefficients, W/V [2][n][ne], Z/H [2][n][nt], hhc [n]
+  // split of the products over edge chunks: few rows give few output tiles,
+  // so the edge sum is cut into nsk chunks (a power of two up to 32) until
+  // about 512 tiles are in flight; their partials are added in chunk order
+  const int64_t tiles = (int64_t)((nt + 127) / 128) * ((n + 63) / 64);
+  int nsk = 1;
+  while (nsk < 32 && tiles * nsk < 512) nsk *= 2;
+  const int ke = ne_pad / nsk;
+  // workspace: coefficients, W/V [2][n][ne_pad], Z/H [2][nsk][n][nt], hhc [n]
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
   if (s == GW_OK)
-    s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap, (int64_t)2 * n * ne * 2 + (int64_t)2 * n * nt * 2 + n,
-                      "time-marginal workspace");
+    s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap,
+                      (int64_t)2 * n * ne_pad * 2 + (int64_t)2 * nsk * n * nt * 2 + n, "time-marginal workspace");
   if (s != GW_OK) return s;
   double* wv = ctx->tm_mom;
-  double* zh = wv + (int64_t)2 * n * ne * 2;
-  double* hhc = zh + (int64_t)2 * n * nt * 2;
+  double* zh = wv + (int64_t)2 * n * ne_pad * 2;
+  double* hhc = zh + (int64_t)2 * nsk * n * nt * 2;
   s = launch_prologue(ctx, theta, n, GW_MARG_PHASE_TIME, ctx->coef, n, st);
   if (s != GW_OK) return s;
   HetConst hc;
@@ -985,15 +1037,17 @@ gw_status loglike_het_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int pre
   }
   hc.dd = ctx->dd;
   switch (ctx->n_det) {
-    case 1: launch_het_tw_nd<1>(ctx, n, prec, hc, wv, hhc, st); break;
-    case 2: launch_het_tw_nd<2>(ctx, n, prec, hc, wv, hhc, st); break;
-    case 3: launch_het_tw_nd<3>(ctx, n, prec, hc, wv, hhc, st); break;
-    case 4: launch_het_tw_nd<4>(ctx, n, prec, hc, wv, hhc, st); break;
+    case 1: launch_het_tw_nd<1>(ctx, n, prec, ne_pad, hc, wv, hhc, st); break;
+    case 2: launch_het_tw_nd<2>(ctx, n, prec, ne_pad, hc, wv, hhc, st); break;
+    case 3: launch_het_tw_nd<3>(ctx, n, prec, ne_pad, hc, wv, hhc, st); break;
+    case 4: launch_het_tw_nd<4>(ctx, n, prec, ne_pad, hc, wv, hhc, st); break;
     default: return set_error(GW_ENOTSUP, "n_det not supported");
   }
   s = check_hip(hipGetLastError(), "edge weight launch");
   if (s != GW_OK) return s;
-  // Z^T = E^T W^T and H^T = F^T V^T in column-major terms: m = nt, n = rows, k = edges
+  // Z^T = E^T W^T and H^T = F^T V^T in column-major terms: m = nt, n = rows,
+  // k = edges; chunk c of nsk takes edges [c ke, (c + 1) ke) into its own
+  // partial (one strided batch per product)
   if (!ctx->blas) {
     if (rocblas_create_handle((rocblas_handle*)&ctx->blas) != rocblas_status_success)
       return set_error(GW_EDEVICE, "rocblas_create_handle failed");
@@ -1002,16 +1056,24 @@ gw_status loglike_het_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int pre
   if (rocblas_set_stream(bh, st) != rocblas_status_success) return set_error(GW_EDEVICE, "rocblas_set_stream failed");
   const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
   const int prof = prof_begin(ctx, st);
-  const rocblas_status bs = rocblas_zgemm_strided_batched(
-      bh, rocblas_operation_none, rocblas_operation_none, nt, (rocblas_int)n, ne, &one,
-      (const rocblas_double_complex*)h->tm_ef, nt, (rocblas_stride)ne * nt, (const rocblas_double_complex*)wv, ne,
-      (rocblas_stride)n * ne, &zero, (rocblas_double_complex*)zh, nt, (rocblas_stride)n * nt, 2);
+  rocblas_status bs = rocblas_status_success;
+  for (int q = 0; q < 2 && bs == rocblas_status_success; ++q) {
+    const rocblas_double_complex* A = (const rocblas_double_complex*)(h->tm_ef + (int64_t)q * ne_pad * nt * 2);
+    const rocblas_double_complex* B = (const rocblas_double_complex*)(wv + (int64_t)q * n * ne_pad * 2);
+    rocblas_double_complex* Cm = (rocblas_double_complex*)(zh + (int64_t)q * nsk * n * nt * 2);
+    if (nsk == 1 && q == 1) break;  // one call covers both products
+    const int batch = nsk == 1 ? 2 : nsk;
+    bs = rocblas_zgemm_strided_batched(
+        bh, rocblas_operation_none, rocblas_operation_none, nt, (rocblas_int)n, nsk == 1 ? ne_pad : ke, &one, A, nt,
+        nsk == 1 ? (rocblas_stride)ne_pad * nt : (rocblas_stride)ke * nt, B, ne_pad,
+        nsk == 1 ? (rocblas_stride)n * ne_pad : (rocblas_stride)ke, &zero, Cm, nt, (rocblas_stride)n * nt, batch);
+  }
   prof_end(ctx, prof, st);
   if (bs != rocblas_status_success) return set_error(GW_EDEVICE, "rocblas_zgemm_strided_batched: status %d", (int)bs);
   LogI0Consts C = make_log_i0_consts();
   C.r1max = ctx->dist_r1max;
   hipLaunchKernelGGL(k_het_tfinal, dim3((unsigned)n), dim3(256), 0, st, (const double*)zh, (const double*)hhc,
-                     (const double*)ctx->coef, n, n, nt, ctx->dd, C, logl);
+                     (const double*)ctx->coef, n, n, nt, nsk, ctx->dd, C, logl);
   return check_hip(hipGetLastError(), "time-marginal epilogue launch");
 }
 

@@ -19,7 +19,8 @@ against U(0, 1), and all of them together by Fisher's combined p-value.
 Configurations: ``baseline`` (the seven Gibbs blocks, one sweep per
 replacement), ``highres`` (three sweeps), and ``nss`` (the unblocked nested
 slice sampler: one block of all 11 coordinates, 3 x 11 joint slice steps per
-replacement).  With ``marg = GW_MARG_PHASE_TIME`` coordinate 10 is d_L (t_c
+replacement); ``joint`` puts the masses, spins and tidal parameters in one
+block.  With ``marg = GW_MARG_PHASE_TIME`` coordinate 10 is d_L (t_c
 marginalised, as in the GW170817 configuration); t_c and phi_c are then not
 reconstructed.
 
@@ -39,7 +40,11 @@ import numpy as np
 from . import Context, _lib
 from .nested import BLOCKS, N_DIM, UNBLOCKED, NestedSampler
 
-CONFIGS = {"baseline": (BLOCKS, 1), "highres": (BLOCKS, 3), "nss": (UNBLOCKED, 3 * N_DIM)}
+# ``joint``: the masses, spins and tidal parameters in one block (a different
+# decomposition of the same space, one sweep per replacement)
+JOINT_INTRINSIC = ((0, 1, 2, 3, 4, 5), (6,), (7, 8), (9,), (10,))
+CONFIGS = {"baseline": (BLOCKS, 1), "highres": (BLOCKS, 3), "nss": (UNBLOCKED, 3 * N_DIM),
+           "joint": (JOINT_INTRINSIC, 1)}
 C_SI = 299792458.0  # m / s
 PARAMS = ("mc", "q", "chi1", "chi2", "lambda1", "lambda2", "iota", "ra", "dec", "psi", "tc")
 LO = np.array([1.1, 0.5, -0.05, -0.05, 0.0, 0.0])

@@ -118,3 +118,20 @@ def test_heterodyned_against_oracle(loud):
             err = np.max(np.abs(got.cpu().numpy() - ref))
             print(f"heterodyned loud={loud} prec {prec}: max |dlogL| {err:.2e}")
             assert err < tol
+
+
+def test_heterodyned_split_matches_unsplit():
+    # few rows split the edge sum of the products into up to 32 chunks; a
+    # large batch keeps one chunk: the same rows agree to rounding
+    import paper_2607_28265_amd as gw
+    prob = problem("cfg1", loud=True)
+    th = np.concatenate([gwsynth.prior_draws(gwsynth.SEEDS["prior"], 8), near(prob, 16, 21, 1.0)])
+    big = np.concatenate([th, gwsynth.prior_draws(7, 16384 - len(th))])
+    with gw.Context(prob) as ctx:
+        ctx.heterodyne_setup(prob.theta_inj, 200)
+        for prec, tol in ((gw.GW_PREC_FP64, 1e-9), (gw.GW_PREC_MIXED, 1e-6)):
+            small = ctx.loglike(torch.from_numpy(th).cuda(), gw.GW_HET, gw.GW_MARG_PHASE_TIME, prec).cpu().numpy()
+            large = ctx.loglike(torch.from_numpy(big).cuda(), gw.GW_HET, gw.GW_MARG_PHASE_TIME, prec).cpu().numpy()
+            err = np.max(np.abs(small - large[:len(th)]))
+            print(f"prec {prec}: split vs unsplit max |dlogL| {err:.2e}")
+            assert err < tol
