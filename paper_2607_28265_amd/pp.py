@@ -165,6 +165,7 @@ class Campaign:
     recon_floor: float = 1e-12  # points below this fraction of the largest weight are not reconstructed
     sky_frame: bool = False     # sample the sky about the baseline of detectors 0 -> 1
     det_time: bool = False      # ... and the arrival time at detector 0
+    sweeps: int = 0             # Gibbs sweeps per replacement (0: the configuration's own M)
 
     def __post_init__(self):
         if self.config not in CONFIGS:
@@ -194,6 +195,8 @@ class Campaign:
         import torch
         th, prob, _ = self.make_data(i)
         blocks, sweeps = CONFIGS[self.config]
+        if self.sweeps > 0:
+            sweeps = self.sweeps
         t0 = time.perf_counter()
         with Context(prob) as ctx:
             if self.like == _lib.GW_HET:
@@ -241,7 +244,8 @@ class Campaign:
             names[10] = "dl"
         lv = np.array([r["levels"] for r in runs])
         ks = {n: ks_pvalue(lv[:, j]) for j, n in enumerate(names)}
-        out = dict(config=self.config, like="het" if self.like == _lib.GW_HET else "full",
+        out = dict(config=self.config, sweeps=self.sweeps or CONFIGS[self.config][1],
+                   like="het" if self.like == _lib.GW_HET else "full",
                    sky_frame="detector" if self.frame is not None else "equatorial", det_time=self.det_time,
                    marg="phase+time" if self.time_marg else "phase+distance", n_injections=len(runs),
                    ks_pvalues=ks, fisher_p=fisher_pvalue(list(ks.values())),
@@ -270,6 +274,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=2026)
     ap.add_argument("--sky-frame", action="store_true", help="sample the sky about the baseline of detectors 0, 1")
     ap.add_argument("--det-time", action="store_true", help="with --sky-frame: sample the arrival time at detector 0")
+    ap.add_argument("--sweeps", type=int, default=0, help="Gibbs sweeps per replacement (default: the config's)")
     ap.add_argument("--out", default=None, help="JSON file for the per-injection records and the summary")
     a = ap.parse_args(argv)
     import gwsynth
@@ -277,7 +282,7 @@ def main(argv=None):
     camp = Campaign(base, config=a.config, like=_lib.GW_HET if a.like == "het" else _lib.GW_FULL,
                     marg=_lib.GW_MARG_PHASE_TIME if a.marg == "time" else _lib.GW_MARG_PHASE_DIST,
                     n_live=a.n_live, n_delete=a.n_delete, n_bins=a.n_bins, seed=a.seed, sky_frame=a.sky_frame,
-                    det_time=a.det_time)
+                    det_time=a.det_time, sweeps=a.sweeps)
     runs = []
     try:
         for i in range(a.n):
