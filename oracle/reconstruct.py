@@ -29,6 +29,12 @@ the total.
 Reading (the paper gives no draw rule): the drawn values are the grid nodes
 themselves, so that the credible levels of reconstructed parameters are
 quantised by the grid, as the appendix notes.
+
+With the phase and coalescence time marginalised (d_L sampled), the pair
+(t_c, phi_c) is drawn the same way.  t_c = t_j comes from the time grid of the
+marginal with weights exp(-<h|h>(t_j)/2 + ln I0(|Z(t_j)|)), Z(t_j) the overlap
+of the template shifted by t_j (its norm depends on t_j only for the
+heterodyned bins).  Then phi_c comes from exp(|Z(t_j)| cos(phi + arg Z(t_j))).
 """
 from __future__ import annotations
 
@@ -99,3 +105,39 @@ def reconstruct(theta, prob, u, marg: int = likelihood.PHASE_DIST, n_phase: int 
         j, d, zc = -1, float(theta[6]), z
     m = draw_index(phase_logweights(zc, n_phase), float(u[1]))
     return d, 2.0 * math.pi * m / n_phase, j, m
+
+
+def time_conditional(theta, prob, het=None):
+    """(t_j, Z(t_j), <h|h>(t_j)) on the time grid of the marginal, for the
+    template with phi_c = 0 shifted by t_j."""
+    th = np.array(theta, dtype=np.float64)
+    th[11] = 0.0
+    th[12] = 0.0
+    t = likelihood.time_grid(prob)
+    if het is None:
+        a, hh = likelihood.overlap_weights(th, prob)
+        z = likelihood.time_shifted_overlaps(a, prob, t)
+        return t, z, np.full(t.size, hh)
+    z = np.empty(t.size, dtype=np.complex128)
+    hh = np.empty(t.size)
+    for j, tj in enumerate(t):
+        th[12] = tj
+        zi, hhi = heterodyne.overlaps(th, prob, het)
+        z[j], hh[j] = complex(np.sum(zi)), float(np.sum(hhi))
+    return t, z, hh
+
+
+def time_logweights(z: np.ndarray, hh: np.ndarray) -> np.ndarray:
+    return -0.5 * np.asarray(hh) + likelihood.log_i0(np.abs(z))
+
+
+def reconstruct_time(theta, prob, u, n_phase: int = N_PHASE, het=None):
+    """(t_c, phi_c, j, m) drawn for one sample of the phase+time marginal with
+    uniforms u = (u_t, u_phi); j indexes the time grid from its first point.
+    Unphysical samples give NaN values and indices -1."""
+    if not likelihood.is_physical(theta, likelihood.PHASE_TIME):
+        return math.nan, math.nan, -1, -1
+    t, z, hh = time_conditional(theta, prob, het)
+    j = draw_index(time_logweights(z, hh), float(u[0]))
+    m = draw_index(phase_logweights(z[j], n_phase), float(u[1]))
+    return float(t[j]), 2.0 * math.pi * m / n_phase, j, m

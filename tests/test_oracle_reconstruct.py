@@ -124,3 +124,47 @@ def test_heterodyned_reconstruction_at_the_fiducial(tiny_problem):
         a = R.reconstruct(th, prob, u, L.PHASE_DIST)
         b = R.reconstruct(th, prob, u, L.PHASE_DIST, het=het)
         assert a[2] == b[2] and a[3] == b[3]
+
+
+def test_time_phase_draw_equals_brute_force_joint(tiny_problem):
+    # The phase+time marginal's pair (t_c, phi_c): the two-stage draw equals the
+    # joint posterior of the unmarginalised likelihood on the time grid times a
+    # 256-point phase grid, evaluated by brute force with t_c and phi_c set in
+    # the parameter vector (this pins the sign of the time shift).
+    prob = tiny_problem
+    n_phase = 256
+    th = gwsynth.near_posterior(4, prob.theta_inj, 1, scale=0.3)[0]
+    th[6] = 150.0
+    t, z, hh = R.time_conditional(th, prob)
+    assert t.size == 25
+    phis = R.phase_grid(n_phase)
+    logp = np.empty((t.size, n_phase))
+    for j, tj in enumerate(t):
+        for m, ph in enumerate(phis):
+            tt = th.copy()
+            tt[12], tt[11] = tj, ph
+            logp[j, m] = L.loglike_direct(tt, prob)
+    joint = np.exp(logp - logp.max())
+    joint /= joint.sum()
+    pt = np.exp(R.time_logweights(z, hh) - R.time_logweights(z, hh).max())
+    pt /= pt.sum()
+    two = np.empty_like(joint)
+    for j in range(t.size):
+        pm = np.exp(R.phase_logweights(z[j], n_phase) - np.max(R.phase_logweights(z[j], n_phase)))
+        two[j] = pt[j] * pm / pm.sum()
+    assert np.max(np.abs(two - joint)) < 1e-10
+    tc, phi, j, m = R.reconstruct_time(th, prob, (0.41, 0.77), n_phase)
+    assert tc == t[j] and phi == 2 * math.pi * m / n_phase
+
+
+def test_heterodyned_time_draw_at_the_fiducial(tiny_problem):
+    # with the fiducial at t_c = 0 the binned overlaps at t_j = 0 equal the
+    # full band's; the time weights agree closely near the peak
+    prob = tiny_problem
+    th = prob.theta_inj.copy()
+    th[12] = 0.0
+    het = H.setup(prob, th, 40)
+    t, z, hh = R.time_conditional(th, prob)
+    th_, zh, hhh = R.time_conditional(th, prob, het)
+    j0 = int(np.argmin(np.abs(t)))
+    assert abs(z[j0] - zh[j0]) < 1e-9 * abs(z[j0]) and abs(hh[j0] - hhh[j0]) < 1e-9 * hh[j0]
