@@ -175,6 +175,12 @@ gw_status gw_time_grid_info(const gw_ctx* ctx, double* delta, int32_t* n_points,
  *       exp(ln w_j - <h|h>_1 / (2 d_j^2) + ln I0(|Z_1| / d_j)), then
  *       phi_c given d_j;
  *   marg = GW_MARG_PHASE: d_L = the sample's own, phi_c drawn;
+ *   marg = GW_MARG_PHASE_TIME (d_L sampled, t_c ignored): t_c = t_j drawn on
+ *       the time grid of the marginal (see gw_set_time_window) from the
+ *       weights exp(-<h|h>(t_j)/2 + ln I0(|Z(t_j)|)), Z(t_j) the overlap of the
+ *       template shifted by t_j, then phi_c given t_j with Z' = Z(t_j);
+ *       out[p][0] is then t_c (s) and idx[p][0] the grid index j (t_j =
+ *       (j - J) delta);
  *   phi_c = 2 pi m / n_phase drawn from the weights
  *       exp(kappa cos(2 pi m / n_phase + arg Z')), Z' = Z / d_L, kappa = |Z'|
  *       (the template carries exp(+i phi_c)).
@@ -186,9 +192,10 @@ gw_status gw_time_grid_info(const gw_ctx* ctx, double* delta, int32_t* n_points,
  * logl:   device [n] the row's marginal log L (as loglike_batch), or NULL.
  * Unphysical rows give NaN and indices -1.  n_phase: 1 .. 2^20 (2048 is a
  * good default: the conditional has width 1 / sqrt(kappa)).  Errors:
- * GW_ENOTSUP for other marginals, GW_ESTATE without a distance grid (distance
+ * GW_ENOTSUP for GW_MARG_NONE, GW_ESTATE without a distance grid (distance
  * marginal) or heterodyne set-up (like = GW_HET).  Work space grows to
- * n (4 + 2 n_det) doubles; the context's likelihood work space is reused.
+ * n (4 + 2 n_det) doubles, or n (3 N_t + 1) for the time marginal; the
+ * context's likelihood work space is reused.
  */
 gw_status gw_reconstruct(gw_ctx* ctx, const double* theta, int64_t n, int32_t like, int32_t marg, int32_t prec,
                          const double* uniforms, int32_t n_phase, double* out, int32_t* idx, double* logl,

@@ -155,5 +155,12 @@ gw_status stage_overlaps(gw_ctx* ctx, const double* theta, int64_t n, int like, 
                          hipStream_t st);
 // Full-band phase+time marginal (GW_MARG_PHASE_TIME).
 gw_status loglike_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, hipStream_t st);
+// Phase+time marginals that also stage each row's grid values for post-hoc
+// draws: zout [n][N_t][3] = (Re Z(t_j), Im Z(t_j), <h|h>(t_j)), Re NaN for
+// unphysical rows.
+gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, double* zout,
+                               hipStream_t st);
+gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl,
+                                   double* zout, hipStream_t st);
 
 }  // namespace gw

@@ -916,26 +916,46 @@ __global__ void __launch_bounds__(64) k_het_tw(const double* __restrict__ coef, 
 // phase-marginal binned log L.
 // The products come in nsk partial sums over chunks of edges
 // (zh [2][nsk][n][nt] complex), added here in chunk order.
-__device__ inline double het_tgrid_value(const double* __restrict__ zh, int64_t n, int nt, int nsk, int64_t p, int j,
-                                         double h0, const LogI0Consts& C) {
-  double zr = 0.0, zi = 0.0, hr = 0.0;
+__device__ inline void het_tgrid_sums(const double* __restrict__ zh, int64_t n, int nt, int nsk, int64_t p, int j,
+                                      double* zr, double* zi, double* hr) {
+  *zr = *zi = *hr = 0.0;
   for (int c = 0; c < nsk; ++c) {
     const double* z = zh + ((int64_t)c * n + p) * nt * 2;
     const double* hv = zh + ((int64_t)(nsk + c) * n + p) * nt * 2;
-    zr += z[2 * j];
-    zi += z[2 * j + 1];
-    hr += hv[2 * j];
+    *zr += z[2 * j];
+    *zi += z[2 * j + 1];
+    *hr += hv[2 * j];
   }
+}
+
+__device__ inline double het_tgrid_value(const double* __restrict__ zh, int64_t n, int nt, int nsk, int64_t p, int j,
+                                         double h0, const LogI0Consts& C) {
+  double zr, zi, hr;
+  het_tgrid_sums(zh, n, nt, nsk, p, j, &zr, &zi, &hr);
   return -0.5 * (h0 + hr) + log_i0(sqrt(zr * zr + zi * zi), C);
 }
 
+// With zout (else NULL) the grid values are also staged for post-hoc draws:
+// zout[p][j] = (Re Z(t_j), Im Z(t_j), <h|h>(t_j)), Re NaN for unphysical rows.
 __global__ void __launch_bounds__(256) k_het_tfinal(const double* __restrict__ zh, const double* __restrict__ hhc,
                                                     const double* __restrict__ coef, int64_t ld, int64_t n, int nt,
-                                                    int nsk, double dd, LogI0Consts C, double* __restrict__ logl) {
+                                                    int nsk, double dd, LogI0Consts C, double* __restrict__ logl,
+                                                    double* __restrict__ zout) {
   __shared__ double red[256];
   const int64_t p = blockIdx.x;
   const int tid = threadIdx.x;
   const double h0 = hhc[p];
+  if (zout) {
+    const bool valid = coef[C_VALID * ld + p] != 0.0;
+    for (int j = tid; j < nt; j += 256) {
+      double zr, zi, hr;
+      het_tgrid_sums(zh, n, nt, nsk, p, j, &zr, &zi, &hr);
+      double* o = zout + (p * nt + j) * 3;
+      o[0] = valid ? zr : NAN;
+      o[1] = zi;
+      o[2] = h0 + hr;
+    }
+  }
   double mx = -INFINITY;
   for (int j = tid; j < nt; j += 256) mx = fmax(mx, het_tgrid_value(zh, n, nt, nsk, p, j, h0, C));
   red[tid] = mx;
@@ -987,6 +1007,11 @@ static void launch_het_tw_nd(gw_ctx* ctx, int64_t n, int prec, int ne_pad, const
 }
 
 gw_status loglike_het_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, hipStream_t st) {
+  return loglike_het_tmarg_staged(ctx, theta, n, prec, logl, nullptr, st);
+}
+
+gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, double* zout,
+                                   hipStream_t st) {
   gw_het_state* h = ctx->het;
   if (!h) return set_error(GW_ESTATE, "loglike_batch: heterodyne_setup has not been called");
   double delta;
@@ -1073,7 +1098,7 @@ gw_status loglike_het_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int pre
   LogI0Consts C = make_log_i0_consts();
   C.r1max = ctx->dist_r1max;
   hipLaunchKernelGGL(k_het_tfinal, dim3((unsigned)n), dim3(256), 0, st, (const double*)zh, (const double*)hhc,
-                     (const double*)ctx->coef, n, n, nt, nsk, ctx->dd, C, logl);
+                     (const double*)ctx->coef, n, n, nt, nsk, ctx->dd, C, logl, zout);
   return check_hip(hipGetLastError(), "time-marginal epilogue launch");
 }
 

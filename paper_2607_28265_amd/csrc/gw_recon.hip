@@ -173,6 +173,58 @@ gw_status stage_overlaps(gw_ctx* ctx, const double* theta, int64_t n, int like, 
   return check_hip(hipGetLastError(), "reconstruction staging launch");
 }
 
+// Phase+time marginal: one wave per sample draws t_j from
+// exp(-<h|h>(t_j)/2 + ln I0(|Z(t_j)|)) on the staged grid values
+// zt [n][nt][3], then phi_c from exp(|Z(t_j)| cos(phi + arg Z(t_j))).
+// out[p] = (t_j, phi_c) with t_j = (j - J) delta; idx[p] = (j, m).
+__global__ void __launch_bounds__(256) k_recon_time(const double* __restrict__ zt, int64_t n, int nt, int J,
+                                                    double delta, int n_phase, LogI0Consts C,
+                                                    const double* __restrict__ uni, double* __restrict__ out,
+                                                    int32_t* __restrict__ idx) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (p >= n) return;  // wave-uniform
+  const double* z = zt + p * nt * 3;
+  auto invalid = [&]() {
+    if (lane == 0) {
+      out[2 * p] = NAN;
+      out[2 * p + 1] = NAN;
+      if (idx) {
+        idx[2 * p] = -1;
+        idx[2 * p + 1] = -1;
+      }
+    }
+  };
+  if (isnan(z[0])) return invalid();
+  auto lw = [&](int q) {
+    const double* r = z + 3 * q;
+    return -0.5 * r[2] + log_i0(sqrt(r[0] * r[0] + r[1] * r[1]), C);
+  };
+  double mx = -INFINITY;
+  for (int q = lane; q < nt; q += 64) mx = fmax(mx, lw(q));
+  mx = wave_max(mx);
+  const int j = wave_draw(lw, nt, mx, uni[2 * p], lane);
+  if (j < 0) return invalid();
+  const double zpr = z[3 * j], zpi = z[3 * j + 1];
+  const double kappa = sqrt(zpr * zpr + zpi * zpi);
+  const double dphi = kTwoPi / (double)n_phase;
+  auto pw = [&](int q) {
+    double sn, cs;
+    sincos(dphi * (double)q, &sn, &cs);
+    return zpr * cs - zpi * sn;
+  };
+  const int m = wave_draw(pw, n_phase, kappa, uni[2 * p + 1], lane);
+  if (m < 0) return invalid();
+  if (lane == 0) {
+    out[2 * p] = (double)(j - J) * delta;
+    out[2 * p + 1] = kTwoPi * (double)m / (double)n_phase;
+    if (idx) {
+      idx[2 * p] = j;
+      idx[2 * p + 1] = m;
+    }
+  }
+}
+
 }  // namespace gw
 
 using namespace gw;
@@ -186,8 +238,8 @@ gw_status gw_reconstruct(gw_ctx* ctx, const double* theta, int64_t n, int32_t li
   if (n < 0) return set_error(GW_EINVAL, "gw_reconstruct: n < 0");
   if (n > 0 && (!theta || !uniforms || !out)) return set_error(GW_EINVAL, "gw_reconstruct: null pointer");
   if (like != GW_FULL && like != GW_HET) return set_error(GW_EINVAL, "gw_reconstruct: bad like=%d", like);
-  if (marg != GW_MARG_PHASE && marg != GW_MARG_PHASE_DIST)
-    return set_error(GW_ENOTSUP, "gw_reconstruct: marg must be GW_MARG_PHASE or GW_MARG_PHASE_DIST");
+  if (marg != GW_MARG_PHASE && marg != GW_MARG_PHASE_DIST && marg != GW_MARG_PHASE_TIME)
+    return set_error(GW_ENOTSUP, "gw_reconstruct: marg must be GW_MARG_PHASE, GW_MARG_PHASE_DIST or GW_MARG_PHASE_TIME");
   if (prec != GW_PREC_FP64 && prec != GW_PREC_MIXED) return set_error(GW_EINVAL, "gw_reconstruct: bad prec=%d", prec);
   if (n_phase < 1 || n_phase > (1 << 20)) return set_error(GW_EINVAL, "gw_reconstruct: n_phase 1 .. 2^20");
   if (marg == GW_MARG_PHASE_DIST && ctx->n_dist <= 0)
@@ -197,11 +249,27 @@ gw_status gw_reconstruct(gw_ctx* ctx, const double* theta, int64_t n, int32_t li
   hipStream_t st = (hipStream_t)stream;
   gw_status s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
   if (s != GW_OK) return s;
+  LogI0Consts C = make_log_i0_consts();
+  C.r1max = ctx->dist_r1max;
+  if (marg == GW_MARG_PHASE_TIME) {
+    double delta;
+    int32_t nt;
+    s = gw_time_grid_info(ctx, &delta, &nt, nullptr, nullptr);
+    if (s == GW_OK)
+      s = ensure_buffer(&ctx->recon, &ctx->recon_cap, (int64_t)nt * 3 * n + n, "reconstruction workspace");
+    if (s != GW_OK) return s;
+    double* zt = ctx->recon;
+    double* ll = logl ? logl : zt + (int64_t)nt * 3 * n;
+    s = like == GW_HET ? loglike_het_tmarg_staged(ctx, theta, n, prec, ll, zt, st)
+                       : loglike_tmarg_staged(ctx, theta, n, prec, ll, zt, st);
+    if (s != GW_OK) return s;
+    hipLaunchKernelGGL(k_recon_time, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, zt, n, nt, (nt - 1) / 2, delta,
+                       n_phase, C, uniforms, out, idx);
+    return check_hip(hipGetLastError(), "time reconstruction launch");
+  }
   s = stage_overlaps(ctx, theta, n, like, marg, prec, logl, st);
   if (s != GW_OK) return s;
   double* zc3 = ctx->recon;
-  LogI0Consts C = make_log_i0_consts();
-  C.r1max = ctx->dist_r1max;
   hipLaunchKernelGGL(k_recon, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, zc3, n, theta, ctx->dist_tab,
                      ctx->n_dist, marg, n_phase, C, uniforms, out, idx);
   return check_hip(hipGetLastError(), "reconstruction launch");

@@ -465,8 +465,9 @@ struct gw_slice_ws {
   void* mem = nullptr;
   double* cand = nullptr;       // [2k][13]
   double* cand_logl = nullptr;  // [2k]
-  int32_t* h_active = nullptr;  // pinned host
+  int32_t* h_active = nullptr;  // pinned host [2]: chains still moving after a group, double-buffered
   unsigned long long* h_kinds = nullptr;  // pinned host [3]
+  hipEvent_t ev[2] = {nullptr, nullptr};  // readback of h_active[i] complete
   SliceState S{};
   SweepParams* dev = nullptr;   // device parameter block
   float2* wc = nullptr;         // waveform cache (block moments) [cap_wc][slot_f2]
@@ -709,10 +710,12 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
     }
   }
   // One group = 4 rounds of (propose, batched likelihood, update); after a
-  // group the host reads the number of chains still moving.  A block takes at
+  // group the number of chains still moving is copied back.  A block takes at
   // most max_out + 1 stepping rounds (both sides in parallel) and max_shrink
-  // shrink rounds, so after max_rounds every chain is done and further rounds
-  // change nothing.
+  // shrink rounds, so after max_rounds every chain is done.  Rounds after every
+  // chain is done change nothing, so the next group is queued before the
+  // previous group's count is read: the host waits on group g while group
+  // g + 1 runs, and at most one group of idle rounds follows the last move.
   const int max_rounds = P.nb * (P.max_out + 1 + P.max_shrink + 1);
   auto group = [&](hipStream_t gs) -> gw_status {
     gw_status g = GW_OK;
@@ -732,13 +735,21 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
     return g;
   };
   if (s == GW_OK && a.use_graph) s = slice_graph(ctx, ws, k, a, group);
+  int cur = 0, prev = -1;
   for (int rounds = 0; s == GW_OK && rounds < max_rounds; rounds += 4) {
     if (a.use_graph) s = check_hip(hipGraphLaunch(ws->exec, st), "slice graph launch");
     else s = group(st);
     if (s != GW_OK) break;
-    s = check_hip(hipMemcpyAsync(ws->h_active, ws->S.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st), "copy");
-    if (s == GW_OK) s = check_hip(hipStreamSynchronize(st), "slice round sync");
-    if (s == GW_OK && *ws->h_active == 0) break;
+    s = check_hip(hipMemcpyAsync(ws->h_active + cur, ws->S.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                  "copy");
+    if (s == GW_OK) s = check_hip(hipEventRecord(ws->ev[cur], st), "slice event");
+    if (s != GW_OK) break;
+    if (prev >= 0) {
+      s = check_hip(hipEventSynchronize(ws->ev[prev]), "slice round sync");
+      if (s == GW_OK && ws->h_active[prev] == 0) break;  // the group just queued only idles
+    }
+    prev = cur;
+    cur ^= 1;
   }
   if (s != GW_OK) return s;
   hipLaunchKernelGGL(k_sweep_finish, dim3(blocks), dim3(tpb), 0, st, (const SweepParams*)ws->dev, ws->S, a.n_evals,
@@ -897,8 +908,11 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
   if (!ws) {
     ws = new (std::nothrow) gw_slice_ws();
     if (!ws) return set_error(GW_ENOMEM, "slice workspace");
-    if (hipHostMalloc((void**)&ws->h_active, sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void**)&ws->h_active, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
       return set_error(GW_ENOMEM, "slice pinned flag");
+    for (int i = 0; i < 2; ++i)
+      if (hipEventCreateWithFlags(&ws->ev[i], hipEventDisableTiming) != hipSuccess)
+        return set_error(GW_EDEVICE, "slice events");
     if (hipHostMalloc((void**)&ws->h_kinds, 3 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
       return set_error(GW_ENOMEM, "slice pinned counters");
     if (hipMalloc((void**)&ws->dev, sizeof(SweepParams)) != hipSuccess) return set_error(GW_ENOMEM, "slice parameters");
@@ -981,6 +995,8 @@ void slice_free(gw_ctx* ctx) {
   if (ws->dev) (void)hipFree(ws->dev);
   if (ws->h_active) (void)hipHostFree(ws->h_active);
   if (ws->h_kinds) (void)hipHostFree(ws->h_kinds);
+  for (hipEvent_t e : ws->ev)
+    if (e) (void)hipEventDestroy(e);
   delete ws;
   ctx->slice = nullptr;
 }

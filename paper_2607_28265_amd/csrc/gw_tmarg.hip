@@ -152,10 +152,15 @@ __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, i
 
 // One workgroup (256 threads) per proposal; P <= kTMaxP.  Dynamic LDS: two
 // buffers of P complex values.
+// With zout (else NULL) each row's grid values are also staged for post-hoc
+// draws: zout[p][j] = (Re Z(t_j), Im Z(t_j), <h|h>) (Re NaN for unphysical
+// rows), the unit factor exp(-2 pi i f_0 t_j) restored: f_0 t_j = j f0_num /
+// f0_den cycles exactly, f0_num = 2 k0 + B - 1 and f0_den = 2 N.
 __global__ void __launch_bounds__(256) k_tmarg(const double* __restrict__ mom, int64_t n, int n_blk, int P, int J,
                                                const double2* __restrict__ tw, double phi_step,
                                                const double* __restrict__ coef, int64_t ld, double dd,
-                                               LogI0Consts C, double* __restrict__ logl) {
+                                               LogI0Consts C, double* __restrict__ logl, double* __restrict__ zout,
+                                               double f0_num, double f0_den) {
   extern __shared__ double2 lds_fft[];
   double2* buf[2] = {lds_fft, lds_fft + P};
   __shared__ double red[256];
@@ -201,6 +206,23 @@ __global__ void __launch_bounds__(256) k_tmarg(const double* __restrict__ mom, i
       }
     }
     __syncthreads();  // before the next moment overwrites the buffers
+  }
+  if (zout) {
+    const bool valid = coef[C_VALID * ld + p] != 0.0;
+    const double hh = coef[C_HH * ld + p];
+#pragma unroll
+    for (int q = 0; q < kOwn; ++q) {
+      const int jj = tid + 256 * q;
+      if (jj < nj) {
+        const double cyc = (double)(jj - J) * f0_num / f0_den;
+        double sn, cs;
+        sincospi(2.0 * (cyc - rint(cyc)), &sn, &cs);
+        double* o = zout + (p * nj + jj) * 3;
+        o[0] = valid ? cs * hr[q] + sn * hi[q] : NAN;
+        o[1] = cs * hi[q] - sn * hr[q];
+        o[2] = hh;
+      }
+    }
   }
   // log-sum-exp of ln I0(|Z_j|) over the grid, in a fixed order
   double v[kOwn];
@@ -278,6 +300,11 @@ static gw_status time_grid(const gw_ctx* ctx, TimeGrid* g) {
 }
 
 gw_status loglike_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, hipStream_t st) {
+  return loglike_tmarg_staged(ctx, theta, n, prec, logl, nullptr, st);
+}
+
+gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, double* zout,
+                               hipStream_t st) {
   TimeGrid g;
   gw_status s = time_grid(ctx, &g);
   if (s != GW_OK) return s;
@@ -320,7 +347,8 @@ gw_status loglike_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int prec, d
   const double phi_step = kPi * ctx->geom.df * g.blk * g.delta;
   hipLaunchKernelGGL(k_tmarg, dim3((unsigned)n), dim3(256), 2 * g.P * sizeof(double2), st,
                      (const double*)ctx->tm_mom, n, g.n_blk, g.P, g.J,
-                     (const double2*)ctx->tm_tw, phi_step, (const double*)ctx->coef, n, ctx->dd, C, logl);
+                     (const double2*)ctx->tm_tw, phi_step, (const double*)ctx->coef, n, ctx->dd, C, logl, zout,
+                     (double)(2 * ctx->geom.k0 + g.blk - 1), (double)(2 * g.N));
   return check_hip(hipGetLastError(), "time marginal launch");
 }
 

@@ -115,7 +115,7 @@ def test_reconstruct_edge_cases(setup):
     with pytest.raises(gw.GwError):
         gw.gw_reconstruct(ctx.handle, tt, ut, marg=0)
     with pytest.raises(gw.GwError):
-        gw.gw_reconstruct(ctx.handle, tt, ut, marg=3)
+        gw.gw_reconstruct(ctx.handle, tt, ut, marg=4)
     with pytest.raises(gw.GwError):
         gw.gw_reconstruct(ctx.handle, tt, ut, n_phase=0)
     with pytest.raises(ValueError):
@@ -149,3 +149,51 @@ def test_reconstruct_full_size_sampled():
         if not edge:
             ok, _ = _index_ok(idx[r, 1], m, R.phase_logweights(z / d, 2048), uni[r, 1], 1e-4)
             assert ok, (r, idx[r, 1], m)
+
+
+@pytest.mark.parametrize("like", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_time_reconstruction_matches_oracle(like, prec):
+    # the phase+time marginal: (t_c, phi_c) drawn on the time grid and the
+    # phase grid; indices as above, values the grid nodes
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2607_28265_amd as gw
+    prob = problem("cfg1", loud=True)
+    th0 = prob.theta_inj.copy()
+    th0[12] = 0.0
+    het = H.setup(prob, th0, 200) if like == 1 else None
+    n, n_phase = 40, 2048
+    th = gwsynth.near_posterior(33, prob.theta_inj, n, scale=1.0)
+    th[:, 12] = 0.0
+    th[3, 1] = 1.5  # unphysical
+    uni = np.random.default_rng(11).uniform(size=(n, 2))
+    tgrid = L.time_grid(prob)
+    with gw.Context(prob) as ctx:
+        if like == 1:
+            ctx.heterodyne_setup(th0, 200)
+        out, idx, logl = gw.gw_reconstruct(ctx.handle, torch.from_numpy(th).cuda(), torch.from_numpy(uni).cuda(),
+                                           like=like, marg=gw.GW_MARG_PHASE_TIME, prec=prec, n_phase=n_phase)
+        torch.cuda.synchronize()
+    out, idx, logl = out.cpu().numpy(), idx.cpu().numpy(), logl.cpu().numpy()
+    tol = 1e-9 if prec == 0 else 1e-4
+    n_edge = 0
+    for r in range(n):
+        if not L.is_physical(th[r], L.PHASE_TIME):
+            assert math.isnan(out[r, 0]) and idx[r, 0] == -1 and logl[r] == -math.inf
+            continue
+        t, z, hh = R.time_conditional(th[r], prob, het)
+        tc, phi, j, m = R.reconstruct_time(th[r], prob, uni[r], n_phase, het=het)
+        ok, edge = _index_ok(idx[r, 0], j, R.time_logweights(z, hh), uni[r, 0], tol)
+        assert ok, (r, idx[r, 0], j)
+        n_edge += edge
+        jj = idx[r, 0]
+        assert out[r, 0] == tgrid[jj]
+        if edge:
+            m = R.draw_index(R.phase_logweights(z[jj], n_phase), uni[r, 1])
+        ok, edge = _index_ok(idx[r, 1], m, R.phase_logweights(z[jj], n_phase), uni[r, 1], tol)
+        assert ok, (r, idx[r, 1], m)
+        n_edge += edge
+        assert out[r, 1] == 2 * math.pi * idx[r, 1] / n_phase
+    print(f"time: like {like} prec {prec}: {n} samples, {n_edge} boundary draws", flush=True)
+    assert n_edge <= 2
