@@ -126,17 +126,18 @@ def test_heterodyned_reconstruction_at_the_fiducial(tiny_problem):
         assert a[2] == b[2] and a[3] == b[3]
 
 
-def test_time_phase_draw_equals_brute_force_joint(tiny_problem):
+def test_time_phase_draw_equals_brute_force_joint(tiny_problem, monkeypatch):
     # The phase+time marginal's pair (t_c, phi_c): the two-stage draw equals the
     # joint posterior of the unmarginalised likelihood on the time grid times a
     # 256-point phase grid, evaluated by brute force with t_c and phi_c set in
     # the parameter vector (this pins the sign of the time shift).
     prob = tiny_problem
     n_phase = 256
+    monkeypatch.setattr(L, "TIME_WINDOW", 0.02)  # 2 sampling intervals a side, 4 points each
     th = gwsynth.near_posterior(4, prob.theta_inj, 1, scale=0.3)[0]
     th[6] = 150.0
     t, z, hh = R.time_conditional(th, prob)
-    assert t.size == 25
+    assert t.size == 17
     phis = R.phase_grid(n_phase)
     logp = np.empty((t.size, n_phase))
     for j, tj in enumerate(t):

@@ -31,12 +31,54 @@ def prob():
 
 
 def test_grid(prob):
-    t = L.time_grid(prob)
+    t = L.time_grid(prob, oversample=1)
     delta = t[1] - t[0]
     # 8 s at 20-512 Hz: the segment's sampling interval is 1/1024 s
     assert delta == pytest.approx(1.0 / 1024.0, rel=1e-15)
     assert t[0] == -t[-1] and abs(t[-1]) <= L.TIME_WINDOW < abs(t[-1]) + delta
     assert t.size == 2 * 102 + 1
+    # the default grid has four points per sampling interval over the same span
+    t4 = L.time_grid(prob)
+    assert L.TIME_OVERSAMPLE == 4 and t4.size == 2 * 102 * 4 + 1
+    assert t4[1] - t4[0] == pytest.approx(delta / 4, rel=1e-15) and t4[-1] == pytest.approx(t[-1], rel=1e-15)
+
+
+def test_oversampled_grid_converges_to_the_integral(monkeypatch):
+    # The grid mean of I0(|Z(t)|) approximates (1 / 2W) times its integral.
+    # For a loud template half a sampling interval off the grid, the plain
+    # interval is far off and the error falls quickly with the oversampling;
+    # the limit agrees with adaptive quadrature of the same integrand up to the
+    # grid's O(1 / N_t) end correction.
+    from scipy import integrate
+    from scipy.special import i0e
+    p = gwsynth.make_problem(4.0, 20.0, 128.0, psd_scale=1e-49)
+    th = gwsynth.prior_draws(gwsynth.SEEDS["injection"], 1)[0]
+    _, hh = L.overlap(th, p)
+    th[6] *= math.sqrt(hh) / 40.0  # network SNR 40
+    th[11] = th[12] = 0.0
+    monkeypatch.setattr(L, "TIME_WINDOW", 0.004)
+    native = L.time_grid(p, oversample=1)
+    delta = native[1] - native[0]
+    inj = th.copy()
+    inj[12] = 0.5 * delta
+    p.data = L.strain(inj, p)
+    a, _ = L.overlap_weights(th, p)
+    vals = {}
+    ladder = (1, 2, 4, 8, 16, 32, 64)
+    for r in ladder:
+        tg = L.time_grid(p, oversample=r)
+        z = np.abs(L.time_shifted_overlaps(a, p, tg))
+        vals[r] = float(np.max(z) + np.log(np.mean(i0e(z) * np.exp(z - np.max(z)))))
+    errs = [abs(vals[r] - vals[64]) for r in ladder[:-1]]
+    assert errs[0] > 10.0 and all(x > y for x, y in zip(errs, errs[1:])) and errs[-1] < 1e-2
+    zmax = np.max(np.abs(L.time_shifted_overlaps(a, p, L.time_grid(p, oversample=64))))
+    f = lambda t: float(i0e(abs(L.time_shifted_overlaps(a, p, np.array([t]))[0]))
+                        * np.exp(abs(L.time_shifted_overlaps(a, p, np.array([t]))[0]) - zmax))
+    span = native[-1]
+    integ, _ = integrate.quad(f, -span, span, points=[0.5 * delta], limit=400, epsabs=0, epsrel=1e-10)
+    want = zmax + math.log(integ / (2 * span))
+    n64 = L.time_grid(p, oversample=64).size
+    assert abs(vals[64] - want) < 2.0 / n64
 
 
 def test_shifted_overlaps_are_an_fft(prob):
