@@ -140,16 +140,20 @@ gw_status loglike_batch(gw_ctx* ctx, const double* theta, int64_t n, int32_t lik
  * Coalescence-time marginal (GW_MARG_PHASE_TIME, with the phase marginal;
  * the appendix's grid sum over time shifts, evaluated by FFT on the uniform
  * grid).  The t_c column of theta is ignored; d_L is used.  On the grid
- * t_j = j delta, |t_j| <= W, delta = 1 / (N df) with N the smallest power of
- * two >= 2 (k0 + n_freq - 1) (the segment's sampling interval):
+ * t_j = j delta / R, |j| <= J R, J = floor(W / delta), delta = 1 / (N df) with N
+ * the smallest power of two >= 2 (k0 + n_freq - 1) (the segment's sampling
+ * interval) and R the oversampling (gw_set_time_oversample, default 4: the
+ * paper's dense grid; on the plain interval the sum of I0(|Z|) misses the
+ * integral by tens of nats for loud signals):
  *   log L = -<d|d>/2 - <h|h>/2 + ln[ (1/N_t) sum_j I0(|Z(t_j)|) ],
  * Z(t) the overlap of the template shifted by t (template at t_c = 0).  The
- * library evaluates Z on the whole grid with 16 FFTs of length P (the
- * smallest power of two >= N_t) over blocks of N / P bins, within which the
- * time shift is expanded to 16 terms (first dropped term below 1e-10 of the
- * block's overlap sum).  W defaults to 0.1 s; gw_set_time_window changes it
- * (GW_ENOTSUP if the grid would exceed 2048 points).  gw_time_grid_info
- * reports delta, N_t, P and the block length.  Work space: n x (n_freq / B)
+ * library evaluates Z on each of the R sub-grids (t = (j + r / R) delta) with
+ * 16 FFTs of length P (the smallest power of two >= 2 J + 1) over blocks of
+ * N / P bins, within which the time shift is expanded to 16 terms (first
+ * dropped term below 1e-10 of the block's overlap sum).  W defaults to 0.1 s;
+ * gw_set_time_window changes it (GW_ENOTSUP if a sub-grid would exceed 2048
+ * points).  gw_time_grid_info reports the grid step delta / R, the number of
+ * points N_t = 2 J R + 1, P and the block length.  Work space: n x (n_freq / B)
  * x 256 bytes per call.
  * With like = GW_HET the same grid sum runs on the binned likelihood, the
  * appendix's direct summation on the heterodyned bins: at every t_j the
@@ -160,6 +164,9 @@ gw_status loglike_batch(gw_ctx* ctx, const double* theta, int64_t n, int32_t lik
  * complex GEMM (rocBLAS); work space n x (n_edges + N_t) x 64 bytes.
  */
 gw_status gw_set_time_window(gw_ctx* ctx, double window);
+/* Grid points per sampling interval of the time marginal: 1, 2, 4 (default),
+ * 8 or 16; GW_EINVAL otherwise.  Applies from the next call on. */
+gw_status gw_set_time_oversample(gw_ctx* ctx, int32_t factor);
 gw_status gw_time_grid_info(const gw_ctx* ctx, double* delta, int32_t* n_points, int32_t* fft_len,
                             int32_t* block_bins);
 

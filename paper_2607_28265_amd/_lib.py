@@ -137,6 +137,7 @@ _SIGS = {
     "slice_step": (ctypes.c_int, [_P, ctypes.POINTER(gw_slice_args), _P]),
     "slice_sweep": (ctypes.c_int, [_P, ctypes.POINTER(gw_sweep_args), _P]),
     "gw_set_time_window": (ctypes.c_int, [_P, ctypes.c_double]),
+    "gw_set_time_oversample": (ctypes.c_int, [_P, ctypes.c_int32]),
     "gw_time_grid_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "gw_wcache_create": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(_P)]),
@@ -697,3 +698,8 @@ def gw_fiducial_search(ctx, x, generations: int, seed: int = 0, f_scale: float =
     check(load().gw_fiducial_search(ctx, ctypes.byref(a), _tensor_ptr(x), _tensor_ptr(fx), _dptr(best),
                                     _stream_ptr(stream)), "gw_fiducial_search")
     return fx, best
+
+
+def gw_set_time_oversample(ctx, factor: int = 4):
+    """Grid points per sampling interval of the time marginal (1, 2, 4, 8, 16)."""
+    check(load().gw_set_time_oversample(ctx, int(factor)), "gw_set_time_oversample")

@@ -57,7 +57,9 @@ struct gw_ctx {
   int prof_used = 0;
   // time marginal: window half-width (s), FFT twiddles and moment workspace
   double tm_window = 0.1;
+  int tm_R = 4;                    // grid points per sampling interval of the segment
   int tm_P = 0;
+  int tm_twR = 0;                  // oversampling the twiddle table was built for
   double* tm_tw = nullptr;
   double* tm_mom = nullptr;
   int64_t tm_mom_cap = 0;

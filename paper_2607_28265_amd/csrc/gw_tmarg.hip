@@ -152,112 +152,117 @@ __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, i
 
 // One workgroup (256 threads) per proposal; P <= kTMaxP.  Dynamic LDS: two
 // buffers of P complex values.
+// The grid is oversampled R times: sub-grid r holds t = (j + r / R) delta,
+// |j| <= J for r = 0 and -J <= j < J otherwise (2 J R + 1 points in all).  A
+// shift of r delta / R multiplies block b's term by exp(-2 pi i b r / (R P))
+// (``sh`` [R][P]), applied to the moments before the FFT.  The log-sum-exp runs
+// over every point of every sub-grid, in a fixed order.
 // With zout (else NULL) each row's grid values are also staged for post-hoc
-// draws: zout[p][j] = (Re Z(t_j), Im Z(t_j), <h|h>) (Re NaN for unphysical
-// rows), the unit factor exp(-2 pi i f_0 t_j) restored: f_0 t_j = j f0_num /
-// f0_den cycles exactly, f0_num = 2 k0 + B - 1 and f0_den = 2 N.
+// draws: zout[p][i] = (Re Z(t_i), Im Z(t_i), <h|h>), t_i = (i - J R) delta / R
+// (Re NaN for unphysical rows), the unit factor exp(-2 pi i f_0 t_i) restored:
+// f_0 t_i = (i - J R) f0_num / (f0_den R) cycles exactly, f0_num = 2 k0 + B - 1
+// and f0_den = 2 N.
 __global__ void __launch_bounds__(256) k_tmarg(const double* __restrict__ mom, int64_t n, int n_blk, int P, int J,
-                                               const double2* __restrict__ tw, double phi_step,
-                                               const double* __restrict__ coef, int64_t ld, double dd,
-                                               LogI0Consts C, double* __restrict__ logl, double* __restrict__ zout,
-                                               double f0_num, double f0_den) {
+                                               int R, const double2* __restrict__ tw, const double2* __restrict__ sh,
+                                               double phi_step, const double* __restrict__ coef, int64_t ld,
+                                               double dd, LogI0Consts C, double* __restrict__ logl,
+                                               double* __restrict__ zout, double f0_num, double f0_den) {
   extern __shared__ double2 lds_fft[];
   double2* buf[2] = {lds_fft, lds_fft + P};
   __shared__ double red[256];
-  constexpr int kOwn = kTMaxP / 256;  // grid points per thread (at most)
+  constexpr int kOwn = kTMaxP / 256;  // grid points per thread and sub-grid (at most)
   const int64_t p = blockIdx.x;
   const int tid = threadIdx.x;
   const int nj = 2 * J + 1;
-  double hr[kOwn], hi[kOwn];
+  const int nt = 2 * J * R + 1;
+  const bool valid = coef[C_VALID * ld + p] != 0.0;
+  const double hh = coef[C_HH * ld + p];
+  double run_mx = -INFINITY, run_acc = 0.0;  // this thread's log-sum-exp so far
+  for (int r = 0; r < R; ++r) {
+    const double frac = (double)r / (double)R;
+    double hr[kOwn], hi[kOwn];
 #pragma unroll
-  for (int q = 0; q < kOwn; ++q) hr[q] = hi[q] = 0.0;
-  for (int m = kTMom - 1; m >= 0; --m) {
-    const double* __restrict__ src = mom + (p * kTMom + m) * n_blk * 2;
-    for (int b = tid; b < P; b += 256)
-      buf[0][b] = b < n_blk ? make_double2(src[2 * b], src[2 * b + 1]) : make_double2(0.0, 0.0);
-    __syncthreads();
-    int cur = 0;
-    for (int ns = 1; ns < P; ns <<= 1) {
-      for (int j = tid; j < P / 2; j += 256) {
-        const double2 v0 = buf[cur][j];
-        const double2 x1 = buf[cur][j + P / 2];
-        const int k = j & (ns - 1);
-        const double2 w = tw[k * (P / (2 * ns))];
-        const double v1r = x1.x * w.x - x1.y * w.y, v1i = x1.x * w.y + x1.y * w.x;
-        const int idx = ((j - k) << 1) + k;
-        buf[cur ^ 1][idx] = make_double2(v0.x + v1r, v0.y + v1i);
-        buf[cur ^ 1][idx + ns] = make_double2(v0.x - v1r, v0.y - v1i);
+    for (int q = 0; q < kOwn; ++q) hr[q] = hi[q] = 0.0;
+    for (int m = kTMom - 1; m >= 0; --m) {
+      const double* __restrict__ src = mom + (p * kTMom + m) * n_blk * 2;
+      for (int b = tid; b < P; b += 256) {
+        double2 v = b < n_blk ? make_double2(src[2 * b], src[2 * b + 1]) : make_double2(0.0, 0.0);
+        if (r > 0) {
+          const double2 w = sh[r * P + b];
+          v = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
+        }
+        buf[0][b] = v;
       }
       __syncthreads();
-      cur ^= 1;
-    }
-    // H = F_m + (-i phi_j / (m + 1)) H
-    const double inv = 1.0 / (double)(m + 1);
-#pragma unroll
-    for (int q = 0; q < kOwn; ++q) {
-      const int jj = tid + 256 * q;
-      if (jj < nj) {
-        const int j = jj - J;
-        const double2 f = buf[cur][j < 0 ? j + P : j];
-        const double qq = phi_step * (double)j * inv;
-        const double nr = fma(qq, hi[q], f.x), ni = fma(-qq, hr[q], f.y);
-        hr[q] = nr;
-        hi[q] = ni;
+      int cur = 0;
+      for (int ns = 1; ns < P; ns <<= 1) {
+        for (int j = tid; j < P / 2; j += 256) {
+          const double2 v0 = buf[cur][j];
+          const double2 x1 = buf[cur][j + P / 2];
+          const int k = j & (ns - 1);
+          const double2 w = tw[k * (P / (2 * ns))];
+          const double v1r = x1.x * w.x - x1.y * w.y, v1i = x1.x * w.y + x1.y * w.x;
+          const int idx = ((j - k) << 1) + k;
+          buf[cur ^ 1][idx] = make_double2(v0.x + v1r, v0.y + v1i);
+          buf[cur ^ 1][idx + ns] = make_double2(v0.x - v1r, v0.y - v1i);
+        }
+        __syncthreads();
+        cur ^= 1;
       }
+      // H = F_m + (-i phi(t) / (m + 1)) H, phi(t) = phi_step (j + r / R)
+      const double inv = 1.0 / (double)(m + 1);
+#pragma unroll
+      for (int q = 0; q < kOwn; ++q) {
+        const int jj = tid + 256 * q;
+        if (jj < nj) {
+          const int j = jj - J;
+          const double2 f = buf[cur][j < 0 ? j + P : j];
+          const double qq = phi_step * ((double)j + frac) * inv;
+          const double nr = fma(qq, hi[q], f.x), ni = fma(-qq, hr[q], f.y);
+          hr[q] = nr;
+          hi[q] = ni;
+        }
+      }
+      __syncthreads();  // before the next moment overwrites the buffers
     }
-    __syncthreads();  // before the next moment overwrites the buffers
-  }
-  if (zout) {
-    const bool valid = coef[C_VALID * ld + p] != 0.0;
-    const double hh = coef[C_HH * ld + p];
 #pragma unroll
     for (int q = 0; q < kOwn; ++q) {
       const int jj = tid + 256 * q;
-      if (jj < nj) {
-        const double cyc = (double)(jj - J) * f0_num / f0_den;
+      if (jj >= nj || (r > 0 && jj == nj - 1)) continue;  // sub-grids r > 0 stop one step short
+      const int i = jj * R + r;                               // position on the full grid
+      if (zout) {
+        const double cyc = (double)(i - J * R) * f0_num / (f0_den * (double)R);
         double sn, cs;
         sincospi(2.0 * (cyc - rint(cyc)), &sn, &cs);
-        double* o = zout + (p * nj + jj) * 3;
+        double* o = zout + (p * nt + i) * 3;
         o[0] = valid ? cs * hr[q] + sn * hi[q] : NAN;
         o[1] = cs * hi[q] - sn * hr[q];
         o[2] = hh;
       }
+      const double v = log_i0(sqrt(hr[q] * hr[q] + hi[q] * hi[q]), C);
+      if (v > run_mx) {
+        run_acc = run_acc * exp(run_mx - v) + 1.0;
+        run_mx = v;
+      } else {
+        run_acc += exp(v - run_mx);
+      }
     }
   }
-  // log-sum-exp of ln I0(|Z_j|) over the grid, in a fixed order
-  double v[kOwn];
-  double mx = -INFINITY;
-#pragma unroll
-  for (int q = 0; q < kOwn; ++q) {
-    const int jj = tid + 256 * q;
-    v[q] = -INFINITY;
-    if (jj < nj) {
-      v[q] = log_i0(sqrt(hr[q] * hr[q] + hi[q] * hi[q]), C);
-      mx = fmax(mx, v[q]);
-    }
-  }
-  red[tid] = mx;
+  red[tid] = run_mx;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (tid < s2) red[tid] = fmax(red[tid], red[tid + s2]);
     __syncthreads();
   }
   const double ref = red[0];
   __syncthreads();
-  double acc = 0.0;
-#pragma unroll
-  for (int q = 0; q < kOwn; ++q)
-    if (tid + 256 * q < nj) acc += exp(v[q] - ref);
-  red[tid] = acc;
+  red[tid] = run_acc > 0.0 ? run_acc * exp(run_mx - ref) : 0.0;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (tid < s2) red[tid] += red[tid + s2];
     __syncthreads();
   }
-  if (tid == 0) {
-    const bool valid = coef[C_VALID * ld + p] != 0.0;
-    logl[p] = valid ? -0.5 * dd - 0.5 * coef[C_HH * ld + p] + ref + log(red[0]) - log((double)nj) : -INFINITY;
-  }
+  if (tid == 0) logl[p] = valid ? -0.5 * dd - 0.5 * hh + ref + log(red[0]) - log((double)nt) : -INFINITY;
 }
 
 template <int ND>
@@ -277,8 +282,8 @@ static void launch_tmom_nd(gw_ctx* ctx, const double* coef, int64_t n, int prec,
 // Grid of the time marginal for the context's window: N, J, P, B.
 struct TimeGrid {
   int64_t N;
-  double delta;
-  int J, P, blk, n_blk;
+  double delta;  // the segment's sampling interval; the grid step is delta / R
+  int J, R, P, blk, n_blk;
 };
 
 static gw_status time_grid(const gw_ctx* ctx, TimeGrid* g) {
@@ -288,6 +293,7 @@ static gw_status time_grid(const gw_ctx* ctx, TimeGrid* g) {
   g->N = N;
   g->delta = 1.0 / ((double)N * ctx->geom.df);
   g->J = (int)floor(ctx->tm_window / g->delta + 1e-9);
+  g->R = ctx->tm_R;
   int P = 2;
   while (P < 2 * g->J + 1) P <<= 1;
   if (P > kTMaxP) return set_error(GW_ENOTSUP, "time marginal: window %.6g s needs more than %d grid points",
@@ -308,14 +314,21 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
   TimeGrid g;
   gw_status s = time_grid(ctx, &g);
   if (s != GW_OK) return s;
-  if (ctx->tm_P != g.P) {
-    // twiddles w^k = exp(-2 pi i k / P), k < P / 2, in FP64
-    std::vector<double> h((size_t)g.P);
+  if (ctx->tm_P != g.P || ctx->tm_twR != g.R) {
+    // twiddles w^k = exp(-2 pi i k / P), k < P / 2, then the sub-grid shifts
+    // exp(-2 pi i b r / (R P)) [R][P], in FP64
+    std::vector<double> h((size_t)g.P + 2 * (size_t)g.R * g.P);
     for (int k = 0; k < g.P / 2; ++k) {
       const double a = -2.0 * kPi * (double)k / (double)g.P;
       h[2 * k] = cos(a);
       h[2 * k + 1] = sin(a);
     }
+    for (int r = 0; r < g.R; ++r)
+      for (int b = 0; b < g.P; ++b) {
+        const double a = -2.0 * kPi * (double)((int64_t)b * r) / ((double)g.R * g.P);
+        h[g.P + 2 * ((size_t)r * g.P + b)] = cos(a);
+        h[g.P + 2 * ((size_t)r * g.P + b) + 1] = sin(a);
+      }
     if (ctx->tm_tw) (void)hipFree(ctx->tm_tw);
     ctx->tm_tw = nullptr;
     ctx->tm_P = 0;
@@ -324,6 +337,7 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
       s = check_hip(hipMemcpy(ctx->tm_tw, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice), "twiddles");
     if (s != GW_OK) return s;
     ctx->tm_P = g.P;
+    ctx->tm_twR = g.R;
   }
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
   if (s == GW_OK) s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap, n * kTMom * g.n_blk * 2, "time moments");
@@ -346,9 +360,9 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
   C.r1max = ctx->dist_r1max;
   const double phi_step = kPi * ctx->geom.df * g.blk * g.delta;
   hipLaunchKernelGGL(k_tmarg, dim3((unsigned)n), dim3(256), 2 * g.P * sizeof(double2), st,
-                     (const double*)ctx->tm_mom, n, g.n_blk, g.P, g.J,
-                     (const double2*)ctx->tm_tw, phi_step, (const double*)ctx->coef, n, ctx->dd, C, logl, zout,
-                     (double)(2 * ctx->geom.k0 + g.blk - 1), (double)(2 * g.N));
+                     (const double*)ctx->tm_mom, n, g.n_blk, g.P, g.J, g.R, (const double2*)ctx->tm_tw,
+                     (const double2*)ctx->tm_tw + g.P / 2, phi_step, (const double*)ctx->coef, n, ctx->dd, C, logl,
+                     zout, (double)(2 * ctx->geom.k0 + g.blk - 1), (double)(2 * g.N));
   return check_hip(hipGetLastError(), "time marginal launch");
 }
 
@@ -365,14 +379,22 @@ extern "C" gw_status gw_set_time_window(gw_ctx* ctx, double window) {
   return s;
 }
 
+extern "C" gw_status gw_set_time_oversample(gw_ctx* ctx, int32_t factor) {
+  if (!ctx) return gw::set_error(GW_EINVAL, "gw_set_time_oversample: ctx is NULL");
+  if (factor != 1 && factor != 2 && factor != 4 && factor != 8 && factor != 16)
+    return gw::set_error(GW_EINVAL, "gw_set_time_oversample: factor must be 1, 2, 4, 8 or 16");
+  ctx->tm_R = factor;
+  return GW_OK;
+}
+
 extern "C" gw_status gw_time_grid_info(const gw_ctx* ctx, double* delta, int32_t* n_points, int32_t* fft_len,
                                        int32_t* block_bins) {
   if (!ctx) return gw::set_error(GW_EINVAL, "gw_time_grid_info: ctx is NULL");
   gw::TimeGrid g;
   const gw_status s = gw::time_grid(ctx, &g);
   if (s != GW_OK) return s;
-  if (delta) *delta = g.delta;
-  if (n_points) *n_points = 2 * g.J + 1;
+  if (delta) *delta = g.delta / g.R;
+  if (n_points) *n_points = 2 * g.J * g.R + 1;
   if (fft_len) *fft_len = g.P;
   if (block_bins) *block_bins = g.blk;
   return GW_OK;

@@ -135,3 +135,30 @@ def test_heterodyned_split_matches_unsplit():
             err = np.max(np.abs(small - large[:len(th)]))
             print(f"prec {prec}: split vs unsplit max |dlogL| {err:.2e}")
             assert err < tol
+
+
+@pytest.mark.parametrize("factor", [1, 8])
+def test_oversampling_factors_against_oracle(factor, monkeypatch):
+    # the grid's oversampling (points per sampling interval) on both sides
+    import paper_2607_28265_amd as gw
+    from oracle import heterodyne as H
+    prob = problem("cfg1", loud=True)
+    th = np.concatenate([gwsynth.prior_draws(gwsynth.SEEDS["prior"], 8), near(prob, 16, 4, 1.0)])
+    monkeypatch.setattr(L, "TIME_OVERSAMPLE", factor)
+    ref = oracle_many(th, prob, L.PHASE_TIME)
+    het = H.setup(prob, prob.theta_inj, 200)
+    dd = L.data_inner(prob)
+    ref_het = np.array([H.loglike(t, prob, het, L.PHASE_TIME, dd) for t in th[:6]])
+    with gw.Context(prob) as ctx:
+        gw.gw_set_time_oversample(ctx.handle, factor)
+        delta, n_t, _, _ = gw.gw_time_grid_info(ctx.handle)
+        t = L.time_grid(prob)
+        assert n_t == t.size and delta == pytest.approx(t[1] - t[0], rel=1e-15)
+        err = np.max(np.abs(run(gw, ctx, th, gw.GW_PREC_FP64) - ref))
+        ctx.heterodyne_setup(prob.theta_inj, 200)
+        got = ctx.loglike(torch.from_numpy(th[:6]).cuda(), gw.GW_HET, gw.GW_MARG_PHASE_TIME, gw.GW_PREC_FP64)
+        err_het = np.max(np.abs(got.cpu().numpy() - ref_het))
+        print(f"oversampling {factor}: {n_t} points, full band {err:.2e}, heterodyned {err_het:.2e}")
+        assert err < 1e-6 and err_het < 1e-6
+        with pytest.raises(gw.GwError):
+            gw.gw_set_time_oversample(ctx.handle, 3)
