@@ -24,7 +24,7 @@
 //   k_tmom: per (proposal, block), the 16 moments M_bm (lane = proposal, the
 //           workgroup's waves walk the same block, wave-uniform bin records
 //           as in the full-band reduction);
-//   k_tmarg: one workgroup per proposal: for m = 15 .. 0, a P-point radix-2
+//   k_tmarg: one workgroup per proposal: for m = 15 .. 0, a P-point radix-4
 //           Stockham FFT of M_.m in LDS, folded into a Horner recurrence over
 //           m for every owned grid point; then ln I0(|Z|) and a fixed-order
 //           log-sum-exp.
@@ -194,17 +194,45 @@ __global__ void __launch_bounds__(256) k_tmarg(const double* __restrict__ mom, i
         buf[0][b] = v;
       }
       __syncthreads();
+      // Stockham FFT: radix-4 stages while they fit, then one radix-2 stage
+      // when log2 P is odd (twiddles w^t = exp(-2 pi i t / P), t < P / 2)
       int cur = 0;
-      for (int ns = 1; ns < P; ns <<= 1) {
-        for (int j = tid; j < P / 2; j += 256) {
-          const double2 v0 = buf[cur][j];
-          const double2 x1 = buf[cur][j + P / 2];
-          const int k = j & (ns - 1);
-          const double2 w = tw[k * (P / (2 * ns))];
-          const double v1r = x1.x * w.x - x1.y * w.y, v1i = x1.x * w.y + x1.y * w.x;
-          const int idx = ((j - k) << 1) + k;
-          buf[cur ^ 1][idx] = make_double2(v0.x + v1r, v0.y + v1i);
-          buf[cur ^ 1][idx + ns] = make_double2(v0.x - v1r, v0.y - v1i);
+      for (int ns = 1; ns < P;) {
+        const double2* __restrict__ src = buf[cur];
+        double2* __restrict__ dst = buf[cur ^ 1];
+        if (4 * ns <= P) {
+          const int q4 = P / 4, stp = P / (4 * ns);
+          for (int j = tid; j < q4; j += 256) {
+            const int k = j & (ns - 1);
+            const double2 w1 = tw[k * stp], w2 = tw[2 * k * stp];
+            const double2 w3 = make_double2(w1.x * w2.x - w1.y * w2.y, w1.x * w2.y + w1.y * w2.x);
+            const double2 a0 = src[j];
+            const double2 x1 = src[j + q4], x2 = src[j + 2 * q4], x3 = src[j + 3 * q4];
+            const double2 a1 = make_double2(x1.x * w1.x - x1.y * w1.y, x1.x * w1.y + x1.y * w1.x);
+            const double2 a2 = make_double2(x2.x * w2.x - x2.y * w2.y, x2.x * w2.y + x2.y * w2.x);
+            const double2 a3 = make_double2(x3.x * w3.x - x3.y * w3.y, x3.x * w3.y + x3.y * w3.x);
+            const double2 b0 = make_double2(a0.x + a2.x, a0.y + a2.y), b1 = make_double2(a0.x - a2.x, a0.y - a2.y);
+            const double2 b2 = make_double2(a1.x + a3.x, a1.y + a3.y);
+            const double2 b3 = make_double2(a1.y - a3.y, a3.x - a1.x);  // (a1 - a3) (-i)
+            const int idx = ((j - k) << 2) + k;
+            dst[idx] = make_double2(b0.x + b2.x, b0.y + b2.y);
+            dst[idx + ns] = make_double2(b1.x + b3.x, b1.y + b3.y);
+            dst[idx + 2 * ns] = make_double2(b0.x - b2.x, b0.y - b2.y);
+            dst[idx + 3 * ns] = make_double2(b1.x - b3.x, b1.y - b3.y);
+          }
+          ns *= 4;
+        } else {
+          for (int j = tid; j < P / 2; j += 256) {
+            const double2 v0 = src[j];
+            const double2 x1 = src[j + P / 2];
+            const int k = j & (ns - 1);
+            const double2 w = tw[k * (P / (2 * ns))];
+            const double v1r = x1.x * w.x - x1.y * w.y, v1i = x1.x * w.y + x1.y * w.x;
+            const int idx = ((j - k) << 1) + k;
+            dst[idx] = make_double2(v0.x + v1r, v0.y + v1i);
+            dst[idx + ns] = make_double2(v0.x - v1r, v0.y - v1i);
+          }
+          ns *= 2;
         }
         __syncthreads();
         cur ^= 1;
