@@ -268,12 +268,15 @@ constexpr double kInvInt[kWMom + 1] = {0.0,        1.0,        1.0 / 2,  1.0 / 3
                                        1.0 / 6,    1.0 / 7,    1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
                                        1.0 / 12,   1.0 / 13,   1.0 / 14, 1.0 / 15, 1.0 / 16};
 
-// k_wmom_build: Q = blk / L lanes per (listed slot, block, detector),
-// L = min(blk, 16) bins each (blk <= 512, so Q <= 32 lanes of one wave).  A
-// lane walks its bins (FP64 phase and sin/cos, FP64 moment sums); the Q
-// partial sums are added by lane exchange in a fixed order and the group's
-// first lane stores them.
-constexpr int kWMomLane = 16;  // bins per lane
+// k_wmom_build: a work unit is (block, group of kWBuildSlots listed slots),
+// units ordered so that neighbouring workgroups share a block (its records
+// stay in L2).  The unit's phasors g_sk (FP64 phase and sin/cos, one per slot
+// and bin, shared by the detectors) go to LDS; then lane (slot, detector,
+// part) sums the moments over L = blk / Q bins of its part (Q = min(16, blk)
+// parts, FP64), the Q partial sums are added by lane exchange in a fixed
+// order and the first lane of the group stores them.  Grid-stride over units:
+// the count is read on the device.
+constexpr int kWBuildSlots = 4;
 
 __global__ void __launch_bounds__(256) k_wmom_build(const double* __restrict__ coef, int64_t ld,
                                                     const int32_t* __restrict__ slots,
@@ -281,51 +284,64 @@ __global__ void __launch_bounds__(256) k_wmom_build(const double* __restrict__ c
                                                     const int32_t* __restrict__ src, const double* __restrict__ bins,
                                                     int rs, int n_freq, int nd, int blk, int n_blk, int64_t slot_f2,
                                                     TrigConsts T, float2* __restrict__ mom) {
+  __shared__ double2 g_lds[kWBuildSlots][512];  // blk <= 512
   const int cnt = *count;
-  const int L = blk < kWMomLane ? blk : kWMomLane;
-  const int Q = blk / L;  // power of two, <= 32
-  const int per = n_blk * nd;
-  const int64_t items = (int64_t)cnt * per * Q;
+  const int ngrp = (cnt + kWBuildSlots - 1) / kWBuildSlots;
+  const int64_t units = (int64_t)n_blk * ngrp;
+  const int Q = blk < 16 ? blk : 16;  // power of two: parts per (slot, detector)
+  const int L = blk / Q;
+  const int tid = threadIdx.x;
+  const int part = tid % Q, combo = tid / Q;
+  const int s_me = combo / nd, i_me = combo - (combo / nd) * nd;
+  const bool lane_on = s_me < kWBuildSlots;  // Q kWBuildSlots nd <= 256 for nd <= 4
   const double cen = 0.5 * (blk - 1), hinv = 2.0 / blk;
-  // whole waves iterate together (the lane exchange needs every part)
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t it0 = (int64_t)blockIdx.x * blockDim.x; it0 < items; it0 += stride) {
-    const int64_t it = it0 + threadIdx.x;
-    const bool act = it < items;
-    const int64_t item = act ? it / Q : 0;
-    const int part = (int)(it - (it / Q) * Q);
-    const int li = (int)(item / per), rem = (int)(item - (int64_t)li * per);
-    const int64_t sl = act ? slots[li] : -1;
-    const int b = rem / nd, i = rem - b * nd;
+  for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
+    const int b = (int)(unit / ngrp), grp = (int)(unit - (int64_t)b * ngrp);
+    const int kb = b * blk;
+    const int nbin = kb + blk < n_freq ? blk : n_freq - kb;
+    for (int e = tid; e < kWBuildSlots * blk; e += blockDim.x) {
+      const int s = e / blk, k = e - (e / blk) * blk;
+      const int li = grp * kWBuildSlots + s;
+      double2 g = make_double2(0.0, 0.0);
+      if (li < cnt && k < nbin && slots[li] >= 0) {
+        const int64_t r = src ? (int64_t)src[li] : (int64_t)slots[li] * rows_per_slot;
+        PhaseCoef c;
+        c.a0 = coef[C_A0 * ld + r];
+        c.a2 = coef[C_A2 * ld + r];
+        c.a3 = coef[C_A3 * ld + r];
+        c.a4 = coef[C_A4 * ld + r];
+        c.a5 = coef[C_A5 * ld + r];
+        c.a6 = coef[C_A6 * ld + r];
+        c.a7 = coef[C_A7 * ld + r];
+        c.a8 = 0.0;  // the linear time term is applied per row
+        c.a10 = coef[C_A10 * ld + r];
+        c.a12 = coef[C_A12 * ld + r];
+        c.b5 = coef[C_B5 * ld + r];
+        c.b6 = coef[C_B6 * ld + r];
+        const double* rec = bins + (int64_t)(kb + k) * rs;
+        const double ph = phase_cycles(c, rec[0], rec[1], rec[2], rec[3]);
+        double sn, cs;
+        sincos_cycles(ph, T, &sn, &cs);
+        g = make_double2(cs, sn);
+      }
+      g_lds[s][k] = g;
+    }
+    __syncthreads();
+    const int li = grp * kWBuildSlots + s_me;
+    const int64_t sl = lane_on && li < cnt ? slots[li] : -1;
     double mr[kWMom], mi[kWMom];
 #pragma unroll
     for (int m = 0; m < kWMom; ++m) mr[m] = mi[m] = 0.0;
     if (sl >= 0) {
-      const int64_t r = src ? (int64_t)src[li] : sl * rows_per_slot;
-      PhaseCoef c;
-      c.a0 = coef[C_A0 * ld + r];
-      c.a2 = coef[C_A2 * ld + r];
-      c.a3 = coef[C_A3 * ld + r];
-      c.a4 = coef[C_A4 * ld + r];
-      c.a5 = coef[C_A5 * ld + r];
-      c.a6 = coef[C_A6 * ld + r];
-      c.a7 = coef[C_A7 * ld + r];
-      c.a8 = 0.0;  // the linear time term is applied per row
-      c.a10 = coef[C_A10 * ld + r];
-      c.a12 = coef[C_A12 * ld + r];
-      c.b5 = coef[C_B5 * ld + r];
-      c.b6 = coef[C_B6 * ld + r];
-      const int kb = b * blk, k1 = kb + part * L;
-      const int k2 = k1 + L < n_freq ? k1 + L : n_freq;
+      const int k1 = part * L;
+      const int k2 = k1 + L < nbin ? k1 + L : nbin;
       for (int k = k1; k < k2; ++k) {
-        const double* rec = bins + (int64_t)k * rs;
-        const double ph = phase_cycles(c, rec[0], rec[1], rec[2], rec[3]);
-        double sn, cs;
-        sincos_cycles(ph, T, &sn, &cs);
-        const double ur = rec[4 + 2 * i], ui = rec[5 + 2 * i];
-        // w = u g with g = cs - i sn
-        const double wr = ur * cs + ui * sn, wi = ui * cs - ur * sn;
-        const double t = ((double)(k - kb) - cen) * hinv;
+        const double2 g = g_lds[s_me][k];
+        const double* rec = bins + (int64_t)(kb + k) * rs;
+        const double ur = rec[4 + 2 * i_me], ui = rec[5 + 2 * i_me];
+        // w = u g with g = cos - i sin
+        const double wr = ur * g.x + ui * g.y, wi = ui * g.x - ur * g.y;
+        const double t = ((double)k - cen) * hinv;
         double tp = 1.0;
 #pragma unroll
         for (int m = 0; m < kWMom; ++m) {
@@ -344,10 +360,11 @@ __global__ void __launch_bounds__(256) k_wmom_build(const double* __restrict__ c
       }
     }
     if (sl >= 0 && part == 0) {
-      float2* __restrict__ out = mom + sl * slot_f2 + ((int64_t)b * nd + i) * kWMom;
+      float2* __restrict__ out = mom + sl * slot_f2 + ((int64_t)b * nd + i_me) * kWMom;
 #pragma unroll
       for (int m = 0; m < kWMom; ++m) out[m] = make_float2((float)mr[m], (float)mi[m]);
     }
+    __syncthreads();  // before the next unit overwrites the phasors
   }
 }
 

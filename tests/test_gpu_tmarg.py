@@ -162,3 +162,21 @@ def test_oversampling_factors_against_oracle(factor, monkeypatch):
         assert err < 1e-6 and err_het < 1e-6
         with pytest.raises(gw.GwError):
             gw.gw_set_time_oversample(ctx.handle, 3)
+
+
+def test_odd_power_fft_length(monkeypatch):
+    # a 0.05 s window gives 103 points per sub-grid and an FFT of 128 points
+    # (radix-4 stages and one radix-2 stage); the default grids use 256 and
+    # 1024 (radix-4 only)
+    import paper_2607_28265_amd as gw
+    prob = problem("cfg1", loud=True)
+    th = np.concatenate([gwsynth.prior_draws(gwsynth.SEEDS["prior"], 8), near(prob, 16, 6, 1.0)])
+    monkeypatch.setattr(L, "TIME_WINDOW", 0.05)
+    ref = oracle_many(th, prob, L.PHASE_TIME)
+    with gw.Context(prob) as ctx:
+        gw.gw_set_time_window(ctx.handle, 0.05)
+        delta, n_t, p_len, blk = gw.gw_time_grid_info(ctx.handle)
+        assert p_len == 128 and n_t == L.time_grid(prob).size
+        err = np.max(np.abs(run(gw, ctx, th, gw.GW_PREC_FP64) - ref))
+        print(f"window 0.05 s: FFT {p_len}, {n_t} points, max |dlogL| {err:.2e}")
+        assert err < 1e-6
