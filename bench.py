@@ -40,9 +40,9 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector, dense
 # (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.000): k_full<3, 1, false> at
 # 4096 x 259,585, and k_wmom<3> at 4096 rows on 2048 cached slots.  Valid only
 # for the kernel sources they were taken on (hash below).
-TRAFFIC = {"sources_sha256": "4908f7f52157efd3dacbe68c498ba2866c26f969e0cdf9d3267de25700568f25",
-           "k_full": {"read_bytes": 22306.09 * 1.99981 * 1024, "write_bytes": 24576.0 * 1024},
-           "k_wmom": {"read_bytes": 397453.8 * 1.99981 * 1024, "write_bytes": 23040.0 * 1024}}
+TRAFFIC = {"sources_sha256": "96f02aa2df65653b43e500d894bc7419a2985573123caf30ce6757dd33ba7391",
+           "k_full": {"read_bytes": 22150.82 * 1.99981 * 1024, "write_bytes": 24576.0 * 1024},
+           "k_wmom": {"read_bytes": 397443.9 * 1.99981 * 1024, "write_bytes": 23040.0 * 1024}}
 TRAFFIC_SOURCES = ("paper_2607_28265_amd/csrc/gw_full.hip", "paper_2607_28265_amd/csrc/gw_device.h")
 
 

@@ -941,7 +941,7 @@ __global__ void __launch_bounds__(256) k_het_tfinal(const double* __restrict__ z
                                                     const double* __restrict__ coef, int64_t ld, int64_t n, int nt,
                                                     int nsk, double dd, LogI0Consts C, double* __restrict__ logl,
                                                     double* __restrict__ zout) {
-  __shared__ double red[256];
+  __shared__ double red[256], red2[256];
   const int64_t p = blockIdx.x;
   const int tid = threadIdx.x;
   const double h0 = hhc[p];
@@ -956,27 +956,37 @@ __global__ void __launch_bounds__(256) k_het_tfinal(const double* __restrict__ z
       o[2] = h0 + hr;
     }
   }
-  double mx = -INFINITY;
-  for (int j = tid; j < nt; j += 256) mx = fmax(mx, het_tgrid_value(zh, n, nt, nsk, p, j, h0, C));
-  red[tid] = mx;
+  // one pass: each thread keeps a running maximum m and the sum s of
+  // exp(v - m) over its grid points, rescaled when m grows; the pairs are
+  // then merged across the workgroup
+  double m = -INFINITY, acc = 0.0;
+  for (int j = tid; j < nt; j += 256) {
+    const double v = het_tgrid_value(zh, n, nt, nsk, p, j, h0, C);
+    if (v > m) {
+      acc = acc * exp(m - v) + 1.0;
+      m = v;
+    } else if (!(v == -INFINITY)) {  // NaN still propagates
+      acc += exp(v - m);
+    }
+  }
+  red[tid] = m;
+  red2[tid] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    if (tid < s) {
+      const double ma = red[tid], mb = red[tid + s];
+      const double mm = fmax(ma, mb);
+      if (mm > -INFINITY) {
+        red2[tid] = red2[tid] * exp(ma - mm) + red2[tid + s] * exp(mb - mm);
+        red[tid] = mm;
+      }
+    }
     __syncthreads();
   }
   const double ref = red[0];
-  __syncthreads();
-  double acc = 0.0;
-  for (int j = tid; j < nt; j += 256) acc += exp(het_tgrid_value(zh, n, nt, nsk, p, j, h0, C) - ref);
-  red[tid] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
   if (tid == 0) {
     const bool valid = coef[C_VALID * ld + p] != 0.0;
-    logl[p] = valid ? -0.5 * dd + ref + log(red[0]) - log((double)nt) : -INFINITY;
+    logl[p] = valid ? -0.5 * dd + ref + log(red2[0]) - log((double)nt) : -INFINITY;
   }
 }
 
