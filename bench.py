@@ -27,12 +27,37 @@ if ROOT not in sys.path:
 METRIC = "logL evals/sec (full-band & heterodyned) vs FP64 plain at |dlogL|<1e-3"
 
 # Algorithmic FP64 flops per (proposal, frequency bin) of the fused kernel, FMA
-# counted as 2: TaylorF2 phase by Horner in f^(1/3) (11 FMA + 1 mul = 23),
-# reduction to a fraction of a cycle (1), detector-0 complex MAC (4 FMA = 8),
-# two detectors' rotation-Horner steps (2 x (2 mul + 6 FMA) = 28).  The FP64
-# form adds the FP64 sin/cos polynomial (47).  The FP32 sin/cos of the mixed
-# form are not counted as FP64 flops.
-FLOPS_PER_BIN = {"mixed": 60.0, "fp64": 107.0}
+# counted as 2.  FP64 form: TaylorF2 phase by Horner in f^(1/3) (11 FMA + 1 mul
+# = 23), reduction to a fraction of a cycle (1), detector-0 complex MAC (4 FMA
+# = 8), two detectors' rotation-Horner steps (2 x (2 mul + 6 FMA) = 28), and
+# the FP64 sin/cos polynomial (47): 107.  Mixed form: the phase comes from a
+# cubic recurrence in runs of bins (gw_full_phase_runs): a recurrence bin
+# costs 3 additions, a directly evaluated one (the first four of a run, and
+# every bin below the lowest level) the phase without its constant and
+# linear terms (9 FMA + 3 mul = 21), the linear term (1 mul + 1 FMA = 3), the
+# difference update (3) and the sum (1); both then add 1 + 8 + 28.  The FP32
+# sin/cos of the mixed form are not counted as FP64 flops.
+FLOPS_PER_BIN = {"fp64": 107.0, "mixed_recurrence": 40.0, "mixed_direct": 65.0}
+
+
+def mixed_flops_per_bin(gw, ctx, n_freq):
+    """Average mixed-form flops per bin over the band.  Runs are aligned
+    blocks, and a chunk that starts inside one also re-evaluates the run's
+    first bins, which adds under 0.2 % at 128 chunks and is not counted."""
+    k_min, lens = gw.gw_full_phase_runs(ctx.handle)
+    direct, k = 0, n_freq - 1
+    while k >= 0:
+        run, s = 0, 0
+        for km, ln in zip(k_min, lens):
+            if k & ~(ln - 1) >= km:
+                run, s = ln, k & ~(ln - 1)
+                break
+        if run == 0:  # every lower bin is evaluated directly
+            direct += k + 1
+            break
+        direct += min(min(s + run - 1, n_freq - 1) - s + 1, 4)
+        k = s - 1
+    return (FLOPS_PER_BIN["mixed_recurrence"] * (n_freq - direct) + FLOPS_PER_BIN["mixed_direct"] * direct) / n_freq
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector, dense
 
 # HBM bytes per launch from two rocprofv3 PMC runs (FETCH_SIZE, WRITE_SIZE)
@@ -40,9 +65,9 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector, dense
 # (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.000): k_full<3, 1, false> at
 # 4096 x 259,585, and k_wmom<3> at 4096 rows on 2048 cached slots.  Valid only
 # for the kernel sources they were taken on (hash below).
-TRAFFIC = {"sources_sha256": "96f02aa2df65653b43e500d894bc7419a2985573123caf30ce6757dd33ba7391",
-           "k_full": {"read_bytes": 22150.82 * 1.99981 * 1024, "write_bytes": 24576.0 * 1024},
-           "k_wmom": {"read_bytes": 397443.9 * 1.99981 * 1024, "write_bytes": 23040.0 * 1024}}
+TRAFFIC = {"sources_sha256": "218bf79004afcdf1a18728ed8ea21f3080492adada04c8d7ea0d687c9c909718",
+           "k_full": {"read_bytes": 22345.68 * 1.99981 * 1024, "write_bytes": 24576.0 * 1024},
+           "k_wmom": {"read_bytes": 397433.5 * 1.99981 * 1024, "write_bytes": 23040.0 * 1024}}
 TRAFFIC_SOURCES = ("paper_2607_28265_amd/csrc/gw_full.hip", "paper_2607_28265_amd/csrc/gw_device.h")
 
 
@@ -585,6 +610,7 @@ def main():
         dt_fp, k_fp = time_steps(ctx, theta, out, fp_steps, 2, gw.GW_PREC_FP64, marg, torch, gw, profile=True)
         fp = out.clone()
         dlogl = float(torch.max(torch.abs(mix - fp)).item())
+        fpb_mixed = mixed_flops_per_bin(gw, ctx, int(prob.n_freq))
         tm = None
         if "tmarg" in set(args.legs.split(",")):
             tm = tmarg_leg(gw, torch, ctx, theta, max(5, args.steps // 2), 2, n * args.steps / dt_mix)
@@ -594,7 +620,7 @@ def main():
     value = n * args.steps / dt_mix
     fp_value = n * fp_steps / dt_fp
     units = n * prob.n_freq
-    ach = FLOPS_PER_BIN["mixed"] * units / (k_mix * 1e-3) / 1e12
+    ach = fpb_mixed * units / (k_mix * 1e-3) / 1e12
     ach_fp = FLOPS_PER_BIN["fp64"] * units / (k_fp * 1e-3) / 1e12
     res = {
         "metric": METRIC,
@@ -611,8 +637,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "full-band BNS likelihood: TaylorF2 3.5PN aligned-spin+tidal, 3 detectors, "
                                "T=128 s, 20-2048 Hz, df=1/128 Hz (259,585 bins/detector), batch 4096 prior "
-                               "draws, phase+distance marginalised; mixed form (FP64 phase, FP32 sin/cos, "
-                               "FP64 sums)",
+                               "draws, phase+distance marginalised; mixed form (FP64 phase by a cubic "
+                               "recurrence in runs of bins, FP32 sin/cos, FP64 sums)",
                    "batch": n, "n_freq": int(prob.n_freq), "n_det": 3, "marg": "phase+distance",
                    "prec": "mixed"},
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
@@ -620,7 +646,7 @@ def main():
                      "hbm_gbs": (traffic_bytes() / (k_mix * 1e-3) / 1e9) if traffic_bytes() else None,
                      "hbm_peak_gbs": 8000.0,
                      "kernel": "k_full<3,1> (mixed)", "kernel_ms": k_mix,
-                     "flops_per_launch": FLOPS_PER_BIN["mixed"] * units},
+                     "flops_per_launch": fpb_mixed * units, "flops_per_bin": fpb_mixed},
         "fp64_plain": {"value": fp_value, "ms_per_step": dt_fp / fp_steps * 1e3, "kernel_ms": k_fp,
                        "roofline_frac": ach_fp / PEAK_FP64_TFLOPS},
         "speedup_vs_fp64": value / fp_value,

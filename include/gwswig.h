@@ -605,6 +605,20 @@ gw_status gw_set_full_kernel(gw_ctx* ctx, int32_t kind);
 /* Block length B of the matrix-core form (0 when the detectors are too far
  * apart for a block of 8 bins at this frequency spacing). */
 gw_status gw_full_info(const gw_ctx* ctx, int32_t* mom_blk);
+/*
+ * Phase recurrence of the vector-ALU mixed reduction.  The TaylorF2 phase
+ * (Sec. III.A) is evaluated over runs of bins: bin k lies in the run
+ * [s, s + len[j] - 1], s = k rounded down to a multiple of len[j], for the
+ * first level j (0..3; len descending powers of two) with s >= k_min[j], and
+ * in no run (phase evaluated directly) if there is none.  A run evaluates the
+ * phase directly on its top four bins and continues downwards with a cubic
+ * finite-difference recurrence, three additions per bin; the levels keep the
+ * recurrence's extrapolation error below 2e-8 cycles for chirp masses down
+ * to 0.8 Msun.  A bin's phase depends only on its run, so results do not
+ * depend on the launch shape beyond summation order.  Fills four entries of
+ * each non-NULL output.  The FP64 form evaluates every bin directly.
+ */
+gw_status gw_full_phase_runs(const gw_ctx* ctx, int32_t* k_min, int32_t* len);
 
 /*
  * Correction factor 1 / (1 + b) applied to the mixed full-band sums, where b

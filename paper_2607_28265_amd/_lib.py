@@ -149,6 +149,7 @@ _SIGS = {
     "gw_prior_transform_marg": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P]),
     "gw_set_full_kernel": (ctypes.c_int, [_P, ctypes.c_int32]),
     "gw_full_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "gw_full_phase_runs": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "gw_phasor_gain": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "gw_mlp_create": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_P)]),
     "gw_mlp_destroy": (ctypes.c_int, [_P]),
@@ -308,6 +309,14 @@ def gw_set_full_shape(ctx, tpb: int, n_chunks: int):
 
 def gw_set_full_kernel(ctx, kind: int):
     check(load().gw_set_full_kernel(ctx, kind), "gw_set_full_kernel")
+
+
+def gw_full_phase_runs(ctx):
+    """(k_min, len): the run levels of the mixed reduction's phase recurrence."""
+    k = (ctypes.c_int32 * 4)()
+    n = (ctypes.c_int32 * 4)()
+    check(load().gw_full_phase_runs(ctx, k, n), "gw_full_phase_runs")
+    return list(k), list(n)
 
 
 def gw_full_info(ctx) -> int:

@@ -9,7 +9,9 @@
 // weighted data u_ik = 4 df d_ik* f^(-7/6) / S_ik) are wave-uniform and are
 // fetched with scalar loads into SGPRs; the proposal's phase coefficients live
 // in VGPRs.  Per bin a lane evaluates the TaylorF2 phase in FP64 (Horner in
-// x = f^(1/3)), one complex phasor exp(-i Phi_0) for detector 0, and folds the
+// x = f^(1/3); the mixed form only on the first bins of each run and by a
+// cubic recurrence in between, see PhaseRuns), one complex phasor
+// exp(-i Phi_0) for detector 0, and folds the
 // other detectors' linear time-shift phases into a Horner recurrence over the
 // bins of the chunk: S_i <- S_i rho_i + u_ik g_k with rho_i = exp(-2 pi i df
 // (tau_i - tau_0)), which is multiplied by exp(-2 pi i f_start (tau_i - tau_0))
@@ -87,6 +89,71 @@ __device__ inline void phasor(double r, const TrigConsts& T, double* gr, double*
   }
 }
 
+// Mixed form: the phase along the descending bin walk by a cubic recurrence.
+// The phase in cycles is lin(f) + nl(f), lin = a5 + a8 f the constant and
+// linear terms and nl the rest of the TaylorF2 series.  A run of L bins
+// evaluates nl directly on its first four bins, which fixes the backward
+// differences n0..n3 of nl at the fourth; every later bin then costs three
+// additions (p2 += p3, p1 += p2, p0 += p1) on the table of the full phase,
+// whose first difference also carries the linear term's step -a8 df.  The
+// cubic's extrapolation error over a run is at most |d^4 nl / df^4| / 4!
+// (L df)^4, and rounding grows with the third difference's error times
+// C(L, 3), so L is limited by both: the host picks, per frequency, the
+// longest of 64, 32, 16 and 8 bins that keeps the extrapolation bound below
+// 2e-8 cycles for chirp masses down to 0.8 Msun (the rounding bound,
+// C(64, 3) 8 eps |nl|, stays below it too), and below that frequency every
+// bin is evaluated directly.  Runs are aligned blocks: bin k lies in the run
+// [s, s + len[j] - 1], s = k rounded down to a multiple of len[j], for the
+// first level j (len descending, powers of two) with s >= k_min[j]; a run's
+// directly evaluated bins are its top ones (the walk descends), and the
+// band's top run may be cut at the last bin.  Bins in no run are evaluated
+// directly.  A bin's phase thus depends on its run alone, not on how the
+// walk is split into chunks.
+struct PhaseRuns {
+  int k_min[4];
+  int len[4];
+};
+
+// nl(f): the phase without the constant (a5) and linear (a8) terms.
+__device__ inline double phase_nonlinear(const PhaseCoef& c, double x, double x2, double xm5, double lnf) {
+  double t = fma(x2, c.a12, c.a10);
+  t = x2 * t;
+  t = fma(x, t, c.a7);
+  t = fma(x, t, c.a6);
+  t = x * t;
+  t = fma(x, t, c.a4);
+  t = fma(x, t, c.a3);
+  t = fma(x, t, c.a2);
+  t = fma(x2, t, c.a0);
+  const double lg = fma(c.b6, x, c.b5);
+  return fma(lg, lnf, t * xm5);
+}
+
+// Run levels for a segment of bin spacing df starting at bin k0.  The bound
+// on the fourth derivative uses the leading term of the phase,
+// |nl| <= A (f / 20 Hz)^(-5/3) with A = 11,500 cycles (the Newtonian phase
+// of a 0.8 Msun chirp mass at 20 Hz, about 3,800 cycles, times three for the
+// post-Newtonian terms); its fourth derivative is
+// (5/3)(8/3)(11/3)(14/3) |nl| / f^4.
+static PhaseRuns make_phase_runs(const Geom& g) {
+  const double tol = 2e-8, amp = 11500.0;
+  const double c4 = (5.0 / 3.0) * (8.0 / 3.0) * (11.0 / 3.0) * (14.0 / 3.0) / 24.0;
+  PhaseRuns R;
+  const int lens[4] = {64, 32, 16, 8};
+  for (int j = 0; j < 4; ++j) {
+    const double span = lens[j] * g.df;
+    // c4 amp (f/20)^(-5/3) span^4 / f^4 <= tol  <=>  f^(17/3) >= c4 amp 20^(5/3) span^4 / tol
+    const double fmin = pow(c4 * amp * pow(20.0, 5.0 / 3.0) * span * span * span * span / tol, 3.0 / 17.0);
+    // the run's lowest bin must lie at or above fmin
+    double kmin = ceil(fmin / g.df) - (double)g.k0;
+    if (kmin < 0.0) kmin = 0.0;
+    if (kmin > (double)g.n_freq) kmin = (double)g.n_freq;
+    R.k_min[j] = (int)kmin;
+    R.len[j] = lens[j];
+  }
+  return R;
+}
+
 // LIST (small batches, e.g. the sampler's rounds): the rows are
 // rows[0 .. *count) (at most n, in any order) instead of 0 .. n - 1, 64 to a
 // workgroup, and the workgroup's waves split the chunk's bins between them
@@ -95,8 +162,8 @@ __device__ inline void phasor(double r, const TrigConsts& T, double* gr, double*
 template <int ND, int PREC, bool LIST>
 __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, int64_t ld, int64_t n,
                                               const double* __restrict__ bins, int64_t k0, double df,
-                                              int n_freq, int chunk_len, int n_chunks, TrigConsts T, double pg_re,
-                                              double pg_im, const int32_t* __restrict__ rows,
+                                              int n_freq, int chunk_len, int n_chunks, TrigConsts T, PhaseRuns R,
+                                              double pg_re, double pg_im, const int32_t* __restrict__ rows,
                                               const int32_t* __restrict__ count, double* __restrict__ partial) {
   constexpr int RS = 4 + 2 * ND;
   const int tpb = LIST ? 64 : blockDim.x;
@@ -164,12 +231,9 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
   // Descending walk so that the Horner recurrence leaves rho^0 on the first
   // bin.  Records alternate between two register sets: while one bin is
   // processed the next one's record is already in flight.
-  auto step = [&](const double* __restrict__ rec) {
-    const double r = phase_cycles(c, rec[0], rec[1], rec[2], rec[3]);
-    double gr, gi;
-    phasor<PREC>(r, T, &gr, &gi);
+  auto accumulate = [&](const double* __restrict__ u, double gr, double gi) {
     {
-      const double ur = rec[4], ui = rec[5];
+      const double ur = u[0], ui = u[1];
       zr[0] = fma(ur, gr, zr[0]);
       zr[0] = fma(-ui, gi, zr[0]);
       zi[0] = fma(ur, gi, zi[0]);
@@ -177,7 +241,7 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
     }
 #pragma unroll
     for (int i = 1; i < ND; ++i) {
-      const double ur = rec[4 + 2 * i], ui = rec[5 + 2 * i];
+      const double ur = u[2 * i], ui = u[2 * i + 1];
       double tr = zr[i] * rr[i];
       tr = fma(-zi[i], ri[i], tr);
       tr = fma(ur, gr, tr);
@@ -190,22 +254,125 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
       zi[i] = ti;
     }
   };
-  if (ke > kb) {
-    double ra[RS], rb[RS];
+  if constexpr (PREC == 0) {
+    auto step = [&](const double* __restrict__ rec) {
+      const double r = phase_cycles(c, rec[0], rec[1], rec[2], rec[3]);
+      double gr, gi;
+      phasor<PREC>(r, T, &gr, &gi);
+      accumulate(rec + 4, gr, gi);
+    };
+    if (ke > kb) {
+      double ra[RS], rb[RS];
 #pragma unroll
-    for (int j = 0; j < RS; ++j) ra[j] = bins[(int64_t)(ke - 1) * RS + j];
+      for (int j = 0; j < RS; ++j) ra[j] = bins[(int64_t)(ke - 1) * RS + j];
+      int k = ke - 1;
+      while (true) {
+        const int k1 = k - 1 >= kb ? k - 1 : kb;
+#pragma unroll
+        for (int j = 0; j < RS; ++j) rb[j] = bins[(int64_t)k1 * RS + j];
+        step(ra);
+        if (--k < kb) break;
+        const int k2 = k - 1 >= kb ? k - 1 : kb;
+#pragma unroll
+        for (int j = 0; j < RS; ++j) ra[j] = bins[(int64_t)k2 * RS + j];
+        step(rb);
+        if (--k < kb) break;
+      }
+    }
+  } else {
+    // runs of the cubic phase recurrence (see PhaseRuns).  A walk that
+    // starts inside a run (a chunk, or a wave's share of one) first advances
+    // the run's table down to its own first bin without accumulating.
+    const double lin_step = -c.a8 * df;  // linear phase change per bin of the descending walk
+    constexpr int US = 2 * ND;
     int k = ke - 1;
-    while (true) {
-      const int k1 = k - 1 >= kb ? k - 1 : kb;
+    while (k >= kb) {
+      int L = 0, s = 0;
 #pragma unroll
-      for (int j = 0; j < RS; ++j) rb[j] = bins[(int64_t)k1 * RS + j];
-      step(ra);
-      if (--k < kb) break;
-      const int k2 = k - 1 >= kb ? k - 1 : kb;
+      for (int j = 0; j < 4; ++j) {
+        const int sj = k & ~(R.len[j] - 1);
+        if (L == 0 && sj >= R.k_min[j]) {
+          L = R.len[j];
+          s = sj;
+        }
+      }
+      if (L == 0) {
+        // below the lowest level: every bin evaluated directly
+        const int nd = k - kb + 1 < 4 ? k - kb + 1 : 4;
 #pragma unroll
-      for (int j = 0; j < RS; ++j) ra[j] = bins[(int64_t)k2 * RS + j];
-      step(rb);
-      if (--k < kb) break;
+        for (int j = 0; j < 4; ++j) {
+          if (j < nd) {
+            const double* __restrict__ rc = bins + (int64_t)(k - j) * RS;
+            const double r = phase_nonlinear(c, rc[0], rc[1], rc[2], rc[3]) + fma(c.a8, rc[0] * rc[1], c.a5);
+            double gr, gi;
+            phasor<PREC>(r, T, &gr, &gi);
+            accumulate(rc + 4, gr, gi);
+          }
+        }
+        k -= nd;
+        continue;
+      }
+      const int top = s + L - 1 < n_freq - 1 ? s + L - 1 : n_freq - 1;
+      const int nd = top - s + 1 < 4 ? top - s + 1 : 4;
+      // the run's first (up to) four bins, evaluated directly; their
+      // nonlinear parts build the backward differences n0..n3
+      double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0, lin = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j < nd) {
+          const int kk = top - j;
+          const double* __restrict__ rc = bins + (int64_t)kk * RS;
+          const double nl = phase_nonlinear(c, rc[0], rc[1], rc[2], rc[3]);
+          lin = fma(c.a8, rc[0] * rc[1], c.a5);
+          const double d1 = nl - n0;
+          const double d2 = d1 - n1;
+          n3 = d2 - n2;
+          n2 = d2;
+          n1 = d1;
+          n0 = nl;
+          if (kk <= k && kk >= kb) {
+            double gr, gi;
+            phasor<PREC>(nl + lin, T, &gr, &gi);
+            accumulate(rc + 4, gr, gi);
+          }
+        }
+      }
+      const int lo = s > kb ? s : kb;  // the run's last bin in this walk
+      int kk = top - nd;
+      if (kk >= lo) {
+        // the remaining bins from the table of the full phase
+        double p0 = n0 + lin, p1 = n1 + lin_step, p2 = n2;
+        const double p3 = n3;
+        for (; kk > k; --kk) {  // above the walk's first bin: advance only
+          p2 += p3;
+          p1 += p2;
+          p0 += p1;
+        }
+        auto step = [&](const double* __restrict__ u) {
+          p2 += p3;
+          p1 += p2;
+          p0 += p1;
+          double gr, gi;
+          phasor<PREC>(p0, T, &gr, &gi);
+          accumulate(u, gr, gi);
+        };
+        double ua[US], ub[US];
+#pragma unroll
+        for (int j = 0; j < US; ++j) ua[j] = bins[(int64_t)kk * RS + 4 + j];
+        while (true) {
+          const int k1 = kk - 1 >= lo ? kk - 1 : lo;
+#pragma unroll
+          for (int j = 0; j < US; ++j) ub[j] = bins[(int64_t)k1 * RS + 4 + j];
+          step(ua);
+          if (--kk < lo) break;
+          const int k2 = kk - 1 >= lo ? kk - 1 : lo;
+#pragma unroll
+          for (int j = 0; j < US; ++j) ua[j] = bins[(int64_t)k2 * RS + 4 + j];
+          step(ub);
+          if (--kk < lo) break;
+        }
+      }
+      k = s - 1;
     }
   }
   // Apply exp(-2 pi i f_kb (tau_i - tau_0)) to the recurrences.
@@ -944,15 +1111,16 @@ static gw_status launch_full_nd(gw_ctx* ctx, const double* coef, int64_t ld, int
   const int nf = (int)ctx->geom.n_freq;
   const int chunk_len = (int)((nf + n_chunks - 1) / n_chunks);
   const TrigConsts T = make_trig_consts();
+  const PhaseRuns PR = make_phase_runs(ctx->geom);
   const int64_t nptile = (n + tpb - 1) / tpb;
   const int64_t blocks = nptile * n_chunks;
   if (blocks > 0x7fffffff) return set_error(GW_EINVAL, "batch too large for one launch");
   if (prec == GW_PREC_FP64) {
     hipLaunchKernelGGL((k_full<ND, 0, false>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
-                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, 1.0, 0.0, nullptr, nullptr, partial);
+                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, PR, 1.0, 0.0, nullptr, nullptr, partial);
   } else {
     hipLaunchKernelGGL((k_full<ND, 1, false>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
-                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, ctx->pgain_re, ctx->pgain_im,
+                       ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, PR, ctx->pgain_re, ctx->pgain_im,
                        nullptr, nullptr, partial);
   }
   return check_hip(hipGetLastError(), "full-band kernel launch");
@@ -1193,6 +1361,7 @@ static gw_status launch_cached_nd(gw_ctx* ctx, const double* coef, int64_t n, in
                                   double* partial, hipStream_t st) {
   const int nf = (int)ctx->geom.n_freq;
   const TrigConsts T = make_trig_consts();
+  const PhaseRuns PR = make_phase_runs(ctx->geom);
   const int64_t nptile = (n + 63) / 64;  // 64 rows per workgroup; tpb / 64 waves split each chunk
   const int64_t blocks = nptile * n_chunks;
   if (blocks > 0x7fffffff) return set_error(GW_EINVAL, "batch too large for one launch");
@@ -1201,10 +1370,10 @@ static gw_status launch_cached_nd(gw_ctx* ctx, const double* coef, int64_t n, in
   if (slow_rows) {
     if (prec == GW_PREC_FP64)
       hipLaunchKernelGGL((k_full<ND, 0, true>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, n, n, ctx->bins,
-                         ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, 1.0, 0.0, slow_rows, counts, partial);
+                         ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, PR, 1.0, 0.0, slow_rows, counts, partial);
     else
       hipLaunchKernelGGL((k_full<ND, 1, true>), dim3((unsigned)blocks), dim3(tpb), 0, st, coef, n, n, ctx->bins,
-                         ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, ctx->pgain_re, ctx->pgain_im,
+                         ctx->geom.k0, ctx->geom.df, nf, chunk_len, n_chunks, T, PR, ctx->pgain_re, ctx->pgain_im,
                          slow_rows, counts, partial);
     s = check_hip(hipGetLastError(), "full-band list kernel launch");
   }
@@ -1266,3 +1435,13 @@ gw_status launch_template(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n
 }
 
 }  // namespace gw
+
+extern "C" gw_status gw_full_phase_runs(const gw_ctx* ctx, int32_t* k_min, int32_t* len) {
+  if (!ctx) return gw::set_error(GW_EINVAL, "gw_full_phase_runs: ctx is NULL");
+  const gw::PhaseRuns R = gw::make_phase_runs(ctx->geom);
+  for (int j = 0; j < 4; ++j) {
+    if (k_min) k_min[j] = R.k_min[j];
+    if (len) len[j] = R.len[j];
+  }
+  return GW_OK;
+}
