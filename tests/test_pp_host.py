@@ -1,6 +1,7 @@
 """Host logic of the injection-campaign driver against the oracle (no GPU):
 the driver's unit-cube inverse and truth draws in both sky frames, and its
-credible levels and p-values on synthetic samples."""
+credible levels and p-values on synthetic samples; the event pipeline's
+weighted posterior summary."""
 import math
 
 import numpy as np
@@ -54,3 +55,24 @@ def test_levels_and_pvalues_match_oracle():
     q = rng.uniform(size=40)
     assert pp.ks_pvalue(q) == OPP.ks_pvalue(q)
     assert pp.fisher_pvalue([0.2, 0.5, 0.01]) == OPP.fisher_combined([0.2, 0.5, 0.01])
+
+
+def test_event_weighted_stats():
+    from paper_2607_28265_amd.event import weighted_stats
+    rng = np.random.default_rng(4)
+    x, w = rng.normal(size=200), rng.uniform(size=200)
+    m, sd = weighted_stats(x, w)
+    assert abs(m - np.average(x, weights=w)) < 1e-12
+    assert abs(sd - math.sqrt(np.cov(x, aweights=w, ddof=0))) < 1e-12
+
+
+def test_event_circular_stats():
+    from paper_2607_28265_amd.event import weighted_circular_stats
+    # two points either side of 0: the mean is 0, not pi
+    m, sd = weighted_circular_stats(np.array([0.1, 2 * math.pi - 0.1]), np.array([1.0, 1.0]))
+    assert min(m, 2 * math.pi - m) < 1e-12 and abs(sd - math.sqrt(-2 * math.log(math.cos(0.1)))) < 1e-12
+    # a narrow wrapped normal: circular sd close to sigma
+    rng = np.random.default_rng(8)
+    x = (3.0 + 0.05 * rng.standard_normal(20000)) % (2 * math.pi)
+    m, sd = weighted_circular_stats(x, np.ones_like(x))
+    assert abs(m - 3.0) < 2e-3 and abs(sd - 0.05) < 2e-3
