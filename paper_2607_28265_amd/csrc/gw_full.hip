@@ -262,22 +262,21 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
       accumulate(rec + 4, gr, gi);
     };
     if (ke > kb) {
+      // bins in pairs with one loop exit (see the mixed form below)
       double ra[RS], rb[RS];
 #pragma unroll
       for (int j = 0; j < RS; ++j) ra[j] = bins[(int64_t)(ke - 1) * RS + j];
-      int k = ke - 1;
-      while (true) {
-        const int k1 = k - 1 >= kb ? k - 1 : kb;
+      int k = ke - 1, left = ke - kb;
+      for (; left >= 2; left -= 2, k -= 2) {
 #pragma unroll
-        for (int j = 0; j < RS; ++j) rb[j] = bins[(int64_t)k1 * RS + j];
+        for (int j = 0; j < RS; ++j) rb[j] = bins[(int64_t)(k - 1) * RS + j];
         step(ra);
-        if (--k < kb) break;
-        const int k2 = k - 1 >= kb ? k - 1 : kb;
+        const int k2 = k - 2 >= kb ? k - 2 : kb;
 #pragma unroll
         for (int j = 0; j < RS; ++j) ra[j] = bins[(int64_t)k2 * RS + j];
         step(rb);
-        if (--k < kb) break;
       }
+      if (left) step(ra);
     }
   } else {
     // runs of the cubic phase recurrence (see PhaseRuns).  A walk that
@@ -356,21 +355,23 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
           phasor<PREC>(p0, T, &gr, &gi);
           accumulate(u, gr, gi);
         };
+        // bins in pairs, one loop exit, so that the accumulators of the
+        // two steps can alternate registers; the next record is in flight
+        // while one is processed
         double ua[US], ub[US];
 #pragma unroll
         for (int j = 0; j < US; ++j) ua[j] = bins[(int64_t)kk * RS + 4 + j];
-        while (true) {
-          const int k1 = kk - 1 >= lo ? kk - 1 : lo;
+        int left = kk - lo + 1;
+        for (; left >= 2; left -= 2, kk -= 2) {
 #pragma unroll
-          for (int j = 0; j < US; ++j) ub[j] = bins[(int64_t)k1 * RS + 4 + j];
+          for (int j = 0; j < US; ++j) ub[j] = bins[(int64_t)(kk - 1) * RS + 4 + j];
           step(ua);
-          if (--kk < lo) break;
-          const int k2 = kk - 1 >= lo ? kk - 1 : lo;
+          const int k2 = kk - 2 >= lo ? kk - 2 : lo;
 #pragma unroll
           for (int j = 0; j < US; ++j) ua[j] = bins[(int64_t)k2 * RS + 4 + j];
           step(ub);
-          if (--kk < lo) break;
         }
+        if (left) step(ua);
       }
       k = s - 1;
     }
