@@ -190,6 +190,27 @@ def test_cfg2_full_batch_sampled(cfg2, marg):
         assert err.max() < TOL[prec]
 
 
+@pytest.mark.parametrize("tpb,chunks", [(64, 8), (128, 24), (256, 5), (64, 200)])
+def test_cfg2_mixed_phase_runs_independent_of_launch_shape(cfg2, gw, tpb, chunks):
+    # The mixed form's phase recurrence runs over fixed aligned blocks, so a
+    # chunk boundary inside a run must not change any phase: launch shapes
+    # may differ only by summation order (~1e-10 here), far below the ~1e-7
+    # a run restarted at each chunk boundary would give.
+    prob, ctx, th, idx = cfg2
+    k_min, lens = gw.gw_full_phase_runs(ctx.handle)
+    assert lens == [64, 32, 16, 8] and 0 < k_min[3] <= k_min[2] <= k_min[1] <= k_min[0] < prob.n_freq
+    sel = th[:512]
+    base = _gpu(ctx, sel, L.PHASE_DIST, 1)
+    ctx.set_full_shape(tpb, chunks)
+    try:
+        got = _gpu(ctx, sel, L.PHASE_DIST, 1)
+    finally:
+        ctx.set_full_shape(0, 0)
+    d = np.max(np.abs(got - base))
+    print(f"cfg2 mixed shape ({tpb}, {chunks}) vs default: max|d logL|={d:.3e}", flush=True)
+    assert d < 1e-8
+
+
 def test_cfg2_loud_precision(gw):
     # Precision stress: PSD scale 1e-49, injection at network SNR 24,
     # near-posterior proposals where the overlap is large.
