@@ -260,6 +260,12 @@ gw_status loglike_batch_uneven(gw_ctx* ctx, const double* theta, int64_t n_rows,
  * persistent grid size in workgroups and number of edge chunks a row's bins
  * are split into (0 = heuristic for either). */
 gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid, int32_t n_ech);
+/* Edge chunks of the heterodyned time marginal's two complex products (App. A
+ * on the binned likelihood): 1, 2, 4, 8, 16 or 32 fixes the split of the
+ * edge sum, 0 (default) restores the heuristic (about 256 output tiles in
+ * flight, at least 64 edges a chunk).  Results differ only by summation
+ * order.  GW_EINVAL otherwise. */
+gw_status gw_set_het_tm_split(gw_ctx* ctx, int32_t n_chunks);
 
 /* Number of instantiated graphs and the last instantiation time (ms), which
  * plays the role of a one-off compilation cost. */

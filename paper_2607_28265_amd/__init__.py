@@ -12,9 +12,9 @@ from ._lib import (  # noqa: F401
     GwError, gw_ctx_create, gw_ctx_destroy, gw_data_inner, gw_last_error, gw_set_full_shape, gw_template,
     gw_version, loglike_batch, heterodyne_setup, gw_het_info, loglike_batch_uneven, gw_set_het_shape,
     gw_graph_info, gw_profile_enable, gw_profile_read, slice_step, slice_sweep, gw_prior_transform, Mlp,
-    gw_set_full_kernel, gw_full_info, gw_full_phase_runs, gw_phasor_gain, WaveformCache, gw_set_time_window, gw_time_grid_info,
-    gw_reconstruct, slice_uniforms_fixed, GW_MAX_BLOCK, gw_set_sky_frame, gw_fiducial_search,
-    gw_set_time_oversample,
+    gw_set_full_kernel, gw_full_info, gw_full_phase_runs, gw_phasor_gain, WaveformCache, gw_set_time_window,
+    gw_time_grid_info, gw_set_het_tm_split, gw_reconstruct, slice_uniforms_fixed, GW_MAX_BLOCK, gw_set_sky_frame,
+    gw_fiducial_search, gw_set_time_oversample,
 )
 
 

@@ -130,6 +130,7 @@ _SIGS = {
     "loglike_batch_uneven": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "gw_set_het_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "gw_set_het_tm_split": (ctypes.c_int, [_P, ctypes.c_int32]),
     "gw_autotune": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                    _P]),
@@ -707,6 +708,11 @@ def gw_fiducial_search(ctx, x, generations: int, seed: int = 0, f_scale: float =
     check(load().gw_fiducial_search(ctx, ctypes.byref(a), _tensor_ptr(x), _tensor_ptr(fx), _dptr(best),
                                     _stream_ptr(stream)), "gw_fiducial_search")
     return fx, best
+
+
+def gw_set_het_tm_split(ctx, n_chunks: int = 0):
+    """Edge chunks of the heterodyned time marginal's products (0 = heuristic)."""
+    check(load().gw_set_het_tm_split(ctx, int(n_chunks)), "gw_set_het_tm_split")
 
 
 def gw_set_time_oversample(ctx, factor: int = 4):

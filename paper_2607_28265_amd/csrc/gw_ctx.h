@@ -58,6 +58,7 @@ struct gw_ctx {
   // time marginal: window half-width (s), FFT twiddles and moment workspace
   double tm_window = 0.1;
   int tm_R = 4;                    // grid points per sampling interval of the segment
+  int tm_nsk = 0;                  // edge chunks of the heterodyned time marginal's products (0 = heuristic)
   int tm_P = 0;
   int tm_twR = 0;                  // oversampling the twiddle table was built for
   double* tm_tw = nullptr;

@@ -857,8 +857,10 @@ __global__ void __launch_bounds__(64) k_het_tw(const double* __restrict__ coef, 
     pr[i] = pim[i] = 0.0;
   }
   const int n_edges = n_bins + 1;
-  double* __restrict__ w_out = wv + pc * ne_pad * 2;
-  double* __restrict__ v_out = wv + (n + pc) * ne_pad * 2;
+  // edge-major [edge][row] complex, so that a wave's stores of one edge are
+  // contiguous; W first, then V
+  double* __restrict__ w_out = wv + pc * 2;
+  double* __restrict__ v_out = wv + ((int64_t)ne_pad * n + pc) * 2;
   if (e0 > 0 && e0 - 1 < n_edges) {  // the previous edge's phasors
     const double* r = rec + (int64_t)(e0 - 1) * RS;
     const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
@@ -897,16 +899,16 @@ __global__ void __launch_bounds__(64) k_het_tw(const double* __restrict__ coef, 
       pim[i] = gi;
     }
     if (p < n) {
-      w_out[2 * e] = wr;
-      w_out[2 * e + 1] = wi;
-      v_out[2 * e] = vr;
-      v_out[2 * e + 1] = vi;
+      w_out[2 * e * n] = wr;
+      w_out[2 * e * n + 1] = wi;
+      v_out[2 * e * n] = vr;
+      v_out[2 * e * n + 1] = vi;
     }
   }
   if (p < n && e0 + chunk >= n_edges) {  // the last chunk clears the padding
     for (int e = n_edges > e0 ? n_edges : e0; e < ne_pad; ++e) {
-      w_out[2 * e] = w_out[2 * e + 1] = 0.0;
-      v_out[2 * e] = v_out[2 * e + 1] = 0.0;
+      w_out[2 * e * n] = w_out[2 * e * n + 1] = 0.0;
+      v_out[2 * e * n] = v_out[2 * e * n + 1] = 0.0;
     }
   }
   if (p < n && e0 == 0) hhc[p] = hconst;
@@ -991,11 +993,11 @@ __global__ void __launch_bounds__(256) k_het_tfinal(const double* __restrict__ z
 }
 
 // Edge chunks of the weight kernel: enough (64-row tile, chunk) waves to fill
-// the chip, chunks of at least 32 edges.
+// the chip, chunks of at least 8 edges.
 static int het_tw_chunk(int64_t n, int n_edges) {
   const int64_t tiles = (n + 63) / 64;
   int64_t want = (4096 + tiles - 1) / tiles;
-  const int64_t most = (n_edges + 31) / 32;
+  const int64_t most = (n_edges + 7) / 8;
   if (want > most) want = most;
   if (want < 1) want = 1;
   return (int)((n_edges + want - 1) / want);
@@ -1047,11 +1049,18 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
     h->tm_delta = delta;
   }
   // split of the products over edge chunks: few rows give few output tiles,
-  // so the edge sum is cut into nsk chunks (a power of two up to 32) until
-  // about 512 tiles are in flight; their partials are added in chunk order
-  const int64_t tiles = (int64_t)((nt + 127) / 128) * ((n + 63) / 64);
+  // so the edge sum is cut into nsk chunks (a power of two) until about 256
+  // tiles of 64 x 64 are in flight, keeping at least 64 edges per chunk (each
+  // chunk writes a full partial product); the partials are added in chunk
+  // order.  gw_set_het_tm_split fixes nsk instead.
   int nsk = 1;
-  while (nsk < 32 && tiles * nsk < 512) nsk *= 2;
+  if (ctx->tm_nsk > 0) {
+    nsk = ctx->tm_nsk;
+  } else {
+    const int64_t tiles = (int64_t)((nt + 63) / 64) * ((n + 63) / 64);
+    while (nsk < 32 && ne_pad / (2 * nsk) >= 64 && tiles * nsk < 256) nsk *= 2;
+  }
+  if (ne_pad % nsk != 0) return set_error(GW_EINVAL, "time marginal: %d edge chunks do not divide %d edges", nsk, ne_pad);
   const int ke = ne_pad / nsk;
   // workspace: coefficients, W/V [2][n][ne_pad], Z/H [2][nsk][n][nt], hhc [n]
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
@@ -1081,8 +1090,9 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
   s = check_hip(hipGetLastError(), "edge weight launch");
   if (s != GW_OK) return s;
   // Z^T = E^T W^T and H^T = F^T V^T in column-major terms: m = nt, n = rows,
-  // k = edges; chunk c of nsk takes edges [c ke, (c + 1) ke) into its own
-  // partial (one strided batch per product)
+  // k = edges, with W and V stored edge-major (the rows x edges matrix with
+  // leading dimension n, used transposed); chunk c of nsk takes edges
+  // [c ke, (c + 1) ke) into its own partial (one strided batch per product)
   if (!ctx->blas) {
     if (rocblas_create_handle((rocblas_handle*)&ctx->blas) != rocblas_status_success)
       return set_error(GW_EDEVICE, "rocblas_create_handle failed");
@@ -1099,9 +1109,9 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
     if (nsk == 1 && q == 1) break;  // one call covers both products
     const int batch = nsk == 1 ? 2 : nsk;
     bs = rocblas_zgemm_strided_batched(
-        bh, rocblas_operation_none, rocblas_operation_none, nt, (rocblas_int)n, nsk == 1 ? ne_pad : ke, &one, A, nt,
-        nsk == 1 ? (rocblas_stride)ne_pad * nt : (rocblas_stride)ke * nt, B, ne_pad,
-        nsk == 1 ? (rocblas_stride)n * ne_pad : (rocblas_stride)ke, &zero, Cm, nt, (rocblas_stride)n * nt, batch);
+        bh, rocblas_operation_none, rocblas_operation_transpose, nt, (rocblas_int)n, nsk == 1 ? ne_pad : ke, &one, A,
+        nt, nsk == 1 ? (rocblas_stride)ne_pad * nt : (rocblas_stride)ke * nt, B, (rocblas_int)n,
+        nsk == 1 ? (rocblas_stride)n * ne_pad : (rocblas_stride)ke * n, &zero, Cm, nt, (rocblas_stride)n * nt, batch);
   }
   prof_end(ctx, prof, st);
   if (bs != rocblas_status_success) return set_error(GW_EDEVICE, "rocblas_zgemm_strided_batched: status %d", (int)bs);
@@ -1349,6 +1359,14 @@ gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid, i
   ctx->het->wpb = waves_per_block;
   ctx->het->grid = grid;
   ctx->het->ech = n_ech;
+  return GW_OK;
+}
+
+gw_status gw_set_het_tm_split(gw_ctx* ctx, int32_t n_chunks) {
+  if (!ctx) return set_error(GW_EINVAL, "gw_set_het_tm_split: ctx is NULL");
+  if (n_chunks < 0 || n_chunks > 32 || (n_chunks & (n_chunks - 1)) != 0)
+    return set_error(GW_EINVAL, "gw_set_het_tm_split: n_chunks must be 0 or a power of two up to 32");
+  ctx->tm_nsk = n_chunks;
   return GW_OK;
 }
 

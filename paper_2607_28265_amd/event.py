@@ -71,7 +71,8 @@ def make_event(seed: int = 2017, snr: float = 32.0, duration: float = 128.0, f_m
 
 def analyse(prob, trigger_mc: float, trigger_tc: float, truth=None, n_bins: int = 5000, pop: int = 8192,
             generations: int = 300, n_live: int = 512, n_delete: int = 64, seed: int = 17,
-            mc_half_width: float = 0.002, tc_half_width: float = 0.005, time_window: float = 0.03) -> dict:
+            mc_half_width: float = 0.002, tc_half_width: float = 0.005, time_window: float = 0.03,
+            tm_split: int = 0) -> dict:
     """Run the four stages on ``prob``; ``truth``, when given, is only
     reported beside the posterior summaries."""
     import torch
@@ -97,6 +98,7 @@ def analyse(prob, trigger_mc: float, trigger_tc: float, truth=None, n_bins: int 
         ctx.heterodyne_setup(fid, n_bins)
         _lib.gw_set_sky_frame(ctx.handle, 1, 0, 1, False)
         _lib.gw_set_time_window(ctx.handle, time_window)
+        _lib.gw_set_het_tm_split(ctx.handle, tm_split)
         torch.cuda.synchronize()
         out["heterodyne_s"] = time.perf_counter() - t0
         # 3. nested sampling (phase and t_c marginalised, d_L sampled)
@@ -145,6 +147,7 @@ def main(argv=None):
     ap.add_argument("--generations", type=int, default=300)
     ap.add_argument("--time-window", type=float, default=0.03)
     ap.add_argument("--sampler-seeds", default="17", help="comma list: one run per seed on the same event")
+    ap.add_argument("--tm-split", type=int, default=0, help="edge chunks of the time marginal's products (0: auto)")
     a = ap.parse_args(argv)
     prob, truth = make_event(a.seed, a.snr)
     rng = np.random.default_rng(a.seed + 5)
@@ -153,7 +156,8 @@ def main(argv=None):
     trig_tc = float(truth[12] + 1e-3 * rng.standard_normal())
     for seed in (int(v) for v in a.sampler_seeds.split(",")):
         res = analyse(prob, trig_mc, trig_tc, truth, n_bins=a.n_bins, pop=a.pop, generations=a.generations,
-                      n_live=a.n_live, n_delete=a.n_delete, seed=seed, time_window=a.time_window)
+                      n_live=a.n_live, n_delete=a.n_delete, seed=seed, time_window=a.time_window,
+                      tm_split=a.tm_split)
         res["seed"] = seed
         res["truth"] = [float(v) for v in truth]
         res["trigger"] = {"mc": trig_mc, "tc": trig_tc}

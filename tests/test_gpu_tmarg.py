@@ -180,3 +180,29 @@ def test_odd_power_fft_length(monkeypatch):
         err = np.max(np.abs(run(gw, ctx, th, gw.GW_PREC_FP64) - ref))
         print(f"window 0.05 s: FFT {p_len}, {n_t} points, max |dlogL| {err:.2e}")
         assert err < 1e-6
+
+
+@pytest.mark.parametrize("nsk", [1, 2, 8, 32])
+def test_heterodyned_fixed_splits_agree(nsk):
+    # every split of the edge sum gives the same grid sums up to summation
+    # order, for a sampler-sized batch (and the default split on the same rows)
+    import paper_2607_28265_amd as gw
+    prob = problem("cfg1", loud=True)
+    th = np.concatenate([gwsynth.prior_draws(gwsynth.SEEDS["prior"], 64), near(prob, 64, 23, 1.0)])
+    with gw.Context(prob) as ctx:
+        ctx.heterodyne_setup(prob.theta_inj, 200)
+        t = torch.from_numpy(th).cuda()
+        for prec, tol in ((gw.GW_PREC_FP64, 1e-9), (gw.GW_PREC_MIXED, 1e-6)):
+            base = ctx.loglike(t, gw.GW_HET, gw.GW_MARG_PHASE_TIME, prec).cpu().numpy()
+            gw.gw_set_het_tm_split(ctx.handle, nsk)
+            try:
+                got = ctx.loglike(t, gw.GW_HET, gw.GW_MARG_PHASE_TIME, prec).cpu().numpy()
+            finally:
+                gw.gw_set_het_tm_split(ctx.handle, 0)
+            fin = np.isfinite(base)
+            assert fin.sum() > 100 and np.array_equal(np.isfinite(got), fin)
+            err = np.max(np.abs(got[fin] - base[fin]))
+            print(f"split {nsk} prec {prec}: max |dlogL| vs default {err:.2e}", flush=True)
+            assert err < tol
+        with pytest.raises(gw.GwError):
+            gw.gw_set_het_tm_split(ctx.handle, 3)
