@@ -584,7 +584,7 @@ def cpu_baseline(n_target_cpu_s: float = 16.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build measures a single GPU "
+        print(f"bench.py: --gpus {args.gpus} is not supported; the benchmark runs on a single GPU "
               "(the batch shards by proposal across GPUs with no exchange but the logL gather).",
               file=sys.stderr, flush=True)
         sys.exit(2)
