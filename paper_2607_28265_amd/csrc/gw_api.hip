@@ -232,7 +232,8 @@ gw_status gw_ctx_destroy(gw_ctx* ctx) {
   if (ctx->blas) (void)rocblas_destroy_handle((rocblas_handle)ctx->blas);
   for (hipEvent_t e : ctx->prof_ev)
     if (e) (void)hipEventDestroy(e);
-  double* bufs[] = {ctx->bins, ctx->dist_tab, ctx->coef, ctx->partial, ctx->zbuf, ctx->tm_tw, ctx->tm_mom, ctx->recon};
+  double* bufs[] = {ctx->bins,   ctx->dist_tab, ctx->coef,   ctx->partial, ctx->zbuf,
+                    ctx->tm_tw,  ctx->tm_tpow,  ctx->tm_mom, ctx->recon};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (ctx->wtab) (void)hipFree(ctx->wtab);

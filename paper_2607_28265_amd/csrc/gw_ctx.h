@@ -62,6 +62,8 @@ struct gw_ctx {
   int tm_P = 0;
   int tm_twR = 0;                  // oversampling the twiddle table was built for
   double* tm_tw = nullptr;
+  double* tm_tpow = nullptr;        // [blk][16] powers of the in-block offset for the moments
+  int tm_tpow_blk = 0;
   double* tm_mom = nullptr;
   int64_t tm_mom_cap = 0;
   void* blas = nullptr;            // rocBLAS handle (created on first use)

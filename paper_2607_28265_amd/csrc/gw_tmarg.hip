@@ -57,7 +57,7 @@ template <int ND, int PREC>
 __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, int64_t ld, int64_t n,
                                               const double* __restrict__ bins, int64_t k0, double df, int n_freq,
                                               int blk, int n_blk, TrigConsts T, double pg_re, double pg_im,
-                                              double* __restrict__ mom) {
+                                              const double* __restrict__ tpow, double* __restrict__ mom) {
   constexpr int RS = 4 + 2 * ND;
   const int tpb = blockDim.x;
   const int nptile = (int)((n + tpb - 1) / tpb);
@@ -104,7 +104,6 @@ __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, i
   double mr[kTMom], mi[kTMom];
 #pragma unroll
   for (int m = 0; m < kTMom; ++m) mr[m] = mi[m] = 0.0;
-  const double cen = 0.5 * (blk - 1), hinv = 2.0 / blk;
   for (int k = kb; k < ke; ++k) {
     const double* __restrict__ rec = bins + (int64_t)k * RS;
     const double r = phase_cycles(c, rec[0], rec[1], rec[2], rec[3]);
@@ -126,13 +125,13 @@ __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, i
       }
     }
     const double yr = gr * sr - gi * si, yi = gr * si + gi * sr;
-    const double t = ((double)(k - kb) - cen) * hinv;
-    double tp = 1.0;
+    // the powers t^m of the bin's offset in the block come from a table
+    // (the same for every block and proposal: wave-uniform scalar loads)
+    const double* __restrict__ tq = tpow + (int64_t)(k - kb) * kTMom;
 #pragma unroll
     for (int m = 0; m < kTMom; ++m) {
-      mr[m] = fma(tp, yr, mr[m]);
-      mi[m] = fma(tp, yi, mi[m]);
-      tp *= t;
+      mr[m] = fma(tq[m], yr, mr[m]);
+      mi[m] = fma(tq[m], yi, mi[m]);
     }
   }
   if (p >= n) return;
@@ -300,11 +299,12 @@ static void launch_tmom_nd(gw_ctx* ctx, const double* coef, int64_t n, int prec,
   const TrigConsts T = make_trig_consts();
   if (prec == GW_PREC_FP64)
     hipLaunchKernelGGL((k_tmom<ND, 0>), dim3((unsigned)(nptile * n_blk)), dim3(tpb), 0, st, coef, n, n, ctx->bins,
-                       ctx->geom.k0, ctx->geom.df, (int)ctx->geom.n_freq, blk, n_blk, T, 1.0, 0.0, mom);
+                       ctx->geom.k0, ctx->geom.df, (int)ctx->geom.n_freq, blk, n_blk, T, 1.0, 0.0,
+                       (const double*)ctx->tm_tpow, mom);
   else
     hipLaunchKernelGGL((k_tmom<ND, 1>), dim3((unsigned)(nptile * n_blk)), dim3(tpb), 0, st, coef, n, n, ctx->bins,
                        ctx->geom.k0, ctx->geom.df, (int)ctx->geom.n_freq, blk, n_blk, T, ctx->pgain_re,
-                       ctx->pgain_im, mom);
+                       ctx->pgain_im, (const double*)ctx->tm_tpow, mom);
 }
 
 // Grid of the time marginal for the context's window: N, J, P, B.
@@ -366,6 +366,28 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
     if (s != GW_OK) return s;
     ctx->tm_P = g.P;
     ctx->tm_twR = g.R;
+  }
+  if (ctx->tm_tpow_blk != g.blk) {
+    // powers t_j^m, t_j = (j - (B - 1) / 2) / (B / 2), m < 16, formed as the
+    // moment sums use them (repeated products from 1)
+    std::vector<double> h((size_t)g.blk * kTMom);
+    const double cen = 0.5 * (g.blk - 1), hinv = 2.0 / g.blk;
+    for (int j = 0; j < g.blk; ++j) {
+      const double t = ((double)j - cen) * hinv;
+      double tp = 1.0;
+      for (int m = 0; m < kTMom; ++m) {
+        h[(size_t)j * kTMom + m] = tp;
+        tp *= t;
+      }
+    }
+    if (ctx->tm_tpow) (void)hipFree(ctx->tm_tpow);
+    ctx->tm_tpow = nullptr;
+    ctx->tm_tpow_blk = 0;
+    s = check_hip(hipMalloc((void**)&ctx->tm_tpow, h.size() * sizeof(double)), "time-grid powers");
+    if (s == GW_OK)
+      s = check_hip(hipMemcpy(ctx->tm_tpow, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice), "powers");
+    if (s != GW_OK) return s;
+    ctx->tm_tpow_blk = g.blk;
   }
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
   if (s == GW_OK) s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap, n * kTMom * g.n_blk * 2, "time moments");
