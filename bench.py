@@ -82,6 +82,14 @@ def traffic_bytes(kernel="k_full"):
     return TRAFFIC[kernel]["read_bytes"] + TRAFFIC[kernel]["write_bytes"]
 
 
+_T0 = time.perf_counter()
+
+
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,8 +97,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="full,het,tmarg,recon,cache,fiducial,nested,nested_full,prescreen",
-                    help="comma list of legs to run: full (always timed), het, tmarg, recon, cache, fiducial, "
+    ap.add_argument("--legs", default="full,cfg1,het,tmarg,recon,cache,fiducial,nested,nested_full,prescreen",
+                    help="comma list of legs to run: full (always timed), cfg1, het, tmarg, recon, cache, fiducial, "
                          "nested, nested_full, prescreen, copy")
     return ap.parse_args()
 
@@ -129,11 +137,25 @@ def time_steps(ctx, theta, out, steps, warmup, prec, marg, torch, gw, profile=Fa
     return (t1 - t0), kern
 
 
+# Algorithmic FP64 flops per (row, edge) of the heterodyned contraction
+# k_het<3, PREC>, FMA = 2: the edge's TaylorF2 phase (11 FMA + 1 mul = 23)
+# minus the fiducial's (1); per detector the delay term of detectors 1 and 2
+# (1 FMA + 1 sub = 3 each), the phasor (mixed: the reduction to a fraction of
+# a cycle (1) and the Newton normalisation of the FP32 pair (7); FP64: the
+# software sin/cos, 47), the summed-by-parts weight product (4 FMA = 8) and
+# the norm term (1 mul + 2 FMA = 5).  Mixed: 24 + 3 (8 + 8 + 5) + 2 x 3 = 93;
+# FP64: 24 + 3 (47 + 13) + 6 = 210.
+HET_FLOPS_PER_EDGE = {"mixed": 93.0, "fp64": 210.0}
+
+
 def het_leg(gw, torch, prob, th_inj, steps, warmup):
-    """Heterodyned form: 500 bins, 65,536 proposals in uneven sub-batches of
-    100-8000, one graph replay per batch (FP64 phase, FP32 sin/cos)."""
+    """Heterodyned form: bins of equal maximum phase change from the 128 s
+    segment (500, the workload, and 5000, the paper's count), 65,536
+    proposals in uneven sub-batches of 100-8000, one graph replay per batch,
+    launch shape from the library's autotuner on this batch."""
     import numpy as np
     import gwsynth
+    from paper_2607_28265_amd import autotune
     n = 65536
     th = np.concatenate([gwsynth.prior_draws(gwsynth.SEEDS["prior"], n // 2),
                          gwsynth.near_posterior(41, th_inj, n // 2, scale=0.5)])
@@ -143,23 +165,41 @@ def het_leg(gw, torch, prob, th_inj, steps, warmup):
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     res = {}
     with gw.Context(prob) as ctx:
+        for n_bins in (500, 5000):
+            ctx.heterodyne_setup(th_inj, n_bins)
+            nb_res = {}
+            for name, prec in (("mixed", gw.GW_PREC_MIXED), ("fp64", gw.GW_PREC_FP64)):
+                shape, tune_ms = autotune.tune(ctx, theta, gw.GW_HET, gw.GW_MARG_PHASE_DIST, prec, reps=3,
+                                               use_cache=False)
+                for _ in range(warmup):
+                    ctx.loglike_uneven(theta, subs, marg=gw.GW_MARG_PHASE_DIST, prec=prec, out=out)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    ctx.loglike_uneven(theta, subs, marg=gw.GW_MARG_PHASE_DIST, prec=prec, out=out)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                gw._lib.gw_profile_read(ctx.handle)
+                gw._lib.gw_profile_enable(ctx.handle, True)
+                for _ in range(3):
+                    ctx.loglike_uneven(theta, subs, marg=gw.GW_MARG_PHASE_DIST, prec=prec, out=out,
+                                       use_graph=False)
+                ms, nl = gw._lib.gw_profile_read(ctx.handle)
+                gw._lib.gw_profile_enable(ctx.handle, False)
+                k_ms = ms / max(nl, 1)
+                flops = HET_FLOPS_PER_EDGE[name] * n * (n_bins + 1)
+                ach = flops / (k_ms * 1e-3) / 1e12
+                nb_res[name] = {"value": n * steps / dt, "ms_per_batch": dt / steps * 1e3, "kernel_ms": k_ms,
+                                "autotuned_shape": list(shape), "autotune_ms_per_call": tune_ms,
+                                "roofline": {"kernel": f"k_het<3,{1 if name == 'mixed' else 0}>", "bound": "alu",
+                                             "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                             "frac": ach / PEAK_FP64_TFLOPS, "flops_per_launch": flops,
+                                             "flops_per_row_edge": HET_FLOPS_PER_EDGE[name], "traffic": None}}
+            nb_res["n_bins"] = n_bins
+            res[f"bins_{n_bins}"] = nb_res
+            ctx.set_het_shape(4, 0, 0)
+        # phase+time marginal on the 500 bins and the same proposals
         ctx.heterodyne_setup(th_inj, 500)
-        for name, prec in (("mixed", gw.GW_PREC_MIXED), ("fp64", gw.GW_PREC_FP64)):
-            for _ in range(warmup):
-                ctx.loglike_uneven(theta, subs, marg=gw.GW_MARG_PHASE_DIST, prec=prec, out=out)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                ctx.loglike_uneven(theta, subs, marg=gw.GW_MARG_PHASE_DIST, prec=prec, out=out)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            gw._lib.gw_profile_read(ctx.handle)
-            gw._lib.gw_profile_enable(ctx.handle, True)
-            ctx.loglike_uneven(theta, subs, marg=gw.GW_MARG_PHASE_DIST, prec=prec, out=out, use_graph=False)
-            ms, nl = gw._lib.gw_profile_read(ctx.handle)
-            gw._lib.gw_profile_enable(ctx.handle, False)
-            res[name] = {"value": n * steps / dt, "ms_per_batch": dt / steps * 1e3, "kernel_ms": ms / max(nl, 1)}
-        # phase+time marginal on the same bins and proposals (one batched GEMM against the grid's phasors)
         tm = {}
         for name, prec in (("mixed", gw.GW_PREC_MIXED), ("fp64", gw.GW_PREC_FP64)):
             for _ in range(2):
@@ -175,14 +215,44 @@ def het_leg(gw, torch, prob, th_inj, steps, warmup):
             dt = (time.perf_counter() - t0) / reps
             ms, nl = gw._lib.gw_profile_read(ctx.handle)
             gw._lib.gw_profile_enable(ctx.handle, False)
-            tm[name] = {"value": n / dt, "ms_per_batch": dt * 1e3, "gemm_ms": ms / max(nl, 1)}
-        res["time_marginal"] = tm
+            tm[name] = {"value": n / dt, "ms_per_batch": dt * 1e3, "grid_kernel_ms": ms / max(nl, 1)}
+        res["time_marginal_500_bins"] = tm
         n_graphs, inst_ms = gw._lib.gw_graph_info(ctx.handle)
-    res.update({"unit": "logL evals/s", "batch": n, "n_sub": int(subs.shape[0]), "n_bins": 500,
+    res.update({"unit": "logL evals/s", "batch": n, "n_sub": int(subs.shape[0]),
                 "graph_instantiate_ms": inst_ms,
-                "workload": "heterodyned: 500 bins of equal maximum phase change from the 128 s segment, "
+                "workload": "heterodyned: 500 and 5000 bins of equal maximum phase change from the 128 s segment, "
                             "65,536 proposals (half prior, half near-posterior) in uneven sub-batches of "
-                            "100-8000, one graph replay per batch, phase+distance marginalised"})
+                            "100-8000, one graph replay per batch, autotuned launch shape, phase+distance "
+                            "marginalised"})
+    return res
+
+
+def cfg1_leg(gw, torch, steps, warmup):
+    """Plain FP64 batch likelihood (no marginalisation): T = 8 s, 20-512 Hz,
+    3937 bins x 3 detectors, 1024 prior draws; the mixed form beside it."""
+    import gwsynth
+    cfg = gwsynth.CONFIGS["cfg1"]
+    prob = gwsynth.make_problem(cfg["duration"], cfg["f_min"], cfg["f_max"], psd_scale=cfg["psd_scale"])
+    th_inj = gwsynth.prior_draws(gwsynth.SEEDS["injection"], 1)
+    noise_only = gw.Context(prob)
+    prob.data = prob.data + noise_only.template(torch.from_numpy(th_inj).cuda())[0].cpu().numpy()
+    noise_only.close()
+    n = 1024
+    theta = torch.from_numpy(gwsynth.prior_draws(gwsynth.SEEDS["prior"], n)).cuda()
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    res = {}
+    with gw.Context(prob) as ctx:
+        for name, prec in (("fp64", gw.GW_PREC_FP64), ("mixed", gw.GW_PREC_MIXED)):
+            dt, k_ms = time_steps(ctx, theta, out, steps, warmup, prec, gw.GW_MARG_NONE, torch, gw, profile=True)
+            fpb = FLOPS_PER_BIN["fp64"] if name == "fp64" else mixed_flops_per_bin(gw, ctx, int(prob.n_freq))
+            ach = fpb * n * prob.n_freq / (k_ms * 1e-3) / 1e12
+            res[name] = {"value": n * steps / dt, "ms_per_batch": dt / steps * 1e3, "kernel_ms": k_ms,
+                         "roofline": {"kernel": f"k_full<3,{0 if name == 'fp64' else 1}>", "bound": "alu",
+                                      "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                      "frac": ach / PEAK_FP64_TFLOPS, "flops_per_bin": fpb}}
+    res.update({"unit": "logL evals/s", "batch": n, "n_freq": int(prob.n_freq),
+                "workload": "plain FP64 batch likelihood: T=8 s, 20-512 Hz, df=1/8 Hz (3937 bins x 3 detectors), "
+                            "1024 prior draws, no marginalisation"})
     return res
 
 
@@ -323,14 +393,28 @@ def nested_leg(gw, torch):
             frames[name] = {"wall_s": time.perf_counter() - t1, "log_z": rf["log_z"], "log_z_err": rf["log_z_err"],
                             "iterations": rf["iterations"], "n_evals": rf["n_evals"], "ess": rf["ess"]}
         gw.gw_set_sky_frame(ctx.handle, 0)
+        # three sweeps per replacement (the High-Res setting), the setting of
+        # the oracle's reference run: its evidence is compared with the
+        # oracle's (runs with one sweep do not decorrelate on this problem)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r3 = NestedSampler(ctx, n_live=1000, n_delete=125, seed=gwsynth.SEEDS["sampler"], like=gw.GW_HET,
+                           prec=gw.GW_PREC_MIXED, sweeps=3).run()
+        m3 = {"wall_s": time.perf_counter() - t1, "log_z": r3["log_z"], "log_z_err": r3["log_z_err"],
+              "iterations": r3["iterations"], "n_evals": r3["n_evals"], "ess": r3["ess"]}
     out = {"wall_s": wall, "log_z": r["log_z"], "log_z_err": r["log_z_err"], "iterations": r["iterations"],
-           "n_evals": r["n_evals"], "evals_per_s": r["n_evals"] / wall, "ess": r["ess"], "sky_frames": frames}
+           "n_evals": r["n_evals"], "evals_per_s": r["n_evals"] / wall, "ess": r["ess"], "sky_frames": frames,
+           "three_sweeps": m3}
     gold = os.path.join(ROOT, "tests", "golden", "ns_cfg2.json")
     if os.path.exists(gold):
         with open(gold) as f:
             g = json.load(f)
         out["oracle_run"] = {"log_z": g["log_z"], "log_z_err": g["log_z_err"], "iterations": g["iterations"],
-                             "n_evals": g["n_evals"], "cpu_wall_s_single_process": g["cpu_wall_s"]}
+                             "n_evals": g["n_evals"], "sweeps": g.get("sweeps", 1),
+                             "cpu_wall_s_single_process": g["cpu_wall_s"]}
+        if g.get("sweeps", 1) == 3:
+            m3["log_z_minus_oracle_in_sigma"] = (r3["log_z"] - g["log_z"]) / math.hypot(r3["log_z_err"],
+                                                                                     g["log_z_err"])
     out["workload"] = ("nested sampling: 1000 live points, 125 deletions per iteration, 7 Gibbs blocks over 11 "
                        "dimensions, heterodyned 500-bin likelihood (mixed form), dlogz 0.1, SNR-24 injection")
     return out
@@ -460,22 +544,33 @@ def nested_full_leg(gw, torch):
     th = gwsynth.prior_draws(gwsynth.SEEDS["injection"], 1)[0]
     th_inj = P.library_injection(gw.Context, prob, th, snr=24.0)
     out = {}
+    pre_cfg = dict(start=100, every=50, audit=0.01)
     with gw.Context(prob) as ctx:
-        for cache in (False, True):
+        for name, cache, pre in (("no_cache", False, None), ("cache", True, None), ("prescreen", False, pre_cfg)):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ns = NestedSampler(ctx, n_live=1000, n_delete=125, seed=gwsynth.SEEDS["sampler"], like=gw.GW_FULL,
-                               prec=gw.GW_PREC_MIXED, cache=cache)
+                               prec=gw.GW_PREC_MIXED, cache=cache, prescreen=pre)
             r = ns.run()
             wall = time.perf_counter() - t0
+            ns.close()
             d = {"wall_s": wall, "log_z": r["log_z"], "log_z_err": r["log_z_err"], "iterations": r["iterations"],
-                 "n_evals": r["n_evals"]}
+                 "n_evals": r["n_evals"], "accepted_proposals": r["moves"],
+                 "accepted_proposals_per_s": r["moves"] / wall}
             if cache:
                 d["evals_full_cachedwaveform_cachedsums"] = r["eval_kinds"]
-            out["cache" if cache else "no_cache"] = d
+            if pre is not None:
+                p = r["prescreen"]
+                d["prescreen"] = {"settings": pre, "screened": p["screened"], "audited": p["audited"],
+                                  "audited_inside_false_negatives": p["audited_inside"],
+                                  "trainings": p["trainings"], "train_s": p["train_s"], "margin_last": p["margin"],
+                                  "accepted_proposals_per_s_excluding_training":
+                                      r["moves"] / max(wall - p["train_s"], 1e-9)}
+            out[name] = d
     out["workload"] = ("nested sampling on the full band: 1000 live points, 125 deletions, 7 Gibbs blocks, "
                        "128 s at 259,585 bins per detector, mixed form, phase+distance marginalised, dlogz 0.1, "
-                       "SNR-24 injection")
+                       "SNR-24 injection; without and with the waveform cache, and with the learned prescreen in "
+                       "the sweeps (trained on the run's dead and live points from iteration 100, every 50)")
     return out
 
 
@@ -558,27 +653,61 @@ def copy_leg(torch, reps=5, mib=256):
     return {"bytes_read_per_copy": a.numel() * 8, "bytes_written_per_copy": a.numel() * 8, "reps": reps}
 
 
-def cpu_baseline(n_target_cpu_s: float = 16.0):
-    """The FP64 oracle on the host cores, on a bounded sample of the same workload."""
+def cpu_baseline(gw, torch, batch: int, n_target_cpu_s: float = 16.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the headline
+    workload (the first rows of its batch), timed; then the same rows' GPU
+    values, taken from a full headline batch in the headline launch
+    configuration on a context built from the oracle's data, are compared with
+    the oracle's: dlogL = GPU - oracle.  The data differ from the headline
+    problem's only in who made the injection (the oracle's template here, the
+    library's there; both the same TaylorF2 of the same parameters).  Config 1
+    (8 s, no marginalisation, all 1024 draws) is compared the same way."""
     import numpy as np
     import gwsynth
     from oracle import likelihood as L
     cores = len(os.sched_getaffinity(0))
-    cfg = gwsynth.CONFIGS["cfg2"]
-    prob = gwsynth.make_problem(cfg["duration"], cfg["f_min"], cfg["f_max"], psd_scale=cfg["psd_scale"])
-    th_inj = gwsynth.prior_draws(gwsynth.SEEDS["injection"], 1)[0]
-    prob.data = prob.data + L.strain(th_inj, prob)
+
+    def oracle_problem(name):
+        cfg = gwsynth.CONFIGS[name]
+        prob = gwsynth.make_problem(cfg["duration"], cfg["f_min"], cfg["f_max"], psd_scale=cfg["psd_scale"])
+        th_inj = gwsynth.prior_draws(gwsynth.SEEDS["injection"], 1)[0]
+        prob.data = prob.data + L.strain(th_inj, prob)
+        return prob, th_inj
+
+    def stats(got, ref):
+        d = np.abs(got - ref)
+        return {"max": float(d.max()), "p99": float(np.quantile(d, 0.99)), "n": int(d.size)}
+
+    prob, th_inj = oracle_problem("cfg2")
     t0 = time.perf_counter()
     L.loglike(th_inj, prob, L.PHASE_DIST)
     one = time.perf_counter() - t0
     n = int(max(cores, min(64 * cores, n_target_cpu_s / max(one, 1e-3))))
-    th = gwsynth.prior_draws(gwsynth.SEEDS["prior"], n)
+    th = gwsynth.prior_draws(gwsynth.SEEDS["prior"], max(n, batch))
     t0 = time.perf_counter()
-    L.loglike_many(th, prob, L.PHASE_DIST, processes=cores)
+    ref = L.loglike_many(th[:n], prob, L.PHASE_DIST, processes=cores)
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "logL evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} prior draws of the same 128 s full-band workload, phase+distance marginalised, "
-                      f"NumPy FP64 oracle over a {cores}-process pool ({dt:.1f} s wall)"}
+    out = {"value": n / dt, "unit": "logL evals/s", "cores": cores, "kind": "oracle",
+           "sample": f"the first {n} of the 4096 prior draws of the 128 s full-band workload, phase+distance "
+                     f"marginalised, NumPy FP64 oracle over a {cores}-process pool ({dt:.1f} s wall)"}
+    dl = {}
+    theta = torch.from_numpy(th[:batch]).cuda()
+    with gw.Context(prob) as ctx:
+        for name, prec in (("mixed", gw.GW_PREC_MIXED), ("fp64", gw.GW_PREC_FP64)):
+            got = ctx.loglike(theta, marg=gw.GW_MARG_PHASE_DIST, prec=prec).cpu().numpy()
+            dl[name] = stats(got[:n], ref)
+    dl["rows"] = f"the first {n} rows of the 4096-row headline batch (evaluated as a whole batch)"
+    prob1, _ = oracle_problem("cfg1")
+    th1 = gwsynth.prior_draws(gwsynth.SEEDS["prior"], 1024)
+    ref1 = L.loglike_many(th1, prob1, L.PLAIN, processes=cores)
+    cfg1 = {}
+    with gw.Context(prob1) as ctx:
+        t1 = torch.from_numpy(th1).cuda()
+        for name, prec in (("fp64", gw.GW_PREC_FP64), ("mixed", gw.GW_PREC_MIXED)):
+            cfg1[name] = stats(ctx.loglike(t1, marg=gw.GW_MARG_NONE, prec=prec).cpu().numpy(), ref1)
+    cfg1["rows"] = "all 1024 prior draws of the 8 s workload, no marginalisation"
+    dl["cfg1_plain"] = cfg1
+    return out, dl
 
 
 def main():
@@ -653,26 +782,37 @@ def main():
         "mixed_vs_fp64_max_dlogl": dlogl,
     }
     legs = set(args.legs.split(","))
+    log(f"full-band legs done: {value:.4g} evals/s mixed")
     if "het" in legs:
         res["heterodyned"] = het_leg(gw, torch, prob, th_inj, max(5, args.steps // 2), 2)
+        log("heterodyned leg done")
     if tm is not None:
         res["time_marginal"] = tm
     if rc is not None:
         res["reconstruction"] = rc
     if "cache" in legs:
         res["waveform_cache"] = cache_leg(gw, torch, prob, args.steps, args.warmup, value)
+        log("cache leg done")
     if "fiducial" in legs:
         res["fiducial_search"] = fiducial_leg(gw, torch)
+        log("fiducial leg done")
     if "nested" in legs:
         res["nested_sampling"] = nested_leg(gw, torch)
+        log("nested-sampling leg done")
     if "nested_full" in legs:
         res["nested_sampling_full_band"] = nested_full_leg(gw, torch)
+        log("full-band nested-sampling leg done")
     if "prescreen" in legs:
         res["prescreen"] = prescreen_leg(gw, torch, 10)
+        log("prescreen leg done")
     if "copy" in legs:
         res["copy_calibration"] = copy_leg(torch)
+    if "cfg1" in legs:
+        res["cfg1_plain_fp64"] = cfg1_leg(gw, torch, args.steps, args.warmup)
+        log("config-1 leg done")
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline()
+        res["cpu_baseline"], res["dlogl_vs_oracle"] = cpu_baseline(gw, torch, n)
+        log("cpu baseline done")
     print(json.dumps(res), flush=True)
 
 

@@ -24,7 +24,12 @@
  * - Device buffers are caller-owned, contiguous, and must stay alive until
  *   the work queued on the caller's stream has completed.  The context owns
  *   everything it uploads.  A context is not thread-safe; all work goes on the
- *   stream passed in (a hipStream_t, NULL for the default stream).
+ *   stream passed in (a hipStream_t, NULL for the default stream).  A context
+ *   serves one stream at a time: its workspaces (coefficients, partial sums,
+ *   marginal buffers) are shared by every call, so two calls on one context
+ *   queued on different streams race unless the caller orders them (finish
+ *   one stream's work, or make the second stream wait on an event recorded
+ *   after the first call).  Use one context per stream for concurrent work.
  * - Errors are returned as status codes; nothing throws across the ABI and on
  *   an error no output is written.  gw_last_error() returns a thread-local
  *   message for the last non-OK status of the calling thread.
@@ -43,6 +48,7 @@ extern "C" {
 #endif
 
 typedef struct gw_ctx gw_ctx;
+typedef struct gw_mlp gw_mlp;  /* prescreen network, see gw_mlp_create */
 
 typedef enum {
   GW_OK = 0,
@@ -286,12 +292,15 @@ gw_status gw_graph_info(const gw_ctx* ctx, int32_t* n_graphs, double* last_insta
  * gw_prior_transform_marg); its rounds are launched without a graph.
  * A block holds 1 .. GW_MAX_BLOCK coordinates; one holding all 11 is the
  * unblocked nested slice sampler of the sampler-configuration section.
- * With F = GW_SLICE_UNI_FIXED(block_dim) = max(4, 2 ceil(block_dim / 2)) + 1:
+ * With F = GW_SLICE_UNI_FIXED(block_dim) = max(4, 2 ceil(block_dim / 2)) + 2:
  * per chain, u a uniform unit vector (Box-Muller pair p from uniforms 2p and
  * 2p + 1, the first block_dim normals, normalised), the direction d = L u
  * with L the block's lower Cholesky factor; a bracket [-r w, (1 - r) w] with
- * r = uniform F - 1; each end stepped out by w while log L > log L* (at most
- * max_out steps per side); then shrink draws
+ * r = uniform F - 2; each end stepped out by w while log L > log L*, the
+ * stepping-out budget m = 2 max_out + 1 split by V = uniform F - 1 into at
+ * most J = floor(m V) steps for the lower end and m - 1 - J for the upper
+ * one (Neal 2003, Sec. 4.1: a split drawn at random keeps the move
+ * reversible when a cap binds); then shrink draws
  * t = t_lo + u_s (t_hi - t_lo), s = 0 .. max_shrink - 1 (uniform F + s),
  * until log L > log L*, the bracket end on the side of t moving to t.  A point
  * outside the cube fails without a likelihood call.  After max_shrink
@@ -304,7 +313,7 @@ gw_status gw_graph_info(const gw_ctx* ctx, int32_t* n_graphs, double* last_insta
  * after every chain has finished change nothing).
  */
 #define GW_MAX_BLOCK 11
-#define GW_SLICE_UNI_FIXED(bd) (((bd) <= 4 ? 4 : 2 * (((bd) + 1) / 2)) + 1)
+#define GW_SLICE_UNI_FIXED(bd) (((bd) <= 4 ? 4 : 2 * (((bd) + 1) / 2)) + 2)
 
 typedef struct {
   int64_t k;              /* number of chains */
@@ -318,7 +327,7 @@ typedef struct {
   uint64_t counter;       /* Philox counter base */
   const double* uniforms; /* device [k, F + max_shrink] or NULL */
   double w;               /* bracket width along t (> 0) */
-  int32_t max_out;        /* >= 0 */
+  int32_t max_out;        /* 0 .. 10000: half the stepping-out budget */
   int32_t max_shrink;     /* 1 .. 10000 */
   int32_t like;           /* GW_FULL or GW_HET */
   int32_t marg;           /* GW_MARG_PHASE_DIST */
@@ -327,10 +336,41 @@ typedef struct {
   int32_t* status;        /* device [k] 0 moved, 1 kept, or NULL */
   int32_t use_graph;      /* 1: replay a captured graph of 4 rounds (captured on
                              first use and again when k, like, marg, prec, the
-                             launch shapes or a workspace change); 0: launch
-                             each kernel.  Results are identical. */
+                             launch shapes, a workspace, the network or its
+                             scaling change); 0: launch each kernel.  Results
+                             are identical. */
+  gw_mlp* mlp;            /* learned prescreen (a network made on this context)
+                             or NULL: see below */
+  double margin;          /* with mlp: finite; candidates predicted
+                             >= log L* - margin get their exact log L */
+  double audit_frac;      /* with mlp: in [0, 1], the share of the other
+                             candidates evaluated anyway (audit) */
+  int64_t* screen_stats;  /* host [3] or NULL: candidates screened out,
+                             audited, audited and inside log L > log L* (a
+                             false negative of the screen); synchronises */
 } gw_slice_args;
 
+/*
+ * Learned prescreen inside the slice update (spec learned form; the
+ * paper's sampler evaluates every candidate).  With mlp, every round runs the
+ * network on each candidate's unit-cube point (BF16 matrix-core inference,
+ * FP32 accumulation; the prediction is compared in FP64).  A candidate whose
+ * prediction is >= log L* - margin gets its exact log L (like, marg, prec);
+ * otherwise it is taken as outside the constraint without a likelihood call
+ * (a stepping-out end stops there, a shrink draw shrinks the bracket), unless
+ * it is drawn for the audit: test ``idx`` of kind ``kind`` (0 lower end, 1
+ * upper end, 2 shrink draw; idx counts that kind's tests in the block) of
+ * chain c in block b is audited when word 0 of Philox4x64-10 at counter
+ * (counter + b, c, kind, idx) under key (seed, 1), mapped as the uniforms
+ * above, is below audit_frac; an audited candidate gets its exact log L and
+ * that value decides.  Every accepted point therefore carries an exact log L;
+ * a screened-out candidate that lies inside the constraint (a false
+ * negative) shortens the bracket, which the audit counts.  n_evals counts
+ * exact evaluations only.  The network's input scaling and weights are read
+ * at each call; the same network may not be trained concurrently.
+ * Errors: GW_EINVAL (network from another context, non-finite margin,
+ * audit_frac outside [0, 1]).
+ */
 gw_status slice_step(gw_ctx* ctx, const gw_slice_args* args, void* stream);
 
 /*
@@ -365,7 +405,7 @@ typedef struct {
   uint64_t seed;           /* Philox key */
   uint64_t counter;        /* counter base of block 0 */
   double w;                /* bracket width along t (> 0) */
-  int32_t max_out;         /* >= 0 */
+  int32_t max_out;         /* 0 .. 10000, as for slice_step */
   int32_t max_shrink;      /* 1 .. 10000 */
   int32_t like;            /* GW_FULL or GW_HET */
   int32_t marg;            /* GW_MARG_PHASE_DIST */
@@ -380,6 +420,10 @@ typedef struct {
                               generated, seeding included), from the cached
                               waveform, and from the cached sums; -1 each
                               without the cache.  Synchronises the stream. */
+  gw_mlp* mlp;             /* learned prescreen or NULL, as for slice_step */
+  double margin;           /* as for slice_step */
+  double audit_frac;       /* as for slice_step */
+  int64_t* screen_stats;   /* as for slice_step (summed over the sweep) */
 } gw_sweep_args;
 
 gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* args, void* stream);
@@ -533,8 +577,6 @@ gw_status gw_wcache_loglike(gw_wcache* cache, const double* theta, const int32_t
  * FP32; inference runs the hidden layers with BF16 weights and activations on
  * the matrix cores, accumulated in FP32.
  */
-typedef struct gw_mlp gw_mlp;
-
 /* He-normal weights from ``seed``, zero biases; identity scaling. */
 gw_status gw_mlp_create(gw_ctx* ctx, uint64_t seed, gw_mlp** out);
 gw_status gw_mlp_destroy(gw_mlp* mlp);

@@ -1,13 +1,18 @@
 """Heterodyned (relative-binning) likelihood, FP64, step by step.
 
-Sec. III.D: a reference waveform h0 near the peak likelihood is used to
-compress the full-resolution inner products into per-detector summary data on
-a bin grid set by the source phasing ("bins of equal maximum phase change",
-shared across the network).  Within each bin the ratio r_i(f) = h_i(f; theta)
-/ h0_i(f) is expanded linearly, and the phase, time and distance
-marginalisations act on the binned inner products unchanged.  The paper defers
-the construction to the relative-binning method of Zackay, Dai & Venumadhav
-(2018) as implemented in Jim; the steps here are:
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+baseline use this module; the library never does.
+
+What is computed (Sec. III.D, which points to the relative-binning method of
+Zackay, Dai & Venumadhav 2018 for the details).  A fiducial template h0 is
+fixed once, close to where the likelihood peaks.  Per detector, the data and
+h0 are folded into a handful of sums per coarse frequency bin (the summary
+data); the bins are wide where the waveform's phase changes slowly and narrow
+where it changes fast, with one bin grid for all detectors.  For a template
+h, only the ratio r_i = h_i / h0_i is needed, and only at the bin edges: it
+is treated as a straight line across each bin.  The binned Z and <h|h> then
+feed the same log L and marginalisation formulae as the full-band sums.  The
+steps here:
 
 1. Phase bound Phi(f) = sum_g sgn(g) (f / f*_g)^g over
    g in {-5/3, -2/3, 1, 5/3, 7/3}, f*_g = f_max for g > 0 else f_min; it is

@@ -18,11 +18,14 @@ Readings used here (where the paper is silent):
   block covariance; a block may hold every coordinate (the unblocked nested
   slice sampler of the sampler-configuration section, run with M d joint
   steps per iteration); bracket width w along t, placed at a uniform offset;
-  stepping out at most ``max_out`` times per side; shrinking at most
-  ``max_shrink`` times, after which the chain keeps its point (status 1);
+  stepping out with a budget of m = 2 max_out + 1 split at random between
+  the two ends, J = floor(m V) steps for the lower end and m - 1 - J for the
+  upper one (the stepping-out procedure of Neal 2003, Sec. 4.1, which keeps
+  the move reversible when a cap binds); shrinking at most ``max_shrink``
+  times, after which the chain keeps its point (status 1);
 * a point outside the unit cube fails the constraint without an evaluation;
 * random numbers: explicit uniforms per chain, laid out as
-  [n_dir direction, 1 offset, max_shrink shrink draws] with
+  [n_dir direction, 1 offset, 1 budget split V, max_shrink shrink draws] with
   n_dir = max(4, 2 ceil(b / 2)) for a block of b coordinates (one Box-Muller
   pair per two coordinates, at least two pairs); or Philox4x64-10
   (Salmon et al. 2011), uniform j of chain c from counter
@@ -45,7 +48,7 @@ N_DIM = 11
 PRIOR_LO = np.array([1.1, 0.5, -0.05, -0.05, 0.0, 0.0])
 PRIOR_HI = np.array([1.4, 1.0, 0.05, 0.05, 5000.0, 5000.0])
 BLOCKS = ((0, 1, 4, 5), (2,), (3,), (6,), (7, 8), (9,), (10,))
-N_UNIFORM_FIXED = 5  # 4 direction + 1 offset (blocks of up to 4 coordinates)
+N_UNIFORM_FIXED = 6  # 4 direction + 1 offset + 1 budget split (blocks of up to 4 coordinates)
 
 _M0 = 0xD2E7470EE14C6C93
 _M1 = 0xCA5A826395121157
@@ -162,8 +165,9 @@ def n_direction_uniforms(b: int) -> int:
 
 
 def n_fixed_uniforms(b: int) -> int:
-    """Uniforms before the shrink draws: direction, then the bracket offset."""
-    return n_direction_uniforms(b) + 1
+    """Uniforms before the shrink draws: direction, the bracket offset, then
+    the split of the stepping-out budget."""
+    return n_direction_uniforms(b) + 2
 
 
 def direction(uni: np.ndarray, chol: np.ndarray) -> np.ndarray:
@@ -180,12 +184,23 @@ def direction(uni: np.ndarray, chol: np.ndarray) -> np.ndarray:
     return chol @ z
 
 
-def slice_chain(x0, logl0, logl_star, block, chol, uni, loglike, w=1.0, max_out=10, max_shrink=100):
+def slice_chain(x0, logl0, logl_star, block, chol, uni, loglike, w=1.0, max_out=10, max_shrink=100,
+                screen=None, screen_margin=0.0, audit_frac=0.0, stats=None):
     """One hit-and-run slice update of one chain on one block.
 
     Returns (x, logl, n_evals, status, min_margin): status 1 when the shrink cap
     was hit (old point kept); min_margin = smallest |logL - logL*| seen, which
     tells a caller how close a comparison came to a tie.
+
+    Learned prescreen (an addition; the paper's sampler evaluates every
+    candidate): with ``screen`` a callable (x, kind, index) -> (prediction,
+    audit uniform), for the index-th test of a kind (0 lower end, 1 upper
+    end, 2 shrink draw, counted within the block), a candidate inside the
+    cube gets its exact log L only when the prediction is at least
+    log L* - screen_margin or the audit uniform is below audit_frac;
+    otherwise it counts as outside the constraint with no evaluation.  The
+    closest |prediction - cut| enters min_margin too.  ``stats`` (a dict)
+    accumulates 'screened', 'audited' and 'audited_inside'.
     """
     x0 = np.asarray(x0, dtype=np.float64)
     idx = np.asarray(block)
@@ -198,33 +213,50 @@ def slice_chain(x0, logl0, logl_star, block, chol, uni, loglike, w=1.0, max_out=
         x[idx] = x0[idx] + t * d
         return x
 
-    def ok(t):
+    def ok(t, kind=0, index=0):
         nonlocal n_evals, margin
         x = point(t)
         if np.any(x[idx] < 0.0) or np.any(x[idx] > 1.0):
             return False, x, -math.inf
+        audited = False
+        if screen is not None:
+            pred, u_audit = screen(x, kind, index)
+            cut = logl_star - screen_margin
+            margin = min(margin, abs(pred - cut))
+            if not pred >= cut:
+                if not u_audit < audit_frac:
+                    if stats is not None:
+                        stats["screened"] = stats.get("screened", 0) + 1
+                    return False, x, -math.inf
+                audited = True
         v = loglike(x)
         n_evals += 1
         margin = min(margin, abs(v - logl_star))
+        if audited and stats is not None:
+            stats["audited"] = stats.get("audited", 0) + 1
+            stats["audited_inside"] = stats.get("audited_inside", 0) + int(v > logl_star)
         return v > logl_star, x, v
 
     nfix = n_fixed_uniforms(len(block))
-    r = uni[nfix - 1]
+    r = uni[nfix - 2]
     t_lo = -r * w
     t_hi = (1.0 - r) * w
-    for _ in range(max_out):
-        good, _, _ = ok(t_lo)
+    budget = 2 * max_out + 1
+    j_lo = int(math.floor(budget * uni[nfix - 1]))
+    j_hi = budget - 1 - j_lo
+    for i in range(j_lo):
+        good, _, _ = ok(t_lo, 0, i)
         if not good:
             break
         t_lo -= w
-    for _ in range(max_out):
-        good, _, _ = ok(t_hi)
+    for i in range(j_hi):
+        good, _, _ = ok(t_hi, 1, i)
         if not good:
             break
         t_hi += w
     for s in range(max_shrink):
         t = t_lo + uni[nfix + s] * (t_hi - t_lo)
-        good, x, v = ok(t)
+        good, x, v = ok(t, 2, s)
         if good:
             return x, v, n_evals, 0, margin
         if t < 0.0:

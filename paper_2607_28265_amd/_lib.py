@@ -69,6 +69,10 @@ class gw_slice_args(ctypes.Structure):
         ("n_evals", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
         ("use_graph", ctypes.c_int32),
+        ("mlp", ctypes.c_void_p),
+        ("margin", ctypes.c_double),
+        ("audit_frac", ctypes.c_double),
+        ("screen_stats", ctypes.POINTER(ctypes.c_int64)),
     ]
 
 
@@ -95,6 +99,10 @@ class gw_sweep_args(ctypes.Structure):
         ("use_graph", ctypes.c_int32),
         ("use_cache", ctypes.c_int32),
         ("eval_kinds", ctypes.POINTER(ctypes.c_int64)),
+        ("mlp", ctypes.c_void_p),
+        ("margin", ctypes.c_double),
+        ("audit_frac", ctypes.c_double),
+        ("screen_stats", ctypes.POINTER(ctypes.c_int64)),
     ]
 
 
@@ -402,14 +410,35 @@ def gw_autotune(ctx, theta, like: int, marg: int, prec: int, reps: int = 3, stre
 
 def slice_uniforms_fixed(block_dim: int) -> int:
     """Uniforms of a slice update before its shrink draws (GW_SLICE_UNI_FIXED)."""
-    return (4 if block_dim <= 4 else 2 * ((block_dim + 1) // 2)) + 1
+    return (4 if block_dim <= 4 else 2 * ((block_dim + 1) // 2)) + 2
+
+
+def _set_screen(a, prescreen, screen_stats):
+    """Prescreen fields of a slice/sweep argument block: ``prescreen`` is None
+    or (Mlp, margin, audit_frac); ``screen_stats`` a dict that receives the
+    counts (screened out, audited, audited and inside)."""
+    buf = (ctypes.c_int64 * 3)()
+    if prescreen is not None:
+        net, margin, audit = prescreen
+        a.mlp = net._m.value if isinstance(net._m, ctypes.c_void_p) else net._m
+        a.margin = float(margin)
+        a.audit_frac = float(audit)
+        if screen_stats is not None:
+            a.screen_stats = buf
+    return buf
+
+
+def _fill_screen(buf, prescreen, screen_stats):
+    if prescreen is not None and screen_stats is not None:
+        screen_stats.update(screened=int(buf[0]), audited=int(buf[1]), audited_inside=int(buf[2]))
 
 
 def slice_step(ctx, x, logl, logl_star: float, block, chol, seed: int = 0, counter: int = 0, uniforms=None,
                w: float = 1.0, max_out: int = 10, max_shrink: int = 100, like: int = GW_HET,
                marg: int = GW_MARG_PHASE_DIST, prec: int = GW_PREC_FP64, n_evals=None, status=None, stream=None,
-               use_graph: bool = True):
-    """One slice update of one block for every chain; x [k, 11] and logl [k] (CUDA float64) change in place."""
+               use_graph: bool = True, prescreen=None, screen_stats=None):
+    """One slice update of one block for every chain; x [k, 11] and logl [k] (CUDA float64) change in place.
+    ``prescreen`` = (Mlp, margin, audit_frac) screens candidates with the network (see gwswig.h)."""
     import numpy as np
     import torch
     if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == 11):
@@ -433,7 +462,9 @@ def slice_step(ctx, x, logl, logl_star: float, block, chol, seed: int = 0, count
                       max_out=int(max_out), max_shrink=int(max_shrink), like=int(like), marg=int(marg),
                       prec=int(prec), n_evals=n_evals.data_ptr() if n_evals is not None else None,
                       status=status.data_ptr() if status is not None else None, use_graph=1 if use_graph else 0)
+    buf = _set_screen(a, prescreen, screen_stats)
     check(load().slice_step(ctx, ctypes.byref(a), _stream_ptr(stream)), "slice_step")
+    _fill_screen(buf, prescreen, screen_stats)
 
 
 def _check_chains(x, logl, n_evals, status):
@@ -452,12 +483,13 @@ def _check_chains(x, logl, n_evals, status):
 def slice_sweep(ctx, x, logl, logl_star: float, blocks, chols, seed: int = 0, counter: int = 0, w: float = 1.0,
                 max_out: int = 10, max_shrink: int = 100, like: int = GW_HET, marg: int = GW_MARG_PHASE_DIST,
                 prec: int = GW_PREC_FP64, n_evals=None, status=None, stream=None, use_graph: bool = True,
-                use_cache: bool = False):
+                use_cache: bool = False, prescreen=None, screen_stats=None):
     """One sweep over ``blocks`` (list of index lists, with their Cholesky
     factors ``chols``) for every chain, block b with Philox counter
     counter + b; x [k, 11] and logl [k] change in place.  Returns the
     evaluations by kind (full, cached waveform, cached sums) with the
-    waveform cache, else None."""
+    waveform cache, else None.  ``prescreen`` / ``screen_stats`` as for
+    slice_step."""
     import numpy as np
     k = _check_chains(x, logl, n_evals, status)
     nb = len(blocks)
@@ -484,7 +516,9 @@ def slice_sweep(ctx, x, logl, logl_star: float, blocks, chols, seed: int = 0, co
     kinds = (ctypes.c_int64 * 3)()
     if use_cache:
         a.eval_kinds = kinds
+    buf = _set_screen(a, prescreen, screen_stats)
     check(load().slice_sweep(ctx, ctypes.byref(a), _stream_ptr(stream)), "slice_sweep")
+    _fill_screen(buf, prescreen, screen_stats)
     return (kinds[0], kinds[1], kinds[2]) if use_cache else None
 
 

@@ -117,6 +117,11 @@ gw_status launch_cached(gw_ctx* ctx, const double* coef, int64_t n, int prec, in
 gw_status launch_epilogue_cached(gw_ctx* ctx, double* partial, int n_chunks, const double* coef, int64_t ld,
                                  int64_t n, int marg, int prec, double* logl, const int32_t* zsrc, const double* zc,
                                  double* zrow, hipStream_t st);
+// As launch_epilogue_cached, with the distance marginal's (|Z_1|, <h|h>_1)
+// staging buffer [2][n] given explicitly instead of the context's.
+gw_status launch_epilogue_z(gw_ctx* ctx, double* partial, int n_chunks, const double* coef, int64_t ld, int64_t n,
+                            int marg, int prec, double* logl, const int32_t* zsrc, const double* zc, double* zrow,
+                            double* zbuf, hipStream_t st);
 gw_status launch_wmom_build(gw_ctx* ctx, const double* coef, int64_t ld, const int32_t* slots, const int32_t* count,
                             int rows_per_slot, const int32_t* src, float2* mom, hipStream_t st);
 // Cached-likelihood launch shape (64 rows per workgroup, chunks of ~512 bins)
@@ -130,6 +135,16 @@ void full_launch_shape(const gw_ctx* ctx, int64_t n, int* tpb, int* n_chunks);
 gw_status build_moment_table(gw_ctx* ctx, const std::vector<double>& rec, const double* det_pos);
 // Measure the hardware phasor bias and set ctx->pgain_re / pgain_im.
 gw_status calibrate_phasor(gw_ctx* ctx);
+
+// Prescreen network hooks for the sampler (gw_mlp.hip): the context a
+// network was made on; a counter that changes whenever its input/output
+// scaling changes (a captured inference launch bakes the scaling in);
+// refreshing the BF16 weight copies (not inside a capture); the BF16
+// inference of n unit-cube rows x [n][11] into out [n] (log L units).
+const gw_ctx* mlp_ctx(const gw_mlp* m);
+uint64_t mlp_scale_version(const gw_mlp* m);
+gw_status mlp_prepare(gw_mlp* m, hipStream_t st);
+gw_status mlp_infer(gw_mlp* m, const double* x, int64_t n, double* out, hipStream_t st);
 
 // Kernel timing: record a start / stop event pair around the dominant kernel.
 // prof_begin returns the pair index or -1 when timing is off or full.

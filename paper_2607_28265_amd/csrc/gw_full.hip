@@ -1307,6 +1307,12 @@ gw_status launch_epilogue(gw_ctx* ctx, double* partial, int n_chunks, const doub
 gw_status launch_epilogue_cached(gw_ctx* ctx, double* partial, int n_chunks, const double* coef, int64_t ld,
                                  int64_t n, int marg, int prec, double* logl, const int32_t* zsrc, const double* zc,
                                  double* zrow, hipStream_t st) {
+  return launch_epilogue_z(ctx, partial, n_chunks, coef, ld, n, marg, prec, logl, zsrc, zc, zrow, ctx->zbuf, st);
+}
+
+gw_status launch_epilogue_z(gw_ctx* ctx, double* partial, int n_chunks, const double* coef, int64_t ld, int64_t n,
+                            int marg, int prec, double* logl, const int32_t* zsrc, const double* zc, double* zrow,
+                            double* zbuf, hipStream_t st) {
   if (n == 0) return GW_OK;
   const int64_t blocks = (n + 63) / 64;
   LogI0Consts C = make_log_i0_consts();
@@ -1322,24 +1328,24 @@ gw_status launch_epilogue_cached(gw_ctx* ctx, double* partial, int n_chunks, con
     if (s != GW_OK) return s;
   }
   hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(1024), 0, st, partial, groups, cstride, ctx->n_det, coef,
-                     ld, n, ctx->dd, marg, C, logl, ctx->zbuf, zsrc, zc, zrow);
+                     ld, n, ctx->dd, marg, C, logl, zbuf, zsrc, zc, zrow);
   gw_status s = check_hip(hipGetLastError(), "epilogue launch");
   if (s != GW_OK || marg != 2) return s;
   if (n >= kDistSliced) {
     const int64_t dblocks = (n + 63) / 64;
     if (prec == GW_PREC_MIXED)
-      hipLaunchKernelGGL(k_dist_marg<1>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, ctx->zbuf, n,
+      hipLaunchKernelGGL(k_dist_marg<1>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, zbuf, n,
                          ctx->dist_tab, ctx->n_dist, ctx->dd, C, logl);
     else
-      hipLaunchKernelGGL(k_dist_marg<0>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, ctx->zbuf, n,
+      hipLaunchKernelGGL(k_dist_marg<0>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, zbuf, n,
                          ctx->dist_tab, ctx->n_dist, ctx->dd, C, logl);
   } else {
     const int64_t dblocks = (n + 3) / 4;
     if (prec == GW_PREC_MIXED)
-      hipLaunchKernelGGL(k_dist_marg_w<1>, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_tab,
+      hipLaunchKernelGGL(k_dist_marg_w<1>, dim3((unsigned)dblocks), dim3(256), 0, st, zbuf, n, ctx->dist_tab,
                          ctx->n_dist, ctx->dd, C, logl);
     else
-      hipLaunchKernelGGL(k_dist_marg_w<0>, dim3((unsigned)dblocks), dim3(256), 0, st, ctx->zbuf, n, ctx->dist_tab,
+      hipLaunchKernelGGL(k_dist_marg_w<0>, dim3((unsigned)dblocks), dim3(256), 0, st, zbuf, n, ctx->dist_tab,
                          ctx->n_dist, ctx->dd, C, logl);
   }
   return check_hip(hipGetLastError(), "distance marginal launch");

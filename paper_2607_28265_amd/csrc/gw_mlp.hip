@@ -422,6 +422,7 @@ struct gw_mlp {
   bool q_dirty = true;
   int64_t t = 0;
   MlpScale sc{};
+  uint64_t sc_version = 0;  // bumped whenever sc changes (a captured launch bakes sc in)
   float* ws = nullptr;  // training workspace
   int64_t ws_rows = 0;
   float* part = nullptr;  // split-K partials
@@ -568,6 +569,28 @@ uint64_t splitmix(uint64_t& s) {
 
 }  // namespace
 
+namespace gw {
+
+const gw_ctx* mlp_ctx(const gw_mlp* m) { return m->ctx; }
+
+uint64_t mlp_scale_version(const gw_mlp* m) { return m->sc_version; }
+
+gw_status mlp_prepare(gw_mlp* m, hipStream_t st) {
+  if (!m->q_dirty) return GW_OK;
+  hipLaunchKernelGGL(k_to_bf16, dim3(nblk(kNQ)), dim3(256), 0, st, m->p, m->q);
+  gw_status s = check_hip(hipGetLastError(), "bf16 conversion launch");
+  if (s == GW_OK) m->q_dirty = false;
+  return s;
+}
+
+gw_status mlp_infer(gw_mlp* m, const double* x, int64_t n, double* out, hipStream_t st) {
+  if (n == 0) return GW_OK;
+  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, x, n, m->sc, m->q, m->p, out);
+  return check_hip(hipGetLastError(), "mlp inference launch");
+}
+
+}  // namespace gw
+
 extern "C" {
 
 gw_status gw_mlp_create(gw_ctx* ctx, uint64_t seed, gw_mlp** out) {
@@ -654,6 +677,7 @@ gw_status gw_mlp_set_scaling(gw_mlp* m, const double* x_mean, const double* x_st
   }
   m->sc.ym = y_mean;
   m->sc.ys = y_std;
+  m->sc_version += 1;
   return GW_OK;
 }
 

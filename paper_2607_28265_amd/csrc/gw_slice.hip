@@ -7,7 +7,11 @@
 // rounds: a propose kernel writes every chain's candidate points as parameter
 // vectors, the batched likelihood evaluates them all, and an update kernel
 // moves each chain's state machine (to its next block once one is done); the
-// host checks for completion every few rounds.
+// host checks for completion every few rounds.  With a prescreen network the
+// round also runs the network on every candidate's unit-cube point between
+// propose and likelihood: a candidate predicted below log L* - margin is taken
+// as outside the constraint without a likelihood call, unless it is drawn for
+// the audit; every accepted point has an exact log L.
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -25,9 +29,9 @@ constexpr int kMaxBlocks = 16;  // blocks per sweep
 constexpr int kCholPack = 160;  // doubles of packed Cholesky factors per sweep
 
 // Uniforms before the shrink draws of a block of bd coordinates: one
-// Box-Muller pair per two coordinates (at least two pairs), then the bracket
-// offset.
-__host__ __device__ inline int uni_fixed(int bd) { return (bd <= 4 ? 4 : 2 * ((bd + 1) / 2)) + 1; }
+// Box-Muller pair per two coordinates (at least two pairs), the bracket
+// offset, then the split of the stepping-out budget between the two ends.
+__host__ __device__ inline int uni_fixed(int bd) { return (bd <= 4 ? 4 : 2 * ((bd + 1) / 2)) + 2; }
 
 // How the sampler's last coordinate is read: t_c (phase and distance
 // marginalised) or d_L (phase and time marginalised).
@@ -70,6 +74,13 @@ struct SweepParams {
   CubeMap cm;
   int32_t n_det;
   int32_t kind[kMaxBlocks];
+  // prescreen: screen = 1 runs the network; a candidate needs its exact log L
+  // when the prediction is >= cut (= log L* - margin) or when its audit draw
+  // (Philox4x64-10, key (seed, 1), counter (counter + b, c, kind, index),
+  // word 0, mapped to (0, 1)) is below audit_frac
+  int32_t screen;
+  double cut;
+  double audit_frac;
 };
 
 // passed by value to the kernel that copies it to the device
@@ -83,7 +94,7 @@ struct SliceState {
   double* d;        // [k][kMaxBlock]
   double* cand_t;   // [k][2]
   int32_t* flags;   // [k]: bit0 lo stepping, bit1 hi stepping, bit2 sweep done
-  int32_t* n_out;   // [k][2]
+  int32_t* n_out;   // [k][2]: steps left to each end's share of the stepping-out budget
   int32_t* n_shrink;
   int32_t* n_evals;  // likelihood calls in the current block
   int32_t* slot_ok;  // [k][2]: candidate inside the cube and needs a likelihood
@@ -95,6 +106,7 @@ struct SliceState {
   int32_t* rkind;      // [2k]: 0 no likelihood, 1 full, 2 cached waveform, 3 cached sums
   int32_t* zsrc;       // [2k]: slot whose cached sums the row uses, or -1
   int32_t* build_list;  // [k]: chains whose waveform is rebuilt after this round
+  int32_t* build_src;  // [k]: the candidate row each rebuild takes its coefficients from
   int32_t* dirty;      // [k]: the chain's cached waveform is older than its point
   int32_t* slow_rows;  // [2k]
   int32_t* stream_rows;  // [2k]
@@ -103,6 +115,12 @@ struct SliceState {
   double* zrow;        // [2k][2 n_det]: every row's sums z_i
   double* zc;          // [k][2 n_det]: the sums at each chain's current point, then
                        // [2k][2 n_det]: the cached-waveform rows' sums
+  // prescreen
+  double* ucand;       // [2k][11]: each slot's unit-cube point (the network's input)
+  double* pred;        // [2k]: the network's log L
+  int32_t* scr;        // [2k]: 0 evaluated (predicted inside), 1 screened out, 2 audited
+  int32_t* side_tests; // [k][2]: stepping-out tests made at each end in this block
+  unsigned long long* scr_tot;  // [3]: screened out, audited, audited and inside (false negatives)
 };
 
 // Uniform j of chain c in block b: explicit table, or Philox word j % 4 of
@@ -112,6 +130,14 @@ __device__ inline double slice_uniform(const SweepParams& P, int b, int64_t c, i
   uint64_t ctr[4] = {P.counter + (uint64_t)b, (uint64_t)c, (uint64_t)(j >> 2), 0ull};
   philox4x64(ctr, P.seed, 0ull);
   return philox_unit(ctr[j & 3]);
+}
+
+// Audit draw of a screened candidate: test ``idx`` of kind ``kind`` (0 lower
+// end, 1 upper end, 2 shrink draw) of chain c in block b.
+__device__ inline double audit_uniform(const SweepParams& P, int b, int64_t c, int kind, int idx) {
+  uint64_t ctr[4] = {P.counter + (uint64_t)b, (uint64_t)c, (uint64_t)kind, (uint64_t)idx};
+  philox4x64(ctr, P.seed, 1ull);
+  return philox_unit(ctr[0]);
 }
 
 // Unit cube -> 13-column parameter vector.  Coordinate 10 is t_c in [-0.1,
@@ -153,7 +179,12 @@ __device__ inline void prior_transform(const double* u, double* th, const CubeMa
 
 // Start block b for chain c: direction d = L u (u from Box-Muller normals,
 // pair p from uniforms 2p and 2p + 1, normalised), bracket [-r w, (1 - r) w]
-// with r the uniform after the direction ones.  Returns the chain's new flags.
+// with r the uniform after the direction ones, and the stepping-out budget
+// m = 2 max_out + 1 split by the next uniform V into J = floor(m V) steps for
+// the lower end and m - 1 - J for the upper one (Neal 2003, Sec. 4.1: with
+// the split drawn at random, every point of the final bracket is equally
+// likely to have produced it, so the move stays reversible when a cap
+// binds).  Returns the chain's new flags.
 __device__ inline int start_block(const SweepParams& P, const SliceState& S, int64_t c, int b) {
   const int bd = P.bd[b];
   const int nfix = uni_fixed(bd);
@@ -175,15 +206,20 @@ __device__ inline int start_block(const SweepParams& P, const SliceState& S, int
       if (a < bd) v += L[a * bd + q] * (z[q] / nrm);
     S.d[c * kMaxBlock + a] = a < bd ? v : 0.0;
   }
-  const double off = slice_uniform(P, b, c, nfix - 1);
+  const double off = slice_uniform(P, b, c, nfix - 2);
   S.t_lo[c] = -off * P.w;
   S.t_hi[c] = (1.0 - off) * P.w;
-  S.n_out[2 * c] = 0;
-  S.n_out[2 * c + 1] = 0;
+  const int budget = 2 * P.max_out + 1;
+  const int j_lo = (int)floor((double)budget * slice_uniform(P, b, c, nfix - 1));
+  const int j_hi = budget - 1 - j_lo;
+  S.n_out[2 * c] = j_lo;
+  S.n_out[2 * c + 1] = j_hi;
+  S.side_tests[2 * c] = 0;
+  S.side_tests[2 * c + 1] = 0;
   S.n_shrink[c] = 0;
   S.n_evals[c] = 0;
   S.cur[c] = b;
-  return P.max_out > 0 ? 3 : 0;
+  return (j_lo > 0 ? 1 : 0) | (j_hi > 0 ? 2 : 0);
 }
 
 // The current block of chain c ends (moved, or kept when capped): count it
@@ -208,11 +244,13 @@ __device__ inline bool make_point(const SweepParams& P, int b, const SliceState&
   return inside;
 }
 
-__global__ void k_sweep_set(SweepParams* D, SweepParams P, unsigned long long* kind_tot) {
+__global__ void k_sweep_set(SweepParams* D, SweepParams P, unsigned long long* kind_tot,
+                            unsigned long long* scr_tot) {
   *D = P;
-  kind_tot[0] = 0;
-  kind_tot[1] = 0;
-  kind_tot[2] = 0;
+  for (int i = 0; i < 3; ++i) {
+    kind_tot[i] = 0;
+    scr_tot[i] = 0;
+  }
 }
 
 __global__ void k_sweep_init(const SweepParams* __restrict__ D, SliceState S) {
@@ -248,6 +286,11 @@ __global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S,
           prior_transform(u, cand + (2 * c + side) * 13, P.cm);
           S.cand_t[2 * c + side] = t;
           ok[side] = 1;
+          if (P.screen) {
+            for (int j = 0; j < kSliceDim; ++j) S.ucand[(2 * c + side) * kSliceDim + j] = u[j];
+            S.scr[2 * c + side] =
+                audit_uniform(P, b, c, side, S.side_tests[2 * c + side]) < P.audit_frac ? 2 : 0;
+          }
         } else {
           fl &= ~(1 << side);  // outside the cube: this side stops here
         }
@@ -263,6 +306,10 @@ __global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S,
           prior_transform(u, cand + 2 * c * 13, P.cm);
           S.cand_t[2 * c] = t;
           ok[0] = 1;
+          if (P.screen) {
+            for (int j = 0; j < kSliceDim; ++j) S.ucand[2 * c * kSliceDim + j] = u[j];
+            S.scr[2 * c] = audit_uniform(P, b, c, 2, S.n_shrink[c]) < P.audit_frac ? 2 : 0;
+          }
           break;
         }
         if (t < 0.0) S.t_lo[c] = t;
@@ -278,6 +325,10 @@ __global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S,
       double* th = cand + (2 * c + side) * 13;
       for (int j = 0; j < 13; ++j) th[j] = 0.0;
       th[1] = -1.0;
+      if (P.screen) {
+        for (int j = 0; j < kSliceDim; ++j) S.ucand[(2 * c + side) * kSliceDim + j] = 0.5;
+        S.scr[2 * c + side] = 0;
+      }
     }
   S.slot_ok[2 * c] = ok[0];
   S.slot_ok[2 * c + 1] = ok[1];
@@ -295,6 +346,24 @@ __global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S,
   }
 }
 
+// Prescreen decision per candidate slot (after the network has written pred):
+// a slot predicted below the cut and not audited gets no likelihood call.
+__global__ void k_sweep_screen(const SweepParams* __restrict__ D, SliceState S, double* __restrict__ cand) {
+  const SweepParams& P = *D;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 2 * P.k || !S.slot_ok[r]) return;
+  if (S.pred[r] >= P.cut) {
+    S.scr[r] = 0;
+    return;
+  }
+  if (S.scr[r] == 2) return;  // audited: evaluated although predicted outside
+  S.scr[r] = 1;
+  if (P.lists) S.rkind[r] = 0;
+  double* th = cand + r * 13;  // the batched forms: a row that costs an unphysical -inf
+  for (int j = 0; j < 13; ++j) th[j] = 0.0;
+  th[1] = -1.0;
+}
+
 __global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, const double* __restrict__ cand_logl) {
   const SweepParams& P = *D;
   double* __restrict__ x = P.x;
@@ -303,27 +372,48 @@ __global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, 
   if (c >= P.k) return;
   int fl = S.flags[c];
   if (fl & 4) return;
-  const int b = S.cur[c];
+  const int b = S.cur[c];  // the block of this round's rows
   const bool stepping = (fl & 3) != 0;
+  bool moved = false;
   if (stepping) {
     for (int side = 0; side < 2; ++side) {
       if (!S.slot_ok[2 * c + side]) continue;
-      S.n_evals[c] += 1;
-      const bool in = cand_logl[2 * c + side] > P.logl_star;
-      int no = S.n_out[2 * c + side];
-      if (in && no < P.max_out) {
+      S.side_tests[2 * c + side] += 1;
+      bool in;
+      if (P.screen && S.scr[2 * c + side] == 1) {
+        atomicAdd(&S.scr_tot[0], 1ull);
+        in = false;
+      } else {
+        S.n_evals[c] += 1;
+        in = cand_logl[2 * c + side] > P.logl_star;
+        if (P.screen && S.scr[2 * c + side] == 2) {
+          atomicAdd(&S.scr_tot[1], 1ull);
+          if (in) atomicAdd(&S.scr_tot[2], 1ull);
+        }
+      }
+      int left = S.n_out[2 * c + side];  // > 0 while this end is active
+      if (in && left > 0) {
         if (side == 0) S.t_lo[c] -= P.w;
         else S.t_hi[c] += P.w;
-        no += 1;
-        S.n_out[2 * c + side] = no;
-        if (no >= P.max_out) fl &= ~(1 << side);
+        left -= 1;
+        S.n_out[2 * c + side] = left;
+        if (left == 0) fl &= ~(1 << side);
       } else {
         fl &= ~(1 << side);
       }
     }
   } else if (S.slot_ok[2 * c]) {
-    S.n_evals[c] += 1;
-    const double v = cand_logl[2 * c];
+    double v = -INFINITY;
+    if (P.screen && S.scr[2 * c] == 1) {
+      atomicAdd(&S.scr_tot[0], 1ull);
+    } else {
+      S.n_evals[c] += 1;
+      v = cand_logl[2 * c];
+      if (P.screen && S.scr[2 * c] == 2) {
+        atomicAdd(&S.scr_tot[1], 1ull);
+        if (v > P.logl_star) atomicAdd(&S.scr_tot[2], 1ull);
+      }
+    }
     const double t = S.cand_t[2 * c];
     if (v > P.logl_star) {
       for (int a = 0; a < P.bd[b]; ++a) {
@@ -338,6 +428,7 @@ __global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, 
           if (j < 2 * P.n_det) S.zc[c * 2 * P.n_det + j] = S.zrow[2 * c * 2 * P.n_det + j];
         if (P.kind[b] == 0) S.dirty[c] = 1;
       }
+      moved = true;
       fl = finish_block(P, S, c, false);
     } else {
       if (t < 0.0) S.t_lo[c] = t;
@@ -349,11 +440,29 @@ __global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, 
   S.flags[c] = fl;
   if (!(fl & 4)) {
     atomicAdd(S.n_active, 1);
-    // the waveform is rebuilt lazily: when a chain is in an extrinsic block
-    // with a stale cache, after this round
+    // The waveform is rebuilt lazily, when a chain is in an extrinsic block
+    // with a stale cache, after this round, from the coefficients of a row of
+    // this round that has the chain's intrinsic parameters: the accepted row
+    // after a move, else a row proposed in a block that keeps them (extrinsic
+    // or projection-only) and not screened out.  A round without one (a slow
+    // block ended at its shrink cap, an end that was never proposed) leaves
+    // the cache stale; the next round's rows then evaluate in full and serve.
     if (P.cache && P.kind[S.cur[c]] == 1 && S.dirty[c]) {
-      S.dirty[c] = 0;
-      S.build_list[atomicAdd(&S.counts[2], 1)] = (int32_t)c;
+      int src = -1;
+      if (moved) {
+        src = (int)(2 * c);
+      } else if (P.kind[b] != 0) {
+        for (int side = 1; side >= 0; --side) {
+          const int64_t r = 2 * c + side;
+          if (S.slot_ok[r] && !(P.screen && S.scr[r] == 1)) src = (int)r;
+        }
+      }
+      if (src >= 0) {
+        S.dirty[c] = 0;
+        const int pos = atomicAdd(&S.counts[2], 1);
+        S.build_list[pos] = (int32_t)c;
+        S.build_src[pos] = src;
+      }
     }
   }
 }
@@ -455,7 +564,8 @@ using namespace gw;
 struct SliceGraphKey {
   int64_t k;
   int32_t like, marg, prec, cache;
-  const void *ws_mem, *coef, *partial, *zbuf, *het, *wc;
+  const void *ws_mem, *coef, *partial, *zbuf, *het, *wc, *mlp;
+  uint64_t mlp_scale;
   int32_t het_wpb, het_grid, het_ech, full_tpb, full_chunks, full_kernel;
   bool operator==(const SliceGraphKey& o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
 };
@@ -466,7 +576,7 @@ struct gw_slice_ws {
   double* cand = nullptr;       // [2k][13]
   double* cand_logl = nullptr;  // [2k]
   int32_t* h_active = nullptr;  // pinned host [2]: chains still moving after a group, double-buffered
-  unsigned long long* h_kinds = nullptr;  // pinned host [3]
+  unsigned long long* h_kinds = nullptr;  // pinned host [6]: evaluation kinds, then prescreen counts
   hipEvent_t ev[2] = {nullptr, nullptr};  // readback of h_active[i] complete
   SliceState S{};
   SweepParams* dev = nullptr;   // device parameter block
@@ -490,6 +600,8 @@ struct SweepCall {
   int32_t cache;
   int64_t* eval_kinds;  // host [3] or null
   int32_t lists;        // full band: row-list likelihood (always with the cache)
+  gw_mlp* mlp;          // prescreen network or null
+  int64_t* screen_stats;  // host [3] or null
 };
 
 // Launch shape of the row-list likelihood: 64 rows per workgroup, its four
@@ -556,6 +668,8 @@ static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const Swee
   key.full_tpb = ctx->full_tpb;
   key.full_chunks = ctx->full_chunks;
   key.full_kernel = ctx->full_kernel;
+  key.mlp = a.mlp;
+  key.mlp_scale = a.mlp ? mlp_scale_version(a.mlp) : 0;
   if (ws->have_graph && ws->key == key) return GW_OK;
   if (ws->exec) (void)hipGraphExecDestroy(ws->exec);
   if (ws->graph) (void)hipGraphDestroy(ws->graph);
@@ -634,8 +748,8 @@ static gw_status check_sweep(const char* who, int64_t k, const double* x, const 
   if (k < 0) return set_error(GW_EINVAL, "%s: k < 0", who);
   if (k > 0 && (!x || !logl)) return set_error(GW_EINVAL, "%s: null pointer", who);
   if (!(w > 0.0) || !isfinite(w)) return set_error(GW_EINVAL, "%s: w must be > 0", who);
-  if (max_out < 0 || max_shrink < 1 || max_shrink > 10000)
-    return set_error(GW_EINVAL, "%s: max_out >= 0, max_shrink 1..10000", who);
+  if (max_out < 0 || max_out > 10000 || max_shrink < 1 || max_shrink > 10000)
+    return set_error(GW_EINVAL, "%s: max_out 0..10000, max_shrink 1..10000", who);
   if (marg == GW_MARG_NONE)
     return set_error(GW_ENOTSUP, "%s: the 11-D sampler needs phi_c and d_L, or phi_c and t_c, marginalised", who);
   if (marg != GW_MARG_PHASE_DIST && marg != GW_MARG_PHASE_TIME)
@@ -644,6 +758,20 @@ static gw_status check_sweep(const char* who, int64_t k, const double* x, const 
     return set_error(GW_EINVAL, "%s: like must be GW_FULL or GW_HET", who);
   if (like == GW_HET && !ctx->het)
     return set_error(GW_ESTATE, "%s: heterodyne_setup has not been called", who);
+  return GW_OK;
+}
+
+// Prescreen arguments shared by both entry points.
+static gw_status set_screen(const char* who, const gw_ctx* ctx, gw_mlp* mlp, double margin, double audit_frac,
+                            SweepParams& P) {
+  P.screen = 0;
+  if (!mlp) return GW_OK;
+  if (mlp_ctx(mlp) != ctx) return set_error(GW_EINVAL, "%s: the prescreen network belongs to another context", who);
+  if (!isfinite(margin)) return set_error(GW_EINVAL, "%s: margin must be finite", who);
+  if (!(audit_frac >= 0.0 && audit_frac <= 1.0)) return set_error(GW_EINVAL, "%s: audit_frac in [0, 1]", who);
+  P.screen = 1;
+  P.cut = P.logl_star - margin;
+  P.audit_frac = audit_frac;
   return GW_OK;
 }
 
@@ -696,7 +824,11 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
   const int64_t k = P.k;
   const int tpb = 256;
   const unsigned blocks = (unsigned)((k + tpb - 1) / tpb);
-  hipLaunchKernelGGL(k_sweep_set, dim3(1), dim3(1), 0, st, ws->dev, P, ws->S.kind_tot);
+  if (a.mlp) {
+    s = mlp_prepare(a.mlp, st);  // BF16 weights current before any capture or launch
+    if (s != GW_OK) return s;
+  }
+  hipLaunchKernelGGL(k_sweep_set, dim3(1), dim3(1), 0, st, ws->dev, P, ws->S.kind_tot, ws->S.scr_tot);
   hipLaunchKernelGGL(k_sweep_init, dim3(blocks), dim3(tpb), 0, st, (const SweepParams*)ws->dev, ws->S);
   s = check_hip(hipGetLastError(), "slice init launch");
   if (s == GW_OK && a.cache) {
@@ -711,18 +843,27 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
   }
   // One group = 4 rounds of (propose, batched likelihood, update); after a
   // group the number of chains still moving is copied back.  A block takes at
-  // most max_out + 1 stepping rounds (both sides in parallel) and max_shrink
-  // shrink rounds, so after max_rounds every chain is done.  Rounds after every
+  // most 2 max_out stepping rounds (both ends in parallel, their shares
+  // summing to 2 max_out) and max_shrink shrink rounds, so after max_rounds
+  // every chain is done.  Rounds after every
   // chain is done change nothing, so the next group is queued before the
   // previous group's count is read: the host waits on group g while group
   // g + 1 runs, and at most one group of idle rounds follows the last move.
-  const int max_rounds = P.nb * (P.max_out + 1 + P.max_shrink + 1);
+  const int max_rounds = P.nb * (2 * P.max_out + 1 + P.max_shrink + 1);
   auto group = [&](hipStream_t gs) -> gw_status {
     gw_status g = GW_OK;
     for (int r = 0; r < 4 && g == GW_OK; ++r) {
       hipLaunchKernelGGL(k_sweep_propose, dim3(blocks), dim3(tpb), 0, gs, (const SweepParams*)ws->dev, ws->S,
                          ws->cand);
       g = check_hip(hipGetLastError(), "slice propose launch");
+      if (g == GW_OK && a.mlp) {
+        g = mlp_infer(a.mlp, ws->S.ucand, 2 * k, ws->S.pred, gs);
+        if (g == GW_OK) {
+          hipLaunchKernelGGL(k_sweep_screen, dim3((unsigned)((2 * k + tpb - 1) / tpb)), dim3(tpb), 0, gs,
+                             (const SweepParams*)ws->dev, ws->S, ws->cand);
+          g = check_hip(hipGetLastError(), "slice screen launch");
+        }
+      }
       if (g == GW_OK) g = eval_rows(ctx, ws, k, a, gs);
       if (g == GW_OK) {
         hipLaunchKernelGGL(k_sweep_update, dim3(blocks), dim3(tpb), 0, gs, (const SweepParams*)ws->dev, ws->S,
@@ -730,7 +871,8 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
         g = check_hip(hipGetLastError(), "slice update launch");
       }
       if (g == GW_OK && a.cache)
-        g = launch_wmom_build(ctx, ctx->coef, 2 * k, ws->S.build_list, ws->S.counts + 2, 2, nullptr, ws->wc, gs);
+        g = launch_wmom_build(ctx, ctx->coef, 2 * k, ws->S.build_list, ws->S.counts + 2, 2, ws->S.build_src, ws->wc,
+                              gs);
     }
     return g;
   };
@@ -755,6 +897,13 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
   hipLaunchKernelGGL(k_sweep_finish, dim3(blocks), dim3(tpb), 0, st, (const SweepParams*)ws->dev, ws->S, a.n_evals,
                      a.status);
   s = check_hip(hipGetLastError(), "slice finish launch");
+  if (s == GW_OK && a.screen_stats) {
+    s = check_hip(hipMemcpyAsync(ws->h_kinds + 3, ws->S.scr_tot, 3 * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, st), "copy");
+    if (s == GW_OK) s = check_hip(hipStreamSynchronize(st), "slice sync");
+    if (s == GW_OK)
+      for (int i = 0; i < 3; ++i) a.screen_stats[i] = (int64_t)ws->h_kinds[3 + i];
+  }
   if (s == GW_OK && a.eval_kinds) {
     if (!a.cache) {
       a.eval_kinds[0] = a.eval_kinds[1] = a.eval_kinds[2] = -1;  // not counted without the cache
@@ -794,11 +943,13 @@ gw_status slice_step(gw_ctx* ctx, const gw_slice_args* a, void* stream) {
   P.logl = a->logl;
   P.lists = a->like == GW_FULL && a->marg == GW_MARG_PHASE_DIST;
   s = cube_map(ctx, a->marg, &P.cm);
+  if (s == GW_OK) s = set_screen("slice_step", ctx, a->mlp, a->margin, a->audit_frac, P);
   if (s != GW_OK) return s;
   // the time marginal sets up tables on first use and calls the BLAS library:
   // its rounds are launched eagerly
   const int32_t graph = a->use_graph && a->marg != GW_MARG_PHASE_TIME;
-  const SweepCall c{a->like, a->marg, a->prec, graph, a->n_evals, a->status, 0, nullptr, P.lists};
+  const SweepCall c{a->like, a->marg, a->prec, graph, a->n_evals, a->status, 0, nullptr, P.lists,
+                    P.screen ? a->mlp : nullptr, a->screen_stats};
   return run_sweep(ctx, P, c, (hipStream_t)stream);
 }
 
@@ -850,9 +1001,11 @@ gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* a, void* stream) {
   }
   P.lists = a->like == GW_FULL && a->marg == GW_MARG_PHASE_DIST;
   s = cube_map(ctx, a->marg, &P.cm);
+  if (s == GW_OK) s = set_screen("slice_sweep", ctx, a->mlp, a->margin, a->audit_frac, P);
   if (s != GW_OK) return s;
   const int32_t graph = a->use_graph && a->marg != GW_MARG_PHASE_TIME;  // as in slice_step
-  const SweepCall c{a->like, a->marg, a->prec, graph, a->n_evals, a->status, P.cache, a->eval_kinds, P.lists};
+  const SweepCall c{a->like, a->marg, a->prec, graph, a->n_evals, a->status, P.cache, a->eval_kinds, P.lists,
+                    P.screen ? a->mlp : nullptr, a->screen_stats};
   return run_sweep(ctx, P, c, (hipStream_t)stream);
 }
 
@@ -913,7 +1066,7 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
     for (int i = 0; i < 2; ++i)
       if (hipEventCreateWithFlags(&ws->ev[i], hipEventDisableTiming) != hipSuccess)
         return set_error(GW_EDEVICE, "slice events");
-    if (hipHostMalloc((void**)&ws->h_kinds, 3 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void**)&ws->h_kinds, 6 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
       return set_error(GW_ENOMEM, "slice pinned counters");
     if (hipMalloc((void**)&ws->dev, sizeof(SweepParams)) != hipSuccess) return set_error(GW_ENOMEM, "slice parameters");
   }
@@ -924,17 +1077,20 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
   if (ws->mem) (void)hipFree(ws->mem);
   ws->mem = nullptr;
   ws->cap = 0;
-  // doubles: t_lo, t_hi, d[4], cand_t[2], cand[26], cand_logl[2], zrow[2][2 kMaxDet], zc[3][2 kMaxDet];
+  // doubles: t_lo, t_hi, d[kMaxBlock], cand_t[2], cand[26], cand_logl[2], zrow[2][2 kMaxDet],
+  // zc[3][2 kMaxDet], ucand[2][11], pred[2];
   // ints: flags, n_out[2], n_shrink, n_evals, slot_ok[2], cur, tot_evals, n_caps, rkind[2], zsrc[2],
-  // build_list, dirty, slow_rows[2], stream_rows[2], then the active counter and the three list counts
-  const size_t nd = (size_t)k * (1 + 1 + kMaxBlock + 2 + 26 + 2 + 4 * kMaxDet + 6 * kMaxDet);
-  const size_t ni = (size_t)k * (1 + 2 + 1 + 1 + 2 + 3 + 2 + 2 + 1 + 1 + 2 + 2) + 4;
+  // build_list, build_src, dirty, slow_rows[2], stream_rows[2], scr[2], side_tests[2], then the active
+  // counter and the three list counts
+  const size_t nd = (size_t)k * (1 + 1 + kMaxBlock + 2 + 26 + 2 + 4 * kMaxDet + 6 * kMaxDet + 2 * kSliceDim + 2);
+  const size_t ni = (size_t)k * (1 + 2 + 1 + 1 + 2 + 3 + 2 + 2 + 1 + 1 + 1 + 2 + 2 + 2 + 2) + 4;
   char* m = nullptr;
-  // three 64-bit counters first, then the doubles and the ints
-  gw_status s = check_hip(hipMalloc((void**)&m, 32 + nd * sizeof(double) + ni * sizeof(int32_t)), "slice workspace");
+  // six 64-bit counters first (evaluation kinds, prescreen counts), then the doubles and the ints
+  gw_status s = check_hip(hipMalloc((void**)&m, 64 + nd * sizeof(double) + ni * sizeof(int32_t)), "slice workspace");
   if (s != GW_OK) return s;
   ws->S.kind_tot = (unsigned long long*)m;
-  double* dp = (double*)(m + 32);
+  ws->S.scr_tot = ws->S.kind_tot + 3;
+  double* dp = (double*)(m + 64);
   ws->S.t_lo = dp; dp += k;
   ws->S.t_hi = dp; dp += k;
   ws->S.d = dp; dp += k * kMaxBlock;
@@ -943,6 +1099,8 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
   ws->cand_logl = dp; dp += 2 * k;
   ws->S.zrow = dp; dp += 4 * kMaxDet * k;
   ws->S.zc = dp; dp += 6 * kMaxDet * k;
+  ws->S.ucand = dp; dp += 2 * kSliceDim * k;
+  ws->S.pred = dp; dp += 2 * k;
   int32_t* ip = (int32_t*)dp;
   ws->S.flags = ip; ip += k;
   ws->S.n_out = ip; ip += 2 * k;
@@ -955,9 +1113,12 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
   ws->S.rkind = ip; ip += 2 * k;
   ws->S.zsrc = ip; ip += 2 * k;
   ws->S.build_list = ip; ip += k;
+  ws->S.build_src = ip; ip += k;
   ws->S.dirty = ip; ip += k;
   ws->S.slow_rows = ip; ip += 2 * k;
   ws->S.stream_rows = ip; ip += 2 * k;
+  ws->S.scr = ip; ip += 2 * k;
+  ws->S.side_tests = ip; ip += 2 * k;
   ws->S.n_active = ip; ip += 1;
   ws->S.counts = ip;
   ws->mem = m;

@@ -16,6 +16,10 @@ a control (M d joint slice steps per iteration, M = 3).  With ``cache=True`` (fu
 chain's waveform and reuses it on the extrinsic blocks (Sec. III.B).  With
 ``marg=GW_MARG_PHASE_TIME`` the phase and coalescence time are marginalised
 and d_L is sampled in place of t_c (the paper's GW170817 configuration).
+With ``prescreen`` (an addition; see prescreen.py) a network trained on the
+run's own dead and live points screens the slice candidates inside every
+sweep from iteration ``start`` on, retrained every ``every`` iterations; an
+accepted point always carries its exact log L.
 
 The host keeps the FP64 evidence bookkeeping (the k deletions taken in order
 with live counts m, m-1, ..., m-k+1), the start-point choice and the block
@@ -52,7 +56,7 @@ class NestedSampler:
     def __init__(self, ctx, n_live: int = 1000, n_delete: int = 125, seed: int = 6, dlogz: float = 0.1,
                  blocks=BLOCKS, like: int = _lib.GW_HET, prec: int = _lib.GW_PREC_MIXED, sweeps: int = 1,
                  w: float = 1.0, max_out: int = 10, max_shrink: int = 100, async_sweep: bool = True,
-                 cache: bool = False, marg: int = _lib.GW_MARG_PHASE_DIST):
+                 cache: bool = False, marg: int = _lib.GW_MARG_PHASE_DIST, prescreen: dict | None = None):
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -82,6 +86,19 @@ class NestedSampler:
         self.n_evals = self.m
         self.eval_kinds = np.zeros(3, np.int64)  # with the cache: full, cached waveform, cached sums
         self.wall = 0.0
+        # learned prescreen: settings, network, counts and training time
+        self.pre_cfg = None
+        self.pre = None
+        self.screen_stats = {"screened": 0, "audited": 0, "audited_inside": 0}
+        self.pre_train_s = 0.0
+        self.pre_trainings = 0
+        self.moves = 0  # blocks that moved (accepted proposals)
+        if prescreen is not None:
+            from .prescreen import Prescreen
+            cfg = dict(start=100, every=50, window=40, audit=0.01, epochs=30, batch=1024, seed=7, k_margin=3.0)
+            cfg.update(prescreen)
+            self.pre_cfg = cfg
+            self.pre = Prescreen(ctx, seed=int(cfg["seed"]))
 
     # -- likelihood of unit-cube points (initial live set) ------------------
     def _eval(self, x, out):
@@ -131,6 +148,8 @@ class NestedSampler:
         xn = self.x.index_select(0, idx).contiguous()
         ln = self.logl.index_select(0, idx).contiguous()
         ne = torch.zeros(self.k, dtype=torch.int32, device=self.dev)
+        caps = torch.zeros(self.k, dtype=torch.int32, device=self.dev)
+        pre = self._prescreen(lstar)
         if self.async_sweep:
             # the M sweeps' blocks in order, at most 16 per call: the same
             # moves as one call per sweep (block j of the sequence draws from
@@ -138,25 +157,53 @@ class NestedSampler:
             seq = [bi for _ in range(self.sweeps) for bi in range(len(self.blocks))]
             for j0 in range(0, len(seq), 16):
                 part = seq[j0:j0 + 16]
+                st = {} if pre is not None else None
                 kinds = _lib.slice_sweep(self.ctx.handle, xn, ln, lstar, [self.blocks[b] for b in part],
                                          [chols[b] for b in part], seed=self.seed, counter=self.counter, w=self.w,
                                          max_out=self.max_out, max_shrink=self.max_shrink, like=self.like,
-                                         marg=self.marg, prec=self.prec, n_evals=ne, use_cache=self.cache)
+                                         marg=self.marg, prec=self.prec, n_evals=ne, status=caps,
+                                         use_cache=self.cache, prescreen=pre, screen_stats=st)
                 if kinds is not None:
                     self.eval_kinds += np.array(kinds, np.int64)
+                if st:
+                    for key in self.screen_stats:
+                        self.screen_stats[key] += st[key]
                 self.n_evals += int(ne.sum().item())
+                self.moves += self.k * len(part) - int(caps.sum().item())
                 self.counter += len(part)
         for _ in range(0 if self.async_sweep else self.sweeps):
             for bi, b in enumerate(self.blocks):
+                st = {} if pre is not None else None
                 _lib.slice_step(self.ctx.handle, xn, ln, lstar, b, chols[bi], seed=self.seed, counter=self.counter,
                                 w=self.w, max_out=self.max_out, max_shrink=self.max_shrink, like=self.like,
-                                marg=self.marg, prec=self.prec, n_evals=ne)
+                                marg=self.marg, prec=self.prec, n_evals=ne, status=caps, prescreen=pre,
+                                screen_stats=st)
+                if st:
+                    for key in self.screen_stats:
+                        self.screen_stats[key] += st[key]
                 self.n_evals += int(ne.sum().item())
+                self.moves += self.k - int(caps.sum().item())
                 self.counter += 1
         wi = torch.from_numpy(worst).to(self.dev)
         self.x.index_copy_(0, wi, xn)
         self.logl.index_copy_(0, wi, ln)
         self.iteration += 1
+
+    def _prescreen(self, lstar):
+        """The (network, margin, audit fraction) for this iteration's sweeps,
+        training it first when due, or None."""
+        if self.pre is None or self.iteration < self.pre_cfg["start"]:
+            return None
+        cfg = self.pre_cfg
+        if (self.iteration - cfg["start"]) % cfg["every"] == 0:
+            from .prescreen import sampler_pairs
+            t0 = time.perf_counter()
+            x, y = sampler_pairs(self, last_iters=cfg["window"])
+            self.pre.train(x, y, self.x.cpu().numpy(), lstar, epochs=cfg["epochs"], batch=cfg["batch"])
+            self.pre.set_margin(lstar, k=cfg["k_margin"])
+            self.pre_train_s += time.perf_counter() - t0
+            self.pre_trainings += 1
+        return (self.pre.mlp, self.pre.margin, cfg["audit"])
 
     def run(self, max_iter: int = 100000, checkpoint: str | None = None, every: int = 50, verbose: bool = False):
         t0 = time.perf_counter()
@@ -186,7 +233,16 @@ class NestedSampler:
                    n_evals=self.n_evals, wall_s=self.wall, ess=ess)
         if self.cache:
             out["eval_kinds"] = [int(v) for v in self.eval_kinds]
+        out["moves"] = self.moves
+        if self.pre is not None:
+            out["prescreen"] = dict(self.screen_stats, trainings=self.pre_trainings, train_s=self.pre_train_s,
+                                    margin=self.pre.margin)
         return out
+
+    def close(self):
+        if self.pre is not None:
+            self.pre.close()
+            self.pre = None
 
     def samples(self):
         """(unit-cube points, normalised posterior weights) of dead + live points."""
@@ -198,6 +254,8 @@ class NestedSampler:
 
     # -- checkpoint / resume -----------------------------------------------
     def save(self, path: str):
+        if self.pre is not None:
+            raise NotImplementedError("checkpoints of a prescreened run are not supported")
         np.savez(path, x=self.x.cpu().numpy(), logl=self.logl.cpu().numpy(),
                  dead_logl=np.array(self.dead_logl), dead_logw=np.array(self.dead_logw),
                  dead_x=np.array(self.dead_x).reshape(-1, N_DIM), log_x=self.log_x, iteration=self.iteration,

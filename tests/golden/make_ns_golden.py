@@ -4,7 +4,12 @@ Calls only the oracle and the seeded input generator:
     python tests/golden/make_ns_golden.py cfg1   # 8 s segment, m=200, k=25, 200 bins
     python tests/golden/make_ns_golden.py cfg2   # 128 s segment, m=1000, k=125, 500 bins
 The injection sits at network SNR 24 under the 1e-49 PSD scale; phi_c and d_L
-are marginalised; seeds as in gwsynth.SEEDS (sampler seed 6).
+are marginalised; seeds as in gwsynth.SEEDS (sampler seed 6).  Each
+replacement runs three Gibbs sweeps (the High-Res setting M = 3 of the
+sampler-configuration table): with one sweep the chains of this problem do not
+decorrelate, and runs that differ only in their random numbers land up to a
+hundred nats apart at cfg1 (most miss the main mode); with three, five seeds
+agreed within 1.7 nats (sigma 0.37) and all found it.
 """
 import json
 import math
@@ -23,7 +28,8 @@ from oracle import heterodyne as H  # noqa: E402
 from oracle import likelihood as L  # noqa: E402
 from oracle import sampler as S  # noqa: E402
 
-SETTINGS = {"cfg1": dict(n_live=200, n_delete=25, n_bins=200), "cfg2": dict(n_live=1000, n_delete=125, n_bins=500)}
+SETTINGS = {"cfg1": dict(n_live=200, n_delete=25, n_bins=200, sweeps=3),
+            "cfg2": dict(n_live=1000, n_delete=125, n_bins=500, sweeps=3)}
 
 
 def loud_problem(name):
@@ -44,8 +50,9 @@ def main(name):
     loglike = lambda u: H.loglike(S.prior_transform(u), prob, het, L.PHASE_DIST, dd)
     t0 = time.time()
     res = S.nested_sampling(loglike, st["n_live"], st["n_delete"], seed=gwsynth.SEEDS["sampler"], dlogz=0.1,
-                            max_shrink=100, max_out=10)
+                            max_shrink=100, max_out=10, sweeps=st["sweeps"])
     out = {"config": name, "n_live": st["n_live"], "n_delete": st["n_delete"], "n_bins": st["n_bins"],
+           "sweeps": st["sweeps"],
            "seed": gwsynth.SEEDS["sampler"], "snr": 24.0, "psd_scale": 1e-49, "dlogz": 0.1,
            "log_z": res["log_z"], "log_z_err": res["log_z_err"], "h": res["h"], "iterations": res["iterations"],
            "n_evals": res["n_evals"], "cpu_wall_s": time.time() - t0}

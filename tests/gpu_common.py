@@ -38,3 +38,33 @@ def problem(name: str, loud: bool = False):
 
 def oracle_many(thetas, prob, marg):
     return L.loglike_many(thetas, prob, marg, processes=N_PROC)
+
+
+_HET_POOL = None
+
+
+def _het_init(prob, het):
+    global _HET_POOL
+    _HET_POOL = (prob, het)
+
+
+def _het_eval(args):
+    from oracle import heterodyne as H
+    theta, marg, dd = args
+    prob, het = _HET_POOL
+    return H.loglike(theta, prob, het, marg, dd)
+
+
+def oracle_het_many(thetas, prob, het, marg):
+    """The heterodyne oracle over a process pool (same values as
+    oracle.heterodyne.loglike_many, row by row)."""
+    import multiprocessing as mp
+    thetas = np.asarray(thetas, dtype=np.float64)
+    dd = L.data_inner(prob)
+    if N_PROC <= 1 or len(thetas) < 2:
+        from oracle import heterodyne as H
+        return H.loglike_many(thetas, prob, het, marg)
+    with mp.get_context("fork").Pool(N_PROC, initializer=_het_init, initargs=(prob, het)) as pool:
+        res = pool.map(_het_eval, [(t, marg, dd) for t in thetas],
+                       chunksize=max(1, len(thetas) // (4 * N_PROC)))
+    return np.array(res)

@@ -81,3 +81,32 @@ def test_no_device_is_reported(lib):
     with pytest.raises(_lib.GwError) as e:
         _lib.gw_ctx_create(prob)
     assert e.value.status == _lib.GW_EDEVICE
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # The ctypes mirrors of the argument structs must have the C compiler's
+    # size and field offsets (a shorter mirror would let the library read past
+    # the caller's struct).
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"gw_problem": _lib.gw_problem, "gw_slice_args": _lib.gw_slice_args,
+               "gw_sweep_args": _lib.gw_sweep_args, "gw_fiducial_args": _lib.gw_fiducial_args}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "gwswig.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)

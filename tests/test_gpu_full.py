@@ -172,12 +172,14 @@ def cfg2(gw):
     ctx.close()
 
 
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("marg", MARGS)
-def test_cfg2_full_batch_sampled(cfg2, marg):
+def test_cfg2_full_batch_all_rows(cfg2, marg):
     # Full size (259,585 bins x 3 detectors, batch 4096) in the benchmark's
-    # launch configuration, checked on a sample of rows the oracle can afford.
+    # launch configuration: every row of the batch against the oracle (about
+    # 10 s of the oracle on a 16-process pool per mode), in all three forms.
     prob, ctx, th, idx = cfg2
-    ref = oracle_many(th[idx], prob, marg)
+    ref = oracle_many(th, prob, marg)
     for prec, kind in FORMS:
         ctx.set_full_kernel(kind)
         try:
@@ -185,8 +187,9 @@ def test_cfg2_full_batch_sampled(cfg2, marg):
         finally:
             ctx.set_full_kernel(0)
         assert np.all(np.isfinite(got))
-        err = np.abs(got[idx] - ref)
-        print(f"cfg2 marg={marg} prec={prec} kind={kind}: max|dlogL|={err.max():.3e}", flush=True)
+        err = np.abs(got - ref)
+        print(f"cfg2 all {len(th)} rows marg={marg} prec={prec} kind={kind}: max|dlogL|={err.max():.3e} "
+              f"p99={np.quantile(err, 0.99):.3e}", flush=True)
         assert err.max() < TOL[prec]
 
 

@@ -256,3 +256,55 @@ def test_prescreen_gain_with_exact_confirmation(trained):
     assert truth_acc.sum() > 50
     assert ne <= 0.8 * n  # at least 20 % of the exact evaluations saved
     assert fn.sum() <= 0.01 * truth_acc.sum()
+
+
+def _to_cube(th):
+    # inverse of the oracle's unit-cube prior transform (coordinates 0..10)
+    u = np.empty(11)
+    u[:6] = (th[:6] - S.PRIOR_LO) / (S.PRIOR_HI - S.PRIOR_LO)
+    u[6] = (1.0 - math.cos(th[7])) / 2.0
+    u[7] = th[8] / (2.0 * math.pi)
+    u[8] = (math.sin(th[9]) + 1.0) / 2.0
+    u[9] = th[10] / math.pi
+    u[10] = (th[12] + 0.1) / 0.2
+    return u
+
+
+@pytest.mark.timeout(600)
+def test_prescreen_confirmation_on_the_128s_grid_matches_oracle():
+    # The prescreen's exact confirmation on the full-band 128 s grid (259,585
+    # bins x 3 detectors, the grid the learned-prescreen workload confirms on):
+    # every candidate the screen sends for evaluation gets the exact
+    # phase+distance-marginal log L, compared here with the oracle's own
+    # likelihood of the oracle's own prior transform of the same cube point.
+    import paper_2607_28265_amd as gw
+    from oracle import likelihood as L
+    from tests.gpu_common import oracle_many
+    prob = problem("cfg2", loud=True)
+    rng = np.random.default_rng(17)
+    n = 1024
+    u0 = _to_cube(prob.theta_inj)
+    x = np.concatenate([rng.uniform(size=(n // 2, 11)),
+                        np.clip(u0 + 0.003 * rng.standard_normal((n // 2, 11)), 0.0, 1.0)])
+    xd = torch.from_numpy(x).cuda()
+    with gw.Context(prob) as c:
+        vec, _ = random_params(16)
+        m = make_mlp(c, vec, ym=-778000.0, ys=50.0)
+        pred = m.forward(xd).cpu().numpy()
+        cut = float(np.median(pred))
+        ev_prev = None
+        for prec, tol in ((gw.GW_PREC_FP64, 1e-6), (gw.GW_PREC_MIXED, 1e-3)):
+            logl, flags, _, ne = m.prescreen(xd, cut, 0.0, audit_frac=0.02, seed=5, use_mlp=True, prec=prec)
+            logl, flags = logl.cpu().numpy(), flags.cpu().numpy()
+            ev = (flags & 1) != 0
+            assert 0.3 * n < ne == ev.sum() < 0.8 * n
+            if ev_prev is None:
+                ref = oracle_many(np.array([S.prior_transform(u) for u in x[ev]]), prob, L.PHASE_DIST)
+                ev_prev = ev
+            assert np.array_equal(ev, ev_prev)  # the screen does not depend on the likelihood's precision
+            err = np.abs(logl[ev] - ref)
+            print(f"prescreen 128 s prec {prec}: {ne} confirmed of {n}, max |dlogL| vs oracle {err.max():.2e}, "
+                  f"logL {ref.min():.1f} .. {ref.max():.1f}", flush=True)
+            assert err.max() < tol
+            assert np.all(np.isneginf(logl[~ev]))
+        m.close()

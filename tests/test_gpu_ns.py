@@ -1,10 +1,11 @@
 """End-to-end nested sampling on the GPU (heterodyned likelihood, phase and
 distance marginalised) against the oracle's own run on the same seeded
 problem, sampler settings and seeds (stored by tests/golden/make_ns_golden.py,
-which calls only the oracle).  The two runs are separate stochastic estimates
-once a near tie resolves differently, so log Z is compared within three
-combined standard errors sqrt(H/m); a checkpoint taken mid-run and resumed
-must reproduce the uninterrupted run exactly.
+which calls only the oracle; three Gibbs sweeps per replacement, the setting
+at which runs with different random numbers agree).  The two runs are
+separate stochastic estimates once a near tie resolves differently, so log Z
+is compared within three combined standard errors sqrt(H/m); a checkpoint
+taken mid-run and resumed must reproduce the uninterrupted run exactly.
 """
 import json
 import math
@@ -33,12 +34,12 @@ def run(name, prec, max_iter=100000, checkpoint_at=None, path=None, async_sweep=
     with gw.Context(prob) as ctx:
         ctx.heterodyne_setup(prob.theta_inj, g["n_bins"])
         ns = NestedSampler(ctx, n_live=g["n_live"], n_delete=g["n_delete"], seed=g["seed"], dlogz=g["dlogz"],
-                           like=gw.GW_HET, prec=prec, async_sweep=async_sweep)
+                           like=gw.GW_HET, prec=prec, async_sweep=async_sweep, sweeps=g.get("sweeps", 1))
         if checkpoint_at is not None:
             ns.run(max_iter=checkpoint_at)
             ns.save(path)
             ns2 = NestedSampler(ctx, n_live=g["n_live"], n_delete=g["n_delete"], seed=g["seed"], dlogz=g["dlogz"],
-                                like=gw.GW_HET, prec=prec)
+                                like=gw.GW_HET, prec=prec, sweeps=g.get("sweeps", 1))
             ns2.load(path)
             ns = ns2
         return ns.run(max_iter=max_iter)
@@ -77,3 +78,31 @@ def test_async_sweep_equals_block_by_block():
     print(f"async {a['wall_s']:.2f} s, block by block {b['wall_s']:.2f} s")
     assert a["iterations"] == b["iterations"] == 60
     assert a["log_z"] == b["log_z"] and a["n_evals"] == b["n_evals"] and a["h"] == b["h"]
+
+
+def test_prescreened_run_evidence_matches_oracle():
+    # The learned prescreen inside the sampler's sweeps (trained on the run's
+    # own dead and live points from iteration 60, retrained every 40): every
+    # accepted point keeps an exact log L, and the evidence stays within three
+    # combined standard errors of the oracle's unscreened run.  The audit
+    # measures how often a screened-out candidate was in fact inside.
+    import paper_2607_28265_amd as gw
+    from paper_2607_28265_amd.nested import NestedSampler
+    g = golden("cfg2")
+    prob = problem("cfg2", loud=True)
+    with gw.Context(prob) as ctx:
+        ctx.heterodyne_setup(prob.theta_inj, g["n_bins"])
+        ns = NestedSampler(ctx, n_live=g["n_live"], n_delete=g["n_delete"], seed=g["seed"], dlogz=g["dlogz"],
+                           like=gw.GW_HET, prec=gw.GW_PREC_MIXED, sweeps=g.get("sweeps", 1),
+                           prescreen=dict(start=60, every=40, audit=0.02))
+        r = ns.run()
+        ns.close()
+    p = r["prescreen"]
+    sig = math.hypot(r["log_z_err"], g["log_z_err"])
+    print(f"prescreened run: logZ {r['log_z']:.3f} +- {r['log_z_err']:.3f} ({r['iterations']} it, {r['n_evals']} "
+          f"exact evals, {r['wall_s']:.2f} s); screened {p['screened']}, audited {p['audited']} of which inside "
+          f"{p['audited_inside']}; {p['trainings']} trainings in {p['train_s']:.2f} s, margin {p['margin']:.3f}; "
+          f"oracle {g['log_z']:.3f} +- {g['log_z_err']:.3f}", flush=True)
+    assert p["screened"] > 0 and p["audited"] > 0
+    assert p["audited_inside"] <= 0.05 * p["audited"] + 1
+    assert abs(r["log_z"] - g["log_z"]) < 3.0 * sig

@@ -11,7 +11,7 @@ import pytest
 
 import gwsynth
 from oracle import likelihood as L
-from tests.gpu_common import oracle_many, problem
+from tests.gpu_common import oracle_het_many, oracle_many, problem
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -118,6 +118,32 @@ def test_heterodyned_against_oracle(loud):
             err = np.max(np.abs(got.cpu().numpy() - ref))
             print(f"heterodyned loud={loud} prec {prec}: max |dlogL| {err:.2e}")
             assert err < tol
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("nb", [500, 5000])
+def test_heterodyned_cfg2_against_oracle(nb):
+    # the 128 s segment (SNR 24) with 500 bins (the benchmark's heterodyned
+    # workload) and 5000 (the paper's count, Sec. III.D): 16 rows alone (a
+    # sampler-round batch, products split over edge chunks) and the same rows
+    # at the head of a 65,536-row batch (the benchmark's launch, unsplit)
+    import paper_2607_28265_amd as gw
+    from oracle import heterodyne as H
+    prob = problem("cfg2", loud=True)
+    het = H.setup(prob, prob.theta_inj, nb)
+    th = np.concatenate([near(prob, 8, 31, 0.3), gwsynth.prior_draws(gwsynth.SEEDS["prior"], 8)])
+    ref = oracle_het_many(th, prob, het, L.PHASE_TIME)
+    big = np.concatenate([th, gwsynth.prior_draws(37, 65536 - len(th))])
+    with gw.Context(prob) as ctx:
+        ctx.heterodyne_setup(prob.theta_inj, nb)
+        for prec, tol in ((gw.GW_PREC_FP64, 1e-6), (gw.GW_PREC_MIXED, 1e-4)):
+            for name, rows in (("16 rows", th), ("65,536 rows", big)):
+                got = ctx.loglike(torch.from_numpy(rows).cuda(), gw.GW_HET, gw.GW_MARG_PHASE_TIME, prec)
+                got = got[:len(th)].cpu().numpy()
+                err = np.max(np.abs(got - ref))
+                print(f"heterodyned 128 s, {nb} bins, {name}, prec {prec}: max |dlogL| {err:.2e}, "
+                      f"logL {ref.min():.1f} .. {ref.max():.1f}", flush=True)
+                assert err < tol
 
 
 def test_heterodyned_split_matches_unsplit():

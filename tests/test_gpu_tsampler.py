@@ -107,6 +107,9 @@ def test_heterodyned_time_marginal_sweep_matches_oracle(monkeypatch):
 
 
 def test_evidence_agrees_between_marginalisations():
+    # three Gibbs sweeps per replacement: with one, runs on this problem that
+    # differ only in their random numbers can miss the main mode and land far
+    # apart (the evidence references use three sweeps for the same reason)
     import paper_2607_28265_amd as gw
     from paper_2607_28265_amd.nested import NestedSampler
     prob = problem("cfg1", loud=True)
@@ -115,7 +118,7 @@ def test_evidence_agrees_between_marginalisations():
         ctx.heterodyne_setup(prob.theta_inj, 200)
         for marg in (gw.GW_MARG_PHASE_DIST, gw.GW_MARG_PHASE_TIME):
             ns = NestedSampler(ctx, n_live=200, n_delete=25, seed=6, dlogz=0.1, like=gw.GW_HET,
-                               prec=gw.GW_PREC_FP64, marg=marg)
+                               prec=gw.GW_PREC_FP64, marg=marg, sweeps=3)
             out[marg] = ns.run()
     a, b = out[gw.GW_MARG_PHASE_DIST], out[gw.GW_MARG_PHASE_TIME]
     sig = math.hypot(a["log_z_err"], b["log_z_err"])

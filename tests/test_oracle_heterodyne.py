@@ -83,3 +83,45 @@ def test_geometric_rule():
     e = H.bin_edges(f, 500, 1)
     r = f[e[1:]] / f[e[:-1]]
     assert np.allclose(r, (2048.0 / 20.0) ** (1 / 500), rtol=0.02)
+
+
+@pytest.mark.parametrize("rule,n_bins", [(0, 60), (1, 37)])
+def test_linear_ratio_is_exact(loud_problem, monkeypatch, rule, n_bins):
+    # Sec. III.D expands r_i = h_i / h0_i to first order in each bin.  With the
+    # fiducial h0 = h(theta) / (alpha + beta f) the ratio is exactly linear in
+    # f, so the expansion is exact: every binned Z_i equals the full-band sum,
+    # and the binned <h_i|h_i> equals the full-band one once the dropped term
+    # |r1|^2 4 df sum_k |h0_ik|^2 (f_k - f_c)^2 / S_ik is added back.  r1 = beta
+    # is far from zero here, so the A1 and B1 terms (their signs, the bin
+    # centre, the slope) carry a large share of both sums.
+    prob = loud_problem
+    th = prob.theta_inj.copy()
+    alpha, beta = 1.0 + 0.2j, 1.5e-3 - 1.0e-3j  # beta per Hz: |beta f| reaches 0.9 at 512 Hz
+    f = L.freqs(prob)
+    true_strain = L.strain
+    h = true_strain(th, prob)
+    h0 = h / (alpha + beta * f)[None, :]
+    monkeypatch.setattr(L, "strain", lambda theta, p, *a, **k: h0)
+    het = H.setup(prob, th, n_bins, rule)
+    monkeypatch.undo()
+    z_bin, hh_bin = H.overlaps(th, prob, het)
+    e = het.edges
+    nb = len(e) - 1
+    for i in range(h.shape[0]):
+        w = 4.0 * prob.df / prob.psd[i]
+        z_full = np.sum(np.conj(prob.data[i]) * h[i] * w)
+        hh_full = np.sum(np.abs(h[i]) ** 2 * w)
+        scale = np.sum(np.abs(prob.data[i]) * np.abs(h[i]) * w)
+        assert abs(z_bin[i] - z_full) < 1e-11 * scale, (i, z_bin[i], z_full)
+        b2 = 0.0
+        for b in range(nb):
+            stop = e[b + 1] + 1 if b == nb - 1 else e[b + 1]
+            sl = slice(e[b], stop)
+            fc = 0.5 * (f[e[b]] + f[e[b + 1]])
+            b2 += np.sum(np.abs(h0[i, sl]) ** 2 * w[sl] * (f[sl] - fc) ** 2)
+        assert abs(hh_bin[i] + abs(beta) ** 2 * b2 - hh_full) < 1e-11 * hh_full, (i, hh_bin[i], hh_full)
+        # the pin has teeth: the first-order terms alone move Z_i and <h_i|h_i>
+        # by ~1e-4 of their scale, seven orders above the tolerance
+        r0 = alpha + beta * 0.5 * (het.f_edges[1:] + het.f_edges[:-1])
+        assert abs(np.sum(het.a1[i] * beta)) > 1e-6 * scale
+        assert abs(np.sum(2.0 * het.b1[i] * (r0 * np.conj(beta)).real)) > 1e-6 * hh_full

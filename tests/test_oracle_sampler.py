@@ -75,10 +75,10 @@ def test_slice_step_keeps_uniform_on_a_ball():
 def test_unblocked_slice_step_keeps_uniform_on_an_11_ball():
     # P17 for one block holding every coordinate (the unblocked nested slice
     # sampler): 6 Box-Muller pairs give the direction, the bracket offset is
-    # uniform 12 and the shrink draws follow.  Uniform on an 11-ball stays
+    # uniform 12, the stepping-out split uniform 13, and the shrink draws follow.  Uniform on an 11-ball stays
     # uniform: radial CDF r^11, one coordinate (s + 1) / 2 ~ Beta(6, 6).
     d, n, rad = 11, 600, 0.3
-    assert S.n_direction_uniforms(d) == 12 and S.n_fixed_uniforms(d) == 13
+    assert S.n_direction_uniforms(d) == 12 and S.n_fixed_uniforms(d) == 14
     assert S.n_fixed_uniforms(4) == S.N_UNIFORM_FIXED == S.n_fixed_uniforms(1)
     rng = np.random.default_rng(2)
     c = np.full(d, 0.5)
@@ -99,6 +99,54 @@ def test_unblocked_slice_step_keeps_uniform_on_an_11_ball():
     assert stats.kstest(r ** d, "uniform").pvalue > 1e-3
     s = (x[:, 3] - c[3]) / rad
     assert stats.kstest((s + 1) / 2, stats.beta(6, 6).cdf).pvalue > 1e-3
+
+
+def test_stepping_out_budget_split_keeps_uniform_when_caps_bind():
+    # Stepping out with a budget m = 2 max_out + 1 split at random between the
+    # ends (Neal 2003, Sec. 4.1) gives every point of the final bracket the
+    # same chance of producing it, so the move leaves the constrained uniform
+    # invariant even when the cap binds on every move (here: a region 0.6 wide,
+    # w = 0.3, max_out = 1).  Capping each end at max_out on its own does not:
+    # in this set-up its histogram after 10 steps fails the same test
+    # (p ~ 2e-6, mass drawn towards the middle).
+    lo, hi, w, n = 0.2, 0.8, 0.3, 6000
+    rng = np.random.default_rng(5)
+    x = rng.uniform(lo, hi, size=n)
+    loglike = lambda p: 0.0 if lo < p[0] < hi else -1.0
+    for _ in range(10):
+        for i in range(n):
+            uni = rng.uniform(size=S.N_UNIFORM_FIXED + 100)
+            xi, _, _, st, _ = S.slice_chain(np.array([x[i]]), 0.0, -0.5, (0,), np.eye(1), uni, loglike, w=w,
+                                            max_out=1)
+            assert st == 0
+            x[i] = xi[0]
+    h, _ = np.histogram(x, bins=12, range=(lo, hi))
+    assert stats.chisquare(h).pvalue > 1e-3
+
+
+def test_stepping_out_budget_split():
+    # J = floor(m V) steps below and m - 1 - J above, m = 2 max_out + 1: a
+    # region wider than the whole budget shows the split in the bracket the
+    # evaluations trace out.
+    seen = []
+    for v, j_lo in ((0.0, 0), (0.2, 1), (0.999, 4)):
+        uni = np.zeros(S.N_UNIFORM_FIXED + 1)
+        uni[:4] = [0.5, 0.0, 0.5, 0.25]  # direction +1 along the single coordinate
+        uni[S.N_UNIFORM_FIXED - 2] = 0.5  # bracket offset
+        uni[S.N_UNIFORM_FIXED - 1] = v
+        uni[S.N_UNIFORM_FIXED] = 0.5  # the shrink draw lands on the start
+        pts = []
+
+        def loglike(p):
+            pts.append(float(p[0]))
+            return 0.0
+
+        S.slice_chain(np.array([0.5]), 0.0, -1.0, (0,), np.eye(1), uni, loglike, w=0.01, max_out=2)
+        below = sum(1 for t in pts[:-1] if t < 0.5)
+        above = sum(1 for t in pts[:-1] if t > 0.5)
+        seen.append((below, above))
+        assert below == j_lo and above == 4 - j_lo, (v, pts)
+    assert len(set(seen)) == 3
 
 
 def test_slice_step_block_moves_only_block():
@@ -192,3 +240,51 @@ def test_detector_frame_time():
         assert np.array_equal(th[keep], plain[keep])
         tt = S.prior_transform_frame(u, pos, 0.7, d_range=(10.0, 200.0))
         assert np.array_equal(tt[[6, 12]], S.prior_transform_time(u, 10.0, 200.0)[[6, 12]])
+
+
+def test_prescreen_rule_special_cases():
+    # The screen only decides which candidates get an exact log L.  With the
+    # exact log L as the prediction and no margin it drops only candidates
+    # outside the constraint, so the chain is unchanged; a screen that
+    # predicts every candidate outside but audits all of them is unchanged
+    # too; one that audits none evaluates nothing and the chain keeps its
+    # point at the shrink cap.
+    c = np.full(3, 0.5)
+    loglike = lambda p: -float(np.sum((p - c) ** 2))
+    lstar = -0.04
+    chol = 0.2 * np.eye(3)
+    rng = np.random.default_rng(4)
+    for trial in range(40):
+        x0 = c + 0.1 * rng.uniform(-1, 1, size=3)
+        uni = rng.uniform(size=S.N_UNIFORM_FIXED + 50)
+        ref = S.slice_chain(x0, loglike(x0), lstar, (0, 1, 2), chol, uni, loglike, w=0.3, max_out=2, max_shrink=50)
+        st = {}
+        exact = S.slice_chain(x0, loglike(x0), lstar, (0, 1, 2), chol, uni, loglike, w=0.3, max_out=2,
+                              max_shrink=50, screen=lambda x, kind, i: (loglike(x), 1.0), screen_margin=0.0,
+                              audit_frac=0.0, stats=st)
+        assert np.array_equal(exact[0], ref[0]) and exact[1] == ref[1] and exact[3] == ref[3]
+        assert exact[2] + st.get("screened", 0) == ref[2]  # the screened candidates were the rejected ones
+        st = {}
+        aud = S.slice_chain(x0, loglike(x0), lstar, (0, 1, 2), chol, uni, loglike, w=0.3, max_out=2,
+                            max_shrink=50, screen=lambda x, kind, i: (-math.inf, 0.5), audit_frac=0.75, stats=st)
+        assert np.array_equal(aud[0], ref[0]) and aud[1:4] == ref[1:4]
+        assert st["audited"] == ref[2] and st["audited_inside"] >= (1 if ref[3] == 0 else 0)
+        none = S.slice_chain(x0, loglike(x0), lstar, (0, 1, 2), chol, uni, loglike, w=0.3, max_out=2,
+                             max_shrink=50, screen=lambda x, kind, i: (-math.inf, 0.5), audit_frac=0.25)
+        assert np.array_equal(none[0], x0) and none[2] == 0 and none[3] == 1
+
+
+def test_prescreen_audit_indices():
+    # The screen sees each test's kind (0 lower end, 1 upper end, 2 shrink
+    # draw) and its index within the block, in the order of the tests.
+    seen = []
+
+    def screen(x, kind, i):
+        seen.append((kind, i))
+        return 0.0, 1.0
+
+    uni = np.full(S.N_UNIFORM_FIXED + 5, 0.5)
+    uni[S.N_UNIFORM_FIXED - 1] = 0.3  # budget split: J = floor(5 * 0.3) = 1 below, 3 above
+    S.slice_chain(np.array([0.5]), 0.0, -1.0, (0,), np.eye(1), uni, lambda p: 0.0, w=0.01, max_out=2,
+                  max_shrink=5, screen=screen, screen_margin=10.0)
+    assert seen == [(0, 0), (1, 0), (1, 1), (1, 2), (2, 0)]
