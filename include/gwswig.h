@@ -223,6 +223,30 @@ gw_status gw_reconstruct(gw_ctx* ctx, const double* theta, int64_t n, int32_t li
 gw_status gw_template(gw_ctx* ctx, const double* theta, int64_t n, double* h, void* stream);
 
 /*
+ * Allocation-free full-band likelihood, for callers that cannot allocate
+ * device memory (work recorded into a graph, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, kernels and results as
+ * loglike_batch with like = GW_FULL, for marg GW_MARG_NONE, GW_MARG_PHASE or
+ * GW_MARG_PHASE_DIST; nothing is allocated: the per-row coefficients, the
+ * distance marginal's staging and the frequency-chunk partial sums live in
+ * one static device array of GW_NOALLOC_DOUBLES FP64 values (16 MiB) per
+ * device, held from the first context created on that device until the
+ * process ends.  A row needs C + 2 + 2 n_det c doubles for c frequency
+ * chunks (C = 32 coefficients); the launch shape's chunk count is lowered in
+ * steps of 8 (at least 8) until the batch fits, so results agree with
+ * loglike_batch up to summation order, and bit for bit when both run the same
+ * shape (gw_set_full_shape).  Every call on a device shares that device's
+ * array: calls that overlap on one device (other streams, threads or
+ * contexts) race, and the caller must order them.
+ * Errors: GW_EINVAL (n above floor(GW_NOALLOC_DOUBLES / (34 + 16 n_det)),
+ * 25,575 rows at 3 detectors; a fixed launch shape that does not fit; a bad
+ * mode), GW_ESTATE (PHASE_DIST without a distance grid), GW_EDEVICE.
+ */
+#define GW_NOALLOC_DOUBLES (1 << 21)
+gw_status loglike_batch_noalloc(gw_ctx* ctx, const double* theta, int64_t n, int32_t marg, int32_t prec,
+                                double* logl, void* stream);
+
+/*
  * Heterodyne (relative-binning) set-up, Sec. III.D: builds the bin grid of
  * "equal maximum phase change" shared across the network and the
  * per-detector summary data of the reference template h0 = h(theta0).

@@ -14,7 +14,7 @@ from ._lib import (  # noqa: F401
     gw_graph_info, gw_profile_enable, gw_profile_read, slice_step, slice_sweep, gw_prior_transform, Mlp,
     gw_set_full_kernel, gw_full_info, gw_full_phase_runs, gw_phasor_gain, WaveformCache, gw_set_time_window,
     gw_time_grid_info, gw_set_het_tm_split, gw_reconstruct, slice_uniforms_fixed, GW_MAX_BLOCK, gw_set_sky_frame,
-    gw_fiducial_search, gw_set_time_oversample,
+    gw_fiducial_search, gw_set_time_oversample, loglike_batch_noalloc, noalloc_max_rows, GW_NOALLOC_DOUBLES,
 )
 
 

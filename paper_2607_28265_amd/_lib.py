@@ -129,6 +129,7 @@ _SIGS = {
     "gw_ctx_destroy": (ctypes.c_int, [_P]),
     "gw_data_inner": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
     "loglike_batch": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    "loglike_batch_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "gw_template": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     "gw_set_full_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "gw_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -299,6 +300,26 @@ def loglike_batch(ctx, theta, like: int = GW_FULL, marg: int = GW_MARG_NONE, pre
         raise ValueError("out must be a contiguous CUDA float64 tensor with at least n elements")
     check(load().loglike_batch(ctx, _tensor_ptr(theta), n, like, marg, prec, _tensor_ptr(out), _stream_ptr(stream)),
           "loglike_batch")
+    return out
+
+
+GW_NOALLOC_DOUBLES = 1 << 21
+
+
+def noalloc_max_rows(n_det: int) -> int:
+    """Largest batch of loglike_batch_noalloc for ``n_det`` detectors."""
+    return GW_NOALLOC_DOUBLES // (34 + 16 * n_det)
+
+
+def loglike_batch_noalloc(ctx, theta, marg: int = GW_MARG_NONE, prec: int = GW_PREC_FP64, out=None, stream=None):
+    """Allocation-free full-band log-likelihood of theta [n, 13] (CUDA float64)."""
+    import torch
+    _check_theta(theta)
+    n = theta.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=theta.device)
+    check(load().loglike_batch_noalloc(ctx, _tensor_ptr(theta), n, int(marg), int(prec), _tensor_ptr(out),
+                                       _stream_ptr(stream)), "loglike_batch_noalloc")
     return out
 
 

@@ -19,7 +19,7 @@ LIB_NAME = "libgwswig.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 
 SOURCES = ["gw_api.hip", "gw_full.hip", "gw_het.hip", "gw_slice.hip", "gw_mlp.hip", "gw_wcache.hip",
-           "gw_tmarg.hip", "gw_recon.hip", "gw_fiducial.hip"]
+           "gw_tmarg.hip", "gw_recon.hip", "gw_fiducial.hip", "gw_noalloc.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 instructions are kept out of the generated code.

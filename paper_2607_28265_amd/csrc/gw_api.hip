@@ -140,6 +140,7 @@ gw_status gw_ctx_create(const gw_problem* pr, int32_t device, gw_ctx** out) {
   if (e != hipSuccess || ndev <= 0) return set_error(GW_EDEVICE, "gw_ctx_create: no HIP device available");
   if (device < 0 || device >= ndev) return set_error(GW_EINVAL, "gw_ctx_create: device %d out of range", device);
   gw_status st = check_hip(hipSetDevice(device), "hipSetDevice");
+  if (st == GW_OK) st = noalloc_init(device);  // this device's allocation-free workspace address
   if (st != GW_OK) return st;
 
   gw_ctx* ctx = new (std::nothrow) gw_ctx();

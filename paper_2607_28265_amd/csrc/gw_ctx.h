@@ -136,6 +136,11 @@ gw_status build_moment_table(gw_ctx* ctx, const std::vector<double>& rec, const 
 // Measure the hardware phasor bias and set ctx->pgain_re / pgain_im.
 gw_status calibrate_phasor(gw_ctx* ctx);
 
+// Record the device address of ``device``'s copy of the allocation-free
+// workspace (gw_noalloc.hip); called by gw_ctx_create with the device
+// current, once per device.
+gw_status noalloc_init(int device);
+
 // Prescreen network hooks for the sampler (gw_mlp.hip): the context a
 // network was made on; a counter that changes whenever its input/output
 // scaling changes (a captured inference launch bakes the scaling in);
