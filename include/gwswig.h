@@ -153,21 +153,25 @@ gw_status loglike_batch(gw_ctx* ctx, const double* theta, int64_t n, int32_t lik
  * integral by tens of nats for loud signals):
  *   log L = -<d|d>/2 - <h|h>/2 + ln[ (1/N_t) sum_j I0(|Z(t_j)|) ],
  * Z(t) the overlap of the template shifted by t (template at t_c = 0).  The
- * library evaluates Z on each of the R sub-grids (t = (j + r / R) delta) with
- * 16 FFTs of length P (the smallest power of two >= 2 J + 1) over blocks of
- * N / P bins, within which the time shift is expanded to 16 terms (first
- * dropped term below 1e-10 of the block's overlap sum).  W defaults to 0.1 s;
- * gw_set_time_window changes it (GW_ENOTSUP if a sub-grid would exceed 2048
- * points).  gw_time_grid_info reports the grid step delta / R, the number of
+ * library cuts the band into blocks of N / P bins (P the smallest power of two
+ * >= 2 J + 1), within which the time shift is expanded to 16 terms (first
+ * dropped term below 1e-10 of the block's overlap sum), and evaluates every
+ * grid point with one FFT of length P R per term over the blocks.  W defaults
+ * to 0.1 s; gw_set_time_window changes it (GW_ENOTSUP if P would exceed 2048);
+ * a grid whose transform P R would exceed 4096 points is GW_ENOTSUP at
+ * evaluation.  gw_time_grid_info reports the grid step delta / R, the number of
  * points N_t = 2 J R + 1, P and the block length.  Work space: n x (n_freq / B)
  * x 256 bytes per call.
  * With like = GW_HET the same grid sum runs on the binned likelihood, the
  * appendix's direct summation on the heterodyned bins: at every t_j the
  * phase-marginal binned log L of the template shifted by t_j (the binned
  * <h|h> depends on t_j through the bin widths).  The library forms per-row
- * edge weights and contracts them with the proposal-independent phasors
- * exp(-2 pi i f_e t_j) and exp(-2 pi i (f_e - f_e-1) t_j) in one batched FP64
- * complex GEMM (rocBLAS); work space n x (n_edges + N_t) x 64 bytes.
+ * edge weights, takes their block moments (the edges lie on the fine grid) into
+ * the same FFTs as the full band, and expands the bin-width phasors
+ * exp(-2 pi i (f_e - f_e-1) t_j) about the widths' centre (as many terms as
+ * keep the first dropped one below 1e-13 of the norm sum; GW_ENOTSUP beyond
+ * 48).  Work space up to 1 GiB of moments per chunk of rows (about 8,000 rows
+ * at 128 s).
  */
 gw_status gw_set_time_window(gw_ctx* ctx, double window);
 /* Grid points per sampling interval of the time marginal: 1, 2, 4 (default),
@@ -290,10 +294,11 @@ gw_status loglike_batch_uneven(gw_ctx* ctx, const double* theta, int64_t n_rows,
  * persistent grid size in workgroups and number of edge chunks a row's bins
  * are split into (0 = heuristic for either). */
 gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid, int32_t n_ech);
-/* Edge chunks of the heterodyned time marginal's two complex products (App. A
- * on the binned likelihood): 1, 2, 4, 8, 16 or 32 fixes the split of the
- * edge sum, 0 (default) restores the heuristic (about 256 output tiles in
- * flight, at least 64 edges a chunk).  Results differ only by summation
+/* Edge chunks of the heterodyned time marginal's per-row edge moments (App. A
+ * on the binned likelihood): 1, 2, 4, 8, 16 or 32 asks for that many chunks of
+ * whole frequency blocks (fewer when the blocks do not allow them), 0
+ * (default) restores the heuristic (about 4096 (row tile, chunk) waves, at
+ * most 64 chunks of at least 8 edges).  Results differ only by summation
  * order.  GW_EINVAL otherwise. */
 gw_status gw_set_het_tm_split(gw_ctx* ctx, int32_t n_chunks);
 
@@ -372,6 +377,14 @@ typedef struct {
   int64_t* screen_stats;  /* host [3] or NULL: candidates screened out,
                              audited, audited and inside log L > log L* (a
                              false negative of the screen); synchronises */
+  double* rec_x;          /* device [rec_cap, 11] or NULL: every exactly
+                             evaluated candidate's unit-cube point goes to
+                             slot (*rec_count)++ mod rec_cap (the pairs the
+                             sampler generates, for training the prescreen);
+                             slots are claimed in no fixed order */
+  double* rec_logl;       /* device [rec_cap]: its exact log L */
+  int64_t rec_cap;        /* >= 1 with rec_x */
+  unsigned long long* rec_count;  /* device counter, set by the caller */
 } gw_slice_args;
 
 /*
@@ -448,6 +461,10 @@ typedef struct {
   double margin;           /* as for slice_step */
   double audit_frac;       /* as for slice_step */
   int64_t* screen_stats;   /* as for slice_step (summed over the sweep) */
+  double* rec_x;           /* as for slice_step */
+  double* rec_logl;
+  int64_t rec_cap;
+  unsigned long long* rec_count;
 } gw_sweep_args;
 
 gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* args, void* stream);

@@ -73,6 +73,10 @@ class gw_slice_args(ctypes.Structure):
         ("margin", ctypes.c_double),
         ("audit_frac", ctypes.c_double),
         ("screen_stats", ctypes.POINTER(ctypes.c_int64)),
+        ("rec_x", ctypes.c_void_p),
+        ("rec_logl", ctypes.c_void_p),
+        ("rec_cap", ctypes.c_int64),
+        ("rec_count", ctypes.c_void_p),
     ]
 
 
@@ -103,6 +107,10 @@ class gw_sweep_args(ctypes.Structure):
         ("margin", ctypes.c_double),
         ("audit_frac", ctypes.c_double),
         ("screen_stats", ctypes.POINTER(ctypes.c_int64)),
+        ("rec_x", ctypes.c_void_p),
+        ("rec_logl", ctypes.c_void_p),
+        ("rec_cap", ctypes.c_int64),
+        ("rec_count", ctypes.c_void_p),
     ]
 
 
@@ -449,6 +457,19 @@ def _set_screen(a, prescreen, screen_stats):
     return buf
 
 
+def _set_record(a, record):
+    """``record`` = (x [cap, 11], logl [cap], count [1] int64) CUDA tensors or None."""
+    if record is None:
+        return
+    import torch
+    rx, rl, rc = record
+    if not (rx.is_cuda and rx.dtype == torch.float64 and rx.is_contiguous() and rx.dim() == 2 and rx.shape[1] == 11
+            and rl.is_cuda and rl.dtype == torch.float64 and rl.numel() == rx.shape[0]
+            and rc.is_cuda and rc.dtype == torch.int64 and rc.numel() == 1):
+        raise ValueError("record = (x [cap, 11] float64, logl [cap] float64, count [1] int64), CUDA tensors")
+    a.rec_x, a.rec_logl, a.rec_cap, a.rec_count = rx.data_ptr(), rl.data_ptr(), rx.shape[0], rc.data_ptr()
+
+
 def _fill_screen(buf, prescreen, screen_stats):
     if prescreen is not None and screen_stats is not None:
         screen_stats.update(screened=int(buf[0]), audited=int(buf[1]), audited_inside=int(buf[2]))
@@ -457,9 +478,10 @@ def _fill_screen(buf, prescreen, screen_stats):
 def slice_step(ctx, x, logl, logl_star: float, block, chol, seed: int = 0, counter: int = 0, uniforms=None,
                w: float = 1.0, max_out: int = 10, max_shrink: int = 100, like: int = GW_HET,
                marg: int = GW_MARG_PHASE_DIST, prec: int = GW_PREC_FP64, n_evals=None, status=None, stream=None,
-               use_graph: bool = True, prescreen=None, screen_stats=None):
+               use_graph: bool = True, prescreen=None, screen_stats=None, record=None):
     """One slice update of one block for every chain; x [k, 11] and logl [k] (CUDA float64) change in place.
-    ``prescreen`` = (Mlp, margin, audit_frac) screens candidates with the network (see gwswig.h)."""
+    ``prescreen`` = (Mlp, margin, audit_frac) screens candidates with the network; ``record`` = (x, logl,
+    count) CUDA tensors collect every exactly evaluated candidate (see gwswig.h)."""
     import numpy as np
     import torch
     if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and x.dim() == 2 and x.shape[1] == 11):
@@ -484,6 +506,7 @@ def slice_step(ctx, x, logl, logl_star: float, block, chol, seed: int = 0, count
                       prec=int(prec), n_evals=n_evals.data_ptr() if n_evals is not None else None,
                       status=status.data_ptr() if status is not None else None, use_graph=1 if use_graph else 0)
     buf = _set_screen(a, prescreen, screen_stats)
+    _set_record(a, record)
     check(load().slice_step(ctx, ctypes.byref(a), _stream_ptr(stream)), "slice_step")
     _fill_screen(buf, prescreen, screen_stats)
 
@@ -504,7 +527,7 @@ def _check_chains(x, logl, n_evals, status):
 def slice_sweep(ctx, x, logl, logl_star: float, blocks, chols, seed: int = 0, counter: int = 0, w: float = 1.0,
                 max_out: int = 10, max_shrink: int = 100, like: int = GW_HET, marg: int = GW_MARG_PHASE_DIST,
                 prec: int = GW_PREC_FP64, n_evals=None, status=None, stream=None, use_graph: bool = True,
-                use_cache: bool = False, prescreen=None, screen_stats=None):
+                use_cache: bool = False, prescreen=None, screen_stats=None, record=None):
     """One sweep over ``blocks`` (list of index lists, with their Cholesky
     factors ``chols``) for every chain, block b with Philox counter
     counter + b; x [k, 11] and logl [k] change in place.  Returns the
@@ -538,6 +561,7 @@ def slice_sweep(ctx, x, logl, logl_star: float, blocks, chols, seed: int = 0, co
     if use_cache:
         a.eval_kinds = kinds
     buf = _set_screen(a, prescreen, screen_stats)
+    _set_record(a, record)
     check(load().slice_sweep(ctx, ctypes.byref(a), _stream_ptr(stream)), "slice_sweep")
     _fill_screen(buf, prescreen, screen_stats)
     return (kinds[0], kinds[1], kinds[2]) if use_cache else None

@@ -19,7 +19,7 @@ LIB_NAME = "libgwswig.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 
 SOURCES = ["gw_api.hip", "gw_full.hip", "gw_het.hip", "gw_slice.hip", "gw_mlp.hip", "gw_wcache.hip",
-           "gw_tmarg.hip", "gw_recon.hip", "gw_fiducial.hip", "gw_noalloc.hip"]
+           "gw_tmarg.hip", "gw_recon.hip", "gw_fiducial.hip", "gw_noalloc.hip", "gw_tgrid.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 instructions are kept out of the generated code.
@@ -56,7 +56,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB_PATH + ".tmp"
-    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lrocblas"]
+    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

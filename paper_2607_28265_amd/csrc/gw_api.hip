@@ -6,8 +6,6 @@
 #include <stdlib.h>
 #include <string.h>
 
-#include <rocblas/rocblas.h>
-
 #include "gw_ctx.h"
 
 namespace {
@@ -214,6 +212,12 @@ gw_status gw_ctx_create(const gw_problem* pr, int32_t device, gw_ctx** out) {
       st = check_hip(hipMemcpy(ctx->dist_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice),
                      "dist copy");
   }
+  if (st == GW_OK) {
+    LogI0Consts c = make_log_i0_consts();
+    c.r1max = ctx->dist_r1max;
+    st = check_hip(hipMalloc((void**)&ctx->i0c, sizeof(LogI0Consts)), "ln I0 table alloc");
+    if (st == GW_OK) st = check_hip(hipMemcpy(ctx->i0c, &c, sizeof(c), hipMemcpyHostToDevice), "ln I0 table copy");
+  }
   if (st == GW_OK) st = build_moment_table(ctx, rec, pr->det_pos);
   if (st == GW_OK) st = calibrate_phasor(ctx);
   if (st != GW_OK) {
@@ -230,7 +234,6 @@ gw_status gw_ctx_destroy(gw_ctx* ctx) {
   het_free(ctx);
   graphs_free(ctx);
   slice_free(ctx);
-  if (ctx->blas) (void)rocblas_destroy_handle((rocblas_handle)ctx->blas);
   for (hipEvent_t e : ctx->prof_ev)
     if (e) (void)hipEventDestroy(e);
   double* bufs[] = {ctx->bins,   ctx->dist_tab, ctx->coef,   ctx->partial, ctx->zbuf,
@@ -238,6 +241,7 @@ gw_status gw_ctx_destroy(gw_ctx* ctx) {
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (ctx->wtab) (void)hipFree(ctx->wtab);
+  if (ctx->i0c) (void)hipFree(ctx->i0c);
   delete ctx;
   return GW_OK;
 }

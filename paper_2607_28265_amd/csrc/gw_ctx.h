@@ -31,6 +31,9 @@ struct gw_ctx {
   std::vector<double> h_dist_grid, h_dist_logw;
   // host copies kept for heterodyne set-up
   std::vector<double> h_data_re, h_data_im, h_psd;
+  // device copy of the ln I0 coefficients (r1max set from the distance grid),
+  // for kernels that read them through a pointer
+  gw::LogI0Consts* i0c = nullptr;
   // workspace (grown on demand)
   double* coef = nullptr;          // [C_NCOEF][cap_n]
   int64_t coef_cap = 0;
@@ -58,15 +61,13 @@ struct gw_ctx {
   // time marginal: window half-width (s), FFT twiddles and moment workspace
   double tm_window = 0.1;
   int tm_R = 4;                    // grid points per sampling interval of the segment
-  int tm_nsk = 0;                  // edge chunks of the heterodyned time marginal's products (0 = heuristic)
-  int tm_P = 0;
-  int tm_twR = 0;                  // oversampling the twiddle table was built for
-  double* tm_tw = nullptr;
+  int tm_nsk = 0;                  // edge chunks of the heterodyned time marginal's moments (0 = heuristic)
+  int tm_L = 0;                    // length of the time-grid transform the twiddles were built for
+  double* tm_tw = nullptr;         // [tm_L] complex exp(-2 pi i t / tm_L)
   double* tm_tpow = nullptr;        // [blk][16] powers of the in-block offset for the moments
   int tm_tpow_blk = 0;
   double* tm_mom = nullptr;
   int64_t tm_mom_cap = 0;
-  void* blas = nullptr;            // rocBLAS handle (created on first use)
   // sampler sky frame: 0 equatorial (ra, dec), 1 zenith and azimuth about the
   // baseline of detectors sky_a -> sky_b; sky_det_time: coordinate 10 is the
   // arrival time at detector sky_a
@@ -135,6 +136,43 @@ void full_launch_shape(const gw_ctx* ctx, int64_t n, int* tpb, int* n_chunks);
 gw_status build_moment_table(gw_ctx* ctx, const std::vector<double>& rec, const double* det_pos);
 // Measure the hardware phasor bias and set ctx->pgain_re / pgain_im.
 gw_status calibrate_phasor(gw_ctx* ctx);
+
+// Time-grid sums from block moments (gw_tgrid.hip), shared by the full-band
+// and heterodyned time marginals: moments [n][kTMomOrders][n_blk] complex,
+// one FFT of length L = P R per order, the grid t_j = j delta / R, |j| <= jmax.
+constexpr int kTMomOrders = 16;
+constexpr int kTgHMax = 48;  // most norm moments of the heterodyned form
+struct TGridArgs {
+  const double* mom;
+  int64_t n;
+  int n_blk, L, jmax;
+  const double* tw;   // [L] complex exp(-2 pi i t / L)
+  const double* coef;  // prologue coefficients of the n rows (stride ld)
+  int64_t ld;
+  double* logl;
+  int het;             // heterodyned norm: hhc [n], hpart [n_hch][n][mh] complex
+  const double* hhc;
+  const double* hpart;
+  int n_hch, mh;
+  double hw_step;      // 2 pi hw / (N R)
+  int64_t c2, cden;    // exp(-2 pi i c u_j) = exp(-2 pi i (c2 j mod cden) / cden)
+  double* zout;        // or NULL: [n][2 jmax + 1][3] staged grid values
+  double f0_num, f0_den;  // f_0 t_j = j f0_num / f0_den cycles
+};
+bool tgrid_plan(int L, int4* radix, int* n_pass);
+// The context's time grid: segment length N (samples), J and R (|j| <= jmax =
+// J R), P, blocks of blk = N / P fine bins (n_blk of them), L = P R.
+struct TimeGridShape {
+  int64_t N;
+  double delta;  // the segment's sampling interval; the grid step is delta / R
+  int J, R, P, blk, n_blk, L, jmax;
+};
+gw_status time_grid_shape(const gw_ctx* ctx, TimeGridShape* g);
+// The context's twiddle table for transforms of length L (rebuilt when L
+// changes), and the rows per chunk whose moments fit the bounded workspace.
+gw_status tgrid_twiddles(gw_ctx* ctx, int L);
+int64_t tgrid_chunk_rows(int64_t n, int n_blk);
+gw_status launch_tgrid(const gw_ctx* ctx, const TGridArgs& a, hipStream_t st);
 
 // Record the device address of ``device``'s copy of the allocation-free
 // workspace (gw_noalloc.hip); called by gw_ctx_create with the device

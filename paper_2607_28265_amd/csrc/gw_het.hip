@@ -23,8 +23,6 @@
 #include <map>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "gw_ctx.h"
 
 // Device-resident arguments of the work-list kernels; a one-thread kernel
@@ -64,11 +62,17 @@ struct gw_het_state {
   int grid = 0;                  // workgroups (0 = heuristic)
   int ech = 0;                   // edge chunks (0 = heuristic)
   int64_t n_rows_last = 0;       // rows of the batch being enqueued (selects the distance form)
-  // time marginal: phasors of the edges and bin widths on the time grid,
-  // [2][n_edges][n_t] complex (E then F), built on first use for a grid
-  double* tm_ef = nullptr;
-  int tm_nt = 0;
-  double tm_delta = 0.0;
+  // time marginal: row-independent tables for the current grid (built on
+  // first use): per block b < n_blk the edges [tm_bs[b], tm_bs[b + 1]) in it,
+  // per edge the powers s_e^m of its offset in the block (m < 16) and
+  // sigma_e^m of its bin width about the widths' centre (m < tm_mh), and the
+  // edge chunks of the moment kernel (whole blocks tm_cb[c] .. tm_cb[c + 1])
+  double* tm_tab = nullptr;      // [n_edges][16 + tm_mh]
+  int32_t* tm_idx = nullptr;     // [n_blk + 1] block starts, then [tm_nch + 1] chunk block starts
+  int tm_blk = 0, tm_nblk = 0, tm_mh = 0, tm_nch = 0, tm_nch_req = -1;
+  double tm_hw = 0.0;            // half-range of the bin widths (fine bins)
+  double tm_umax = -1.0;         // the window's largest |u| the norm series was sized for
+  int64_t tm_c2 = 0;             // smallest + largest bin width (fine bins)
 };
 
 struct GraphKey {
@@ -598,7 +602,8 @@ __global__ void __launch_bounds__(64 * kHetDistWaves) k_het_dist(const HetArgs* 
 
 static void free_state(gw_het_state* h) {
   if (!h) return;
-  if (h->tm_ef) (void)hipFree(h->tm_ef);
+  if (h->tm_tab) (void)hipFree(h->tm_tab);
+  if (h->tm_idx) (void)hipFree(h->tm_idx);
   if (h->rec) (void)hipFree(h->rec);
   if (h->args) (void)hipFree(h->args);
   if (h->tile_pre) (void)hipFree(h->tile_pre);
@@ -795,50 +800,35 @@ void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech)
 //   W_e = sum_i q_i K_ie g_ie          (K the summed-by-parts overlap weights),
 //   V_e = sum_i |q_i|^2 (B0_e / 2) g_ie conj(g_i,e-1)   (bin e's norm term),
 // q_i = (A P_i) / (A0 P0_i), the binned overlap and norm at t_j are
-//   Z(t_j)  = sum_e W_e E_ej,              E_ej = exp(-2 pi i f_e t_j),
-//   hh(t_j) = sum_i |q_i|^2 hh0_i + Re sum_e V_e F_ej,  F_ej = exp(-2 pi i (f_e - f_e-1) t_j),
-// two dense complex products [rows x edges] x [edges x grid] with
-// proposal-independent right factors (one batched GEMM), then the
-// phase-marginal log L per grid point and a fixed-order log-sum-exp.
+//   Z(t_j)  = sum_e W_e exp(-2 pi i f_e t_j),
+//   hh(t_j) = sum_i |q_i|^2 hh0_i + Re sum_e V_e exp(-2 pi i (f_e - f_e-1) t_j).
+// The edges lie on the fine grid, so Z goes through the block moments of the
+// full band's time marginal with W_e in place of the per-bin weights
+// (gw_tgrid.hip); the widths f_e - f_e-1 = dk_e df span a short range, and
+// exp(-2 pi i dk_e u) about the widths' centre c, dk_e = c + hw sigma_e, is a
+// series in (2 pi hw u) sigma_e whose moments S_m = sum_e sigma_e^m V_e the
+// grid kernel sums (tm_mh terms, the first dropped one below 1e-13 of
+// sum_e |V_e| at the window's edge).
 
-// E and F on the grid t_j = (j - J) delta (FP64 phase, FP64 sin/cos).
-__global__ void __launch_bounds__(256) k_het_tm_phasors(const double* __restrict__ rec, int rs, int n_edges,
-                                                        int ne_pad, int nt, int J, double delta, TrigConsts T,
-                                                        double* __restrict__ ef) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t per = (int64_t)ne_pad * nt;
-  if (idx >= 2 * per) return;
-  const int which = (int)(idx / per);
-  const int64_t r = idx - which * per;
-  const int e = (int)(r / nt), j = (int)(r - (int64_t)e * nt);
-  if (e >= n_edges) {  // padding edges take no part in the products
-    ef[2 * idx] = 0.0;
-    ef[2 * idx + 1] = 0.0;
-    return;
-  }
-  const double t = (double)(j - J) * delta;
-  double f = rec[(int64_t)e * rs + H_F];
-  if (which == 1) f = e > 0 ? f - rec[(int64_t)(e - 1) * rs + H_F] : 0.0;
-  double sn, cs;
-  sincos_cycles(f * t, T, &sn, &cs);
-  ef[2 * idx] = which == 1 && e == 0 ? 0.0 : cs;
-  ef[2 * idx + 1] = which == 1 && e == 0 ? 0.0 : -sn;
-}
-
-// The edge weights W and V ([2][n][ne_pad] complex, zero beyond the last
-// edge) and the constant norm part sum_i |q_i|^2 hh0_i (hhc[n]).  One wave
-// per (64-row tile, chunk of ``chunk`` edges): lane = row, edge records
-// wave-uniform; a chunk starts its phasor recurrence from the edge before it.
+// Edge-weight moments of one (64-row tile, edge chunk): lane = row, the
+// chunk's edges in order (edge records and tables wave-uniform).  what = 0:
+// the 16 block moments of W for every block of the chunk into mom
+// [rows][16][n_blk]; what = 1: S_m, m0 <= m < m0 + 16 (m < mh), over the
+// chunk's edges into hpart [chunk][rows][mh]; chunk 0 also writes the
+// constant norm part hhc [rows].
 template <int ND, int PREC>
-__global__ void __launch_bounds__(64) k_het_tw(const double* __restrict__ coef, int64_t ld, int64_t n,
-                                               const double* __restrict__ rec, int n_bins, int ne_pad, int chunk,
-                                               HetConst hc, TrigConsts T, double* __restrict__ wv,
-                                               double* __restrict__ hhc) {
+__global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef, int64_t ld, int64_t n,
+                                                 const double* __restrict__ rec, int n_bins,
+                                                 const double* __restrict__ tab, int mh,
+                                                 const int32_t* __restrict__ bs, const int32_t* __restrict__ cb,
+                                                 int n_blk, int what, int m0, HetConst hc, TrigConsts T,
+                                                 double2* __restrict__ mom, double2* __restrict__ hpart,
+                                                 double* __restrict__ hhc) {
   constexpr int RS = het_rs(ND);
   constexpr int BO = het_bin_off(ND);
   const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
   const int64_t pc = p < n ? p : n - 1;
-  const int e0 = blockIdx.y * chunk;
+  const int ch = blockIdx.y;
   const double* cf = coef + pc;
   PhaseCoef c;
   c.a0 = cf[C_A0 * ld]; c.a2 = cf[C_A2 * ld]; c.a3 = cf[C_A3 * ld]; c.a4 = cf[C_A4 * ld];
@@ -856,13 +846,12 @@ __global__ void __launch_bounds__(64) k_het_tw(const double* __restrict__ coef, 
     hconst = fma(q2[i], hc.hh0[i], hconst);
     pr[i] = pim[i] = 0.0;
   }
-  const int n_edges = n_bins + 1;
-  // edge-major [edge][row] complex, so that a wave's stores of one edge are
-  // contiguous; W first, then V
-  double* __restrict__ w_out = wv + pc * 2;
-  double* __restrict__ v_out = wv + ((int64_t)ne_pad * n + pc) * 2;
-  if (e0 > 0 && e0 - 1 < n_edges) {  // the previous edge's phasors
-    const double* r = rec + (int64_t)(e0 - 1) * RS;
+  if (what == 0 && ch == 0 && p < n) hhc[p] = hconst;
+  const int b_lo = cb[ch], b_hi = cb[ch + 1];
+  const int e_lo = bs[b_lo], e_hi = bs[b_hi];
+  const int tw_ = kTMomOrders + mh;  // table row length
+  if (what == 1 && e_lo > 0) {  // the norm term needs the previous edge's phasors
+    const double* r = rec + (int64_t)(e_lo - 1) * RS;
     const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
@@ -870,152 +859,169 @@ __global__ void __launch_bounds__(64) k_het_tw(const double* __restrict__ coef, 
       het_phasor<PREC>(di, T, &pr[i], &pim[i]);
     }
   }
-  const int e_end = e0 + chunk < n_edges ? e0 + chunk : n_edges;
-  for (int e = e0; e < e_end; ++e) {
-    const double* r = rec + (int64_t)e * RS;
-    const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
-    const double f = r[H_F];
-    const int side = e == 0 ? 1 : (e == n_bins ? 2 : 0);
-    double wr = 0.0, wi = 0.0, vr = 0.0, vi = 0.0;
+  double ar_[kTMomOrders], ai_[kTMomOrders];
 #pragma unroll
-    for (int i = 0; i < ND; ++i) {
-      const double di = i == 0 ? d0 : fma(f, dt[i], d0) - r[H_PHI0 + i];
-      double gr, gi;
-      het_phasor<PREC>(di, T, &gr, &gi);
-      const double* w = r + BO + 1 + 6 * i;
-      const double kr = side == 0 ? w[0] : (side == 1 ? w[0] - w[2] : w[2]);
-      const double ki = side == 0 ? w[1] : (side == 1 ? w[1] - w[3] : w[3]);
-      // q K g
-      const double kgr = kr * gr - ki * gi, kgi = kr * gi + ki * gr;
-      wr = fma(qr[i], kgr, fma(-qi[i], kgi, wr));
-      wi = fma(qr[i], kgi, fma(qi[i], kgr, wi));
-      if (e > 0) {
-        // |q|^2 (B0 / 2) g_e conj(g_e-1)
-        const double s = q2[i] * w[4];
-        vr = fma(s, fma(gr, pr[i], gi * pim[i]), vr);
-        vi = fma(s, fma(gi, pr[i], -gr * pim[i]), vi);
+  for (int m = 0; m < kTMomOrders; ++m) ar_[m] = ai_[m] = 0.0;
+  int e = e_lo;
+  for (int b = b_lo; b < b_hi; ++b) {
+    const int be = bs[b + 1];
+    for (; e < be; ++e) {
+      const double* r = rec + (int64_t)e * RS;
+      const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
+      const double f = r[H_F];
+      const int side = e == 0 ? 1 : (e == n_bins ? 2 : 0);
+      double wr = 0.0, wi = 0.0;
+#pragma unroll
+      for (int i = 0; i < ND; ++i) {
+        const double di = i == 0 ? d0 : fma(f, dt[i], d0) - r[H_PHI0 + i];
+        double gr, gi;
+        het_phasor<PREC>(di, T, &gr, &gi);
+        const double* w = r + BO + 1 + 6 * i;
+        if (what == 0) {
+          const double kr = side == 0 ? w[0] : (side == 1 ? w[0] - w[2] : w[2]);
+          const double ki = side == 0 ? w[1] : (side == 1 ? w[1] - w[3] : w[3]);
+          const double kgr = kr * gr - ki * gi, kgi = kr * gi + ki * gr;  // q K g
+          wr = fma(qr[i], kgr, fma(-qi[i], kgi, wr));
+          wi = fma(qr[i], kgi, fma(qi[i], kgr, wi));
+        } else if (e > 0) {
+          const double sq = q2[i] * w[4];  // |q|^2 (B0 / 2) g_e conj(g_e-1)
+          wr = fma(sq, fma(gr, pr[i], gi * pim[i]), wr);
+          wi = fma(sq, fma(gi, pr[i], -gr * pim[i]), wi);
+        }
+        pr[i] = gr;
+        pim[i] = gi;
       }
-      pr[i] = gr;
-      pim[i] = gi;
-    }
-    if (p < n) {
-      w_out[2 * e * n] = wr;
-      w_out[2 * e * n + 1] = wi;
-      v_out[2 * e * n] = vr;
-      v_out[2 * e * n + 1] = vi;
-    }
-  }
-  if (p < n && e0 + chunk >= n_edges) {  // the last chunk clears the padding
-    for (int e = n_edges > e0 ? n_edges : e0; e < ne_pad; ++e) {
-      w_out[2 * e * n] = w_out[2 * e * n + 1] = 0.0;
-      v_out[2 * e * n] = v_out[2 * e * n + 1] = 0.0;
-    }
-  }
-  if (p < n && e0 == 0) hhc[p] = hconst;
-}
-
-// One workgroup (256 threads) per row: log-mean-exp over the grid of the
-// phase-marginal binned log L.
-// The products come in nsk partial sums over chunks of edges
-// (zh [2][nsk][n][nt] complex), added here in chunk order.
-__device__ inline void het_tgrid_sums(const double* __restrict__ zh, int64_t n, int nt, int nsk, int64_t p, int j,
-                                      double* zr, double* zi, double* hr) {
-  *zr = *zi = *hr = 0.0;
-  for (int c = 0; c < nsk; ++c) {
-    const double* z = zh + ((int64_t)c * n + p) * nt * 2;
-    const double* hv = zh + ((int64_t)(nsk + c) * n + p) * nt * 2;
-    *zr += z[2 * j];
-    *zi += z[2 * j + 1];
-    *hr += hv[2 * j];
-  }
-}
-
-__device__ inline double het_tgrid_value(const double* __restrict__ zh, int64_t n, int nt, int nsk, int64_t p, int j,
-                                         double h0, const LogI0Consts& C) {
-  double zr, zi, hr;
-  het_tgrid_sums(zh, n, nt, nsk, p, j, &zr, &zi, &hr);
-  return -0.5 * (h0 + hr) + log_i0(sqrt(zr * zr + zi * zi), C);
-}
-
-// With zout (else NULL) the grid values are also staged for post-hoc draws:
-// zout[p][j] = (Re Z(t_j), Im Z(t_j), <h|h>(t_j)), Re NaN for unphysical rows.
-__global__ void __launch_bounds__(256) k_het_tfinal(const double* __restrict__ zh, const double* __restrict__ hhc,
-                                                    const double* __restrict__ coef, int64_t ld, int64_t n, int nt,
-                                                    int nsk, double dd, LogI0Consts C, double* __restrict__ logl,
-                                                    double* __restrict__ zout) {
-  __shared__ double red[256], red2[256];
-  const int64_t p = blockIdx.x;
-  const int tid = threadIdx.x;
-  const double h0 = hhc[p];
-  if (zout) {
-    const bool valid = coef[C_VALID * ld + p] != 0.0;
-    for (int j = tid; j < nt; j += 256) {
-      double zr, zi, hr;
-      het_tgrid_sums(zh, n, nt, nsk, p, j, &zr, &zi, &hr);
-      double* o = zout + (p * nt + j) * 3;
-      o[0] = valid ? zr : NAN;
-      o[1] = zi;
-      o[2] = h0 + hr;
-    }
-  }
-  // one pass: each thread keeps a running maximum m and the sum s of
-  // exp(v - m) over its grid points, rescaled when m grows; the pairs are
-  // then merged across the workgroup
-  double m = -INFINITY, acc = 0.0;
-  for (int j = tid; j < nt; j += 256) {
-    const double v = het_tgrid_value(zh, n, nt, nsk, p, j, h0, C);
-    if (v > m) {
-      acc = acc * exp(m - v) + 1.0;
-      m = v;
-    } else if (!(v == -INFINITY)) {  // NaN still propagates
-      acc += exp(v - m);
-    }
-  }
-  red[tid] = m;
-  red2[tid] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) {
-      const double ma = red[tid], mb = red[tid + s];
-      const double mm = fmax(ma, mb);
-      if (mm > -INFINITY) {
-        red2[tid] = red2[tid] * exp(ma - mm) + red2[tid + s] * exp(mb - mm);
-        red[tid] = mm;
+      const double* tp = tab + (int64_t)e * tw_ + (what == 0 ? 0 : kTMomOrders + m0);
+#pragma unroll
+      for (int m = 0; m < kTMomOrders; ++m) {
+        if (what == 1 && m0 + m >= mh) break;
+        ar_[m] = fma(tp[m], wr, ar_[m]);
+        ai_[m] = fma(tp[m], wi, ai_[m]);
       }
     }
-    __syncthreads();
+    if (what == 0) {
+      if (p < n) {
+        double2* out = mom + p * kTMomOrders * n_blk + b;
+#pragma unroll
+        for (int m = 0; m < kTMomOrders; ++m) out[(int64_t)m * n_blk] = make_double2(ar_[m], ai_[m]);
+      }
+#pragma unroll
+      for (int m = 0; m < kTMomOrders; ++m) ar_[m] = ai_[m] = 0.0;
+    }
   }
-  const double ref = red[0];
-  if (tid == 0) {
-    const bool valid = coef[C_VALID * ld + p] != 0.0;
-    logl[p] = valid ? -0.5 * dd + ref + log(red2[0]) - log((double)nt) : -INFINITY;
+  if (what == 1 && p < n) {
+    double2* out = hpart + ((int64_t)ch * n + p) * mh + m0;
+#pragma unroll
+    for (int m = 0; m < kTMomOrders; ++m)
+      if (m0 + m < mh) out[m] = make_double2(ar_[m], ai_[m]);
   }
-}
-
-// Edge chunks of the weight kernel: enough (64-row tile, chunk) waves to fill
-// the chip, chunks of at least 8 edges.
-static int het_tw_chunk(int64_t n, int n_edges) {
-  const int64_t tiles = (n + 63) / 64;
-  int64_t want = (4096 + tiles - 1) / tiles;
-  const int64_t most = (n_edges + 7) / 8;
-  if (want > most) want = most;
-  if (want < 1) want = 1;
-  return (int)((n_edges + want - 1) / want);
 }
 
 template <int ND>
-static void launch_het_tw_nd(gw_ctx* ctx, int64_t n, int prec, int ne_pad, const HetConst& hc, double* wv,
-                             double* hhc, hipStream_t st) {
+static void launch_het_tmom_nd(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, const HetConst& hc,
+                               int what, int m0, double2* mom, double2* hpart, double* hhc, hipStream_t st) {
   const gw_het_state* h = ctx->het;
   const TrigConsts T = make_trig_consts();
-  const int chunk = het_tw_chunk(n, h->n_edges);
-  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((h->n_edges + chunk - 1) / chunk));
+  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)h->tm_nch);
+  const int32_t* bs = h->tm_idx;
+  const int32_t* cb = h->tm_idx + h->tm_nblk + 1;
   if (prec == GW_PREC_FP64)
-    hipLaunchKernelGGL((k_het_tw<ND, 0>), grid, dim3(64), 0, st, (const double*)ctx->coef, n, n,
-                       (const double*)h->rec, h->n_bins, ne_pad, chunk, hc, T, wv, hhc);
+    hipLaunchKernelGGL((k_het_tmom<ND, 0>), grid, dim3(64), 0, st, coef, ld, n, (const double*)h->rec, h->n_bins,
+                       (const double*)h->tm_tab, h->tm_mh, bs, cb, h->tm_nblk, what, m0, hc, T, mom, hpart, hhc);
   else
-    hipLaunchKernelGGL((k_het_tw<ND, 1>), grid, dim3(64), 0, st, (const double*)ctx->coef, n, n,
-                       (const double*)h->rec, h->n_bins, ne_pad, chunk, hc, T, wv, hhc);
+    hipLaunchKernelGGL((k_het_tmom<ND, 1>), grid, dim3(64), 0, st, coef, ld, n, (const double*)h->rec, h->n_bins,
+                       (const double*)h->tm_tab, h->tm_mh, bs, cb, h->tm_nblk, what, m0, hc, T, mom, hpart, hhc);
+}
+
+// Edge chunks of the moment kernel: whole blocks, about n_edges / want edges
+// each, want chosen for about 4096 (tile, chunk) waves (at most 64 chunks), or
+// fixed by gw_set_het_tm_split.
+static int het_tm_chunks(const gw_ctx* ctx, int64_t n) {
+  if (ctx->tm_nsk > 0) return ctx->tm_nsk;
+  const int64_t tiles = (n + 63) / 64;
+  int64_t want = (4096 + tiles - 1) / tiles;
+  const int64_t most = std::max<int64_t>(1, std::min<int64_t>(64, ctx->het->n_edges / 8));
+  return (int)std::max<int64_t>(1, std::min(want, most));
+}
+
+// Row-independent tables of the time marginal for the grid (blocks of blk
+// fine bins, n_blk of them, the window's largest |u| = umax fine-grid cycles)
+// and nch edge chunks.
+static gw_status het_tm_tables(gw_ctx* ctx, int blk, int n_blk, double umax, int nch) {
+  gw_het_state* h = ctx->het;
+  if (h->tm_tab && h->tm_blk == blk && h->tm_nblk == n_blk && h->tm_nch_req == nch && h->tm_umax == umax)
+    return GW_OK;
+  const int ne = h->n_edges;
+  std::vector<int64_t> k(ne);
+  for (int e = 0; e < ne; ++e) k[e] = (int64_t)llround(h->f_edges[e] / ctx->geom.df) - ctx->geom.k0;
+  int64_t dmin = INT64_MAX, dmax = 0;
+  for (int e = 1; e < ne; ++e) {
+    dmin = std::min(dmin, k[e] - k[e - 1]);
+    dmax = std::max(dmax, k[e] - k[e - 1]);
+  }
+  if (ne < 2) dmin = dmax = 0;
+  const double cw = 0.5 * (double)(dmin + dmax), hw = 0.5 * (double)(dmax - dmin);
+  // norm series length: (x^M / M!) e^x below 1e-13, x = 2 pi hw umax
+  const double x = 2.0 * kPi * hw * umax;
+  int mh = 1;
+  double term = x;
+  while (term * exp(x) > 1e-13 && mh < kTgHMax) {
+    ++mh;
+    term *= x / (double)mh;
+  }
+  if (term * exp(x) > 1e-13)
+    return set_error(GW_ENOTSUP, "heterodyned time marginal: bin widths up to %lld fine bins over a +-%.3g s window "
+                                 "need more than %d norm terms", (long long)dmax, ctx->tm_window, kTgHMax);
+  const int tw_ = kTMomOrders + mh;
+  std::vector<double> tab((size_t)ne * tw_, 0.0);
+  std::vector<int32_t> bs(n_blk + 1, 0);
+  const double cen = 0.5 * (blk - 1), hinv = 2.0 / blk;
+  for (int e = 0; e < ne; ++e) {
+    const int64_t b = k[e] / blk;
+    if (b < 0 || b >= n_blk) return set_error(GW_EINVAL, "heterodyned time marginal: edge outside the band");
+    bs[b + 1] += 1;
+    const double sv = ((double)(k[e] - b * blk) - cen) * hinv;
+    double tp = 1.0;
+    for (int m = 0; m < kTMomOrders; ++m) {
+      tab[(size_t)e * tw_ + m] = tp;
+      tp *= sv;
+    }
+    const double sg = e > 0 && hw > 0.0 ? ((double)(k[e] - k[e - 1]) - cw) / hw : 0.0;
+    tp = 1.0;
+    for (int m = 0; m < mh; ++m) {
+      tab[(size_t)e * tw_ + kTMomOrders + m] = tp;
+      tp *= sg;
+    }
+  }
+  for (int b = 0; b < n_blk; ++b) bs[b + 1] += bs[b];
+  // chunks of whole blocks with about ne / nch edges each
+  std::vector<int32_t> cb(1, 0);
+  const double per = (double)ne / nch;
+  for (int b = 1; b < n_blk && (int)cb.size() < nch; ++b)
+    if (bs[b] >= per * (double)cb.size() && bs[b] > bs[cb.back()]) cb.push_back(b);
+  cb.push_back(n_blk);
+  std::vector<int32_t> idx(bs);
+  idx.insert(idx.end(), cb.begin(), cb.end());
+  if (h->tm_tab) (void)hipFree(h->tm_tab);
+  if (h->tm_idx) (void)hipFree(h->tm_idx);
+  h->tm_tab = nullptr;
+  h->tm_idx = nullptr;
+  gw_status s = check_hip(hipMalloc((void**)&h->tm_tab, tab.size() * sizeof(double)), "time-marginal tables");
+  if (s == GW_OK) s = check_hip(hipMalloc((void**)&h->tm_idx, idx.size() * sizeof(int32_t)), "time-marginal index");
+  if (s == GW_OK)
+    s = check_hip(hipMemcpy(h->tm_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice), "tables");
+  if (s == GW_OK)
+    s = check_hip(hipMemcpy(h->tm_idx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice), "index");
+  if (s != GW_OK) return s;
+  h->tm_blk = blk;
+  h->tm_nblk = n_blk;
+  h->tm_mh = mh;
+  h->tm_nch = (int)cb.size() - 1;
+  h->tm_nch_req = nch;
+  h->tm_hw = hw;
+  h->tm_c2 = dmin + dmax;
+  h->tm_umax = umax;
+  return GW_OK;
 }
 
 gw_status loglike_het_tmarg(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl, hipStream_t st) {
@@ -1026,51 +1032,26 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
                                    hipStream_t st) {
   gw_het_state* h = ctx->het;
   if (!h) return set_error(GW_ESTATE, "loglike_batch: heterodyne_setup has not been called");
-  double delta;
-  int32_t nt;
-  gw_status s = gw_time_grid_info(ctx, &delta, &nt, nullptr, nullptr);
+  TimeGridShape g;
+  gw_status s = time_grid_shape(ctx, &g);
+  if (s == GW_OK) s = tgrid_twiddles(ctx, g.L);
+  const int nch = het_tm_chunks(ctx, n);
+  const double umax = (double)g.jmax / ((double)g.N * (double)g.R);
+  if (s == GW_OK) s = het_tm_tables(ctx, g.blk, g.n_blk, umax, nch);
   if (s != GW_OK) return s;
-  const int J = (nt - 1) / 2;
-  const int ne = h->n_edges;
-  // edges padded to a multiple of 32 (zero weights and phasors), so that the
-  // products can be split into up to 32 equal chunks of edges
-  const int ne_pad = (ne + 31) / 32 * 32;
-  if (!h->tm_ef || h->tm_nt != nt || h->tm_delta != delta) {
-    if (h->tm_ef) (void)hipFree(h->tm_ef);
-    h->tm_ef = nullptr;
-    s = check_hip(hipMalloc((void**)&h->tm_ef, (size_t)2 * ne_pad * nt * 2 * sizeof(double)), "time-grid phasors");
-    if (s != GW_OK) return s;
-    const int64_t tot = (int64_t)2 * ne_pad * nt;
-    hipLaunchKernelGGL(k_het_tm_phasors, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
-                       (const double*)h->rec, h->rs, ne, ne_pad, nt, J, delta, make_trig_consts(), h->tm_ef);
-    s = check_hip(hipGetLastError(), "time-grid phasor launch");
-    if (s != GW_OK) return s;
-    h->tm_nt = nt;
-    h->tm_delta = delta;
-  }
-  // split of the products over edge chunks: few rows give few output tiles,
-  // so the edge sum is cut into nsk chunks (a power of two) until about 256
-  // tiles of 64 x 64 are in flight, keeping at least 64 edges per chunk (each
-  // chunk writes a full partial product); the partials are added in chunk
-  // order.  gw_set_het_tm_split fixes nsk instead.
-  int nsk = 1;
-  if (ctx->tm_nsk > 0) {
-    nsk = ctx->tm_nsk;
-  } else {
-    const int64_t tiles = (int64_t)((nt + 63) / 64) * ((n + 63) / 64);
-    while (nsk < 32 && ne_pad / (2 * nsk) >= 64 && tiles * nsk < 256) nsk *= 2;
-  }
-  if (ne_pad % nsk != 0) return set_error(GW_EINVAL, "time marginal: %d edge chunks do not divide %d edges", nsk, ne_pad);
-  const int ke = ne_pad / nsk;
-  // workspace: coefficients, W/V [2][n][ne_pad], Z/H [2][nsk][n][nt], hhc [n]
+  const int64_t chunk = tgrid_chunk_rows(n, g.n_blk);
+  const int mh = h->tm_mh;
+  // workspace: coefficients for all rows; per row chunk the moments
+  // [rows][16][n_blk], the norm moments [n_ch][rows][mh] and hhc [rows]
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
   if (s == GW_OK)
     s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap,
-                      (int64_t)2 * n * ne_pad * 2 + (int64_t)2 * nsk * n * nt * 2 + n, "time-marginal workspace");
+                      chunk * kTMomOrders * g.n_blk * 2 + (int64_t)h->tm_nch * chunk * mh * 2 + chunk,
+                      "time-marginal workspace");
   if (s != GW_OK) return s;
-  double* wv = ctx->tm_mom;
-  double* zh = wv + (int64_t)2 * n * ne_pad * 2;
-  double* hhc = zh + (int64_t)2 * nsk * n * nt * 2;
+  double2* mom = (double2*)ctx->tm_mom;
+  double2* hpart = mom + chunk * kTMomOrders * g.n_blk;
+  double* hhc = (double*)(hpart + (int64_t)h->tm_nch * chunk * mh);
   s = launch_prologue(ctx, theta, n, GW_MARG_PHASE_TIME, ctx->coef, n, st);
   if (s != GW_OK) return s;
   HetConst hc;
@@ -1080,46 +1061,47 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
     hc.hh0[i] = h->hh0[i];
   }
   hc.dd = ctx->dd;
-  switch (ctx->n_det) {
-    case 1: launch_het_tw_nd<1>(ctx, n, prec, ne_pad, hc, wv, hhc, st); break;
-    case 2: launch_het_tw_nd<2>(ctx, n, prec, ne_pad, hc, wv, hhc, st); break;
-    case 3: launch_het_tw_nd<3>(ctx, n, prec, ne_pad, hc, wv, hhc, st); break;
-    case 4: launch_het_tw_nd<4>(ctx, n, prec, ne_pad, hc, wv, hhc, st); break;
-    default: return set_error(GW_ENOTSUP, "n_det not supported");
+  const int nt = 2 * g.jmax + 1;
+  for (int64_t r0 = 0; r0 < n && s == GW_OK; r0 += chunk) {
+    const int64_t cn = n - r0 < chunk ? n - r0 : chunk;
+    const int prof = prof_begin(ctx, st);
+    for (int what = 0; what < 2; ++what)
+      for (int m0 = 0; m0 < (what == 0 ? 1 : mh); m0 += kTMomOrders) {
+        switch (ctx->n_det) {
+          case 1: launch_het_tmom_nd<1>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, hpart, hhc, st); break;
+          case 2: launch_het_tmom_nd<2>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, hpart, hhc, st); break;
+          case 3: launch_het_tmom_nd<3>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, hpart, hhc, st); break;
+          case 4: launch_het_tmom_nd<4>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, hpart, hhc, st); break;
+          default: return set_error(GW_ENOTSUP, "n_det not supported");
+        }
+        s = check_hip(hipGetLastError(), "time-marginal moment launch");
+        if (s != GW_OK) return s;
+      }
+    prof_end(ctx, prof, st);
+    TGridArgs a{};
+    a.mom = (const double*)mom;
+    a.n = cn;
+    a.n_blk = g.n_blk;
+    a.L = g.L;
+    a.jmax = g.jmax;
+    a.tw = ctx->tm_tw;
+    a.coef = ctx->coef + r0;
+    a.ld = n;
+    a.logl = logl + r0;
+    a.het = 1;
+    a.hhc = hhc;
+    a.hpart = (const double*)hpart;
+    a.n_hch = h->tm_nch;
+    a.mh = mh;
+    a.hw_step = 2.0 * kPi * h->tm_hw / ((double)g.N * (double)g.R);
+    a.c2 = h->tm_c2;
+    a.cden = 2 * g.N * (int64_t)g.R;
+    a.zout = zout ? zout + r0 * nt * 3 : nullptr;
+    a.f0_num = (double)(2 * ctx->geom.k0 + g.blk - 1);
+    a.f0_den = (double)(2 * g.N) * (double)g.R;
+    s = launch_tgrid(ctx, a, st);
   }
-  s = check_hip(hipGetLastError(), "edge weight launch");
-  if (s != GW_OK) return s;
-  // Z^T = E^T W^T and H^T = F^T V^T in column-major terms: m = nt, n = rows,
-  // k = edges, with W and V stored edge-major (the rows x edges matrix with
-  // leading dimension n, used transposed); chunk c of nsk takes edges
-  // [c ke, (c + 1) ke) into its own partial (one strided batch per product)
-  if (!ctx->blas) {
-    if (rocblas_create_handle((rocblas_handle*)&ctx->blas) != rocblas_status_success)
-      return set_error(GW_EDEVICE, "rocblas_create_handle failed");
-  }
-  rocblas_handle bh = (rocblas_handle)ctx->blas;
-  if (rocblas_set_stream(bh, st) != rocblas_status_success) return set_error(GW_EDEVICE, "rocblas_set_stream failed");
-  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
-  const int prof = prof_begin(ctx, st);
-  rocblas_status bs = rocblas_status_success;
-  for (int q = 0; q < 2 && bs == rocblas_status_success; ++q) {
-    const rocblas_double_complex* A = (const rocblas_double_complex*)(h->tm_ef + (int64_t)q * ne_pad * nt * 2);
-    const rocblas_double_complex* B = (const rocblas_double_complex*)(wv + (int64_t)q * n * ne_pad * 2);
-    rocblas_double_complex* Cm = (rocblas_double_complex*)(zh + (int64_t)q * nsk * n * nt * 2);
-    if (nsk == 1 && q == 1) break;  // one call covers both products
-    const int batch = nsk == 1 ? 2 : nsk;
-    bs = rocblas_zgemm_strided_batched(
-        bh, rocblas_operation_none, rocblas_operation_transpose, nt, (rocblas_int)n, nsk == 1 ? ne_pad : ke, &one, A,
-        nt, nsk == 1 ? (rocblas_stride)ne_pad * nt : (rocblas_stride)ke * nt, B, (rocblas_int)n,
-        nsk == 1 ? (rocblas_stride)n * ne_pad : (rocblas_stride)ke * n, &zero, Cm, nt, (rocblas_stride)n * nt, batch);
-  }
-  prof_end(ctx, prof, st);
-  if (bs != rocblas_status_success) return set_error(GW_EDEVICE, "rocblas_zgemm_strided_batched: status %d", (int)bs);
-  LogI0Consts C = make_log_i0_consts();
-  C.r1max = ctx->dist_r1max;
-  hipLaunchKernelGGL(k_het_tfinal, dim3((unsigned)n), dim3(256), 0, st, (const double*)zh, (const double*)hhc,
-                     (const double*)ctx->coef, n, n, nt, nsk, ctx->dd, C, logl, zout);
-  return check_hip(hipGetLastError(), "time-marginal epilogue launch");
+  return s;
 }
 
 gw_status loglike_het(gw_ctx* ctx, const double* theta, int64_t n, int marg, int prec, double* logl, hipStream_t st) {

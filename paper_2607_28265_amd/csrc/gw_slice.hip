@@ -81,6 +81,13 @@ struct SweepParams {
   int32_t screen;
   double cut;
   double audit_frac;
+  // record = 1 appends every exactly evaluated candidate (unit-cube point,
+  // log L) to the ring buffer rec_x / rec_l at slot (*rec_count)++ mod rec_cap
+  int32_t record;
+  int64_t rec_cap;
+  double* rec_x;
+  double* rec_l;
+  unsigned long long* rec_count;
 };
 
 // passed by value to the kernel that copies it to the device
@@ -286,11 +293,11 @@ __global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S,
           prior_transform(u, cand + (2 * c + side) * 13, P.cm);
           S.cand_t[2 * c + side] = t;
           ok[side] = 1;
-          if (P.screen) {
+          if (P.screen || P.record)
             for (int j = 0; j < kSliceDim; ++j) S.ucand[(2 * c + side) * kSliceDim + j] = u[j];
+          if (P.screen)
             S.scr[2 * c + side] =
                 audit_uniform(P, b, c, side, S.side_tests[2 * c + side]) < P.audit_frac ? 2 : 0;
-          }
         } else {
           fl &= ~(1 << side);  // outside the cube: this side stops here
         }
@@ -306,10 +313,9 @@ __global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S,
           prior_transform(u, cand + 2 * c * 13, P.cm);
           S.cand_t[2 * c] = t;
           ok[0] = 1;
-          if (P.screen) {
+          if (P.screen || P.record)
             for (int j = 0; j < kSliceDim; ++j) S.ucand[2 * c * kSliceDim + j] = u[j];
-            S.scr[2 * c] = audit_uniform(P, b, c, 2, S.n_shrink[c]) < P.audit_frac ? 2 : 0;
-          }
+          if (P.screen) S.scr[2 * c] = audit_uniform(P, b, c, 2, S.n_shrink[c]) < P.audit_frac ? 2 : 0;
           break;
         }
         if (t < 0.0) S.t_lo[c] = t;
@@ -364,6 +370,14 @@ __global__ void k_sweep_screen(const SweepParams* __restrict__ D, SliceState S, 
   th[1] = -1.0;
 }
 
+// Append an exactly evaluated candidate to the caller's ring buffer.
+__device__ inline void record_pair(const SweepParams& P, const SliceState& S, int64_t slot, double v) {
+  if (!P.record) return;
+  const int64_t pos = (int64_t)(atomicAdd(P.rec_count, 1ull) % (unsigned long long)P.rec_cap);
+  for (int j = 0; j < kSliceDim; ++j) P.rec_x[pos * kSliceDim + j] = S.ucand[slot * kSliceDim + j];
+  P.rec_l[pos] = v;
+}
+
 __global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, const double* __restrict__ cand_logl) {
   const SweepParams& P = *D;
   double* __restrict__ x = P.x;
@@ -386,6 +400,7 @@ __global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, 
       } else {
         S.n_evals[c] += 1;
         in = cand_logl[2 * c + side] > P.logl_star;
+        record_pair(P, S, 2 * c + side, cand_logl[2 * c + side]);
         if (P.screen && S.scr[2 * c + side] == 2) {
           atomicAdd(&S.scr_tot[1], 1ull);
           if (in) atomicAdd(&S.scr_tot[2], 1ull);
@@ -409,6 +424,7 @@ __global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, 
     } else {
       S.n_evals[c] += 1;
       v = cand_logl[2 * c];
+      record_pair(P, S, 2 * c, v);
       if (P.screen && S.scr[2 * c] == 2) {
         atomicAdd(&S.scr_tot[1], 1ull);
         if (v > P.logl_star) atomicAdd(&S.scr_tot[2], 1ull);
@@ -775,6 +791,21 @@ static gw_status set_screen(const char* who, const gw_ctx* ctx, gw_mlp* mlp, dou
   return GW_OK;
 }
 
+// Candidate recording arguments shared by both entry points.
+static gw_status set_record(const char* who, double* rec_x, double* rec_logl, int64_t rec_cap,
+                            unsigned long long* rec_count, SweepParams& P) {
+  P.record = 0;
+  if (!rec_x && !rec_logl && !rec_count) return GW_OK;
+  if (!rec_x || !rec_logl || !rec_count || rec_cap < 1)
+    return set_error(GW_EINVAL, "%s: rec_x, rec_logl and rec_count with rec_cap >= 1, or none of them", who);
+  P.record = 1;
+  P.rec_cap = rec_cap;
+  P.rec_x = rec_x;
+  P.rec_l = rec_logl;
+  P.rec_count = rec_count;
+  return GW_OK;
+}
+
 // Check one block (indices distinct in 0..10, 1..11 of them) and pack its
 // lower Cholesky factor (row-major, stride ``ld``) into P.chol.  A block equal
 // to an earlier one of the sweep (same coordinates and factor) shares its
@@ -944,6 +975,7 @@ gw_status slice_step(gw_ctx* ctx, const gw_slice_args* a, void* stream) {
   P.lists = a->like == GW_FULL && a->marg == GW_MARG_PHASE_DIST;
   s = cube_map(ctx, a->marg, &P.cm);
   if (s == GW_OK) s = set_screen("slice_step", ctx, a->mlp, a->margin, a->audit_frac, P);
+  if (s == GW_OK) s = set_record("slice_step", a->rec_x, a->rec_logl, a->rec_cap, a->rec_count, P);
   if (s != GW_OK) return s;
   // the time marginal sets up tables on first use and calls the BLAS library:
   // its rounds are launched eagerly
@@ -1002,6 +1034,7 @@ gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* a, void* stream) {
   P.lists = a->like == GW_FULL && a->marg == GW_MARG_PHASE_DIST;
   s = cube_map(ctx, a->marg, &P.cm);
   if (s == GW_OK) s = set_screen("slice_sweep", ctx, a->mlp, a->margin, a->audit_frac, P);
+  if (s == GW_OK) s = set_record("slice_sweep", a->rec_x, a->rec_logl, a->rec_cap, a->rec_count, P);
   if (s != GW_OK) return s;
   const int32_t graph = a->use_graph && a->marg != GW_MARG_PHASE_TIME;  // as in slice_step
   const SweepCall c{a->like, a->marg, a->prec, graph, a->n_evals, a->status, P.cache, a->eval_kinds, P.lists,

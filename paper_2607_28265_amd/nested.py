@@ -16,10 +16,14 @@ a control (M d joint slice steps per iteration, M = 3).  With ``cache=True`` (fu
 chain's waveform and reuses it on the extrinsic blocks (Sec. III.B).  With
 ``marg=GW_MARG_PHASE_TIME`` the phase and coalescence time are marginalised
 and d_L is sampled in place of t_c (the paper's GW170817 configuration).
-With ``prescreen`` (an addition; see prescreen.py) a network trained on the
-run's own dead and live points screens the slice candidates inside every
-sweep from iteration ``start`` on, retrained every ``every`` iterations; an
-accepted point always carries its exact log L.
+With ``prescreen`` (an addition; see prescreen.py) every exactly evaluated
+slice candidate is recorded (unit-cube point, log L) in a device ring buffer,
+and from iteration ``start`` on a network trained on the recorded pairs and
+the live set screens the candidates inside every sweep, retrained every
+``every`` iterations.  The audit draws' false-negative count drives the margin:
+whenever more than ``fn_target`` of the audited screened-out candidates since
+the last change turn out inside, the margin grows by half.  An accepted point
+always carries its exact log L.
 
 The host keeps the FP64 evidence bookkeeping (the k deletions taken in order
 with live counts m, m-1, ..., m-k+1), the start-point choice and the block
@@ -95,10 +99,16 @@ class NestedSampler:
         self.moves = 0  # blocks that moved (accepted proposals)
         if prescreen is not None:
             from .prescreen import Prescreen
-            cfg = dict(start=100, every=50, window=40, audit=0.01, epochs=30, batch=1024, seed=7, k_margin=3.0)
+            cfg = dict(start=100, every=50, audit=0.01, steps=1500, retrain_steps=400, batch=1024, seed=7,
+                       k_margin=3.0, fn_target=0.02, capacity=1 << 17)
             cfg.update(prescreen)
             self.pre_cfg = cfg
             self.pre = Prescreen(ctx, seed=int(cfg["seed"]))
+            cap = int(cfg["capacity"])
+            self.rec = (torch.empty((cap, N_DIM), dtype=torch.float64, device=self.dev),
+                        torch.empty(cap, dtype=torch.float64, device=self.dev),
+                        torch.zeros(1, dtype=torch.int64, device=self.dev))
+            self._fn = [0, 0]  # audited, audited and inside since the margin last changed
 
     # -- likelihood of unit-cube points (initial live set) ------------------
     def _eval(self, x, out):
@@ -162,12 +172,12 @@ class NestedSampler:
                                          [chols[b] for b in part], seed=self.seed, counter=self.counter, w=self.w,
                                          max_out=self.max_out, max_shrink=self.max_shrink, like=self.like,
                                          marg=self.marg, prec=self.prec, n_evals=ne, status=caps,
-                                         use_cache=self.cache, prescreen=pre, screen_stats=st)
+                                         use_cache=self.cache, prescreen=pre, screen_stats=st,
+                                         record=self.rec if self.pre is not None else None)
                 if kinds is not None:
                     self.eval_kinds += np.array(kinds, np.int64)
                 if st:
-                    for key in self.screen_stats:
-                        self.screen_stats[key] += st[key]
+                    self._count_screen(st)
                 self.n_evals += int(ne.sum().item())
                 self.moves += self.k * len(part) - int(caps.sum().item())
                 self.counter += len(part)
@@ -177,10 +187,9 @@ class NestedSampler:
                 _lib.slice_step(self.ctx.handle, xn, ln, lstar, b, chols[bi], seed=self.seed, counter=self.counter,
                                 w=self.w, max_out=self.max_out, max_shrink=self.max_shrink, like=self.like,
                                 marg=self.marg, prec=self.prec, n_evals=ne, status=caps, prescreen=pre,
-                                screen_stats=st)
+                                screen_stats=st, record=self.rec if self.pre is not None else None)
                 if st:
-                    for key in self.screen_stats:
-                        self.screen_stats[key] += st[key]
+                    self._count_screen(st)
                 self.n_evals += int(ne.sum().item())
                 self.moves += self.k - int(caps.sum().item())
                 self.counter += 1
@@ -189,6 +198,17 @@ class NestedSampler:
         self.logl.index_copy_(0, wi, ln)
         self.iteration += 1
 
+    def _count_screen(self, st):
+        for key in self.screen_stats:
+            self.screen_stats[key] += st[key]
+        self._fn[0] += st["audited"]
+        self._fn[1] += st["audited_inside"]
+        # the audit estimates the share of screened-out candidates that were
+        # inside; above the target the margin widens
+        if self._fn[0] >= 50 and self._fn[1] > self.pre_cfg["fn_target"] * self._fn[0]:
+            self.pre.margin *= 1.5
+            self._fn = [0, 0]
+
     def _prescreen(self, lstar):
         """The (network, margin, audit fraction) for this iteration's sweeps,
         training it first when due, or None."""
@@ -196,11 +216,17 @@ class NestedSampler:
             return None
         cfg = self.pre_cfg
         if (self.iteration - cfg["start"]) % cfg["every"] == 0:
-            from .prescreen import sampler_pairs
             t0 = time.perf_counter()
-            x, y = sampler_pairs(self, last_iters=cfg["window"])
-            self.pre.train(x, y, self.x.cpu().numpy(), lstar, epochs=cfg["epochs"], batch=cfg["batch"])
+            cnt = int(self.rec[2].item())
+            n_rec = min(cnt, self.rec[0].shape[0])
+            x = np.concatenate([self.rec[0][:n_rec].cpu().numpy(), self.x.cpu().numpy()])
+            y = np.concatenate([self.rec[1][:n_rec].cpu().numpy(), self.logl.cpu().numpy()])
+            steps = cfg["steps"] if self.pre_trainings == 0 else cfg["retrain_steps"]
+            n_train = int(0.9 * len(x))
+            epochs = max(1, int(math.ceil(steps * cfg["batch"] / max(n_train, 1))))
+            self.pre.train(x, y, self.x.cpu().numpy(), lstar, epochs=epochs, batch=cfg["batch"])
             self.pre.set_margin(lstar, k=cfg["k_margin"])
+            self._fn = [0, 0]
             self.pre_train_s += time.perf_counter() - t0
             self.pre_trainings += 1
         return (self.pre.mlp, self.pre.margin, cfg["audit"])

