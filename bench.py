@@ -198,25 +198,36 @@ def het_leg(gw, torch, prob, th_inj, steps, warmup):
             nb_res["n_bins"] = n_bins
             res[f"bins_{n_bins}"] = nb_res
             ctx.set_het_shape(4, 0, 0)
-        # phase+time marginal on the 500 bins and the same proposals
-        ctx.heterodyne_setup(th_inj, 500)
-        tm = {}
-        for name, prec in (("mixed", gw.GW_PREC_MIXED), ("fp64", gw.GW_PREC_FP64)):
-            for _ in range(2):
-                ctx.loglike(theta, gw.GW_HET, gw.GW_MARG_PHASE_TIME, prec, out=out)
-            torch.cuda.synchronize()
-            gw._lib.gw_profile_read(ctx.handle)
-            gw._lib.gw_profile_enable(ctx.handle, True)
-            reps = max(3, steps // 2)
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                ctx.loglike(theta, gw.GW_HET, gw.GW_MARG_PHASE_TIME, prec, out=out)
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / reps
-            ms, nl = gw._lib.gw_profile_read(ctx.handle)
-            gw._lib.gw_profile_enable(ctx.handle, False)
-            tm[name] = {"value": n / dt, "ms_per_batch": dt * 1e3, "grid_kernel_ms": ms / max(nl, 1)}
-        res["time_marginal_500_bins"] = tm
+        # phase+time marginal on 500 and 5000 bins and the same proposals
+        delta, n_t, p_len, blk = gw.gw_time_grid_info(ctx.handle)
+        L = p_len * 4
+        K = tgrid_orders(L, (n_t - 1) // 2)
+        for n_bins in (500, 5000):
+            ctx.heterodyne_setup(th_inj, n_bins)
+            tm = {}
+            for name, prec in (("mixed", gw.GW_PREC_MIXED), ("fp64", gw.GW_PREC_FP64)):
+                run = lambda: ctx.loglike(theta, gw.GW_HET, gw.GW_MARG_PHASE_TIME, prec, out=out)
+                for _ in range(2):
+                    run()
+                torch.cuda.synchronize()
+                reps = max(3, steps // 2)
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    run()
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / reps
+                mom_ms, n_mom = time_kernel(gw, torch, ctx, run, reps, 1)
+                grid_ms, n_grid = time_kernel(gw, torch, ctx, run, reps, 2)
+                rows_per_launch = n * reps / max(n_grid, 1)
+                gflops = tgrid_flops_per_row(K, L) * rows_per_launch
+                tm[name] = {"value": n / dt, "ms_per_batch": dt * 1e3,
+                            "moments_ms_per_batch": mom_ms * n_mom / reps,
+                            "k_tgrid_ms_per_batch": grid_ms * n_grid / reps,
+                            "k_tgrid_roofline": {"bound": "alu", "achieved": gflops / (grid_ms * 1e-3) / 1e12,
+                                                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                                 "frac": gflops / (grid_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                                                 "rows_per_launch": rows_per_launch}}
+            res[f"time_marginal_{n_bins}_bins"] = tm
         n_graphs, inst_ms = gw._lib.gw_graph_info(ctx.handle)
     res.update({"unit": "logL evals/s", "batch": n, "n_sub": int(subs.shape[0]),
                 "graph_instantiate_ms": inst_ms,
@@ -502,34 +513,90 @@ def cache_leg(gw, torch, prob, steps, warmup, mixed_value):
     return res
 
 
+def tgrid_orders(L, jmax):
+    """Expansion orders the library takes for a grid (12 when the dropped
+    Chebyshev terms' bound 2 (phi/2)^12 / 12! at phi = pi jmax / L is at most
+    2e-11, else 16)."""
+    phi = math.pi * jmax / L
+    b = 2.0
+    for i in range(1, 13):
+        b *= 0.5 * phi / i
+    return 12 if b <= 2e-11 else 16
+
+
+# k_tmom (mixed, ND = 3), FP64 flops per (row, bin) on the recurrence path, from
+# the source: phase recurrence 3, cycle reduction 1, detector sums 3 x 4 FMA,
+# two delay rotations 2 x 6, y = g s 6, and K moment updates of 2 FMA each.
+def tmom_flops_per_bin(K):
+    return 3 + 1 + 24 + 12 + 6 + 4 * K
+
+
+# k_tgrid, FP64 flops per row: K transforms of L points at the conventional
+# 5 L log2 L, plus the weighted accumulation (2 FMA per point and order); the
+# grid epilogue (ln I0, log-sum-exp) is not counted.
+def tgrid_flops_per_row(K, L):
+    return K * (5 * L * math.log2(L) + 4 * L)
+
+
+def time_kernel(gw, torch, ctx, fn, steps, mode):
+    gw._lib.gw_profile_read(ctx.handle)
+    gw._lib.gw_profile_enable(ctx.handle, mode)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ms, nl = gw._lib.gw_profile_read(ctx.handle)
+    gw._lib.gw_profile_enable(ctx.handle, 0)
+    return ms / max(nl, 1), nl
+
+
 def tmarg_leg(gw, torch, ctx, theta, steps, warmup, mixed_value):
     """Phase + coalescence-time marginal on the same 4096 proposals of the
-    128 s band: grid t_j = j / 4096 s over |t| <= 0.1 s (819 points), block
-    moments of 512 bins and 16 FFTs of length 1024 per proposal."""
+    128 s band: grid t_j = j / 16384 s over |t| <= 0.1 s (3273 points, R = 4),
+    block moments of 512 bins (K Chebyshev orders) and K FFTs of 4096 points
+    per proposal; k_tmom and k_tgrid timed separately with HIP events."""
     n = theta.shape[0]
     out = torch.empty(n, dtype=torch.float64, device="cuda")
+    delta, n_t, p_len, blk = gw.gw_time_grid_info(ctx.handle)
+    R = 4
+    L = p_len * R
+    jmax = (n_t - 1) // 2
+    K = tgrid_orders(L, jmax)
     res = {}
     for name, prec in (("mixed", gw.GW_PREC_MIXED), ("fp64", gw.GW_PREC_FP64)):
+        run = lambda: ctx.loglike(theta, gw.GW_FULL, gw.GW_MARG_PHASE_TIME, prec, out=out)
         for _ in range(warmup):
-            ctx.loglike(theta, gw.GW_FULL, gw.GW_MARG_PHASE_TIME, prec, out=out)
+            run()
         torch.cuda.synchronize()
-        gw._lib.gw_profile_read(ctx.handle)
-        gw._lib.gw_profile_enable(ctx.handle, True)
         t0 = time.perf_counter()
         for _ in range(steps):
-            ctx.loglike(theta, gw.GW_FULL, gw.GW_MARG_PHASE_TIME, prec, out=out)
+            run()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        ms, nl = gw._lib.gw_profile_read(ctx.handle)
-        gw._lib.gw_profile_enable(ctx.handle, False)
-        res[name] = {"value": n / dt, "ms_per_batch": dt * 1e3, "k_tmom_ms": ms / max(nl, 1)}
-    delta, n_t, p_len, blk = gw.gw_time_grid_info(ctx.handle)
+        mom_ms, _ = time_kernel(gw, torch, ctx, run, steps, 1)
+        grid_ms, _ = time_kernel(gw, torch, ctx, run, steps, 2)
+        r = {"value": n / dt, "ms_per_batch": dt * 1e3, "k_tmom_ms": mom_ms, "k_tgrid_ms": grid_ms}
+        gflops = tgrid_flops_per_row(K, L) * n
+        r["k_tgrid_roofline"] = {"bound": "alu", "achieved": gflops / (grid_ms * 1e-3) / 1e12,
+                                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": gflops / (grid_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                                 "flops_per_row": tgrid_flops_per_row(K, L)}
+        if name == "mixed":
+            mflops = tmom_flops_per_bin(K) * n * prob_n_freq(ctx)
+            r["k_tmom_roofline"] = {"bound": "alu", "achieved": mflops / (mom_ms * 1e-3) / 1e12,
+                                    "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": mflops / (mom_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                                    "flops_per_bin": tmom_flops_per_bin(K)}
+        res[name] = r
     res["cost_vs_distance_marginal_mixed"] = mixed_value / res["mixed"]["value"]
-    res.update({"unit": "logL evals/s", "batch": n, "grid_points": n_t, "delta_s": delta, "fft_len": p_len,
-                "block_bins": blk,
-                "workload": "phase+time marginal on the 128 s full band, 4096 prior draws, t_c grid of the "
-                            "segment's sampling interval over +-0.1 s"})
+    res.update({"unit": "logL evals/s", "batch": n, "grid_points": n_t, "delta_s": delta, "blocks_P": p_len,
+                "fft_len": L, "orders": K, "block_bins": blk,
+                "workload": "phase+time marginal on the 128 s full band, 4096 prior draws, t_c grid of a quarter "
+                            "of the segment's sampling interval over +-0.1 s"})
     return res
+
+
+def prob_n_freq(ctx):
+    return int(ctx.n_freq)
 
 
 def nested_full_leg(gw, torch):

@@ -154,14 +154,16 @@ gw_status loglike_batch(gw_ctx* ctx, const double* theta, int64_t n, int32_t lik
  *   log L = -<d|d>/2 - <h|h>/2 + ln[ (1/N_t) sum_j I0(|Z(t_j)|) ],
  * Z(t) the overlap of the template shifted by t (template at t_c = 0).  The
  * library cuts the band into blocks of N / P bins (P the smallest power of two
- * >= 2 J + 1), within which the time shift is expanded to 16 terms (first
- * dropped term below 1e-10 of the block's overlap sum), and evaluates every
- * grid point with one FFT of length P R per term over the blocks.  W defaults
- * to 0.1 s; gw_set_time_window changes it (GW_ENOTSUP if P would exceed 2048);
- * a grid whose transform P R would exceed 4096 points is GW_ENOTSUP at
- * evaluation.  gw_time_grid_info reports the grid step delta / R, the number of
- * points N_t = 2 J R + 1, P and the block length.  Work space: n x (n_freq / B)
- * x 256 bytes per call.
+ * >= 2 J + 1, and at least 16 / R), within which the time shift is expanded in
+ * Chebyshev polynomials of the bin's offset (Jacobi-Anger: K = 12 terms when
+ * the dropped ones stay below 2e-11 of the block's sum of |overlap weight|,
+ * every grid of the default window, else 16), and evaluates every grid point
+ * with one FFT of length P R per term over the blocks.  W defaults to 0.1 s;
+ * gw_set_time_window changes it (GW_ENOTSUP if P would exceed 2048); a grid
+ * whose transform P R would exceed 4096 points is GW_ENOTSUP at evaluation.
+ * gw_time_grid_info reports the grid step delta / R, the number of points
+ * N_t = 2 J R + 1, P and the block length.  Work space: n x (n_freq / B) x
+ * 16 K bytes per call (in row chunks of at most 1 GiB).
  * With like = GW_HET the same grid sum runs on the binned likelihood, the
  * appendix's direct summation on the heterodyned bins: at every t_j the
  * phase-marginal binned log L of the template shifted by t_j (the binned
@@ -720,9 +722,11 @@ gw_status gw_full_phase_runs(const gw_ctx* ctx, int32_t* k_min, int32_t* len);
 gw_status gw_phasor_gain(const gw_ctx* ctx, double* re, double* im);
 
 /*
- * Kernel timing of the dominant kernel (full-band overlap kernel, or the
- * heterodyned evaluation kernel) for roofline reporting: while enabled, every
- * launch of it is bracketed by HIP events recorded on the launch stream.
+ * Kernel timing for roofline reporting.  enable = 1: the dominant kernel (the
+ * full-band overlap kernel, the heterodyned evaluation kernel, or the moment
+ * kernel of a time marginal); enable = 2: the time-grid kernel of the time
+ * marginals; 0 turns timing off.  While enabled, every launch of the chosen
+ * kernel is bracketed by HIP events recorded on the launch stream.
  * gw_profile_read waits for the recorded events, returns the summed kernel
  * time (ms) and the number of launches, and clears the record.  At most 4096
  * launches are recorded between reads (later ones are not timed).

@@ -369,8 +369,9 @@ def gw_phasor_gain(ctx):
     return complex(re.value, im.value)
 
 
-def gw_profile_enable(ctx, enable: bool = True):
-    check(load().gw_profile_enable(ctx, 1 if enable else 0), "gw_profile_enable")
+def gw_profile_enable(ctx, enable=True):
+    """enable: True/1 the dominant kernel, 2 the time-grid kernel, False/0 off."""
+    check(load().gw_profile_enable(ctx, int(enable)), "gw_profile_enable")
 
 
 def gw_profile_read(ctx):

@@ -68,8 +68,8 @@ struct CompSum {
 
 constexpr int kProfSlots = 4096;
 
-int prof_begin(gw_ctx* ctx, hipStream_t st) {
-  if (!ctx->prof || ctx->prof_used >= kProfSlots) return -1;
+int prof_begin(gw_ctx* ctx, hipStream_t st, int which) {
+  if (ctx->prof != which || ctx->prof_used >= kProfSlots) return -1;
   if (ctx->prof_ev.empty()) {
     ctx->prof_ev.resize(2 * kProfSlots, nullptr);
   }
@@ -237,7 +237,7 @@ gw_status gw_ctx_destroy(gw_ctx* ctx) {
   for (hipEvent_t e : ctx->prof_ev)
     if (e) (void)hipEventDestroy(e);
   double* bufs[] = {ctx->bins,   ctx->dist_tab, ctx->coef,   ctx->partial, ctx->zbuf,
-                    ctx->tm_tw,  ctx->tm_tpow,  ctx->tm_mom, ctx->recon};
+                    ctx->tm_ccoef, ctx->tm_basis, ctx->tm_mom, ctx->recon};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (ctx->wtab) (void)hipFree(ctx->wtab);
@@ -278,7 +278,7 @@ gw_status loglike_batch(gw_ctx* ctx, const double* theta, int64_t n, int32_t lik
   const int64_t ld = n;
   s = launch_prologue(ctx, theta, n, marg, ctx->coef, ld, st);
   if (s == GW_OK) {
-    const int slot = prof_begin(ctx, st);
+    const int slot = prof_begin(ctx, st, 1);
     s = launch_full(ctx, ctx->coef, ld, n, prec, tpb, nch, ctx->partial, st);
     prof_end(ctx, slot, st);
   }
@@ -301,7 +301,8 @@ gw_status gw_template(gw_ctx* ctx, const double* theta, int64_t n, double* h, vo
 
 gw_status gw_profile_enable(gw_ctx* ctx, int32_t enable) {
   if (!ctx) return set_error(GW_EINVAL, "gw_profile_enable: ctx is NULL");
-  ctx->prof = enable != 0;
+  if (enable < 0 || enable > 2) return set_error(GW_EINVAL, "gw_profile_enable: enable must be 0, 1 or 2");
+  ctx->prof = enable;
   return GW_OK;
 }
 

@@ -55,17 +55,17 @@ struct gw_ctx {
   int mom_blk = 0;                 // bins per block (power of two, >= 8); 0 = form unavailable
   int64_t mom_pad = 0;             // n_freq rounded up to a multiple of mom_blk
   // kernel timing (gw_profile_enable / gw_profile_read)
-  bool prof = false;
+  int prof = 0;                     // 0 off, 1 the dominant kernel, 2 the time-grid kernel
   std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
   int prof_used = 0;
   // time marginal: window half-width (s), FFT twiddles and moment workspace
   double tm_window = 0.1;
   int tm_R = 4;                    // grid points per sampling interval of the segment
   int tm_nsk = 0;                  // edge chunks of the heterodyned time marginal's moments (0 = heuristic)
-  int tm_L = 0;                    // length of the time-grid transform the twiddles were built for
-  double* tm_tw = nullptr;         // [tm_L] complex exp(-2 pi i t / tm_L)
-  double* tm_tpow = nullptr;        // [blk][16] powers of the in-block offset for the moments
-  int tm_tpow_blk = 0;
+  double* tm_ccoef = nullptr;      // [K][256][16] expansion coefficients of the grid (tm_cc_L, tm_cc_jmax, tm_cc_K)
+  int tm_cc_L = 0, tm_cc_jmax = 0, tm_cc_K = 0;
+  double* tm_basis = nullptr;      // [blk][K] Chebyshev values of the in-block offset for the moments
+  int tm_basis_blk = 0, tm_basis_K = 0;
   double* tm_mom = nullptr;
   int64_t tm_mom_cap = 0;
   // sampler sky frame: 0 equatorial (ra, dec), 1 zenith and azimuth about the
@@ -138,15 +138,14 @@ gw_status build_moment_table(gw_ctx* ctx, const std::vector<double>& rec, const 
 gw_status calibrate_phasor(gw_ctx* ctx);
 
 // Time-grid sums from block moments (gw_tgrid.hip), shared by the full-band
-// and heterodyned time marginals: moments [n][kTMomOrders][n_blk] complex,
-// one FFT of length L = P R per order, the grid t_j = j delta / R, |j| <= jmax.
-constexpr int kTMomOrders = 16;
+// and heterodyned time marginals: moments [n][K][n_blk] complex (K expansion
+// orders, 12 or 16), one FFT of length L = P R per order, the grid
+// t_j = j delta / R, |j| <= jmax.
 constexpr int kTgHMax = 48;  // most norm moments of the heterodyned form
 struct TGridArgs {
   const double* mom;
   int64_t n;
-  int n_blk, L, jmax;
-  const double* tw;   // [L] complex exp(-2 pi i t / L)
+  int n_blk, L, jmax, K;
   const double* coef;  // prologue coefficients of the n rows (stride ld)
   int64_t ld;
   double* logl;
@@ -159,7 +158,6 @@ struct TGridArgs {
   double* zout;        // or NULL: [n][2 jmax + 1][3] staged grid values
   double f0_num, f0_den;  // f_0 t_j = j f0_num / f0_den cycles
 };
-bool tgrid_plan(int L, int4* radix, int* n_pass);
 // The context's time grid: segment length N (samples), J and R (|j| <= jmax =
 // J R), P, blocks of blk = N / P fine bins (n_blk of them), L = P R.
 struct TimeGridShape {
@@ -168,10 +166,10 @@ struct TimeGridShape {
   int J, R, P, blk, n_blk, L, jmax;
 };
 gw_status time_grid_shape(const gw_ctx* ctx, TimeGridShape* g);
-// The context's twiddle table for transforms of length L (rebuilt when L
-// changes), and the rows per chunk whose moments fit the bounded workspace.
-gw_status tgrid_twiddles(gw_ctx* ctx, int L);
-int64_t tgrid_chunk_rows(int64_t n, int n_blk);
+// The context's coefficient table for a grid (rebuilt when L, jmax or K
+// change), and the rows per chunk whose moments fit the bounded workspace.
+gw_status tgrid_tables(gw_ctx* ctx, int L, int jmax, int K);
+int64_t tgrid_chunk_rows(int64_t n, int n_blk, int K);
 gw_status launch_tgrid(const gw_ctx* ctx, const TGridArgs& a, hipStream_t st);
 
 // Record the device address of ``device``'s copy of the allocation-free
@@ -191,7 +189,7 @@ gw_status mlp_infer(gw_mlp* m, const double* x, int64_t n, double* out, hipStrea
 
 // Kernel timing: record a start / stop event pair around the dominant kernel.
 // prof_begin returns the pair index or -1 when timing is off or full.
-int prof_begin(gw_ctx* ctx, hipStream_t st);
+int prof_begin(gw_ctx* ctx, hipStream_t st, int which = 1);
 void prof_end(gw_ctx* ctx, int slot, hipStream_t st);
 
 // Grow the workspace a likelihood call of n rows needs, without launching

@@ -404,6 +404,7 @@ __device__ inline double wave_dist_lse(double z1, double hh1, const double* __re
   const int tier = wave_i0_tier(z1, C);
   double s = 0.0;
   for (int j = lane; j < n_dist; j += 64) {
+    asm volatile("" ::: "memory");  // coefficient loads stay in the loop (see slice_dist_sum)
     const double* r = tab + 4 * j;
     const double a = fma(-hh1, r[2], r[3]);
     const double x = z1 * r[1];
@@ -485,6 +486,10 @@ __device__ inline double slice_dist_sum(double z1, double hh1, double bmax, cons
   const int tier = wave_i0_tier(z1, C);
   double s = 0.0;
   for (int j = j0; j < j1; ++j) {
+    // Keeps the series coefficients' loads in the loop: hoisted, the 64
+    // doubles exceed the scalar registers and spill into vector lanes, read
+    // back lane by lane at every use.
+    asm volatile("" ::: "memory");
     const double* r = tab + 4 * j;
     const double a = fma(-hh1, r[2], r[3]);
     const double x = z1 * r[1];

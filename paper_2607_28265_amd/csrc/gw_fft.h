@@ -69,6 +69,24 @@ __host__ __device__ inline double2 w16(int k) {
   }
 }
 
+// DFT4 of t[0..4) with only the leading NZ inputs nonzero (NZ in {1, 2, 4}).
+template <int NZ>
+__host__ __device__ inline void dft4_nz(double2* t) {
+  if constexpr (NZ == 1) {
+    t[1] = t[0];
+    t[2] = t[0];
+    t[3] = t[0];
+  } else if constexpr (NZ == 2) {
+    const double2 a = t[0], b = t[1], mb = c_mul_mi(b);
+    t[0] = c_add(a, b);
+    t[1] = c_add(a, mb);
+    t[2] = c_sub(a, b);
+    t[3] = c_sub(a, mb);
+  } else {
+    Dft<4>::run(t);
+  }
+}
+
 // Radix 8 and 16 in place as (R / 4) x 4: with n = n1 + (R / 4) n2 and
 // k = 4 k1 + k2, DFT4 over n2 for each n1, twiddle by exp(-2 pi i n1 k2 / R),
 // then DFT over n1 for each k2.  Output k lands in slot slot<R>(k) of v.
@@ -98,6 +116,29 @@ struct Dft {
       Dft<A>::run(t);
 #pragma unroll
       for (int k1 = 0; k1 < A; ++k1) v[A * k2 + k1] = t[k1];  // X[4 k1 + k2]
+    }
+  }
+  // run_slots for inputs of which only v[0 .. NZ) may be nonzero (R = 16,
+  // NZ in {1, 2, 4, 8, 16}; the others must hold zero): the work on the known
+  // zeros is skipped
+  template <int NZ>
+  __host__ __device__ static inline void run_slots_nz(double2* v) {
+    static_assert(R == 16, "pruned form for radix 16 only");
+    constexpr int N1 = NZ < 4 ? NZ : 4;        // rows n1 holding a nonzero input
+    constexpr int N2 = NZ <= 4 ? 1 : NZ / 4;   // nonzero inputs per such row
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      double2 t[4] = {v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]};
+      dft4_nz<N2>(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[n1 + 4 * k2] = (n1 * k2) ? c_mul(w16(n1 * k2), t[k2]) : t[k2];
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      double2 t[4] = {v[4 * k2], v[4 * k2 + 1], v[4 * k2 + 2], v[4 * k2 + 3]};
+      dft4_nz<N1>(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) v[4 * k2 + k1] = t[k1];
     }
   }
   // natural order

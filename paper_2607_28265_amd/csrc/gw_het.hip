@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "gw_ctx.h"
+#include "gw_tgrid.h"
 
 // Device-resident arguments of the work-list kernels; a one-thread kernel
 // writes them before each launch so that a captured graph can be replayed
@@ -64,12 +65,13 @@ struct gw_het_state {
   int64_t n_rows_last = 0;       // rows of the batch being enqueued (selects the distance form)
   // time marginal: row-independent tables for the current grid (built on
   // first use): per block b < n_blk the edges [tm_bs[b], tm_bs[b + 1]) in it,
-  // per edge the powers s_e^m of its offset in the block (m < 16) and
-  // sigma_e^m of its bin width about the widths' centre (m < tm_mh), and the
-  // edge chunks of the moment kernel (whole blocks tm_cb[c] .. tm_cb[c + 1])
-  double* tm_tab = nullptr;      // [n_edges][16 + tm_mh]
+  // per edge the Chebyshev values T_m(s_e) of its offset in the block
+  // (m < tm_K) and the powers sigma_e^m of its bin width about the widths'
+  // centre (m < tm_mh), and the edge chunks of the moment kernel (whole
+  // blocks tm_cb[c] .. tm_cb[c + 1])
+  double* tm_tab = nullptr;      // [n_edges][tm_K + tm_mh]
   int32_t* tm_idx = nullptr;     // [n_blk + 1] block starts, then [tm_nch + 1] chunk block starts
-  int tm_blk = 0, tm_nblk = 0, tm_mh = 0, tm_nch = 0, tm_nch_req = -1;
+  int tm_blk = 0, tm_nblk = 0, tm_mh = 0, tm_nch = 0, tm_nch_req = -1, tm_K = 0;
   double tm_hw = 0.0;            // half-range of the bin widths (fine bins)
   double tm_umax = -1.0;         // the window's largest |u| the norm series was sized for
   int64_t tm_c2 = 0;             // smallest + largest bin width (fine bins)
@@ -472,7 +474,8 @@ __device__ inline void het_finish_row(const HetArgs* __restrict__ ab, int64_t ro
 // Large batches: one lane per row (coalesced over rows), the edge-chunk
 // partials summed in chunk order.
 __global__ void __launch_bounds__(256) k_het_combine(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
-                                                     int nd, int n_ech, int marg, HetConst hc, LogI0Consts C) {
+                                                     int nd, int n_ech, int marg, HetConst hc, const LogI0Consts* __restrict__ Cp) {
+  const LogI0Consts& C = *Cp;
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
@@ -503,7 +506,8 @@ __global__ void __launch_bounds__(256) k_het_combine(const HetArgs* __restrict__
 // loads of a row are issued together instead of one chain per thread.
 __global__ void __launch_bounds__(256) k_het_combine_w(const HetArgs* __restrict__ ab,
                                                        const int64_t* __restrict__ pre, int nd, int n_ech, int marg,
-                                                       HetConst hc, LogI0Consts C) {
+                                                       HetConst hc, const LogI0Consts* __restrict__ Cp) {
+  const LogI0Consts& C = *Cp;
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
@@ -543,7 +547,8 @@ __global__ void __launch_bounds__(256) k_het_combine_w(const HetArgs* __restrict
 template <int PREC>
 __global__ void __launch_bounds__(256) k_het_dist_w(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
                                                     const double* __restrict__ dtab, int n_dist, double dd,
-                                                    LogI0Consts C) {
+                                                    const LogI0Consts* __restrict__ Cp) {
+  const LogI0Consts& C = *Cp;
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
@@ -577,7 +582,8 @@ template <int PREC>
 __global__ void __launch_bounds__(64 * kHetDistWaves) k_het_dist(const HetArgs* __restrict__ ab,
                                                                  const int64_t* __restrict__ pre,
                                                                  const double* __restrict__ dtab, int n_dist,
-                                                                 double dd, LogI0Consts C) {
+                                                                 double dd, const LogI0Consts* __restrict__ Cp) {
+  const LogI0Consts& C = *Cp;
   __shared__ double red[kHetDistWaves * 64];
   const int lane = threadIdx.x & 63;
   const int nw = blockDim.x >> 6;
@@ -698,7 +704,7 @@ static gw_status launch_het_nd(gw_ctx* ctx, int marg, int prec, int n_ech, hipSt
   // 64 waves per CU (several rounds of the resident 20); small batches have
   // few items, and an idle grid still costs dispatch time
   if (grid <= 0) grid = (h->n_rows_last < kDistRowsPerLane ? 1024 : kHetWaves) / h->wpb;
-  const int slot = prof_begin(ctx, st);
+  const int slot = prof_begin(ctx, st, 1);
   if (prec == GW_PREC_FP64)
     hipLaunchKernelGGL((k_het<ND, 0>), dim3(grid), dim3(tpb), 0, st, h->args, h->tile_pre, h->rec, h->n_bins, n_ech,
                        T);
@@ -734,8 +740,7 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
     hc.hh0[i] = h->hh0[i];
   }
   hc.dd = ctx->dd;
-  LogI0Consts C = make_log_i0_consts();
-  C.r1max = ctx->dist_r1max;
+  const LogI0Consts* C = ctx->i0c;  // device copy, r1max from the distance grid
   if (h->n_rows_last < kDistRowsPerLane && n_ech <= 64)
     hipLaunchKernelGGL(k_het_combine_w, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->n_det, n_ech,
                        marg, hc, C);
@@ -747,16 +752,16 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
   const bool sliced = h->n_rows_last >= kDistRowsPerLane;
   if (sliced && prec == GW_PREC_MIXED)
     hipLaunchKernelGGL(k_het_dist<1>, dim3(256 * 8), dim3(64 * kHetDistWaves), 0, st, h->args, h->tile_pre,
-                       ctx->dist_tab, ctx->n_dist, ctx->dd, C);
+                       ctx->dist_tab, ctx->n_dist, ctx->dd, ctx->i0c);
   else if (sliced)
     hipLaunchKernelGGL(k_het_dist<0>, dim3(256 * 8), dim3(64 * kHetDistWaves), 0, st, h->args, h->tile_pre,
-                       ctx->dist_tab, ctx->n_dist, ctx->dd, C);
+                       ctx->dist_tab, ctx->n_dist, ctx->dd, ctx->i0c);
   else if (prec == GW_PREC_MIXED)
     hipLaunchKernelGGL(k_het_dist_w<1>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
-                       ctx->n_dist, ctx->dd, C);
+                       ctx->n_dist, ctx->dd, ctx->i0c);
   else
     hipLaunchKernelGGL(k_het_dist_w<0>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
-                       ctx->n_dist, ctx->dd, C);
+                       ctx->n_dist, ctx->dd, ctx->i0c);
   return check_hip(hipGetLastError(), "heterodyne distance marginal launch");
 }
 
@@ -812,11 +817,11 @@ void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech)
 
 // Edge-weight moments of one (64-row tile, edge chunk): lane = row, the
 // chunk's edges in order (edge records and tables wave-uniform).  what = 0:
-// the 16 block moments of W for every block of the chunk into mom
-// [rows][16][n_blk]; what = 1: S_m, m0 <= m < m0 + 16 (m < mh), over the
+// the K block moments of W for every block of the chunk into mom
+// [rows][K][n_blk]; what = 1: S_m, m0 <= m < m0 + K (m < mh), over the
 // chunk's edges into hpart [chunk][rows][mh]; chunk 0 also writes the
 // constant norm part hhc [rows].
-template <int ND, int PREC>
+template <int ND, int PREC, int K>
 __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef, int64_t ld, int64_t n,
                                                  const double* __restrict__ rec, int n_bins,
                                                  const double* __restrict__ tab, int mh,
@@ -849,7 +854,7 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
   if (what == 0 && ch == 0 && p < n) hhc[p] = hconst;
   const int b_lo = cb[ch], b_hi = cb[ch + 1];
   const int e_lo = bs[b_lo], e_hi = bs[b_hi];
-  const int tw_ = kTMomOrders + mh;  // table row length
+  const int tw_ = K + mh;  // table row length
   if (what == 1 && e_lo > 0) {  // the norm term needs the previous edge's phasors
     const double* r = rec + (int64_t)(e_lo - 1) * RS;
     const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
@@ -859,9 +864,9 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
       het_phasor<PREC>(di, T, &pr[i], &pim[i]);
     }
   }
-  double ar_[kTMomOrders], ai_[kTMomOrders];
+  double ar_[K], ai_[K];
 #pragma unroll
-  for (int m = 0; m < kTMomOrders; ++m) ar_[m] = ai_[m] = 0.0;
+  for (int m = 0; m < K; ++m) ar_[m] = ai_[m] = 0.0;
   int e = e_lo;
   for (int b = b_lo; b < b_hi; ++b) {
     const int be = bs[b + 1];
@@ -891,9 +896,9 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
         pr[i] = gr;
         pim[i] = gi;
       }
-      const double* tp = tab + (int64_t)e * tw_ + (what == 0 ? 0 : kTMomOrders + m0);
+      const double* tp = tab + (int64_t)e * tw_ + (what == 0 ? 0 : K + m0);
 #pragma unroll
-      for (int m = 0; m < kTMomOrders; ++m) {
+      for (int m = 0; m < K; ++m) {
         if (what == 1 && m0 + m >= mh) break;
         ar_[m] = fma(tp[m], wr, ar_[m]);
         ai_[m] = fma(tp[m], wi, ai_[m]);
@@ -901,36 +906,45 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
     }
     if (what == 0) {
       if (p < n) {
-        double2* out = mom + p * kTMomOrders * n_blk + b;
+        double2* out = mom + p * K * n_blk + b;
 #pragma unroll
-        for (int m = 0; m < kTMomOrders; ++m) out[(int64_t)m * n_blk] = make_double2(ar_[m], ai_[m]);
+        for (int m = 0; m < K; ++m) out[(int64_t)m * n_blk] = make_double2(ar_[m], ai_[m]);
       }
 #pragma unroll
-      for (int m = 0; m < kTMomOrders; ++m) ar_[m] = ai_[m] = 0.0;
+      for (int m = 0; m < K; ++m) ar_[m] = ai_[m] = 0.0;
     }
   }
   if (what == 1 && p < n) {
     double2* out = hpart + ((int64_t)ch * n + p) * mh + m0;
 #pragma unroll
-    for (int m = 0; m < kTMomOrders; ++m)
+    for (int m = 0; m < K; ++m)
       if (m0 + m < mh) out[m] = make_double2(ar_[m], ai_[m]);
   }
 }
 
-template <int ND>
-static void launch_het_tmom_nd(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, const HetConst& hc,
-                               int what, int m0, double2* mom, double2* hpart, double* hhc, hipStream_t st) {
+template <int ND, int K>
+static void launch_het_tmom_k(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, const HetConst& hc,
+                              int what, int m0, double2* mom, double2* hpart, double* hhc, hipStream_t st) {
   const gw_het_state* h = ctx->het;
   const TrigConsts T = make_trig_consts();
   const dim3 grid((unsigned)((n + 63) / 64), (unsigned)h->tm_nch);
   const int32_t* bs = h->tm_idx;
   const int32_t* cb = h->tm_idx + h->tm_nblk + 1;
   if (prec == GW_PREC_FP64)
-    hipLaunchKernelGGL((k_het_tmom<ND, 0>), grid, dim3(64), 0, st, coef, ld, n, (const double*)h->rec, h->n_bins,
+    hipLaunchKernelGGL((k_het_tmom<ND, 0, K>), grid, dim3(64), 0, st, coef, ld, n, (const double*)h->rec, h->n_bins,
                        (const double*)h->tm_tab, h->tm_mh, bs, cb, h->tm_nblk, what, m0, hc, T, mom, hpart, hhc);
   else
-    hipLaunchKernelGGL((k_het_tmom<ND, 1>), grid, dim3(64), 0, st, coef, ld, n, (const double*)h->rec, h->n_bins,
+    hipLaunchKernelGGL((k_het_tmom<ND, 1, K>), grid, dim3(64), 0, st, coef, ld, n, (const double*)h->rec, h->n_bins,
                        (const double*)h->tm_tab, h->tm_mh, bs, cb, h->tm_nblk, what, m0, hc, T, mom, hpart, hhc);
+}
+
+template <int ND>
+static void launch_het_tmom_nd(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, const HetConst& hc,
+                               int what, int m0, double2* mom, double2* hpart, double* hhc, hipStream_t st) {
+  if (ctx->het->tm_K == 12)
+    launch_het_tmom_k<ND, 12>(ctx, coef, ld, n, prec, hc, what, m0, mom, hpart, hhc, st);
+  else
+    launch_het_tmom_k<ND, 16>(ctx, coef, ld, n, prec, hc, what, m0, mom, hpart, hhc, st);
 }
 
 // Edge chunks of the moment kernel: whole blocks, about n_edges / want edges
@@ -947,9 +961,10 @@ static int het_tm_chunks(const gw_ctx* ctx, int64_t n) {
 // Row-independent tables of the time marginal for the grid (blocks of blk
 // fine bins, n_blk of them, the window's largest |u| = umax fine-grid cycles)
 // and nch edge chunks.
-static gw_status het_tm_tables(gw_ctx* ctx, int blk, int n_blk, double umax, int nch) {
+static gw_status het_tm_tables(gw_ctx* ctx, int blk, int n_blk, double umax, int nch, int K) {
   gw_het_state* h = ctx->het;
-  if (h->tm_tab && h->tm_blk == blk && h->tm_nblk == n_blk && h->tm_nch_req == nch && h->tm_umax == umax)
+  if (h->tm_tab && h->tm_blk == blk && h->tm_nblk == n_blk && h->tm_nch_req == nch && h->tm_umax == umax &&
+      h->tm_K == K)
     return GW_OK;
   const int ne = h->n_edges;
   std::vector<int64_t> k(ne);
@@ -972,7 +987,7 @@ static gw_status het_tm_tables(gw_ctx* ctx, int blk, int n_blk, double umax, int
   if (term * exp(x) > 1e-13)
     return set_error(GW_ENOTSUP, "heterodyned time marginal: bin widths up to %lld fine bins over a +-%.3g s window "
                                  "need more than %d norm terms", (long long)dmax, ctx->tm_window, kTgHMax);
-  const int tw_ = kTMomOrders + mh;
+  const int tw_ = K + mh;
   std::vector<double> tab((size_t)ne * tw_, 0.0);
   std::vector<int32_t> bs(n_blk + 1, 0);
   const double cen = 0.5 * (blk - 1), hinv = 2.0 / blk;
@@ -981,15 +996,11 @@ static gw_status het_tm_tables(gw_ctx* ctx, int blk, int n_blk, double umax, int
     if (b < 0 || b >= n_blk) return set_error(GW_EINVAL, "heterodyned time marginal: edge outside the band");
     bs[b + 1] += 1;
     const double sv = ((double)(k[e] - b * blk) - cen) * hinv;
-    double tp = 1.0;
-    for (int m = 0; m < kTMomOrders; ++m) {
-      tab[(size_t)e * tw_ + m] = tp;
-      tp *= sv;
-    }
+    tgrid_basis_at(sv, K, tab.data() + (size_t)e * tw_);
     const double sg = e > 0 && hw > 0.0 ? ((double)(k[e] - k[e - 1]) - cw) / hw : 0.0;
-    tp = 1.0;
+    double tp = 1.0;
     for (int m = 0; m < mh; ++m) {
-      tab[(size_t)e * tw_ + kTMomOrders + m] = tp;
+      tab[(size_t)e * tw_ + K + m] = tp;
       tp *= sg;
     }
   }
@@ -1021,6 +1032,7 @@ static gw_status het_tm_tables(gw_ctx* ctx, int blk, int n_blk, double umax, int
   h->tm_hw = hw;
   h->tm_c2 = dmin + dmax;
   h->tm_umax = umax;
+  h->tm_K = K;
   return GW_OK;
 }
 
@@ -1034,23 +1046,24 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
   if (!h) return set_error(GW_ESTATE, "loglike_batch: heterodyne_setup has not been called");
   TimeGridShape g;
   gw_status s = time_grid_shape(ctx, &g);
-  if (s == GW_OK) s = tgrid_twiddles(ctx, g.L);
+  const int K = tgrid_orders(g.L, g.jmax);
+  if (s == GW_OK) s = tgrid_tables(ctx, g.L, g.jmax, K);
   const int nch = het_tm_chunks(ctx, n);
   const double umax = (double)g.jmax / ((double)g.N * (double)g.R);
-  if (s == GW_OK) s = het_tm_tables(ctx, g.blk, g.n_blk, umax, nch);
+  if (s == GW_OK) s = het_tm_tables(ctx, g.blk, g.n_blk, umax, nch, K);
   if (s != GW_OK) return s;
-  const int64_t chunk = tgrid_chunk_rows(n, g.n_blk);
+  const int64_t chunk = tgrid_chunk_rows(n, g.n_blk, K);
   const int mh = h->tm_mh;
   // workspace: coefficients for all rows; per row chunk the moments
   // [rows][16][n_blk], the norm moments [n_ch][rows][mh] and hhc [rows]
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
   if (s == GW_OK)
     s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap,
-                      chunk * kTMomOrders * g.n_blk * 2 + (int64_t)h->tm_nch * chunk * mh * 2 + chunk,
+                      chunk * K * g.n_blk * 2 + (int64_t)h->tm_nch * chunk * mh * 2 + chunk,
                       "time-marginal workspace");
   if (s != GW_OK) return s;
   double2* mom = (double2*)ctx->tm_mom;
-  double2* hpart = mom + chunk * kTMomOrders * g.n_blk;
+  double2* hpart = mom + chunk * K * g.n_blk;
   double* hhc = (double*)(hpart + (int64_t)h->tm_nch * chunk * mh);
   s = launch_prologue(ctx, theta, n, GW_MARG_PHASE_TIME, ctx->coef, n, st);
   if (s != GW_OK) return s;
@@ -1064,9 +1077,9 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
   const int nt = 2 * g.jmax + 1;
   for (int64_t r0 = 0; r0 < n && s == GW_OK; r0 += chunk) {
     const int64_t cn = n - r0 < chunk ? n - r0 : chunk;
-    const int prof = prof_begin(ctx, st);
+    const int prof = prof_begin(ctx, st, 1);
     for (int what = 0; what < 2; ++what)
-      for (int m0 = 0; m0 < (what == 0 ? 1 : mh); m0 += kTMomOrders) {
+      for (int m0 = 0; m0 < (what == 0 ? 1 : mh); m0 += K) {
         switch (ctx->n_det) {
           case 1: launch_het_tmom_nd<1>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, hpart, hhc, st); break;
           case 2: launch_het_tmom_nd<2>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, hpart, hhc, st); break;
@@ -1084,7 +1097,7 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
     a.n_blk = g.n_blk;
     a.L = g.L;
     a.jmax = g.jmax;
-    a.tw = ctx->tm_tw;
+    a.K = K;
     a.coef = ctx->coef + r0;
     a.ld = n;
     a.logl = logl + r0;
@@ -1099,7 +1112,9 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
     a.zout = zout ? zout + r0 * nt * 3 : nullptr;
     a.f0_num = (double)(2 * ctx->geom.k0 + g.blk - 1);
     a.f0_den = (double)(2 * g.N) * (double)g.R;
+    const int gslot = prof_begin(ctx, st, 2);
     s = launch_tgrid(ctx, a, st);
+    prof_end(ctx, gslot, st);
   }
   return s;
 }

@@ -219,104 +219,129 @@ __global__ void k_to_bf16(const float* __restrict__ p, uint16_t* __restrict__ q)
 }
 
 // ---------------------------------------------------------------------------
-// BF16 MFMA inference: one workgroup (4 waves) per 64 rows.
+// BF16 MFMA inference: one workgroup (8 waves) per 128 rows.  Each layer is
+// computed transposed, out^T [feature][row] = W [feature][k] act^T [k][row],
+// with the 16x16x32 BF16 matrix instruction (FP32 accumulation): operand A is
+// a 16-feature x 32-k tile of the weights (read from memory, one k-step
+// ahead), operand B a 32-k x 16-row tile of the activations (LDS, rows of
+// kActStride bf16 so that the 16 rows of a read fall in distinct banks); a
+// lane's 4 results are 4 consecutive features of one row, stored as one
+// 8-byte write.  Wave w owns features 64 (w mod 4) .. + 63 of rows
+// 64 (w / 4) .. + 63: 4 feature tiles x 4 row tiles.
 
-typedef short s4v __attribute__((ext_vector_type(4)));
+typedef short s8v __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) k_mlp_infer(const double* __restrict__ x, int64_t n, MlpScale sc,
+constexpr int kInferRows = 128;
+constexpr int kActStride = kH + 8;  // bf16 per activation row in LDS
+
+__device__ inline f4v mfma_bf16_16x16x32(s8v a, s8v b, f4v c) {
+  typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8v, a), __builtin_bit_cast(b8v, b), c, 0, 0,
+                                                 0);
+}
+
+__global__ void __launch_bounds__(512) k_mlp_infer(const double* __restrict__ x, int64_t n, MlpScale sc,
                                                    const uint16_t* __restrict__ q, const float* __restrict__ p,
                                                    double* __restrict__ out) {
-  __shared__ uint16_t act[64 * kH];  // [row][k], row stride kH
-  __shared__ float red[4][64];
+  __shared__ __attribute__((aligned(16))) uint16_t act[kInferRows * kActStride];  // [row][k]
+  __shared__ float red[4][kInferRows];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int fw = wave & 3, rw = wave >> 2;  // feature block, row half
+  const int64_t r0 = (int64_t)blockIdx.x * kInferRows;
   // standardised input, K padded to 32
-  for (int e = threadIdx.x; e < 64 * kInPad; e += 256) {
+  for (int e = threadIdx.x; e < kInferRows * kInPad; e += 512) {
     const int row = e / kInPad, k = e % kInPad;
     float v = 0.0f;
     if (k < kIn && r0 + row < n) v = ((float)x[(r0 + row) * kIn + k] - sc.xm[k]) * sc.xs_inv[k];
-    act[row * kH + k] = to_bf16(v);
+    act[row * kActStride + k] = to_bf16(v);
   }
   __syncthreads();
-  const int lr = lane & 15;        // row within a 16-row tile (A) / column (B, D)
-  const int lk = (lane >> 4) * 4;  // K offset of this lane's 4 values
-  f4v acc[4][4];
+  const int l16 = lane & 15;        // feature (A) / row (B) within a tile
+  const int lk = (lane >> 4) * 8;   // this lane's 8 values of the 32-k step
+  const int lf = (lane >> 4) * 4;   // first of this lane's 4 output features in a tile
+  f4v acc[4][4];                    // [feature tile][row tile]
   for (int layer = 0; layer < 3; ++layer) {
     const int K = layer == 0 ? kInPad : kH;
-    const uint16_t* W = q + (layer == 0 ? QW1 : (layer == 1 ? QW2 : QW3));
-    const float* bias = p + (layer == 0 ? OB1 : (layer == 1 ? OB2 : OB3));
+    const uint16_t* __restrict__ W = q + (layer == 0 ? QW1 : (layer == 1 ? QW2 : QW3));
+    const float* __restrict__ bias = p + (layer == 0 ? OB1 : (layer == 1 ? OB2 : OB3));
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int ft = 0; ft < 4; ++ft)
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-      s4v a[4], b[4];
+      for (int rt = 0; rt < 4; ++rt) acc[ft][rt] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    const uint16_t* __restrict__ wrow = W + (int64_t)(fw * 64 + l16) * K + lk;
+    s8v a_cur[4], a_nxt[4];
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt) a[rt] = *(const s4v*)&act[(rt * 16 + lr) * kH + k0 + lk];
+    for (int ft = 0; ft < 4; ++ft) a_cur[ft] = *(const s8v*)(wrow + (int64_t)ft * 16 * K);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      if (k0 + 32 < K) {
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) {
-        const int col = wave * 64 + ct * 16 + lr;
-        b[ct] = *(const s4v*)&W[(int64_t)col * K + k0 + lk];
+        for (int ft = 0; ft < 4; ++ft) a_nxt[ft] = *(const s8v*)(wrow + (int64_t)ft * 16 * K + k0 + 32);
       }
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
+      for (int rt = 0; rt < 4; ++rt) {
+        const s8v b = *(const s8v*)&act[(rw * 64 + rt * 16 + l16) * kActStride + k0 + lk];
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[rt], b[ct], acc[rt][ct], 0, 0, 0);
+        for (int ft = 0; ft < 4; ++ft) acc[ft][rt] = mfma_bf16_16x16x32(a_cur[ft], b, acc[ft][rt]);
+      }
+      if (k0 + 32 < K) {
+#pragma unroll
+        for (int ft = 0; ft < 4; ++ft) a_cur[ft] = a_nxt[ft];
+      }
     }
-    // bias + GELU in FP32; D[row = 4 (lane / 16) + j][col = lane % 16] per tile
+    // bias + GELU in FP32; D[feature = lf + j][row = l16] per tile
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      const float bc = bias[wave * 64 + ct * 16 + lr];
+    for (int ft = 0; ft < 4; ++ft) {
+      const float4 bc = *(const float4*)&bias[fw * 64 + ft * 16 + lf];
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[rt][ct][j] = gelu_f(acc[rt][ct][j] + bc);
+      for (int rt = 0; rt < 4; ++rt) {
+        acc[ft][rt][0] = gelu_f(acc[ft][rt][0] + bc.x);
+        acc[ft][rt][1] = gelu_f(acc[ft][rt][1] + bc.y);
+        acc[ft][rt][2] = gelu_f(acc[ft][rt][2] + bc.z);
+        acc[ft][rt][3] = gelu_f(acc[ft][rt][3] + bc.w);
+      }
     }
     __syncthreads();  // every wave has read this layer's input
     if (layer < 2) {
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
+      for (int ft = 0; ft < 4; ++ft)
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int row = rt * 16 + lk + j;
-            const int col = wave * 64 + ct * 16 + lr;
-            act[row * kH + col] = to_bf16(acc[rt][ct][j]);
-          }
+        for (int rt = 0; rt < 4; ++rt) {
+          const uint32_t lo = (uint32_t)to_bf16(acc[ft][rt][0]) | ((uint32_t)to_bf16(acc[ft][rt][1]) << 16);
+          const uint32_t hi = (uint32_t)to_bf16(acc[ft][rt][2]) | ((uint32_t)to_bf16(acc[ft][rt][3]) << 16);
+          *(uint2*)&act[(rw * 64 + rt * 16 + l16) * kActStride + fw * 64 + ft * 16 + lf] = make_uint2(lo, hi);
+        }
       __syncthreads();
     }
   }
-  // output layer 256 -> 1 in FP32: per-lane partial over its columns, then
-  // a shuffle tree over the 16 lanes that share rows, then the 4 waves in order
-  float w4[4];
+  // output layer 256 -> 1 in FP32: per-lane partial over its 16 features,
+  // then the 4 lane groups that share a row, then the 4 feature blocks in order
+  float w4[4][4];
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) w4[ct] = p[OW4 + wave * 64 + ct * 16 + lr];
-  float s[4][4];
+  for (int ft = 0; ft < 4; ++ft) {
+    const float4 w = *(const float4*)&p[OW4 + fw * 64 + ft * 16 + lf];
+    w4[ft][0] = w.x;
+    w4[ft][1] = w.y;
+    w4[ft][2] = w.z;
+    w4[ft][3] = w.w;
+  }
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+  for (int rt = 0; rt < 4; ++rt) {
+    float v = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      float v = 0.0f;
+    for (int ft = 0; ft < 4; ++ft)
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) v = fmaf(acc[rt][ct][j], w4[ct], v);
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
-      s[rt][j] = v;
-    }
-  if (lr == 0) {
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) red[wave][rt * 16 + lk + j] = s[rt][j];
+      for (int j = 0; j < 4; ++j) v = fmaf(acc[ft][rt][j], w4[ft][j], v);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (lane < 16) red[fw][rw * 64 + rt * 16 + l16] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 64 && r0 + threadIdx.x < n) {
-    const float y = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x])) + p[OB4];
-    out[r0 + threadIdx.x] = sc.ym + sc.ys * (double)y;
+  if (threadIdx.x < kInferRows && r0 + threadIdx.x < n) {
+    const int t = threadIdx.x;
+    const float y = ((red[0][t] + red[1][t]) + (red[2][t] + red[3][t])) + p[OB4];
+    out[r0 + t] = sc.ym + sc.ys * (double)y;
   }
 }
 
@@ -585,7 +610,8 @@ gw_status mlp_prepare(gw_mlp* m, hipStream_t st) {
 
 gw_status mlp_infer(gw_mlp* m, const double* x, int64_t n, double* out, hipStream_t st) {
   if (n == 0) return GW_OK;
-  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, x, n, m->sc, m->q, m->p, out);
+  hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + kInferRows - 1) / kInferRows)), dim3(512), 0, st, x, n, m->sc,
+                     m->q, m->p, out);
   return check_hip(hipGetLastError(), "mlp inference launch");
 }
 
@@ -745,7 +771,8 @@ gw_status gw_mlp_forward(gw_mlp* m, const double* x, int64_t n, double* out, int
       if (s != GW_OK) return s;
       m->q_dirty = false;
     }
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, x, n, m->sc, m->q, m->p, out);
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + kInferRows - 1) / kInferRows)), dim3(512), 0, st, x, n, m->sc,
+                     m->q, m->p, out);
     return check_hip(hipGetLastError(), "mlp inference launch");
   }
   const int64_t chunk = 1 << 16;

@@ -88,9 +88,10 @@ __global__ void __launch_bounds__(256) k_recon_stage(const double* __restrict__ 
 // d_L is the sample's own (phase marginal); NaN and -1 for unphysical rows.
 __global__ void __launch_bounds__(256) k_recon(const double* __restrict__ zc3, int64_t n,
                                                const double* __restrict__ theta, const double* __restrict__ tab,
-                                               int n_dist, int marg, int n_phase, LogI0Consts C,
+                                               int n_dist, int marg, int n_phase, const LogI0Consts* __restrict__ Cp,
                                                const double* __restrict__ uni, double* __restrict__ out,
                                                int32_t* __restrict__ idx) {
+  const LogI0Consts& C = *Cp;
   const int lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (p >= n) return;  // wave-uniform
@@ -178,9 +179,10 @@ gw_status stage_overlaps(gw_ctx* ctx, const double* theta, int64_t n, int like, 
 // zt [n][nt][3], then phi_c from exp(|Z(t_j)| cos(phi + arg Z(t_j))).
 // out[p] = (t_j, phi_c) with t_j = (j - J) delta; idx[p] = (j, m).
 __global__ void __launch_bounds__(256) k_recon_time(const double* __restrict__ zt, int64_t n, int nt, int J,
-                                                    double delta, int n_phase, LogI0Consts C,
+                                                    double delta, int n_phase, const LogI0Consts* __restrict__ Cp,
                                                     const double* __restrict__ uni, double* __restrict__ out,
                                                     int32_t* __restrict__ idx) {
+  const LogI0Consts& C = *Cp;
   const int lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (p >= n) return;  // wave-uniform
@@ -249,8 +251,7 @@ gw_status gw_reconstruct(gw_ctx* ctx, const double* theta, int64_t n, int32_t li
   hipStream_t st = (hipStream_t)stream;
   gw_status s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
   if (s != GW_OK) return s;
-  LogI0Consts C = make_log_i0_consts();
-  C.r1max = ctx->dist_r1max;
+  const LogI0Consts* C = ctx->i0c;  // device copy, r1max from the distance grid
   if (marg == GW_MARG_PHASE_TIME) {
     double delta;
     int32_t nt;

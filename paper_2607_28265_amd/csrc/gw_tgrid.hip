@@ -8,19 +8,30 @@
 // bins per block (P a power of two >= 2 J + 1) and s in [-1, 1], so that
 //   exp(-2 pi i f t_j) = exp(-2 pi i f_0 t_j) exp(-2 pi i b j / L) exp(-i phi_j s),
 // L = P R, phi_j = pi j / L, |phi_j| < pi / 2, f_0 the first block's centre.
-// With M_bm = sum_{k in block b} s_k^m y_k (y the per-bin overlap weights of
-// the full band, or the per-edge weights of the heterodyned bins),
-//   Z(t_j) = exp(-2 pi i f_0 t_j) sum_{m < 16} (-i phi_j)^m / m! F_m(j),
-//   F_m(j) = sum_b M_bm exp(-2 pi i b j / L),
-// one length-L DFT per moment (16 terms leave a first dropped term below
-// 1e-10 of the block's sum of |y|).  The leading factor has unit modulus.
+// The last factor is expanded in Chebyshev polynomials of s (the Jacobi-Anger
+// expansion), exp(-i phi s) = sum_n eps_n (-i)^n J_n(phi) T_n(s), eps_0 = 1 and
+// eps_n = 2 otherwise; with M_bn = sum_{k in block b} T_n(s_k) y_k (y the
+// per-bin overlap weights of the full band, or the per-edge weights of the
+// heterodyned bins),
+//   Z(t_j) = exp(-2 pi i f_0 t_j) sum_{n < K} eps_n (-i)^n J_n(phi_j) F_n(j),
+//   F_n(j) = sum_b M_bn exp(-2 pi i b j / L),
+// one length-L DFT per order.  |T_n| <= 1 and |J_n(phi)| <= (phi / 2)^n / n!,
+// so the dropped orders stay below 2 (phi / 2)^K / K! of the sum of |y|; the
+// host takes K = 12 when that is below 2e-11 (|phi| up to 1.27, every grid of
+// the default window) and K = 16 otherwise (below 3e-15 at pi / 2).  The
+// leading factor has unit modulus.
 //
-// k_tgrid: one workgroup (256 lanes) per row.  For m = 15 .. 0 it runs a
-// Stockham FFT of length L <= 4096 in radix-16 (then 8, 4 or 2) passes: the
-// first pass reads the moments straight from memory (blocks beyond n_blk are
-// zero), the others go through one LDS buffer of L values, at most one
-// butterfly per lane and pass; each lane keeps the Horner recurrence over m
-// for its own grid points.  Then ln I0(|Z|) - <h|h>(t_j) / 2 and a fixed-order
+// k_tgrid: one workgroup (256 lanes) per row.  Per order, an in-place
+// decimation-in-frequency FFT of L = D1 D2 16 points (D1 = L / 256 for
+// L >= 256, else D1 = 1 and D2 = L / 16) in three passes: the first reads the
+// moments straight from memory (blocks at or beyond n_blk are zero; for
+// L = 4096 the radix-16 butterfly skips the inputs known to be zero), the
+// second works in LDS, and the third leaves each lane its 16 outputs in
+// registers, where they are weighted by the expansion coefficients (a table
+// per grid) and accumulated.  The LDS buffer stores element i at
+// i + floor(i / 16), which keeps all three access patterns free of bank
+// conflicts.  Twiddles are powers of one root of unity per lane, formed by
+// repeated products.  Then ln I0(|Z|) - <h|h>(t_j) / 2 and a fixed-order
 // log-sum-exp.  For the heterodyned bins the norm also depends on t_j:
 // <h|h>(t_j) = hhc + Re exp(-2 pi i c u_j) sum_{m < MH} (-i x_j)^m / m! S_m,
 // u_j = j / (N R) (fine-grid cycles), x_j = 2 pi hw u_j, with the bin widths
@@ -33,169 +44,212 @@
 
 #include "gw_ctx.h"
 #include "gw_fft.h"
+#include "gw_tgrid.h"
 
 namespace gw {
 
-constexpr int kTgMaxL = 4096;
-constexpr int kTgOwn = 16;  // grid points per lane: 256 * 16 >= 2 jmax + 1 for L <= 4096
+constexpr int kTgBuf = kTgMaxL + kTgMaxL / 16;  // padded LDS buffer
 
-// One Stockham pass of radix R over buf (L points, span ns), at most one
-// butterfly per lane; reads, waits, then writes in place.
-template <int R>
-__device__ inline void tg_pass(double2* __restrict__ buf, const double2* __restrict__ tw, int L, int ns, int tid) {
-  const int nb = L / R;
-  double2 v[R];
-  const bool on = tid < nb;
-  const int k = tid & (ns - 1);
-  if (on) {
-    const int stp = L / (ns * R);
+// w2 = exp(-2 pi i n3 / (16 D2)) for the lane's n3 = tid mod 16
+template <int D2>
+__device__ inline void tg_lds_pass2(double2* __restrict__ buf, int tid, int D1, int S1, double2 w2) {
+  if (tid < 16 * D1) {
+    const int n3 = tid & 15, k1 = tid >> 4;
+    // element n3 + 16 q + S1 k1 sits at tg_pad(n3 + S1 k1) + 17 q (S1 is a
+    // multiple of 16)
+    const int pb = tg_pad(n3 + S1 * k1);
+    double2 v[D2];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      v[q] = buf[tid + q * nb];
-      if (q > 0 && ns > 1) v[q] = c_mul(v[q], tw[k * q * stp]);
-    }
-  }
-  __syncthreads();
-  if (on) {
-    Dft<R>::run_slots(v);
-    const int base = (tid - k) * R + k;
+    for (int q = 0; q < D2; ++q) v[q] = buf[pb + 17 * q];
+    tg_pass2<D2>(v, w2);
 #pragma unroll
-    for (int q = 0; q < R; ++q) buf[base + q * ns] = v[dft_slot<R>(q)];
-  }
-  __syncthreads();
-}
-
-// First pass (span 1): inputs straight from the row's moments of order m.
-template <int R>
-__device__ inline void tg_first(double2* __restrict__ buf, const double2* __restrict__ src, int n_blk, int L,
-                                int tid) {
-  const int nb = L / R;
-  if (tid < nb) {
-    double2 v[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int b = tid + q * nb;
-      v[q] = b < n_blk ? src[b] : make_double2(0.0, 0.0);
-    }
-    Dft<R>::run_slots(v);
-#pragma unroll
-    for (int q = 0; q < R; ++q) buf[tid * R + q] = v[dft_slot<R>(q)];
-  }
-  __syncthreads();
-}
-
-__device__ inline void tg_run_first(int R, double2* buf, const double2* src, int n_blk, int L, int tid) {
-  switch (R) {
-    case 16: tg_first<16>(buf, src, n_blk, L, tid); break;
-    case 8: tg_first<8>(buf, src, n_blk, L, tid); break;
-    case 4: tg_first<4>(buf, src, n_blk, L, tid); break;
-    default: tg_first<2>(buf, src, n_blk, L, tid); break;
+    for (int q = 0; q < D2; ++q) buf[pb + 17 * q] = v[q];
   }
 }
 
-__device__ inline void tg_run_pass(int R, double2* buf, const double2* tw, int L, int ns, int tid) {
-  switch (R) {
-    case 16: tg_pass<16>(buf, tw, L, ns, tid); break;
-    case 8: tg_pass<8>(buf, tw, L, ns, tid); break;
-    case 4: tg_pass<4>(buf, tw, L, ns, tid); break;
-    default: tg_pass<2>(buf, tw, L, ns, tid); break;
-  }
-}
+struct TgKernelArgs {
+  const double2* mom;  // [n][K][n_blk]
+  int64_t n;
+  int n_blk, L, D2, K, jmax;
+  const double* ccoef;  // [K][256][16]
+  const double* coef;
+  int64_t ld;
+  double dd;
+  const LogI0Consts* C;
+  double* logl;
+  const double* hhc;
+  const double2* hpart;
+  int n_hch, mh;
+  double hw_step;
+  int64_t c2, cden;
+  double* zout;
+  double f0_num, f0_den;
+};
 
-// mom: [n][16][n_blk] complex (row p, order m, block b at ((p 16 + m) n_blk + b)).
-// HET = 0: <h|h> = coef[C_HH]; HET = 1: <h|h>(t_j) as above from hhc [n], the
-// H moments hpart [n_hch][n][mh] complex, hw_step = 2 pi hw / (N R), c2 = 2 c
-// and cden = 2 N R (exp(-2 pi i c u_j) = exp(-2 pi i (c2 j mod cden) / cden)).
-// zout (else NULL): [n][2 jmax + 1][3] = (Re Z(t_j), Im Z(t_j), <h|h>(t_j)),
-// Re NaN for unphysical rows, with f_0 t_j = j f0_num / f0_den cycles.
-template <int HET>
-__global__ void __launch_bounds__(256, 2) k_tgrid(const double2* __restrict__ mom, int64_t n, int n_blk, int L,
-                                               int4 radix, int n_pass, const double2* __restrict__ tw, int jmax,
-                                               double phi_step, const double* __restrict__ coef, int64_t ld, double dd,
-                                               const LogI0Consts* __restrict__ Cp, double* __restrict__ logl,
-                                               const double* __restrict__ hhc, const double2* __restrict__ hpart,
-                                               int n_hch, int mh, double hw_step, int64_t c2, int64_t cden,
-                                               double* __restrict__ zout, double f0_num, double f0_den) {
-  __shared__ double2 buf[kTgMaxL];
+// mom: [n][K][n_blk] complex (row p, order m, block b at ((p K + m) n_blk + b)).
+// ccoef: eps_m J_m(phi_j) for lane l's output slot k3 at (m 256 + l) 16 + k3,
+// with the sign of (-i)^m folded in (+ for m mod 4 in {0, 1}, - otherwise)
+// and zero where |j| > jmax.  HET = 0: <h|h> = coef[C_HH]; HET = 1:
+// <h|h>(t_j) as above from hhc [n], the H moments hpart [n_hch][n][mh]
+// complex, hw_step = 2 pi hw / (N R), c2 = 2 c and cden = 2 N R
+// (exp(-2 pi i c u_j) = exp(-2 pi i (c2 j mod cden) / cden)).  zout (else
+// NULL): [n][2 jmax + 1][3] = (Re Z(t_j), Im Z(t_j), <h|h>(t_j)), Re NaN for
+// unphysical rows, with f_0 t_j = j f0_num / f0_den cycles.
+template <int HET, int D1, int NZ>
+__global__ void __launch_bounds__(256, 2) k_tgrid(TgKernelArgs a) {
+  __shared__ double2 buf[kTgBuf];
   __shared__ double2 sm[kTgHMax];
+  __shared__ double sinv[kTgHMax];  // 1 / (q + 1)
   __shared__ double red[256], red2[256];
   const int64_t p = blockIdx.x;
   const int tid = threadIdx.x;
-  const int nt = 2 * jmax + 1;
-  const int rad[4] = {radix.x, radix.y, radix.z, radix.w};
-  double ar[kTgOwn], ai[kTgOwn];
+  const int L = a.L, D2 = D1 > 1 ? 16 : a.D2, K = a.K;
+  const int S1 = L / D1;  // = 16 D2
+  const int nt = 2 * a.jmax + 1;
+  const double2* __restrict__ mrow = a.mom + p * (int64_t)K * a.n_blk;
+  const bool on1 = tid < S1, on3 = tid < L / 16;
+  double2 w1 = make_double2(1.0, 0.0), w2;
+  if (D1 > 1) {
+    double s, c;
+    sincospi(-2.0 * (double)tid / (double)L, &s, &c);
+    w1 = make_double2(c, s);
+  }
+  {
+    double s, c;
+    sincospi(-2.0 * (double)(tid & 15) / (double)(16 * D2), &s, &c);
+    w2 = make_double2(c, s);
+  }
+  double ar[16], ai[16];
 #pragma unroll
-  for (int o = 0; o < kTgOwn; ++o) ar[o] = ai[o] = 0.0;
-  for (int m = kTMomOrders - 1; m >= 0; --m) {
-    __syncthreads();  // the previous order's grid reads are done
-    tg_run_first(rad[0], buf, mom + (p * kTMomOrders + m) * n_blk, n_blk, L, tid);
-    int ns = rad[0];
-    for (int s = 1; s < n_pass; ++s) {
-      tg_run_pass(rad[s], buf, tw, L, ns, tid);
-      ns *= rad[s];
+  for (int o = 0; o < 16; ++o) ar[o] = ai[o] = 0.0;
+  // the first pass's inputs of the current order (prefetched one order
+  // ahead when they are few)
+  constexpr bool kPrefetch = NZ <= 4;
+  double2 x[NZ];
+  auto load = [&](int m) {
+    const double2* __restrict__ src = mrow + (int64_t)m * a.n_blk;
+#pragma unroll
+    for (int q = 0; q < NZ; ++q) {
+      const int b = tid + S1 * q;
+      x[q] = (on1 && b < a.n_blk) ? src[b] : make_double2(0.0, 0.0);
     }
-    // H = F_m + (-i phi_j / (m + 1)) H at this lane's grid points
-    const double inv = phi_step / (double)(m + 1);
+  };
+  if (kPrefetch) load(0);
+  for (int m = 0; m < K; ++m) {
+    // The twiddle powers are formed afresh in every order: an empty asm
+    // statement marks the roots as changing here, so the compiler does not
+    // hoist 30 loop-invariant powers out of the loop (they would spill).
+    asm volatile("" : "+v"(w1.x), "+v"(w1.y), "+v"(w2.x), "+v"(w2.y));
+    if (!kPrefetch) load(m);
+    double2 v[D1];
 #pragma unroll
-    for (int o = 0; o < kTgOwn; ++o) {
-      const int jj = tid + 256 * o;
-      if (jj < nt) {
-        const int j = jj - jmax;
-        const double2 f = buf[j < 0 ? j + L : j];
-        const double qq = inv * (double)j;
-        const double nr = fma(qq, ai[o], f.x), ni = fma(-qq, ar[o], f.y);
-        ar[o] = nr;
-        ai[o] = ni;
+    for (int q = 0; q < D1; ++q) v[q] = q < NZ ? x[q] : make_double2(0.0, 0.0);
+    if (kPrefetch && m + 1 < K) load(m + 1);
+    tg_pass1<D1, NZ>(v, w1);
+    __syncthreads();  // the previous order's last-pass reads are done
+    if (on1) {
+      const int pb = tg_pad(tid);
+#pragma unroll
+      for (int k = 0; k < D1; ++k) buf[pb + 17 * (S1 / 16) * k] = v[k];
+    }
+    __syncthreads();
+    if constexpr (D1 > 1) {
+      tg_lds_pass2<16>(buf, tid, D1, S1, w2);  // L >= 512: D2 = 16
+    } else {
+      switch (D2) {
+        case 16: tg_lds_pass2<16>(buf, tid, D1, S1, w2); break;
+        case 8: tg_lds_pass2<8>(buf, tid, D1, S1, w2); break;
+        case 4: tg_lds_pass2<4>(buf, tid, D1, S1, w2); break;
+        case 2: tg_lds_pass2<2>(buf, tid, D1, S1, w2); break;
+        default: break;
+      }
+    }
+    __syncthreads();
+    if (on3) {
+      double2 f[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) f[q] = buf[17 * tid + q];
+      Dft<16>::run_slots(f);
+      const double* __restrict__ cm = a.ccoef + ((int64_t)m * 256 + tid) * 16;
+      if ((m & 1) == 0) {
+#pragma unroll
+        for (int k3 = 0; k3 < 16; ++k3) {
+          const double t = cm[k3];
+          const double2 z = f[dft_slot<16>(k3)];
+          ar[k3] = fma(t, z.x, ar[k3]);
+          ai[k3] = fma(t, z.y, ai[k3]);
+        }
+      } else {
+#pragma unroll
+        for (int k3 = 0; k3 < 16; ++k3) {
+          const double t = cm[k3];
+          const double2 z = f[dft_slot<16>(k3)];
+          ar[k3] = fma(t, z.y, ar[k3]);
+          ai[k3] = fma(-t, z.x, ai[k3]);
+        }
       }
     }
   }
-  const bool valid = coef[C_VALID * ld + p] != 0.0;
-  const LogI0Consts& C = *Cp;
-  // the finished Z(t_j) go to the buffer (nt <= L points), read back below
-  // in a plain loop
+  const bool valid = a.coef[C_VALID * a.ld + p] != 0.0;
+  const LogI0Consts& C = *a.C;
+  // the finished Z(t_j) go to the buffer in grid order (nt <= L points), read
+  // back below in a plain loop
   __syncthreads();
+  if (on3) {
 #pragma unroll
-  for (int o = 0; o < kTgOwn; ++o) {
-    const int jj = tid + 256 * o;
-    if (jj < nt) buf[jj] = make_double2(ar[o], ai[o]);
+    for (int k3 = 0; k3 < 16; ++k3) {
+      const int X = tg_owned(L, D1, D2, tid, k3);
+      const int j = X <= a.jmax ? X : X - L;
+      if (j >= -a.jmax && j <= a.jmax) buf[j + a.jmax] = make_double2(ar[k3], ai[k3]);
+    }
   }
   double hh = 0.0;
   if (HET) {
-    hh = hhc[p];
+    hh = a.hhc[p];
     // this row's H moments, summed over the edge chunks in order
-    for (int q = tid; q < mh; q += 256) {
-      double2 a = make_double2(0.0, 0.0);
-      for (int c = 0; c < n_hch; ++c) a = c_add(a, hpart[((int64_t)c * n + p) * mh + q]);
-      sm[q] = a;
+    for (int q = tid; q < a.mh; q += 256) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int c = 0; c < a.n_hch; ++c) s = c_add(s, a.hpart[((int64_t)c * a.n + p) * a.mh + q]);
+      sm[q] = s;
+      sinv[q] = 1.0 / (double)(q + 1);
     }
   } else {
-    hh = coef[C_HH * ld + p];
+    hh = a.coef[C_HH * a.ld + p];
+  }
+  // exp(-2 pi i c u_j) at this lane's first point, and its step over 256
+  // points (a rotation applied once per point below)
+  double cs = 1.0, sn = 0.0, rc = 1.0, rs = 0.0;
+  if (HET) {
+    const int64_t num = (a.c2 * (int64_t)(tid - a.jmax)) % a.cden;
+    sincospi(-2.0 * (double)num / (double)a.cden, &sn, &cs);
+    const int64_t stp = (a.c2 * 256) % a.cden;
+    sincospi(-2.0 * (double)stp / (double)a.cden, &rs, &rc);
   }
   __syncthreads();
   double run_mx = -INFINITY, run_acc = 0.0;
   for (int jj = tid; jj < nt; jj += 256) {
-    const int j = jj - jmax;
+    const int j = jj - a.jmax;
     const double2 z = buf[jj];
     double hj = hh;
     if (HET) {
-      const double x = hw_step * (double)j;
+      const double xq = a.hw_step * (double)j;
       double tr = 0.0, ti = 0.0;
-      for (int q = mh - 1; q >= 0; --q) {
-        const double qq = x / (double)(q + 1);
+      for (int q = a.mh - 1; q >= 0; --q) {
+        const double qq = xq * sinv[q];
         const double nr = fma(qq, ti, sm[q].x), ni = fma(-qq, tr, sm[q].y);
         tr = nr;
         ti = ni;
       }
-      const int64_t num = (c2 * (int64_t)j) % cden;
-      double sn, cs;
-      sincospi(-2.0 * (double)num / (double)cden, &sn, &cs);
       hj += cs * tr - sn * ti;
+      const double c2_ = cs * rc - sn * rs;
+      sn = cs * rs + sn * rc;
+      cs = c2_;
     }
-    if (zout) {
-      const double cyc = (double)j * f0_num / f0_den;
+    if (a.zout) {
+      const double cyc = (double)j * a.f0_num / a.f0_den;
       double sn, cs;
       sincospi(2.0 * (cyc - rint(cyc)), &sn, &cs);
-      double* zo = zout + (p * nt + jj) * 3;
+      double* zo = a.zout + (p * nt + jj) * 3;
       zo[0] = valid ? cs * z.x + sn * z.y : NAN;
       zo[1] = cs * z.y - sn * z.x;
       zo[2] = hj;
@@ -223,69 +277,104 @@ __global__ void __launch_bounds__(256, 2) k_tgrid(const double2* __restrict__ mo
     }
     __syncthreads();
   }
-  if (tid == 0) logl[p] = valid ? -0.5 * dd + red[0] + log(red2[0]) - log((double)nt) : -INFINITY;
+  if (tid == 0) a.logl[p] = valid ? -0.5 * a.dd + red[0] + log(red2[0]) - log((double)nt) : -INFINITY;
 }
 
-// Radix plan for a length L = 2^q <= 4096: radix-16 passes, then one of 8, 4
-// or 2 for the rest (at most one butterfly per lane of 256 in every pass).
-bool tgrid_plan(int L, int4* radix, int* n_pass) {
-  if (L < 2 || L > kTgMaxL || (L & (L - 1)) != 0) return false;
-  int r[4] = {0, 0, 0, 0};
-  int np = 0, rest = L;
-  while (rest >= 16) {
-    r[np++] = 16;
-    rest /= 16;
-  }
-  if (rest > 1) r[np++] = rest;
-  *radix = make_int4(r[0], r[1], r[2], r[3]);
-  *n_pass = np;
-  return true;
-}
-
-gw_status tgrid_twiddles(gw_ctx* ctx, int L) {
-  if (ctx->tm_tw && ctx->tm_L == L) return GW_OK;
-  std::vector<double> h(2 * (size_t)L);
-  for (int t = 0; t < L; ++t) {
-    const double a = -2.0 * kPi * (double)t / (double)L;
-    h[2 * t] = cos(a);
-    h[2 * t + 1] = sin(a);
-  }
-  if (ctx->tm_tw) (void)hipFree(ctx->tm_tw);
-  ctx->tm_tw = nullptr;
-  ctx->tm_L = 0;
-  gw_status s = check_hip(hipMalloc((void**)&ctx->tm_tw, h.size() * sizeof(double)), "time-grid twiddles");
-  if (s == GW_OK) s = check_hip(hipMemcpy(ctx->tm_tw, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice),
-                                "time-grid twiddles");
-  if (s == GW_OK) ctx->tm_L = L;
-  return s;
+gw_status tgrid_tables(gw_ctx* ctx, int L, int jmax, int K) {
+  if (ctx->tm_ccoef && ctx->tm_cc_L == L && ctx->tm_cc_jmax == jmax && ctx->tm_cc_K == K) return GW_OK;
+  int D1, D2;
+  if (!tgrid_plan(L, &D1, &D2)) return set_error(GW_ENOTSUP, "time marginal: transform length %d not supported", L);
+  std::vector<double> h;
+  tgrid_coefficients(L, jmax, K, &h);
+  if (ctx->tm_ccoef) (void)hipFree(ctx->tm_ccoef);
+  ctx->tm_ccoef = nullptr;
+  ctx->tm_cc_L = 0;
+  gw_status s = check_hip(hipMalloc((void**)&ctx->tm_ccoef, h.size() * sizeof(double)), "time-grid coefficients");
+  if (s == GW_OK) s = check_hip(hipMemcpy(ctx->tm_ccoef, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice),
+                                "time-grid coefficients");
+  if (s != GW_OK) return s;
+  ctx->tm_cc_L = L;
+  ctx->tm_cc_jmax = jmax;
+  ctx->tm_cc_K = K;
+  return GW_OK;
 }
 
 // Rows per chunk: the moments of a chunk take at most 1 GiB.
-int64_t tgrid_chunk_rows(int64_t n, int n_blk) {
-  const int64_t per_row = (int64_t)kTMomOrders * n_blk * 16;
+int64_t tgrid_chunk_rows(int64_t n, int n_blk, int K) {
+  const int64_t per_row = (int64_t)K * n_blk * 16;
   int64_t c = ((int64_t)1 << 30) / per_row;
   if (c < 64) c = 64;
   return n < c ? n : c;
 }
 
+template <int HET>
+static void launch_tgrid_form(const TgKernelArgs& k, int D1, int nz, unsigned n, hipStream_t st) {
+  const dim3 grid(n), blk(256);
+  switch (D1) {
+    case 16:
+      switch (nz) {
+        case 1: hipLaunchKernelGGL((k_tgrid<HET, 16, 1>), grid, blk, 0, st, k); break;
+        case 2: hipLaunchKernelGGL((k_tgrid<HET, 16, 2>), grid, blk, 0, st, k); break;
+        case 4: hipLaunchKernelGGL((k_tgrid<HET, 16, 4>), grid, blk, 0, st, k); break;
+        case 8: hipLaunchKernelGGL((k_tgrid<HET, 16, 8>), grid, blk, 0, st, k); break;
+        default: hipLaunchKernelGGL((k_tgrid<HET, 16, 16>), grid, blk, 0, st, k); break;
+      }
+      break;
+    case 8: hipLaunchKernelGGL((k_tgrid<HET, 8, 8>), grid, blk, 0, st, k); break;
+    case 4: hipLaunchKernelGGL((k_tgrid<HET, 4, 4>), grid, blk, 0, st, k); break;
+    case 2: hipLaunchKernelGGL((k_tgrid<HET, 2, 2>), grid, blk, 0, st, k); break;
+    default: hipLaunchKernelGGL((k_tgrid<HET, 1, 1>), grid, blk, 0, st, k); break;
+  }
+}
+
 gw_status launch_tgrid(const gw_ctx* ctx, const TGridArgs& a, hipStream_t st) {
-  int4 radix;
-  int n_pass;
-  if (!tgrid_plan(a.L, &radix, &n_pass) || 2 * a.jmax + 1 > 256 * kTgOwn)
+  int D1, D2;
+  if (!tgrid_plan(a.L, &D1, &D2) || 2 * a.jmax + 1 > a.L)
     return set_error(GW_ENOTSUP, "time marginal: a grid of %d points per %d-point transform is not supported",
                      2 * a.jmax + 1, a.L);
   if (a.het && a.mh > kTgHMax) return set_error(GW_ENOTSUP, "time marginal: %d norm moments exceed %d", a.mh, kTgHMax);
-  const double phi_step = kPi / (double)a.L;
-  const LogI0Consts* C = ctx->i0c;
-  if (a.het)
-    hipLaunchKernelGGL(k_tgrid<1>, dim3((unsigned)a.n), dim3(256), 0, st, (const double2*)a.mom, a.n, a.n_blk, a.L,
-                       radix, n_pass, (const double2*)a.tw, a.jmax, phi_step, a.coef, a.ld, ctx->dd, C, a.logl,
-                       a.hhc, (const double2*)a.hpart, a.n_hch, a.mh, a.hw_step, a.c2, a.cden, a.zout, a.f0_num,
-                       a.f0_den);
-  else
-    hipLaunchKernelGGL(k_tgrid<0>, dim3((unsigned)a.n), dim3(256), 0, st, (const double2*)a.mom, a.n, a.n_blk, a.L,
-                       radix, n_pass, (const double2*)a.tw, a.jmax, phi_step, a.coef, a.ld, ctx->dd, C, a.logl,
-                       nullptr, nullptr, 0, 0, 0.0, (int64_t)0, (int64_t)1, a.zout, a.f0_num, a.f0_den);
+  if (!ctx->tm_ccoef || ctx->tm_cc_L != a.L || ctx->tm_cc_jmax != a.jmax || ctx->tm_cc_K != a.K)
+    return set_error(GW_ESTATE, "time marginal: coefficient table not built for this grid");
+  if (a.n_blk > a.L) return set_error(GW_EINVAL, "time marginal: %d blocks exceed the transform length", a.n_blk);
+  if (a.n <= 0) return GW_OK;
+  // nonzero first-pass inputs per lane: blocks b = lane + (L / D1) q < n_blk
+  const int S1 = a.L / D1;
+  int nz = D1;
+  if (D1 == 16) {
+    const int need = (a.n_blk + S1 - 1) / S1;
+    nz = 1;
+    while (nz < need) nz <<= 1;
+  }
+  TgKernelArgs k{};
+  k.mom = (const double2*)a.mom;
+  k.n = a.n;
+  k.n_blk = a.n_blk;
+  k.L = a.L;
+  k.D2 = D2;
+  k.K = a.K;
+  k.jmax = a.jmax;
+  k.ccoef = ctx->tm_ccoef;
+  k.coef = a.coef;
+  k.ld = a.ld;
+  k.dd = ctx->dd;
+  k.C = ctx->i0c;
+  k.logl = a.logl;
+  k.zout = a.zout;
+  k.f0_num = a.f0_num;
+  k.f0_den = a.f0_den;
+  k.cden = 1;
+  if (a.het) {
+    k.hhc = a.hhc;
+    k.hpart = (const double2*)a.hpart;
+    k.n_hch = a.n_hch;
+    k.mh = a.mh;
+    k.hw_step = a.hw_step;
+    k.c2 = a.c2;
+    k.cden = a.cden;
+    launch_tgrid_form<1>(k, D1, nz, (unsigned)a.n, st);
+  } else {
+    launch_tgrid_form<0>(k, D1, nz, (unsigned)a.n, st);
+  }
   return check_hip(hipGetLastError(), "time-grid launch");
 }
 

@@ -13,23 +13,25 @@
 //
 // Evaluation.  P is the smallest power of two >= 2J + 1 and the band is cut
 // into blocks of B = N / P bins (512 at 128 s); the grid sum then goes through
-// the block moments M_bm = sum_{k in block b} s_k^m y_k of the projected data
-// and one FFT of length P R per moment order (gw_tgrid.hip):
-//   k_tmom:  per (proposal, block), the 16 moments (lane = proposal, the
+// the block moments M_bm = sum_{k in block b} T_m(s_k) y_k of the projected
+// data (T_m the Chebyshev polynomials, s_k the bin's offset in its block
+// scaled to [-1, 1]) and one FFT of length P R per order (gw_tgrid.hip):
+//   k_tmom:  per (proposal, block), the K moments (lane = proposal, the
 //            workgroup's waves walk the same block, wave-uniform bin records
 //            as in the full-band reduction);
-//   k_tgrid: one workgroup per proposal, FFTs, Horner over the orders,
-//            ln I0(|Z|) and a fixed-order log-sum-exp.
+//   k_tgrid: one workgroup per proposal, FFTs weighted by the expansion
+//            coefficients, ln I0(|Z|) and a fixed-order log-sum-exp.
 // Rows go through in chunks whose moments fit a bounded workspace.
 #include <math.h>
 
 #include <vector>
 
 #include "gw_ctx.h"
+#include "gw_phase.h"
+#include "gw_tgrid.h"
 
 namespace gw {
 
-constexpr int kTMom = kTMomOrders;
 constexpr int kTMaxP = 2048;
 
 template <int PREC>
@@ -46,11 +48,20 @@ __device__ inline void tm_phasor(double r, const TrigConsts& T, double* gr, doub
   }
 }
 
-template <int ND, int PREC>
+// Per (256-row tile, block): lane = row, the block's bins walked from the top
+// down (wave-uniform records).  FP64: the phase of every bin by its full
+// series.  Mixed: the phase by the cubic recurrence in the runs of the
+// full-band walk (gw_phase.h: a bin's phase depends on its run alone, so it
+// is the same here as in the distance-marginal reduction), FP32 hardware
+// sin/cos, FP64 sums.
+// e_i = (A P_i) exp(-2 pi i f_k dtau_i) starts at the block's top bin and
+// steps down by conj(rho_i), rho_i = exp(-2 pi i df dtau_i).
+template <int ND, int PREC, int K>
 __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, int64_t ld, int64_t n,
                                               const double* __restrict__ bins, int64_t k0, double df, int n_freq,
-                                              int blk, int n_blk, TrigConsts T, double pg_re, double pg_im,
-                                              const double* __restrict__ tpow, double* __restrict__ mom) {
+                                              int blk, int n_blk, TrigConsts T, PhaseRuns R, double pg_re,
+                                              double pg_im, const double* __restrict__ basis,
+                                              double* __restrict__ mom) {
   constexpr int RS = 4 + 2 * ND;
   const int tpb = blockDim.x;
   const int nptile = (int)((n + tpb - 1) / tpb);
@@ -71,11 +82,9 @@ __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, i
   c.a12 = coef[C_A12 * ld + pc];
   c.b5 = coef[C_B5 * ld + pc];
   c.b6 = coef[C_B6 * ld + pc];
-  // e_i = (A P_i) exp(-2 pi i f_k dtau_i), advanced bin by bin by the rotation
-  // rho_i = exp(-2 pi i df dtau_i) (detector 0: the constant A P_0)
-  double er[ND], ei[ND], rr[ND], ri[ND];
   const int kb = b * blk;
   const int ke = kb + blk < n_freq ? kb + blk : n_freq;
+  double er[ND], ei[ND], rr[ND], ri[ND];
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
     const double apr = coef[(C_APRE + i) * ld + pc], api = coef[(C_APIM + i) * ld + pc];
@@ -86,27 +95,24 @@ __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, i
     if (i > 0) {
       const double dt = coef[(C_DT1 + i - 1) * ld + pc];
       double s, co;
-      sincos_cycles((double)(k0 + kb) * df * dt, T, &s, &co);
+      sincos_cycles((double)(k0 + ke - 1) * df * dt, T, &s, &co);
       er[i] = apr * co + api * s;
       ei[i] = api * co - apr * s;
       sincos_cycles(df * dt, T, &s, &co);
       rr[i] = co;
-      ri[i] = -s;
+      ri[i] = s;  // conj(rho_i): the walk descends
     }
   }
-  double mr[kTMom], mi[kTMom];
+  double mr[K], mi[K];
 #pragma unroll
-  for (int m = 0; m < kTMom; ++m) mr[m] = mi[m] = 0.0;
-  for (int k = kb; k < ke; ++k) {
-    const double* __restrict__ rec = bins + (int64_t)k * RS;
-    const double r = phase_cycles(c, rec[0], rec[1], rec[2], rec[3]);
-    double gr, gi;
-    tm_phasor<PREC>(r, T, &gr, &gi);
-    // s = sum_i u_ik e_i
+  for (int m = 0; m < K; ++m) mr[m] = mi[m] = 0.0;
+  // one bin: y = g sum_i u_ik e_i into the moments, then e_i one bin down
+  auto visit = [&](int k, double gr, double gi) {
+    const double* __restrict__ u = bins + (int64_t)k * RS + 4;
     double sr = 0.0, si = 0.0;
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
-      const double ur = rec[4 + 2 * i], ui = rec[5 + 2 * i];
+      const double ur = u[2 * i], ui = u[2 * i + 1];
       sr = fma(ur, er[i], sr);
       sr = fma(-ui, ei[i], sr);
       si = fma(ur, ei[i], si);
@@ -118,19 +124,97 @@ __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, i
       }
     }
     const double yr = gr * sr - gi * si, yi = gr * si + gi * sr;
-    // the powers t^m of the bin's offset in the block come from a table
-    // (the same for every block and proposal: wave-uniform scalar loads)
-    const double* __restrict__ tq = tpow + (int64_t)(k - kb) * kTMom;
+    // T_m of the bin's offset in the block come from a table (the same for
+    // every block and proposal: wave-uniform scalar loads)
+    const double* __restrict__ tq = basis + (int64_t)(k - kb) * K;
 #pragma unroll
-    for (int m = 0; m < kTMom; ++m) {
+    for (int m = 0; m < K; ++m) {
       mr[m] = fma(tq[m], yr, mr[m]);
       mi[m] = fma(tq[m], yi, mi[m]);
     }
+  };
+  if constexpr (PREC == 0) {
+    for (int k = ke - 1; k >= kb; --k) {
+      const double* __restrict__ rec = bins + (int64_t)k * RS;
+      double gr, gi;
+      tm_phasor<0>(phase_cycles(c, rec[0], rec[1], rec[2], rec[3]), T, &gr, &gi);
+      visit(k, gr, gi);
+    }
+  } else {
+    const double lin_step = -c.a8 * df;  // linear phase change per bin of the descending walk
+    int k = ke - 1;
+    while (k >= kb) {
+      int L = 0, s = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int sj = k & ~(R.len[j] - 1);
+        if (L == 0 && sj >= R.k_min[j]) {
+          L = R.len[j];
+          s = sj;
+        }
+      }
+      if (L == 0) {  // below the lowest level: evaluated directly
+        const double* __restrict__ rc = bins + (int64_t)k * RS;
+        double gr, gi;
+        tm_phasor<1>(phase_nonlinear(c, rc[0], rc[1], rc[2], rc[3]) + fma(c.a8, rc[0] * rc[1], c.a5), T, &gr, &gi);
+        visit(k, gr, gi);
+        --k;
+        continue;
+      }
+      // the run's first (up to) four bins from its top, evaluated directly,
+      // build the backward differences; a block that starts inside a run
+      // (blocks shorter than the run, or the top block) visits only its own
+      // bins and advances the table through the others
+      const int top = s + L - 1 < n_freq - 1 ? s + L - 1 : n_freq - 1;
+      const int nd = top - s + 1 < 4 ? top - s + 1 : 4;
+      double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0, lin = 0.0;
+#pragma nounroll
+      for (int j = 0; j < 4; ++j) {
+        if (j < nd) {
+          const int kk = top - j;
+          const double* __restrict__ rc = bins + (int64_t)kk * RS;
+          const double nl = phase_nonlinear(c, rc[0], rc[1], rc[2], rc[3]);
+          lin = fma(c.a8, rc[0] * rc[1], c.a5);
+          const double d1 = nl - n0;
+          const double d2 = d1 - n1;
+          n3 = d2 - n2;
+          n2 = d2;
+          n1 = d1;
+          n0 = nl;
+          if (kk <= k && kk >= kb) {
+            double gr, gi;
+            tm_phasor<1>(nl + lin, T, &gr, &gi);
+            visit(kk, gr, gi);
+          }
+        }
+      }
+      const int lo = s > kb ? s : kb;
+      int kk = top - nd;
+      if (kk >= lo) {
+        double p0 = n0 + lin, p1 = n1 + lin_step, p2 = n2;
+        const double p3 = n3;
+        for (; kk > k; --kk) {  // above the walk's first bin: advance only
+          p2 += p3;
+          p1 += p2;
+          p0 += p1;
+        }
+#pragma unroll 2
+        for (; kk >= lo; --kk) {
+          p2 += p3;
+          p1 += p2;
+          p0 += p1;
+          double gr, gi;
+          tm_phasor<1>(p0, T, &gr, &gi);
+          visit(kk, gr, gi);
+        }
+      }
+      k = s - 1;
+    }
   }
   if (p >= n) return;
-  double* __restrict__ out = mom + (p * kTMom * n_blk + b) * 2;
+  double* __restrict__ out = mom + (p * K * n_blk + b) * 2;
 #pragma unroll
-  for (int m = 0; m < kTMom; ++m) {
+  for (int m = 0; m < K; ++m) {
     double vr = mr[m], vi = mi[m];
     if (PREC == 1) {  // remove the mean bias of the hardware phasor
       const double tr = vr * pg_re - vi * pg_im;
@@ -142,19 +226,29 @@ __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, i
   }
 }
 
-template <int ND>
-static void launch_tmom_nd(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, int blk, int n_blk,
-                           int tpb, double* mom, hipStream_t st) {
+template <int ND, int K>
+static void launch_tmom_k(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, int blk, int n_blk,
+                          int tpb, double* mom, hipStream_t st) {
   const int64_t nptile = (n + tpb - 1) / tpb;
   const TrigConsts T = make_trig_consts();
+  const PhaseRuns R = make_phase_runs(ctx->geom);
   if (prec == GW_PREC_FP64)
-    hipLaunchKernelGGL((k_tmom<ND, 0>), dim3((unsigned)(nptile * n_blk)), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
-                       ctx->geom.k0, ctx->geom.df, (int)ctx->geom.n_freq, blk, n_blk, T, 1.0, 0.0,
-                       (const double*)ctx->tm_tpow, mom);
+    hipLaunchKernelGGL((k_tmom<ND, 0, K>), dim3((unsigned)(nptile * n_blk)), dim3(tpb), 0, st, coef, ld, n,
+                       ctx->bins, ctx->geom.k0, ctx->geom.df, (int)ctx->geom.n_freq, blk, n_blk, T, R, 1.0, 0.0,
+                       (const double*)ctx->tm_basis, mom);
   else
-    hipLaunchKernelGGL((k_tmom<ND, 1>), dim3((unsigned)(nptile * n_blk)), dim3(tpb), 0, st, coef, ld, n, ctx->bins,
-                       ctx->geom.k0, ctx->geom.df, (int)ctx->geom.n_freq, blk, n_blk, T, ctx->pgain_re,
-                       ctx->pgain_im, (const double*)ctx->tm_tpow, mom);
+    hipLaunchKernelGGL((k_tmom<ND, 1, K>), dim3((unsigned)(nptile * n_blk)), dim3(tpb), 0, st, coef, ld, n,
+                       ctx->bins, ctx->geom.k0, ctx->geom.df, (int)ctx->geom.n_freq, blk, n_blk, T, R,
+                       ctx->pgain_re, ctx->pgain_im, (const double*)ctx->tm_basis, mom);
+}
+
+template <int ND>
+static void launch_tmom_nd(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, int K, int blk,
+                           int n_blk, int tpb, double* mom, hipStream_t st) {
+  if (K == 12)
+    launch_tmom_k<ND, 12>(ctx, coef, ld, n, prec, blk, n_blk, tpb, mom, st);
+  else
+    launch_tmom_k<ND, 16>(ctx, coef, ld, n, prec, blk, n_blk, tpb, mom, st);
 }
 
 // Grid of the time marginal for the context's window: N, J, P, B.
@@ -173,8 +267,9 @@ static gw_status time_grid(const gw_ctx* ctx, TimeGrid* g) {
   g->delta = 1.0 / ((double)N * ctx->geom.df);
   g->J = (int)floor(ctx->tm_window / g->delta + 1e-9);
   g->R = ctx->tm_R;
+  // P >= 2 J + 1, and at least 16 / R so that the transform has 16 points
   int P = 2;
-  while (P < 2 * g->J + 1) P <<= 1;
+  while (P < 2 * g->J + 1 || P * g->R < 16) P <<= 1;
   if (P > kTMaxP) return set_error(GW_ENOTSUP, "time marginal: window %.6g s needs more than %d grid points",
                                    ctx->tm_window, kTMaxP);
   if (N / P < 1) return set_error(GW_ENOTSUP, "time marginal: grid finer than the segment's sampling");
@@ -182,9 +277,8 @@ static gw_status time_grid(const gw_ctx* ctx, TimeGrid* g) {
   g->blk = (int)(N / P);
   g->n_blk = (int)((ctx->geom.n_freq + g->blk - 1) / g->blk);
   g->L = P * g->R;
-  int4 radix;
-  int n_pass;
-  if (!tgrid_plan(g->L, &radix, &n_pass))
+  int D1, D2;
+  if (!tgrid_plan(g->L, &D1, &D2))
     return set_error(GW_ENOTSUP, "time marginal: %d grid points per sampling interval over +-%.6g s need a "
                                  "%d-point transform (at most 4096)", g->R, ctx->tm_window, g->L);
   return GW_OK;
@@ -214,33 +308,25 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
                                hipStream_t st) {
   TimeGrid g;
   gw_status s = time_grid(ctx, &g);
-  if (s == GW_OK) s = tgrid_twiddles(ctx, g.L);
+  const int K = tgrid_orders(g.L, g.J * g.R);
+  if (s == GW_OK) s = tgrid_tables(ctx, g.L, g.J * g.R, K);
   if (s != GW_OK) return s;
-  if (ctx->tm_tpow_blk != g.blk) {
-    // powers t_j^m, t_j = (j - (B - 1) / 2) / (B / 2), m < 16, formed as the
-    // moment sums use them (repeated products from 1)
-    std::vector<double> h((size_t)g.blk * kTMom);
-    const double cen = 0.5 * (g.blk - 1), hinv = 2.0 / g.blk;
-    for (int j = 0; j < g.blk; ++j) {
-      const double t = ((double)j - cen) * hinv;
-      double tp = 1.0;
-      for (int m = 0; m < kTMom; ++m) {
-        h[(size_t)j * kTMom + m] = tp;
-        tp *= t;
-      }
-    }
-    if (ctx->tm_tpow) (void)hipFree(ctx->tm_tpow);
-    ctx->tm_tpow = nullptr;
-    ctx->tm_tpow_blk = 0;
-    s = check_hip(hipMalloc((void**)&ctx->tm_tpow, h.size() * sizeof(double)), "time-grid powers");
+  if (ctx->tm_basis_blk != g.blk || ctx->tm_basis_K != K) {
+    std::vector<double> h;
+    tgrid_basis(g.blk, K, &h);
+    if (ctx->tm_basis) (void)hipFree(ctx->tm_basis);
+    ctx->tm_basis = nullptr;
+    ctx->tm_basis_blk = 0;
+    s = check_hip(hipMalloc((void**)&ctx->tm_basis, h.size() * sizeof(double)), "time-grid basis");
     if (s == GW_OK)
-      s = check_hip(hipMemcpy(ctx->tm_tpow, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice), "powers");
+      s = check_hip(hipMemcpy(ctx->tm_basis, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice), "basis");
     if (s != GW_OK) return s;
-    ctx->tm_tpow_blk = g.blk;
+    ctx->tm_basis_blk = g.blk;
+    ctx->tm_basis_K = K;
   }
-  const int64_t chunk = tgrid_chunk_rows(n, g.n_blk);
+  const int64_t chunk = tgrid_chunk_rows(n, g.n_blk, K);
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
-  if (s == GW_OK) s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap, chunk * kTMom * g.n_blk * 2, "time moments");
+  if (s == GW_OK) s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap, chunk * K * g.n_blk * 2, "time moments");
   if (s != GW_OK) return s;
   s = launch_prologue(ctx, theta, n, GW_MARG_PHASE_TIME, ctx->coef, n, st);
   if (s != GW_OK) return s;
@@ -248,12 +334,12 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
   for (int64_t r0 = 0; r0 < n && s == GW_OK; r0 += chunk) {
     const int64_t cn = n - r0 < chunk ? n - r0 : chunk;
     const int tpb = cn >= 2048 ? 256 : 64;
-    const int slot = prof_begin(ctx, st);
+    const int slot = prof_begin(ctx, st, 1);
     switch (ctx->n_det) {
-      case 1: launch_tmom_nd<1>(ctx, ctx->coef + r0, n, cn, prec, g.blk, g.n_blk, tpb, ctx->tm_mom, st); break;
-      case 2: launch_tmom_nd<2>(ctx, ctx->coef + r0, n, cn, prec, g.blk, g.n_blk, tpb, ctx->tm_mom, st); break;
-      case 3: launch_tmom_nd<3>(ctx, ctx->coef + r0, n, cn, prec, g.blk, g.n_blk, tpb, ctx->tm_mom, st); break;
-      case 4: launch_tmom_nd<4>(ctx, ctx->coef + r0, n, cn, prec, g.blk, g.n_blk, tpb, ctx->tm_mom, st); break;
+      case 1: launch_tmom_nd<1>(ctx, ctx->coef + r0, n, cn, prec, K, g.blk, g.n_blk, tpb, ctx->tm_mom, st); break;
+      case 2: launch_tmom_nd<2>(ctx, ctx->coef + r0, n, cn, prec, K, g.blk, g.n_blk, tpb, ctx->tm_mom, st); break;
+      case 3: launch_tmom_nd<3>(ctx, ctx->coef + r0, n, cn, prec, K, g.blk, g.n_blk, tpb, ctx->tm_mom, st); break;
+      case 4: launch_tmom_nd<4>(ctx, ctx->coef + r0, n, cn, prec, K, g.blk, g.n_blk, tpb, ctx->tm_mom, st); break;
       default: return set_error(GW_ENOTSUP, "n_det %d not supported", ctx->n_det);
     }
     prof_end(ctx, slot, st);
@@ -265,14 +351,16 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
     a.n_blk = g.n_blk;
     a.L = g.L;
     a.jmax = g.J * g.R;
-    a.tw = ctx->tm_tw;
+    a.K = K;
     a.coef = ctx->coef + r0;
     a.ld = n;
     a.logl = logl + r0;
     a.zout = zout ? zout + r0 * nt * 3 : nullptr;
     a.f0_num = (double)(2 * ctx->geom.k0 + g.blk - 1);
     a.f0_den = (double)(2 * g.N) * (double)g.R;
+    const int gslot = prof_begin(ctx, st, 2);
     s = launch_tgrid(ctx, a, st);
+    prof_end(ctx, gslot, st);
   }
   return s;
 }
