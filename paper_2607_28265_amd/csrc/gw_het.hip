@@ -1048,11 +1048,12 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
   gw_status s = time_grid_shape(ctx, &g);
   const int K = tgrid_orders(g.L, g.jmax);
   if (s == GW_OK) s = tgrid_tables(ctx, g.L, g.jmax, K);
-  const int nch = het_tm_chunks(ctx, n);
+  const int64_t chunk = tgrid_chunk_rows(n, g.n_blk, K);
+  // edge chunks sized for the rows of one launch
+  const int nch = het_tm_chunks(ctx, chunk);
   const double umax = (double)g.jmax / ((double)g.N * (double)g.R);
   if (s == GW_OK) s = het_tm_tables(ctx, g.blk, g.n_blk, umax, nch, K);
   if (s != GW_OK) return s;
-  const int64_t chunk = tgrid_chunk_rows(n, g.n_blk, K);
   const int mh = h->tm_mh;
   // workspace: coefficients for all rows; per row chunk the moments
   // [rows][16][n_blk], the norm moments [n_ch][rows][mh] and hhc [rows]

@@ -141,6 +141,12 @@ __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, i
       visit(k, gr, gi);
     }
   } else {
+    // One run at a time: its top (up to) four bins evaluated directly give
+    // the backward differences; every bin of the run in this block is then
+    // visited from one call site (direct phases for the top bins, the
+    // recurrence below them), which keeps the loop body small.  A block
+    // that starts inside a run advances the recurrence through the run's
+    // bins above it without visiting them.
     const double lin_step = -c.a8 * df;  // linear phase change per bin of the descending walk
     int k = ke - 1;
     while (k >= kb) {
@@ -153,60 +159,52 @@ __global__ void __launch_bounds__(256) k_tmom(const double* __restrict__ coef, i
           s = sj;
         }
       }
-      if (L == 0) {  // below the lowest level: evaluated directly
-        const double* __restrict__ rc = bins + (int64_t)k * RS;
-        double gr, gi;
-        tm_phasor<1>(phase_nonlinear(c, rc[0], rc[1], rc[2], rc[3]) + fma(c.a8, rc[0] * rc[1], c.a5), T, &gr, &gi);
-        visit(k, gr, gi);
-        --k;
-        continue;
-      }
-      // the run's first (up to) four bins from its top, evaluated directly,
-      // build the backward differences; a block that starts inside a run
-      // (blocks shorter than the run, or the top block) visits only its own
-      // bins and advances the table through the others
-      const int top = s + L - 1 < n_freq - 1 ? s + L - 1 : n_freq - 1;
+      // a bin below the lowest level is a run of one, evaluated directly
+      const int top = L == 0 ? k : (s + L - 1 < n_freq - 1 ? s + L - 1 : n_freq - 1);
+      if (L == 0) s = k;
       const int nd = top - s + 1 < 4 ? top - s + 1 : 4;
+      double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;  // direct phases of bins top, top - 1, ...
       double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0, lin = 0.0;
 #pragma nounroll
-      for (int j = 0; j < 4; ++j) {
-        if (j < nd) {
-          const int kk = top - j;
-          const double* __restrict__ rc = bins + (int64_t)kk * RS;
-          const double nl = phase_nonlinear(c, rc[0], rc[1], rc[2], rc[3]);
-          lin = fma(c.a8, rc[0] * rc[1], c.a5);
-          const double d1 = nl - n0;
-          const double d2 = d1 - n1;
-          n3 = d2 - n2;
-          n2 = d2;
-          n1 = d1;
-          n0 = nl;
-          if (kk <= k && kk >= kb) {
-            double gr, gi;
-            tm_phasor<1>(nl + lin, T, &gr, &gi);
-            visit(kk, gr, gi);
-          }
-        }
+      for (int j = 0; j < nd; ++j) {
+        const double* __restrict__ rc = bins + (int64_t)(top - j) * RS;
+        const double nl = phase_nonlinear(c, rc[0], rc[1], rc[2], rc[3]);
+        lin = fma(c.a8, rc[0] * rc[1], c.a5);
+        const double d1 = nl - n0;
+        const double d2 = d1 - n1;
+        n3 = d2 - n2;
+        n2 = d2;
+        n1 = d1;
+        n0 = nl;
+        const double ph = nl + lin;
+        r0 = j == 0 ? ph : r0;
+        r1 = j == 1 ? ph : r1;
+        r2 = j == 2 ? ph : r2;
+        r3 = j == 3 ? ph : r3;
+      }
+      double p0 = n0 + lin, p1 = n1 + lin_step, p2 = n2;
+      const double p3 = n3;
+      int kk = top - nd;
+      for (; kk > k; --kk) {  // above the walk's first bin: advance only
+        p2 += p3;
+        p1 += p2;
+        p0 += p1;
       }
       const int lo = s > kb ? s : kb;
-      int kk = top - nd;
-      if (kk >= lo) {
-        double p0 = n0 + lin, p1 = n1 + lin_step, p2 = n2;
-        const double p3 = n3;
-        for (; kk > k; --kk) {  // above the walk's first bin: advance only
+      for (kk = k; kk >= lo; --kk) {
+        const int j = top - kk;
+        double ph;
+        if (j < nd) {
+          ph = j == 0 ? r0 : (j == 1 ? r1 : (j == 2 ? r2 : r3));
+        } else {
           p2 += p3;
           p1 += p2;
           p0 += p1;
+          ph = p0;
         }
-#pragma unroll 2
-        for (; kk >= lo; --kk) {
-          p2 += p3;
-          p1 += p2;
-          p0 += p1;
-          double gr, gi;
-          tm_phasor<1>(p0, T, &gr, &gi);
-          visit(kk, gr, gi);
-        }
+        double gr, gi;
+        tm_phasor<1>(ph, T, &gr, &gi);
+        visit(kk, gr, gi);
       }
       k = s - 1;
     }
