@@ -97,8 +97,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="full,cfg1,het,tmarg,recon,cache,fiducial,nested,nested_full,prescreen",
-                    help="comma list of legs to run: full (always timed), cfg1, het, tmarg, recon, cache, fiducial, "
+    ap.add_argument("--legs", default="full,cfg1,het,tmarg,recon,mlp,cache,fiducial,nested,nested_full,prescreen",
+                    help="comma list of legs to run: full (always timed), cfg1, het, tmarg, recon, mlp, cache, fiducial, "
                          "nested, nested_full, prescreen, copy")
     return ap.parse_args()
 
@@ -487,15 +487,16 @@ def cache_leg(gw, torch, prob, steps, warmup, mixed_value):
                 ms, nl = gw._lib.gw_profile_read(ctx.handle)
                 gw._lib.gw_profile_enable(ctx.handle, False)
                 k_ms = ms / max(nl, 1)
-                # moment cache: blocks of B bins (256 at df = 1/128 Hz), 16 moments per block and detector,
-                # FP32 complex; algorithmic bytes = each used slot's moments once
+                # moment cache: blocks of B bins (256 at df = 1/128 Hz), 12 Chebyshev moments per block and
+                # detector, FP32 complex; algorithmic bytes = each used slot's moments once
                 blk = 4
                 while blk < 512 and math.pi * prob.df * (2 * blk) * 0.25 <= 1.61:
                     blk *= 2
                 n_blk = -(-prob.n_freq // blk)
-                nbytes = n_slots * n_blk * 3 * 16 * 8
-                # per row, block and detector: 15 Horner steps (2 FMA) + block factor and rotation (8 flop-pairs)
-                flops = n * n_blk * 3 * (15 * 2 + 8) * 2
+                nbytes = n_slots * n_blk * 3 * 12 * 8
+                # per row, block and detector: 12 weighted moments (2 FMA each) + block factor and rotation
+                # (8 flop-pairs)
+                flops = n * n_blk * 3 * (12 * 2 + 8) * 2
                 r["kernel"] = "k_wmom<3>"
                 r["kernel_ms"] = k_ms
                 r["moment_block_bins"] = blk
@@ -720,6 +721,36 @@ def copy_leg(torch, reps=5, mib=256):
     return {"bytes_read_per_copy": a.numel() * 8, "bytes_written_per_copy": a.numel() * 8, "reps": reps}
 
 
+def mlp_leg(gw, torch, ctx, reps):
+    """BF16 inference of the prescreen network (11 -> 256 -> 256 -> 256 -> 1,
+    GELU; random weights) on 65,536 unit-cube rows, the kernel timed with HIP
+    events on the stream it runs on."""
+    import numpy as np
+    n = 65536
+    rng = np.random.default_rng(17)
+    x = torch.from_numpy(rng.random((n, 11))).cuda()
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    net = gw.Mlp(ctx, seed=7)
+    try:
+        net.set_scaling(np.full(11, 0.5), np.full(11, 0.29), 0.0, 1.0)
+        for _ in range(3):
+            net.forward(x, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            net.forward(x, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+    finally:
+        net.close()
+    flops = 2.0 * (11 * 256 + 2 * 256 * 256 + 256) * n
+    return {"rows": n, "ms_per_call": ms, "tflops": flops / (ms * 1e-3) / 1e12, "peak_bf16_tflops": 2500.0,
+            "frac": flops / (ms * 1e-3) / 1e12 / 2500.0,
+            "workload": "prescreen network inference, 65,536 rows, BF16 matrix cores with FP32 accumulation"}
+
+
 def cpu_baseline(gw, torch, batch: int, n_target_cpu_s: float = 16.0):
     """The FP64 oracle on the host cores, on a bounded sample of the headline
     workload (the first rows of its batch), timed; then the same rows' GPU
@@ -813,6 +844,9 @@ def main():
         rc = None
         if "recon" in set(args.legs.split(",")):
             rc = recon_leg(gw, torch, ctx, theta, max(5, args.steps // 2), 2, dt_mix / args.steps)
+        ml = None
+        if "mlp" in set(args.legs.split(",")):
+            ml = mlp_leg(gw, torch, ctx, max(10, args.steps))
     value = n * args.steps / dt_mix
     fp_value = n * fp_steps / dt_fp
     units = n * prob.n_freq
@@ -857,6 +891,8 @@ def main():
         res["time_marginal"] = tm
     if rc is not None:
         res["reconstruction"] = rc
+    if ml is not None:
+        res["mlp_inference"] = ml
     if "cache" in legs:
         res["waveform_cache"] = cache_leg(gw, torch, prob, args.steps, args.warmup, value)
         log("cache leg done")

@@ -219,6 +219,7 @@ gw_status gw_ctx_create(const gw_problem* pr, int32_t device, gw_ctx** out) {
     if (st == GW_OK) st = check_hip(hipMemcpy(ctx->i0c, &c, sizeof(c), hipMemcpyHostToDevice), "ln I0 table copy");
   }
   if (st == GW_OK) st = build_moment_table(ctx, rec, pr->det_pos);
+  if (st == GW_OK) st = wmom_init(ctx);
   if (st == GW_OK) st = calibrate_phasor(ctx);
   if (st != GW_OK) {
     gw_ctx_destroy(ctx);
@@ -237,7 +238,7 @@ gw_status gw_ctx_destroy(gw_ctx* ctx) {
   for (hipEvent_t e : ctx->prof_ev)
     if (e) (void)hipEventDestroy(e);
   double* bufs[] = {ctx->bins,   ctx->dist_tab, ctx->coef,   ctx->partial, ctx->zbuf,
-                    ctx->tm_ccoef, ctx->tm_basis, ctx->tm_mom, ctx->recon};
+                    ctx->tm_ccoef, ctx->tm_basis, ctx->tm_mom, ctx->recon, ctx->wc_basis};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (ctx->wtab) (void)hipFree(ctx->wtab);

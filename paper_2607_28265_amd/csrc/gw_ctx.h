@@ -62,6 +62,7 @@ struct gw_ctx {
   double tm_window = 0.1;
   int tm_R = 4;                    // grid points per sampling interval of the segment
   int tm_nsk = 0;                  // edge chunks of the heterodyned time marginal's moments (0 = heuristic)
+  double* wc_basis = nullptr;      // [wmom_block][12] Chebyshev values for the waveform cache
   double* tm_ccoef = nullptr;      // [K][256][16] expansion coefficients of the grid (tm_cc_L, tm_cc_jmax, tm_cc_K)
   int tm_cc_L = 0, tm_cc_jmax = 0, tm_cc_K = 0;
   double* tm_basis = nullptr;      // [blk][K] Chebyshev values of the in-block offset for the moments
@@ -98,7 +99,7 @@ gw_status launch_epilogue(gw_ctx* ctx, double* partial, int n_chunks, const doub
 gw_status launch_template(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, double* h,
                           hipStream_t st);
 // Waveform-cache forms (fast/slow blocks of the sampler).  A cache slot holds
-// the block moments of one intrinsic waveform (float2 [n_blk][n_det][16],
+// the block moments of one intrinsic waveform (float2 [n_blk][n_det][12],
 // wmom_slot_f2 entries; block length wmom_block bins).  launch_cached runs the
 // full reduction on rows slow_rows[0 .. counts[0]) (none when slow_rows is
 // NULL) into partials of n_chunks chunks and row stride n (coefficients with
@@ -108,8 +109,9 @@ gw_status launch_template(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n
 // whose |t_c + dt_i| exceeds the cache's range get NaN).
 // launch_epilogue_cached combines partials (rows with zsrc[p] >= 0 take their
 // sums from zc[zsrc[p]]) and writes every row's sums to zrow when not NULL.
-// launch_wmom_build rebuilds the slots slots[i] >= 0, i < *count, from
-// coefficient row src[i] (slot * rows_per_slot when src is NULL).
+// launch_wmom_build rebuilds the slots slots[i] >= 0, i < *count <= max_count,
+// from coefficient row src[i] (slot * rows_per_slot when src is NULL), with
+// the phase and phasor of precision prec.
 int wmom_block(const gw_ctx* ctx);
 int64_t wmom_slot_f2(const gw_ctx* ctx);
 gw_status launch_cached(gw_ctx* ctx, const double* coef, int64_t n, int prec, int tpb, int n_chunks,
@@ -124,7 +126,10 @@ gw_status launch_epilogue_z(gw_ctx* ctx, double* partial, int n_chunks, const do
                             int marg, int prec, double* logl, const int32_t* zsrc, const double* zc, double* zrow,
                             double* zbuf, hipStream_t st);
 gw_status launch_wmom_build(gw_ctx* ctx, const double* coef, int64_t ld, const int32_t* slots, const int32_t* count,
-                            int rows_per_slot, const int32_t* src, float2* mom, hipStream_t st);
+                            int64_t max_count, int rows_per_slot, const int32_t* src, int prec, float2* mom,
+                            hipStream_t st);
+// The cache's Chebyshev table [wmom_block][12] (built at context creation).
+gw_status wmom_init(gw_ctx* ctx);
 // Cached-likelihood launch shape (64 rows per workgroup, chunks of ~512 bins)
 // and the workspace it needs for n rows.
 void cached_shape(const gw_ctx* ctx, int* tpb, int* nch);

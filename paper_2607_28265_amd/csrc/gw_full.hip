@@ -346,7 +346,8 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
   }
 }
 
-constexpr int kWMom = 16;          // moments per block and detector
+constexpr int kWMom = 12;          // Chebyshev orders per block and detector
+constexpr int64_t kWBuildManyRows = 512;  // builds listing fewer slots use k_wmom_build_few
 constexpr double kTauCap = 0.25;    // largest |t_c + dt_i| (s) the moment cache is built for
 
 // Extrinsic moves with a cached waveform (Sec. III.B: the fast blocks reuse
@@ -359,50 +360,232 @@ constexpr double kTauCap = 0.25;    // largest |t_c + dt_i| (s) the moment cache
 // t_j = (j - (B - 1) / 2) / (B / 2) in [-1, 1],
 //   exp(-2 pi i f_k tau) = E exp(-i phi t_j),  E = exp(-2 pi i f_c tau),
 //   phi = pi df B tau,
-// so each block contributes E sum_m (-i phi)^m / m! M_m with the slot's
-// moments M_m = sum_j t_j^m u_ij g_j (m < kWMom).  The moments depend on the
-// slot only: they are built once per slot (k_wmom_build, FP64 sums rounded to
-// FP32) and a fast row costs kWMom terms per block and detector instead of B
-// bins.  B is chosen so that |phi| <= 1.61 for |tau| <= kTauCap, where the
-// first dropped term, |phi|^16 / 16!, is below 1e-10 of the block's sum of
-// |u g|; rows with a larger |tau_i| are flagged (NaN).
+// and exp(-i phi t) = sum_m eps_m (-i)^m J_m(phi) T_m(t) (Jacobi-Anger,
+// eps_0 = 1, eps_m = 2), so each block contributes
+// E sum_m eps_m (-i)^m J_m(phi) M_m with the slot's Chebyshev moments
+// M_m = sum_j T_m(t_j) u_ij g_j (m < kWMom).  The moments depend on the slot
+// only: they are built once per slot (k_wmom_build, FP64 sums rounded to FP32)
+// and a fast row costs kWMom terms per block and detector instead of B bins.
+// B is chosen so that |phi| <= 1.61 for |tau| <= kTauCap, where the dropped
+// orders stay below 2 (phi / 2)^12 / 12! = 3e-10 of the block's sum of |u g|
+// (the FP32 moments carry 6e-8); rows with a larger |tau_i| are flagged (NaN).
 //
 // Slot layout: float2 [n_blk][n_det][kWMom].
-constexpr double kInvInt[kWMom + 1] = {0.0,        1.0,        1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,
-                                       1.0 / 6,    1.0 / 7,    1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
-                                       1.0 / 12,   1.0 / 13,   1.0 / 14, 1.0 / 15, 1.0 / 16};
 
-// k_wmom_build: a work unit is (block, group of kWBuildSlots listed slots),
-// units ordered so that neighbouring workgroups share a block (its records
-// stay in L2).  The unit's phasors g_sk (FP64 phase and sin/cos, one per slot
-// and bin, shared by the detectors) go to LDS; then lane (slot, detector,
-// part) sums the moments over L = blk / Q bins of its part (Q = min(16, blk)
-// parts, FP64), the Q partial sums are added by lane exchange in a fixed
-// order and the first lane of the group stores them.  Grid-stride over units:
-// the count is read on the device.
+// t[m] = eps_m J_m(x) with the sign of (-i)^m folded in (+ for m mod 4 in
+// {0, 1}, - otherwise), m < kWMom, |x| <= 1.61: the power series of J_m, 14
+// terms (the last below 3e-14 of the first).
+__device__ inline void wmom_coefs(double x, double* t) {
+  const double h = 0.5 * x, y = -h * h;
+  double lead = 1.0;  // (x / 2)^m / m!
+#pragma unroll
+  for (int m = 0; m < kWMom; ++m) {
+    double term = 1.0, sum = 1.0;
+#pragma unroll
+    for (int k = 1; k <= 14; ++k) {
+      term *= y * (1.0 / (double)(k * (m + k)));
+      sum += term;
+    }
+    const double j = lead * sum * (m == 0 ? 1.0 : 2.0);
+    t[m] = (m & 3) < 2 ? j : -j;
+    lead *= h * (1.0 / (double)(m + 1));
+  }
+}
+
+// k_wmom_build: lane = listed slot (64 per workgroup), workgroup = (block,
+// slot tile); the block's bins are walked from the top (wave-uniform
+// records) as in the time-marginal moments: FP64 phase and sin/cos for
+// PREC = 0, the mixed form's phase recurrence in runs and the FP32 hardware
+// sin/cos for PREC = 1 (the moments are stored in FP32 either way); FP64
+// sums.  Tiles at or beyond the device-side count exit at once.
+template <int ND, int PREC>
+__global__ void __launch_bounds__(64) k_wmom_build(const double* __restrict__ coef, int64_t ld,
+                                                   const int32_t* __restrict__ slots,
+                                                   const int32_t* __restrict__ count, int rows_per_slot,
+                                                   const int32_t* __restrict__ src, const double* __restrict__ bins,
+                                                   int n_freq, int blk, int64_t slot_f2, TrigConsts T, PhaseRuns R,
+                                                   double pg_re, double pg_im, const double* __restrict__ basis,
+                                                   float2* __restrict__ mom) {
+  constexpr int RS = 4 + 2 * ND;
+  const int b = blockIdx.x, tile = blockIdx.y;
+  const int cnt = *count;
+  if (tile * 64 >= cnt) return;  // uniform over the workgroup
+  const int li = tile * 64 + (int)threadIdx.x;
+  const int sl = li < cnt ? slots[li] : -1;
+  int64_t r = 0;  // coefficient row; row 0 for lanes that store nothing
+  if (sl >= 0) r = src ? (int64_t)src[li] : (int64_t)sl * rows_per_slot;
+  PhaseCoef c;
+  c.a0 = coef[C_A0 * ld + r];
+  c.a2 = coef[C_A2 * ld + r];
+  c.a3 = coef[C_A3 * ld + r];
+  c.a4 = coef[C_A4 * ld + r];
+  c.a5 = coef[C_A5 * ld + r];
+  c.a6 = coef[C_A6 * ld + r];
+  c.a7 = coef[C_A7 * ld + r];
+  c.a8 = 0.0;  // the linear time term is applied per row
+  c.a10 = coef[C_A10 * ld + r];
+  c.a12 = coef[C_A12 * ld + r];
+  c.b5 = coef[C_B5 * ld + r];
+  c.b6 = coef[C_B6 * ld + r];
+  const int kb = b * blk;
+  const int ke = kb + blk < n_freq ? kb + blk : n_freq;
+  double mr[ND][kWMom], mi[ND][kWMom];
+#pragma unroll
+  for (int i = 0; i < ND; ++i)
+#pragma unroll
+    for (int m = 0; m < kWMom; ++m) mr[i][m] = mi[i][m] = 0.0;
+  auto visit = [&](int k, double gr, double gi) {
+    const double* __restrict__ u = bins + (int64_t)k * RS + 4;
+    const double* __restrict__ tq = basis + (int64_t)(k - kb) * kWMom;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const double ur = u[2 * i], ui = u[2 * i + 1];
+      const double wr = ur * gr - ui * gi, wi = ur * gi + ui * gr;
+#pragma unroll
+      for (int m = 0; m < kWMom; ++m) {
+        mr[i][m] = fma(tq[m], wr, mr[i][m]);
+        mi[i][m] = fma(tq[m], wi, mi[i][m]);
+      }
+    }
+  };
+  if constexpr (PREC == 0) {
+    for (int k = ke - 1; k >= kb; --k) {
+      const double* __restrict__ rc = bins + (int64_t)k * RS;
+      double sn, cs;
+      sincos_cycles(phase_cycles(c, rc[0], rc[1], rc[2], rc[3]), T, &sn, &cs);
+      visit(k, cs, -sn);
+    }
+  } else {
+    // the runs of the mixed walk, as in k_tmom: one visit site per bin
+    int k = ke - 1;
+    while (k >= kb) {
+      int L = 0, s = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int sj = k & ~(R.len[j] - 1);
+        if (L == 0 && sj >= R.k_min[j]) {
+          L = R.len[j];
+          s = sj;
+        }
+      }
+      const int top = L == 0 ? k : (s + L - 1 < n_freq - 1 ? s + L - 1 : n_freq - 1);
+      if (L == 0) s = k;
+      const int nd = top - s + 1 < 4 ? top - s + 1 : 4;
+      double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+      double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
+#pragma nounroll
+      for (int j = 0; j < nd; ++j) {
+        const double* __restrict__ rc = bins + (int64_t)(top - j) * RS;
+        const double nl = phase_nonlinear(c, rc[0], rc[1], rc[2], rc[3]);
+        const double d1 = nl - n0;
+        const double d2 = d1 - n1;
+        n3 = d2 - n2;
+        n2 = d2;
+        n1 = d1;
+        n0 = nl;
+        const double ph = nl + c.a5;
+        r0 = j == 0 ? ph : r0;
+        r1 = j == 1 ? ph : r1;
+        r2 = j == 2 ? ph : r2;
+        r3 = j == 3 ? ph : r3;
+      }
+      double p0 = n0 + c.a5, p1 = n1, p2 = n2;
+      const double p3 = n3;
+      int kk = top - nd;
+      for (; kk > k; --kk) {  // above the walk's first bin: advance only
+        p2 += p3;
+        p1 += p2;
+        p0 += p1;
+      }
+      const int lo = s > kb ? s : kb;
+      for (kk = k; kk >= lo; --kk) {
+        const int j = top - kk;
+        double ph;
+        if (j < nd) {
+          ph = j == 0 ? r0 : (j == 1 ? r1 : (j == 2 ? r2 : r3));
+        } else {
+          p2 += p3;
+          p1 += p2;
+          p0 += p1;
+          ph = p0;
+        }
+        const float t = (float)(ph - rint(ph));
+        visit(kk, (double)__builtin_amdgcn_cosf(t), -(double)__builtin_amdgcn_sinf(t));
+      }
+      k = s - 1;
+    }
+  }
+  if (sl < 0) return;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    float2* __restrict__ out = mom + sl * slot_f2 + ((int64_t)b * ND + i) * kWMom;
+#pragma unroll
+    for (int m = 0; m < kWMom; ++m) {
+      double vr = mr[i][m], vi = mi[i][m];
+      if (PREC == 1) {  // remove the mean bias of the hardware phasor
+        const double tr = vr * pg_re - vi * pg_im;
+        vi = vr * pg_im + vi * pg_re;
+        vr = tr;
+      }
+      out[m] = make_float2((float)vr, (float)vi);
+    }
+  }
+}
+
+// k_wmom_build_few: the same moments for the sampler's rounds, where a few
+// listed slots rebuild at a time; the work follows the device-side count.  A
+// unit is (block, group of kWBuildSlots listed slots), units ordered so that
+// neighbouring workgroups share a block (its records stay in L2); the grid
+// strides over the units.  Per unit the slots' phasors g_sk (one per slot and
+// bin, shared by the detectors; FP64 phase, FP64 or FP32 hardware sin/cos),
+// the block's projected data u_ik and its Chebyshev values T_m(t_k) go to LDS;
+// then lane (slot, detector, part) sums the moments over blk / Q bins of its
+// part (Q = min(16, blk) parts, FP64) from LDS alone, and the Q partial sums
+// are added by lane exchange in a fixed order.  Dynamic LDS:
+// blk (16 kWBuildSlots + 16 nd + 8 kWMom) bytes.
 constexpr int kWBuildSlots = 4;
 
-__global__ void __launch_bounds__(256) k_wmom_build(const double* __restrict__ coef, int64_t ld,
-                                                    const int32_t* __restrict__ slots,
-                                                    const int32_t* __restrict__ count, int rows_per_slot,
-                                                    const int32_t* __restrict__ src, const double* __restrict__ bins,
-                                                    int rs, int n_freq, int nd, int blk, int n_blk, int64_t slot_f2,
-                                                    TrigConsts T, float2* __restrict__ mom) {
-  __shared__ double2 g_lds[kWBuildSlots][512];  // blk <= 512
+inline size_t wmom_build_few_lds(int blk, int nd) {
+  return (size_t)blk * (16 * kWBuildSlots + 16 * nd + 8 * kWMom);
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_wmom_build_few(const double* __restrict__ coef, int64_t ld,
+                                                        const int32_t* __restrict__ slots,
+                                                        const int32_t* __restrict__ count, int rows_per_slot,
+                                                        const int32_t* __restrict__ src,
+                                                        const double* __restrict__ bins, int rs, int n_freq, int nd,
+                                                        int blk, int n_blk, int64_t slot_f2, TrigConsts T,
+                                                        double pg_re, double pg_im,
+                                                        const double* __restrict__ basis, float2* __restrict__ mom) {
+  extern __shared__ __attribute__((aligned(16))) double lds[];
+  double2* g_lds = reinterpret_cast<double2*>(lds);   // [kWBuildSlots][blk]
+  double* u_lds = lds + 2 * kWBuildSlots * blk;        // [blk][2 nd]
+  double* t_lds = u_lds + 2 * nd * blk;                // [blk][kWMom]
   const int cnt = *count;
   const int ngrp = (cnt + kWBuildSlots - 1) / kWBuildSlots;
   const int64_t units = (int64_t)n_blk * ngrp;
+  if (units <= blockIdx.x) return;
   const int Q = blk < 16 ? blk : 16;  // power of two: parts per (slot, detector)
   const int L = blk / Q;
   const int tid = threadIdx.x;
   const int part = tid % Q, combo = tid / Q;
   const int s_me = combo / nd, i_me = combo - (combo / nd) * nd;
   const bool lane_on = s_me < kWBuildSlots;  // Q kWBuildSlots nd <= 256 for nd <= 4
-  const double cen = 0.5 * (blk - 1), hinv = 2.0 / blk;
+  for (int e = tid; e < blk * kWMom; e += blockDim.x) t_lds[e] = basis[e];
+  int b_prev = -1;
   for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
     const int b = (int)(unit / ngrp), grp = (int)(unit - (int64_t)b * ngrp);
     const int kb = b * blk;
     const int nbin = kb + blk < n_freq ? blk : n_freq - kb;
+    __syncthreads();  // the previous unit's LDS contents are consumed
+    if (b != b_prev) {  // uniform: the block's projected data
+      for (int e = tid; e < nbin * 2 * nd; e += blockDim.x) {
+        const int k = e / (2 * nd), j = e - k * (2 * nd);
+        u_lds[e] = bins[(int64_t)(kb + k) * rs + 4 + j];
+      }
+      b_prev = b;
+    }
     for (int e = tid; e < kWBuildSlots * blk; e += blockDim.x) {
       const int s = e / blk, k = e - (e / blk) * blk;
       const int li = grp * kWBuildSlots + s;
@@ -424,11 +607,16 @@ __global__ void __launch_bounds__(256) k_wmom_build(const double* __restrict__ c
         c.b6 = coef[C_B6 * ld + r];
         const double* rec = bins + (int64_t)(kb + k) * rs;
         const double ph = phase_cycles(c, rec[0], rec[1], rec[2], rec[3]);
-        double sn, cs;
-        sincos_cycles(ph, T, &sn, &cs);
-        g = make_double2(cs, sn);
+        if (PREC == 0) {
+          double sn, cs;
+          sincos_cycles(ph, T, &sn, &cs);
+          g = make_double2(cs, -sn);
+        } else {
+          const float t = (float)(ph - rint(ph));
+          g = make_double2((double)__builtin_amdgcn_cosf(t), -(double)__builtin_amdgcn_sinf(t));
+        }
       }
-      g_lds[s][k] = g;
+      g_lds[s * blk + k] = g;
     }
     __syncthreads();
     const int li = grp * kWBuildSlots + s_me;
@@ -440,18 +628,14 @@ __global__ void __launch_bounds__(256) k_wmom_build(const double* __restrict__ c
       const int k1 = part * L;
       const int k2 = k1 + L < nbin ? k1 + L : nbin;
       for (int k = k1; k < k2; ++k) {
-        const double2 g = g_lds[s_me][k];
-        const double* rec = bins + (int64_t)(kb + k) * rs;
-        const double ur = rec[4 + 2 * i_me], ui = rec[5 + 2 * i_me];
-        // w = u g with g = cos - i sin
-        const double wr = ur * g.x + ui * g.y, wi = ui * g.x - ur * g.y;
-        const double t = ((double)k - cen) * hinv;
-        double tp = 1.0;
+        const double2 g = g_lds[s_me * blk + k];
+        const double ur = u_lds[k * 2 * nd + 2 * i_me], ui = u_lds[k * 2 * nd + 2 * i_me + 1];
+        const double wr = ur * g.x - ui * g.y, wi = ur * g.y + ui * g.x;
+        const double* tq = t_lds + k * kWMom;
 #pragma unroll
         for (int m = 0; m < kWMom; ++m) {
-          mr[m] = fma(tp, wr, mr[m]);
-          mi[m] = fma(tp, wi, mi[m]);
-          tp *= t;
+          mr[m] = fma(tq[m], wr, mr[m]);
+          mi[m] = fma(tq[m], wi, mi[m]);
         }
       }
     }
@@ -466,9 +650,16 @@ __global__ void __launch_bounds__(256) k_wmom_build(const double* __restrict__ c
     if (sl >= 0 && part == 0) {
       float2* __restrict__ out = mom + sl * slot_f2 + ((int64_t)b * nd + i_me) * kWMom;
 #pragma unroll
-      for (int m = 0; m < kWMom; ++m) out[m] = make_float2((float)mr[m], (float)mi[m]);
+      for (int m = 0; m < kWMom; ++m) {
+        double vr = mr[m], vi = mi[m];
+        if (PREC == 1) {  // remove the mean bias of the hardware phasor
+          const double tr = vr * pg_re - vi * pg_im;
+          vi = vr * pg_im + vi * pg_re;
+          vr = tr;
+        }
+        out[m] = make_float2((float)vr, (float)vi);
+      }
     }
-    __syncthreads();  // before the next unit overwrites the phasors
   }
 }
 
@@ -504,13 +695,13 @@ __global__ void __launch_bounds__(256) k_wmom(const double* __restrict__ coef, i
   const int bb = cb + wv * sub, be = bb + sub < ce ? bb + sub : ce;
 
   const double tau0 = coef[C_TAU0 * ld + p];
-  double zr[ND], zi[ND], er[ND], ei[ND], rr[ND], ri[ND], ph[ND];
+  double zr[ND], zi[ND], er[ND], ei[ND], rr[ND], ri[ND], tc[ND][kWMom];
   bool in_range = true;
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
     const double tau = i == 0 ? tau0 : tau0 + coef[(C_DT1 + i - 1) * ld + p];
     in_range = in_range && fabs(tau) <= kTauCap;
-    ph[i] = kPi * df * blk * tau;
+    wmom_coefs(kPi * df * blk * (fabs(tau) <= kTauCap ? tau : 0.0), tc[i]);
     double sn, cs;
     // E at the centre of the first block, and the block-to-block rotation
     sincos_cycles(((double)k0 + (double)bb * blk + 0.5 * (blk - 1)) * df * tau, T, &sn, &cs);
@@ -529,17 +720,19 @@ __global__ void __launch_bounds__(256) k_wmom(const double* __restrict__ coef, i
       float4 v[kWMom / 2];
 #pragma unroll
       for (int q = 0; q < kWMom / 2; ++q) v[q] = mb[i * (kWMom / 2) + q];
-      // Horner in (-i phi): H = M_m + (-i phi / (m + 1)) H
-      double hr = (double)v[kWMom / 2 - 1].z, hi = (double)v[kWMom / 2 - 1].w;
+      // H = sum_m eps_m (-i)^m J_m(phi) M_m (signs folded into tc)
+      double hr = 0.0, hi = 0.0;
 #pragma unroll
-      for (int m = kWMom - 2; m >= 0; --m) {
-        const double q = ph[i] * kInvInt[m + 1];
-        const double mr = (double)((m & 1) ? v[m >> 1].z : v[m >> 1].x);
-        const double mi = (double)((m & 1) ? v[m >> 1].w : v[m >> 1].y);
-        const double nr = fma(q, hi, mr);
-        const double ni = fma(-q, hr, mi);
-        hr = nr;
-        hi = ni;
+      for (int m = 0; m < kWMom; ++m) {
+        const double mre = (double)((m & 1) ? v[m >> 1].z : v[m >> 1].x);
+        const double mim = (double)((m & 1) ? v[m >> 1].w : v[m >> 1].y);
+        if ((m & 1) == 0) {
+          hr = fma(tc[i][m], mre, hr);
+          hi = fma(tc[i][m], mim, hi);
+        } else {
+          hr = fma(tc[i][m], mim, hr);
+          hi = fma(-tc[i][m], mre, hi);
+        }
       }
       zr[i] = fma(er[i], hr, zr[i]);
       zr[i] = fma(-ei[i], hi, zr[i]);
@@ -1363,14 +1556,75 @@ gw_status launch_cached(gw_ctx* ctx, const double* coef, int64_t n, int prec, in
   }
 }
 
+template <int ND>
+static void launch_wmom_build_nd(gw_ctx* ctx, const double* coef, int64_t ld, const int32_t* slots,
+                                 const int32_t* count, int rows_per_slot, const int32_t* src, int prec, dim3 grid,
+                                 float2* mom, hipStream_t st) {
+  const int blk = wmom_block(ctx);
+  const TrigConsts T = make_trig_consts();
+  const PhaseRuns R = make_phase_runs(ctx->geom);
+  if (prec == GW_PREC_FP64)
+    hipLaunchKernelGGL((k_wmom_build<ND, 0>), grid, dim3(64), 0, st, coef, ld, slots, count, rows_per_slot, src,
+                       ctx->bins, (int)ctx->geom.n_freq, blk, wmom_slot_f2(ctx), T, R, 1.0, 0.0,
+                       (const double*)ctx->wc_basis, mom);
+  else
+    hipLaunchKernelGGL((k_wmom_build<ND, 1>), grid, dim3(64), 0, st, coef, ld, slots, count, rows_per_slot, src,
+                       ctx->bins, (int)ctx->geom.n_freq, blk, wmom_slot_f2(ctx), T, R, ctx->pgain_re, ctx->pgain_im,
+                       (const double*)ctx->wc_basis, mom);
+}
+
 gw_status launch_wmom_build(gw_ctx* ctx, const double* coef, int64_t ld, const int32_t* slots, const int32_t* count,
-                            int rows_per_slot, const int32_t* src, float2* mom, hipStream_t st) {
+                            int64_t max_count, int rows_per_slot, const int32_t* src, int prec, float2* mom,
+                            hipStream_t st) {
+  if (max_count <= 0) return GW_OK;
+  if (!ctx->wc_basis) return set_error(GW_ESTATE, "waveform cache: basis table missing");
   const int blk = wmom_block(ctx);
   const int n_blk = (int)((ctx->geom.n_freq + blk - 1) / blk);
-  hipLaunchKernelGGL(k_wmom_build, dim3(2048), dim3(256), 0, st, coef, ld, slots, count, rows_per_slot, src, ctx->bins,
-                     ctx->rec_stride, (int)ctx->geom.n_freq, ctx->n_det, blk, n_blk, wmom_slot_f2(ctx),
-                     make_trig_consts(), mom);
+  if (max_count < kWBuildManyRows) {
+    // the sampler's rounds: cost follows the device-side count
+    const TrigConsts T = make_trig_consts();
+    const size_t lds = wmom_build_few_lds(blk, ctx->n_det);
+    if (prec == GW_PREC_FP64)
+      hipLaunchKernelGGL(k_wmom_build_few<0>, dim3(2048), dim3(256), lds, st, coef, ld, slots, count, rows_per_slot,
+                         src, ctx->bins, ctx->rec_stride, (int)ctx->geom.n_freq, ctx->n_det, blk, n_blk,
+                         wmom_slot_f2(ctx), T, 1.0, 0.0, (const double*)ctx->wc_basis, mom);
+    else
+      hipLaunchKernelGGL(k_wmom_build_few<1>, dim3(2048), dim3(256), lds, st, coef, ld, slots, count, rows_per_slot,
+                         src, ctx->bins, ctx->rec_stride, (int)ctx->geom.n_freq, ctx->n_det, blk, n_blk,
+                         wmom_slot_f2(ctx), T, ctx->pgain_re, ctx->pgain_im, (const double*)ctx->wc_basis, mom);
+    return check_hip(hipGetLastError(), "waveform cache build launch");
+  }
+  const dim3 grid((unsigned)n_blk, (unsigned)((max_count + 63) / 64));
+  switch (ctx->n_det) {
+    case 1: launch_wmom_build_nd<1>(ctx, coef, ld, slots, count, rows_per_slot, src, prec, grid, mom, st); break;
+    case 2: launch_wmom_build_nd<2>(ctx, coef, ld, slots, count, rows_per_slot, src, prec, grid, mom, st); break;
+    case 3: launch_wmom_build_nd<3>(ctx, coef, ld, slots, count, rows_per_slot, src, prec, grid, mom, st); break;
+    case 4: launch_wmom_build_nd<4>(ctx, coef, ld, slots, count, rows_per_slot, src, prec, grid, mom, st); break;
+    default: return set_error(GW_ENOTSUP, "n_det %d not supported", ctx->n_det);
+  }
   return check_hip(hipGetLastError(), "waveform cache build launch");
+}
+
+gw_status wmom_init(gw_ctx* ctx) {
+  const int blk = wmom_block(ctx);
+  std::vector<double> h((size_t)blk * kWMom);
+  const double cen = 0.5 * (blk - 1), hinv = 2.0 / blk;
+  for (int j = 0; j < blk; ++j) {
+    // T_m of the bin's offset in the block, by the three-term recurrence
+    const double t = ((double)j - cen) * hinv;
+    double a = 1.0, b = t;
+    for (int m = 0; m < kWMom; ++m) {
+      h[(size_t)j * kWMom + m] = a;
+      const double c = 2.0 * t * b - a;
+      a = b;
+      b = c;
+    }
+  }
+  gw_status s = check_hip(hipMalloc((void**)&ctx->wc_basis, h.size() * sizeof(double)), "cache basis alloc");
+  if (s == GW_OK)
+    s = check_hip(hipMemcpy(ctx->wc_basis, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice),
+                  "cache basis copy");
+  return s;
 }
 
 gw_status launch_template(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, double* h, hipStream_t st) {

@@ -176,13 +176,28 @@ __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const 
   if (threadIdx.x == 0) *loss = red[0] / (float)n;
 }
 
-// db[j] = sum_i d[i][j], rows in order.
-__global__ void k_colsum(const float* __restrict__ d, int64_t rows, int cols, float* __restrict__ db) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
-  float s = 0.0f;
-  for (int64_t i = 0; i < rows; ++i) s += d[i * cols + j];
-  db[j] = s;
+// db[j] = sum_i d[i][j]: workgroup = 64 columns x 4 waves; wave w sums rows
+// i = w mod 4 in four interleaved partial sums (i mod 16), the 16 partials
+// are added in a fixed order.
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ d, int64_t rows, int cols,
+                                               float* __restrict__ db) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+  if (j < cols) {
+    int64_t i = w;
+    for (; i + 12 < rows; i += 16) {
+      a0 += d[i * cols + j];
+      a1 += d[(i + 4) * cols + j];
+      a2 += d[(i + 8) * cols + j];
+      a3 += d[(i + 12) * cols + j];
+    }
+    for (; i < rows; i += 4) a0 += d[i * cols + j];
+  }
+  red[w][lane] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (w == 0 && j < cols) db[j] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
@@ -565,22 +580,22 @@ gw_status grad32(gw_mlp* m, const double* x, const double* y, int64_t n, hipStre
   float* g = m->g;
   // layer 4
   s = gemm(m, true, false, kH, 1, R, a.a3, kH, a.dy, 1, g + OW4, 1, nullptr, sp, st);
-  if (s == GW_OK) hipLaunchKernelGGL(k_colsum, dim3(1), dim3(64), 0, st, a.dy, n, 1, g + OB4);
+  if (s == GW_OK) hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, a.dy, n, 1, g + OB4);
   if (s == GW_OK) s = gemm(m, false, true, R, kH, 1, a.dy, 1, m->p + OW4, 1, a.d0, kH, nullptr, 1, st);
   if (s == GW_OK) hipLaunchKernelGGL(k_gelu_bwd, dim3(nblk(n * kH)), dim3(256), 0, st, a.d0, a.z3, n * kH);
   // layer 3
   if (s == GW_OK) s = gemm(m, true, false, kH, kH, R, a.a2, kH, a.d0, kH, g + OW3, kH, nullptr, sp, st);
-  if (s == GW_OK) hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, a.d0, n, kH, g + OB3);
+  if (s == GW_OK) hipLaunchKernelGGL(k_colsum, dim3(kH / 64), dim3(256), 0, st, a.d0, n, kH, g + OB3);
   if (s == GW_OK) s = gemm(m, false, true, R, kH, kH, a.d0, kH, m->p + OW3, kH, a.d1, kH, nullptr, 1, st);
   if (s == GW_OK) hipLaunchKernelGGL(k_gelu_bwd, dim3(nblk(n * kH)), dim3(256), 0, st, a.d1, a.z2, n * kH);
   // layer 2
   if (s == GW_OK) s = gemm(m, true, false, kH, kH, R, a.a1, kH, a.d1, kH, g + OW2, kH, nullptr, sp, st);
-  if (s == GW_OK) hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, a.d1, n, kH, g + OB2);
+  if (s == GW_OK) hipLaunchKernelGGL(k_colsum, dim3(kH / 64), dim3(256), 0, st, a.d1, n, kH, g + OB2);
   if (s == GW_OK) s = gemm(m, false, true, R, kH, kH, a.d1, kH, m->p + OW2, kH, a.d0, kH, nullptr, 1, st);
   if (s == GW_OK) hipLaunchKernelGGL(k_gelu_bwd, dim3(nblk(n * kH)), dim3(256), 0, st, a.d0, a.z1, n * kH);
   // layer 1
   if (s == GW_OK) s = gemm(m, true, false, kIn, kH, R, a.xs, kIn, a.d0, kH, g + OW1, kH, nullptr, sp, st);
-  if (s == GW_OK) hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, a.d0, n, kH, g + OB1);
+  if (s == GW_OK) hipLaunchKernelGGL(k_colsum, dim3(kH / 64), dim3(256), 0, st, a.d0, n, kH, g + OB1);
   if (s == GW_OK) s = check_hip(hipGetLastError(), "mlp backward");
   return s;
 }

@@ -902,8 +902,8 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
         g = check_hip(hipGetLastError(), "slice update launch");
       }
       if (g == GW_OK && a.cache)
-        g = launch_wmom_build(ctx, ctx->coef, 2 * k, ws->S.build_list, ws->S.counts + 2, 2, ws->S.build_src, ws->wc,
-                              gs);
+        g = launch_wmom_build(ctx, ctx->coef, 2 * k, ws->S.build_list, ws->S.counts + 2, k, 2, ws->S.build_src,
+                              a.prec, ws->wc, gs);
     }
     return g;
   };

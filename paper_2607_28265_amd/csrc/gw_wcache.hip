@@ -196,7 +196,7 @@ gw_status gw_wcache_update(gw_wcache* c, const double* theta, const int32_t* slo
     hipLaunchKernelGGL(k_wc_store_z, dim3(blocks), dim3(256), 0, st, c->zrow, c->sl, c->owner, n, ctx->n_det, c->zc);
     s = check_hip(hipGetLastError(), "cached sums launch");
   }
-  if (s == GW_OK) s = launch_wmom_build(ctx, ctx->coef, n, c->sl, c->counts, 1, c->rows, c->wc, st);
+  if (s == GW_OK) s = launch_wmom_build(ctx, ctx->coef, n, c->sl, c->counts, n, 1, c->rows, prec, c->wc, st);
   if (s == GW_OK) {
     hipLaunchKernelGGL(k_wc_release, dim3(blocks), dim3(256), 0, st, slots, n, c->n_slots, c->owner);
     hipLaunchKernelGGL(k_wc_mark, dim3(blocks), dim3(256), 0, st, c->sl, n, logl);
