@@ -821,12 +821,12 @@ void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech)
 // [rows][K][n_blk]; what = 1: S_m, m0 <= m < m0 + K (m < mh), over the
 // chunk's edges into hpart [chunk][rows][mh]; chunk 0 also writes the
 // constant norm part hhc [rows].
-template <int ND, int PREC, int K>
+template <int ND, int PREC, int K, int WHAT>
 __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef, int64_t ld, int64_t n,
                                                  const double* __restrict__ rec, int n_bins,
                                                  const double* __restrict__ tab, int mh,
                                                  const int32_t* __restrict__ bs, const int32_t* __restrict__ cb,
-                                                 int n_blk, int what, int m0, HetConst hc, TrigConsts T,
+                                                 int n_blk, int m0, HetConst hc, TrigConsts T,
                                                  double2* __restrict__ mom, double2* __restrict__ hpart,
                                                  double* __restrict__ hhc) {
   constexpr int RS = het_rs(ND);
@@ -851,11 +851,11 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
     hconst = fma(q2[i], hc.hh0[i], hconst);
     pr[i] = pim[i] = 0.0;
   }
-  if (what == 0 && ch == 0 && p < n) hhc[p] = hconst;
+  if (WHAT == 0 && ch == 0 && p < n) hhc[p] = hconst;
   const int b_lo = cb[ch], b_hi = cb[ch + 1];
   const int e_lo = bs[b_lo], e_hi = bs[b_hi];
   const int tw_ = K + mh;  // table row length
-  if (what == 1 && e_lo > 0) {  // the norm term needs the previous edge's phasors
+  if (WHAT == 1 && e_lo > 0) {  // the norm term needs the previous edge's phasors
     const double* r = rec + (int64_t)(e_lo - 1) * RS;
     const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
 #pragma unroll
@@ -867,44 +867,46 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
   double ar_[K], ai_[K];
 #pragma unroll
   for (int m = 0; m < K; ++m) ar_[m] = ai_[m] = 0.0;
-  int e = e_lo;
-  for (int b = b_lo; b < b_hi; ++b) {
-    const int be = bs[b + 1];
-    for (; e < be; ++e) {
-      const double* r = rec + (int64_t)e * RS;
-      const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
-      const double f = r[H_F];
-      const int side = e == 0 ? 1 : (e == n_bins ? 2 : 0);
-      double wr = 0.0, wi = 0.0;
+  // one edge: its weight (W_e for WHAT = 0, V_e for WHAT = 1) into the moments
+  auto edge = [&](int e) {
+    const double* r = rec + (int64_t)e * RS;
+    const double d0 = phase_cycles(c, r[H_X], r[H_X2], r[H_XM5], r[H_LNF]) - r[H_PHI0];
+    const double f = r[H_F];
+    double wr = 0.0, wi = 0.0;
 #pragma unroll
-      for (int i = 0; i < ND; ++i) {
-        const double di = i == 0 ? d0 : fma(f, dt[i], d0) - r[H_PHI0 + i];
-        double gr, gi;
-        het_phasor<PREC>(di, T, &gr, &gi);
-        const double* w = r + BO + 1 + 6 * i;
-        if (what == 0) {
-          const double kr = side == 0 ? w[0] : (side == 1 ? w[0] - w[2] : w[2]);
-          const double ki = side == 0 ? w[1] : (side == 1 ? w[1] - w[3] : w[3]);
-          const double kgr = kr * gr - ki * gi, kgi = kr * gi + ki * gr;  // q K g
-          wr = fma(qr[i], kgr, fma(-qi[i], kgi, wr));
-          wi = fma(qr[i], kgi, fma(qi[i], kgr, wi));
-        } else if (e > 0) {
-          const double sq = q2[i] * w[4];  // |q|^2 (B0 / 2) g_e conj(g_e-1)
-          wr = fma(sq, fma(gr, pr[i], gi * pim[i]), wr);
-          wi = fma(sq, fma(gi, pr[i], -gr * pim[i]), wi);
-        }
+    for (int i = 0; i < ND; ++i) {
+      const double di = i == 0 ? d0 : fma(f, dt[i], d0) - r[H_PHI0 + i];
+      double gr, gi;
+      het_phasor<PREC>(di, T, &gr, &gi);
+      const double* w = r + BO + 1 + 6 * i;
+      if constexpr (WHAT == 0) {
+        // summed-by-parts weights; the first and last edges take one side
+        const double kr = e == 0 ? w[0] - w[2] : (e == n_bins ? w[2] : w[0]);
+        const double ki = e == 0 ? w[1] - w[3] : (e == n_bins ? w[3] : w[1]);
+        const double kgr = kr * gr - ki * gi, kgi = kr * gi + ki * gr;  // q K g
+        wr = fma(qr[i], kgr, fma(-qi[i], kgi, wr));
+        wi = fma(qr[i], kgi, fma(qi[i], kgr, wi));
+      } else {
+        const double sq = e > 0 ? q2[i] * w[4] : 0.0;  // |q|^2 (B0 / 2) g_e conj(g_e-1)
+        wr = fma(sq, fma(gr, pr[i], gi * pim[i]), wr);
+        wi = fma(sq, fma(gi, pr[i], -gr * pim[i]), wi);
         pr[i] = gr;
         pim[i] = gi;
       }
-      const double* tp = tab + (int64_t)e * tw_ + (what == 0 ? 0 : K + m0);
-#pragma unroll
-      for (int m = 0; m < K; ++m) {
-        if (what == 1 && m0 + m >= mh) break;
-        ar_[m] = fma(tp[m], wr, ar_[m]);
-        ai_[m] = fma(tp[m], wi, ai_[m]);
-      }
     }
-    if (what == 0) {
+    const double* tp = tab + (int64_t)e * tw_ + (WHAT == 0 ? 0 : K + m0);
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const double t = (WHAT == 0 || m0 + m < mh) ? tp[m] : 0.0;
+      ar_[m] = fma(t, wr, ar_[m]);
+      ai_[m] = fma(t, wi, ai_[m]);
+    }
+  };
+  if constexpr (WHAT == 0) {
+    int e = e_lo;
+    for (int b = b_lo; b < b_hi; ++b) {
+      const int be = bs[b + 1];
+      for (; e < be; ++e) edge(e);
       if (p < n) {
         double2* out = mom + p * K * n_blk + b;
 #pragma unroll
@@ -913,12 +915,14 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
 #pragma unroll
       for (int m = 0; m < K; ++m) ar_[m] = ai_[m] = 0.0;
     }
-  }
-  if (what == 1 && p < n) {
-    double2* out = hpart + ((int64_t)ch * n + p) * mh + m0;
+  } else {
+    for (int e = e_lo; e < e_hi; ++e) edge(e);
+    if (p < n) {
+      double2* out = hpart + ((int64_t)ch * n + p) * mh + m0;
 #pragma unroll
-    for (int m = 0; m < K; ++m)
-      if (m0 + m < mh) out[m] = make_double2(ar_[m], ai_[m]);
+      for (int m = 0; m < K; ++m)
+        if (m0 + m < mh) out[m] = make_double2(ar_[m], ai_[m]);
+    }
   }
 }
 
@@ -930,12 +934,15 @@ static void launch_het_tmom_k(gw_ctx* ctx, const double* coef, int64_t ld, int64
   const dim3 grid((unsigned)((n + 63) / 64), (unsigned)h->tm_nch);
   const int32_t* bs = h->tm_idx;
   const int32_t* cb = h->tm_idx + h->tm_nblk + 1;
-  if (prec == GW_PREC_FP64)
-    hipLaunchKernelGGL((k_het_tmom<ND, 0, K>), grid, dim3(64), 0, st, coef, ld, n, (const double*)h->rec, h->n_bins,
-                       (const double*)h->tm_tab, h->tm_mh, bs, cb, h->tm_nblk, what, m0, hc, T, mom, hpart, hhc);
-  else
-    hipLaunchKernelGGL((k_het_tmom<ND, 1, K>), grid, dim3(64), 0, st, coef, ld, n, (const double*)h->rec, h->n_bins,
-                       (const double*)h->tm_tab, h->tm_mh, bs, cb, h->tm_nblk, what, m0, hc, T, mom, hpart, hhc);
+#define GW_HET_TMOM(P, W)                                                                                     \
+  hipLaunchKernelGGL((k_het_tmom<ND, P, K, W>), grid, dim3(64), 0, st, coef, ld, n, (const double*)h->rec,        \
+                     h->n_bins, (const double*)h->tm_tab, h->tm_mh, bs, cb, h->tm_nblk, m0, hc, T, mom, hpart, hhc)
+  if (prec == GW_PREC_FP64) {
+    if (what == 0) GW_HET_TMOM(0, 0); else GW_HET_TMOM(0, 1);
+  } else {
+    if (what == 0) GW_HET_TMOM(1, 0); else GW_HET_TMOM(1, 1);
+  }
+#undef GW_HET_TMOM
 }
 
 template <int ND>
