@@ -97,9 +97,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="full,cfg1,het,tmarg,recon,mlp,cache,fiducial,nested,nested_full,prescreen",
+    ap.add_argument("--legs", default="full,cfg1,het,tmarg,recon,mlp,cache,fiducial,nested,nested_tmarg,nested_full,"
+                                      "prescreen",
                     help="comma list of legs to run: full (always timed), cfg1, het, tmarg, recon, mlp, cache, fiducial, "
-                         "nested, nested_full, prescreen, copy")
+                         "nested, nested_tmarg, nested_full, prescreen, copy")
     return ap.parse_args()
 
 
@@ -428,6 +429,46 @@ def nested_leg(gw, torch):
                                                                                      g["log_z_err"])
     out["workload"] = ("nested sampling: 1000 live points, 125 deletions per iteration, 7 Gibbs blocks over 11 "
                        "dimensions, heterodyned 500-bin likelihood (mixed form), dlogz 0.1, SNR-24 injection")
+    return out
+
+
+def nested_tmarg_leg(gw, torch):
+    """Heterodyned nested sampling at 5000 bins in the detector sky frame with
+    t_c and phi_c marginalised and d_L sampled (the paper's GW170817
+    configuration), against the same run with phi_c and d_L marginalised and
+    t_c sampled: 512 live points, 64 deletions, one sweep, mixed form, the
+    SNR-24 injection of the 128 s grid.  The cost per iteration is the figure
+    of merit (the two runs integrate the same likelihood over different
+    coordinates)."""
+    import gwsynth
+    from paper_2607_28265_amd import prescreen as P
+    from paper_2607_28265_amd.nested import NestedSampler
+    cfg = gwsynth.CONFIGS["cfg2"]
+    prob = gwsynth.make_problem(cfg["duration"], cfg["f_min"], cfg["f_max"], psd_scale=1e-49)
+    th = gwsynth.prior_draws(gwsynth.SEEDS["injection"], 1)[0]
+    th_inj = P.library_injection(gw.Context, prob, th, snr=24.0)
+    out = {}
+    with gw.Context(prob) as ctx:
+        ctx.heterodyne_setup(th_inj, 5000)
+        gw.gw_set_sky_frame(ctx.handle, 1, 0, 1, False)
+        for name, marg in (("phase_time", gw.GW_MARG_PHASE_TIME), ("phase_distance", gw.GW_MARG_PHASE_DIST)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ns = NestedSampler(ctx, n_live=512, n_delete=64, seed=gwsynth.SEEDS["sampler"], like=gw.GW_HET,
+                               prec=gw.GW_PREC_MIXED, marg=marg)
+            r = ns.run()
+            wall = time.perf_counter() - t0
+            ns.close()
+            out[name] = {"wall_s": wall, "log_z": r["log_z"], "log_z_err": r["log_z_err"],
+                         "iterations": r["iterations"], "n_evals": r["n_evals"],
+                         "ms_per_iteration": 1e3 * wall / max(1, r["iterations"])}
+        gw.gw_set_sky_frame(ctx.handle, 0)
+    out["time_over_distance_per_iteration"] = (out["phase_time"]["ms_per_iteration"]
+                                               / out["phase_distance"]["ms_per_iteration"])
+    out["workload"] = ("nested sampling, heterodyned 5000-bin likelihood (mixed form) in the detector sky frame: "
+                       "512 live points, 64 deletions, one sweep, dlogz 0.1, SNR-24 injection on the 128 s grid; "
+                       "phase+time marginal (d_L sampled, 3273 grid points) against phase+distance marginal "
+                       "(t_c sampled)")
     return out
 
 
@@ -902,6 +943,9 @@ def main():
     if "nested" in legs:
         res["nested_sampling"] = nested_leg(gw, torch)
         log("nested-sampling leg done")
+    if "nested_tmarg" in legs:
+        res["nested_sampling_time_marginal"] = nested_tmarg_leg(gw, torch)
+        log("time-marginal nested-sampling leg done")
     if "nested_full" in legs:
         res["nested_sampling_full_band"] = nested_full_leg(gw, torch)
         log("full-band nested-sampling leg done")

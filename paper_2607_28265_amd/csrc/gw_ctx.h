@@ -106,7 +106,9 @@ gw_status launch_template(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n
 // ld = n), and, when mom is not NULL, the moment reduction on rows
 // fast_rows[0 .. counts[1]) (row p uses slot slot_of[p], or p / rows_per_slot
 // when slot_of is NULL), whose complete sums go to zfast[p][2 n_det] (rows
-// whose |t_c + dt_i| exceeds the cache's range get NaN).
+// whose |t_c + dt_i| exceeds the cache's range get NaN), or, when zfast is
+// NULL, into the same n_chunks partials as the full reduction (summed by the
+// epilogue like any other row).
 // launch_epilogue_cached combines partials (rows with zsrc[p] >= 0 take their
 // sums from zc[zsrc[p]]) and writes every row's sums to zrow when not NULL.
 // launch_wmom_build rebuilds the slots slots[i] >= 0, i < *count <= max_count,

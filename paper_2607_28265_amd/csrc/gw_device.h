@@ -394,12 +394,41 @@ __device__ inline double wave_sum(double s) {
   return s;
 }
 
+// FP32 term of the single-precision form below: I0 from the FP32 fits,
+// exp from the hardware 2^x; a = ln w - hh1 r2, x = |Z1| r1, B the bound.
+__device__ inline float dist_term_f32(double a, double x, double bmax) {
+  const float xf = (float)x;
+  float p;
+  double e;
+  if (xf <= 8.0f) {
+    const float sv = xf * xf * 0.015625f;
+    p = kI0Small[kI0SmallDeg];
+#pragma unroll
+    for (int k = kI0SmallDeg - 1; k >= 0; --k) p = fmaf(p, sv, kI0Small[k]);
+    e = a - bmax;
+  } else {
+    const float t = 8.0f * __builtin_amdgcn_rcpf(xf);
+    float q = kI0Large[kI0LargeDeg];
+#pragma unroll
+    for (int k = kI0LargeDeg - 1; k >= 0; --k) q = fmaf(q, t, kI0Large[k]);
+    p = q * __builtin_amdgcn_rsqf(xf);
+    e = (a + x) - bmax;
+  }
+  return __builtin_amdgcn_exp2f((float)(e * kLog2E)) * p;
+}
+
 // FP64 form: I0 by its power series in y = x^2/4 below x = 20 (40 terms) and
 // by the asymptotic series e^x / sqrt(2 pi x) sum_k c_k x^-k above (24 terms).
+// A term whose bound a + x lies more than 35 below B is at most e^-20 of the
+// sum (ln I0(x) >= x - 15 at the bound's maximiser, so the sum is at least
+// e^(B - 15)); such terms take the FP32 form (relative error below 4e-6, most
+// of it from the exponent rounded to FP32), which moves the sum by less than
+// n_dist e^-20 4e-6 of itself (1e-11 at 1000 grid points).  Lanes walk
+// consecutive grid points, so a wave mostly takes one form at a time.
 __device__ inline double wave_dist_lse(double z1, double hh1, const double* __restrict__ tab, int n_dist, int lane,
                                        const LogI0Consts& C) {
   const double bmax = wave_dist_bound(z1, hh1, tab, n_dist, lane);
-  const double cut = bmax - 60.0;
+  const double cut = bmax - 60.0, fine = bmax - 35.0;
   const double iz = z1 > 0.0 ? 1.0 / z1 : 0.0;
   const int tier = wave_i0_tier(z1, C);
   double s = 0.0;
@@ -409,6 +438,10 @@ __device__ inline double wave_dist_lse(double z1, double hh1, const double* __re
     const double a = fma(-hh1, r[2], r[3]);
     const double x = z1 * r[1];
     if (a + x < cut) continue;
+    if (a + x < fine) {
+      s += (double)dist_term_f32(a, x, bmax);
+      continue;
+    }
     double v, e;
     if (x < 20.0) {
       v = i0_series_tier(tier, 0.25 * x * x, C);

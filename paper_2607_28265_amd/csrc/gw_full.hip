@@ -347,6 +347,7 @@ __global__ void __launch_bounds__(256) k_full(const double* __restrict__ coef, i
 }
 
 constexpr int kWMom = 12;          // Chebyshev orders per block and detector
+static_assert(kWMom % 2 == 0, "the few-slot build reads the orders in pairs");
 constexpr int64_t kWBuildManyRows = 512;  // builds listing fewer slots use k_wmom_build_few
 constexpr double kTauCap = 0.25;    // largest |t_c + dt_i| (s) the moment cache is built for
 
@@ -536,17 +537,21 @@ __global__ void __launch_bounds__(64) k_wmom_build(const double* __restrict__ co
 // listed slots rebuild at a time; the work follows the device-side count.  A
 // unit is (block, group of kWBuildSlots listed slots), units ordered so that
 // neighbouring workgroups share a block (its records stay in L2); the grid
-// strides over the units.  Per unit the slots' phasors g_sk (one per slot and
-// bin, shared by the detectors; FP64 phase, FP64 or FP32 hardware sin/cos),
-// the block's projected data u_ik and its Chebyshev values T_m(t_k) go to LDS;
-// then lane (slot, detector, part) sums the moments over blk / Q bins of its
-// part (Q = min(16, blk) parts, FP64) from LDS alone, and the Q partial sums
-// are added by lane exchange in a fixed order.  Dynamic LDS:
-// blk (16 kWBuildSlots + 16 nd + 8 kWMom) bytes.
+// strides over the units.  Per unit: the group's phase coefficients go to
+// LDS (one load per thread), then thread k evaluates bin k's phasor for every
+// slot of the group (FP64 phase; FP64 or FP32 hardware sin/cos) and stages
+// the bin's projected data, all in LDS; lane (slot, detector, part) then sums
+// the moments over bins part, part + Q, ... (Q = min(16, blk) parts, FP64),
+// so that the 16 lanes of a (slot, detector) read 16 consecutive bins of each
+// LDS array (no bank conflicts), and the Q partial sums are added by lane
+// exchange in a fixed order.  The Chebyshev values are copied to LDS once per
+// workgroup, as pairs (T_2j, T_2j+1) per bin.  Dynamic LDS:
+// blk (16 kWBuildSlots + 16 nd + 8 kWMom) bytes + the coefficients.
 constexpr int kWBuildSlots = 4;
+constexpr int kWBuildCoef = 12;  // phase coefficients per slot
 
 inline size_t wmom_build_few_lds(int blk, int nd) {
-  return (size_t)blk * (16 * kWBuildSlots + 16 * nd + 8 * kWMom);
+  return (size_t)blk * (16 * kWBuildSlots + 16 * nd + 8 * kWMom) + 8 * kWBuildSlots * kWBuildCoef;
 }
 
 template <int PREC>
@@ -561,62 +566,73 @@ __global__ void __launch_bounds__(256) k_wmom_build_few(const double* __restrict
   extern __shared__ __attribute__((aligned(16))) double lds[];
   double2* g_lds = reinterpret_cast<double2*>(lds);   // [kWBuildSlots][blk]
   double* u_lds = lds + 2 * kWBuildSlots * blk;        // [blk][2 nd]
-  double* t_lds = u_lds + 2 * nd * blk;                // [blk][kWMom]
+  double2* t_lds = reinterpret_cast<double2*>(u_lds + 2 * nd * blk);  // [kWMom / 2][blk]
+  double* c_lds = u_lds + 2 * nd * blk + kWMom * blk;  // [kWBuildSlots][kWBuildCoef]
   const int cnt = *count;
   const int ngrp = (cnt + kWBuildSlots - 1) / kWBuildSlots;
   const int64_t units = (int64_t)n_blk * ngrp;
   if (units <= blockIdx.x) return;
   const int Q = blk < 16 ? blk : 16;  // power of two: parts per (slot, detector)
-  const int L = blk / Q;
   const int tid = threadIdx.x;
   const int part = tid % Q, combo = tid / Q;
   const int s_me = combo / nd, i_me = combo - (combo / nd) * nd;
   const bool lane_on = s_me < kWBuildSlots;  // Q kWBuildSlots nd <= 256 for nd <= 4
-  for (int e = tid; e < blk * kWMom; e += blockDim.x) t_lds[e] = basis[e];
-  int b_prev = -1;
+  constexpr int kCoefIdx[kWBuildCoef] = {C_A0, C_A2, C_A3, C_A4, C_A5, C_A6, C_A7, C_A10, C_A12, C_B5, C_B6, C_A0};
+  for (int e = tid; e < blk * (kWMom / 2); e += blockDim.x) {
+    const int j = e / blk, k = e - j * blk;
+    t_lds[e] = make_double2(basis[k * kWMom + 2 * j], basis[k * kWMom + 2 * j + 1]);
+  }
   for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
     const int b = (int)(unit / ngrp), grp = (int)(unit - (int64_t)b * ngrp);
     const int kb = b * blk;
     const int nbin = kb + blk < n_freq ? blk : n_freq - kb;
     __syncthreads();  // the previous unit's LDS contents are consumed
-    if (b != b_prev) {  // uniform: the block's projected data
-      for (int e = tid; e < nbin * 2 * nd; e += blockDim.x) {
-        const int k = e / (2 * nd), j = e - k * (2 * nd);
-        u_lds[e] = bins[(int64_t)(kb + k) * rs + 4 + j];
-      }
-      b_prev = b;
-    }
-    for (int e = tid; e < kWBuildSlots * blk; e += blockDim.x) {
-      const int s = e / blk, k = e - (e / blk) * blk;
+    if (tid < kWBuildSlots * kWBuildCoef) {
+      const int s = tid / kWBuildCoef, j = tid - s * kWBuildCoef;
       const int li = grp * kWBuildSlots + s;
-      double2 g = make_double2(0.0, 0.0);
-      if (li < cnt && k < nbin && slots[li] >= 0) {
+      double v = 0.0;
+      if (li < cnt && slots[li] >= 0 && j < 11) {
         const int64_t r = src ? (int64_t)src[li] : (int64_t)slots[li] * rows_per_slot;
-        PhaseCoef c;
-        c.a0 = coef[C_A0 * ld + r];
-        c.a2 = coef[C_A2 * ld + r];
-        c.a3 = coef[C_A3 * ld + r];
-        c.a4 = coef[C_A4 * ld + r];
-        c.a5 = coef[C_A5 * ld + r];
-        c.a6 = coef[C_A6 * ld + r];
-        c.a7 = coef[C_A7 * ld + r];
-        c.a8 = 0.0;  // the linear time term is applied per row
-        c.a10 = coef[C_A10 * ld + r];
-        c.a12 = coef[C_A12 * ld + r];
-        c.b5 = coef[C_B5 * ld + r];
-        c.b6 = coef[C_B6 * ld + r];
-        const double* rec = bins + (int64_t)(kb + k) * rs;
-        const double ph = phase_cycles(c, rec[0], rec[1], rec[2], rec[3]);
-        if (PREC == 0) {
-          double sn, cs;
-          sincos_cycles(ph, T, &sn, &cs);
-          g = make_double2(cs, -sn);
-        } else {
-          const float t = (float)(ph - rint(ph));
-          g = make_double2((double)__builtin_amdgcn_cosf(t), -(double)__builtin_amdgcn_sinf(t));
-        }
+        v = coef[kCoefIdx[j] * ld + r];
       }
-      g_lds[s * blk + k] = g;
+      c_lds[tid] = v;
+    }
+    __syncthreads();
+    for (int k = tid; k < blk; k += blockDim.x) {
+      const double* rec = bins + (int64_t)(kb + (k < nbin ? k : 0)) * rs;
+      const double x = rec[0], x2 = rec[1], xm5 = rec[2], lnf = rec[3];
+      for (int j = 0; j < 2 * nd; ++j) u_lds[k * 2 * nd + j] = k < nbin ? rec[4 + j] : 0.0;
+#pragma unroll
+      for (int s = 0; s < kWBuildSlots; ++s) {
+        const int li = grp * kWBuildSlots + s;
+        double2 g = make_double2(0.0, 0.0);
+        if (li < cnt && k < nbin && slots[li] >= 0) {
+          const double* cs = c_lds + s * kWBuildCoef;
+          PhaseCoef c;
+          c.a0 = cs[0];
+          c.a2 = cs[1];
+          c.a3 = cs[2];
+          c.a4 = cs[3];
+          c.a5 = cs[4];
+          c.a6 = cs[5];
+          c.a7 = cs[6];
+          c.a8 = 0.0;  // the linear time term is applied per row
+          c.a10 = cs[7];
+          c.a12 = cs[8];
+          c.b5 = cs[9];
+          c.b6 = cs[10];
+          const double ph = phase_cycles(c, x, x2, xm5, lnf);
+          if (PREC == 0) {
+            double sn, csn;
+            sincos_cycles(ph, T, &sn, &csn);
+            g = make_double2(csn, -sn);
+          } else {
+            const float t = (float)(ph - rint(ph));
+            g = make_double2((double)__builtin_amdgcn_cosf(t), -(double)__builtin_amdgcn_sinf(t));
+          }
+        }
+        g_lds[s * blk + k] = g;
+      }
     }
     __syncthreads();
     const int li = grp * kWBuildSlots + s_me;
@@ -625,17 +641,17 @@ __global__ void __launch_bounds__(256) k_wmom_build_few(const double* __restrict
 #pragma unroll
     for (int m = 0; m < kWMom; ++m) mr[m] = mi[m] = 0.0;
     if (sl >= 0) {
-      const int k1 = part * L;
-      const int k2 = k1 + L < nbin ? k1 + L : nbin;
-      for (int k = k1; k < k2; ++k) {
+      for (int k = part; k < nbin; k += Q) {
         const double2 g = g_lds[s_me * blk + k];
-        const double ur = u_lds[k * 2 * nd + 2 * i_me], ui = u_lds[k * 2 * nd + 2 * i_me + 1];
-        const double wr = ur * g.x - ui * g.y, wi = ur * g.y + ui * g.x;
-        const double* tq = t_lds + k * kWMom;
+        const double2 u = *reinterpret_cast<const double2*>(u_lds + k * 2 * nd + 2 * i_me);
+        const double wr = u.x * g.x - u.y * g.y, wi = u.x * g.y + u.y * g.x;
 #pragma unroll
-        for (int m = 0; m < kWMom; ++m) {
-          mr[m] = fma(tq[m], wr, mr[m]);
-          mi[m] = fma(tq[m], wi, mi[m]);
+        for (int j = 0; j < kWMom / 2; ++j) {
+          const double2 t = t_lds[j * blk + k];
+          mr[2 * j] = fma(t.x, wr, mr[2 * j]);
+          mi[2 * j] = fma(t.x, wi, mi[2 * j]);
+          mr[2 * j + 1] = fma(t.y, wr, mr[2 * j + 1]);
+          mi[2 * j + 1] = fma(t.y, wi, mi[2 * j + 1]);
         }
       }
     }
@@ -667,10 +683,13 @@ __global__ void __launch_bounds__(256) k_wmom_build_few(const double* __restrict
 // workgroup, slot slot_of[p] or p / rows_per_slot); the workgroup owns a chunk
 // of blocks that its waves split, their sums added in wave order; chunk
 // partials as k_full's ([chunk][2 ND][n]).  Each lane streams its slot's
-// moments, one 128-byte line per detector and block.
+// moments, 96 bytes per detector and block.  With n_out > n_chunks the
+// partials fill the first n_chunks of a layout of n_out chunks (that of the
+// full reduction of the same round) and the rest are written zero, so the
+// common epilogue sums them.
 template <int ND>
 __global__ void __launch_bounds__(256) k_wmom(const double* __restrict__ coef, int64_t ld, int64_t n, int64_t k0,
-                                              double df, int blk, int n_blk, int n_chunks, TrigConsts T,
+                                              double df, int blk, int n_blk, int n_chunks, int n_out, TrigConsts T,
                                               const int32_t* __restrict__ rows, const int32_t* __restrict__ count,
                                               int rows_per_slot, const int32_t* __restrict__ slot_of,
                                               const float2* __restrict__ mom, int64_t slot_f2,
@@ -754,6 +773,9 @@ __global__ void __launch_bounds__(256) k_wmom(const double* __restrict__ coef, i
       partial[((int64_t)chunk * 2 * ND + 2 * i) * n + p] = zr[i];
       partial[((int64_t)chunk * 2 * ND + 2 * i + 1) * n + p] = zi[i];
     }
+    for (int c = n_chunks + chunk; c < n_out; c += n_chunks)
+#pragma unroll
+      for (int j = 0; j < 2 * ND; ++j) partial[((int64_t)c * 2 * ND + j) * n + p] = 0.0;
   }
 }
 
@@ -1462,14 +1484,13 @@ gw_status launch_epilogue_z(gw_ctx* ctx, double* partial, int n_chunks, const do
                      ld, n, ctx->dd, marg, C, logl, zbuf, zsrc, zc, zrow);
   gw_status s = check_hip(hipGetLastError(), "epilogue launch");
   if (s != GW_OK || marg != 2) return s;
-  if (n >= kDistSliced) {
+  // large mixed batches: lane = row (grid records shared by 64 rows); FP64 at
+  // every size and small batches: wave = row (the FP64 form's FP32 tier then
+  // covers most terms, see wave_dist_lse)
+  if (n >= kDistSliced && prec == GW_PREC_MIXED) {
     const int64_t dblocks = (n + 63) / 64;
-    if (prec == GW_PREC_MIXED)
-      hipLaunchKernelGGL(k_dist_marg<1>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, zbuf, n,
-                         ctx->dist_tab, ctx->n_dist, ctx->dd, C, logl);
-    else
-      hipLaunchKernelGGL(k_dist_marg<0>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, zbuf, n,
-                         ctx->dist_tab, ctx->n_dist, ctx->dd, C, logl);
+    hipLaunchKernelGGL(k_dist_marg<1>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, zbuf, n,
+                       ctx->dist_tab, ctx->n_dist, ctx->dd, C, logl);
   } else {
     const int64_t dblocks = (n + 3) / 4;
     if (prec == GW_PREC_MIXED)
@@ -1528,11 +1549,11 @@ static gw_status launch_cached_nd(gw_ctx* ctx, const double* coef, int64_t n, in
   if (cm > 8) cm = cm / 8 * 8;
   const int slot = prof_begin(ctx, st, 1);
   hipLaunchKernelGGL((k_wmom<ND>), dim3((unsigned)(nptile * cm)), dim3(256), 0, st, coef, n, n, ctx->geom.k0,
-                     ctx->geom.df, blk, n_blk, cm, T, fast_rows, counts + 1, rows_per_slot, slot_of, mom,
-                     wmom_slot_f2(ctx), partial);
+                     ctx->geom.df, blk, n_blk, cm, zfast ? cm : n_chunks, T, fast_rows, counts + 1, rows_per_slot,
+                     slot_of, mom, wmom_slot_f2(ctx), partial);
   prof_end(ctx, slot, st);
   s = check_hip(hipGetLastError(), "cached-waveform kernel launch");
-  if (s != GW_OK) return s;
+  if (s != GW_OK || !zfast) return s;  // without zfast the epilogue sums the fast rows' partials
   hipLaunchKernelGGL(k_wmom_sum, dim3((unsigned)((n * 2 * ND + 255) / 256)), dim3(256), 0, st, partial, cm, ND, n,
                      fast_rows, counts + 1, zfast);
   return check_hip(hipGetLastError(), "cached-waveform sum launch");

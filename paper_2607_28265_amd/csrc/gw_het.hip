@@ -749,12 +749,12 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
                        marg, hc, C);
   s = check_hip(hipGetLastError(), "heterodyne combine launch");
   if (s != GW_OK || marg != 2) return s;
+  // large mixed batches: lane = row (grid records shared by 64 rows); FP64
+  // at every size and small batches: wave = row, consecutive grid points per
+  // wave, where the FP64 form takes most terms in its FP32 tier
   const bool sliced = h->n_rows_last >= kDistRowsPerLane;
   if (sliced && prec == GW_PREC_MIXED)
     hipLaunchKernelGGL(k_het_dist<1>, dim3(256 * 8), dim3(64 * kHetDistWaves), 0, st, h->args, h->tile_pre,
-                       ctx->dist_tab, ctx->n_dist, ctx->dd, ctx->i0c);
-  else if (sliced)
-    hipLaunchKernelGGL(k_het_dist<0>, dim3(256 * 8), dim3(64 * kHetDistWaves), 0, st, h->args, h->tile_pre,
                        ctx->dist_tab, ctx->n_dist, ctx->dd, ctx->i0c);
   else if (prec == GW_PREC_MIXED)
     hipLaunchKernelGGL(k_het_dist_w<1>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,

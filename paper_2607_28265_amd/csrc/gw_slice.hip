@@ -494,7 +494,7 @@ __global__ void __launch_bounds__(1024) k_sweep_lists(const SweepParams* __restr
   for (int64_t r0 = 0; r0 < n; r0 += 1024) {
     const int64_t r = r0 + threadIdx.x;
     const int kd = r < n ? S.rkind[r] : 0;
-    if (r < n) S.zsrc[r] = kd == 3 ? (int32_t)(r >> 1) : kd == 2 ? (int32_t)(D->k + r) : -1;
+    if (r < n) S.zsrc[r] = kd == 3 ? (int32_t)(r >> 1) : -1;  // cached-waveform rows sum their partials
     const uint64_t m1 = __ballot(kd == 1), m2 = __ballot(kd == 2);
     if (lane == 0) {
       tot[0][wave] = __popcll(m1);
@@ -652,7 +652,7 @@ static gw_status eval_rows(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const SweepC
   if (s == GW_OK) s = launch_prologue(ctx, ws->cand, n, a.marg, ctx->coef, n, st);
   if (s == GW_OK)
     s = launch_cached(ctx, ctx->coef, n, a.prec, tpb, nch, ws->S.slow_rows, ws->S.stream_rows, ws->S.counts, 2,
-                      nullptr, a.cache ? ws->wc : nullptr, ws->S.zc + k * 2 * ctx->n_det, ctx->partial, st);
+                      nullptr, a.cache ? ws->wc : nullptr, nullptr, ctx->partial, st);
   if (s == GW_OK)
     s = launch_epilogue_cached(ctx, ctx->partial, nch, ctx->coef, n, n, a.marg, a.prec, ws->cand_logl, ws->S.zsrc,
                                ws->S.zc, ws->S.zrow, st);

@@ -289,3 +289,28 @@ def test_wcache_slot_rules():
         with pytest.raises(gw.GwError):
             cache.loglike(torch.from_numpy(th).cuda(), torch.tensor([0, 0], dtype=torch.int32, device="cuda"), 3)
         cache.close()
+
+
+def test_wcache_large_update_matches_oracle():
+    # an update of 600 slots builds them with one lane per slot (the kernel
+    # for large lists), 24 slots with the kernel whose work follows the
+    # count; moved rows on either agree with the oracle to the FP32 tolerance
+    import paper_2607_28265_amd as gw
+    from tests.gpu_common import oracle_many
+    prob = problem("cfg1", loud=True)
+    n_big, n_small = 600, 24
+    base = _base_thetas(prob, n_big, 41)
+    rng = np.random.default_rng(42)
+    pick = np.arange(0, n_big, n_big // n_small)[:n_small]
+    th = _moved(base[pick], 1, rng)
+    ref = oracle_many(th, prob, 2)
+    with gw.Context(prob) as ctx:
+        for n_slots, rows in ((n_big, pick), (n_small, np.arange(n_small))):
+            cache = gw.WaveformCache(ctx.handle, n_slots)
+            src = base if n_slots == n_big else base[pick]
+            cache.update(torch.from_numpy(src).cuda(), torch.arange(n_slots, dtype=torch.int32, device="cuda"))
+            got = cache.loglike(torch.from_numpy(th).cuda(), torch.from_numpy(rows.astype(np.int32)).cuda(), 1)
+            err = np.max(np.abs(got.cpu().numpy() - ref))
+            print(f"{n_slots} slots: kind 1 on {len(rows)} rows, max |dlogL| vs oracle {err:.2e}")
+            assert err < 1e-5
+            cache.close()
