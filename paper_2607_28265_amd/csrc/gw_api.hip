@@ -215,6 +215,7 @@ gw_status gw_ctx_create(const gw_problem* pr, int32_t device, gw_ctx** out) {
   if (st == GW_OK) {
     LogI0Consts c = make_log_i0_consts();
     c.r1max = ctx->dist_r1max;
+    for (double dj : ctx->h_dist_grid) c.dmax = fmax(c.dmax, dj);
     st = check_hip(hipMalloc((void**)&ctx->i0c, sizeof(LogI0Consts)), "ln I0 table alloc");
     if (st == GW_OK) st = check_hip(hipMemcpy(ctx->i0c, &c, sizeof(c), hipMemcpyHostToDevice), "ln I0 table copy");
   }

@@ -150,7 +150,8 @@ gw_status calibrate_phasor(gw_ctx* ctx);
 // t_j = j delta / R, |j| <= jmax.
 constexpr int kTgHMax = 48;  // most norm moments of the heterodyned form
 struct TGridArgs {
-  const double* mom;
+  const double* mom;   // complex moment (row p, order m, block b) at p rs + (m n_blk + b) es
+  int64_t mom_rs, mom_es;  // (K n_blk, 1): row-major, one row's moments contiguous; (1, n): row fastest
   int64_t n;
   int n_blk, L, jmax, K;
   const double* coef;  // prologue coefficients of the n rows (stride ld)

@@ -278,15 +278,16 @@ __device__ inline void sincos_cycles(double r, const TrigConsts& T, double* s_ou
 // large-argument expansion I0(x) ~ e^x / sqrt(2 pi x) sum_k c_k x^-k with
 // c_k = ((2k-1)!!)^2 / (k! 8^k) (Abramowitz & Stegun 9.7.1), Horner in
 // u = 1/x with 24 terms (the terms still decrease there; truncation below
-// 1e-16).  Kernels take the coefficients as an argument.
-struct LogI0Consts {
+// 1e-16).  The coefficients are compile-time constants, so the kernels take
+// them as scalar operands: loaded from memory inside the distance loops, 64
+// of them cost a 64-lane load each per grid point.
+struct I0Coefs {
   double ser[40];
   double asy[24];
-  double r1max;  // largest 1/d of the distance grid (bounds x = |Z1| / d); 0 if unknown
 };
 
-__host__ __device__ inline LogI0Consts make_log_i0_consts() {
-  LogI0Consts c;
+constexpr I0Coefs make_i0_coefs() {
+  I0Coefs c{};
   double f = 1.0;
   for (int k = 0; k < 40; ++k) {
     if (k > 0) f *= (double)k;
@@ -297,17 +298,68 @@ __host__ __device__ inline LogI0Consts make_log_i0_consts() {
     if (k > 0) a *= (double)(2 * k - 1) * (double)(2 * k - 1) / (8.0 * k);
     c.asy[k] = a;
   }
+  return c;
+}
+
+constexpr I0Coefs kI0 = make_i0_coefs();
+
+// Per-context constants of the distance marginal (kernels take them by
+// device pointer).
+struct LogI0Consts {
+  double r1max;  // largest 1/d of the distance grid (bounds x = |Z1| / d); 0 if unknown
+  double dmax;   // largest d of the grid (bounds u = 1/x = d / |Z1|); 0 if unknown
+};
+
+__host__ __device__ inline LogI0Consts make_log_i0_consts() {
+  LogI0Consts c;
   c.r1max = 0.0;
+  c.dmax = 0.0;
+  return c;
+}
+
+// A compile-time constant placed in a scalar register pair where it is used:
+// the empty asm keeps the compiler from hoisting the 64 coefficients of the
+// distance loops into vector registers (where each Horner step then costs a
+// move and a multiply-add) or from loading them from memory.
+__device__ inline double sgpr_const(double c) {
+  asm volatile("" : "+s"(c));
   return c;
 }
 
 // Power series of I0 in y = x^2 / 4 truncated after K terms (Horner).
 template <int K>
-__device__ inline double i0_series(double y, const LogI0Consts& C) {
-  double p = C.ser[K - 1];
+__device__ inline double i0_series(double y) {
+  double p = sgpr_const(kI0.ser[K - 1]);
 #pragma unroll
-  for (int k = K - 2; k >= 0; --k) p = fma(p, y, C.ser[k]);
+  for (int k = K - 2; k >= 0; --k) p = fma(p, y, sgpr_const(kI0.ser[k]));
   return p;
+}
+
+// Large-argument series sum_k c_k u^k truncated after K terms (Horner).
+template <int K>
+__device__ inline double i0_asym_k(double u) {
+  double p = sgpr_const(kI0.asy[K - 1]);
+#pragma unroll
+  for (int k = K - 2; k >= 0; --k) p = fma(p, u, sgpr_const(kI0.asy[k]));
+  return p;
+}
+
+__device__ inline double i0_asym(double u) { return i0_asym_k<24>(u); }
+
+// Series length for every u <= umax: the first dropped term c_K u^K is below
+// 1e-17 for K = 10, 13, 16 up to u = 0.01, 0.02, 0.03 (x >= 100, 50, 33);
+// otherwise the full 24 terms (below 1e-16 at u = 0.05, x = 20).
+__device__ inline int asym_tier(double umax) {
+  return umax <= 0.01 ? 0 : (umax <= 0.02 ? 1 : (umax <= 0.03 ? 2 : 3));
+}
+
+__device__ inline double i0_asym_tier(int tier, double u) {
+  switch (tier) {
+    case 0: return i0_asym_k<10>(u);
+    case 1: return i0_asym_k<13>(u);
+    case 2: return i0_asym_k<16>(u);
+    default: return i0_asym_k<24>(u);
+  }
 }
 
 // Series length for every y <= ymax: the first dropped term y^K / (K!)^2 is
@@ -317,13 +369,13 @@ __device__ inline int i0_tier(double ymax) {
   return ymax <= 0.106 ? 0 : (ymax <= 1.07 ? 1 : (ymax <= 4.0 ? 2 : (ymax <= 18.8 ? 3 : 4)));
 }
 
-__device__ inline double i0_series_tier(int tier, double y, const LogI0Consts& C) {
+__device__ inline double i0_series_tier(int tier, double y) {
   switch (tier) {
-    case 0: return i0_series<8>(y, C);
-    case 1: return i0_series<12>(y, C);
-    case 2: return i0_series<16>(y, C);
-    case 3: return i0_series<24>(y, C);
-    default: return i0_series<40>(y, C);
+    case 0: return i0_series<8>(y);
+    case 1: return i0_series<12>(y);
+    case 2: return i0_series<16>(y);
+    case 3: return i0_series<24>(y);
+    default: return i0_series<40>(y);
   }
 }
 
@@ -338,21 +390,26 @@ __device__ inline int wave_i0_tier(double z1, const LogI0Consts& C) {
   return __builtin_amdgcn_readfirstlane(i0_tier(y));
 }
 
+// Wave-uniform tier of the large-argument series for u = d / z1 up to
+// dmax / z1 (only arguments x >= 20, u <= 0.05, take that series).
+__device__ inline int wave_asym_tier(double z1, const LogI0Consts& C) {
+  if (!(C.dmax > 0.0)) return 3;
+  double u = z1 > 0.0 ? C.dmax / z1 : 1.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) u = fmax(u, __shfl_xor(u, o, 64));
+  return __builtin_amdgcn_readfirstlane(asym_tier(u));
+}
+
 // ln I0(x) given x and u = 1/x (u is only used when x >= 20).
-__device__ inline double log_i0_xu(double x, double u, const LogI0Consts& C) {
+__device__ inline double log_i0_xu(double x, double u) {
   double arg, base, scale;
   if (x < 20.0) {
     const double y = 0.25 * x * x;
-    double p = C.ser[39];
-#pragma unroll
-    for (int k = 38; k >= 0; --k) p = fma(p, y, C.ser[k]);
-    arg = p;
+    arg = i0_series<40>(y);
     base = 0.0;
     scale = 1.0;
   } else {
-    double p = C.asy[23];
-#pragma unroll
-    for (int k = 22; k >= 0; --k) p = fma(p, u, C.asy[k]);
+    const double p = i0_asym(u);
     // x - ln(2 pi x)/2 + ln p = x + ln(p^2 u / (2 pi)) / 2
     arg = p * p * u * kInvTwoPi;
     base = x;
@@ -361,8 +418,8 @@ __device__ inline double log_i0_xu(double x, double u, const LogI0Consts& C) {
   return fma(scale, log(arg), base);
 }
 
-__device__ inline double log_i0(double x, const LogI0Consts& C) {
-  return log_i0_xu(x, x >= 20.0 ? 1.0 / x : 0.0, C);
+__device__ inline double log_i0(double x) {
+  return log_i0_xu(x, x >= 20.0 ? 1.0 / x : 0.0);
 }
 
 // Distance marginal over a grid, evaluated by one wave for one proposal:
@@ -430,10 +487,9 @@ __device__ inline double wave_dist_lse(double z1, double hh1, const double* __re
   const double bmax = wave_dist_bound(z1, hh1, tab, n_dist, lane);
   const double cut = bmax - 60.0, fine = bmax - 35.0;
   const double iz = z1 > 0.0 ? 1.0 / z1 : 0.0;
-  const int tier = wave_i0_tier(z1, C);
+  const int tier = wave_i0_tier(z1, C), atier = wave_asym_tier(z1, C);
   double s = 0.0;
   for (int j = lane; j < n_dist; j += 64) {
-    asm volatile("" ::: "memory");  // coefficient loads stay in the loop (see slice_dist_sum)
     const double* r = tab + 4 * j;
     const double a = fma(-hh1, r[2], r[3]);
     const double x = z1 * r[1];
@@ -444,13 +500,11 @@ __device__ inline double wave_dist_lse(double z1, double hh1, const double* __re
     }
     double v, e;
     if (x < 20.0) {
-      v = i0_series_tier(tier, 0.25 * x * x, C);
+      v = i0_series_tier(tier, 0.25 * x * x);
       e = a - bmax;
     } else {
       const double u = r[0] * iz;  // 1 / x
-      double p = C.asy[23];
-#pragma unroll
-      for (int k = 22; k >= 0; --k) p = fma(p, u, C.asy[k]);
+      const double p = i0_asym_tier(atier, u);
       v = p * sqrt(u * kInvTwoPi);
       e = (a + x) - bmax;
     }
@@ -511,31 +565,30 @@ __device__ inline double slice_dist_bound(double z1, double hh1, const double* _
   return bmax;
 }
 
-// sum_j exp(t_j - bmax) over the slice (FP64 form).
+// sum_j exp(t_j - bmax) over the slice (FP64 form; terms more than 35
+// below the bound in FP32, as in wave_dist_lse).
 __device__ inline double slice_dist_sum(double z1, double hh1, double bmax, const double* __restrict__ tab, int j0,
                                         int j1, const LogI0Consts& C) {
-  const double cut = bmax - 60.0;
+  const double cut = bmax - 60.0, fine = bmax - 35.0;
   const double iz = z1 > 0.0 ? 1.0 / z1 : 0.0;
-  const int tier = wave_i0_tier(z1, C);
+  const int tier = wave_i0_tier(z1, C), atier = wave_asym_tier(z1, C);
   double s = 0.0;
   for (int j = j0; j < j1; ++j) {
-    // Keeps the series coefficients' loads in the loop: hoisted, the 64
-    // doubles exceed the scalar registers and spill into vector lanes, read
-    // back lane by lane at every use.
-    asm volatile("" ::: "memory");
     const double* r = tab + 4 * j;
     const double a = fma(-hh1, r[2], r[3]);
     const double x = z1 * r[1];
     if (a + x < cut) continue;
+    if (a + x < fine) {
+      s += (double)dist_term_f32(a, x, bmax);
+      continue;
+    }
     double v, e;
     if (x < 20.0) {
-      v = i0_series_tier(tier, 0.25 * x * x, C);
+      v = i0_series_tier(tier, 0.25 * x * x);
       e = a - bmax;
     } else {
       const double u = r[0] * iz;  // 1 / x
-      double p = C.asy[23];
-#pragma unroll
-      for (int k = 22; k >= 0; --k) p = fma(p, u, C.asy[k]);
+      const double p = i0_asym_tier(atier, u);
       v = p * sqrt(u * kInvTwoPi);
       e = (a + x) - bmax;
     }

@@ -1044,10 +1044,9 @@ __global__ void __launch_bounds__(256) k_full_mfma(const double* __restrict__ co
 // group length after k_partial_reduce).
 __global__ void __launch_bounds__(1024) k_epilogue(const double* __restrict__ partial, int n_chunks, int cstride,
                                                   int nd, const double* __restrict__ coef, int64_t ld, int64_t n,
-                                                  double dd, int marg, const LogI0Consts* __restrict__ Cp, double* __restrict__ logl,
+                                                  double dd, int marg, double* __restrict__ logl,
                                                   double* __restrict__ zbuf, const int32_t* __restrict__ zsrc,
                                                   const double* __restrict__ zc, double* __restrict__ zrow) {
-  const LogI0Consts& C = *Cp;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t p = (int64_t)blockIdx.x * 64 + lane;
@@ -1109,7 +1108,7 @@ __global__ void __launch_bounds__(1024) k_epilogue(const double* __restrict__ pa
   } else if (marg == 0) {
     out = -0.5 * dd + plain - 0.5 * hh;
   } else {
-    out = -0.5 * dd - 0.5 * hh + log_i0(sqrt(Zr * Zr + Zi * Zi), C);
+    out = -0.5 * dd - 0.5 * hh + log_i0(sqrt(Zr * Zr + Zi * Zi));
   }
   logl[p] = out;
 }
@@ -1481,16 +1480,19 @@ gw_status launch_epilogue_z(gw_ctx* ctx, double* partial, int n_chunks, const do
     if (s != GW_OK) return s;
   }
   hipLaunchKernelGGL(k_epilogue, dim3((unsigned)blocks), dim3(1024), 0, st, partial, groups, cstride, ctx->n_det, coef,
-                     ld, n, ctx->dd, marg, C, logl, zbuf, zsrc, zc, zrow);
+                     ld, n, ctx->dd, marg, logl, zbuf, zsrc, zc, zrow);
   gw_status s = check_hip(hipGetLastError(), "epilogue launch");
   if (s != GW_OK || marg != 2) return s;
-  // large mixed batches: lane = row (grid records shared by 64 rows); FP64 at
-  // every size and small batches: wave = row (the FP64 form's FP32 tier then
-  // covers most terms, see wave_dist_lse)
-  if (n >= kDistSliced && prec == GW_PREC_MIXED) {
+  // large batches: lane = row (grid records are scalar loads shared by 64
+  // rows); small batches: wave = row
+  if (n >= kDistSliced) {
     const int64_t dblocks = (n + 63) / 64;
-    hipLaunchKernelGGL(k_dist_marg<1>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, zbuf, n,
-                       ctx->dist_tab, ctx->n_dist, ctx->dd, C, logl);
+    if (prec == GW_PREC_MIXED)
+      hipLaunchKernelGGL(k_dist_marg<1>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, zbuf, n,
+                         ctx->dist_tab, ctx->n_dist, ctx->dd, C, logl);
+    else
+      hipLaunchKernelGGL(k_dist_marg<0>, dim3((unsigned)dblocks), dim3(64 * kDistWaves), 0, st, zbuf, n,
+                         ctx->dist_tab, ctx->n_dist, ctx->dd, C, logl);
   } else {
     const int64_t dblocks = (n + 3) / 4;
     if (prec == GW_PREC_MIXED)

@@ -436,8 +436,7 @@ __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, con
 // plain or phase-marginalised epilogue (or stage |Z_1| and <h|h>_1 for the
 // distance marginal).
 __device__ inline void het_finish_row(const HetArgs* __restrict__ ab, int64_t row, int nd, int marg,
-                                      const double* zr, const double* zi, const double* hh, const HetConst& hc,
-                                      const LogI0Consts& C) {
+                                      const double* zr, const double* zi, const double* hh, const HetConst& hc) {
   const int64_t ld = ab->ld;
   const double* cf = ab->coef + row;
   double Zr = 0.0, Zi = 0.0, plain = 0.0, hht = 0.0;
@@ -466,7 +465,7 @@ __device__ inline void het_finish_row(const HetArgs* __restrict__ ab, int64_t ro
     double out;
     if (!valid) out = -INFINITY;
     else if (marg == 0) out = -0.5 * hc.dd + plain - 0.5 * hht;
-    else out = -0.5 * hc.dd - 0.5 * hht + log_i0(zabs, C);
+    else out = -0.5 * hc.dd - 0.5 * hht + log_i0(zabs);
     ab->logl[row] = out;
   }
 }
@@ -474,8 +473,7 @@ __device__ inline void het_finish_row(const HetArgs* __restrict__ ab, int64_t ro
 // Large batches: one lane per row (coalesced over rows), the edge-chunk
 // partials summed in chunk order.
 __global__ void __launch_bounds__(256) k_het_combine(const HetArgs* __restrict__ ab, const int64_t* __restrict__ pre,
-                                                     int nd, int n_ech, int marg, HetConst hc, const LogI0Consts* __restrict__ Cp) {
-  const LogI0Consts& C = *Cp;
+                                                     int nd, int n_ech, int marg, HetConst hc) {
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
@@ -497,7 +495,7 @@ __global__ void __launch_bounds__(256) k_het_combine(const HetArgs* __restrict__
         hh[i] += p[2 * ld];
       }
     }
-    het_finish_row(ab, row, nd, marg, zr, zi, hh, hc, C);
+    het_finish_row(ab, row, nd, marg, zr, zi, hh, hc);
   }
 }
 
@@ -506,8 +504,7 @@ __global__ void __launch_bounds__(256) k_het_combine(const HetArgs* __restrict__
 // loads of a row are issued together instead of one chain per thread.
 __global__ void __launch_bounds__(256) k_het_combine_w(const HetArgs* __restrict__ ab,
                                                        const int64_t* __restrict__ pre, int nd, int n_ech, int marg,
-                                                       HetConst hc, const LogI0Consts* __restrict__ Cp) {
-  const LogI0Consts& C = *Cp;
+                                                       HetConst hc) {
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
@@ -538,7 +535,7 @@ __global__ void __launch_bounds__(256) k_het_combine_w(const HetArgs* __restrict
       zi[i] = b;
       hh[i] = c;
     }
-    if (lane == 0) het_finish_row(ab, row, nd, marg, zr, zi, hh, hc, C);
+    if (lane == 0) het_finish_row(ab, row, nd, marg, zr, zi, hh, hc);
   }
 }
 
@@ -740,21 +737,22 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
     hc.hh0[i] = h->hh0[i];
   }
   hc.dd = ctx->dd;
-  const LogI0Consts* C = ctx->i0c;  // device copy, r1max from the distance grid
   if (h->n_rows_last < kDistRowsPerLane && n_ech <= 64)
     hipLaunchKernelGGL(k_het_combine_w, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->n_det, n_ech,
-                       marg, hc, C);
+                       marg, hc);
   else
     hipLaunchKernelGGL(k_het_combine, dim3(256 * 4), dim3(256), 0, st, h->args, h->tile_pre, ctx->n_det, n_ech,
-                       marg, hc, C);
+                       marg, hc);
   s = check_hip(hipGetLastError(), "heterodyne combine launch");
   if (s != GW_OK || marg != 2) return s;
-  // large mixed batches: lane = row (grid records shared by 64 rows); FP64
-  // at every size and small batches: wave = row, consecutive grid points per
-  // wave, where the FP64 form takes most terms in its FP32 tier
+  // large batches: lane = row (grid records are scalar loads shared by 64
+  // rows); small batches: wave = row
   const bool sliced = h->n_rows_last >= kDistRowsPerLane;
   if (sliced && prec == GW_PREC_MIXED)
     hipLaunchKernelGGL(k_het_dist<1>, dim3(256 * 8), dim3(64 * kHetDistWaves), 0, st, h->args, h->tile_pre,
+                       ctx->dist_tab, ctx->n_dist, ctx->dd, ctx->i0c);
+  else if (sliced)
+    hipLaunchKernelGGL(k_het_dist<0>, dim3(256 * 8), dim3(64 * kHetDistWaves), 0, st, h->args, h->tile_pre,
                        ctx->dist_tab, ctx->n_dist, ctx->dd, ctx->i0c);
   else if (prec == GW_PREC_MIXED)
     hipLaunchKernelGGL(k_het_dist_w<1>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->dist_tab,
@@ -818,7 +816,8 @@ void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech)
 // Edge-weight moments of one (64-row tile, edge chunk): lane = row, the
 // chunk's edges in order (edge records and tables wave-uniform).  what = 0:
 // the K block moments of W for every block of the chunk into mom
-// [rows][K][n_blk]; what = 1: S_m, m0 <= m < m0 + K (m < mh), over the
+// [K][n_blk][rows] (rows fastest, so the stores of a wave are contiguous);
+// what = 1: S_m, m0 <= m < m0 + K (m < mh), over the
 // chunk's edges into hpart [chunk][rows][mh]; chunk 0 also writes the
 // constant norm part hhc [rows].
 template <int ND, int PREC, int K, int WHAT>
@@ -907,10 +906,10 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
     for (int b = b_lo; b < b_hi; ++b) {
       const int be = bs[b + 1];
       for (; e < be; ++e) edge(e);
-      if (p < n) {
-        double2* out = mom + p * K * n_blk + b;
+      if (p < n) {  // rows fastest: a wave's 64 rows store 1 KB contiguously
+        double2* out = mom + (int64_t)b * n + p;
 #pragma unroll
-        for (int m = 0; m < K; ++m) out[(int64_t)m * n_blk] = make_double2(ar_[m], ai_[m]);
+        for (int m = 0; m < K; ++m) out[(int64_t)m * n_blk * n] = make_double2(ar_[m], ai_[m]);
       }
 #pragma unroll
       for (int m = 0; m < K; ++m) ar_[m] = ai_[m] = 0.0;
@@ -954,14 +953,15 @@ static void launch_het_tmom_nd(gw_ctx* ctx, const double* coef, int64_t ld, int6
     launch_het_tmom_k<ND, 16>(ctx, coef, ld, n, prec, hc, what, m0, mom, hpart, hhc, st);
 }
 
-// Edge chunks of the moment kernel: whole blocks, about n_edges / want edges
-// each, want chosen for about 4096 (tile, chunk) waves (at most 64 chunks), or
-// fixed by gw_set_het_tm_split.
-static int het_tm_chunks(const gw_ctx* ctx, int64_t n) {
+// Edge chunks of the moment kernel: whole blocks of about equal cost (an
+// edge or a block's moment stores count one unit each), the count chosen for
+// about 4096 (tile, chunk) waves (at most 256 chunks, each of at least 8
+// units), or fixed by gw_set_het_tm_split.
+static int het_tm_chunks(const gw_ctx* ctx, int64_t n, int n_blk) {
   if (ctx->tm_nsk > 0) return ctx->tm_nsk;
   const int64_t tiles = (n + 63) / 64;
   int64_t want = (4096 + tiles - 1) / tiles;
-  const int64_t most = std::max<int64_t>(1, std::min<int64_t>(64, ctx->het->n_edges / 8));
+  const int64_t most = std::max<int64_t>(1, std::min<int64_t>(256, (ctx->het->n_edges + n_blk) / 8));
   return (int)std::max<int64_t>(1, std::min(want, most));
 }
 
@@ -1012,11 +1012,13 @@ static gw_status het_tm_tables(gw_ctx* ctx, int blk, int n_blk, double umax, int
     }
   }
   for (int b = 0; b < n_blk; ++b) bs[b + 1] += bs[b];
-  // chunks of whole blocks with about ne / nch edges each
+  // chunks of whole blocks of about (ne + n_blk) / nch cost units each, an
+  // edge and a block's moment stores one unit each (blocks before b cost
+  // bs[b] + b)
   std::vector<int32_t> cb(1, 0);
-  const double per = (double)ne / nch;
+  const double per = (double)(ne + n_blk) / nch;
   for (int b = 1; b < n_blk && (int)cb.size() < nch; ++b)
-    if (bs[b] >= per * (double)cb.size() && bs[b] > bs[cb.back()]) cb.push_back(b);
+    if ((double)(bs[b] + b) >= per * (double)cb.size()) cb.push_back(b);
   cb.push_back(n_blk);
   std::vector<int32_t> idx(bs);
   idx.insert(idx.end(), cb.begin(), cb.end());
@@ -1057,13 +1059,13 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
   if (s == GW_OK) s = tgrid_tables(ctx, g.L, g.jmax, K);
   const int64_t chunk = tgrid_chunk_rows(n, g.n_blk, K);
   // edge chunks sized for the rows of one launch
-  const int nch = het_tm_chunks(ctx, chunk);
+  const int nch = het_tm_chunks(ctx, chunk, g.n_blk);
   const double umax = (double)g.jmax / ((double)g.N * (double)g.R);
   if (s == GW_OK) s = het_tm_tables(ctx, g.blk, g.n_blk, umax, nch, K);
   if (s != GW_OK) return s;
   const int mh = h->tm_mh;
   // workspace: coefficients for all rows; per row chunk the moments
-  // [rows][16][n_blk], the norm moments [n_ch][rows][mh] and hhc [rows]
+  // [K][n_blk][rows] (rows fastest), the norm moments [n_ch][rows][mh] and hhc [rows]
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
   if (s == GW_OK)
     s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap,
@@ -1101,6 +1103,8 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
     prof_end(ctx, prof, st);
     TGridArgs a{};
     a.mom = (const double*)mom;
+    a.mom_rs = 1;  // k_het_tmom writes rows fastest
+    a.mom_es = cn;
     a.n = cn;
     a.n_blk = g.n_blk;
     a.L = g.L;
@@ -1369,8 +1373,8 @@ gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid, i
 
 gw_status gw_set_het_tm_split(gw_ctx* ctx, int32_t n_chunks) {
   if (!ctx) return set_error(GW_EINVAL, "gw_set_het_tm_split: ctx is NULL");
-  if (n_chunks < 0 || n_chunks > 32 || (n_chunks & (n_chunks - 1)) != 0)
-    return set_error(GW_EINVAL, "gw_set_het_tm_split: n_chunks must be 0 or a power of two up to 32");
+  if (n_chunks < 0 || n_chunks > 256 || (n_chunks & (n_chunks - 1)) != 0)
+    return set_error(GW_EINVAL, "gw_set_het_tm_split: n_chunks must be 0 or a power of two up to 256");
   ctx->tm_nsk = n_chunks;
   return GW_OK;
 }

@@ -88,10 +88,9 @@ __global__ void __launch_bounds__(256) k_recon_stage(const double* __restrict__ 
 // d_L is the sample's own (phase marginal); NaN and -1 for unphysical rows.
 __global__ void __launch_bounds__(256) k_recon(const double* __restrict__ zc3, int64_t n,
                                                const double* __restrict__ theta, const double* __restrict__ tab,
-                                               int n_dist, int marg, int n_phase, const LogI0Consts* __restrict__ Cp,
+                                               int n_dist, int marg, int n_phase,
                                                const double* __restrict__ uni, double* __restrict__ out,
                                                int32_t* __restrict__ idx) {
-  const LogI0Consts& C = *Cp;
   const int lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (p >= n) return;  // wave-uniform
@@ -113,7 +112,7 @@ __global__ void __launch_bounds__(256) k_recon(const double* __restrict__ zc3, i
     const double za = sqrt(zr * zr + zi * zi);
     auto lw = [&](int q) {
       const double* r = tab + 4 * q;
-      return fma(-hh, r[2], r[3]) + log_i0(za * r[1], C);
+      return fma(-hh, r[2], r[3]) + log_i0(za * r[1]);
     };
     double mx = -INFINITY;
     for (int q = lane; q < n_dist; q += 64) mx = fmax(mx, lw(q));
@@ -179,10 +178,9 @@ gw_status stage_overlaps(gw_ctx* ctx, const double* theta, int64_t n, int like, 
 // zt [n][nt][3], then phi_c from exp(|Z(t_j)| cos(phi + arg Z(t_j))).
 // out[p] = (t_j, phi_c) with t_j = (j - J) delta; idx[p] = (j, m).
 __global__ void __launch_bounds__(256) k_recon_time(const double* __restrict__ zt, int64_t n, int nt, int J,
-                                                    double delta, int n_phase, const LogI0Consts* __restrict__ Cp,
+                                                    double delta, int n_phase,
                                                     const double* __restrict__ uni, double* __restrict__ out,
                                                     int32_t* __restrict__ idx) {
-  const LogI0Consts& C = *Cp;
   const int lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (p >= n) return;  // wave-uniform
@@ -200,7 +198,7 @@ __global__ void __launch_bounds__(256) k_recon_time(const double* __restrict__ z
   if (isnan(z[0])) return invalid();
   auto lw = [&](int q) {
     const double* r = z + 3 * q;
-    return -0.5 * r[2] + log_i0(sqrt(r[0] * r[0] + r[1] * r[1]), C);
+    return -0.5 * r[2] + log_i0(sqrt(r[0] * r[0] + r[1] * r[1]));
   };
   double mx = -INFINITY;
   for (int q = lane; q < nt; q += 64) mx = fmax(mx, lw(q));
@@ -251,7 +249,6 @@ gw_status gw_reconstruct(gw_ctx* ctx, const double* theta, int64_t n, int32_t li
   hipStream_t st = (hipStream_t)stream;
   gw_status s = check_hip(hipSetDevice(ctx->device), "hipSetDevice");
   if (s != GW_OK) return s;
-  const LogI0Consts* C = ctx->i0c;  // device copy, r1max from the distance grid
   if (marg == GW_MARG_PHASE_TIME) {
     double delta;
     int32_t nt;
@@ -265,14 +262,14 @@ gw_status gw_reconstruct(gw_ctx* ctx, const double* theta, int64_t n, int32_t li
                        : loglike_tmarg_staged(ctx, theta, n, prec, ll, zt, st);
     if (s != GW_OK) return s;
     hipLaunchKernelGGL(k_recon_time, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, zt, n, nt, (nt - 1) / 2, delta,
-                       n_phase, C, uniforms, out, idx);
+                       n_phase, uniforms, out, idx);
     return check_hip(hipGetLastError(), "time reconstruction launch");
   }
   s = stage_overlaps(ctx, theta, n, like, marg, prec, logl, st);
   if (s != GW_OK) return s;
   double* zc3 = ctx->recon;
   hipLaunchKernelGGL(k_recon, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, zc3, n, theta, ctx->dist_tab,
-                     ctx->n_dist, marg, n_phase, C, uniforms, out, idx);
+                     ctx->n_dist, marg, n_phase, uniforms, out, idx);
   return check_hip(hipGetLastError(), "reconstruction launch");
 }
 

@@ -68,14 +68,14 @@ __device__ inline void tg_lds_pass2(double2* __restrict__ buf, int tid, int D1, 
 }
 
 struct TgKernelArgs {
-  const double2* mom;  // [n][K][n_blk]
+  const double2* mom;  // element (p, m, b) at p mom_rs + (m n_blk + b) mom_es
+  int64_t mom_rs, mom_es;
   int64_t n;
   int n_blk, L, D2, K, jmax;
   const double* ccoef;  // [K][256][16]
   const double* coef;
   int64_t ld;
   double dd;
-  const LogI0Consts* C;
   double* logl;
   const double* hhc;
   const double2* hpart;
@@ -86,7 +86,9 @@ struct TgKernelArgs {
   double f0_num, f0_den;
 };
 
-// mom: [n][K][n_blk] complex (row p, order m, block b at ((p K + m) n_blk + b)).
+// mom: complex moments, row p, order m, block b at p mom_rs + (m n_blk + b)
+// mom_es (row-major [n][K][n_blk]: (K n_blk, 1); row fastest [K][n_blk][n]:
+// (1, n)).
 // ccoef: eps_m J_m(phi_j) for lane l's output slot k3 at (m 256 + l) 16 + k3,
 // with the sign of (-i)^m folded in (+ for m mod 4 in {0, 1}, - otherwise)
 // and zero where |j| > jmax.  HET = 0: <h|h> = coef[C_HH]; HET = 1:
@@ -106,7 +108,8 @@ __global__ void __launch_bounds__(256, 2) k_tgrid(TgKernelArgs a) {
   const int L = a.L, D2 = D1 > 1 ? 16 : a.D2, K = a.K;
   const int S1 = L / D1;  // = 16 D2
   const int nt = 2 * a.jmax + 1;
-  const double2* __restrict__ mrow = a.mom + p * (int64_t)K * a.n_blk;
+  const double2* __restrict__ mrow = a.mom + p * a.mom_rs;
+  const int64_t es = a.mom_es;
   const bool on1 = tid < S1, on3 = tid < L / 16;
   double2 w1 = make_double2(1.0, 0.0), w2;
   if (D1 > 1) {
@@ -127,11 +130,11 @@ __global__ void __launch_bounds__(256, 2) k_tgrid(TgKernelArgs a) {
   constexpr bool kPrefetch = NZ <= 4;
   double2 x[NZ];
   auto load = [&](int m) {
-    const double2* __restrict__ src = mrow + (int64_t)m * a.n_blk;
+    const double2* __restrict__ src = mrow + (int64_t)m * a.n_blk * es;
 #pragma unroll
     for (int q = 0; q < NZ; ++q) {
       const int b = tid + S1 * q;
-      x[q] = (on1 && b < a.n_blk) ? src[b] : make_double2(0.0, 0.0);
+      x[q] = (on1 && b < a.n_blk) ? src[b * es] : make_double2(0.0, 0.0);
     }
   };
   if (kPrefetch) load(0);
@@ -191,7 +194,6 @@ __global__ void __launch_bounds__(256, 2) k_tgrid(TgKernelArgs a) {
     }
   }
   const bool valid = a.coef[C_VALID * a.ld + p] != 0.0;
-  const LogI0Consts& C = *a.C;
   // the finished Z(t_j) go to the buffer in grid order (nt <= L points), read
   // back below in a plain loop
   __syncthreads();
@@ -206,12 +208,22 @@ __global__ void __launch_bounds__(256, 2) k_tgrid(TgKernelArgs a) {
   double hh = 0.0;
   if (HET) {
     hh = a.hhc[p];
-    // this row's H moments, summed over the edge chunks in order
-    for (int q = tid; q < a.mh; q += 256) {
+    // this row's H moments, summed over the edge chunks: thread (g, q)
+    // adds chunks g, g + 4, ... of moment q, and the four sums are added in
+    // order g = 0 .. 3 (red and red2 hold them; mh <= kTgHMax <= 64)
+    {
+      const int q = tid & 63, g = tid >> 6;
       double2 s = make_double2(0.0, 0.0);
-      for (int c = 0; c < a.n_hch; ++c) s = c_add(s, a.hpart[((int64_t)c * a.n + p) * a.mh + q]);
-      sm[q] = s;
-      sinv[q] = 1.0 / (double)(q + 1);
+      if (q < a.mh)
+        for (int c = g; c < a.n_hch; c += 4) s = c_add(s, a.hpart[((int64_t)c * a.n + p) * a.mh + q]);
+      red[tid] = s.x;
+      red2[tid] = s.y;
+      __syncthreads();
+      if (tid < a.mh) {
+        sm[tid] = make_double2(((red[tid] + red[tid + 64]) + red[tid + 128]) + red[tid + 192],
+                               ((red2[tid] + red2[tid + 64]) + red2[tid + 128]) + red2[tid + 192]);
+        sinv[tid] = 1.0 / (double)(tid + 1);
+      }
     }
   } else {
     hh = a.coef[C_HH * a.ld + p];
@@ -254,7 +266,7 @@ __global__ void __launch_bounds__(256, 2) k_tgrid(TgKernelArgs a) {
       zo[1] = cs * z.y - sn * z.x;
       zo[2] = hj;
     }
-    const double v = -0.5 * hj + log_i0(sqrt(z.x * z.x + z.y * z.y), C);
+    const double v = -0.5 * hj + log_i0(sqrt(z.x * z.x + z.y * z.y));
     if (v > run_mx) {
       run_acc = run_acc * exp(run_mx - v) + 1.0;
       run_mx = v;
@@ -347,6 +359,8 @@ gw_status launch_tgrid(const gw_ctx* ctx, const TGridArgs& a, hipStream_t st) {
   }
   TgKernelArgs k{};
   k.mom = (const double2*)a.mom;
+  k.mom_rs = a.mom_rs;
+  k.mom_es = a.mom_es;
   k.n = a.n;
   k.n_blk = a.n_blk;
   k.L = a.L;
@@ -357,7 +371,6 @@ gw_status launch_tgrid(const gw_ctx* ctx, const TGridArgs& a, hipStream_t st) {
   k.coef = a.coef;
   k.ld = a.ld;
   k.dd = ctx->dd;
-  k.C = ctx->i0c;
   k.logl = a.logl;
   k.zout = a.zout;
   k.f0_num = a.f0_num;

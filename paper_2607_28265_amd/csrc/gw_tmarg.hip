@@ -345,6 +345,8 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
     if (s != GW_OK) return s;
     TGridArgs a{};
     a.mom = ctx->tm_mom;
+    a.mom_rs = (int64_t)K * g.n_blk;  // k_tmom writes one row's moments contiguously
+    a.mom_es = 1;
     a.n = cn;
     a.n_blk = g.n_blk;
     a.L = g.L;

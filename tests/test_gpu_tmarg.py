@@ -208,7 +208,7 @@ def test_odd_power_fft_length(monkeypatch):
         assert err < 1e-6
 
 
-@pytest.mark.parametrize("nsk", [1, 2, 8, 32])
+@pytest.mark.parametrize("nsk", [1, 2, 8, 32, 256])
 def test_heterodyned_fixed_splits_agree(nsk):
     # every split of the edge sum gives the same grid sums up to summation
     # order, for a sampler-sized batch (and the default split on the same rows)
@@ -230,5 +230,6 @@ def test_heterodyned_fixed_splits_agree(nsk):
             err = np.max(np.abs(got[fin] - base[fin]))
             print(f"split {nsk} prec {prec}: max |dlogL| vs default {err:.2e}", flush=True)
             assert err < tol
-        with pytest.raises(gw.GwError):
-            gw.gw_set_het_tm_split(ctx.handle, 3)
+        for bad in (3, 512):
+            with pytest.raises(gw.GwError):
+                gw.gw_set_het_tm_split(ctx.handle, bad)
