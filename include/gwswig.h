@@ -297,9 +297,10 @@ gw_status loglike_batch_uneven(gw_ctx* ctx, const double* theta, int64_t n_rows,
  * are split into (0 = heuristic for either). */
 gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid, int32_t n_ech);
 /* Edge chunks of the heterodyned time marginal's per-row edge moments (App. A
- * on the binned likelihood): 1, 2, 4, ..., 256 asks for that many chunks of
- * whole frequency blocks of about equal cost (an edge or a block one unit;
- * fewer chunks when the blocks do not allow them), 0 (default) restores the
+ * on the binned likelihood): 1, 2, 4, ..., 256 asks for that many edge
+ * ranges of about equal cost (an edge or a frequency block one unit; a block
+ * cut by several ranges gets its moments summed from their pieces in order;
+ * fewer ranges when there are fewer units), 0 (default) restores the
  * heuristic (about 4096 (row tile, chunk) waves, at most 256 chunks of at
  * least 8 units).  Results differ only by summation order.  GW_EINVAL
  * otherwise. */

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "gw_ctx.h"
+#include "gw_hetplan.h"
 #include "gw_tgrid.h"
 
 // Device-resident arguments of the work-list kernels; a one-thread kernel
@@ -64,14 +65,16 @@ struct gw_het_state {
   int ech = 0;                   // edge chunks (0 = heuristic)
   int64_t n_rows_last = 0;       // rows of the batch being enqueued (selects the distance form)
   // time marginal: row-independent tables for the current grid (built on
-  // first use): per block b < n_blk the edges [tm_bs[b], tm_bs[b + 1]) in it,
-  // per edge the Chebyshev values T_m(s_e) of its offset in the block
-  // (m < tm_K) and the powers sigma_e^m of its bin width about the widths'
-  // centre (m < tm_mh), and the edge chunks of the moment kernel (whole
-  // blocks tm_cb[c] .. tm_cb[c + 1])
+  // first use): per block b < n_blk the edges [bs[b], bs[b + 1]) in it, per
+  // edge the Chebyshev values T_m(s_e) of its offset in the block (m < tm_K)
+  // and the powers sigma_e^m of its bin width about the widths' centre
+  // (m < tm_mh), and the moment kernel's chunks (gw_hetplan.h)
   double* tm_tab = nullptr;      // [n_edges][tm_K + tm_mh]
-  int32_t* tm_idx = nullptr;     // [n_blk + 1] block starts, then [tm_nch + 1] chunk block starts
+  // bs [n_blk + 1], then the plan: e0 [nch + 1], blo, bhi, sfirst, slast
+  // [nch] each, then per cut block fb, fs, fc [tm_nsplit] each
+  int32_t* tm_idx = nullptr;
   int tm_blk = 0, tm_nblk = 0, tm_mh = 0, tm_nch = 0, tm_nch_req = -1, tm_K = 0;
+  int tm_nslot = 0, tm_nsplit = 0;  // piece slots and cut blocks of the plan
   double tm_hw = 0.0;            // half-range of the bin widths (fine bins)
   double tm_umax = -1.0;         // the window's largest |u| the norm series was sized for
   int64_t tm_c2 = 0;             // smallest + largest bin width (fine bins)
@@ -813,10 +816,11 @@ void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech)
 // grid kernel sums (tm_mh terms, the first dropped one below 1e-13 of
 // sum_e |V_e| at the window's edge).
 
-// Edge-weight moments of one (64-row tile, edge chunk): lane = row, the
-// chunk's edges in order (edge records and tables wave-uniform).  what = 0:
-// the K block moments of W for every block of the chunk into mom
-// [K][n_blk][rows] (rows fastest, so the stores of a wave are contiguous);
+// Edge-weight moments of one (64-row tile, chunk): lane = row, the chunk's
+// edges e0[c] .. e0[c + 1] in order (edge records and tables wave-uniform).
+// what = 0: the K block moments of W for the blocks the chunk emits, into mom
+// [K][n_blk][rows] (rows fastest, so the stores of a wave are contiguous), or
+// for a block the plan cuts, the chunk's piece into part [slot][K][rows];
 // what = 1: S_m, m0 <= m < m0 + K (m < mh), over the
 // chunk's edges into hpart [chunk][rows][mh]; chunk 0 also writes the
 // constant norm part hhc [rows].
@@ -824,10 +828,10 @@ template <int ND, int PREC, int K, int WHAT>
 __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef, int64_t ld, int64_t n,
                                                  const double* __restrict__ rec, int n_bins,
                                                  const double* __restrict__ tab, int mh,
-                                                 const int32_t* __restrict__ bs, const int32_t* __restrict__ cb,
-                                                 int n_blk, int m0, HetConst hc, TrigConsts T,
-                                                 double2* __restrict__ mom, double2* __restrict__ hpart,
-                                                 double* __restrict__ hhc) {
+                                                 const int32_t* __restrict__ bs, const int32_t* __restrict__ plan,
+                                                 int nch, int n_blk, int m0, HetConst hc, TrigConsts T,
+                                                 double2* __restrict__ mom, double2* __restrict__ part,
+                                                 double2* __restrict__ hpart, double* __restrict__ hhc) {
   constexpr int RS = het_rs(ND);
   constexpr int BO = het_bin_off(ND);
   const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
@@ -851,8 +855,8 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
     pr[i] = pim[i] = 0.0;
   }
   if (WHAT == 0 && ch == 0 && p < n) hhc[p] = hconst;
-  const int b_lo = cb[ch], b_hi = cb[ch + 1];
-  const int e_lo = bs[b_lo], e_hi = bs[b_hi];
+  const int32_t* __restrict__ e0 = plan;
+  const int e_lo = e0[ch], e_hi = e0[ch + 1];
   const int tw_ = K + mh;  // table row length
   if (WHAT == 1 && e_lo > 0) {  // the norm term needs the previous edge's phasors
     const double* r = rec + (int64_t)(e_lo - 1) * RS;
@@ -902,14 +906,21 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
     }
   };
   if constexpr (WHAT == 0) {
+    const int32_t* __restrict__ blo = e0 + nch + 1;
+    const int32_t* __restrict__ bhi = blo + nch;
+    const int32_t* __restrict__ sfirst = bhi + nch;
+    const int32_t* __restrict__ slast = sfirst + nch;
+    const int b_lo = blo[ch], b_hi = bhi[ch];
     int e = e_lo;
     for (int b = b_lo; b < b_hi; ++b) {
-      const int be = bs[b + 1];
+      const int be = bs[b + 1] < e_hi ? bs[b + 1] : e_hi;
       for (; e < be; ++e) edge(e);
+      const int slot = b == b_hi - 1 ? slast[ch] : (b == b_lo ? sfirst[ch] : -1);
       if (p < n) {  // rows fastest: a wave's 64 rows store 1 KB contiguously
-        double2* out = mom + (int64_t)b * n + p;
+        double2* out = slot < 0 ? mom + (int64_t)b * n + p : part + (int64_t)slot * K * n + p;
+        const int64_t ms = slot < 0 ? (int64_t)n_blk * n : n;
 #pragma unroll
-        for (int m = 0; m < K; ++m) out[(int64_t)m * n_blk * n] = make_double2(ar_[m], ai_[m]);
+        for (int m = 0; m < K; ++m) out[m * ms] = make_double2(ar_[m], ai_[m]);
       }
 #pragma unroll
       for (int m = 0; m < K; ++m) ar_[m] = ai_[m] = 0.0;
@@ -925,38 +936,64 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
   }
 }
 
+// Blocks the plan cuts: each sums its pieces part [slot][K][rows] in chunk
+// order into mom [K][n_blk][rows]; lane = row, one cut block per grid row.
+template <int K>
+__global__ void __launch_bounds__(64) k_het_tmom_fix(int64_t n, int n_blk, const int32_t* __restrict__ fb,
+                                                     const int32_t* __restrict__ fs, const int32_t* __restrict__ fc,
+                                                     const double2* __restrict__ part, double2* __restrict__ mom) {
+  const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (p >= n) return;
+  const int i = blockIdx.y;
+  const int b = fb[i], s0 = fs[i], cnt = fc[i];
+#pragma unroll
+  for (int m = 0; m < K; ++m) {
+    double2 v = part[((int64_t)s0 * K + m) * n + p];
+    for (int k = 1; k < cnt; ++k) v = c_add(v, part[((int64_t)(s0 + k) * K + m) * n + p]);
+    mom[((int64_t)m * n_blk + b) * n + p] = v;
+  }
+}
+
 template <int ND, int K>
 static void launch_het_tmom_k(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, const HetConst& hc,
-                              int what, int m0, double2* mom, double2* hpart, double* hhc, hipStream_t st) {
+                              int what, int m0, double2* mom, double2* part, double2* hpart, double* hhc,
+                              hipStream_t st) {
   const gw_het_state* h = ctx->het;
   const TrigConsts T = make_trig_consts();
   const dim3 grid((unsigned)((n + 63) / 64), (unsigned)h->tm_nch);
   const int32_t* bs = h->tm_idx;
-  const int32_t* cb = h->tm_idx + h->tm_nblk + 1;
+  const int32_t* plan = h->tm_idx + h->tm_nblk + 1;
 #define GW_HET_TMOM(P, W)                                                                                     \
   hipLaunchKernelGGL((k_het_tmom<ND, P, K, W>), grid, dim3(64), 0, st, coef, ld, n, (const double*)h->rec,        \
-                     h->n_bins, (const double*)h->tm_tab, h->tm_mh, bs, cb, h->tm_nblk, m0, hc, T, mom, hpart, hhc)
+                     h->n_bins, (const double*)h->tm_tab, h->tm_mh, bs, plan, h->tm_nch, h->tm_nblk, m0, hc, T, mom, \
+                     part, hpart, hhc)
   if (prec == GW_PREC_FP64) {
     if (what == 0) GW_HET_TMOM(0, 0); else GW_HET_TMOM(0, 1);
   } else {
     if (what == 0) GW_HET_TMOM(1, 0); else GW_HET_TMOM(1, 1);
   }
 #undef GW_HET_TMOM
+  if (what == 0 && h->tm_nsplit > 0) {  // add the pieces of the cut blocks
+    const int32_t* fb = plan + (h->tm_nch + 1) + 4 * h->tm_nch;
+    hipLaunchKernelGGL((k_het_tmom_fix<K>), dim3((unsigned)((n + 63) / 64), (unsigned)h->tm_nsplit), dim3(64), 0,
+                       st, n, h->tm_nblk, fb, fb + h->tm_nsplit, fb + 2 * h->tm_nsplit, (const double2*)part, mom);
+  }
 }
 
 template <int ND>
 static void launch_het_tmom_nd(gw_ctx* ctx, const double* coef, int64_t ld, int64_t n, int prec, const HetConst& hc,
-                               int what, int m0, double2* mom, double2* hpart, double* hhc, hipStream_t st) {
+                               int what, int m0, double2* mom, double2* part, double2* hpart, double* hhc,
+                               hipStream_t st) {
   if (ctx->het->tm_K == 12)
-    launch_het_tmom_k<ND, 12>(ctx, coef, ld, n, prec, hc, what, m0, mom, hpart, hhc, st);
+    launch_het_tmom_k<ND, 12>(ctx, coef, ld, n, prec, hc, what, m0, mom, part, hpart, hhc, st);
   else
-    launch_het_tmom_k<ND, 16>(ctx, coef, ld, n, prec, hc, what, m0, mom, hpart, hhc, st);
+    launch_het_tmom_k<ND, 16>(ctx, coef, ld, n, prec, hc, what, m0, mom, part, hpart, hhc, st);
 }
 
-// Edge chunks of the moment kernel: whole blocks of about equal cost (an
-// edge or a block's moment stores count one unit each), the count chosen for
-// about 4096 (tile, chunk) waves (at most 256 chunks, each of at least 8
-// units), or fixed by gw_set_het_tm_split.
+// Chunks of the moment kernel: edge ranges of about equal cost (an edge or
+// a block's moment stores count one unit each; gw_hetplan.h), the count
+// chosen for about 4096 (tile, chunk) waves (at most 256 chunks, each of at
+// least 8 units), or fixed by gw_set_het_tm_split.
 static int het_tm_chunks(const gw_ctx* ctx, int64_t n, int n_blk) {
   if (ctx->tm_nsk > 0) return ctx->tm_nsk;
   const int64_t tiles = (n + 63) / 64;
@@ -1012,16 +1049,11 @@ static gw_status het_tm_tables(gw_ctx* ctx, int blk, int n_blk, double umax, int
     }
   }
   for (int b = 0; b < n_blk; ++b) bs[b + 1] += bs[b];
-  // chunks of whole blocks of about (ne + n_blk) / nch cost units each, an
-  // edge and a block's moment stores one unit each (blocks before b cost
-  // bs[b] + b)
-  std::vector<int32_t> cb(1, 0);
-  const double per = (double)(ne + n_blk) / nch;
-  for (int b = 1; b < n_blk && (int)cb.size() < nch; ++b)
-    if ((double)(bs[b] + b) >= per * (double)cb.size()) cb.push_back(b);
-  cb.push_back(n_blk);
+  const HetTmPlan plan = het_tm_plan(bs, n_blk, ne, nch);
   std::vector<int32_t> idx(bs);
-  idx.insert(idx.end(), cb.begin(), cb.end());
+  for (const std::vector<int32_t>* v : {&plan.e0, &plan.blo, &plan.bhi, &plan.sfirst, &plan.slast, &plan.fb,
+                                        &plan.fs, &plan.fc})
+    idx.insert(idx.end(), v->begin(), v->end());
   if (h->tm_tab) (void)hipFree(h->tm_tab);
   if (h->tm_idx) (void)hipFree(h->tm_idx);
   h->tm_tab = nullptr;
@@ -1036,8 +1068,10 @@ static gw_status het_tm_tables(gw_ctx* ctx, int blk, int n_blk, double umax, int
   h->tm_blk = blk;
   h->tm_nblk = n_blk;
   h->tm_mh = mh;
-  h->tm_nch = (int)cb.size() - 1;
+  h->tm_nch = plan.nch();
   h->tm_nch_req = nch;
+  h->tm_nslot = plan.nslot;
+  h->tm_nsplit = (int)plan.fb.size();
   h->tm_hw = hw;
   h->tm_c2 = dmin + dmax;
   h->tm_umax = umax;
@@ -1065,15 +1099,18 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
   if (s != GW_OK) return s;
   const int mh = h->tm_mh;
   // workspace: coefficients for all rows; per row chunk the moments
-  // [K][n_blk][rows] (rows fastest), the norm moments [n_ch][rows][mh] and hhc [rows]
+  // [K][n_blk][rows] (rows fastest), the pieces of cut blocks [slot][K][rows],
+  // the norm moments [n_ch][rows][mh] and hhc [rows]
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
   if (s == GW_OK)
     s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap,
-                      chunk * K * g.n_blk * 2 + (int64_t)h->tm_nch * chunk * mh * 2 + chunk,
+                      chunk * K * g.n_blk * 2 + (int64_t)h->tm_nslot * K * chunk * 2 +
+                          (int64_t)h->tm_nch * chunk * mh * 2 + chunk,
                       "time-marginal workspace");
   if (s != GW_OK) return s;
   double2* mom = (double2*)ctx->tm_mom;
-  double2* hpart = mom + chunk * K * g.n_blk;
+  double2* part = mom + chunk * K * g.n_blk;
+  double2* hpart = part + (int64_t)h->tm_nslot * K * chunk;
   double* hhc = (double*)(hpart + (int64_t)h->tm_nch * chunk * mh);
   s = launch_prologue(ctx, theta, n, GW_MARG_PHASE_TIME, ctx->coef, n, st);
   if (s != GW_OK) return s;
@@ -1091,10 +1128,18 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
     for (int what = 0; what < 2; ++what)
       for (int m0 = 0; m0 < (what == 0 ? 1 : mh); m0 += K) {
         switch (ctx->n_det) {
-          case 1: launch_het_tmom_nd<1>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, hpart, hhc, st); break;
-          case 2: launch_het_tmom_nd<2>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, hpart, hhc, st); break;
-          case 3: launch_het_tmom_nd<3>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, hpart, hhc, st); break;
-          case 4: launch_het_tmom_nd<4>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, hpart, hhc, st); break;
+          case 1:
+            launch_het_tmom_nd<1>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, part, hpart, hhc, st);
+            break;
+          case 2:
+            launch_het_tmom_nd<2>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, part, hpart, hhc, st);
+            break;
+          case 3:
+            launch_het_tmom_nd<3>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, part, hpart, hhc, st);
+            break;
+          case 4:
+            launch_het_tmom_nd<4>(ctx, ctx->coef + r0, n, cn, prec, hc, what, m0, mom, part, hpart, hhc, st);
+            break;
           default: return set_error(GW_ENOTSUP, "n_det not supported");
         }
         s = check_hip(hipGetLastError(), "time-marginal moment launch");
