@@ -278,9 +278,7 @@ __device__ inline void sincos_cycles(double r, const TrigConsts& T, double* s_ou
 // large-argument expansion I0(x) ~ e^x / sqrt(2 pi x) sum_k c_k x^-k with
 // c_k = ((2k-1)!!)^2 / (k! 8^k) (Abramowitz & Stegun 9.7.1), Horner in
 // u = 1/x with 24 terms (the terms still decrease there; truncation below
-// 1e-16).  The coefficients are compile-time constants, so the kernels take
-// them as scalar operands: loaded from memory inside the distance loops, 64
-// of them cost a 64-lane load each per grid point.
+// 1e-16).  The coefficients are fixed at compile time (below).
 struct I0Coefs {
   double ser[40];
   double asy[24];
@@ -317,11 +315,25 @@ __host__ __device__ inline LogI0Consts make_log_i0_consts() {
   return c;
 }
 
-// A compile-time constant placed in a scalar register pair where it is used:
-// the empty asm keeps the compiler from hoisting the 64 coefficients of the
-// distance loops into vector registers (where each Horner step then costs a
-// move and a multiply-add) or from loading them from memory.
-__device__ inline double sgpr_const(double c) {
+// The coefficients in constant memory, read with scalar loads where they are
+// used: the empty asm on the table's address keeps the compiler from hoisting
+// the 64 values out of the distance loops (they exceed the scalar registers,
+// and hoisted into vector registers each Horner step costs extra moves), and
+// sgpr() keeps each value in the scalar register the load wrote, so that a
+// Horner step is one multiply-add with a scalar operand.  Materialising the
+// constants with scalar moves instead costs two scalar instructions per use,
+// as many as the vector work of the loops.
+static __constant__ I0Coefs kI0Dev = make_i0_coefs();
+
+typedef const __attribute__((address_space(4))) double* I0Table;
+
+__device__ inline I0Table i0_table() {
+  I0Table p = (I0Table)&kI0Dev.ser[0];
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+__device__ inline double sgpr(double c) {
   asm volatile("" : "+s"(c));
   return c;
 }
@@ -329,18 +341,20 @@ __device__ inline double sgpr_const(double c) {
 // Power series of I0 in y = x^2 / 4 truncated after K terms (Horner).
 template <int K>
 __device__ inline double i0_series(double y) {
-  double p = sgpr_const(kI0.ser[K - 1]);
+  const I0Table t = i0_table();
+  double p = sgpr(t[K - 1]);
 #pragma unroll
-  for (int k = K - 2; k >= 0; --k) p = fma(p, y, sgpr_const(kI0.ser[k]));
+  for (int k = K - 2; k >= 0; --k) p = fma(p, y, sgpr(t[k]));
   return p;
 }
 
 // Large-argument series sum_k c_k u^k truncated after K terms (Horner).
 template <int K>
 __device__ inline double i0_asym_k(double u) {
-  double p = sgpr_const(kI0.asy[K - 1]);
+  const I0Table t = i0_table() + 40;
+  double p = sgpr(t[K - 1]);
 #pragma unroll
-  for (int k = K - 2; k >= 0; --k) p = fma(p, u, sgpr_const(kI0.asy[k]));
+  for (int k = K - 2; k >= 0; --k) p = fma(p, u, sgpr(t[k]));
   return p;
 }
 

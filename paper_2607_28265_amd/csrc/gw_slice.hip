@@ -260,7 +260,12 @@ __global__ void k_sweep_set(SweepParams* D, SweepParams P, unsigned long long* k
   }
 }
 
-__global__ void k_sweep_init(const SweepParams* __restrict__ D, SliceState S) {
+// Threads per workgroup of the sweep kernels (one per chain): the bound lets
+// the chain's state (a point, a direction, the block's Cholesky row) stay in
+// registers instead of scratch memory.
+constexpr int kSweepThreads = 256;
+
+__global__ void __launch_bounds__(kSweepThreads) k_sweep_init(const SweepParams* __restrict__ D, SliceState S) {
   const SweepParams& P = *D;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P.k) return;
@@ -272,7 +277,7 @@ __global__ void k_sweep_init(const SweepParams* __restrict__ D, SliceState S) {
 // Write the candidates of every chain that is still moving: the two bracket
 // ends while stepping out, else one shrink draw (points outside the cube
 // count as rejections immediately, without a likelihood call).
-__global__ void k_sweep_propose(const SweepParams* __restrict__ D, SliceState S, double* __restrict__ cand) {
+__global__ void __launch_bounds__(kSweepThreads) k_sweep_propose(const SweepParams* __restrict__ D, SliceState S, double* __restrict__ cand) {
   const SweepParams& P = *D;
   const double* __restrict__ x0 = P.x;
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -378,7 +383,7 @@ __device__ inline void record_pair(const SweepParams& P, const SliceState& S, in
   P.rec_l[pos] = v;
 }
 
-__global__ void k_sweep_update(const SweepParams* __restrict__ D, SliceState S, const double* __restrict__ cand_logl) {
+__global__ void __launch_bounds__(kSweepThreads) k_sweep_update(const SweepParams* __restrict__ D, SliceState S, const double* __restrict__ cand_logl) {
   const SweepParams& P = *D;
   double* __restrict__ x = P.x;
   double* __restrict__ logl = P.logl;
@@ -853,7 +858,7 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
   if (s == GW_OK && a.cache) s = slice_wcache(ctx, ws, P.k);
   if (s != GW_OK) return s;
   const int64_t k = P.k;
-  const int tpb = 256;
+  const int tpb = kSweepThreads;
   const unsigned blocks = (unsigned)((k + tpb - 1) / tpb);
   if (a.mlp) {
     s = mlp_prepare(a.mlp, st);  // BF16 weights current before any capture or launch
