@@ -982,8 +982,8 @@ gw_status slice_step(gw_ctx* ctx, const gw_slice_args* a, void* stream) {
   if (s == GW_OK) s = set_screen("slice_step", ctx, a->mlp, a->margin, a->audit_frac, P);
   if (s == GW_OK) s = set_record("slice_step", a->rec_x, a->rec_logl, a->rec_cap, a->rec_count, P);
   if (s != GW_OK) return s;
-  // the time marginal sets up tables on first use and calls the BLAS library:
-  // its rounds are launched eagerly
+  // the time marginal builds its tables and sizes its workspace on first
+  // use, which a captured graph cannot do: its rounds are launched eagerly
   const int32_t graph = a->use_graph && a->marg != GW_MARG_PHASE_TIME;
   const SweepCall c{a->like, a->marg, a->prec, graph, a->n_evals, a->status, 0, nullptr, P.lists,
                     P.screen ? a->mlp : nullptr, a->screen_stats};

@@ -67,6 +67,8 @@ __device__ inline void tg_lds_pass2(double2* __restrict__ buf, int tid, int D1, 
   }
 }
 
+constexpr int kTgXcds = 8;  // XCDs of the GPU (workgroups are dealt to them in turn)
+
 struct TgKernelArgs {
   const double2* mom;  // element (p, m, b) at p mom_rs + (m n_blk + b) mom_es
   int64_t mom_rs, mom_es;
@@ -103,7 +105,14 @@ __global__ void __launch_bounds__(256, 2) k_tgrid(TgKernelArgs a) {
   __shared__ double2 sm[kTgHMax];
   __shared__ double sinv[kTgHMax];  // 1 / (q + 1)
   __shared__ double red[256], red2[256];
-  const int64_t p = blockIdx.x;
+  // Workgroups are dealt to the 8 XCDs in turn, each with its own L2; in the
+  // rows-fastest moment layout neighbouring rows share cache lines, so there
+  // workgroup i takes row (i mod 8) span + i / 8 and the rows of one XCD are
+  // consecutive (row-major moments: row i).
+  const int64_t span = (a.n + kTgXcds - 1) / kTgXcds;
+  const int64_t p = a.mom_es != 1 ? (int64_t)(blockIdx.x % kTgXcds) * span + blockIdx.x / kTgXcds
+                                  : (int64_t)blockIdx.x;
+  if (p >= a.n) return;  // whole workgroup, before any barrier
   const int tid = threadIdx.x;
   const int L = a.L, D2 = D1 > 1 ? 16 : a.D2, K = a.K;
   const int S1 = L / D1;  // = 16 D2
@@ -321,7 +330,7 @@ int64_t tgrid_chunk_rows(int64_t n, int n_blk, int K) {
 
 template <int HET>
 static void launch_tgrid_form(const TgKernelArgs& k, int D1, int nz, unsigned n, hipStream_t st) {
-  const dim3 grid(n), blk(256);
+  const dim3 grid((unsigned)(kTgXcds * ((n + kTgXcds - 1) / kTgXcds))), blk(256);
   switch (D1) {
     case 16:
       switch (nz) {
