@@ -62,12 +62,12 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector, dense
 
 # HBM bytes per launch from two rocprofv3 PMC runs (FETCH_SIZE, WRITE_SIZE)
 # scaled by what the same counters read for a plain 256 MiB device copy
-# (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.000): k_full<3, 1, false> at
-# 4096 x 259,585, and k_wmom<3> at 4096 rows on 2048 cached slots.  Valid only
-# for the kernel sources they were taken on (hash below).
-TRAFFIC = {"sources_sha256": "8691f68cc9ae6136fe007c14efbcf1f40676b8a743eadbd940bb748cbc4f2a3a",
-           "k_full": {"read_bytes": 22399.55 * 1.99981 * 1024, "write_bytes": 49152.0 * 1024},
-           "k_wmom": {"read_bytes": 397442.0 * 1.99981 * 1024, "write_bytes": 23040.0 * 1024}}
+# (FETCH_SIZE x 1.99982, WRITE_SIZE x 1.000): k_full<3, 1, false> at
+# 4096 x 259,585, and k_wmom<3> at 4096 rows on 2048 cached slots (12 orders).
+# Valid only for the kernel sources they were taken on (hash below).
+TRAFFIC = {"sources_sha256": "cdca963ad041d84c58da7cceccda8c33b7c7113d673ab4adfeda943fa274ebb4",
+           "k_full": {"read_bytes": 22404.2 * 1.99982 * 1024, "write_bytes": 49152.0 * 1024},
+           "k_wmom": {"read_bytes": 320487.9 * 1.99982 * 1024, "write_bytes": 23040.0 * 1024}}
 TRAFFIC_SOURCES = ("paper_2607_28265_amd/csrc/gw_full.hip", "paper_2607_28265_amd/csrc/gw_device.h")
 
 
