@@ -64,8 +64,10 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector, dense
 # scaled by what the same counters read for a plain 256 MiB device copy
 # (FETCH_SIZE x 1.99982, WRITE_SIZE x 1.000): k_full<3, 1, false> at
 # 4096 x 259,585, and k_wmom<3> at 4096 rows on 2048 cached slots (12 orders).
-# Valid only for the kernel sources they were taken on (hash below).
-TRAFFIC = {"sources_sha256": "cdca963ad041d84c58da7cceccda8c33b7c7113d673ab4adfeda943fa274ebb4",
+# Valid only for the kernel sources they were taken on (hash below; retaken
+# when those files change, or carried over after checking that the compiled
+# code of both kernels is unchanged).
+TRAFFIC = {"sources_sha256": "78485f89754a80c14c8330dda9495618a08f1c73a5db95363cacc7f73b1b324d",
            "k_full": {"read_bytes": 22404.2 * 1.99982 * 1024, "write_bytes": 49152.0 * 1024},
            "k_wmom": {"read_bytes": 320487.9 * 1.99982 * 1024, "write_bytes": 23040.0 * 1024}}
 TRAFFIC_SOURCES = ("paper_2607_28265_amd/csrc/gw_full.hip", "paper_2607_28265_amd/csrc/gw_device.h")

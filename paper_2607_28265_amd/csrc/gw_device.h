@@ -306,13 +306,38 @@ constexpr I0Coefs kI0 = make_i0_coefs();
 struct LogI0Consts {
   double r1max;  // largest 1/d of the distance grid (bounds x = |Z1| / d); 0 if unknown
   double dmax;   // largest d of the grid (bounds u = 1/x = d / |Z1|); 0 if unknown
+  double exp2_64[64];  // 2^(i/64), i < 64, rounded to FP64 (for exp_nonpos)
 };
 
-__host__ __device__ inline LogI0Consts make_log_i0_consts() {
+// The host fills exp2_64 from long-double 2^(i/64).
+inline LogI0Consts make_log_i0_consts() {
   LogI0Consts c;
   c.r1max = 0.0;
   c.dmax = 0.0;
+  for (int i = 0; i < 64; ++i) c.exp2_64[i] = (double)exp2l((long double)i / 64.0L);
   return c;
+}
+
+// exp(e) for -700 < e <= 0 (the distance marginal's terms relative to their
+// bound), by the table method: e = (64 n + i) ln2/64 + r with |r| <= ln2/128
+// (ln2/64 split in two parts so that k ln2/64 is exact for |k| < 2^13, i.e.
+// e > -88; beyond that the reduction loses digits of terms below e^-88),
+// exp(r) by its Taylor polynomial to r^5 (the first dropped term is below
+// 4e-17), and exp(e) = 2^n 2^(i/64) exp(r).
+__device__ inline double exp_nonpos(double e, const double* __restrict__ t64) {
+  constexpr double kInvStep = 0x1.71547652b82fep+6;   // 64 / ln 2
+  constexpr double kStepHi = 0x1.62e42fefa4000p-7;    // ln 2 / 64, leading 40 bits
+  constexpr double kStepLo = -0x1.8432a1b0e2634p-49;  // ln 2 / 64 - kStepHi
+  const double k = rint(e * kInvStep);
+  const double r = fma(-k, kStepLo, fma(-k, kStepHi, e));
+  const int ki = (int)k;
+  double p = 1.0 / 120.0;
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(t64[ki & 63] * p, ki >> 6);
 }
 
 // The coefficients in constant memory, read with scalar loads where they are
@@ -522,7 +547,7 @@ __device__ inline double wave_dist_lse(double z1, double hh1, const double* __re
       v = p * sqrt(u * kInvTwoPi);
       e = (a + x) - bmax;
     }
-    s = fma(exp(e), v, s);
+    s = fma(exp_nonpos(e, C.exp2_64), v, s);
   }
   return bmax + log(wave_sum(s));
 }
@@ -606,7 +631,7 @@ __device__ inline double slice_dist_sum(double z1, double hh1, double bmax, cons
       v = p * sqrt(u * kInvTwoPi);
       e = (a + x) - bmax;
     }
-    s = fma(exp(e), v, s);
+    s = fma(exp_nonpos(e, C.exp2_64), v, s);
   }
   return s;
 }

@@ -937,21 +937,20 @@ __global__ void __launch_bounds__(64) k_het_tmom(const double* __restrict__ coef
 }
 
 // Blocks the plan cuts: each sums its pieces part [slot][K][rows] in chunk
-// order into mom [K][n_blk][rows]; lane = row, one cut block per grid row.
+// order into mom [K][n_blk][rows]; lane = row, one (cut block, order) per
+// grid row and layer (a block of the narrow windows' wide blocks can have
+// tens of pieces, so the orders run in parallel).
 template <int K>
 __global__ void __launch_bounds__(64) k_het_tmom_fix(int64_t n, int n_blk, const int32_t* __restrict__ fb,
                                                      const int32_t* __restrict__ fs, const int32_t* __restrict__ fc,
                                                      const double2* __restrict__ part, double2* __restrict__ mom) {
   const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (p >= n) return;
-  const int i = blockIdx.y;
+  const int i = blockIdx.y, m = blockIdx.z;
   const int b = fb[i], s0 = fs[i], cnt = fc[i];
-#pragma unroll
-  for (int m = 0; m < K; ++m) {
-    double2 v = part[((int64_t)s0 * K + m) * n + p];
-    for (int k = 1; k < cnt; ++k) v = c_add(v, part[((int64_t)(s0 + k) * K + m) * n + p]);
-    mom[((int64_t)m * n_blk + b) * n + p] = v;
-  }
+  double2 v = part[((int64_t)s0 * K + m) * n + p];
+  for (int k = 1; k < cnt; ++k) v = c_add(v, part[((int64_t)(s0 + k) * K + m) * n + p]);
+  mom[((int64_t)m * n_blk + b) * n + p] = v;
 }
 
 template <int ND, int K>
@@ -975,7 +974,7 @@ static void launch_het_tmom_k(gw_ctx* ctx, const double* coef, int64_t ld, int64
 #undef GW_HET_TMOM
   if (what == 0 && h->tm_nsplit > 0) {  // add the pieces of the cut blocks
     const int32_t* fb = plan + (h->tm_nch + 1) + 4 * h->tm_nch;
-    hipLaunchKernelGGL((k_het_tmom_fix<K>), dim3((unsigned)((n + 63) / 64), (unsigned)h->tm_nsplit), dim3(64), 0,
+    hipLaunchKernelGGL((k_het_tmom_fix<K>), dim3((unsigned)((n + 63) / 64), (unsigned)h->tm_nsplit, K), dim3(64), 0,
                        st, n, h->tm_nblk, fb, fb + h->tm_nsplit, fb + 2 * h->tm_nsplit, (const double2*)part, mom);
   }
 }
