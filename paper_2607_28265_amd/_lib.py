@@ -791,7 +791,7 @@ def gw_fiducial_search(ctx, x, generations: int, seed: int = 0, f_scale: float =
 
 
 def gw_set_het_tm_split(ctx, n_chunks: int = 0):
-    """Edge chunks of the heterodyned time marginal's products (0 = heuristic)."""
+    """Edge chunks of the heterodyned time marginal's edge moments (0 = heuristic)."""
     check(load().gw_set_het_tm_split(ctx, int(n_chunks)), "gw_set_het_tm_split")
 
 

@@ -147,7 +147,7 @@ def main(argv=None):
     ap.add_argument("--generations", type=int, default=300)
     ap.add_argument("--time-window", type=float, default=0.03)
     ap.add_argument("--sampler-seeds", default="17", help="comma list: one run per seed on the same event")
-    ap.add_argument("--tm-split", type=int, default=0, help="edge chunks of the time marginal's products (0: auto)")
+    ap.add_argument("--tm-split", type=int, default=0, help="edge chunks of the time marginal's edge moments (0: auto)")
     a = ap.parse_args(argv)
     prob, truth = make_event(a.seed, a.snr)
     rng = np.random.default_rng(a.seed + 5)
