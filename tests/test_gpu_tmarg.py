@@ -146,6 +146,32 @@ def test_heterodyned_cfg2_against_oracle(nb):
                 assert err < tol
 
 
+@pytest.mark.timeout(600)
+def test_heterodyned_narrow_window_against_oracle(monkeypatch):
+    # the event analysis' +-0.03 s window at 5000 bins: a shorter transform
+    # and wide frequency blocks, hundreds of edges in the lowest ones, so the
+    # edge moments of a sampler-round batch come from chunks that cut blocks
+    # into many pieces, added by the fix-up pass
+    import paper_2607_28265_amd as gw
+    from oracle import heterodyne as H
+    prob = problem("cfg2", loud=True)
+    monkeypatch.setattr(L, "TIME_WINDOW", 0.03)
+    het = H.setup(prob, prob.theta_inj, 5000)
+    th = np.concatenate([near(prob, 8, 41, 0.3), gwsynth.prior_draws(gwsynth.SEEDS["prior"], 8)])
+    ref = oracle_het_many(th, prob, het, L.PHASE_TIME)
+    with gw.Context(prob) as ctx:
+        gw.gw_set_time_window(ctx.handle, 0.03)
+        _, n_t, _, _ = gw.gw_time_grid_info(ctx.handle)
+        assert n_t == L.time_grid(prob).size
+        ctx.heterodyne_setup(prob.theta_inj, 5000)
+        for prec, tol in ((gw.GW_PREC_FP64, 1e-6), (gw.GW_PREC_MIXED, 1e-4)):
+            got = ctx.loglike(torch.from_numpy(th).cuda(), gw.GW_HET, gw.GW_MARG_PHASE_TIME, prec).cpu().numpy()
+            err = np.max(np.abs(got - ref))
+            print(f"heterodyned 128 s, 5000 bins, window 0.03 s ({n_t} points), prec {prec}: max |dlogL| {err:.2e}",
+                  flush=True)
+            assert err < tol
+
+
 def test_heterodyned_split_matches_unsplit():
     # few rows split the edge sum of the products into up to 32 chunks; a
     # large batch keeps one chunk: the same rows agree to rounding
