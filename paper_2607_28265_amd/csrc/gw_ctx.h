@@ -165,6 +165,7 @@ struct TGridArgs {
   int64_t c2, cden;    // exp(-2 pi i c u_j) = exp(-2 pi i (c2 j mod cden) / cden)
   double* zout;        // or NULL: [n][2 jmax + 1][3] staged grid values
   double f0_num, f0_den;  // f_0 t_j = j f0_num / f0_den cycles
+  double* zpart;       // [tgrid_split(n, K)][n][2 jmax + 1] complex when the split exceeds 1
 };
 // The context's time grid: segment length N (samples), J and R (|j| <= jmax =
 // J R), P, blocks of blk = N / P fine bins (n_blk of them), L = P R.
@@ -178,6 +179,12 @@ gw_status time_grid_shape(const gw_ctx* ctx, TimeGridShape* g);
 // change), and the rows per chunk whose moments fit the bounded workspace.
 gw_status tgrid_tables(gw_ctx* ctx, int L, int jmax, int K);
 int64_t tgrid_chunk_rows(int64_t n, int n_blk, int K);
+// Order groups per row of a launch of n rows (1, 2 or 4); above 1 the launch
+// needs zpart.
+int tgrid_split(int64_t n, int K);
+// Complex elements of zpart needed by the launches of n rows in chunks of
+// chunk rows on a grid of nt points.
+int64_t tgrid_zpart_elems(int64_t n, int64_t chunk, int K, int nt);
 gw_status launch_tgrid(const gw_ctx* ctx, const TGridArgs& a, hipStream_t st);
 
 // Record the device address of ``device``'s copy of the allocation-free

@@ -1099,18 +1099,21 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
   const int mh = h->tm_mh;
   // workspace: coefficients for all rows; per row chunk the moments
   // [K][n_blk][rows] (rows fastest), the pieces of cut blocks [slot][K][rows],
-  // the norm moments [n_ch][rows][mh] and hhc [rows]
+  // the norm moments [n_ch][rows][mh], hhc [rows] and, for a small launch,
+  // the order groups' partial grids (16-byte aligned)
+  const int64_t zp = tgrid_zpart_elems(n, chunk, K, 2 * g.jmax + 1);
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
   if (s == GW_OK)
     s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap,
                       chunk * K * g.n_blk * 2 + (int64_t)h->tm_nslot * K * chunk * 2 +
-                          (int64_t)h->tm_nch * chunk * mh * 2 + chunk,
+                          (int64_t)h->tm_nch * chunk * mh * 2 + chunk + 1 + 2 * zp,
                       "time-marginal workspace");
   if (s != GW_OK) return s;
   double2* mom = (double2*)ctx->tm_mom;
   double2* part = mom + chunk * K * g.n_blk;
   double2* hpart = part + (int64_t)h->tm_nslot * K * chunk;
   double* hhc = (double*)(hpart + (int64_t)h->tm_nch * chunk * mh);
+  double* zpart = zp > 0 ? hhc + (chunk + 1) / 2 * 2 : nullptr;
   s = launch_prologue(ctx, theta, n, GW_MARG_PHASE_TIME, ctx->coef, n, st);
   if (s != GW_OK) return s;
   HetConst hc;
@@ -1168,6 +1171,7 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
     a.zout = zout ? zout + r0 * nt * 3 : nullptr;
     a.f0_num = (double)(2 * ctx->geom.k0 + g.blk - 1);
     a.f0_den = (double)(2 * g.N) * (double)g.R;
+    a.zpart = zpart;
     const int gslot = prof_begin(ctx, st, 2);
     s = launch_tgrid(ctx, a, st);
     prof_end(ctx, gslot, st);

@@ -40,6 +40,7 @@
 // chunk order).
 #include <math.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "gw_ctx.h"
@@ -86,134 +87,21 @@ struct TgKernelArgs {
   int64_t c2, cden;
   double* zout;
   double f0_num, f0_den;
+  int S;            // order groups per row (1: one workgroup per row finishes it)
+  double2* zpart;   // S > 1: [S][n][2 jmax + 1] the groups' partial Z(t_j)
 };
 
-// mom: complex moments, row p, order m, block b at p mom_rs + (m n_blk + b)
-// mom_es (row-major [n][K][n_blk]: (K n_blk, 1); row fastest [K][n_blk][n]:
-// (1, n)).
-// ccoef: eps_m J_m(phi_j) for lane l's output slot k3 at (m 256 + l) 16 + k3,
-// with the sign of (-i)^m folded in (+ for m mod 4 in {0, 1}, - otherwise)
-// and zero where |j| > jmax.  HET = 0: <h|h> = coef[C_HH]; HET = 1:
-// <h|h>(t_j) as above from hhc [n], the H moments hpart [n_hch][n][mh]
-// complex, hw_step = 2 pi hw / (N R), c2 = 2 c and cden = 2 N R
-// (exp(-2 pi i c u_j) = exp(-2 pi i (c2 j mod cden) / cden)).  zout (else
-// NULL): [n][2 jmax + 1][3] = (Re Z(t_j), Im Z(t_j), <h|h>(t_j)), Re NaN for
-// unphysical rows, with f_0 t_j = j f0_num / f0_den cycles.
-template <int HET, int D1, int NZ>
-__global__ void __launch_bounds__(256, 2) k_tgrid(TgKernelArgs a) {
-  __shared__ double2 buf[kTgBuf];
-  __shared__ double2 sm[kTgHMax];
-  __shared__ double sinv[kTgHMax];  // 1 / (q + 1)
-  __shared__ double red[256], red2[256];
-  // Workgroups are dealt to the 8 XCDs in turn, each with its own L2; in the
-  // rows-fastest moment layout neighbouring rows share cache lines, so there
-  // workgroup i takes row (i mod 8) span + i / 8 and the rows of one XCD are
-  // consecutive (row-major moments: row i).
-  const int64_t span = (a.n + kTgXcds - 1) / kTgXcds;
-  const int64_t p = a.mom_es != 1 ? (int64_t)(blockIdx.x % kTgXcds) * span + blockIdx.x / kTgXcds
-                                  : (int64_t)blockIdx.x;
-  if (p >= a.n) return;  // whole workgroup, before any barrier
+// Epilogue of one row: Z(t_j) in buf [0, nt) in grid order (written before
+// the call, made visible by its first barrier); <h|h>(t_j), the staged
+// values (zout), ln I0(|Z|) - <h|h>/2 and a fixed-order log-sum-exp into
+// logl[p].  All 256 threads of the workgroup call it.
+template <int HET>
+__device__ inline void tg_epilogue(const TgKernelArgs& a, int64_t p, const double2* __restrict__ buf,
+                                   double2* __restrict__ sm, double* __restrict__ sinv, double* __restrict__ red,
+                                   double* __restrict__ red2) {
   const int tid = threadIdx.x;
-  const int L = a.L, D2 = D1 > 1 ? 16 : a.D2, K = a.K;
-  const int S1 = L / D1;  // = 16 D2
   const int nt = 2 * a.jmax + 1;
-  const double2* __restrict__ mrow = a.mom + p * a.mom_rs;
-  const int64_t es = a.mom_es;
-  const bool on1 = tid < S1, on3 = tid < L / 16;
-  double2 w1 = make_double2(1.0, 0.0), w2;
-  if (D1 > 1) {
-    double s, c;
-    sincospi(-2.0 * (double)tid / (double)L, &s, &c);
-    w1 = make_double2(c, s);
-  }
-  {
-    double s, c;
-    sincospi(-2.0 * (double)(tid & 15) / (double)(16 * D2), &s, &c);
-    w2 = make_double2(c, s);
-  }
-  double ar[16], ai[16];
-#pragma unroll
-  for (int o = 0; o < 16; ++o) ar[o] = ai[o] = 0.0;
-  // the first pass's inputs of the current order (prefetched one order
-  // ahead when they are few)
-  constexpr bool kPrefetch = NZ <= 4;
-  double2 x[NZ];
-  auto load = [&](int m) {
-    const double2* __restrict__ src = mrow + (int64_t)m * a.n_blk * es;
-#pragma unroll
-    for (int q = 0; q < NZ; ++q) {
-      const int b = tid + S1 * q;
-      x[q] = (on1 && b < a.n_blk) ? src[b * es] : make_double2(0.0, 0.0);
-    }
-  };
-  if (kPrefetch) load(0);
-  for (int m = 0; m < K; ++m) {
-    // The twiddle powers are formed afresh in every order: an empty asm
-    // statement marks the roots as changing here, so the compiler does not
-    // hoist 30 loop-invariant powers out of the loop (they would spill).
-    asm volatile("" : "+v"(w1.x), "+v"(w1.y), "+v"(w2.x), "+v"(w2.y));
-    if (!kPrefetch) load(m);
-    double2 v[D1];
-#pragma unroll
-    for (int q = 0; q < D1; ++q) v[q] = q < NZ ? x[q] : make_double2(0.0, 0.0);
-    if (kPrefetch && m + 1 < K) load(m + 1);
-    tg_pass1<D1, NZ>(v, w1);
-    __syncthreads();  // the previous order's last-pass reads are done
-    if (on1) {
-      const int pb = tg_pad(tid);
-#pragma unroll
-      for (int k = 0; k < D1; ++k) buf[pb + 17 * (S1 / 16) * k] = v[k];
-    }
-    __syncthreads();
-    if constexpr (D1 > 1) {
-      tg_lds_pass2<16>(buf, tid, D1, S1, w2);  // L >= 512: D2 = 16
-    } else {
-      switch (D2) {
-        case 16: tg_lds_pass2<16>(buf, tid, D1, S1, w2); break;
-        case 8: tg_lds_pass2<8>(buf, tid, D1, S1, w2); break;
-        case 4: tg_lds_pass2<4>(buf, tid, D1, S1, w2); break;
-        case 2: tg_lds_pass2<2>(buf, tid, D1, S1, w2); break;
-        default: break;
-      }
-    }
-    __syncthreads();
-    if (on3) {
-      double2 f[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) f[q] = buf[17 * tid + q];
-      Dft<16>::run_slots(f);
-      const double* __restrict__ cm = a.ccoef + ((int64_t)m * 256 + tid) * 16;
-      if ((m & 1) == 0) {
-#pragma unroll
-        for (int k3 = 0; k3 < 16; ++k3) {
-          const double t = cm[k3];
-          const double2 z = f[dft_slot<16>(k3)];
-          ar[k3] = fma(t, z.x, ar[k3]);
-          ai[k3] = fma(t, z.y, ai[k3]);
-        }
-      } else {
-#pragma unroll
-        for (int k3 = 0; k3 < 16; ++k3) {
-          const double t = cm[k3];
-          const double2 z = f[dft_slot<16>(k3)];
-          ar[k3] = fma(t, z.y, ar[k3]);
-          ai[k3] = fma(-t, z.x, ai[k3]);
-        }
-      }
-    }
-  }
   const bool valid = a.coef[C_VALID * a.ld + p] != 0.0;
-  // the finished Z(t_j) go to the buffer in grid order (nt <= L points), read
-  // back below in a plain loop
-  __syncthreads();
-  if (on3) {
-#pragma unroll
-    for (int k3 = 0; k3 < 16; ++k3) {
-      const int X = tg_owned(L, D1, D2, tid, k3);
-      const int j = X <= a.jmax ? X : X - L;
-      if (j >= -a.jmax && j <= a.jmax) buf[j + a.jmax] = make_double2(ar[k3], ai[k3]);
-    }
-  }
   double hh = 0.0;
   if (HET) {
     hh = a.hhc[p];
@@ -301,6 +189,168 @@ __global__ void __launch_bounds__(256, 2) k_tgrid(TgKernelArgs a) {
   if (tid == 0) a.logl[p] = valid ? -0.5 * a.dd + red[0] + log(red2[0]) - log((double)nt) : -INFINITY;
 }
 
+// mom: complex moments, row p, order m, block b at p mom_rs + (m n_blk + b)
+// mom_es (row-major [n][K][n_blk]: (K n_blk, 1); row fastest [K][n_blk][n]:
+// (1, n)).
+// ccoef: eps_m J_m(phi_j) for lane l's output slot k3 at (m 256 + l) 16 + k3,
+// with the sign of (-i)^m folded in (+ for m mod 4 in {0, 1}, - otherwise)
+// and zero where |j| > jmax.  HET = 0: <h|h> = coef[C_HH]; HET = 1:
+// <h|h>(t_j) as above from hhc [n], the H moments hpart [n_hch][n][mh]
+// complex, hw_step = 2 pi hw / (N R), c2 = 2 c and cden = 2 N R
+// (exp(-2 pi i c u_j) = exp(-2 pi i (c2 j mod cden) / cden)).  zout (else
+// NULL): [n][2 jmax + 1][3] = (Re Z(t_j), Im Z(t_j), <h|h>(t_j)), Re NaN for
+// unphysical rows, with f_0 t_j = j f0_num / f0_den cycles.
+template <int HET, int D1, int NZ>
+__global__ void __launch_bounds__(256, 2) k_tgrid(TgKernelArgs a) {
+  __shared__ double2 buf[kTgBuf];
+  __shared__ double2 sm[kTgHMax];
+  __shared__ double sinv[kTgHMax];  // 1 / (q + 1)
+  __shared__ double red[256], red2[256];
+  // Workgroups are dealt to the 8 XCDs in turn, each with its own L2; in the
+  // rows-fastest moment layout neighbouring rows share cache lines, so there
+  // workgroup i takes row (i mod 8) span + i / 8 and the rows of one XCD are
+  // consecutive (row-major moments: row i).
+  // With S > 1 order groups, workgroup i takes group i mod S of row slot
+  // i / S (the groups' partial sums are added by k_tgrid_fin).
+  const int g = (int)(blockIdx.x % (unsigned)a.S);
+  const int64_t w = blockIdx.x / (unsigned)a.S;
+  const int64_t span = (a.n + kTgXcds - 1) / kTgXcds;
+  const int64_t p = a.mom_es != 1 ? (w % kTgXcds) * span + w / kTgXcds : w;
+  if (p >= a.n) return;  // whole workgroup, before any barrier
+  const int tid = threadIdx.x;
+  const int L = a.L, D2 = D1 > 1 ? 16 : a.D2, K = a.K;
+  const int S1 = L / D1;  // = 16 D2
+  const int nt = 2 * a.jmax + 1;
+  const double2* __restrict__ mrow = a.mom + p * a.mom_rs;
+  const int64_t es = a.mom_es;
+  const bool on1 = tid < S1, on3 = tid < L / 16;
+  double2 w1 = make_double2(1.0, 0.0), w2;
+  if (D1 > 1) {
+    double s, c;
+    sincospi(-2.0 * (double)tid / (double)L, &s, &c);
+    w1 = make_double2(c, s);
+  }
+  {
+    double s, c;
+    sincospi(-2.0 * (double)(tid & 15) / (double)(16 * D2), &s, &c);
+    w2 = make_double2(c, s);
+  }
+  double ar[16], ai[16];
+#pragma unroll
+  for (int o = 0; o < 16; ++o) ar[o] = ai[o] = 0.0;
+  // the first pass's inputs of the current order (prefetched one order
+  // ahead when they are few)
+  constexpr bool kPrefetch = NZ <= 4;
+  double2 x[NZ];
+  auto load = [&](int m) {
+    const double2* __restrict__ src = mrow + (int64_t)m * a.n_blk * es;
+#pragma unroll
+    for (int q = 0; q < NZ; ++q) {
+      const int b = tid + S1 * q;
+      x[q] = (on1 && b < a.n_blk) ? src[b * es] : make_double2(0.0, 0.0);
+    }
+  };
+  const int m_lo = g * (K / a.S), m_hi = m_lo + K / a.S;  // this group's orders
+  if (kPrefetch) load(m_lo);
+  for (int m = m_lo; m < m_hi; ++m) {
+    // The twiddle powers are formed afresh in every order: an empty asm
+    // statement marks the roots as changing here, so the compiler does not
+    // hoist 30 loop-invariant powers out of the loop (they would spill).
+    asm volatile("" : "+v"(w1.x), "+v"(w1.y), "+v"(w2.x), "+v"(w2.y));
+    if (!kPrefetch) load(m);
+    double2 v[D1];
+#pragma unroll
+    for (int q = 0; q < D1; ++q) v[q] = q < NZ ? x[q] : make_double2(0.0, 0.0);
+    if (kPrefetch && m + 1 < m_hi) load(m + 1);
+    tg_pass1<D1, NZ>(v, w1);
+    __syncthreads();  // the previous order's last-pass reads are done
+    if (on1) {
+      const int pb = tg_pad(tid);
+#pragma unroll
+      for (int k = 0; k < D1; ++k) buf[pb + 17 * (S1 / 16) * k] = v[k];
+    }
+    __syncthreads();
+    if constexpr (D1 > 1) {
+      tg_lds_pass2<16>(buf, tid, D1, S1, w2);  // L >= 512: D2 = 16
+    } else {
+      switch (D2) {
+        case 16: tg_lds_pass2<16>(buf, tid, D1, S1, w2); break;
+        case 8: tg_lds_pass2<8>(buf, tid, D1, S1, w2); break;
+        case 4: tg_lds_pass2<4>(buf, tid, D1, S1, w2); break;
+        case 2: tg_lds_pass2<2>(buf, tid, D1, S1, w2); break;
+        default: break;
+      }
+    }
+    __syncthreads();
+    if (on3) {
+      double2 f[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) f[q] = buf[17 * tid + q];
+      Dft<16>::run_slots(f);
+      const double* __restrict__ cm = a.ccoef + ((int64_t)m * 256 + tid) * 16;
+      if ((m & 1) == 0) {
+#pragma unroll
+        for (int k3 = 0; k3 < 16; ++k3) {
+          const double t = cm[k3];
+          const double2 z = f[dft_slot<16>(k3)];
+          ar[k3] = fma(t, z.x, ar[k3]);
+          ai[k3] = fma(t, z.y, ai[k3]);
+        }
+      } else {
+#pragma unroll
+        for (int k3 = 0; k3 < 16; ++k3) {
+          const double t = cm[k3];
+          const double2 z = f[dft_slot<16>(k3)];
+          ar[k3] = fma(t, z.y, ar[k3]);
+          ai[k3] = fma(-t, z.x, ai[k3]);
+        }
+      }
+    }
+  }
+  if (a.S > 1) {  // this group's partial Z(t_j), finished by k_tgrid_fin
+    if (on3) {
+      double2* __restrict__ zp = a.zpart + ((int64_t)g * a.n + p) * nt + a.jmax;
+#pragma unroll
+      for (int k3 = 0; k3 < 16; ++k3) {
+        const int X = tg_owned(L, D1, D2, tid, k3);
+        const int j = X <= a.jmax ? X : X - L;
+        if (j >= -a.jmax && j <= a.jmax) zp[j] = make_double2(ar[k3], ai[k3]);
+      }
+    }
+    return;
+  }
+  // the finished Z(t_j) go to the buffer in grid order (nt <= L points), read
+  // back by the epilogue in a plain loop
+  __syncthreads();
+  if (on3) {
+#pragma unroll
+    for (int k3 = 0; k3 < 16; ++k3) {
+      const int X = tg_owned(L, D1, D2, tid, k3);
+      const int j = X <= a.jmax ? X : X - L;
+      if (j >= -a.jmax && j <= a.jmax) buf[j + a.jmax] = make_double2(ar[k3], ai[k3]);
+    }
+  }
+  tg_epilogue<HET>(a, p, buf, sm, sinv, red, red2);
+}
+
+// k_tgrid_fin: one workgroup per row adds the S groups' partial Z(t_j) in
+// group order and runs the epilogue.
+template <int HET>
+__global__ void __launch_bounds__(256) k_tgrid_fin(TgKernelArgs a) {
+  __shared__ double2 buf[kTgMaxL];
+  __shared__ double2 sm[kTgHMax];
+  __shared__ double sinv[kTgHMax];
+  __shared__ double red[256], red2[256];
+  const int64_t p = blockIdx.x;
+  const int nt = 2 * a.jmax + 1;
+  for (int jj = threadIdx.x; jj < nt; jj += 256) {
+    double2 z = a.zpart[p * nt + jj];
+    for (int g = 1; g < a.S; ++g) z = c_add(z, a.zpart[((int64_t)g * a.n + p) * nt + jj]);
+    buf[jj] = z;
+  }
+  tg_epilogue<HET>(a, p, buf, sm, sinv, red, red2);
+}
+
 gw_status tgrid_tables(gw_ctx* ctx, int L, int jmax, int K) {
   if (ctx->tm_ccoef && ctx->tm_cc_L == L && ctx->tm_cc_jmax == jmax && ctx->tm_cc_K == K) return GW_OK;
   int D1, D2;
@@ -330,7 +380,7 @@ int64_t tgrid_chunk_rows(int64_t n, int n_blk, int K) {
 
 template <int HET>
 static void launch_tgrid_form(const TgKernelArgs& k, int D1, int nz, unsigned n, hipStream_t st) {
-  const dim3 grid((unsigned)(kTgXcds * ((n + kTgXcds - 1) / kTgXcds))), blk(256);
+  const dim3 grid((unsigned)(k.S * kTgXcds * ((n + kTgXcds - 1) / kTgXcds))), blk(256);
   switch (D1) {
     case 16:
       switch (nz) {
@@ -346,6 +396,25 @@ static void launch_tgrid_form(const TgKernelArgs& k, int D1, int nz, unsigned n,
     case 2: hipLaunchKernelGGL((k_tgrid<HET, 2, 2>), grid, blk, 0, st, k); break;
     default: hipLaunchKernelGGL((k_tgrid<HET, 1, 1>), grid, blk, 0, st, k); break;
   }
+  if (k.S > 1) hipLaunchKernelGGL((k_tgrid_fin<HET>), dim3(n), blk, 0, st, k);
+}
+
+// Order groups per row: a launch of few rows (a sampler round) would leave
+// most of the 256 CUs idle with one workgroup per row, so its orders are
+// split over 2 or 4 workgroups, whose partial sums k_tgrid_fin adds.
+int tgrid_split(int64_t n, int K) {
+  if (n >= 512) return 1;
+  if (n >= 256 || K % 4 != 0) return K % 2 == 0 ? 2 : 1;
+  return 4;
+}
+
+int64_t tgrid_zpart_elems(int64_t n, int64_t chunk, int K, int nt) {
+  int64_t need = 0;
+  for (const int64_t cn : {n < chunk ? n : chunk, n % chunk}) {  // full chunks and the last one
+    const int S = tgrid_split(cn, K);
+    if (cn > 0 && S > 1) need = std::max(need, (int64_t)S * cn * nt);
+  }
+  return need;
 }
 
 gw_status launch_tgrid(const gw_ctx* ctx, const TGridArgs& a, hipStream_t st) {
@@ -385,6 +454,9 @@ gw_status launch_tgrid(const gw_ctx* ctx, const TGridArgs& a, hipStream_t st) {
   k.f0_num = a.f0_num;
   k.f0_den = a.f0_den;
   k.cden = 1;
+  k.S = tgrid_split(a.n, a.K);
+  k.zpart = (double2*)a.zpart;
+  if (k.S > 1 && !k.zpart) return set_error(GW_EINVAL, "time marginal: no workspace for the order groups");
   if (a.het) {
     k.hhc = a.hhc;
     k.hpart = (const double2*)a.hpart;

@@ -323,12 +323,16 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
     ctx->tm_basis_K = K;
   }
   const int64_t chunk = tgrid_chunk_rows(n, g.n_blk, K);
+  const int nt = 2 * g.J * g.R + 1;
+  // workspace: the moments of a row chunk, then the order groups' partial
+  // grids of a small launch
+  const int64_t zp = tgrid_zpart_elems(n, chunk, K, nt);
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
-  if (s == GW_OK) s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap, chunk * K * g.n_blk * 2, "time moments");
+  if (s == GW_OK)
+    s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap, chunk * K * g.n_blk * 2 + 2 * zp, "time moments");
   if (s != GW_OK) return s;
   s = launch_prologue(ctx, theta, n, GW_MARG_PHASE_TIME, ctx->coef, n, st);
   if (s != GW_OK) return s;
-  const int nt = 2 * g.J * g.R + 1;
   for (int64_t r0 = 0; r0 < n && s == GW_OK; r0 += chunk) {
     const int64_t cn = n - r0 < chunk ? n - r0 : chunk;
     const int tpb = cn >= 2048 ? 256 : 64;
@@ -358,6 +362,7 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
     a.zout = zout ? zout + r0 * nt * 3 : nullptr;
     a.f0_num = (double)(2 * ctx->geom.k0 + g.blk - 1);
     a.f0_den = (double)(2 * g.N) * (double)g.R;
+    a.zpart = zp > 0 ? ctx->tm_mom + chunk * K * g.n_blk * 2 : nullptr;
     const int gslot = prof_begin(ctx, st, 2);
     s = launch_tgrid(ctx, a, st);
     prof_end(ctx, gslot, st);
