@@ -322,7 +322,7 @@ gw_status gw_graph_info(const gw_ctx* ctx, int32_t* n_graphs, double* last_insta
  * and d_L marginalised (marg = GW_MARG_PHASE_DIST), or, with marg =
  * GW_MARG_PHASE_TIME (the paper's GW170817 configuration), phi_c and t_c
  * marginalised and d_L sampled as coordinate 10 in place of t_c (see
- * gw_prior_transform_marg); its rounds are launched without a graph.
+ * gw_prior_transform_marg).
  * A block holds 1 .. GW_MAX_BLOCK coordinates; one holding all 11 is the
  * unblocked nested slice sampler of the sampler-configuration section.
  * With F = GW_SLICE_UNI_FIXED(block_dim) = max(4, 2 ceil(block_dim / 2)) + 2:
@@ -369,9 +369,10 @@ typedef struct {
   int32_t* status;        /* device [k] 0 moved, 1 kept, or NULL */
   int32_t use_graph;      /* 1: replay a captured graph of 4 rounds (captured on
                              first use and again when k, like, marg, prec, the
-                             launch shapes, a workspace, the network or its
-                             scaling change); 0: launch each kernel.  Results
-                             are identical. */
+                             launch shapes, the time grid (window, oversampling,
+                             edge split), the heterodyne setup, a workspace,
+                             the network or its scaling change); 0: launch each
+                             kernel.  Results are identical. */
   gw_mlp* mlp;            /* learned prescreen (a network made on this context)
                              or NULL: see below */
   double margin;          /* with mlp: finite; candidates predicted

@@ -333,6 +333,7 @@ gw_status gw_set_full_shape(gw_ctx* ctx, int32_t tpb, int32_t n_chunks) {
   if (n_chunks < 0) return set_error(GW_EINVAL, "gw_set_full_shape: n_chunks < 0");
   ctx->full_tpb = tpb;
   ctx->full_chunks = n_chunks;
+  ++ctx->gen;
   return GW_OK;
 }
 
@@ -340,6 +341,7 @@ gw_status gw_set_full_kernel(gw_ctx* ctx, int32_t kind) {
   if (!ctx) return set_error(GW_EINVAL, "gw_set_full_kernel: ctx is NULL");
   if (kind < 0 || kind > 2) return set_error(GW_EINVAL, "gw_set_full_kernel: kind must be 0, 1 or 2");
   ctx->full_kernel = kind;
+  ++ctx->gen;
   return GW_OK;
 }
 

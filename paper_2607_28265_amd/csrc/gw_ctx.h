@@ -69,6 +69,9 @@ struct gw_ctx {
   int tm_basis_blk = 0, tm_basis_K = 0;
   double* tm_mom = nullptr;
   int64_t tm_mom_cap = 0;
+  // bumped by every setter that changes what a captured likelihood launch
+  // holds as arguments (grid shapes, launch shapes, heterodyne state)
+  uint64_t gen = 0;
   // sampler sky frame: 0 equatorial (ra, dec), 1 zenith and azimuth about the
   // baseline of detectors sky_a -> sky_b; sky_det_time: coordinate 10 is the
   // arrival time at detector sky_a
@@ -213,6 +216,9 @@ void prof_end(gw_ctx* ctx, int slot, hipStream_t st);
 gw_status full_reserve(gw_ctx* ctx, int64_t n);
 gw_status het_reserve(gw_ctx* ctx, int64_t n);
 void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech);
+// The heterodyned time marginal's table and index addresses and plan sizes
+// (zeros without heterodyne state), for keying captured graphs.
+void het_tm_key(const gw_ctx* ctx, const void** tab, const void** idx, int32_t* nch, int32_t* nslot, int32_t* nsplit);
 
 // Heterodyne and graph state owned by the context.
 void het_free(gw_ctx* ctx);
@@ -238,5 +244,9 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
                                hipStream_t st);
 gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int prec, double* logl,
                                    double* zout, hipStream_t st);
+// Build the tables and size the work space a phase+time marginal of n rows
+// uses (like GW_FULL or GW_HET), launching nothing: afterwards such a call
+// allocates nothing and can be captured into a graph.
+gw_status tmarg_reserve(gw_ctx* ctx, int64_t n, int like);
 
 }  // namespace gw

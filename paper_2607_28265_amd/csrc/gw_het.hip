@@ -799,6 +799,15 @@ void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech)
   *ech = ctx->het ? ctx->het->ech : 0;
 }
 
+void het_tm_key(const gw_ctx* ctx, const void** tab, const void** idx, int32_t* nch, int32_t* nslot, int32_t* nsplit) {
+  const gw_het_state* h = ctx->het;
+  *tab = h ? h->tm_tab : nullptr;
+  *idx = h ? h->tm_idx : nullptr;
+  *nch = h ? h->tm_nch : 0;
+  *nslot = h ? h->tm_nslot : 0;
+  *nsplit = h ? h->tm_nsplit : 0;
+}
+
 // ---------------------------------------------------------------------------
 // Time marginal on the binned likelihood (the appendix's direct sum on the
 // heterodyned bins).  A shift t multiplies every edge phasor by
@@ -1108,7 +1117,7 @@ gw_status loglike_het_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, 
                       chunk * K * g.n_blk * 2 + (int64_t)h->tm_nslot * K * chunk * 2 +
                           (int64_t)h->tm_nch * chunk * mh * 2 + chunk + 1 + 2 * zp,
                       "time-marginal workspace");
-  if (s != GW_OK) return s;
+  if (s != GW_OK || !theta) return s;  // theta NULL: reserve only
   double2* mom = (double2*)ctx->tm_mom;
   double2* part = mom + chunk * K * g.n_blk;
   double2* hpart = part + (int64_t)h->tm_nslot * K * chunk;
@@ -1333,6 +1342,7 @@ gw_status heterodyne_setup(gw_ctx* ctx, const double* theta0, int32_t n_bins, in
     }
   }
   ctx->het = h;
+  ++ctx->gen;
   if (edges_out)
     for (int e = 0; e < ne; ++e) edges_out[e] = h->f_edges[e];
   return GW_OK;
@@ -1416,6 +1426,7 @@ gw_status gw_set_het_shape(gw_ctx* ctx, int32_t waves_per_block, int32_t grid, i
   ctx->het->wpb = waves_per_block;
   ctx->het->grid = grid;
   ctx->het->ech = n_ech;
+  ++ctx->gen;
   return GW_OK;
 }
 
@@ -1424,6 +1435,7 @@ gw_status gw_set_het_tm_split(gw_ctx* ctx, int32_t n_chunks) {
   if (n_chunks < 0 || n_chunks > 256 || (n_chunks & (n_chunks - 1)) != 0)
     return set_error(GW_EINVAL, "gw_set_het_tm_split: n_chunks must be 0 or a power of two up to 256");
   ctx->tm_nsk = n_chunks;
+  ++ctx->gen;
   return GW_OK;
 }
 

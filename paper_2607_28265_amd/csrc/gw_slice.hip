@@ -586,8 +586,10 @@ struct SliceGraphKey {
   int64_t k;
   int32_t like, marg, prec, cache;
   const void *ws_mem, *coef, *partial, *zbuf, *het, *wc, *mlp;
-  uint64_t mlp_scale;
+  uint64_t mlp_scale, gen;
+  const void *tm_mom, *tm_ccoef, *tm_basis, *tm_tab, *tm_idx;
   int32_t het_wpb, het_grid, het_ech, full_tpb, full_chunks, full_kernel;
+  int32_t tm_nch, tm_nslot, tm_nsplit, tm_pad;
   bool operator==(const SliceGraphKey& o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
 };
 
@@ -671,6 +673,7 @@ template <class Group>
 static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const SweepCall& a, Group group) {
   const int64_t n = 2 * k;
   gw_status s = a.lists ? cached_reserve(ctx, n) : a.like == GW_HET ? het_reserve(ctx, n) : full_reserve(ctx, n);
+  if (s == GW_OK && a.marg == GW_MARG_PHASE_TIME) s = tmarg_reserve(ctx, n, a.like);
   if (s != GW_OK) return s;
   SliceGraphKey key;
   memset(&key, 0, sizeof(key));
@@ -691,6 +694,13 @@ static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const Swee
   key.full_kernel = ctx->full_kernel;
   key.mlp = a.mlp;
   key.mlp_scale = a.mlp ? mlp_scale_version(a.mlp) : 0;
+  key.gen = ctx->gen;
+  if (a.marg == GW_MARG_PHASE_TIME) {
+    key.tm_mom = ctx->tm_mom;
+    key.tm_ccoef = ctx->tm_ccoef;
+    key.tm_basis = ctx->tm_basis;
+    het_tm_key(ctx, &key.tm_tab, &key.tm_idx, &key.tm_nch, &key.tm_nslot, &key.tm_nsplit);
+  }
   if (ws->have_graph && ws->key == key) return GW_OK;
   if (ws->exec) (void)hipGraphExecDestroy(ws->exec);
   if (ws->graph) (void)hipGraphDestroy(ws->graph);
@@ -982,9 +992,7 @@ gw_status slice_step(gw_ctx* ctx, const gw_slice_args* a, void* stream) {
   if (s == GW_OK) s = set_screen("slice_step", ctx, a->mlp, a->margin, a->audit_frac, P);
   if (s == GW_OK) s = set_record("slice_step", a->rec_x, a->rec_logl, a->rec_cap, a->rec_count, P);
   if (s != GW_OK) return s;
-  // the time marginal builds its tables and sizes its workspace on first
-  // use, which a captured graph cannot do: its rounds are launched eagerly
-  const int32_t graph = a->use_graph && a->marg != GW_MARG_PHASE_TIME;
+  const int32_t graph = a->use_graph;
   const SweepCall c{a->like, a->marg, a->prec, graph, a->n_evals, a->status, 0, nullptr, P.lists,
                     P.screen ? a->mlp : nullptr, a->screen_stats};
   return run_sweep(ctx, P, c, (hipStream_t)stream);
@@ -1041,7 +1049,7 @@ gw_status slice_sweep(gw_ctx* ctx, const gw_sweep_args* a, void* stream) {
   if (s == GW_OK) s = set_screen("slice_sweep", ctx, a->mlp, a->margin, a->audit_frac, P);
   if (s == GW_OK) s = set_record("slice_sweep", a->rec_x, a->rec_logl, a->rec_cap, a->rec_count, P);
   if (s != GW_OK) return s;
-  const int32_t graph = a->use_graph && a->marg != GW_MARG_PHASE_TIME;  // as in slice_step
+  const int32_t graph = a->use_graph;
   const SweepCall c{a->like, a->marg, a->prec, graph, a->n_evals, a->status, P.cache, a->eval_kinds, P.lists,
                     P.screen ? a->mlp : nullptr, a->screen_stats};
   return run_sweep(ctx, P, c, (hipStream_t)stream);

@@ -330,7 +330,7 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
   s = ensure_buffer(&ctx->coef, &ctx->coef_cap, (int64_t)C_NCOEF * n, "coefficient workspace");
   if (s == GW_OK)
     s = ensure_buffer(&ctx->tm_mom, &ctx->tm_mom_cap, chunk * K * g.n_blk * 2 + 2 * zp, "time moments");
-  if (s != GW_OK) return s;
+  if (s != GW_OK || !theta) return s;  // theta NULL: reserve only
   s = launch_prologue(ctx, theta, n, GW_MARG_PHASE_TIME, ctx->coef, n, st);
   if (s != GW_OK) return s;
   for (int64_t r0 = 0; r0 < n && s == GW_OK; r0 += chunk) {
@@ -370,6 +370,11 @@ gw_status loglike_tmarg_staged(gw_ctx* ctx, const double* theta, int64_t n, int 
   return s;
 }
 
+gw_status tmarg_reserve(gw_ctx* ctx, int64_t n, int like) {
+  return like == GW_HET ? loglike_het_tmarg_staged(ctx, nullptr, n, GW_PREC_FP64, nullptr, nullptr, 0)
+                        : loglike_tmarg_staged(ctx, nullptr, n, GW_PREC_FP64, nullptr, nullptr, 0);
+}
+
 }  // namespace gw
 
 extern "C" gw_status gw_set_time_window(gw_ctx* ctx, double window) {
@@ -380,6 +385,7 @@ extern "C" gw_status gw_set_time_window(gw_ctx* ctx, double window) {
   gw::TimeGrid g;
   const gw_status s = gw::time_grid(ctx, &g);
   if (s != GW_OK) ctx->tm_window = old;
+  else ++ctx->gen;
   return s;
 }
 
@@ -388,6 +394,7 @@ extern "C" gw_status gw_set_time_oversample(gw_ctx* ctx, int32_t factor) {
   if (factor != 1 && factor != 2 && factor != 4 && factor != 8 && factor != 16)
     return gw::set_error(GW_EINVAL, "gw_set_time_oversample: factor must be 1, 2, 4, 8 or 16");
   ctx->tm_R = factor;
+  ++ctx->gen;
   return GW_OK;
 }
 

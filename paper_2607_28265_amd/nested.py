@@ -84,6 +84,8 @@ class NestedSampler:
         self.dead_logl: list[float] = []
         self.dead_logw: list[float] = []
         self.dead_x: list[np.ndarray] = []
+        self._log_z_dead = -math.inf  # log-sum-exp of dead_logw, kept as points die
+        self._host = None  # host copies (x, logL) of the live set, or None when stale
         self.log_x = 0.0
         self.iteration = 0
         self.counter = 0
@@ -122,7 +124,7 @@ class NestedSampler:
 
     # -- evidence ----------------------------------------------------------
     def log_z_dead(self):
-        return _logsumexp(self.dead_logw)
+        return self._log_z_dead
 
     def log_z_live(self, logl_host):
         return self.log_x + _logsumexp(logl_host) - math.log(self.m)
@@ -136,22 +138,25 @@ class NestedSampler:
     # -- one iteration -----------------------------------------------------
     def step(self):
         torch = self.torch
-        logl = self.logl.cpu().numpy()
-        x_host = self.x.cpu().numpy()
+        x_host, logl = self.live_host()
         order = np.argsort(logl, kind="stable")
         worst = order[: self.k]
         lstar = float(logl[worst[-1]])
+        new_w = []
         for j, i in enumerate(worst):
             new_log_x = self.log_x - 1.0 / (self.m - j)
             self.dead_logl.append(float(logl[i]))
-            self.dead_logw.append(float(logl[i]) + self.log_x + math.log1p(-math.exp(new_log_x - self.log_x)))
+            new_w.append(float(logl[i]) + self.log_x + math.log1p(-math.exp(new_log_x - self.log_x)))
             self.dead_x.append(x_host[i].copy())
             self.log_x = new_log_x
+        self.dead_logw.extend(new_w)
+        self._log_z_dead = float(np.logaddexp(self._log_z_dead, _logsumexp(new_w)))
         survivors = order[self.k:]
         starts = self.rng.choice(survivors, size=self.k, replace=True)
         chols = []
+        x_surv = x_host[survivors]
         for b in self.blocks:
-            sub = x_host[survivors][:, list(b)]
+            sub = x_surv[:, list(b)]
             cov = np.atleast_2d(np.cov(sub, rowvar=False)) + 1e-12 * np.eye(len(b))
             chols.append(np.linalg.cholesky(cov))
         idx = torch.from_numpy(starts).to(self.dev)
@@ -160,6 +165,8 @@ class NestedSampler:
         ne = torch.zeros(self.k, dtype=torch.int32, device=self.dev)
         caps = torch.zeros(self.k, dtype=torch.int32, device=self.dev)
         pre = self._prescreen(lstar)
+        sums = []  # per call on the device: (likelihood calls, chains kept), read once per iteration
+        moved = 0  # chain-blocks run by those calls
         if self.async_sweep:
             # the M sweeps' blocks in order, at most 16 per call: the same
             # moves as one call per sweep (block j of the sequence draws from
@@ -178,8 +185,8 @@ class NestedSampler:
                     self.eval_kinds += np.array(kinds, np.int64)
                 if st:
                     self._count_screen(st)
-                self.n_evals += int(ne.sum().item())
-                self.moves += self.k * len(part) - int(caps.sum().item())
+                sums.append(torch.stack((ne.sum(), caps.sum())))
+                moved += self.k * len(part)
                 self.counter += len(part)
         for _ in range(0 if self.async_sweep else self.sweeps):
             for bi, b in enumerate(self.blocks):
@@ -190,13 +197,28 @@ class NestedSampler:
                                 screen_stats=st, record=self.rec if self.pre is not None else None)
                 if st:
                     self._count_screen(st)
-                self.n_evals += int(ne.sum().item())
-                self.moves += self.k - int(caps.sum().item())
+                sums.append(torch.stack((ne.sum(), caps.sum())))
+                moved += self.k
                 self.counter += 1
         wi = torch.from_numpy(worst).to(self.dev)
         self.x.index_copy_(0, wi, xn)
         self.logl.index_copy_(0, wi, ln)
+        # one copy back: the new points (to update the host copies) and the counts
+        cnt = torch.cat(sums).reshape(-1, 2).sum(0).to(torch.float64) if sums else torch.zeros(2, dtype=torch.float64,
+                                                                                                device=self.dev)
+        pack = torch.cat((xn.reshape(-1), ln, cnt)).cpu().numpy()
+        x_host[worst] = pack[: self.k * N_DIM].reshape(self.k, N_DIM)
+        logl[worst] = pack[self.k * N_DIM: self.k * (N_DIM + 1)]
+        self.n_evals += int(pack[-2])
+        self.moves += moved - int(pack[-1])
         self.iteration += 1
+
+    def live_host(self):
+        """Host copies (x [m, 11], logL [m]) of the live set; the sampler keeps
+        them current, so the caller must not change them."""
+        if self._host is None:
+            self._host = (self.x.cpu().numpy(), self.logl.cpu().numpy())
+        return self._host
 
     def _count_screen(self, st):
         for key in self.screen_stats:
@@ -235,7 +257,7 @@ class NestedSampler:
         t0 = time.perf_counter()
         while self.iteration < max_iter:
             self.step()
-            logl = self.logl.cpu().numpy()
+            logl = self.live_host()[1]
             if verbose and self.iteration % 20 == 0:
                 print(f"it {self.iteration} logL*={max(self.dead_logl[-self.k:]):.3f} "
                       f"logZ_dead={self.log_z_dead():.3f} evals={self.n_evals}", flush=True)
@@ -295,6 +317,8 @@ class NestedSampler:
         self.logl = self.torch.from_numpy(d["logl"]).to(self.dev)
         self.dead_logl = list(d["dead_logl"])
         self.dead_logw = list(d["dead_logw"])
+        self._log_z_dead = _logsumexp(self.dead_logw)
+        self._host = None
         self.dead_x = list(d["dead_x"])
         self.log_x = float(d["log_x"])
         self.iteration = int(d["iteration"])

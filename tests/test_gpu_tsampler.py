@@ -106,6 +106,47 @@ def test_heterodyned_time_marginal_sweep_matches_oracle(monkeypatch):
     assert n_cmp >= len(xs) - 2
 
 
+@pytest.mark.parametrize("like", [0, 1])
+def test_time_marginal_graph_replay_equals_eager(like):
+    # the rounds' captured graph runs the kernels the eager launches run, in
+    # the same order: identical moves.  A new time window or a new chain
+    # count between calls must re-capture it (a stale graph would keep the
+    # old grid's shapes).
+    import paper_2607_28265_amd as gw
+    prob = problem("cfg1", loud=True)
+    d_lo, d_hi = prob.dist_grid[0], prob.dist_grid[-1]
+    rng = np.random.default_rng(23)
+    u0 = to_unit_time(prob.theta_inj, d_lo, d_hi)
+    x = np.clip(u0 + 0.01 * rng.standard_normal((48, 11)), 0.001, 0.999)
+    blocks = list(S.BLOCKS)
+    chols = [S.block_cholesky(x, b) for b in blocks]
+    marg, prec = gw.GW_MARG_PHASE_TIME, gw.GW_PREC_MIXED
+    with gw.Context(prob) as ctx:
+        if like == gw.GW_HET:
+            ctx.heterodyne_setup(prob.theta_inj, 200)
+        for call, (window, k) in enumerate([(0.1, 48), (0.1, 48), (0.03, 48), (0.03, 30), (0.1, 30)]):
+            gw.gw_set_time_window(ctx.handle, window)
+            xt = torch.from_numpy(x[:k].copy()).cuda()
+            th = gw.gw_prior_transform(ctx.handle, xt, marg=marg)
+            l0 = gw.loglike_batch(ctx.handle, th, like, marg, prec).cpu().numpy()
+            lstar = float(np.quantile(l0, 0.3))
+            keep = l0 > lstar
+            outs = []
+            for g in (False, True):
+                xg = torch.from_numpy(x[:k][keep].copy()).cuda()
+                lg = torch.from_numpy(l0[keep].copy()).cuda()
+                ne = torch.zeros(len(xg), dtype=torch.int32, device="cuda")
+                st = torch.zeros(len(xg), dtype=torch.int32, device="cuda")
+                gw.slice_sweep(ctx.handle, xg, lg, lstar, blocks, chols, seed=3, counter=50 * call, w=1.0,
+                               max_out=4, max_shrink=60, like=like, marg=marg, prec=prec, n_evals=ne, status=st,
+                               use_graph=g)
+                torch.cuda.synchronize()
+                outs.append((xg.cpu().numpy(), lg.cpu().numpy(), ne.cpu().numpy(), st.cpu().numpy()))
+            for a, b in zip(*outs):
+                assert np.array_equal(a, b), (call, window, k)
+            assert outs[0][2].sum() > 0
+
+
 def test_evidence_agrees_between_marginalisations():
     # three Gibbs sweeps per replacement: with one, runs on this problem that
     # differ only in their random numbers can miss the main mode and land far
