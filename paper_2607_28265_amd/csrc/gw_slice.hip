@@ -195,29 +195,63 @@ __device__ inline void prior_transform(const double* u, double* th, const CubeMa
 __device__ inline int start_block(const SweepParams& P, const SliceState& S, int64_t c, int b) {
   const int bd = P.bd[b];
   const int nfix = uni_fixed(bd);
+  // the fixed uniforms 0 .. nfix - 1 (nfix <= 14): each Philox block of four
+  // is drawn once, giving the values slice_uniform returns one at a time
+  double un[16];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (4 * q < nfix) {
+      if (P.uniforms) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+          un[4 * q + w] = 4 * q + w < nfix ? P.uniforms[c * (nfix + P.max_shrink) + 4 * q + w] : 0.5;
+      } else {
+        uint64_t ctr[4] = {P.counter + (uint64_t)b, (uint64_t)c, (uint64_t)q, 0ull};
+        philox4x64(ctr, P.seed, 0ull);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) un[4 * q + w] = philox_unit(ctr[w]);
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) un[4 * q + w] = 0.5;
+    }
+  }
+  // normals for the block's coordinates only
   double z[kMaxBlock + 1];
-  for (int p = 0; 2 * p < nfix - 1; ++p) {
-    const double r = sqrt(-2.0 * log(slice_uniform(P, b, c, 2 * p)));
-    double sn, cs;
-    sincos(kTwoPi * slice_uniform(P, b, c, 2 * p + 1), &sn, &cs);
-    if (2 * p < bd) z[2 * p] = r * cs;
-    if (2 * p + 1 < bd) z[2 * p + 1] = r * sn;
+#pragma unroll
+  for (int p = 0; p < (kMaxBlock + 1) / 2; ++p) {
+    z[2 * p] = z[2 * p + 1] = 0.0;
+    if (2 * p < bd) {
+      const double r = sqrt(-2.0 * log(un[2 * p]));
+      double sn, cs;
+      sincos(kTwoPi * un[2 * p + 1], &sn, &cs);
+      z[2 * p] = r * cs;
+      z[2 * p + 1] = r * sn;
+    }
   }
   double nrm = 0.0;
-  for (int j = 0; j < bd; ++j) nrm += z[j] * z[j];
+#pragma unroll
+  for (int j = 0; j < kMaxBlock; ++j)
+    if (j < bd) nrm += z[j] * z[j];
   nrm = sqrt(nrm);
   const double* L = P.chol + P.choff[b];
   for (int a = 0; a < kMaxBlock; ++a) {
     double v = 0.0;
-    for (int q = 0; q < bd; ++q)
-      if (a < bd) v += L[a * bd + q] * (z[q] / nrm);
+#pragma unroll
+    for (int q = 0; q < kMaxBlock; ++q)
+      if (q < bd && a < bd) v += L[a * bd + q] * (z[q] / nrm);
     S.d[c * kMaxBlock + a] = a < bd ? v : 0.0;
   }
-  const double off = slice_uniform(P, b, c, nfix - 2);
+  double off = 0.0, vsplit = 0.0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (j == nfix - 2) off = un[j];
+    if (j == nfix - 1) vsplit = un[j];
+  }
   S.t_lo[c] = -off * P.w;
   S.t_hi[c] = (1.0 - off) * P.w;
   const int budget = 2 * P.max_out + 1;
-  const int j_lo = (int)floor((double)budget * slice_uniform(P, b, c, nfix - 1));
+  const int j_lo = (int)floor((double)budget * vsplit);
   const int j_hi = budget - 1 - j_lo;
   S.n_out[2 * c] = j_lo;
   S.n_out[2 * c + 1] = j_hi;
@@ -459,8 +493,10 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep_update(const SweepParam
     }
   }
   S.flags[c] = fl;
+  // one atomic per wave for the count of chains still moving
+  const unsigned long long act = __ballot(!(fl & 4));
+  if (act && (int)__lane_id() == __ffsll((long long)act) - 1) atomicAdd(S.n_active, (int32_t)__popcll(act));
   if (!(fl & 4)) {
-    atomicAdd(S.n_active, 1);
     // The waveform is rebuilt lazily, when a chain is in an extrinsic block
     // with a stale cache, after this round, from the coefficients of a row of
     // this round that has the chain's intrinsic parameters: the accepted row
