@@ -108,7 +108,7 @@ struct SliceState {
   int32_t* cur;      // current block
   int32_t* tot_evals;
   int32_t* n_caps;   // blocks whose shrink cap was hit
-  int32_t* n_active;
+  int32_t* n_active;  // [2] chains still moving after a round (the fused rounds alternate)
   // row lists and waveform cache bookkeeping (list mode only)
   int32_t* rkind;      // [2k]: 0 no likelihood, 1 full, 2 cached waveform, 3 cached sums
   int32_t* zsrc;       // [2k]: slot whose cached sums the row uses, or -1
@@ -311,12 +311,9 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep_init(const SweepParams*
 // Write the candidates of every chain that is still moving: the two bracket
 // ends while stepping out, else one shrink draw (points outside the cube
 // count as rejections immediately, without a likelihood call).
-__global__ void __launch_bounds__(kSweepThreads) k_sweep_propose(const SweepParams* __restrict__ D, SliceState S, double* __restrict__ cand) {
-  const SweepParams& P = *D;
+__device__ inline void propose_chain(const SweepParams& P, const SliceState& S, double* __restrict__ cand,
+                                     int64_t c) {
   const double* __restrict__ x0 = P.x;
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c == 0) *S.n_active = 0;
-  if (c >= P.k) return;
   int fl = S.flags[c];
   double u[kSliceDim];
   int ok[2] = {0, 0};
@@ -325,6 +322,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep_propose(const SweepPara
   for (int guard = 0; guard <= kMaxBlocks && !(fl & 4) && !ok[0] && !ok[1]; ++guard) {
     const int b = S.cur[c];
     if (fl & 3) {
+      #pragma unroll
       for (int side = 0; side < 2; ++side) {
         if (!(fl & (1 << side))) continue;
         const double t = side == 0 ? S.t_lo[c] : S.t_hi[c];
@@ -365,6 +363,7 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep_propose(const SweepPara
     }
   }
   // rows that need no likelihood get an unphysical vector (cheap -inf)
+  #pragma unroll
   for (int side = 0; side < 2; ++side)
     if (!ok[side]) {
       double* th = cand + (2 * c + side) * 13;
@@ -389,6 +388,14 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep_propose(const SweepPara
     S.rkind[2 * c] = ok[0] ? kd : 0;
     S.rkind[2 * c + 1] = ok[1] ? kd : 0;
   }
+}
+
+__global__ void __launch_bounds__(kSweepThreads) k_sweep_propose(const SweepParams* __restrict__ D, SliceState S, double* __restrict__ cand) {
+  const SweepParams& P = *D;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) *S.n_active = 0;
+  if (c >= P.k) return;
+  propose_chain(P, S, cand, c);
 }
 
 // Prescreen decision per candidate slot (after the network has written pred):
@@ -417,14 +424,14 @@ __device__ inline void record_pair(const SweepParams& P, const SliceState& S, in
   P.rec_l[pos] = v;
 }
 
-__global__ void __launch_bounds__(kSweepThreads) k_sweep_update(const SweepParams* __restrict__ D, SliceState S, const double* __restrict__ cand_logl) {
-  const SweepParams& P = *D;
+// Returns the chain's flags (4 set once its sweep is done, also when it was
+// done before this round).
+__device__ inline int update_chain(const SweepParams& P, const SliceState& S, const double* __restrict__ cand_logl,
+                                   int64_t c) {
   double* __restrict__ x = P.x;
   double* __restrict__ logl = P.logl;
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= P.k) return;
   int fl = S.flags[c];
-  if (fl & 4) return;
+  if (fl & 4) return fl;
   const int b = S.cur[c];  // the block of this round's rows
   const bool stepping = (fl & 3) != 0;
   bool moved = false;
@@ -493,9 +500,6 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep_update(const SweepParam
     }
   }
   S.flags[c] = fl;
-  // one atomic per wave for the count of chains still moving
-  const unsigned long long act = __ballot(!(fl & 4));
-  if (act && (int)__lane_id() == __ffsll((long long)act) - 1) atomicAdd(S.n_active, (int32_t)__popcll(act));
   if (!(fl & 4)) {
     // The waveform is rebuilt lazily, when a chain is in an extrinsic block
     // with a stale cache, after this round, from the coefficients of a row of
@@ -522,6 +526,34 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep_update(const SweepParam
       }
     }
   }
+  return fl;
+}
+
+// Count the chains still moving (flags without 4): one atomic per wave.
+__device__ inline void count_active(int32_t* n_active, int fl) {
+  const unsigned long long act = __ballot(!(fl & 4));
+  if (act && (int)__lane_id() == __ffsll((long long)act) - 1) atomicAdd(n_active, (int32_t)__popcll(act));
+}
+
+__global__ void __launch_bounds__(kSweepThreads) k_sweep_update(const SweepParams* __restrict__ D, SliceState S, const double* __restrict__ cand_logl) {
+  const SweepParams& P = *D;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.k) return;
+  count_active(S.n_active, update_chain(P, S, cand_logl, c));
+}
+
+// One round's update followed by the next round's proposals, for calls with
+// no waveform cache, prescreen or record: the same per-chain steps in the same
+// order as k_sweep_update then k_sweep_propose, in one launch.  Moving chains
+// are counted in n_active[slot]; n_active[slot ^ 1], which the next round
+// counts into, is cleared here.
+__global__ void __launch_bounds__(kSweepThreads) k_sweep_step(const SweepParams* __restrict__ D, SliceState S, const double* __restrict__ cand_logl, double* __restrict__ cand, int slot) {
+  const SweepParams& P = *D;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) S.n_active[slot ^ 1] = 0;
+  if (c >= P.k) return;
+  count_active(S.n_active + slot, update_chain(P, S, cand_logl, c));
+  propose_chain(P, S, cand, c);
 }
 
 // Row lists of the cached likelihood: rows of kind 1 and 2 in ascending
@@ -625,7 +657,7 @@ struct SliceGraphKey {
   uint64_t mlp_scale, gen;
   const void *tm_mom, *tm_ccoef, *tm_basis, *tm_tab, *tm_idx;
   int32_t het_wpb, het_grid, het_ech, full_tpb, full_chunks, full_kernel;
-  int32_t tm_nch, tm_nslot, tm_nsplit, tm_pad;
+  int32_t tm_nch, tm_nslot, tm_nsplit, fused;
   bool operator==(const SliceGraphKey& o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
 };
 
@@ -706,7 +738,7 @@ static gw_status eval_rows(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const SweepC
 // changes) on the workspace's own capture stream.  Buffers the likelihood
 // would grow are reserved first: no allocation may happen during capture.
 template <class Group>
-static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const SweepCall& a, Group group) {
+static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const SweepCall& a, bool fused, Group group) {
   const int64_t n = 2 * k;
   gw_status s = a.lists ? cached_reserve(ctx, n) : a.like == GW_HET ? het_reserve(ctx, n) : full_reserve(ctx, n);
   if (s == GW_OK && a.marg == GW_MARG_PHASE_TIME) s = tmarg_reserve(ctx, n, a.like);
@@ -731,6 +763,7 @@ static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const Swee
   key.mlp = a.mlp;
   key.mlp_scale = a.mlp ? mlp_scale_version(a.mlp) : 0;
   key.gen = ctx->gen;
+  key.fused = fused ? 1 : 0;
   if (a.marg == GW_MARG_PHASE_TIME) {
     key.tm_mom = ctx->tm_mom;
     key.tm_ccoef = ctx->tm_ccoef;
@@ -932,12 +965,23 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
   // previous group's count is read: the host waits on group g while group
   // g + 1 runs, and at most one group of idle rounds follows the last move.
   const int max_rounds = P.nb * (2 * P.max_out + 1 + P.max_shrink + 1);
+  // Without a cache, prescreen or record, a round's update and the next
+  // round's proposals run as one kernel (k_sweep_step) and the first
+  // proposals are launched once before the groups.
+  const bool fused = !a.cache && !a.mlp && !P.record;
+  if (s == GW_OK && fused) {
+    hipLaunchKernelGGL(k_sweep_propose, dim3(blocks), dim3(tpb), 0, st, (const SweepParams*)ws->dev, ws->S,
+                       ws->cand);
+    s = check_hip(hipGetLastError(), "slice propose launch");
+  }
   auto group = [&](hipStream_t gs) -> gw_status {
     gw_status g = GW_OK;
     for (int r = 0; r < 4 && g == GW_OK; ++r) {
-      hipLaunchKernelGGL(k_sweep_propose, dim3(blocks), dim3(tpb), 0, gs, (const SweepParams*)ws->dev, ws->S,
-                         ws->cand);
-      g = check_hip(hipGetLastError(), "slice propose launch");
+      if (!fused) {
+        hipLaunchKernelGGL(k_sweep_propose, dim3(blocks), dim3(tpb), 0, gs, (const SweepParams*)ws->dev, ws->S,
+                           ws->cand);
+        g = check_hip(hipGetLastError(), "slice propose launch");
+      }
       if (g == GW_OK && a.mlp) {
         g = mlp_infer(a.mlp, ws->S.ucand, 2 * k, ws->S.pred, gs);
         if (g == GW_OK) {
@@ -947,7 +991,11 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
         }
       }
       if (g == GW_OK) g = eval_rows(ctx, ws, k, a, gs);
-      if (g == GW_OK) {
+      if (g == GW_OK && fused) {
+        hipLaunchKernelGGL(k_sweep_step, dim3(blocks), dim3(tpb), 0, gs, (const SweepParams*)ws->dev, ws->S,
+                           (const double*)ws->cand_logl, ws->cand, r & 1);
+        g = check_hip(hipGetLastError(), "slice step launch");
+      } else if (g == GW_OK) {
         hipLaunchKernelGGL(k_sweep_update, dim3(blocks), dim3(tpb), 0, gs, (const SweepParams*)ws->dev, ws->S,
                            (const double*)ws->cand_logl);
         g = check_hip(hipGetLastError(), "slice update launch");
@@ -958,13 +1006,15 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
     }
     return g;
   };
-  if (s == GW_OK && a.use_graph) s = slice_graph(ctx, ws, k, a, group);
+  if (s == GW_OK && a.use_graph) s = slice_graph(ctx, ws, k, a, fused, group);
   int cur = 0, prev = -1;
   for (int rounds = 0; s == GW_OK && rounds < max_rounds; rounds += 4) {
     if (a.use_graph) s = check_hip(hipGraphLaunch(ws->exec, st), "slice graph launch");
     else s = group(st);
     if (s != GW_OK) break;
-    s = check_hip(hipMemcpyAsync(ws->h_active + cur, ws->S.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+    // a group's last round (r = 3) counts into n_active[1] when fused
+    s = check_hip(hipMemcpyAsync(ws->h_active + cur, ws->S.n_active + (fused ? 1 : 0), sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, st),
                   "copy");
     if (s == GW_OK) s = check_hip(hipEventRecord(ws->ev[cur], st), "slice event");
     if (s != GW_OK) break;
@@ -1162,10 +1212,10 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
   // doubles: t_lo, t_hi, d[kMaxBlock], cand_t[2], cand[26], cand_logl[2], zrow[2][2 kMaxDet],
   // zc[3][2 kMaxDet], ucand[2][11], pred[2];
   // ints: flags, n_out[2], n_shrink, n_evals, slot_ok[2], cur, tot_evals, n_caps, rkind[2], zsrc[2],
-  // build_list, build_src, dirty, slow_rows[2], stream_rows[2], scr[2], side_tests[2], then the active
-  // counter and the three list counts
+  // build_list, build_src, dirty, slow_rows[2], stream_rows[2], scr[2], side_tests[2], then the two active
+  // counters and the three list counts
   const size_t nd = (size_t)k * (1 + 1 + kMaxBlock + 2 + 26 + 2 + 4 * kMaxDet + 6 * kMaxDet + 2 * kSliceDim + 2);
-  const size_t ni = (size_t)k * (1 + 2 + 1 + 1 + 2 + 3 + 2 + 2 + 1 + 1 + 1 + 2 + 2 + 2 + 2) + 4;
+  const size_t ni = (size_t)k * (1 + 2 + 1 + 1 + 2 + 3 + 2 + 2 + 1 + 1 + 1 + 2 + 2 + 2 + 2) + 5;
   char* m = nullptr;
   // six 64-bit counters first (evaluation kinds, prescreen counts), then the doubles and the ints
   gw_status s = check_hip(hipMalloc((void**)&m, 64 + nd * sizeof(double) + ni * sizeof(int32_t)), "slice workspace");
@@ -1201,7 +1251,7 @@ static gw_status slice_ws(gw_ctx* ctx, int64_t k, gw_slice_ws** out) {
   ws->S.stream_rows = ip; ip += 2 * k;
   ws->S.scr = ip; ip += 2 * k;
   ws->S.side_tests = ip; ip += 2 * k;
-  ws->S.n_active = ip; ip += 1;
+  ws->S.n_active = ip; ip += 2;
   ws->S.counts = ip;
   ws->mem = m;
   ws->cap = k;
