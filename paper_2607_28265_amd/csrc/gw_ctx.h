@@ -215,6 +215,13 @@ void prof_end(gw_ctx* ctx, int slot, hipStream_t st);
 // launch shape (zeros without heterodyne set-up).
 gw_status full_reserve(gw_ctx* ctx, int64_t n);
 gw_status het_reserve(gw_ctx* ctx, int64_t n);
+// Write the argument block of the single batch (theta, n rows, logl) now, on
+// st; until het_unpin_args or a call with other arguments, heterodyned calls
+// on that batch launch no argument kernel (a sampler's rounds, graph-captured
+// or not, reuse the block).  The caller keeps other calls off the context
+// meanwhile.
+gw_status het_pin_args(gw_ctx* ctx, const double* theta, int64_t n, double* logl, hipStream_t st);
+void het_unpin_args(gw_ctx* ctx);
 void het_shape_key(const gw_ctx* ctx, int32_t* wpb, int32_t* grid, int32_t* ech);
 // The heterodyned time marginal's table and index addresses and plan sizes
 // (zeros without heterodyne state), for keying captured graphs.

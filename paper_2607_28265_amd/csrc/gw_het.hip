@@ -64,6 +64,13 @@ struct gw_het_state {
   int grid = 0;                  // workgroups (0 = heuristic)
   int ech = 0;                   // edge chunks (0 = heuristic)
   int64_t n_rows_last = 0;       // rows of the batch being enqueued (selects the distance form)
+  // a caller that evaluates the same single batch (theta, rows, logl) many
+  // times in a row writes the argument block once (het_pin_args); meanwhile
+  // matching calls launch no k_set_args
+  bool args_pinned = false;
+  const double* pin_theta = nullptr;
+  const double* pin_logl = nullptr;
+  int64_t pin_rows = 0;
   // time marginal: row-independent tables for the current grid (built on
   // first use): per block b < n_blk the edges [bs[b], bs[b + 1]) in it, per
   // edge the Chebyshev values T_m(s_e) of its offset in the block (m < tm_K)
@@ -777,11 +784,33 @@ static gw_status het_prepare(gw_ctx* ctx, const double* theta, const int64_t* su
   if (s == GW_OK)
     s = ensure_buffer(&ctx->partial, &ctx->partial_cap, (int64_t)(*n_ech) * 3 * ctx->n_det * n_rows, "partials");
   if (s != GW_OK) return s;
+  if (h->args_pinned) {
+    if (single && !zcplx && theta == h->pin_theta && logl == h->pin_logl && n_rows == h->pin_rows) return GW_OK;
+    h->args_pinned = false;  // the block is rewritten below
+  }
   hipLaunchKernelGGL(k_set_args, dim3(1), dim3(256), 0, st, h->args, theta,
                      single ? (const int64_t*)h->subs_single : subs, logl, ctx->coef, ctx->zbuf, ctx->partial, n_rows,
                      single ? 1 : n_sub, single ? h->subs_single : (int64_t*)nullptr, single ? n_rows : (int64_t)0,
                      h->tile_pre, zcplx);
   return check_hip(hipGetLastError(), "argument kernel launch");
+}
+
+gw_status het_pin_args(gw_ctx* ctx, const double* theta, int64_t n, double* logl, hipStream_t st) {
+  gw_het_state* h = ctx->het;
+  if (!h) return set_error(GW_ESTATE, "heterodyne_setup has not been called");
+  h->args_pinned = false;
+  int n_ech = 1;
+  gw_status s = het_prepare(ctx, theta, nullptr, 1, n, logl, true, &n_ech, st);
+  if (s != GW_OK) return s;
+  h->pin_theta = theta;
+  h->pin_logl = logl;
+  h->pin_rows = n;
+  h->args_pinned = true;
+  return GW_OK;
+}
+
+void het_unpin_args(gw_ctx* ctx) {
+  if (ctx->het) ctx->het->args_pinned = false;
 }
 
 gw_status het_reserve(gw_ctx* ctx, int64_t n) {

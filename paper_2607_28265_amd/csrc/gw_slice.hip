@@ -657,7 +657,7 @@ struct SliceGraphKey {
   uint64_t mlp_scale, gen;
   const void *tm_mom, *tm_ccoef, *tm_basis, *tm_tab, *tm_idx;
   int32_t het_wpb, het_grid, het_ech, full_tpb, full_chunks, full_kernel;
-  int32_t tm_nch, tm_nslot, tm_nsplit, fused;
+  int32_t tm_nch, tm_nslot, tm_nsplit, fused, pinned, pad;
   bool operator==(const SliceGraphKey& o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
 };
 
@@ -738,7 +738,8 @@ static gw_status eval_rows(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const SweepC
 // changes) on the workspace's own capture stream.  Buffers the likelihood
 // would grow are reserved first: no allocation may happen during capture.
 template <class Group>
-static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const SweepCall& a, bool fused, Group group) {
+static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const SweepCall& a, bool fused, bool pinned,
+                             Group group) {
   const int64_t n = 2 * k;
   gw_status s = a.lists ? cached_reserve(ctx, n) : a.like == GW_HET ? het_reserve(ctx, n) : full_reserve(ctx, n);
   if (s == GW_OK && a.marg == GW_MARG_PHASE_TIME) s = tmarg_reserve(ctx, n, a.like);
@@ -764,6 +765,7 @@ static gw_status slice_graph(gw_ctx* ctx, gw_slice_ws* ws, int64_t k, const Swee
   key.mlp_scale = a.mlp ? mlp_scale_version(a.mlp) : 0;
   key.gen = ctx->gen;
   key.fused = fused ? 1 : 0;
+  key.pinned = pinned ? 1 : 0;
   if (a.marg == GW_MARG_PHASE_TIME) {
     key.tm_mom = ctx->tm_mom;
     key.tm_ccoef = ctx->tm_ccoef;
@@ -1006,7 +1008,20 @@ static gw_status run_sweep(gw_ctx* ctx, const SweepParams& P, const SweepCall& a
     }
     return g;
   };
-  if (s == GW_OK && a.use_graph) s = slice_graph(ctx, ws, k, a, fused, group);
+  // the heterodyned rounds all evaluate the same 2k candidate rows: their
+  // argument block is written once here instead of by every round
+  struct Unpin {
+    gw_ctx* c = nullptr;
+    ~Unpin() {
+      if (c) het_unpin_args(c);
+    }
+  } unpin;
+  const bool pin = a.like == GW_HET && a.marg != GW_MARG_PHASE_TIME;
+  if (s == GW_OK && pin) {
+    s = het_pin_args(ctx, ws->cand, 2 * k, ws->cand_logl, st);
+    if (s == GW_OK) unpin.c = ctx;
+  }
+  if (s == GW_OK && a.use_graph) s = slice_graph(ctx, ws, k, a, fused, pin, group);
   int cur = 0, prev = -1;
   for (int rounds = 0; s == GW_OK && rounds < max_rounds; rounds += 4) {
     if (a.use_graph) s = check_hip(hipGraphLaunch(ws->exec, st), "slice graph launch");
