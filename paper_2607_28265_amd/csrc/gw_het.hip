@@ -445,8 +445,15 @@ __global__ void __launch_bounds__(256) k_het(const HetArgs* __restrict__ ab, con
 // restore the prefactor (A P_i) / (A0 P0_i), sum the detectors and apply the
 // plain or phase-marginalised epilogue (or stage |Z_1| and <h|h>_1 for the
 // distance marginal).
-__device__ inline void het_finish_row(const HetArgs* __restrict__ ab, int64_t row, int nd, int marg,
-                                      const double* zr, const double* zi, const double* hh, const HetConst& hc) {
+struct HetRow {
+  double Zr, Zi, plain, hht;
+  bool valid;
+};
+
+// A row's binned overlap, its plain real part and <h|h> from the summed edge
+// partials (the heterodyne's per-detector ratio to the reference applied).
+__device__ inline HetRow het_row(const HetArgs* __restrict__ ab, int64_t row, int nd, const double* zr,
+                                 const double* zi, const double* hh, const HetConst& hc) {
   const int64_t ld = ab->ld;
   const double* cf = ab->coef + row;
   double Zr = 0.0, Zi = 0.0, plain = 0.0, hht = 0.0;
@@ -461,7 +468,15 @@ __device__ inline void het_finish_row(const HetArgs* __restrict__ ab, int64_t ro
     Zi += wi;
     hht += (qr * qr + qi * qi) * (hc.hh0[i] + hh[i]);
   }
-  const bool valid = cf[C_VALID * ld] != 0.0;
+  return HetRow{Zr, Zi, plain, hht, cf[C_VALID * ld] != 0.0};
+}
+
+__device__ inline void het_finish_row(const HetArgs* __restrict__ ab, int64_t row, int nd, int marg,
+                                      const double* zr, const double* zi, const double* hh, const HetConst& hc) {
+  const int64_t ld = ab->ld;
+  const HetRow R = het_row(ab, row, nd, zr, zi, hh, hc);
+  const double Zr = R.Zr, Zi = R.Zi, plain = R.plain, hht = R.hht;
+  const bool valid = R.valid;
   const double zabs = sqrt(Zr * Zr + Zi * Zi);
   if (ab->zcplx) {
     ab->zcplx[row] = valid ? Zr : NAN;
@@ -576,6 +591,66 @@ __global__ void __launch_bounds__(256) k_het_dist_w(const HetArgs* __restrict__ 
     const double v = PREC == 0 ? wave_dist_lse(z1, h1, dtab, n_dist, lane, C)
                                : wave_dist_lse_f32(z1, h1, dtab, n_dist, lane);
     if (lane == 0) ab->logl[row] = -0.5 * dd + v;
+  }
+}
+
+// Small batches with the distance marginal: k_het_combine_w and k_het_dist_w
+// in one launch (one wave per row), the row's |Z| and <h|h> passed on in
+// registers; the same arithmetic, so the same log L.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_het_combine_dist_w(const HetArgs* __restrict__ ab,
+                                                            const int64_t* __restrict__ pre, int nd, int n_ech,
+                                                            HetConst hc, const double* __restrict__ dtab, int n_dist,
+                                                            const LogI0Consts* __restrict__ Cp) {
+  const LogI0Consts& C = *Cp;
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const int64_t wid = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * wpb;
+  const int64_t total = pre[ab->n_sub] * 64;
+  const int64_t ld = ab->ld;
+  for (int64_t it = wid; it < total; it += nwaves) {
+    int64_t row0, row_end;
+    if (!tile_rows(ab, pre, it >> 6, &row0, &row_end)) continue;
+    const int64_t row = row0 + (it & 63);
+    if (row >= row_end) continue;
+    double zr[kMaxDet], zi[kMaxDet], hh[kMaxDet];
+    for (int i = 0; i < nd; ++i) {
+      double a = 0.0, b = 0.0, c = 0.0;
+      if (lane < n_ech) {
+        const double* p = ab->part + ((int64_t)lane * 3 * nd + 3 * i) * ld + row;
+        a = p[0];
+        b = p[ld];
+        c = p[2 * ld];
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+        c += __shfl_xor(c, o, 64);
+      }
+      zr[i] = a;
+      zi[i] = b;
+      hh[i] = c;
+    }
+    const HetRow R = het_row(ab, row, nd, zr, zi, hh, hc);
+    const double z1 = R.valid ? sqrt(R.Zr * R.Zr + R.Zi * R.Zi) : -1.0, h1 = R.hht;
+    if (lane == 0) {
+      if (ab->zcplx) {
+        ab->zcplx[row] = R.valid ? R.Zr : NAN;
+        ab->zcplx[ld + row] = R.Zi;
+        ab->zcplx[2 * ld + row] = R.hht;
+      }
+      ab->zbuf[row] = z1;
+      ab->zbuf[ld + row] = h1;
+    }
+    if (z1 < 0.0) {
+      if (lane == 0) ab->logl[row] = -INFINITY;
+      continue;
+    }
+    const double v = PREC == 0 ? wave_dist_lse(z1, h1, dtab, n_dist, lane, C)
+                               : wave_dist_lse_f32(z1, h1, dtab, n_dist, lane);
+    if (lane == 0) ab->logl[row] = -0.5 * hc.dd + v;
   }
 }
 
@@ -747,6 +822,15 @@ static gw_status enqueue_het(gw_ctx* ctx, int marg, int prec, int n_ech, hipStre
     hc.hh0[i] = h->hh0[i];
   }
   hc.dd = ctx->dd;
+  if (marg == 2 && h->n_rows_last < kDistRowsPerLane && n_ech <= 64) {
+    if (prec == GW_PREC_MIXED)
+      hipLaunchKernelGGL(k_het_combine_dist_w<1>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->n_det,
+                         n_ech, hc, ctx->dist_tab, ctx->n_dist, ctx->i0c);
+    else
+      hipLaunchKernelGGL(k_het_combine_dist_w<0>, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->n_det,
+                         n_ech, hc, ctx->dist_tab, ctx->n_dist, ctx->i0c);
+    return check_hip(hipGetLastError(), "heterodyne combine and distance marginal launch");
+  }
   if (h->n_rows_last < kDistRowsPerLane && n_ech <= 64)
     hipLaunchKernelGGL(k_het_combine_w, dim3(256 * 8), dim3(256), 0, st, h->args, h->tile_pre, ctx->n_det, n_ech,
                        marg, hc);
