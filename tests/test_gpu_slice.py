@@ -213,3 +213,43 @@ def test_sweep_one_block_equals_step_and_errors(setup):
         gw.slice_sweep(ctx.handle, xt, lt, lstar, [[0]] * 17, [np.eye(1)] * 17)
     with pytest.raises(gw.GwError):  # two distinct 11-coordinate factors exceed the packed store
         gw.slice_sweep(ctx.handle, xt, lt, lstar, [list(range(11))] * 2, [np.eye(11), 0.5 * np.eye(11)])
+
+
+def test_sweeps_between_other_heterodyned_calls(setup):
+    # A heterodyned sweep writes the likelihood's argument block once and its
+    # rounds (replayed from a graph) reuse it.  Batch calls on other rows
+    # between sweeps rewrite the block; the next sweep must rewrite it again,
+    # so graph-replayed sweeps interleaved with such calls equal eager sweeps,
+    # and the batch calls equal the same call made alone.
+    gw, ctx, prob, het, loglike_u, x, logl = setup
+    blocks = list(S.BLOCKS)
+    chols = [S.block_cholesky(x, b) for b in blocks]
+    lstar = float(np.quantile(logl, 0.3))
+    keep = logl > lstar
+    xs, ls = x[keep], logl[keep]
+
+    def sweep(use_graph, counter):
+        xt = torch.from_numpy(xs.copy()).cuda()
+        lt = torch.from_numpy(ls.copy()).cuda()
+        ne = torch.zeros(len(xs), dtype=torch.int32, device="cuda")
+        st = torch.zeros(len(xs), dtype=torch.int32, device="cuda")
+        gw.slice_sweep(ctx.handle, xt, lt, lstar, blocks, chols, seed=11, counter=counter, w=1.0, max_out=4,
+                       max_shrink=60, like=gw.GW_HET, marg=gw.GW_MARG_PHASE_DIST, prec=gw.GW_PREC_MIXED,
+                       n_evals=ne, status=st, use_graph=use_graph)
+        torch.cuda.synchronize()
+        return [t.cpu().numpy() for t in (xt, lt, ne, st)]
+
+    th = gw.gw_prior_transform(ctx.handle, torch.from_numpy(x[:37].copy()).cuda())
+    alone = gw.loglike_batch(ctx.handle, th, gw.GW_HET, gw.GW_MARG_PHASE_DIST, gw.GW_PREC_MIXED).cpu().numpy()
+    eager = [sweep(False, c) for c in (500, 600, 700)]
+    replayed, between = [], []
+    for c in (500, 600, 700):
+        replayed.append(sweep(True, c))
+        between.append(gw.loglike_batch(ctx.handle, th, gw.GW_HET, gw.GW_MARG_PHASE_DIST,
+                                        gw.GW_PREC_MIXED).cpu().numpy())
+    for call, (a, b) in enumerate(zip(eager, replayed)):
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v), call
+    assert eager[0][2].sum() > 0
+    for v in between:
+        assert np.array_equal(v, alone)
